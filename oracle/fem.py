@@ -1,0 +1,160 @@
+"""GLS-stabilised trilinear finite elements for the model problem (Section 2).
+
+The discrete problem is a(u, v) = b(u, v) + z(u, v) = g(v) with
+  b(u, v) = int nu grad u . grad v + C(x) Lu Lv + ctilde u v
+  z(u, v) = 1/2 int (a . grad u) v - (a . grad v) u
+  g(v)    = int f v + C(x) f Lv
+  L u     = -div(nu grad u) + a . grad u + c u,  ctilde = c - div(a) / 2
+and the element parameter C_K of the Peclet-number switch with tau (Section 2,
+definition of P_K and C(x)).  The paper uses linear tetrahedra; the workloads
+here use trilinear boxes (a reading recorded with the other readings), on
+which -div(nu grad u) vanishes inside an element for constant nu_K, so
+L u = a . grad u + c u elementwise.
+
+Entry A_K[i, j] = a(phi_j, phi_i): row = test function, column = trial.
+Element local node (p, q, r) in {0,1}^3 has index p + 2 q + 4 r.
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.sparse as sp
+
+
+def gauss01(npts):
+    """Gauss-Legendre points and weights on [0, 1]."""
+    x, w = np.polynomial.legendre.leggauss(npts)
+    return 0.5 * (x + 1.0), 0.5 * w
+
+
+def _corner_bits():
+    idx = np.arange(8)
+    return idx & 1, (idx >> 1) & 1, (idx >> 2) & 1
+
+
+def velocity(problem, pts):
+    """a(x) = beta0 + beta1 x at points pts (..., 3)."""
+    return problem["beta0"] + pts @ problem["beta1"].T
+
+
+def element_geometry(problem, topo):
+    """Lower corners (ne, 3) and sizes (3,) of all elements (x-fastest)."""
+    L = problem["length"]
+    h = np.array([L[a] / topo.ne_axis[a] for a in range(3)])
+    e = np.arange(topo.n_elem)
+    ex = e % topo.ne_axis[0]
+    ey = (e // topo.ne_axis[0]) % topo.ne_axis[1]
+    ez = e // (topo.ne_axis[0] * topo.ne_axis[1])
+    x0 = np.stack([ex * h[0], ey * h[1], ez * h[2]], axis=1)
+    return x0, h, (ex, ey, ez)
+
+
+def element_node_ids(topo, ex, ey, ez):
+    px, py, pz = _corner_bits()
+    return topo.node_id(ex[:, None] + px[None, :], ey[:, None] + py[None, :], ez[:, None] + pz[None, :])
+
+
+def stabilisation(problem, x0, h, nu):
+    """C_K of Section 2: tau h_K / (2 |a|_K) if P_K >= 1, else tau h_K^2 / (4 nu).
+
+    h_K is the box diameter; |a|_K = sup over K of |a|, attained at a vertex
+    because |a(x)| is convex for affine a."""
+    tau = problem["tau"]
+    hK = float(np.sqrt(np.sum(h ** 2)))
+    px, py, pz = _corner_bits()
+    corners = x0[:, None, :] + np.stack([px, py, pz], axis=1)[None, :, :] * h[None, None, :]
+    amax = np.linalg.norm(velocity(problem, corners), axis=2).max(axis=1)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        peclet = hK * amax / (2.0 * nu)
+        c_adv = tau * hK / (2.0 * amax)
+    c_diff = tau * hK ** 2 / (4.0 * nu)
+    return np.where(peclet >= 1.0, c_adv, c_diff), peclet
+
+
+def element_matrices(problem, topo, npts=3):
+    """Element matrices A_K (ne, 8, 8) and loads F_K (ne, 8) by tensor Gauss
+    quadrature with npts points per axis (3 is exact for affine a and
+    trilinear f)."""
+    x0, h, (ex, ey, ez) = element_geometry(problem, topo)
+    nu = problem["nu"]
+    c = problem["c"]
+    ctil = c - 0.5 * np.trace(problem["beta1"])
+    CK, _ = stabilisation(problem, x0, h, nu)
+    nodes = element_node_ids(topo, ex, ey, ez)
+    fnod = problem["f_nodal"]
+    px, py, pz = _corner_bits()
+    qp, qw = gauss01(npts)
+    vol = float(np.prod(h))
+    ne = topo.n_elem
+    A = np.zeros((ne, 8, 8))
+    F = np.zeros((ne, 8))
+    for i, s in enumerate(qp):
+        for j, t in enumerate(qp):
+            for k, u in enumerate(qp):
+                w = qw[i] * qw[j] * qw[k] * vol
+                fs = np.where(px == 1, s, 1 - s)
+                ft = np.where(py == 1, t, 1 - t)
+                fu = np.where(pz == 1, u, 1 - u)
+                phi = fs * ft * fu                                   # (8,)
+                grad = np.stack([(2 * px - 1) / h[0] * ft * fu,
+                                 fs * (2 * py - 1) / h[1] * fu,
+                                 fs * ft * (2 * pz - 1) / h[2]], axis=1)  # (8, 3)
+                xq = x0 + np.array([s, t, u]) * h                     # (ne, 3)
+                aq = velocity(problem, xq)                           # (ne, 3)
+                agrad = aq @ grad.T                                  # (ne, 8)
+                Lphi = agrad + c * phi[None, :]
+                diff = grad @ grad.T                                 # (8, 8)
+                A += w * (nu[:, None, None] * diff[None]
+                          + CK[:, None, None] * Lphi[:, :, None] * Lphi[:, None, :]
+                          + ctil * np.outer(phi, phi)[None]
+                          + 0.5 * (agrad[:, None, :] * phi[None, :, None]
+                                   - agrad[:, :, None] * phi[None, None, :]))
+                if fnod is None:
+                    fq = np.full(ne, problem["f_const"])
+                else:
+                    fq = fnod[nodes] @ phi
+                F += w * (fq[:, None] * phi[None, :] + CK[:, None] * fq[:, None] * Lphi)
+    return A, F, nodes
+
+
+def assemble_global(problem, topo, npts=3):
+    """Global sparse matrix and load over the free dofs (free-node order)."""
+    A, F, nodes = element_matrices(problem, topo, npts)
+    dof = topo.dof_of_node[nodes]                                    # (ne, 8)
+    rows = np.repeat(dof[:, :, None], 8, axis=2)
+    cols = np.repeat(dof[:, None, :], 8, axis=1)
+    keep = (rows >= 0) & (cols >= 0)
+    M = sp.coo_matrix((A[keep], (rows[keep], cols[keep])), shape=(topo.n_dof, topo.n_dof)).tocsr()
+    b = np.zeros(topo.n_dof)
+    kf = dof >= 0
+    np.add.at(b, dof[kf], F[kf])
+    return M, b
+
+
+def assemble_subdomains(problem, topo, npts=3, elem=None):
+    """Dense local matrices A^(i) and loads f^(i) in local order [I; Gamma_i].
+
+    Section 3: A^(i), f^(i) come from a_i(., .) and g(.) restricted to the
+    elements of subdomain i; Dirichlet nodes are dropped."""
+    if elem is None:
+        elem = element_matrices(problem, topo, npts)
+    A, F, nodes = elem
+    out = []
+    for s in range(topo.n_sub):
+        (x0, x1), (y0, y1), (z0, z1) = topo.element_box(s)
+        EZ, EY, EX = np.meshgrid(np.arange(z0, z1), np.arange(y0, y1), np.arange(x0, x1), indexing="ij")
+        eids = topo.elem_id(EX.ravel(), EY.ravel(), EZ.ravel())
+        lnodes = topo.local_nodes(s)
+        lmap = -np.ones(topo.n_nodes, dtype=np.int64)
+        lmap[lnodes] = np.arange(lnodes.size)
+        n = lnodes.size
+        loc = lmap[nodes[eids]]                                      # (nel, 8)
+        Al = np.zeros((n, n))
+        fl = np.zeros(n)
+        rows = np.repeat(loc[:, :, None], 8, axis=2)
+        cols = np.repeat(loc[:, None, :], 8, axis=1)
+        keep = (rows >= 0) & (cols >= 0)
+        np.add.at(Al, (rows[keep], cols[keep]), A[eids][keep])
+        kf = loc >= 0
+        np.add.at(fl, loc[kf], F[eids][kf])
+        out.append((Al, fl))
+    return out
