@@ -1,0 +1,230 @@
+/*
+ * abddc.h -- C ABI of the MI355X (gfx950) adaptive BDDC library.
+ *
+ * Method: Peng, Shu, Wang, Zhong, "A BDDC method with an adaptive coarse
+ * space for three-dimensional advection-diffusion problems", arXiv 2501.01676.
+ *
+ *   problem      Section 2, eq. (model-AD-equation) and (stab-var-pb): GLS
+ *                stabilised advection-diffusion, a(.,.) = b(.,.) + z(.,.)
+ *   system       Section 3, eq. (Schur-complex-sys): the interface Schur
+ *                complement system Rt^T St Rt u = Rt^T gt
+ *   precond.     Section 3: M^{-1} = Rt^T Dt St^{-1} Dt^T Rt, deluxe scaling,
+ *                vertex constraints, adaptive face constraints (eq. equ-4-8,
+ *                primal-constraints-F) and the edge constraints of the new
+ *                edge eigenproblem (eq. equ-5-21, equ-5-22, and the Remark
+ *                after it on the SVD/QR change of basis)
+ *   solver       Section 4: GMRES stopped at a residual of 1e-8 or 300 steps
+ *
+ * Discretisation here: trilinear (Q1) boxes on a tensor-product box
+ * partition of a box domain with zero Dirichlet data (the paper uses linear
+ * tetrahedra; the element is a reading of this library).
+ *
+ * Conventions (every entry point):
+ *  - Return value: ABDDC_OK (0) on success, a positive warning code when the
+ *    result is valid but flagged, a negative error code otherwise.  The
+ *    message of the last error on the calling thread is abddc_last_error().
+ *    No C++ exception crosses this boundary.
+ *  - Call order: abddc_assemble -> abddc_setup_coarse_space -> any number of
+ *    abddc_apply_bddc / abddc_apply_schur / abddc_gmres_solve.  Out of order
+ *    calls return ABDDC_ESTATE.  One context must not be used by two host
+ *    threads at once; different contexts are independent.
+ *  - Problem arrays (abddc_problem) are HOST pointers, copied by
+ *    abddc_assemble; the caller keeps ownership.
+ *  - Vectors passed to apply/solve (r, z, x, y, u) are DEVICE pointers of
+ *    the context's device, read and written in stream order on the stream
+ *    given at assemble time; the caller owns them.
+ *  - The library owns all other device memory (allocated at assemble/setup,
+ *    released by abddc_destroy).
+ *  - Vector layouts: the interface vector (length n_gamma) lists all faces,
+ *    then all edges, then all vertices; objects of one kind by increasing
+ *    smallest grid-node id; the nodes of an object by increasing node id.
+ *    Grid node id = ix + (nx+1)(iy + (ny+1) iz).  The full solution u
+ *    (length n_dof) lists the free (non-Dirichlet) grid nodes by node id.
+ *    Subdomain id = sx + Nx (sy + Ny sz).
+ */
+#ifndef ABDDC_H
+#define ABDDC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct abddc_ctx abddc_ctx; /* opaque, owned by the library */
+
+enum {
+  ABDDC_OK = 0,
+  ABDDC_NOT_CONVERGED = 1, /* gmres_solve: maxit reached; last iterate returned */
+  ABDDC_EINVAL = -1,       /* invalid argument (sizes, coefficients, options)   */
+  ABDDC_ENOMEM = -2,       /* device allocation failed                          */
+  ABDDC_ESINGULAR = -3,    /* zero or non-finite pivot in a factorisation       */
+  ABDDC_EEIG = -4,         /* eigensolver failure (metric not positive definite)*/
+  ABDDC_EDEVICE = -5,      /* HIP runtime error                                 */
+  ABDDC_ESTATE = -6        /* entry point called out of order                   */
+};
+
+/* Device binding: which GPU and which HIP stream (hipStream_t) to use.
+ * stream may be NULL for the default stream. */
+typedef struct {
+  int32_t device;
+  void* stream;
+} abddc_device;
+
+/* The model problem of Section 2 on a box split into box subdomains.
+ * Coefficients: nu > 0 piecewise constant per element; affine velocity
+ * a(x) = beta0 + beta1 x (beta1 row-major 3x3); constant reaction c;
+ * source f constant (f_nodal == NULL) or trilinear from nodal values. */
+typedef struct {
+  int32_t nsub[3];          /* subdomains per axis                              */
+  const int32_t* width[3];  /* elements per subdomain along each axis (>= 2)   */
+  double length[3];         /* box edge lengths (> 0)                           */
+  const double* nu;         /* per element, x-fastest, len prod_a sum(width[a]) */
+  double beta0[3];
+  double beta1[9];
+  double c;
+  const double* f_nodal;    /* NULL, or per grid node (x-fastest)               */
+  double f_const;
+  double tau;               /* GLS constant tau of C(x) (0.7 in the paper)      */
+} abddc_problem;
+
+enum { ABDDC_PREC_FP64 = 0, ABDDC_PREC_MIXED = 1 };
+enum { ABDDC_EDGE_NEW = 0, ABDDC_EDGE_OLD = 1 };
+enum { ABDDC_H_SHARED = 0, ABDDC_H_SEPARATE = 1 };
+enum { ABDDC_DELUXE_S = 0, ABDDC_DELUXE_B = 1 };
+enum { ABDDC_CONSTRAINTS_EXACT = 0, ABDDC_CONSTRAINTS_MLP = 1 };
+
+/* Adaptive coarse-space options (Section 3 thresholds; Section 4 values
+ * are Theta_F = 1 + log m, Theta_E = 10). */
+typedef struct {
+  double theta_face;        /* Theta_F >= 0: select lambda >= Theta_F           */
+  double theta_edge;        /* Theta_E >= 0                                      */
+  int32_t edge_variant;     /* ABDDC_EDGE_NEW (eq. equ-5-21); OLD not provided  */
+  int32_t edge_h_mode;      /* prior-selected primal unknowns shared / separate */
+  int32_t deluxe_source;    /* deluxe weights from S^(i) (default) or B^(i)     */
+  double pinv_rtol;         /* pseudo-inverse eigenvalue cut (1e-10)            */
+  double svd_rtol;          /* edge SVD rank cut relative to sigma_1 (1e-8)     */
+  double tie_rtol;          /* |lambda - Theta| <= tie_rtol Theta: near tie     */
+  int32_t precision;        /* ABDDC_PREC_FP64 or ABDDC_PREC_MIXED             */
+  int32_t constraint_source;/* exact GEP, or learned edge constraints          */
+  const char* mlp_weights;  /* weights file for ABDDC_CONSTRAINTS_MLP           */
+} abddc_options;
+
+typedef struct {
+  int32_t n_vertex, pnum_face, pnum_edge, n_primal, n_near_ties;
+} abddc_counts;
+
+typedef struct {
+  int32_t iters;            /* preconditioned Arnoldi steps                      */
+  int32_t restarts;
+  double relres_true;       /* ||ghat - Shat u|| / ||ghat|| at exit              */
+  double t_setup_s;         /* assemble + setup wall time (stream-synchronised) */
+  double t_iter_s;          /* gmres_solve wall time incl. interior recovery     */
+  double* resid_history;    /* HOST array or NULL; Arnoldi estimates / ||ghat|| */
+  int32_t resid_cap;        /* capacity of resid_history                         */
+} abddc_solve_info;
+
+/* Section 3 (local matrices A^(i), f^(i) of a_i and g; Schur complements
+ * S^(i) = A_BB - A_BI A_II^{-1} A_IB, g^(i) = f_B - A_BI A_II^{-1} f_I;
+ * B^(i) = sym(S^(i))).  Builds the topology, assembles every subdomain on
+ * the GPU and forms S^(i), g^(i), B^(i) and ghat = sum R_i^T g^(i).
+ * EINVAL on bad sizes / non-positive or non-finite nu / tau <= 0. */
+int abddc_assemble(const abddc_problem* prob, const abddc_device* dev, abddc_ctx** out);
+
+/* Section 3: deluxe weights, face eigenproblems (eq. equ-4-8), new edge
+ * eigenproblems (eq. equ-5-21) with the SVD/QR edge basis, change of basis,
+ * local constrained factorisations and the coarse matrix.  Fills counts
+ * (may be NULL).  opts may be NULL (defaults: Theta_F = Theta_E = 10,
+ * shared H, deluxe from S, FP64). */
+int abddc_setup_coarse_space(abddc_ctx* ctx, const abddc_options* opts, abddc_counts* counts);
+
+/* z = M^{-1} r (Section 3, M_BDDC^{-1}); r, z device vectors of length
+ * n_gamma (may not alias). */
+int abddc_apply_bddc(abddc_ctx* ctx, const double* r, double* z);
+
+/* y = Shat x = sum_i R_i^T S^(i) R_i x (the operator of eq.
+ * Schur-complex-sys); device vectors of length n_gamma (may not alias). */
+int abddc_apply_schur(abddc_ctx* ctx, const double* x, double* y);
+
+/* Copies ghat (device, length n_gamma) into g. */
+int abddc_get_rhs(abddc_ctx* ctx, double* g);
+
+/* Right-preconditioned restarted GMRES(restart) on the Schur system from
+ * u = 0 (Section 4 stopping rule: ||ghat - Shat u|| <= rtol ||ghat|| or maxit
+ * Arnoldi steps), then interior recovery u_I = A_II^{-1}(f_I - A_IB u_B).
+ * u: device vector of length n_dof (full solution).  info may be NULL.
+ * Returns ABDDC_NOT_CONVERGED when maxit is reached first. */
+int abddc_gmres_solve(abddc_ctx* ctx, int32_t restart, double rtol, int32_t maxit,
+                      double* u, abddc_solve_info* info);
+
+/* Sizes of an assembled context; any pointer may be NULL. */
+int abddc_query(const abddc_ctx* ctx, int64_t* n_dof, int64_t* n_gamma, int32_t* n_sub,
+                int32_t* n_face, int32_t* n_edge);
+
+/* Parity hook: copies an intermediate into the HOST buffer buf (capacity
+ * cap doubles).  Returns the number of doubles of the item (>= 0; nothing
+ * is written when it exceeds cap) or a negative error code.
+ *   ABDDC_STAGE_SCHUR      S^(index), n_B x n_B row-major
+ *   ABDDC_STAGE_LOCAL_RHS  g^(index)
+ *   ABDDC_STAGE_FACE_EIG   mu = 1/lambda of face index (ascending)
+ *   ABDDC_STAGE_EDGE_EIG   mu = 1/lambda of edge index (ascending)
+ *   ABDDC_STAGE_FACE_BASIS [Q_F | Q_F^perp] of face index, n_F x n_F row-major
+ *   ABDDC_STAGE_EDGE_BASIS [Q_E | Q_E^perp] of edge index, n_E x n_E row-major
+ *   ABDDC_STAGE_COUNTS     per face p_F then per edge r_E (as doubles)
+ *   ABDDC_STAGE_DELUXE     D of object index/8, member index%8 of n(X) */
+enum {
+  ABDDC_STAGE_SCHUR = 0,
+  ABDDC_STAGE_LOCAL_RHS = 1,
+  ABDDC_STAGE_FACE_EIG = 2,
+  ABDDC_STAGE_EDGE_EIG = 3,
+  ABDDC_STAGE_FACE_BASIS = 4,
+  ABDDC_STAGE_EDGE_BASIS = 5,
+  ABDDC_STAGE_COUNTS = 6,
+  ABDDC_STAGE_DELUXE = 7
+};
+int64_t abddc_get_stage(abddc_ctx* ctx, int32_t stage, int32_t index, double* buf, int64_t cap);
+
+/* Per-phase device times of the last setup / solve in seconds (HIP events
+ * on the context stream): [0] assemble, [1] local Schur, [2] deluxe,
+ * [3] face stage, [4] edge stage, [5] change of basis + local factors,
+ * [6] coarse, [7] GMRES iterations, [8] recovery.  n <= 16. */
+int abddc_phase_times(const abddc_ctx* ctx, double* t, int32_t n);
+
+void abddc_destroy(abddc_ctx* ctx);
+
+/* Thread-local message of the last failed call on this thread ("" if none). */
+const char* abddc_last_error(void);
+
+/* ---- Primitive test hooks (batched kernels the setup is built from) ----
+ * Batched partial LU without pivoting, in place, on row-major matrices that
+ * live in one DEVICE buffer: matrix b starts at buf + off[b] (host array),
+ * has nrow[b] rows, ncol[b] columns, leading dimension ld[b], and its first
+ * k[b] pivots are eliminated, leaving the Schur complement
+ * A22 - A21 A11^{-1} A12 in rows/cols >= k[b], U/L factors in front.
+ * precision: 0 = FP64 (buf is double*), 1 = FP32 (buf is float*).
+ * Returns ABDDC_ESINGULAR on a zero or non-finite pivot. */
+int abddc_test_partial_lu(int32_t batch, void* buf, const int64_t* off, const int32_t* nrow,
+                          const int32_t* ncol, const int32_t* ld, const int32_t* k,
+                          int32_t precision, void* stream);
+
+/* Batched C_b = alpha op(A_b) op(B_b) + beta C_b on row-major FP64 DEVICE
+ * matrices inside one buffer; offsets in doubles (host arrays); trans*
+ * nonzero means the transpose.  Used to test the MFMA tile kernel. */
+int abddc_test_gemm(int32_t batch, double* buf, const int64_t* offA, const int64_t* offB,
+                    const int64_t* offC, const int32_t* m, const int32_t* n, const int32_t* k,
+                    const int32_t* lda, const int32_t* ldb, const int32_t* ldc, int32_t transA,
+                    int32_t transB, double alpha, double beta, void* stream);
+
+/* Batched symmetric-definite generalized eigenproblem A y = mu B y with B
+ * SPD, n x n row-major FP64 DEVICE matrices in one buffer (A at offA[b], B
+ * at offB[b], ld = n[b]); writes mu ascending to buf + offW[b] and X = L Y
+ * (B = L L^T, Y orthonormal eigenvectors of L^{-1} A L^{-T}) to
+ * buf + offX[b].  Returns ABDDC_EEIG if B is not positive definite. */
+int abddc_test_sygv(int32_t batch, double* buf, const int64_t* offA, const int64_t* offB,
+                    const int64_t* offW, const int64_t* offX, const int32_t* n, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ABDDC_H */

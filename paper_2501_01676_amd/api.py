@@ -1,0 +1,208 @@
+"""Thin Python binding of the C ABI (argument marshalling only).
+
+torch supplies device memory and the HIP stream; every step of the method
+runs in the library's kernels.  Names follow include/abddc.h.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+DEFAULT_OPTIONS = {
+    "theta_face": 10.0,
+    "theta_edge": 10.0,
+    "edge_variant": 0,
+    "edge_h_mode": 0,
+    "deluxe_source": 0,
+    "pinv_rtol": 1e-10,
+    "svd_rtol": 1e-8,
+    "tie_rtol": 1e-9,
+    "precision": 0,
+    "constraint_source": 0,
+    "mlp_weights": None,
+}
+
+
+def _stream_handle(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _dptr(t):
+    return C.c_void_p(t.data_ptr())
+
+
+class Solver:
+    """One assembled problem on one GPU (abddc_ctx)."""
+
+    def __init__(self, problem, device=0, stream=None):
+        self.lib = L.load()
+        self.device = device
+        torch.cuda.set_device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(device)
+        p = L.Problem()
+        self._keep = []
+        for a in range(3):
+            p.nsub[a] = int(problem["nsub"][a])
+            w = np.ascontiguousarray(problem["widths"][a], dtype=np.int32)
+            self._keep.append(w)
+            p.width[a] = w.ctypes.data_as(C.POINTER(C.c_int32))
+            p.length[a] = float(problem["length"][a])
+            p.beta0[a] = float(problem["beta0"][a])
+        for i in range(9):
+            p.beta1[i] = float(np.asarray(problem["beta1"]).reshape(9)[i])
+        nu = np.ascontiguousarray(problem["nu"], dtype=np.float64)
+        self._keep.append(nu)
+        p.nu = nu.ctypes.data_as(C.POINTER(C.c_double))
+        if problem.get("f_nodal") is not None:
+            f = np.ascontiguousarray(problem["f_nodal"], dtype=np.float64)
+            self._keep.append(f)
+            p.f_nodal = f.ctypes.data_as(C.POINTER(C.c_double))
+        p.f_const = float(problem["f_const"])
+        p.c = float(problem["c"])
+        p.tau = float(problem["tau"])
+        dev = L.Device(device, _stream_handle(self.stream))
+        ctx = C.c_void_p()
+        L.check(self.lib.abddc_assemble(C.byref(p), C.byref(dev), C.byref(ctx)))
+        self.ctx = ctx
+        nd, ng = C.c_int64(), C.c_int64()
+        ns, nf, ne = C.c_int32(), C.c_int32(), C.c_int32()
+        L.check(self.lib.abddc_query(ctx, C.byref(nd), C.byref(ng), C.byref(ns), C.byref(nf), C.byref(ne)))
+        self.n_dof, self.n_gamma = nd.value, ng.value
+        self.n_sub, self.n_face, self.n_edge = ns.value, nf.value, ne.value
+        self.counts = None
+
+    def setup_coarse_space(self, **opts):
+        o = dict(DEFAULT_OPTIONS)
+        o.update(opts)
+        s = L.Options()
+        for k, v in o.items():
+            if k == "mlp_weights":
+                s.mlp_weights = None if v is None else str(v).encode()
+            else:
+                setattr(s, k, v)
+        cnt = L.Counts()
+        L.check(self.lib.abddc_setup_coarse_space(self.ctx, C.byref(s), C.byref(cnt)))
+        self.counts = cnt.as_dict()
+        return self.counts
+
+    def _vec(self, n):
+        return torch.empty(n, dtype=torch.float64, device=f"cuda:{self.device}")
+
+    def apply_bddc(self, r, out=None):
+        z = self._vec(self.n_gamma) if out is None else out
+        L.check(self.lib.abddc_apply_bddc(self.ctx, _dptr(r), _dptr(z)))
+        return z
+
+    def apply_schur(self, x, out=None):
+        y = self._vec(self.n_gamma) if out is None else out
+        L.check(self.lib.abddc_apply_schur(self.ctx, _dptr(x), _dptr(y)))
+        return y
+
+    def rhs(self):
+        g = self._vec(self.n_gamma)
+        L.check(self.lib.abddc_get_rhs(self.ctx, _dptr(g)))
+        return g
+
+    def gmres_solve(self, restart=30, rtol=1e-8, maxit=300, out=None, history=True):
+        u = self._vec(self.n_dof) if out is None else out
+        info = L.SolveInfo()
+        hist = np.zeros(maxit + 1) if history else None
+        if history:
+            info.resid_history = hist.ctypes.data_as(C.POINTER(C.c_double))
+            info.resid_cap = hist.size
+        rc = L.check(self.lib.abddc_gmres_solve(self.ctx, int(restart), float(rtol), int(maxit), _dptr(u),
+                                                C.byref(info)))
+        res = {"iters": info.iters, "restarts": info.restarts, "relres_true": info.relres_true,
+               "t_setup_s": info.t_setup_s, "t_iter_s": info.t_iter_s, "converged": rc == L.OK}
+        if history:
+            res["history"] = hist[:info.iters].copy()
+        return u, res
+
+    def stage(self, stage, index=0):
+        n = self.lib.abddc_get_stage(self.ctx, stage, index, None, 0)
+        L.check(n)
+        buf = np.zeros(max(int(n), 1))
+        L.check(self.lib.abddc_get_stage(self.ctx, stage, index, buf.ctypes.data_as(C.POINTER(C.c_double)), n))
+        return buf[:n]
+
+    def phase_times(self):
+        t = np.zeros(9)
+        L.check(self.lib.abddc_phase_times(self.ctx, t.ctypes.data_as(C.POINTER(C.c_double)), 9))
+        return t
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            self.lib.abddc_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ------------------------------------------------------------- test hooks
+def _pack(mats, dtype, device):
+    offs, flat = [], []
+    pos = 0
+    for m in mats:
+        offs.append(pos)
+        flat.append(np.ascontiguousarray(m, dtype=dtype).ravel())
+        pos += m.size
+        pad = (-pos) % 64
+        flat.append(np.zeros(pad, dtype=dtype))
+        pos += pad
+    buf = torch.from_numpy(np.concatenate(flat) if flat else np.zeros(1, dtype)).to(device)
+    return buf, offs
+
+
+def partial_lu(mats, ks, precision=0, device="cuda"):
+    """Batched in-place partial LU (library primitive) on host matrices."""
+    lib = L.load()
+    dtype = np.float64 if precision == 0 else np.float32
+    buf, offs = _pack(mats, dtype, device)
+    rc = lib.abddc_test_partial_lu(len(mats), _dptr(buf), L.i64(offs), L.i32([m.shape[0] for m in mats]),
+                                   L.i32([m.shape[1] for m in mats]), L.i32([m.shape[1] for m in mats]),
+                                   L.i32(ks), precision, _stream_handle())
+    L.check(rc)
+    h = buf.cpu().numpy()
+    return [h[o:o + m.size].reshape(m.shape) for o, m in zip(offs, mats)]
+
+
+def gemm(As, Bs, Cs, transA=False, transB=False, alpha=1.0, beta=0.0, device="cuda"):
+    lib = L.load()
+    buf, offs = _pack(list(As) + list(Bs) + list(Cs), np.float64, device)
+    nb = len(As)
+    oA, oB, oC = offs[:nb], offs[nb:2 * nb], offs[2 * nb:]
+    m = [a.shape[1] if transA else a.shape[0] for a in As]
+    k = [a.shape[0] if transA else a.shape[1] for a in As]
+    n = [b.shape[0] if transB else b.shape[1] for b in Bs]
+    rc = lib.abddc_test_gemm(nb, _dptr(buf), L.i64(oA), L.i64(oB), L.i64(oC), L.i32(m), L.i32(n), L.i32(k),
+                             L.i32([a.shape[1] for a in As]), L.i32([b.shape[1] for b in Bs]),
+                             L.i32([c.shape[1] for c in Cs]), int(transA), int(transB), alpha, beta,
+                             _stream_handle())
+    L.check(rc)
+    h = buf.cpu().numpy()
+    return [h[o:o + c.size].reshape(c.shape) for o, c in zip(oC, Cs)]
+
+
+def sygv(As, Bs, device="cuda"):
+    lib = L.load()
+    n = [a.shape[0] for a in As]
+    Ws = [np.zeros(k) for k in n]
+    Xs = [np.zeros((k, k)) for k in n]
+    buf, offs = _pack(list(As) + list(Bs) + Ws + Xs, np.float64, device)
+    nb = len(As)
+    rc = lib.abddc_test_sygv(nb, _dptr(buf), L.i64(offs[:nb]), L.i64(offs[nb:2 * nb]),
+                             L.i64(offs[2 * nb:3 * nb]), L.i64(offs[3 * nb:]), L.i32(n), _stream_handle())
+    L.check(rc)
+    h = buf.cpu().numpy()
+    w = [h[o:o + k] for o, k in zip(offs[2 * nb:3 * nb], n)]
+    X = [h[o:o + k * k].reshape(k, k) for o, k in zip(offs[3 * nb:], n)]
+    return w, X

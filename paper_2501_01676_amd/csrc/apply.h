@@ -1,0 +1,52 @@
+// Per-iteration kernel launchers (GEMV, gather-sum, GMRES vector ops).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace abddc {
+
+constexpr int GEMV_ROWS_PER_WAVE = 4;
+constexpr int GEMV_ROWS_PER_BLOCK = 4 * GEMV_ROWS_PER_WAVE;
+constexpr int DOT_BLOCKS = 256;
+constexpr int GMRES_MAXR = 64;   // maximum restart length
+
+struct GemvMat {
+  int64_t moff;   // matrix offset (elements)
+  int64_t xoff;   // input offset into x or into the gather index
+  int64_t yoff;   // output offset
+  int32_t nrows, ncols, ld, pad;
+};
+
+struct GemvBlock {
+  int32_t mat;
+  int32_t row0;
+};
+
+// Device-resident GMRES scalars (Hessenberg, rotations, rotated rhs).
+struct GmresState {
+  double H[(GMRES_MAXR + 1) * GMRES_MAXR];
+  double cs[GMRES_MAXR], sn[GMRES_MAXR];
+  double g[GMRES_MAXR + 1];
+  double y[GMRES_MAXR];
+  double beta, hn, inv_hn, res;
+};
+
+template <class TM>
+void launch_gemv(const GemvBlock* blocks, int nblk, const GemvMat* mats, int max_ncols, const TM* M,
+                 const double* x, const int32_t* xidx, double* y, bool accumulate, hipStream_t s);
+void launch_gather_sum(const int32_t* ptr, const int32_t* idx, const double* src, double* dst, int64_t n,
+                       hipStream_t s);
+void launch_dots(const double* V, int64_t ldv, int nv, const double* w, int64_t n, double* partial, double* out,
+                 hipStream_t s);
+void launch_axpy_multi(const double* V, int64_t ldv, int nv, const double* coef, double sign, double* w, int64_t n,
+                       hipStream_t s);
+void launch_arnoldi_finish(GmresState* st, int j, const double* h1, const double* h2, const double* nrm2,
+                           hipStream_t s);
+void launch_gmres_trisolve(GmresState* st, int m, hipStream_t s);
+void launch_gmres_start(GmresState* st, const double* nrm2, hipStream_t s);
+void launch_scale_copy(const double* src, const double* factor, double* dst, int64_t n, hipStream_t s);
+void launch_sub(const double* a, const double* b, double* out, int64_t n, hipStream_t s);
+
+}  // namespace abddc

@@ -1,0 +1,69 @@
+// The library context: problem, topology, device data of every stage.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <array>
+#include <vector>
+
+#include "internal.h"
+#include "topology.h"
+
+struct abddc_ctx {
+  // ---------------------------------------------------------- problem
+  int device = 0;
+  hipStream_t stream = nullptr;
+  abddc::Topology topo;
+  double length[3], beta0[3], beta1[9], c = 0, f_const = 0, tau = 0;
+  bool have_fnodal = false;
+  int state = 0;  // 1 assembled, 2 set up
+  abddc_options opt{};
+
+  // --------------------------------------------------- per-subdomain
+  std::vector<int> nI, nB, nloc;           // interior, interface, total local dofs
+  std::vector<int64_t> aoff;               // [A | f] matrices, ld = nloc + 1
+  std::vector<int64_t> soff;               // S, B matrices (nB x nB)
+  std::vector<int64_t> goff;               // vectors of length nB
+  abddc::DevBuf<double> dA, dS, dB, dg;
+  abddc::DevBuf<int32_t> d_gam;            // concatenated Gamma_i -> interface index
+  abddc::DevBuf<int32_t> d_own_ptr, d_own_idx;   // interface dof -> positions in goff space
+  abddc::DevBuf<double> d_ghat;
+  abddc::DevBuf<double> d_nu, d_fnodal;
+  abddc::DevBuf<int32_t> d_iface_dof, d_int_dof;  // recovery scatter maps (goff / interior space)
+  std::vector<int64_t> ioff;               // interior offsets (concatenated interior dofs)
+
+  // ---------------------------------------------------- coarse space
+  std::vector<int> pF;                     // primal count per face (kind index)
+  std::vector<int> rE;                     // primal count per edge (kind index)
+  std::vector<int> nselE;                  // selected eigenvectors per edge
+  std::vector<int64_t> dxoff;              // deluxe block of (object, member) [8 per object]
+  abddc::DevBuf<double> dD;
+  std::vector<int64_t> tfoff, teoff;       // face / edge bases
+  abddc::DevBuf<double> dTF, dTE;
+  std::vector<int64_t> wfoff, weoff;       // eigenvalues (mu) of face / edge GEPs
+  abddc::DevBuf<double> dWF, dWE;
+  int n_primal = 0, n_vertex = 0, pnum_face = 0, pnum_edge = 0, n_ties = 0;
+
+  // ----------------------------------------------------- apply operators
+  std::vector<int> nPi;                    // primal unknowns per subdomain
+  std::vector<int64_t> moff;               // [L; V] (nB + nPi) x nB
+  std::vector<int64_t> uoff;               // U  nB x nPi
+  std::vector<int64_t> ooff;               // output vectors of length nB + nPi
+  std::vector<int64_t> poff;               // concatenated primal ids per subdomain
+  abddc::DevBuf<double> dM, dU, dSPinv;
+  abddc::DevBuf<float> dM32, dU32;
+  abddc::DevBuf<int32_t> d_pid;            // concatenated Pi_i -> global primal id
+  abddc::DevBuf<int32_t> d_pown_ptr, d_pown_idx;   // primal id -> positions in ooff space
+  abddc::DevBuf<int32_t> d_aown_ptr, d_aown_idx;   // interface dof -> positions in ooff space
+  abddc::DevBuf<int64_t> d_moff, d_uoff, d_goff, d_ooff, d_poff, d_soff;
+  abddc::DevBuf<int32_t> d_nB, d_nPi;
+  abddc::DevBuf<int32_t> d_gemv_blocks_M, d_gemv_blocks_U, d_gemv_blocks_S, d_gemv_blocks_C;
+  int nblk_M = 0, nblk_U = 0, nblk_S = 0, nblk_C = 0;
+  abddc::DevBuf<double> d_out, d_work_s, d_bpi, d_xpi;  // apply/Schur work vectors
+
+  // ------------------------------------------------------------- misc
+  abddc::DevBuf<int> d_flag;
+  std::array<double, 16> phase{};
+  hipEvent_t ev[20] = {};
+  bool events = false;
+};

@@ -1,0 +1,180 @@
+// Internal declarations of the gfx950 adaptive BDDC library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/abddc.h"
+
+namespace abddc {
+
+struct Error : std::runtime_error {
+  int code;
+  Error(int c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+#define ABDDC_HIP(call)                                                                      \
+  do {                                                                                       \
+    hipError_t e_ = (call);                                                                  \
+    if (e_ != hipSuccess)                                                                    \
+      throw ::abddc::Error(e_ == hipErrorOutOfMemory ? ABDDC_ENOMEM : ABDDC_EDEVICE,         \
+                           std::string(#call) + ": " + hipGetErrorString(e_));               \
+  } while (0)
+
+#define ABDDC_REQUIRE(cond, code, msg)                 \
+  do {                                                 \
+    if (!(cond)) throw ::abddc::Error((code), (msg));  \
+  } while (0)
+
+// Owning device allocation.
+template <class T>
+struct DevBuf {
+  T* p = nullptr;
+  size_t n = 0;
+  DevBuf() = default;
+  explicit DevBuf(size_t count) { alloc(count); }
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  DevBuf(DevBuf&& o) noexcept : p(o.p), n(o.n) { o.p = nullptr; o.n = 0; }
+  DevBuf& operator=(DevBuf&& o) noexcept {
+    release();
+    p = o.p; n = o.n; o.p = nullptr; o.n = 0;
+    return *this;
+  }
+  ~DevBuf() { release(); }
+  void alloc(size_t count) {
+    release();
+    n = count;
+    if (count) ABDDC_HIP(hipMalloc(&p, count * sizeof(T)));
+  }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    n = 0;
+  }
+  void upload(const std::vector<T>& h, hipStream_t s) {
+    if (h.size() > n) alloc(h.size());
+    if (!h.empty()) ABDDC_HIP(hipMemcpyAsync(p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, s));
+  }
+  void zero(hipStream_t s) {
+    if (n) ABDDC_HIP(hipMemsetAsync(p, 0, n * sizeof(T), s));
+  }
+};
+
+template <class T>
+inline DevBuf<T> to_device(const std::vector<T>& h, hipStream_t s) {
+  DevBuf<T> d(h.size());
+  if (!h.empty()) ABDDC_HIP(hipMemcpyAsync(d.p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, s));
+  return d;
+}
+
+template <class T>
+inline std::vector<T> to_host(const T* d, size_t n, hipStream_t s) {
+  std::vector<T> h(n);
+  if (n) {
+    ABDDC_HIP(hipMemcpyAsync(h.data(), d, n * sizeof(T), hipMemcpyDeviceToHost, s));
+    ABDDC_HIP(hipStreamSynchronize(s));
+  }
+  return h;
+}
+
+// ------------------------------------------------------------ descriptors
+// One matrix of a batched in-place partial LU: eliminate the first k pivots
+// of an nrow x ncol row-major matrix with leading dimension ld.
+template <class T>
+struct PluDesc {
+  T* a;
+  int32_t nrow, ncol, ld, k;
+};
+
+// One product of a batched GEMM: C = alpha op(A) op(B) + beta C (row-major).
+template <class T>
+struct GemmDesc {
+  const T* A;
+  const T* B;
+  T* C;
+  int32_t m, n, k, lda, ldb, ldc;
+};
+
+// One matrix gather: dst[r][c] = scale * src[rmap[r]][cmap[c]] (map < 0 -> 0,
+// null map = identity).
+struct GatherDesc {
+  const double* src;
+  double* dst;
+  const int32_t* rmap;
+  const int32_t* cmap;
+  int32_t nr, nc, lds, ldd;
+  double scale;
+};
+
+// dst[rows[q]][cols[q]] = val for q < n.
+struct SetDesc {
+  double* dst;
+  const int32_t* rows;
+  const int32_t* cols;
+  int32_t n, ld;
+  double val;
+};
+
+// dst = (src + src^T) / 2 (n x n).
+struct SymDesc {
+  const double* src;
+  double* dst;
+  int32_t n, lds, ldd;
+};
+
+// Symmetric pseudo-inverse: out = sum_{lambda > rtol lambda_max} v v^T / lambda.
+struct PinvDesc {
+  const double* M;
+  double* out;
+  int32_t n, ld;
+};
+
+// Householder completion: T (n x n) orthogonal, first p columns span range(X).
+struct QrDesc {
+  const double* X;
+  double* T;
+  int32_t n, p, ldx;
+};
+
+// Left singular basis of G (n x ncol): T = U sorted by sigma descending,
+// rank[0] = #{sigma > rtol sigma_max}.
+struct SvdDesc {
+  const double* G;
+  double* T;
+  int32_t* rank;
+  int32_t n, ncol, ldg;
+};
+
+// Batched symmetric-definite eigenproblem A y = mu B y (n x n, ld n).
+struct SygvDesc {
+  const double* A;
+  const double* B;
+  double* w;   // mu ascending
+  double* X;   // L Y
+  int32_t n;
+};
+
+// ---------------------------------------------------------------- launchers
+// k_dense.hip
+template <class T>
+void partial_lu(const std::vector<PluDesc<T>>& d, int* dflag, hipStream_t s);
+template <class T>
+void gemm_batched(const std::vector<GemmDesc<T>>& d, bool transA, bool transB, T alpha, T beta,
+                  hipStream_t s);
+void gather_batched(const std::vector<GatherDesc>& d, hipStream_t s);
+
+void set_batched(const std::vector<SetDesc>& d, hipStream_t s);
+void sym_batched(const std::vector<SymDesc>& d, hipStream_t s);
+
+// k_eig.hip
+void sygv_batched(const std::vector<SygvDesc>& d, int* dflag, hipStream_t s);
+void pinv_batched(const std::vector<PinvDesc>& d, double rtol, hipStream_t s);
+void qr_complete_batched(const std::vector<QrDesc>& d, hipStream_t s);
+void svd_left_batched(const std::vector<SvdDesc>& d, double rtol, hipStream_t s);
+
+}  // namespace abddc

@@ -1,0 +1,245 @@
+// Per-iteration kernels: batched ragged GEMV with gathered input (the local
+// and coarse pieces of M^{-1} and the local Schur complements of Shat), the
+// deterministic interface gather-sum R^T (sum over the subdomains sharing a
+// dof, fixed order), and the GMRES vector kernels (multi-dot with wavefront
+// reductions, multi-axpy, Givens update of the Hessenberg column).
+//
+// These kernels move O(bytes) with O(1) flops per byte: they are bound by
+// HBM bandwidth, so the design goal is coalesced 512-byte wave loads of
+// matrix rows and no re-reads.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+
+#include "apply.h"
+#include "internal.h"
+
+namespace abddc {
+
+namespace {
+
+__device__ inline double wave_sum(double v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  return v;
+}
+
+// A workgroup = 4 waves x GEMV_ROWS_PER_WAVE rows of one matrix.  The
+// gathered input vector is staged in LDS once per workgroup.
+template <class TM>
+__global__ void __launch_bounds__(256) gemv_kernel(const GemvBlock* __restrict__ blocks,
+                                                   const GemvMat* __restrict__ mats, const TM* __restrict__ M,
+                                                   const double* __restrict__ x, const int32_t* __restrict__ xidx,
+                                                   double* __restrict__ y, int accumulate) {
+  extern __shared__ double xs[];
+  const GemvBlock blk = blocks[blockIdx.x];
+  const GemvMat d = mats[blk.mat];
+  for (int c = threadIdx.x; c < d.ncols; c += blockDim.x)
+    xs[c] = xidx ? x[xidx[d.xoff + c]] : x[d.xoff + c];
+  __syncthreads();
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int r0 = blk.row0 + w * GEMV_ROWS_PER_WAVE;
+  double acc[GEMV_ROWS_PER_WAVE];
+#pragma unroll
+  for (int q = 0; q < GEMV_ROWS_PER_WAVE; ++q) acc[q] = 0.0;
+  const TM* base = M + d.moff + (int64_t)r0 * d.ld;
+  const int nr = min(GEMV_ROWS_PER_WAVE, d.nrows - r0);
+  if (nr == GEMV_ROWS_PER_WAVE) {
+    for (int c = lane; c < d.ncols; c += 64) {
+      const double xv = xs[c];
+#pragma unroll
+      for (int q = 0; q < GEMV_ROWS_PER_WAVE; ++q) acc[q] += (double)base[(int64_t)q * d.ld + c] * xv;
+    }
+  } else {
+    for (int c = lane; c < d.ncols; c += 64) {
+      const double xv = xs[c];
+      for (int q = 0; q < nr; ++q) acc[q] += (double)base[(int64_t)q * d.ld + c] * xv;
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < GEMV_ROWS_PER_WAVE; ++q) {
+    const double v = wave_sum(acc[q]);
+    if (lane == 0 && q < nr) {
+      double* yp = y + d.yoff + r0 + q;
+      *yp = accumulate ? *yp + v : v;
+    }
+  }
+}
+
+__global__ void gather_sum_kernel(const int32_t* __restrict__ ptr, const int32_t* __restrict__ idx,
+                                  const double* __restrict__ src, double* __restrict__ dst, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double v = 0.0;
+  for (int j = ptr[i]; j < ptr[i + 1]; ++j) v += src[idx[j]];
+  dst[i] = v;
+}
+
+// partial[b * 32 + j] = sum over block b's chunk of V[j][i] w[i]
+__global__ void __launch_bounds__(256) dots_partial_kernel(const double* __restrict__ V, int64_t ldv, int nv,
+                                                           const double* __restrict__ w, int64_t n,
+                                                           double* __restrict__ partial) {
+  __shared__ double red[4];
+  const int64_t chunk = (n + gridDim.x - 1) / gridDim.x;
+  const int64_t lo = blockIdx.x * chunk, hi = min(n, lo + chunk);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int j = 0; j < nv; ++j) {
+    double a = 0.0;
+    const double* vj = V + (int64_t)j * ldv;
+    for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) a += vj[i] * w[i];
+    a = wave_sum(a);
+    if (lane == 0) red[wv] = a;
+    __syncthreads();
+    if (threadIdx.x == 0) partial[blockIdx.x * 32 + j] = (red[0] + red[1]) + (red[2] + red[3]);
+    __syncthreads();
+  }
+}
+
+__global__ void dots_final_kernel(const double* __restrict__ partial, int nblk, int nv, double* __restrict__ out) {
+  const int j = threadIdx.x;
+  if (j >= nv) return;
+  double s = 0.0;
+  for (int b = 0; b < nblk; ++b) s += partial[b * 32 + j];
+  out[j] = s;
+}
+
+// w[i] += sign * sum_j coef[j] V[j][i]
+__global__ void axpy_multi_kernel(const double* __restrict__ V, int64_t ldv, int nv, const double* __restrict__ coef,
+                                  double sign, double* __restrict__ w, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double s = 0.0;
+  for (int j = 0; j < nv; ++j) s += coef[j] * V[(int64_t)j * ldv + i];
+  w[i] += sign * s;
+}
+
+// Hessenberg column j from the two Gram-Schmidt passes and the norm, the
+// previous Givens rotations, a new rotation, the rotated rhs g and the
+// residual estimate |g[j+1]|.
+__global__ void arnoldi_finish_kernel(GmresState* st, int j, const double* __restrict__ h1,
+                                      const double* __restrict__ h2, const double* __restrict__ nrm2) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double col[GMRES_MAXR + 1];
+  for (int i = 0; i <= j; ++i) col[i] = h1[i] + h2[i];
+  const double hn = sqrt(fmax(nrm2[0], 0.0));
+  col[j + 1] = hn;
+  for (int i = 0; i < j; ++i) {
+    const double t = st->cs[i] * col[i] + st->sn[i] * col[i + 1];
+    col[i + 1] = -st->sn[i] * col[i] + st->cs[i] * col[i + 1];
+    col[i] = t;
+  }
+  const double a = col[j], b = col[j + 1];
+  const double r = hypot(a, b);
+  double c = 1.0, s = 0.0;
+  if (r != 0.0) {
+    c = a / r;
+    s = b / r;
+  }
+  st->cs[j] = c;
+  st->sn[j] = s;
+  col[j] = r;
+  col[j + 1] = 0.0;
+  st->g[j + 1] = -s * st->g[j];
+  st->g[j] = c * st->g[j];
+  for (int i = 0; i <= j + 1; ++i) st->H[i * GMRES_MAXR + j] = col[i];
+  st->hn = hn;
+  st->inv_hn = hn > 0.0 ? 1.0 / hn : 0.0;
+  st->res = fabs(st->g[j + 1]);
+}
+
+// y = H(0:m, 0:m)^{-1} g(0:m) (upper triangular)
+__global__ void gmres_trisolve_kernel(GmresState* st, int m) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  for (int i = m - 1; i >= 0; --i) {
+    double v = st->g[i];
+    for (int q = i + 1; q < m; ++q) v -= st->H[i * GMRES_MAXR + q] * st->y[q];
+    st->y[i] = v / st->H[i * GMRES_MAXR + i];
+  }
+}
+
+__global__ void gmres_start_kernel(GmresState* st, const double* __restrict__ nrm2) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const double b = sqrt(fmax(nrm2[0], 0.0));
+  for (int i = 0; i <= GMRES_MAXR; ++i) st->g[i] = 0.0;
+  st->g[0] = b;
+  st->beta = b;
+  st->inv_hn = b > 0.0 ? 1.0 / b : 0.0;
+  st->res = b;
+}
+
+__global__ void scale_copy_kernel(const double* __restrict__ src, const double* __restrict__ factor,
+                                  double* __restrict__ dst, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = src[i] * factor[0];
+}
+
+__global__ void sub_kernel(const double* __restrict__ a, const double* __restrict__ b, double* __restrict__ out,
+                           int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = a[i] - b[i];
+}
+
+inline unsigned nblocks(int64_t n) { return (unsigned)std::max<int64_t>(1, (n + 255) / 256); }
+
+}  // namespace
+
+template <class TM>
+void launch_gemv(const GemvBlock* blocks, int nblk, const GemvMat* mats, int max_ncols, const TM* M,
+                 const double* x, const int32_t* xidx, double* y, bool accumulate, hipStream_t s) {
+  if (nblk == 0) return;
+  gemv_kernel<TM><<<nblk, 256, max_ncols * sizeof(double), s>>>(blocks, mats, M, x, xidx, y, accumulate ? 1 : 0);
+  ABDDC_HIP(hipGetLastError());
+}
+template void launch_gemv<double>(const GemvBlock*, int, const GemvMat*, int, const double*, const double*,
+                                  const int32_t*, double*, bool, hipStream_t);
+template void launch_gemv<float>(const GemvBlock*, int, const GemvMat*, int, const float*, const double*,
+                                 const int32_t*, double*, bool, hipStream_t);
+
+void launch_gather_sum(const int32_t* ptr, const int32_t* idx, const double* src, double* dst, int64_t n,
+                       hipStream_t s) {
+  if (n == 0) return;
+  gather_sum_kernel<<<nblocks(n), 256, 0, s>>>(ptr, idx, src, dst, n);
+  ABDDC_HIP(hipGetLastError());
+}
+
+void launch_dots(const double* V, int64_t ldv, int nv, const double* w, int64_t n, double* partial, double* out,
+                 hipStream_t s) {
+  dots_partial_kernel<<<DOT_BLOCKS, 256, 0, s>>>(V, ldv, nv, w, n, partial);
+  dots_final_kernel<<<1, 64, 0, s>>>(partial, DOT_BLOCKS, nv, out);
+  ABDDC_HIP(hipGetLastError());
+}
+
+void launch_axpy_multi(const double* V, int64_t ldv, int nv, const double* coef, double sign, double* w, int64_t n,
+                       hipStream_t s) {
+  axpy_multi_kernel<<<nblocks(n), 256, 0, s>>>(V, ldv, nv, coef, sign, w, n);
+  ABDDC_HIP(hipGetLastError());
+}
+
+void launch_arnoldi_finish(GmresState* st, int j, const double* h1, const double* h2, const double* nrm2,
+                           hipStream_t s) {
+  arnoldi_finish_kernel<<<1, 64, 0, s>>>(st, j, h1, h2, nrm2);
+  ABDDC_HIP(hipGetLastError());
+}
+
+void launch_gmres_trisolve(GmresState* st, int m, hipStream_t s) {
+  gmres_trisolve_kernel<<<1, 64, 0, s>>>(st, m);
+  ABDDC_HIP(hipGetLastError());
+}
+
+void launch_gmres_start(GmresState* st, const double* nrm2, hipStream_t s) {
+  gmres_start_kernel<<<1, 64, 0, s>>>(st, nrm2);
+  ABDDC_HIP(hipGetLastError());
+}
+
+void launch_scale_copy(const double* src, const double* factor, double* dst, int64_t n, hipStream_t s) {
+  scale_copy_kernel<<<nblocks(n), 256, 0, s>>>(src, factor, dst, n);
+  ABDDC_HIP(hipGetLastError());
+}
+
+void launch_sub(const double* a, const double* b, double* out, int64_t n, hipStream_t s) {
+  sub_kernel<<<nblocks(n), 256, 0, s>>>(a, b, out, n);
+  ABDDC_HIP(hipGetLastError());
+}
+
+}  // namespace abddc

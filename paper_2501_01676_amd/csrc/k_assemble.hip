@@ -1,0 +1,232 @@
+// Assembly of the GLS-stabilised trilinear-box system (Section 2) into dense
+// per-subdomain matrices [A^(i) | f^(i)] in local order [interior; Gamma_i]
+// (Section 3), extraction of S^(i), g^(i), B^(i) after the interior
+// elimination, and interior recovery u_I = A_II^{-1}(f_I - A_IB u_B).
+//
+// a(u, v) = int nu grad u . grad v + C_K Lu Lv + ctilde u v
+//           + 1/2 (a . grad u v - a . grad v u),
+// g(v)    = int f v + C_K f Lv,   L u = a . grad u + c u inside a box,
+// C_K from the Peclet switch with tau; entry (i, j) = a(phi_j, phi_i).
+
+#include <hip/hip_runtime.h>
+
+#include "assemble.h"
+#include "internal.h"
+
+namespace abddc {
+
+namespace {
+
+__device__ inline void shape(double s, double t, double u, int i, double hx, double hy, double hz,
+                             double& phi, double& gx, double& gy, double& gz) {
+  const int a = i & 1, b = (i >> 1) & 1, c = (i >> 2) & 1;
+  const double fs = a ? s : 1.0 - s, ft = b ? t : 1.0 - t, fu = c ? u : 1.0 - u;
+  phi = fs * ft * fu;
+  gx = (a ? 1.0 : -1.0) / hx * ft * fu;
+  gy = fs * (b ? 1.0 : -1.0) / hy * fu;
+  gz = fs * ft * (c ? 1.0 : -1.0) / hz;
+}
+
+// One thread per (element, test function i): row i of A_K and F_K[i].
+__global__ void elem_kernel(ElemParams P, const double* __restrict__ nu, const double* __restrict__ fnodal,
+                            double* __restrict__ Ae, double* __restrict__ Fe) {
+  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (tid >= P.n_elem * 8) return;
+  const int64_t e = tid >> 3;
+  const int i = (int)(tid & 7);
+  const int ex = (int)(e % P.ne[0]);
+  const int ey = (int)((e / P.ne[0]) % P.ne[1]);
+  const int ez = (int)(e / ((int64_t)P.ne[0] * P.ne[1]));
+  const double hx = P.h[0], hy = P.h[1], hz = P.h[2];
+  const double x0 = ex * hx, y0 = ey * hy, z0 = ez * hz;
+  const double nue = nu[e];
+  // |a|_K: maximum over the corners (|a| is convex for affine a)
+  double amax = 0.0;
+  for (int k = 0; k < 8; ++k) {
+    const double xc = x0 + (k & 1) * hx, yc = y0 + ((k >> 1) & 1) * hy, zc = z0 + ((k >> 2) & 1) * hz;
+    const double ax = P.b0[0] + P.b1[0] * xc + P.b1[1] * yc + P.b1[2] * zc;
+    const double ay = P.b0[1] + P.b1[3] * xc + P.b1[4] * yc + P.b1[5] * zc;
+    const double az = P.b0[2] + P.b1[6] * xc + P.b1[7] * yc + P.b1[8] * zc;
+    amax = fmax(amax, sqrt(ax * ax + ay * ay + az * az));
+  }
+  const double hK = sqrt(hx * hx + hy * hy + hz * hz);
+  const double peclet = hK * amax / (2.0 * nue);
+  const double CK = (peclet >= 1.0) ? P.tau * hK / (2.0 * amax) : P.tau * hK * hK / (4.0 * nue);
+  const double ctil = P.c - 0.5 * (P.b1[0] + P.b1[4] + P.b1[8]);
+  int64_t nodes[8];
+  if (fnodal) {
+    for (int k = 0; k < 8; ++k)
+      nodes[k] = (ex + (k & 1)) + (int64_t)P.nn[0] * ((ey + ((k >> 1) & 1)) + (int64_t)P.nn[1] * (ez + ((k >> 2) & 1)));
+  }
+  const double qp[3] = {0.5 - 0.5 * sqrt(0.6), 0.5, 0.5 + 0.5 * sqrt(0.6)};
+  const double qw[3] = {5.0 / 18.0, 8.0 / 18.0, 5.0 / 18.0};
+  const double vol = hx * hy * hz;
+  double row[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  double fi = 0.0;
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b)
+      for (int cq = 0; cq < 3; ++cq) {
+        const double s = qp[a], t = qp[b], u = qp[cq];
+        const double w = qw[a] * qw[b] * qw[cq] * vol;
+        const double xq = x0 + s * hx, yq = y0 + t * hy, zq = z0 + u * hz;
+        const double ax = P.b0[0] + P.b1[0] * xq + P.b1[1] * yq + P.b1[2] * zq;
+        const double ay = P.b0[1] + P.b1[3] * xq + P.b1[4] * yq + P.b1[5] * zq;
+        const double az = P.b0[2] + P.b1[6] * xq + P.b1[7] * yq + P.b1[8] * zq;
+        double phii, gix, giy, giz;
+        shape(s, t, u, i, hx, hy, hz, phii, gix, giy, giz);
+        const double agi = ax * gix + ay * giy + az * giz;
+        const double Li = agi + P.c * phii;
+        double fq = P.f_const;
+        if (fnodal) {
+          fq = 0.0;
+          for (int k = 0; k < 8; ++k) {
+            double pk, g1, g2, g3;
+            shape(s, t, u, k, hx, hy, hz, pk, g1, g2, g3);
+            fq += fnodal[nodes[k]] * pk;
+          }
+        }
+        for (int j = 0; j < 8; ++j) {
+          double phij, gjx, gjy, gjz;
+          shape(s, t, u, j, hx, hy, hz, phij, gjx, gjy, gjz);
+          const double agj = ax * gjx + ay * gjy + az * gjz;
+          const double Lj = agj + P.c * phij;
+          row[j] += w * (nue * (gix * gjx + giy * gjy + giz * gjz) + CK * Li * Lj + ctil * phii * phij +
+                         0.5 * (agj * phii - agi * phij));
+        }
+        fi += w * (fq * phii + CK * fq * Li);
+      }
+  for (int j = 0; j < 8; ++j) Ae[e * 64 + i * 8 + j] = row[j];
+  Fe[e * 8 + i] = fi;
+}
+
+// One thread per local row (subdomain s, local node p): the 27 possible
+// couplings and the load, summed over the elements of s in a fixed order.
+__global__ void scatter_kernel(const SubAsm* __restrict__ subs, const int32_t* __restrict__ rowsub,
+                               const int32_t* __restrict__ lnode, const int32_t* __restrict__ lmap,
+                               int64_t nrows, int nn0, int nn1, int ne0, int ne1, const double* __restrict__ Ae,
+                               const double* __restrict__ Fe, double* __restrict__ A) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nrows) return;
+  const int s = rowsub[t];
+  const SubAsm S = subs[s];
+  const int p = (int)(t - S.loff);
+  const int node = lnode[t];
+  const int ix = node % nn0, iy = (node / nn0) % nn1, iz = node / (nn0 * nn1);
+  const int bx = S.ebox[1] - S.ebox[0] + 1, by = S.ebox[3] - S.ebox[2] + 1;
+  double* arow = A + S.aoff + (int64_t)p * S.ld;
+  for (int dz = -1; dz <= 1; ++dz)
+    for (int dy = -1; dy <= 1; ++dy)
+      for (int dx = -1; dx <= 1; ++dx) {
+        const int qx = ix + dx, qy = iy + dy, qz = iz + dz;
+        if (qx < S.ebox[0] || qx > S.ebox[1] || qy < S.ebox[2] || qy > S.ebox[3] || qz < S.ebox[4] ||
+            qz > S.ebox[5])
+          continue;
+        const int lq = lmap[S.lmoff + (qx - S.ebox[0]) + bx * ((qy - S.ebox[2]) + by * (qz - S.ebox[4]))];
+        if (lq < 0) continue;
+        double sum = 0.0;
+        for (int ez = max(max(iz, qz) - 1, S.ebox[4]); ez <= min(min(iz, qz), S.ebox[5] - 1); ++ez)
+          for (int ey = max(max(iy, qy) - 1, S.ebox[2]); ey <= min(min(iy, qy), S.ebox[3] - 1); ++ey)
+            for (int ex = max(max(ix, qx) - 1, S.ebox[0]); ex <= min(min(ix, qx), S.ebox[1] - 1); ++ex) {
+              const int64_t e = ex + (int64_t)ne0 * (ey + (int64_t)ne1 * ez);
+              const int il = (ix - ex) + 2 * (iy - ey) + 4 * (iz - ez);
+              const int jl = (qx - ex) + 2 * (qy - ey) + 4 * (qz - ez);
+              sum += Ae[e * 64 + il * 8 + jl];
+            }
+        arow[lq] = sum;
+      }
+  double f = 0.0;
+  for (int ez = max(iz - 1, S.ebox[4]); ez <= min(iz, S.ebox[5] - 1); ++ez)
+    for (int ey = max(iy - 1, S.ebox[2]); ey <= min(iy, S.ebox[3] - 1); ++ey)
+      for (int ex = max(ix - 1, S.ebox[0]); ex <= min(ix, S.ebox[1] - 1); ++ex) {
+        const int64_t e = ex + (int64_t)ne0 * (ey + (int64_t)ne1 * ez);
+        f += Fe[e * 8 + (ix - ex) + 2 * (iy - ey) + 4 * (iz - ez)];
+      }
+  arow[S.nloc] = f;
+}
+
+// S^(i) = trailing block after eliminating the interior, g^(i) = trailing
+// rhs column, B^(i) = (S + S^T) / 2.
+__global__ void extract_kernel(const SubAsm* __restrict__ subs, const double* __restrict__ A,
+                               double* __restrict__ S, double* __restrict__ B, double* __restrict__ g) {
+  const SubAsm d = subs[blockIdx.y];
+  const int nB = d.nloc - d.nI;
+  const double* T = A + d.aoff + (int64_t)d.nI * d.ld + d.nI;
+  for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < nB * nB; idx += gridDim.x * blockDim.x) {
+    const int i = idx / nB, j = idx % nB;
+    const double sij = T[(int64_t)i * d.ld + j];
+    S[d.soff + idx] = sij;
+    B[d.soff + idx] = 0.5 * (sij + T[(int64_t)j * d.ld + i]);
+    if (j == 0) g[d.goff + i] = T[(int64_t)i * d.ld + nB];
+  }
+}
+
+// u_I = U11^{-1} (c - U12 u_B) with A_II = L11 U11, c = L11^{-1} f_I and
+// U12 = L11^{-1} A_IB left in place by the interior elimination.
+__global__ void __launch_bounds__(256) recover_kernel(const SubAsm* __restrict__ subs, const double* __restrict__ A,
+                                                      const int32_t* __restrict__ gam, const double* __restrict__ uhat,
+                                                      const int32_t* __restrict__ int_dof, double* __restrict__ u,
+                                                      double* __restrict__ work) {
+  const SubAsm d = subs[blockIdx.x];
+  const int nI = d.nI, nB = d.nloc - d.nI;
+  double* t = work + d.ioff;
+  const double* M = A + d.aoff;
+  for (int r = threadIdx.x; r < nI; r += blockDim.x) {
+    double v = M[(int64_t)r * d.ld + d.nloc];
+    const double* row = M + (int64_t)r * d.ld + nI;
+    for (int c = 0; c < nB; ++c) v -= row[c] * uhat[gam[d.goff + c]];
+    t[r] = v;
+  }
+  __syncthreads();
+  __shared__ double xr;
+  for (int r = nI - 1; r >= 0; --r) {
+    if (threadIdx.x == 0) {
+      xr = t[r] / M[(int64_t)r * d.ld + r];
+      t[r] = xr;
+    }
+    __syncthreads();
+    const double x = xr;
+    for (int q = threadIdx.x; q < r; q += blockDim.x) t[q] -= M[(int64_t)q * d.ld + r] * x;
+    __syncthreads();
+  }
+  for (int r = threadIdx.x; r < nI; r += blockDim.x) u[int_dof[d.ioff + r]] = t[r];
+}
+
+__global__ void iface_scatter_kernel(const double* __restrict__ uhat, const int32_t* __restrict__ iface_dof,
+                                     int64_t n, double* __restrict__ u) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g < n) u[iface_dof[g]] = uhat[g];
+}
+
+}  // namespace
+
+void launch_elem(const ElemParams& P, const double* nu, const double* fnodal, double* Ae, double* Fe,
+                 hipStream_t s) {
+  const int64_t n = P.n_elem * 8;
+  elem_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(P, nu, fnodal, Ae, Fe);
+  ABDDC_HIP(hipGetLastError());
+}
+
+void launch_scatter(const SubAsm* subs, const int32_t* rowsub, const int32_t* lnode, const int32_t* lmap,
+                    int64_t nrows, const int nn[3], const int ne[3], const double* Ae, const double* Fe, double* A,
+                    hipStream_t s) {
+  scatter_kernel<<<(unsigned)((nrows + 255) / 256), 256, 0, s>>>(subs, rowsub, lnode, lmap, nrows, nn[0], nn[1],
+                                                                  ne[0], ne[1], Ae, Fe, A);
+  ABDDC_HIP(hipGetLastError());
+}
+
+void launch_extract(const SubAsm* subs, int nsub, int max_nB, const double* A, double* S, double* B, double* g,
+                    hipStream_t s) {
+  const int gx = std::min(1024, (max_nB * max_nB + 255) / 256);
+  extract_kernel<<<dim3(std::max(gx, 1), nsub), 256, 0, s>>>(subs, A, S, B, g);
+  ABDDC_HIP(hipGetLastError());
+}
+
+void launch_recover(const SubAsm* subs, int nsub, const double* A, const int32_t* gam, const double* uhat,
+                    const int32_t* int_dof, const int32_t* iface_dof, int64_t n_gamma, double* u, double* work,
+                    hipStream_t s) {
+  recover_kernel<<<nsub, 256, 0, s>>>(subs, A, gam, uhat, int_dof, u, work);
+  iface_scatter_kernel<<<(unsigned)((n_gamma + 255) / 256), 256, 0, s>>>(uhat, iface_dof, n_gamma, u);
+  ABDDC_HIP(hipGetLastError());
+}
+
+}  // namespace abddc

@@ -1,0 +1,54 @@
+// Host-side box-partition topology: interface classes and orderings.
+//
+// A free grid node on an internal subdomain cut plane in exactly one / two /
+// three axes is a face / edge / vertex node; nodes with the same set n(x)
+// of sharing subdomains form one interface object (Section 3 defers the
+// definitions of faces, edges and vertices; this is the box-partition rule).
+// Orderings are part of the C ABI (include/abddc.h).
+#pragma once
+
+#include <cstdint>
+#include <vector>
+
+namespace abddc {
+
+enum ObjKind { KIND_FACE = 0, KIND_EDGE = 1, KIND_VERTEX = 2 };
+
+struct Object {
+  int kind;
+  std::vector<int> subs;        // sorted subdomain ids n(X)
+  std::vector<int64_t> nodes;   // sorted grid node ids
+  int64_t gstart;               // first interface index
+  int n;                        // number of dofs
+};
+
+struct SubInfo {
+  int ebox[3][2];               // element index range [lo, hi) per axis
+  std::vector<int64_t> interior;  // grid node ids, sorted
+  std::vector<int64_t> gamma;     // interface indices, sorted
+  std::vector<int> objs;          // objects of Gamma_i, interface order
+  std::vector<int> obj_off;       // local offset of each object inside Gamma_i
+  int nI = 0, nB = 0;
+  int local_pos(int obj) const;   // offset of object obj in Gamma_i or -1
+};
+
+struct Topology {
+  int nsub[3];
+  std::vector<int> widths[3];
+  std::vector<int> cuts[3];
+  int ne[3], nn[3];
+  int64_t n_nodes, n_elem, n_dof, n_gamma;
+  int n_sub;
+  std::vector<int64_t> dof_of_node;   // -1 for Dirichlet nodes
+  std::vector<int64_t> iface_of_node; // -1 for non-interface nodes
+  std::vector<Object> objects;
+  std::vector<int> faces, edges, vertices;   // indices into objects
+  std::vector<int> kind_index;               // position of object within its kind
+  std::vector<SubInfo> sub;
+
+  void build(const int nsub_in[3], const int* const width_in[3]);
+  int64_t node_id(int64_t ix, int64_t iy, int64_t iz) const { return ix + nn[0] * (iy + (int64_t)nn[1] * iz); }
+  int sub_id(int sx, int sy, int sz) const { return sx + nsub[0] * (sy + nsub[1] * sz); }
+};
+
+}  // namespace abddc
