@@ -4,6 +4,7 @@
 #include <cstring>
 #include <string>
 
+#include "guard.h"
 #include "internal.h"
 
 namespace abddc {
@@ -20,19 +21,6 @@ using namespace abddc;
 extern "C" const char* abddc_last_error(void) { return g_last_error.c_str(); }
 
 namespace {
-template <class F>
-int guarded(F&& f) {
-  try {
-    g_last_error.clear();
-    return f();
-  } catch (const Error& e) {
-    return fail(e.code, e.what());
-  } catch (const std::bad_alloc&) {
-    return fail(ABDDC_ENOMEM, "host allocation failed");
-  } catch (const std::exception& e) {
-    return fail(ABDDC_EDEVICE, e.what());
-  }
-}
 
 int check_flag(int* dflag, hipStream_t s) {
   int h = 0;

@@ -1,14 +1,522 @@
-// Placeholder entry points (replaced by the full context implementation).
+// C ABI entry points: assemble, setup_coarse_space, apply_bddc, apply_schur,
+// gmres_solve and the query / parity hooks (include/abddc.h).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstddef>
+#include <memory>
+
+#include "apply.h"
+#include "arena.h"
+#include "assemble.h"
+#include "ctx.h"
+#include "guard.h"
 #include "internal.h"
-extern "C" {
-int abddc_assemble(const abddc_problem*, const abddc_device*, abddc_ctx**) { return ABDDC_ESTATE; }
-int abddc_setup_coarse_space(abddc_ctx*, const abddc_options*, abddc_counts*) { return ABDDC_ESTATE; }
-int abddc_apply_bddc(abddc_ctx*, const double*, double*) { return ABDDC_ESTATE; }
-int abddc_apply_schur(abddc_ctx*, const double*, double*) { return ABDDC_ESTATE; }
-int abddc_get_rhs(abddc_ctx*, double*) { return ABDDC_ESTATE; }
-int abddc_gmres_solve(abddc_ctx*, int32_t, double, int32_t, double*, abddc_solve_info*) { return ABDDC_ESTATE; }
-int abddc_query(const abddc_ctx*, int64_t*, int64_t*, int32_t*, int32_t*, int32_t*) { return ABDDC_ESTATE; }
-int64_t abddc_get_stage(abddc_ctx*, int32_t, int32_t, double*, int64_t) { return ABDDC_ESTATE; }
-int abddc_phase_times(const abddc_ctx*, double*, int32_t) { return ABDDC_ESTATE; }
-void abddc_destroy(abddc_ctx*) {}
+
+namespace abddc {
+void run_setup(abddc_ctx* c);
+}
+
+using namespace abddc;
+
+namespace {
+
+double ev_ms(abddc_ctx* c, int a, int b) {
+  float ms = 0.f;
+  if (c->events && hipEventElapsedTime(&ms, c->ev[a], c->ev[b]) == hipSuccess) return ms * 1e-3;
+  return 0.0;
+}
+
+void record(abddc_ctx* c, int i) {
+  if (c->events) ABDDC_HIP(hipEventRecord(c->ev[i], c->stream));
+}
+
+// z = M^{-1} r (device vectors of length n_gamma)
+void apply_bddc_dev(abddc_ctx* c, const double* r, double* z) {
+  hipStream_t s = c->stream;
+  const int np = c->n_primal;
+  launch_gemv<double>(c->blk_M.p, c->nblk_M, c->gemv_M.p, c->maxc_M, c->dM.p, r, c->d_gam.p, c->d_out.p, false, s);
+  if (np > 0) {
+    launch_gather_sum(c->d_pown_ptr.p, c->d_pown_idx.p, c->d_out.p, c->d_bpi.p, np, s);
+    launch_gemv<double>(c->blk_C.p, c->nblk_C, c->gemv_C.p, np, c->dSPinv.p, c->d_bpi.p, nullptr, c->d_xpi.p, false, s);
+    launch_gemv<double>(c->blk_U.p, c->nblk_U, c->gemv_U.p, c->maxc_U, c->dU.p, c->d_xpi.p, c->d_pid.p, c->d_out.p,
+                        true, s);
+  }
+  launch_gather_sum(c->d_aown_ptr.p, c->d_aown_idx.p, c->d_out.p, z, c->topo.n_gamma, s);
+}
+
+// y = Shat x
+void apply_schur_dev(abddc_ctx* c, const double* x, double* y) {
+  hipStream_t s = c->stream;
+  launch_gemv<double>(c->blk_S.p, c->nblk_S, c->gemv_S.p, c->maxc_S, c->dS.p, x, c->d_gam.p, c->d_wS.p, false, s);
+  launch_gather_sum(c->d_own_ptr.p, c->d_own_idx.p, c->d_wS.p, y, c->topo.n_gamma, s);
+}
+
+}  // namespace
+
+extern "C" int abddc_assemble(const abddc_problem* prob, const abddc_device* dev, abddc_ctx** out) {
+  return guarded([&]() -> int {
+    ABDDC_REQUIRE(prob && dev && out, ABDDC_EINVAL, "null argument");
+    *out = nullptr;
+    for (int a = 0; a < 3; ++a) {
+      ABDDC_REQUIRE(prob->nsub[a] >= 1 && prob->width[a], ABDDC_EINVAL, "bad nsub / width");
+      ABDDC_REQUIRE(prob->length[a] > 0 && std::isfinite(prob->length[a]), ABDDC_EINVAL, "length must be > 0");
+    }
+    ABDDC_REQUIRE(prob->tau > 0 && std::isfinite(prob->tau), ABDDC_EINVAL, "tau must be > 0");
+    ABDDC_REQUIRE(prob->nu, ABDDC_EINVAL, "nu is null");
+    std::unique_ptr<abddc_ctx> c(new abddc_ctx());
+    c->device = dev->device;
+    ABDDC_HIP(hipSetDevice(dev->device));
+    c->stream = (hipStream_t)dev->stream;
+    hipStream_t s = c->stream;
+    Topology& T = c->topo;
+    int nsub_in[3] = {prob->nsub[0], prob->nsub[1], prob->nsub[2]};
+    const int* w_in[3] = {prob->width[0], prob->width[1], prob->width[2]};
+    T.build(nsub_in, w_in);
+    for (int64_t e = 0; e < T.n_elem; ++e)
+      ABDDC_REQUIRE(prob->nu[e] > 0 && std::isfinite(prob->nu[e]), ABDDC_EINVAL, "nu must be positive and finite");
+    for (int a = 0; a < 3; ++a) {
+      c->length[a] = prob->length[a];
+      c->beta0[a] = prob->beta0[a];
+    }
+    for (int i = 0; i < 9; ++i) c->beta1[i] = prob->beta1[i];
+    c->c = prob->c;
+    c->f_const = prob->f_const;
+    c->tau = prob->tau;
+    for (int i = 0; i < 20; ++i) ABDDC_HIP(hipEventCreate(&c->ev[i]));
+    c->events = true;
+    c->d_flag.alloc(1);
+    c->d_flag.zero(s);
+    record(c.get(), 10);
+
+    // ---------------------------------------------------- local layout
+    const int nsub = T.n_sub;
+    c->nI.resize(nsub);
+    c->nB.resize(nsub);
+    c->nloc.resize(nsub);
+    c->aoff.resize(nsub);
+    c->soff.resize(nsub);
+    c->goff.resize(nsub);
+    c->ioff.resize(nsub);
+    int64_t at = 0, st = 0, gt = 0, it = 0, rows = 0, lmt = 0;
+    std::vector<SubAsm> sa(nsub);
+    std::vector<int32_t> lnode, rowsub, lmap, gam, int_dof;
+    for (int sub = 0; sub < nsub; ++sub) {
+      const SubInfo& si = T.sub[sub];
+      c->nI[sub] = si.nI;
+      c->nB[sub] = si.nB;
+      c->nloc[sub] = si.nI + si.nB;
+      const int ld = c->nloc[sub] + 1;
+      c->aoff[sub] = at;
+      c->soff[sub] = st;
+      c->goff[sub] = gt;
+      c->ioff[sub] = it;
+      SubAsm& a = sa[sub];
+      a.aoff = at;
+      a.soff = st;
+      a.goff = gt;
+      a.ioff = it;
+      a.loff = rows;
+      a.lmoff = (int32_t)lmt;
+      a.nloc = c->nloc[sub];
+      a.nI = si.nI;
+      a.ld = ld;
+      for (int ax = 0; ax < 3; ++ax) {
+        a.ebox[2 * ax] = si.ebox[ax][0];
+        a.ebox[2 * ax + 1] = si.ebox[ax][1];
+      }
+      at += (int64_t)c->nloc[sub] * ld;
+      st += (int64_t)si.nB * si.nB;
+      gt += si.nB;
+      it += si.nI;
+      // local node list [interior; Gamma_i] and the box-local map
+      const int bx = si.ebox[0][1] - si.ebox[0][0] + 1, by = si.ebox[1][1] - si.ebox[1][0] + 1,
+                bz = si.ebox[2][1] - si.ebox[2][0] + 1;
+      std::vector<int32_t> bm((size_t)bx * by * bz, -1);
+      auto boxpos = [&](int64_t nid) {
+        const int ix = (int)(nid % T.nn[0]), iy = (int)((nid / T.nn[0]) % T.nn[1]), iz = (int)(nid / ((int64_t)T.nn[0] * T.nn[1]));
+        return (ix - si.ebox[0][0]) + (int64_t)bx * ((iy - si.ebox[1][0]) + (int64_t)by * (iz - si.ebox[2][0]));
+      };
+      int loc = 0;
+      for (int64_t nid : si.interior) {
+        lnode.push_back((int32_t)nid);
+        rowsub.push_back(sub);
+        bm[boxpos(nid)] = loc++;
+        int_dof.push_back((int32_t)T.dof_of_node[nid]);
+      }
+      for (int k : si.objs)
+        for (int64_t nid : T.objects[k].nodes) {
+          lnode.push_back((int32_t)nid);
+          rowsub.push_back(sub);
+          bm[boxpos(nid)] = loc++;
+        }
+      for (int64_t g : si.gamma) gam.push_back((int32_t)g);
+      lmap.insert(lmap.end(), bm.begin(), bm.end());
+      lmt += (int64_t)bm.size();
+      rows += c->nloc[sub];
+    }
+    ABDDC_REQUIRE(T.n_nodes < (int64_t)1 << 31 && lmt < (int64_t)1 << 31, ABDDC_EINVAL, "mesh too large");
+    c->d_subs = to_device(sa, s);
+    DevBuf<int32_t> d_lnode = to_device(lnode, s), d_rowsub = to_device(rowsub, s), d_lmap = to_device(lmap, s);
+    c->d_gam = to_device(gam, s);
+    c->d_int_dof = to_device(int_dof, s);
+    std::vector<int32_t> iface_dof(T.n_gamma);
+    for (const Object& o : T.objects)
+      for (int q = 0; q < o.n; ++q) iface_dof[o.gstart + q] = (int32_t)T.dof_of_node[o.nodes[q]];
+    c->d_iface_dof = to_device(iface_dof, s);
+    std::vector<double> nu(prob->nu, prob->nu + T.n_elem);
+    c->d_nu = to_device(nu, s);
+    if (prob->f_nodal) {
+      std::vector<double> fn(prob->f_nodal, prob->f_nodal + T.n_nodes);
+      c->d_fnodal = to_device(fn, s);
+      c->have_fnodal = true;
+    }
+
+    // -------------------------------------------- element matrices + scatter
+    c->dA.alloc(std::max<int64_t>(at, 1));
+    c->dA.zero(s);
+    {
+      DevBuf<double> Ae(T.n_elem * 64), Fe(T.n_elem * 8);
+      ElemParams P{};
+      P.n_elem = T.n_elem;
+      for (int a = 0; a < 3; ++a) {
+        P.ne[a] = T.ne[a];
+        P.nn[a] = T.nn[a];
+        P.h[a] = c->length[a] / T.ne[a];
+        P.b0[a] = c->beta0[a];
+      }
+      for (int i = 0; i < 9; ++i) P.b1[i] = c->beta1[i];
+      P.c = c->c;
+      P.tau = c->tau;
+      P.f_const = c->f_const;
+      launch_elem(P, c->d_nu.p, c->have_fnodal ? c->d_fnodal.p : nullptr, Ae.p, Fe.p, s);
+      launch_scatter(c->d_subs.p, d_rowsub.p, d_lnode.p, d_lmap.p, rows, T.nn, T.ne, Ae.p, Fe.p, c->dA.p, s);
+      record(c.get(), 11);
+      // interior elimination: S^(i), g^(i) in the trailing block / column
+      std::vector<PluDesc<double>> pd;
+      for (int sub = 0; sub < nsub; ++sub)
+        pd.push_back({c->dA.p + c->aoff[sub], c->nloc[sub], c->nloc[sub] + 1, c->nloc[sub] + 1, c->nI[sub]});
+      partial_lu<double>(pd, c->d_flag.p, s);
+      ABDDC_HIP(hipStreamSynchronize(s));
+    }
+    c->dS.alloc(std::max<int64_t>(st, 1));
+    c->dB.alloc(std::max<int64_t>(st, 1));
+    c->dg.alloc(std::max<int64_t>(gt, 1));
+    int maxnB = 1;
+    for (int sub = 0; sub < nsub; ++sub) maxnB = std::max(maxnB, c->nB[sub]);
+    launch_extract(c->d_subs.p, nsub, maxnB, c->dA.p, c->dS.p, c->dB.p, c->dg.p, s);
+
+    // interface owners (goff space) and ghat = sum R_i^T g^(i)
+    std::vector<std::vector<int32_t>> own(T.n_gamma);
+    for (int sub = 0; sub < nsub; ++sub)
+      for (int l = 0; l < c->nB[sub]; ++l) own[T.sub[sub].gamma[l]].push_back((int32_t)(c->goff[sub] + l));
+    std::vector<int32_t> optr(T.n_gamma + 1, 0), oidx;
+    for (int64_t g = 0; g < T.n_gamma; ++g) {
+      optr[g + 1] = optr[g] + (int)own[g].size();
+      oidx.insert(oidx.end(), own[g].begin(), own[g].end());
+    }
+    c->d_own_ptr = to_device(optr, s);
+    c->d_own_idx = to_device(oidx, s);
+    c->d_ghat.alloc(std::max<int64_t>(T.n_gamma, 1));
+    launch_gather_sum(c->d_own_ptr.p, c->d_own_idx.p, c->dg.p, c->d_ghat.p, T.n_gamma, s);
+
+    // Schur operator GEMV metadata
+    std::vector<GemvMat> mS;
+    std::vector<GemvBlock> bS;
+    for (int sub = 0; sub < nsub; ++sub) {
+      const int nB = c->nB[sub];
+      mS.push_back({c->soff[sub], c->goff[sub], c->goff[sub], nB, nB, std::max(nB, 1), 0});
+      for (int r = 0; r < nB; r += GEMV_ROWS_PER_BLOCK) bS.push_back({sub, r});
+    }
+    c->gemv_S = to_device(mS, s);
+    c->blk_S = to_device(bS, s);
+    c->nblk_S = (int)bS.size();
+    c->maxc_S = maxnB;
+    c->d_wS.alloc(std::max<int64_t>(gt, 1));
+    c->d_rec.alloc(std::max<int64_t>(it, 1));
+    record(c.get(), 12);
+    int h = 0;
+    ABDDC_HIP(hipMemcpyAsync(&h, c->d_flag.p, sizeof(int), hipMemcpyDeviceToHost, s));
+    ABDDC_HIP(hipStreamSynchronize(s));
+    ABDDC_REQUIRE(!(h & 1), ABDDC_ESINGULAR, "interior elimination: zero or non-finite pivot");
+    c->phase[0] = ev_ms(c.get(), 10, 11);
+    c->phase[1] = ev_ms(c.get(), 11, 12);
+    c->state = 1;
+    *out = c.release();
+    return ABDDC_OK;
+  });
+}
+
+extern "C" int abddc_setup_coarse_space(abddc_ctx* c, const abddc_options* opts, abddc_counts* counts) {
+  return guarded([&]() -> int {
+    ABDDC_REQUIRE(c, ABDDC_EINVAL, "null context");
+    ABDDC_REQUIRE(c->state >= 1, ABDDC_ESTATE, "setup before assemble");
+    ABDDC_HIP(hipSetDevice(c->device));
+    abddc_options o{};
+    o.theta_face = 10.0;
+    o.theta_edge = 10.0;
+    o.pinv_rtol = 1e-10;
+    o.svd_rtol = 1e-8;
+    o.tie_rtol = 1e-9;
+    if (opts) o = *opts;
+    ABDDC_REQUIRE(o.theta_face >= 0 && o.theta_edge >= 0, ABDDC_EINVAL, "thresholds must be >= 0");
+    ABDDC_REQUIRE(o.edge_variant == ABDDC_EDGE_NEW, ABDDC_EINVAL, "only the new edge eigenproblem is provided");
+    ABDDC_REQUIRE(o.edge_h_mode == ABDDC_H_SHARED || o.edge_h_mode == ABDDC_H_SEPARATE, ABDDC_EINVAL, "bad edge_h_mode");
+    ABDDC_REQUIRE(o.deluxe_source == ABDDC_DELUXE_S || o.deluxe_source == ABDDC_DELUXE_B, ABDDC_EINVAL,
+                  "bad deluxe_source");
+    ABDDC_REQUIRE(o.precision == ABDDC_PREC_FP64, ABDDC_EINVAL, "precision mode not provided");
+    ABDDC_REQUIRE(o.constraint_source == ABDDC_CONSTRAINTS_EXACT, ABDDC_EINVAL, "constraint source not provided");
+    ABDDC_REQUIRE(o.pinv_rtol >= 0 && o.svd_rtol >= 0 && o.tie_rtol >= 0, ABDDC_EINVAL, "negative tolerance");
+    c->opt = o;
+    c->n_ties = 0;
+    c->state = 1;
+    run_setup(c);
+    c->phase[2] = ev_ms(c, 2, 3);
+    c->phase[3] = ev_ms(c, 3, 4);
+    c->phase[4] = ev_ms(c, 4, 5);
+    c->phase[5] = ev_ms(c, 5, 6);
+    c->phase[6] = ev_ms(c, 6, 8);
+    if (counts) *counts = {c->n_vertex, c->pnum_face, c->pnum_edge, c->n_primal, c->n_ties};
+    c->state = 2;
+    return ABDDC_OK;
+  });
+}
+
+extern "C" int abddc_apply_bddc(abddc_ctx* c, const double* r, double* z) {
+  return guarded([&]() -> int {
+    ABDDC_REQUIRE(c && r && z, ABDDC_EINVAL, "null argument");
+    ABDDC_REQUIRE(c->state >= 2, ABDDC_ESTATE, "apply before setup");
+    apply_bddc_dev(c, r, z);
+    return ABDDC_OK;
+  });
+}
+
+extern "C" int abddc_apply_schur(abddc_ctx* c, const double* x, double* y) {
+  return guarded([&]() -> int {
+    ABDDC_REQUIRE(c && x && y, ABDDC_EINVAL, "null argument");
+    ABDDC_REQUIRE(c->state >= 1, ABDDC_ESTATE, "apply before assemble");
+    apply_schur_dev(c, x, y);
+    return ABDDC_OK;
+  });
+}
+
+extern "C" int abddc_get_rhs(abddc_ctx* c, double* g) {
+  return guarded([&]() -> int {
+    ABDDC_REQUIRE(c && g, ABDDC_EINVAL, "null argument");
+    ABDDC_REQUIRE(c->state >= 1, ABDDC_ESTATE, "rhs before assemble");
+    if (c->topo.n_gamma)
+      ABDDC_HIP(hipMemcpyAsync(g, c->d_ghat.p, c->topo.n_gamma * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    return ABDDC_OK;
+  });
+}
+
+extern "C" int abddc_gmres_solve(abddc_ctx* c, int32_t restart, double rtol, int32_t maxit, double* u,
+                                 abddc_solve_info* info) {
+  return guarded([&]() -> int {
+    ABDDC_REQUIRE(c && u, ABDDC_EINVAL, "null argument");
+    ABDDC_REQUIRE(c->state >= 2, ABDDC_ESTATE, "solve before setup");
+    ABDDC_REQUIRE(restart >= 1 && restart <= GMRES_MAXR, ABDDC_EINVAL, "restart must be in [1, 63]");
+    ABDDC_REQUIRE(rtol > 0 && rtol < 1, ABDDC_EINVAL, "rtol must be in (0, 1)");
+    ABDDC_REQUIRE(maxit >= 1, ABDDC_EINVAL, "maxit must be >= 1");
+    ABDDC_HIP(hipSetDevice(c->device));
+    hipStream_t s = c->stream;
+    const int64_t n = c->topo.n_gamma;
+    const size_t nn = (size_t)std::max<int64_t>(n, 1);
+    if (c->gm_restart < restart) {
+      c->d_V.alloc((restart + 1) * nn);
+      c->d_Z.alloc(restart * nn);
+      c->gm_restart = restart;
+    }
+    if (!c->d_w.p) {
+      c->d_w.alloc(nn);
+      c->d_r.alloc(nn);
+      c->d_x.alloc(nn);
+      c->d_h1.alloc(GMRES_MAXR + 1);
+      c->d_h2.alloc(GMRES_MAXR + 1);
+      c->d_nrm.alloc(1);
+      c->d_partial.alloc((size_t)DOT_BLOCKS * DOT_STRIDE);
+      c->d_gst.alloc(1);
+      ABDDC_HIP(hipHostMalloc(&c->h_gst, sizeof(GmresState), hipHostMallocDefault));
+    }
+    const auto t0 = std::chrono::steady_clock::now();
+    record(c, 13);
+    double* V = c->d_V.p;
+    double* Z = c->d_Z.p;
+    const size_t tail = offsetof(GmresState, beta);
+    auto read_scalars = [&]() {
+      ABDDC_HIP(hipMemcpyAsync(reinterpret_cast<char*>(c->h_gst) + tail, reinterpret_cast<char*>(c->d_gst.p) + tail,
+                               4 * sizeof(double), hipMemcpyDeviceToHost, s));
+      ABDDC_HIP(hipStreamSynchronize(s));
+    };
+    int iters = 0, restarts = 0;
+    double relres = 0.0;
+    bool converged = false;
+    ABDDC_HIP(hipMemsetAsync(c->d_x.p, 0, nn * sizeof(double), s));
+    if (n > 0) {
+      ABDDC_HIP(hipMemcpyAsync(c->d_r.p, c->d_ghat.p, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+      launch_dots(c->d_r.p, n, 1, c->d_r.p, n, c->d_partial.p, c->d_nrm.p, s);
+      launch_gmres_start(c->d_gst.p, c->d_nrm.p, s);
+      read_scalars();
+      const double bnorm = c->h_gst->beta;
+      if (bnorm == 0.0) converged = true;
+      while (!converged) {
+        // cycle start: V[0] = r / ||r|| (r and its norm already in place)
+        launch_scale_copy(c->d_r.p, &c->d_gst.p->inv_hn, V, n, s);
+        int jend = 0;
+        for (int j = 0; j < restart; ++j) {
+          double* vj = V + (size_t)j * nn;
+          double* zj = Z + (size_t)j * nn;
+          apply_bddc_dev(c, vj, zj);
+          apply_schur_dev(c, zj, c->d_w.p);
+          ++iters;
+          launch_dots(V, nn, j + 1, c->d_w.p, n, c->d_partial.p, c->d_h1.p, s);
+          launch_axpy_multi(V, nn, j + 1, c->d_h1.p, -1.0, c->d_w.p, n, s);
+          launch_dots(V, nn, j + 1, c->d_w.p, n, c->d_partial.p, c->d_h2.p, s);
+          launch_axpy_multi(V, nn, j + 1, c->d_h2.p, -1.0, c->d_w.p, n, s);
+          launch_dots(c->d_w.p, n, 1, c->d_w.p, n, c->d_partial.p, c->d_nrm.p, s);
+          launch_arnoldi_finish(c->d_gst.p, j, c->d_h1.p, c->d_h2.p, c->d_nrm.p, s);
+          read_scalars();
+          const double res = c->h_gst->res;
+          if (info && info->resid_history && iters <= info->resid_cap) info->resid_history[iters - 1] = res / bnorm;
+          jend = j + 1;
+          if (c->h_gst->hn == 0.0 || res <= rtol * bnorm || iters >= maxit) break;
+          launch_scale_copy(c->d_w.p, &c->d_gst.p->inv_hn, V + (size_t)(j + 1) * nn, n, s);
+        }
+        launch_gmres_trisolve(c->d_gst.p, jend, s);
+        launch_axpy_multi(Z, nn, jend, c->d_gst.p->y, 1.0, c->d_x.p, n, s);
+        // true residual
+        apply_schur_dev(c, c->d_x.p, c->d_w.p);
+        launch_sub(c->d_ghat.p, c->d_w.p, c->d_r.p, n, s);
+        launch_dots(c->d_r.p, n, 1, c->d_r.p, n, c->d_partial.p, c->d_nrm.p, s);
+        launch_gmres_start(c->d_gst.p, c->d_nrm.p, s);
+        read_scalars();
+        const double beta = c->h_gst->beta;
+        relres = beta / bnorm;
+        if (beta <= rtol * bnorm) {
+          converged = true;
+          break;
+        }
+        if (iters >= maxit) break;
+        ++restarts;
+      }
+    }
+    record(c, 14);
+    launch_recover(c->d_subs.p, c->topo.n_sub, c->dA.p, c->d_gam.p, c->d_x.p, c->d_int_dof.p, c->d_iface_dof.p, n, u,
+                   c->d_rec.p, s);
+    record(c, 15);
+    ABDDC_HIP(hipStreamSynchronize(s));
+    const double wall = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    c->phase[7] = ev_ms(c, 13, 14);
+    c->phase[8] = ev_ms(c, 14, 15);
+    if (info) {
+      info->iters = iters;
+      info->restarts = restarts;
+      info->relres_true = relres;
+      double ts = 0;
+      for (int i = 0; i < 7; ++i) ts += c->phase[i];
+      info->t_setup_s = ts;
+      info->t_iter_s = wall;
+    }
+    return converged ? ABDDC_OK : ABDDC_NOT_CONVERGED;
+  });
+}
+
+extern "C" int abddc_query(const abddc_ctx* c, int64_t* n_dof, int64_t* n_gamma, int32_t* n_sub, int32_t* n_face,
+                           int32_t* n_edge) {
+  if (!c) return fail(ABDDC_EINVAL, "null context");
+  if (n_dof) *n_dof = c->topo.n_dof;
+  if (n_gamma) *n_gamma = c->topo.n_gamma;
+  if (n_sub) *n_sub = c->topo.n_sub;
+  if (n_face) *n_face = (int32_t)c->topo.faces.size();
+  if (n_edge) *n_edge = (int32_t)c->topo.edges.size();
+  return ABDDC_OK;
+}
+
+extern "C" int64_t abddc_get_stage(abddc_ctx* c, int32_t stage, int32_t index, double* buf, int64_t cap) {
+  int64_t result = 0;
+  int rc = guarded([&]() -> int {
+    ABDDC_REQUIRE(c, ABDDC_EINVAL, "null context");
+    ABDDC_REQUIRE(c->state >= 1, ABDDC_ESTATE, "stage before assemble");
+    const Topology& T = c->topo;
+    const double* src = nullptr;
+    int64_t n = 0;
+    std::vector<double> host;
+    auto need_setup = [&]() { ABDDC_REQUIRE(c->state >= 2, ABDDC_ESTATE, "stage needs setup"); };
+    switch (stage) {
+      case ABDDC_STAGE_SCHUR:
+        ABDDC_REQUIRE(index >= 0 && index < T.n_sub, ABDDC_EINVAL, "bad subdomain index");
+        src = c->dS.p + c->soff[index];
+        n = (int64_t)c->nB[index] * c->nB[index];
+        break;
+      case ABDDC_STAGE_LOCAL_RHS:
+        ABDDC_REQUIRE(index >= 0 && index < T.n_sub, ABDDC_EINVAL, "bad subdomain index");
+        src = c->dg.p + c->goff[index];
+        n = c->nB[index];
+        break;
+      case ABDDC_STAGE_FACE_EIG:
+      case ABDDC_STAGE_FACE_BASIS: {
+        need_setup();
+        ABDDC_REQUIRE(index >= 0 && index < (int)T.faces.size(), ABDDC_EINVAL, "bad face index");
+        const int nF = T.objects[T.faces[index]].n;
+        src = stage == ABDDC_STAGE_FACE_EIG ? c->dWF.p + c->wfoff[index] : c->dTF.p + c->tfoff[index];
+        n = stage == ABDDC_STAGE_FACE_EIG ? nF : (int64_t)nF * nF;
+        break;
+      }
+      case ABDDC_STAGE_EDGE_EIG:
+      case ABDDC_STAGE_EDGE_BASIS: {
+        need_setup();
+        ABDDC_REQUIRE(index >= 0 && index < (int)T.edges.size(), ABDDC_EINVAL, "bad edge index");
+        const Object& o = T.objects[T.edges[index]];
+        src = stage == ABDDC_STAGE_EDGE_EIG ? c->dWE.p + c->weoff[index] : c->dTE.p + c->teoff[index];
+        n = stage == ABDDC_STAGE_EDGE_EIG ? (int64_t)(o.subs.size() - 1) * o.n : (int64_t)o.n * o.n;
+        break;
+      }
+      case ABDDC_STAGE_COUNTS:
+        need_setup();
+        for (int v : c->pF) host.push_back(v);
+        for (int v : c->rE) host.push_back(v);
+        n = (int64_t)host.size();
+        break;
+      case ABDDC_STAGE_DELUXE: {
+        need_setup();
+        const int obj = index / 8, mem = index % 8;
+        ABDDC_REQUIRE(obj >= 0 && obj < (int)T.objects.size() && c->dxoff[(size_t)index] >= 0, ABDDC_EINVAL,
+                      "bad deluxe index");
+        src = c->dD.p + c->dxoff[(size_t)obj * 8 + mem];
+        n = (int64_t)T.objects[obj].n * T.objects[obj].n;
+        break;
+      }
+      default:
+        throw Error(ABDDC_EINVAL, "unknown stage");
+    }
+    result = n;
+    if (buf && cap >= n && n > 0) {
+      if (src) {
+        ABDDC_HIP(hipMemcpyAsync(buf, src, n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        ABDDC_HIP(hipStreamSynchronize(c->stream));
+      } else {
+        std::copy(host.begin(), host.end(), buf);
+      }
+    }
+    return ABDDC_OK;
+  });
+  return rc < 0 ? rc : result;
+}
+
+extern "C" int abddc_phase_times(const abddc_ctx* c, double* t, int32_t n) {
+  if (!c || !t || n < 0) return fail(ABDDC_EINVAL, "null argument");
+  for (int i = 0; i < n && i < 16; ++i) t[i] = c->phase[i];
+  return ABDDC_OK;
+}
+
+extern "C" void abddc_destroy(abddc_ctx* c) {
+  if (!c) return;
+  (void)hipSetDevice(c->device);
+  (void)hipStreamSynchronize(c->stream);
+  if (c->h_gst) (void)hipHostFree(c->h_gst);
+  for (int i = 0; i < 20; ++i)
+    if (c->ev[i]) (void)hipEventDestroy(c->ev[i]);
+  delete c;
 }

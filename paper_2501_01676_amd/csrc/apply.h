@@ -10,7 +10,8 @@ namespace abddc {
 constexpr int GEMV_ROWS_PER_WAVE = 4;
 constexpr int GEMV_ROWS_PER_BLOCK = 4 * GEMV_ROWS_PER_WAVE;
 constexpr int DOT_BLOCKS = 256;
-constexpr int GMRES_MAXR = 64;   // maximum restart length
+constexpr int DOT_STRIDE = 64;   // partial-sum stride (>= restart + 1 vectors)
+constexpr int GMRES_MAXR = 63;   // maximum restart length
 
 struct GemvMat {
   int64_t moff;   // matrix offset (elements)

@@ -6,6 +6,8 @@
 #include <array>
 #include <vector>
 
+#include "apply.h"
+#include "assemble.h"
 #include "internal.h"
 #include "topology.h"
 
@@ -53,13 +55,22 @@ struct abddc_ctx {
   abddc::DevBuf<double> dM, dU, dSPinv;
   abddc::DevBuf<float> dM32, dU32;
   abddc::DevBuf<int32_t> d_pid;            // concatenated Pi_i -> global primal id
+  abddc::DevBuf<int32_t> d_sown_ptr, d_sown_idx;   // interface dof -> positions in goff space
   abddc::DevBuf<int32_t> d_pown_ptr, d_pown_idx;   // primal id -> positions in ooff space
   abddc::DevBuf<int32_t> d_aown_ptr, d_aown_idx;   // interface dof -> positions in ooff space
-  abddc::DevBuf<int64_t> d_moff, d_uoff, d_goff, d_ooff, d_poff, d_soff;
-  abddc::DevBuf<int32_t> d_nB, d_nPi;
-  abddc::DevBuf<int32_t> d_gemv_blocks_M, d_gemv_blocks_U, d_gemv_blocks_S, d_gemv_blocks_C;
-  int nblk_M = 0, nblk_U = 0, nblk_S = 0, nblk_C = 0;
-  abddc::DevBuf<double> d_out, d_work_s, d_bpi, d_xpi;  // apply/Schur work vectors
+  abddc::DevBuf<abddc::GemvMat> gemv_M, gemv_U, gemv_C, gemv_S;
+  abddc::DevBuf<abddc::GemvBlock> blk_M, blk_U, blk_C, blk_S;
+  int nblk_M = 0, nblk_U = 0, nblk_C = 0, nblk_S = 0;
+  int maxc_M = 1, maxc_U = 1, maxc_S = 1;
+  abddc::DevBuf<double> d_out, d_wS, d_bpi, d_xpi;  // apply / Schur work vectors
+  abddc::DevBuf<abddc::SubAsm> d_subs;
+  abddc::DevBuf<double> d_rec;                      // recovery work (interior space)
+
+  // ------------------------------------------------------------- GMRES
+  abddc::DevBuf<double> d_V, d_Z, d_w, d_r, d_x, d_h1, d_h2, d_nrm, d_partial;
+  abddc::DevBuf<abddc::GmresState> d_gst;
+  abddc::GmresState* h_gst = nullptr;               // pinned mirror of the scalars
+  int gm_restart = 0;
 
   // ------------------------------------------------------------- misc
   abddc::DevBuf<int> d_flag;

@@ -58,7 +58,10 @@ struct DevBuf {
   }
   void upload(const std::vector<T>& h, hipStream_t s) {
     if (h.size() > n) alloc(h.size());
-    if (!h.empty()) ABDDC_HIP(hipMemcpyAsync(p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, s));
+    if (!h.empty()) {
+      ABDDC_HIP(hipMemcpyAsync(p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, s));
+      ABDDC_HIP(hipStreamSynchronize(s));
+    }
   }
   void zero(hipStream_t s) {
     if (n) ABDDC_HIP(hipMemsetAsync(p, 0, n * sizeof(T), s));
@@ -68,7 +71,10 @@ struct DevBuf {
 template <class T>
 inline DevBuf<T> to_device(const std::vector<T>& h, hipStream_t s) {
   DevBuf<T> d(h.size());
-  if (!h.empty()) ABDDC_HIP(hipMemcpyAsync(d.p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, s));
+  if (!h.empty()) {
+    ABDDC_HIP(hipMemcpyAsync(d.p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, s));
+    ABDDC_HIP(hipStreamSynchronize(s));  // the host vector may be released after return
+  }
   return d;
 }
 

@@ -76,7 +76,7 @@ __global__ void gather_sum_kernel(const int32_t* __restrict__ ptr, const int32_t
   dst[i] = v;
 }
 
-// partial[b * 32 + j] = sum over block b's chunk of V[j][i] w[i]
+// partial[b * DOT_STRIDE + j] = sum over block b's chunk of V[j][i] w[i]
 __global__ void __launch_bounds__(256) dots_partial_kernel(const double* __restrict__ V, int64_t ldv, int nv,
                                                            const double* __restrict__ w, int64_t n,
                                                            double* __restrict__ partial) {
@@ -91,7 +91,7 @@ __global__ void __launch_bounds__(256) dots_partial_kernel(const double* __restr
     a = wave_sum(a);
     if (lane == 0) red[wv] = a;
     __syncthreads();
-    if (threadIdx.x == 0) partial[blockIdx.x * 32 + j] = (red[0] + red[1]) + (red[2] + red[3]);
+    if (threadIdx.x == 0) partial[blockIdx.x * DOT_STRIDE + j] = (red[0] + red[1]) + (red[2] + red[3]);
     __syncthreads();
   }
 }
@@ -100,7 +100,7 @@ __global__ void dots_final_kernel(const double* __restrict__ partial, int nblk, 
   const int j = threadIdx.x;
   if (j >= nv) return;
   double s = 0.0;
-  for (int b = 0; b < nblk; ++b) s += partial[b * 32 + j];
+  for (int b = 0; b < nblk; ++b) s += partial[b * DOT_STRIDE + j];
   out[j] = s;
 }
 

@@ -10,6 +10,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "assemble.h"
 #include "internal.h"
 
@@ -225,7 +227,7 @@ void launch_recover(const SubAsm* subs, int nsub, const double* A, const int32_t
                     const int32_t* int_dof, const int32_t* iface_dof, int64_t n_gamma, double* u, double* work,
                     hipStream_t s) {
   recover_kernel<<<nsub, 256, 0, s>>>(subs, A, gam, uhat, int_dof, u, work);
-  iface_scatter_kernel<<<(unsigned)((n_gamma + 255) / 256), 256, 0, s>>>(uhat, iface_dof, n_gamma, u);
+  if (n_gamma > 0) iface_scatter_kernel<<<(unsigned)((n_gamma + 255) / 256), 256, 0, s>>>(uhat, iface_dof, n_gamma, u);
   ABDDC_HIP(hipGetLastError());
 }
 

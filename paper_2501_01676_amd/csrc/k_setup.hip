@@ -1,0 +1,180 @@
+// Setup-only helper kernels: deluxe systems, edge operator assembly,
+// coarse-matrix assembly and elementwise combinations.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "arena.h"
+#include "internal.h"
+#include "setup_k.h"
+
+namespace abddc {
+
+namespace {
+
+// [[sum_k S_k, S_1, ..., S_m], [-I, 0, ..., 0]]: its Schur complement onto
+// the trailing block is [(sum S)^{-1} S_1, ..., (sum S)^{-1} S_m].
+__global__ void deluxe_build_kernel(const DeluxeDesc* __restrict__ descs) {
+  const DeluxeDesc d = descs[blockIdx.y];
+  const int n = d.n, cols = (d.m + 1) * n;
+  for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < 2 * n * cols; idx += gridDim.x * blockDim.x) {
+    const int r = idx / cols, c = idx % cols;
+    double v = 0.0;
+    if (r < n) {
+      if (c < n) {
+        for (int k = 0; k < d.m; ++k) v += d.src[k][(size_t)r * d.lds[k] + c];
+      } else {
+        const int k = c / n - 1, cc = c % n;
+        v = d.src[k][(size_t)r * d.lds[k] + cc];
+      }
+    } else if (c < n && r - n == c) {
+      v = -1.0;
+    }
+    d.dst[(size_t)r * cols + c] = v;
+  }
+}
+
+// Edge operators for one edge shared by m subdomains (reference = member 0):
+//   That_k = [-D_2 ... -D_m] + (I in slot k for k >= 2)      (n_E x (m-1) n_E)
+//   M_E    = sum_k That_k^T B_E^(k) That_k
+//   Q      = sum_k P_k^T Btilde^(k) P_k in the variable order
+//            [what (n_E), w_H (n_H), wcheck ((m-1) n_E)], where P_k maps
+//            (wcheck, what, w_H) to (w_k,E = That_k wcheck + what, w_k,H = R_k w_H).
+__global__ void __launch_bounds__(256) edge_assemble_kernel(const EdgeAsmDesc* __restrict__ descs) {
+  constexpr int NE = 16, NW = 48;
+  __shared__ double Th[4][NE][NW];
+  __shared__ double Z[NE][NW + NE];
+  const EdgeAsmDesc d = descs[blockIdx.x];
+  const int nE = d.nE, m = d.m, nw = (m - 1) * nE, nv = d.nv, nH = d.nH, tid = threadIdx.x;
+  const int nt = nw + nE;  // [wcheck, what] width of T_E^(k) = [That_k | I]
+  // variable position in Q of paper-order index a (wcheck, what)
+  auto qpos = [&](int a) { return a < nw ? nE + nH + a : a - nw; };
+  for (int k = 0; k < m; ++k)
+    for (int idx = tid; idx < nE * nw; idx += blockDim.x) {
+      const int p = idx / nw, a = idx % nw, slot = a / nE + 1, q = a % nE;
+      double v = -d.D[slot][p * nE + q];
+      if (slot == k && p == q) v += 1.0;
+      Th[k][p][a] = v;
+    }
+  for (int idx = tid; idx < nw * nw; idx += blockDim.x) d.ME[idx] = 0.0;
+  for (int idx = tid; idx < nv * nv; idx += blockDim.x) d.Q[idx] = 0.0;
+  __syncthreads();
+  for (int k = 0; k < m; ++k) {
+    // M_E += That^T (B_E That)
+    for (int idx = tid; idx < nE * nw; idx += blockDim.x) {
+      const int p = idx / nw, a = idx % nw;
+      double v = 0.0;
+      for (int q = 0; q < nE; ++q) v += d.BE[k][(size_t)p * d.ldBE[k] + q] * Th[k][q][a];
+      Z[p][a] = v;
+    }
+    __syncthreads();
+    for (int idx = tid; idx < nw * nw; idx += blockDim.x) {
+      const int a = idx / nw, b = idx % nw;
+      double v = 0.0;
+      for (int p = 0; p < nE; ++p) v += Th[k][p][a] * Z[p][b];
+      d.ME[idx] += v;
+    }
+    __syncthreads();
+    // Z = Btilde_EE T_E  (n_E x nt), T_E = [That | I]
+    const double* Bt = d.Bt[k];
+    const int ldb = d.ldBt[k], nHk = d.nHk[k];
+    for (int idx = tid; idx < nE * nt; idx += blockDim.x) {
+      const int p = idx / nt, a = idx % nt;
+      double v = 0.0;
+      if (a < nw)
+        for (int q = 0; q < nE; ++q) v += Bt[(size_t)p * ldb + q] * Th[k][q][a];
+      else
+        v = Bt[(size_t)p * ldb + (a - nw)];
+      Z[p][a] = v;
+    }
+    __syncthreads();
+    // (wcheck what, wcheck what) block: T_E^T Z
+    for (int idx = tid; idx < nt * nt; idx += blockDim.x) {
+      const int a = idx / nt, b = idx % nt;
+      double v = 0.0;
+      if (a < nw)
+        for (int p = 0; p < nE; ++p) v += Th[k][p][a] * Z[p][b];
+      else
+        v = Z[a - nw][b];
+      d.Q[(size_t)qpos(a) * nv + qpos(b)] += v;
+    }
+    // (wcheck what, H) and (H, wcheck what): T_E^T Btilde_EH R_k and transpose side
+    for (int idx = tid; idx < nt * nHk; idx += blockDim.x) {
+      const int a = idx / nHk, h = idx % nHk;
+      double v1 = 0.0, v2 = 0.0;
+      for (int p = 0; p < nE; ++p) {
+        const double t = a < nw ? Th[k][p][a] : (p == a - nw ? 1.0 : 0.0);
+        v1 += t * Bt[(size_t)p * ldb + nE + h];
+        v2 += Bt[(size_t)(nE + h) * ldb + p] * t;
+      }
+      const int hq = nE + d.R[k][h];
+      d.Q[(size_t)qpos(a) * nv + hq] += v1;
+      d.Q[(size_t)hq * nv + qpos(a)] += v2;
+    }
+    // (H, H)
+    for (int idx = tid; idx < nHk * nHk; idx += blockDim.x) {
+      const int h1 = idx / nHk, h2 = idx % nHk;
+      d.Q[(size_t)(nE + d.R[k][h1]) * nv + nE + d.R[k][h2]] += Bt[(size_t)(nE + h1) * ldb + nE + h2];
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void coarse_add_kernel(const CoarseAddDesc* __restrict__ descs, double* __restrict__ SPi, int64_t ldc) {
+  const CoarseAddDesc d = descs[blockIdx.y];
+  for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < d.n * d.n; idx += gridDim.x * blockDim.x) {
+    const int a = idx / d.n, b = idx % d.n;
+    SPi[(int64_t)d.gid[a] * ldc + d.gid[b]] += d.src[(size_t)a * d.ld + b];
+  }
+}
+
+__global__ void axpby_kernel(const AxpbyDesc* __restrict__ descs) {
+  const AxpbyDesc d = descs[blockIdx.y];
+  for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < d.nr * d.nc; idx += gridDim.x * blockDim.x) {
+    const int r = idx / d.nc, c = idx % d.nc;
+    d.dst[(size_t)r * d.ldd + c] = d.alpha * d.X[(size_t)r * d.ldx + c] + d.beta * d.Y[(size_t)r * d.ldy + c];
+  }
+}
+
+}  // namespace
+
+void deluxe_build_batched(const std::vector<DeluxeDesc>& descs, hipStream_t s) {
+  if (descs.empty()) return;
+  int maxe = 0;
+  for (auto& d : descs) maxe = std::max(maxe, 2 * d.n * (d.m + 1) * d.n);
+  const DeluxeDesc* dd = Arena::for_stream(s).put(descs);
+  deluxe_build_kernel<<<dim3(std::min(256, (maxe + 255) / 256), descs.size()), 256, 0, s>>>(dd);
+  ABDDC_HIP(hipGetLastError());
+}
+
+void edge_assemble_batched(const std::vector<EdgeAsmDesc>& descs, hipStream_t s) {
+  if (descs.empty()) return;
+  for (auto& d : descs)
+    ABDDC_REQUIRE(d.nE <= 16 && (d.m - 1) * d.nE <= 48 && d.m <= 4, ABDDC_EINVAL, "edge too large");
+  const EdgeAsmDesc* dd = Arena::for_stream(s).put(descs);
+  edge_assemble_kernel<<<descs.size(), 256, 0, s>>>(dd);
+  ABDDC_HIP(hipGetLastError());
+}
+
+void coarse_add_batched(const std::vector<CoarseAddDesc>& descs, double* SPi, int64_t ldc, hipStream_t s) {
+  if (descs.empty()) return;
+  int maxe = 0;
+  for (auto& d : descs) maxe = std::max(maxe, d.n * d.n);
+  if (maxe == 0) return;
+  const CoarseAddDesc* dd = Arena::for_stream(s).put(descs);
+  coarse_add_kernel<<<dim3(std::min(64, (maxe + 255) / 256), descs.size()), 256, 0, s>>>(dd, SPi, ldc);
+  ABDDC_HIP(hipGetLastError());
+}
+
+void axpby_batched(const std::vector<AxpbyDesc>& descs, hipStream_t s) {
+  if (descs.empty()) return;
+  int maxe = 0;
+  for (auto& d : descs) maxe = std::max(maxe, d.nr * d.nc);
+  if (maxe == 0) return;
+  const AxpbyDesc* dd = Arena::for_stream(s).put(descs);
+  axpby_kernel<<<dim3(std::min(256, (maxe + 255) / 256), descs.size()), 256, 0, s>>>(dd);
+  ABDDC_HIP(hipGetLastError());
+}
+
+}  // namespace abddc

@@ -1,0 +1,799 @@
+// Host orchestration of the adaptive coarse-space setup (Section 3):
+// deluxe weights, face eigenproblems (eq. equ-4-8), new edge eigenproblems
+// (eq. equ-5-21) with the SVD/QR edge basis, change of basis, the local
+// constrained factorisations, the coarse matrix, and the per-iteration
+// operators of M^{-1}.  Each stage is a few batched launches over all
+// faces / edges / subdomains; the host only builds index maps and
+// descriptors and reads back the primal counts.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+
+#include "apply.h"
+#include "arena.h"
+#include "ctx.h"
+#include "internal.h"
+#include "setup_k.h"
+
+namespace abddc {
+
+namespace {
+
+struct IntPool {
+  // Concatenated host int arrays uploaded once; device pointers handed out by offset.
+  std::vector<int32_t> h;
+  DevBuf<int32_t> d;
+  size_t add(const std::vector<int32_t>& v) {
+    size_t off = h.size();
+    h.insert(h.end(), v.begin(), v.end());
+    return off;
+  }
+  void upload(hipStream_t s) { d = to_device(h, s); }
+  const int32_t* ptr(size_t off) const { return d.p + off; }
+};
+
+void record(abddc_ctx* c, int i) {
+  if (c->events) ABDDC_HIP(hipEventRecord(c->ev[i], c->stream));
+}
+
+int check_flag(abddc_ctx* c) {
+  int h = 0;
+  ABDDC_HIP(hipMemcpyAsync(&h, c->d_flag.p, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  ABDDC_HIP(hipStreamSynchronize(c->stream));
+  return h;
+}
+
+void require_flag_clean(abddc_ctx* c, const char* stage) {
+  const int h = check_flag(c);
+  if (h & 1) throw Error(ABDDC_ESINGULAR, std::string(stage) + ": zero or non-finite pivot");
+  if (h & 2) throw Error(ABDDC_EEIG, std::string(stage) + ": eigenproblem metric not positive definite");
+}
+
+}  // namespace
+
+void run_setup(abddc_ctx* c) {
+  const Topology& T = c->topo;
+  hipStream_t s = c->stream;
+  const int nsub = T.n_sub;
+  const int nf = (int)T.faces.size(), ned = (int)T.edges.size(), nvx = (int)T.vertices.size();
+  const bool useS = c->opt.deluxe_source == ABDDC_DELUXE_S;
+  const double* src_dx = useS ? c->dS.p : c->dB.p;
+  auto Sblk = [&](const double* base, int sub, int obj) {
+    const int off = T.sub[sub].local_pos(obj);
+    return base + c->soff[sub] + (int64_t)off * c->nB[sub] + off;
+  };
+  c->d_flag.zero(s);
+
+  // ------------------------------------------------------------ deluxe
+  record(c, 2);
+  const int nobj = (int)T.objects.size();
+  c->dxoff.assign((size_t)nobj * 8, -1);
+  int64_t dxtot = 0;
+  for (int k = 0; k < nobj; ++k) {
+    const Object& o = T.objects[k];
+    if (o.kind == KIND_VERTEX) continue;
+    for (size_t q = 0; q < o.subs.size(); ++q) {
+      c->dxoff[(size_t)k * 8 + q] = dxtot;
+      dxtot += (int64_t)o.n * o.n;
+    }
+  }
+  c->dD.alloc(std::max<int64_t>(dxtot, 1));
+  {
+    std::vector<int64_t> woff(nobj, -1);
+    int64_t wtot = 0;
+    for (int k = 0; k < nobj; ++k) {
+      const Object& o = T.objects[k];
+      if (o.kind == KIND_VERTEX) continue;
+      woff[k] = wtot;
+      wtot += (int64_t)2 * o.n * (o.subs.size() + 1) * o.n;
+    }
+    DevBuf<double> wk(std::max<int64_t>(wtot, 1));
+    std::vector<DeluxeDesc> dd;
+    std::vector<PluDesc<double>> pd;
+    std::vector<GatherDesc> gd;
+    for (int k = 0; k < nobj; ++k) {
+      const Object& o = T.objects[k];
+      if (o.kind == KIND_VERTEX) continue;
+      DeluxeDesc d{};
+      d.n = o.n;
+      d.m = (int)o.subs.size();
+      for (int q = 0; q < d.m; ++q) {
+        d.src[q] = Sblk(src_dx, o.subs[q], k);
+        d.lds[q] = c->nB[o.subs[q]];
+      }
+      d.dst = wk.p + woff[k];
+      dd.push_back(d);
+      const int cols = (d.m + 1) * o.n;
+      pd.push_back({wk.p + woff[k], 2 * o.n, cols, cols, o.n});
+      for (int q = 0; q < d.m; ++q)
+        gd.push_back({wk.p + woff[k] + (int64_t)o.n * cols + o.n + (int64_t)q * o.n, c->dD.p + c->dxoff[(size_t)k * 8 + q],
+                      nullptr, nullptr, o.n, o.n, cols, o.n, 1.0});
+    }
+    deluxe_build_batched(dd, s);
+    partial_lu<double>(pd, c->d_flag.p, s);
+    gather_batched(gd, s);
+    require_flag_clean(c, "deluxe");
+  }
+
+  // ------------------------------------------------------------- faces
+  record(c, 3);
+  c->pF.assign(nf, 0);
+  c->tfoff.assign(nf, 0);
+  c->wfoff.assign(nf, 0);
+  int64_t ftot = 0;
+  for (int f = 0; f < nf; ++f) {
+    c->tfoff[f] = ftot;
+    c->wfoff[f] = 0;
+    ftot += (int64_t)T.objects[T.faces[f]].n * T.objects[T.faces[f]].n;
+  }
+  {
+    int64_t wsum = 0;
+    for (int f = 0; f < nf; ++f) {
+      c->wfoff[f] = wsum;
+      wsum += T.objects[T.faces[f]].n;
+    }
+    c->dWF.alloc(std::max<int64_t>(wsum, 1));
+  }
+  c->dTF.alloc(std::max<int64_t>(ftot, 1));
+  if (nf > 0) {
+    DevBuf<double> W1(ftot), W2(ftot), BF(ftot), Sum(ftot), Pinv(ftot), T1(ftot), Bt(ftot), XF(ftot);
+    // B_F = D_j^T B_F^(i) D_j + D_i^T B_F^(j) D_i
+    std::vector<GemmDesc<double>> g1, g2, g3;
+    for (int f = 0; f < nf; ++f) {
+      const int k = T.faces[f];
+      const Object& o = T.objects[k];
+      const int i = o.subs[0], j = o.subs[1], n = o.n;
+      const double* Di = c->dD.p + c->dxoff[(size_t)k * 8 + 0];
+      const double* Dj = c->dD.p + c->dxoff[(size_t)k * 8 + 1];
+      g1.push_back({Sblk(c->dB.p, i, k), Dj, W1.p + c->tfoff[f], n, n, n, c->nB[i], n, n});
+      g1.push_back({Sblk(c->dB.p, j, k), Di, W2.p + c->tfoff[f], n, n, n, c->nB[j], n, n});
+      g2.push_back({Dj, W1.p + c->tfoff[f], BF.p + c->tfoff[f], n, n, n, n, n, n});
+      g3.push_back({Di, W2.p + c->tfoff[f], BF.p + c->tfoff[f], n, n, n, n, n, n});
+    }
+    gemm_batched<double>(g1, false, false, 1.0, 0.0, s);
+    gemm_batched<double>(g2, true, false, 1.0, 0.0, s);
+    gemm_batched<double>(g3, true, false, 1.0, 1.0, s);
+
+    // Btilde_F^(nu): Schur complement of B^(nu) onto F (eliminate Gamma_nu minus F)
+    std::vector<int64_t> eoff(2 * nf);
+    int64_t etot = 0;
+    for (int f = 0; f < nf; ++f)
+      for (int side = 0; side < 2; ++side) {
+        const int sub = T.objects[T.faces[f]].subs[side];
+        eoff[2 * f + side] = etot;
+        etot += (int64_t)c->nB[sub] * c->nB[sub];
+      }
+    DevBuf<double> E(etot);
+    IntPool pool;
+    std::vector<size_t> mapoff(2 * nf);
+    for (int f = 0; f < nf; ++f) {
+      const int k = T.faces[f];
+      for (int side = 0; side < 2; ++side) {
+        const int sub = T.objects[k].subs[side];
+        const int off = T.sub[sub].local_pos(k), n = T.objects[k].n, nB = c->nB[sub];
+        std::vector<int32_t> mp;
+        for (int q = 0; q < nB; ++q)
+          if (q < off || q >= off + n) mp.push_back(q);
+        for (int q = 0; q < n; ++q) mp.push_back(off + q);
+        mapoff[2 * f + side] = pool.add(mp);
+      }
+    }
+    pool.upload(s);
+    std::vector<GatherDesc> gd;
+    std::vector<PluDesc<double>> pd;
+    for (int f = 0; f < nf; ++f)
+      for (int side = 0; side < 2; ++side) {
+        const int sub = T.objects[T.faces[f]].subs[side];
+        const int nB = c->nB[sub], n = T.objects[T.faces[f]].n;
+        gd.push_back({c->dB.p + c->soff[sub], E.p + eoff[2 * f + side], pool.ptr(mapoff[2 * f + side]),
+                      pool.ptr(mapoff[2 * f + side]), nB, nB, nB, nB, 1.0});
+        pd.push_back({E.p + eoff[2 * f + side], nB, nB, nB, nB - n});
+      }
+    gather_batched(gd, s);
+    partial_lu<double>(pd, c->d_flag.p, s);
+
+    // parallel sum Btilde_F = A (A + B)^+ B
+    std::vector<AxpbyDesc> ad;
+    std::vector<PinvDesc> pv;
+    std::vector<GemmDesc<double>> h1, h2;
+    std::vector<SymDesc> sy;
+    for (int f = 0; f < nf; ++f) {
+      const int k = T.faces[f];
+      const int n = T.objects[k].n;
+      const int si = T.objects[k].subs[0], sj = T.objects[k].subs[1];
+      const int ldi = c->nB[si], ldj = c->nB[sj];
+      const double* A = E.p + eoff[2 * f] + (int64_t)(ldi - n) * ldi + (ldi - n);
+      const double* B = E.p + eoff[2 * f + 1] + (int64_t)(ldj - n) * ldj + (ldj - n);
+      ad.push_back({A, B, Sum.p + c->tfoff[f], n, n, ldi, ldj, n, 1.0, 1.0});
+      pv.push_back({Sum.p + c->tfoff[f], Pinv.p + c->tfoff[f], n, n});
+      h1.push_back({Pinv.p + c->tfoff[f], B, T1.p + c->tfoff[f], n, n, n, n, ldj, n});
+      h2.push_back({A, T1.p + c->tfoff[f], Bt.p + c->tfoff[f], n, n, n, ldi, n, n});
+      sy.push_back({Bt.p + c->tfoff[f], Sum.p + c->tfoff[f], n, n, n});
+    }
+    axpby_batched(ad, s);
+    pinv_batched(pv, c->opt.pinv_rtol, s);
+    gemm_batched<double>(h1, false, false, 1.0, 0.0, s);
+    gemm_batched<double>(h2, false, false, 1.0, 0.0, s);
+    sym_batched(sy, s);  // Sum now holds sym(Btilde_F)
+    require_flag_clean(c, "face elimination");
+
+    // Btilde_F y = mu B_F y
+    std::vector<SygvDesc> gv;
+    for (int f = 0; f < nf; ++f)
+      gv.push_back({Sum.p + c->tfoff[f], BF.p + c->tfoff[f], c->dWF.p + c->wfoff[f], XF.p + c->tfoff[f],
+                    T.objects[T.faces[f]].n});
+    sygv_batched(gv, c->d_flag.p, s);
+    require_flag_clean(c, "face eigenproblem");
+    std::vector<double> mu = to_host(c->dWF.p, c->dWF.n, s);
+    std::vector<QrDesc> qd;
+    for (int f = 0; f < nf; ++f) {
+      const int n = T.objects[T.faces[f]].n;
+      int p = 0;
+      for (int q = 0; q < n; ++q) {
+        const double m = mu[c->wfoff[f] + q];
+        if (m <= 1.0 / c->opt.theta_face) ++p;
+        const double lam = m > 0 ? 1.0 / m : INFINITY;
+        if (std::fabs(lam - c->opt.theta_face) <= c->opt.tie_rtol * c->opt.theta_face) ++c->n_ties;
+      }
+      c->pF[f] = p;
+      qd.push_back({XF.p + c->tfoff[f], c->dTF.p + c->tfoff[f], n, p, n});
+    }
+    qr_complete_batched(qd, s);
+    ABDDC_HIP(hipStreamSynchronize(s));
+  }
+
+  // primal numbering: vertices, face primals, edge primals
+  c->n_vertex = nvx;
+  std::vector<int> face_pbase(nf, 0);
+  int nxt = nvx;
+  for (int f = 0; f < nf; ++f) {
+    face_pbase[f] = nxt;
+    nxt += c->pF[f];
+  }
+  c->pnum_face = nxt - nvx;
+
+  // ------------------------------------------------------------- edges
+  record(c, 4);
+  c->rE.assign(ned, 0);
+  c->nselE.assign(ned, 0);
+  c->teoff.assign(ned, 0);
+  c->weoff.assign(ned, 0);
+  {
+    int64_t tt = 0, wt = 0;
+    for (int e = 0; e < ned; ++e) {
+      const Object& o = T.objects[T.edges[e]];
+      c->teoff[e] = tt;
+      tt += (int64_t)o.n * o.n;
+      c->weoff[e] = wt;
+      wt += (int64_t)(o.subs.size() - 1) * o.n;
+    }
+    c->dTE.alloc(std::max<int64_t>(tt, 1));
+    c->dWE.alloc(std::max<int64_t>(wt, 1));
+  }
+  if (ned > 0) {
+    // face-rotated Bbar^(s) = T_F^T B^(s) T_F on every face block
+    DevBuf<double> Y(c->dB.n), Bbar(c->dB.n);
+    ABDDC_HIP(hipMemcpyAsync(Y.p, c->dB.p, c->dB.n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    std::vector<GemmDesc<double>> gc, gr;
+    for (int sub = 0; sub < nsub; ++sub) {
+      const SubInfo& si = T.sub[sub];
+      const int nB = c->nB[sub];
+      for (size_t q = 0; q < si.objs.size(); ++q) {
+        const int k = si.objs[q];
+        if (T.objects[k].kind != KIND_FACE) continue;
+        const int f = T.kind_index[k], n = T.objects[k].n, off = si.obj_off[q];
+        gc.push_back({c->dB.p + c->soff[sub] + off, c->dTF.p + c->tfoff[f], Y.p + c->soff[sub] + off, nB, n, n, nB, n, nB});
+        gr.push_back({c->dTF.p + c->tfoff[f], Y.p + c->soff[sub] + (int64_t)off * nB, Bbar.p + c->soff[sub] + (int64_t)off * nB,
+                      n, nB, n, n, nB, nB});
+      }
+    }
+    gemm_batched<double>(gc, false, false, 1.0, 0.0, s);
+    ABDDC_HIP(hipMemcpyAsync(Bbar.p, Y.p, c->dB.n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    gemm_batched<double>(gr, true, false, 1.0, 0.0, s);
+
+    // stage 1: per subdomain eliminate all face dual coordinates; the Schur
+    // complement W^(s) lives on [edge dofs, vertex dofs, face primals]
+    IntPool pool;
+    std::vector<size_t> m1off(nsub);
+    std::vector<int> nfd(nsub), nW(nsub), nedof(nsub);
+    std::vector<std::vector<int>> edge_pos_in_W(nsub);   // per object position list index
+    std::vector<std::vector<int32_t>> Hpid(nsub);          // global primal ids of H_s (W order)
+    for (int sub = 0; sub < nsub; ++sub) {
+      const SubInfo& si = T.sub[sub];
+      std::vector<int32_t> fdual, edofs, vdofs, fprim, pid_v, pid_f;
+      edge_pos_in_W[sub].assign(si.objs.size(), -1);
+      for (size_t q = 0; q < si.objs.size(); ++q) {
+        const int k = si.objs[q];
+        const Object& o = T.objects[k];
+        const int off = si.obj_off[q];
+        if (o.kind == KIND_FACE) {
+          const int f = T.kind_index[k], p = c->pF[f];
+          for (int l = 0; l < p; ++l) {
+            fprim.push_back(off + l);
+            pid_f.push_back(face_pbase[f] + l);
+          }
+          for (int l = p; l < o.n; ++l) fdual.push_back(off + l);
+        } else if (o.kind == KIND_EDGE) {
+          edge_pos_in_W[sub][q] = (int)edofs.size();
+          for (int l = 0; l < o.n; ++l) edofs.push_back(off + l);
+        } else {
+          vdofs.push_back(off);
+          pid_v.push_back(T.kind_index[k]);
+        }
+      }
+      std::vector<int32_t> mp = fdual;
+      mp.insert(mp.end(), edofs.begin(), edofs.end());
+      mp.insert(mp.end(), vdofs.begin(), vdofs.end());
+      mp.insert(mp.end(), fprim.begin(), fprim.end());
+      m1off[sub] = pool.add(mp);
+      nfd[sub] = (int)fdual.size();
+      nedof[sub] = (int)edofs.size();
+      nW[sub] = c->nB[sub] - nfd[sub];
+      Hpid[sub] = pid_v;
+      Hpid[sub].insert(Hpid[sub].end(), pid_f.begin(), pid_f.end());
+    }
+    // stage 2 maps per (edge, member): [other edge dofs; E dofs; H] inside W
+    std::vector<size_t> m2off((size_t)ned * 4);
+    std::vector<int64_t> e2off((size_t)ned * 4);
+    std::vector<size_t> roff((size_t)ned * 4);
+    std::vector<int> nHunion(ned);
+    int64_t e2tot = 0;
+    for (int e = 0; e < ned; ++e) {
+      const int k = T.edges[e];
+      const Object& o = T.objects[k];
+      std::vector<int32_t> uni;
+      for (int sub : o.subs) uni.insert(uni.end(), Hpid[sub].begin(), Hpid[sub].end());
+      std::sort(uni.begin(), uni.end());
+      uni.erase(std::unique(uni.begin(), uni.end()), uni.end());
+      const bool separate = c->opt.edge_h_mode == ABDDC_H_SEPARATE;
+      int hbase = 0;
+      for (size_t q = 0; q < o.subs.size(); ++q) {
+        const int sub = o.subs[q];
+        const SubInfo& si = T.sub[sub];
+        const int qi = (int)(std::lower_bound(si.objs.begin(), si.objs.end(), k) - si.objs.begin());
+        const int epos = edge_pos_in_W[sub][qi];
+        std::vector<int32_t> mp;
+        for (int t = 0; t < nedof[sub]; ++t)
+          if (t < epos || t >= epos + o.n) mp.push_back(t);
+        for (int t = 0; t < o.n; ++t) mp.push_back(epos + t);
+        for (int t = nedof[sub]; t < nW[sub]; ++t) mp.push_back(t);
+        m2off[(size_t)e * 4 + q] = pool.add(mp);
+        e2off[(size_t)e * 4 + q] = e2tot;
+        e2tot += (int64_t)nW[sub] * nW[sub];
+        std::vector<int32_t> R;
+        for (size_t h = 0; h < Hpid[sub].size(); ++h)
+          R.push_back(separate ? hbase + (int)h
+                               : (int)(std::lower_bound(uni.begin(), uni.end(), Hpid[sub][h]) - uni.begin()));
+        hbase += (int)Hpid[sub].size();
+        roff[(size_t)e * 4 + q] = pool.add(R);
+      }
+      nHunion[e] = separate ? hbase : (int)uni.size();
+    }
+    pool.upload(s);
+    DevBuf<double> E1(c->dB.n);
+    {
+      std::vector<GatherDesc> gd;
+      std::vector<PluDesc<double>> pd;
+      for (int sub = 0; sub < nsub; ++sub) {
+        const int nB = c->nB[sub];
+        gd.push_back({Bbar.p + c->soff[sub], E1.p + c->soff[sub], pool.ptr(m1off[sub]), pool.ptr(m1off[sub]), nB, nB,
+                      nB, nB, 1.0});
+        pd.push_back({E1.p + c->soff[sub], nB, nB, nB, nfd[sub]});
+      }
+      gather_batched(gd, s);
+      partial_lu<double>(pd, c->d_flag.p, s);
+    }
+    DevBuf<double> E2(std::max<int64_t>(e2tot, 1));
+    {
+      std::vector<GatherDesc> gd;
+      std::vector<PluDesc<double>> pd;
+      for (int e = 0; e < ned; ++e) {
+        const Object& o = T.objects[T.edges[e]];
+        for (size_t q = 0; q < o.subs.size(); ++q) {
+          const int sub = o.subs[q], nB = c->nB[sub], w = nW[sub];
+          const double* Wbase = E1.p + c->soff[sub] + (int64_t)nfd[sub] * nB + nfd[sub];
+          gd.push_back({Wbase, E2.p + e2off[(size_t)e * 4 + q], pool.ptr(m2off[(size_t)e * 4 + q]),
+                        pool.ptr(m2off[(size_t)e * 4 + q]), w, w, nB, w, 1.0});
+          pd.push_back({E2.p + e2off[(size_t)e * 4 + q], w, w, w, nedof[sub] - o.n});
+        }
+      }
+      gather_batched(gd, s);
+      partial_lu<double>(pd, c->d_flag.p, s);
+    }
+    // M_E and the coupled matrix; Schur complement onto the jumps
+    std::vector<int64_t> meoff(ned), qoff(ned), btoff(ned);
+    int64_t metot = 0, qtot = 0;
+    for (int e = 0; e < ned; ++e) {
+      const Object& o = T.objects[T.edges[e]];
+      const int nw = (int)(o.subs.size() - 1) * o.n;
+      const int nv = (int)o.subs.size() * o.n + nHunion[e];
+      meoff[e] = metot;
+      metot += (int64_t)nw * nw;
+      qoff[e] = qtot;
+      qtot += (int64_t)nv * nv;
+    }
+    DevBuf<double> ME(std::max<int64_t>(metot, 1)), Qb(std::max<int64_t>(qtot, 1)), Btt(std::max<int64_t>(metot, 1)),
+        XE(std::max<int64_t>(metot, 1));
+    std::vector<EdgeAsmDesc> ea;
+    std::vector<PluDesc<double>> pd;
+    std::vector<SymDesc> sy;
+    for (int e = 0; e < ned; ++e) {
+      const int k = T.edges[e];
+      const Object& o = T.objects[k];
+      EdgeAsmDesc d{};
+      d.nE = o.n;
+      d.m = (int)o.subs.size();
+      d.nH = nHunion[e];
+      d.nv = d.m * d.nE + d.nH;
+      for (int q = 0; q < d.m; ++q) {
+        const int sub = o.subs[q], w = nW[sub];
+        d.D[q] = c->dD.p + c->dxoff[(size_t)k * 8 + q];
+        d.BE[q] = Sblk(c->dB.p, sub, k);
+        d.ldBE[q] = c->nB[sub];
+        const int kk = w - (nedof[sub] - o.n);  // trailing order n_E + n_H,s
+        d.Bt[q] = E2.p + e2off[(size_t)e * 4 + q] + (int64_t)(w - kk) * w + (w - kk);
+        d.ldBt[q] = w;
+        d.nHk[q] = (int)Hpid[sub].size();
+        d.R[q] = pool.ptr(roff[(size_t)e * 4 + q]);
+      }
+      d.ME = ME.p + meoff[e];
+      d.Q = Qb.p + qoff[e];
+      ea.push_back(d);
+      const int nw = (d.m - 1) * d.nE;
+      pd.push_back({Qb.p + qoff[e], d.nv, d.nv, d.nv, d.nv - nw});
+      sy.push_back({Qb.p + qoff[e] + (int64_t)(d.nv - nw) * d.nv + (d.nv - nw), Btt.p + meoff[e], nw, d.nv, nw});
+    }
+    edge_assemble_batched(ea, s);
+    partial_lu<double>(pd, c->d_flag.p, s);
+    sym_batched(sy, s);
+    require_flag_clean(c, "edge elimination");
+    std::vector<SygvDesc> gv;
+    for (int e = 0; e < ned; ++e) {
+      const Object& o = T.objects[T.edges[e]];
+      const int nw = (int)(o.subs.size() - 1) * o.n;
+      gv.push_back({Btt.p + meoff[e], ME.p + meoff[e], c->dWE.p + c->weoff[e], XE.p + meoff[e], nw});
+    }
+    sygv_batched(gv, c->d_flag.p, s);
+    require_flag_clean(c, "edge eigenproblem");
+    std::vector<double> mu = to_host(c->dWE.p, c->dWE.n, s);
+    // G = [g_{l,k}] (n_E x (m-1) |N_E|) and its left singular basis
+    int64_t gtot = 0;
+    std::vector<int64_t> goffE(ned);
+    for (int e = 0; e < ned; ++e) {
+      const Object& o = T.objects[T.edges[e]];
+      const int m1 = (int)o.subs.size() - 1, nw = m1 * o.n;
+      int ns = 0;
+      for (int q = 0; q < nw; ++q) {
+        const double m = mu[c->weoff[e] + q];
+        if (m <= 1.0 / c->opt.theta_edge) ++ns;
+        const double lam = m > 0 ? 1.0 / m : INFINITY;
+        if (std::fabs(lam - c->opt.theta_edge) <= c->opt.tie_rtol * c->opt.theta_edge) ++c->n_ties;
+      }
+      c->nselE[e] = ns;
+      goffE[e] = gtot;
+      gtot += (int64_t)o.n * m1 * ns;
+    }
+    DevBuf<double> G(std::max<int64_t>(gtot, 1));
+    DevBuf<int32_t> ranks(std::max(ned, 1));
+    IntPool gp;
+    std::vector<int32_t> iota(64);
+    for (int q = 0; q < 64; ++q) iota[q] = q;
+    const size_t iota_off = gp.add(iota);
+    std::vector<size_t> rowmap_off((size_t)ned * 4);
+    for (int e = 0; e < ned; ++e) {
+      const Object& o = T.objects[T.edges[e]];
+      for (int b = 0; b < (int)o.subs.size() - 1; ++b) {
+        std::vector<int32_t> rm(o.n);
+        for (int i = 0; i < o.n; ++i) rm[i] = b * o.n + i;
+        rowmap_off[(size_t)e * 4 + b] = gp.add(rm);
+      }
+    }
+    gp.upload(s);
+    std::vector<GatherDesc> gd;
+    std::vector<SvdDesc> sv;
+    for (int e = 0; e < ned; ++e) {
+      const Object& o = T.objects[T.edges[e]];
+      const int m1 = (int)o.subs.size() - 1, nw = m1 * o.n, ns = c->nselE[e];
+      for (int b = 0; b < m1 && ns > 0; ++b)
+        gd.push_back({XE.p + meoff[e], G.p + goffE[e] + (int64_t)b * ns, gp.ptr(rowmap_off[(size_t)e * 4 + b]),
+                      gp.ptr(iota_off), o.n, ns, nw, m1 * ns, 1.0});
+      sv.push_back({G.p + goffE[e], c->dTE.p + c->teoff[e], ranks.p + e, o.n, m1 * ns, std::max(m1 * ns, 1)});
+    }
+    gather_batched(gd, s);
+    svd_left_batched(sv, c->opt.svd_rtol, s);
+    std::vector<int32_t> rk = to_host(ranks.p, ned, s);
+    for (int e = 0; e < ned; ++e) c->rE[e] = rk[e];
+  }
+  c->pnum_edge = 0;
+  std::vector<int> edge_pbase(ned, 0);
+  for (int e = 0; e < ned; ++e) {
+    edge_pbase[e] = nxt;
+    nxt += c->rE[e];
+    c->pnum_edge += c->rE[e];
+  }
+  c->n_primal = nxt;
+
+  // -------------------------------------------- change of basis + local
+  record(c, 5);
+  // local coordinate order per object: [primal, dual]; Pi / Delta positions
+  std::vector<std::vector<int32_t>> Pi(nsub), Dl(nsub), Pid(nsub);
+  for (int sub = 0; sub < nsub; ++sub) {
+    const SubInfo& si = T.sub[sub];
+    for (size_t q = 0; q < si.objs.size(); ++q) {
+      const int k = si.objs[q];
+      const Object& o = T.objects[k];
+      const int off = si.obj_off[q];
+      int p = 0, base = 0;
+      if (o.kind == KIND_VERTEX) {
+        p = 1;
+        base = T.kind_index[k];
+      } else if (o.kind == KIND_FACE) {
+        p = c->pF[T.kind_index[k]];
+        base = face_pbase[T.kind_index[k]];
+      } else {
+        p = c->rE[T.kind_index[k]];
+        base = edge_pbase[T.kind_index[k]];
+      }
+      for (int l = 0; l < p; ++l) {
+        Pi[sub].push_back(off + l);
+        Pid[sub].push_back(base + l);
+      }
+      for (int l = p; l < o.n; ++l) Dl[sub].push_back(off + l);
+    }
+  }
+  c->nPi.assign(nsub, 0);
+  c->moff.assign(nsub, 0);
+  c->uoff.assign(nsub, 0);
+  c->ooff.assign(nsub, 0);
+  c->poff.assign(nsub, 0);
+  int64_t mt = 0, ut = 0, ot = 0, pt = 0, at = 0, wt = 0;
+  std::vector<int64_t> aoff2(nsub), woffX;
+  std::vector<std::vector<int64_t>> wpos(nsub);
+  for (int sub = 0; sub < nsub; ++sub) {
+    const int nB = c->nB[sub], nP = (int)Pi[sub].size(), nD = (int)Dl[sub].size();
+    c->nPi[sub] = nP;
+    c->moff[sub] = mt;
+    mt += (int64_t)(nB + nP) * nB;
+    c->uoff[sub] = ut;
+    ut += (int64_t)nB * nP;
+    c->ooff[sub] = ot;
+    ot += nB + nP;
+    c->poff[sub] = pt;
+    pt += nP;
+    aoff2[sub] = at;
+    at += (int64_t)(2 * nD + nP) * (2 * nD + nP);
+    for (int k : T.sub[sub].objs) {
+      wpos[sub].push_back(wt);
+      wt += (int64_t)T.objects[k].n * T.objects[k].n;
+    }
+  }
+  DevBuf<double> Sb(c->dS.n), Y(c->dS.n), Aug(std::max<int64_t>(at, 1)), WX(std::max<int64_t>(wt, 1));
+  DevBuf<double> Kt(c->dS.n), Y2(c->dS.n), Vt(std::max<int64_t>(ut, 1)), Ut(std::max<int64_t>(ut, 1));
+  c->dM.alloc(std::max<int64_t>(mt, 1));
+  c->dU.alloc(std::max<int64_t>(ut, 1));
+  {
+    // Sbar = T^T S T (face and edge blocks)
+    ABDDC_HIP(hipMemcpyAsync(Y.p, c->dS.p, c->dS.n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    std::vector<GemmDesc<double>> gc, gr, wg;
+    std::vector<SetDesc> vset;
+    IntPool vp;
+    std::vector<int32_t> zero1(1, 0);
+    const size_t z_off = vp.add(zero1);
+    vp.upload(s);
+    for (int sub = 0; sub < nsub; ++sub) {
+      const SubInfo& si = T.sub[sub];
+      const int nB = c->nB[sub];
+      for (size_t q = 0; q < si.objs.size(); ++q) {
+        const int k = si.objs[q];
+        const Object& o = T.objects[k];
+        const int off = si.obj_off[q], n = o.n;
+        double* wx = WX.p + wpos[sub][q];
+        if (o.kind == KIND_VERTEX) {
+          vset.push_back({wx, vp.ptr(z_off), vp.ptr(z_off), 1, 1, 1.0 / (double)o.subs.size()});
+          continue;
+        }
+        const double* TX = o.kind == KIND_FACE ? c->dTF.p + c->tfoff[T.kind_index[k]] : c->dTE.p + c->teoff[T.kind_index[k]];
+        gc.push_back({c->dS.p + c->soff[sub] + off, TX, Y.p + c->soff[sub] + off, nB, n, n, nB, n, nB});
+        gr.push_back({TX, Y.p + c->soff[sub] + (int64_t)off * nB, Sb.p + c->soff[sub] + (int64_t)off * nB, n, nB, n, n, nB, nB});
+        const int mem = (int)(std::lower_bound(o.subs.begin(), o.subs.end(), sub) - o.subs.begin());
+        wg.push_back({c->dD.p + c->dxoff[(size_t)k * 8 + mem], TX, wx, n, n, n, n, n, n});
+      }
+    }
+    gemm_batched<double>(gc, false, false, 1.0, 0.0, s);
+    ABDDC_HIP(hipMemcpyAsync(Sb.p, Y.p, c->dS.n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    gemm_batched<double>(gr, true, false, 1.0, 0.0, s);
+    gemm_batched<double>(wg, false, false, 1.0, 0.0, s);   // W_X = D_X T_X
+    set_batched(vset, s);                                    // vertices: 1/|n(V)|
+  }
+  {
+    // augmented [[Sdd, Sdp, I], [Spd, Spp, 0], [-I, 0, 0]], eliminate Delta
+    IntPool pool;
+    std::vector<size_t> am(nsub), dr(nsub), dc(nsub), kt(nsub), vr(nsub), vc(nsub), ur(nsub), uc(nsub), pi_off(nsub),
+        pidx(nsub), iota_off(nsub);
+    for (int sub = 0; sub < nsub; ++sub) {
+      const int nB = c->nB[sub], nP = (int)Pi[sub].size(), nD = (int)Dl[sub].size();
+      std::vector<int32_t> mp = Dl[sub];
+      mp.insert(mp.end(), Pi[sub].begin(), Pi[sub].end());
+      for (int q = 0; q < nD; ++q) mp.push_back(-1);
+      am[sub] = pool.add(mp);
+      std::vector<int32_t> r1(nD), c1(nD), r2(nD), c2(nD);
+      for (int q = 0; q < nD; ++q) {
+        r1[q] = q;
+        c1[q] = nD + nP + q;
+        r2[q] = nD + nP + q;
+        c2[q] = q;
+      }
+      dr[sub] = pool.add(r1);
+      dc[sub] = pool.add(c1);
+      kt[sub] = pool.add(r2);
+      (void)c2;
+      vr[sub] = pool.add(c2);
+      // Ktilde map (local coordinate q -> aug row/col of K), -1 on Pi
+      std::vector<int32_t> km(nB, -1);
+      for (int q = 0; q < nD; ++q) km[Dl[sub][q]] = nD + nP + q;
+      vc[sub] = pool.add(km);
+      // Pi rows of the aug matrix and the -Phi columns
+      std::vector<int32_t> pr(nP), pc(nP), it(nP);
+      for (int l = 0; l < nP; ++l) {
+        pr[l] = nD + l;
+        it[l] = l;
+      }
+      ur[sub] = pool.add(pr);
+      pi_off[sub] = pool.add(Pi[sub]);
+      iota_off[sub] = pool.add(it);
+      pidx[sub] = pool.add(Pid[sub]);
+    }
+    pool.upload(s);
+    std::vector<GatherDesc> gd;
+    std::vector<SetDesc> st;
+    std::vector<PluDesc<double>> pd;
+    for (int sub = 0; sub < nsub; ++sub) {
+      const int nB = c->nB[sub], nP = (int)Pi[sub].size(), nD = (int)Dl[sub].size(), na = 2 * nD + nP;
+      gd.push_back({Sb.p + c->soff[sub], Aug.p + aoff2[sub], pool.ptr(am[sub]), pool.ptr(am[sub]), na, na, nB, na, 1.0});
+      st.push_back({Aug.p + aoff2[sub], pool.ptr(dr[sub]), pool.ptr(dc[sub]), nD, na, 1.0});
+      st.push_back({Aug.p + aoff2[sub], pool.ptr(kt[sub]), pool.ptr(vr[sub]), nD, na, -1.0});
+      pd.push_back({Aug.p + aoff2[sub], na, na, na, nD});
+    }
+    gather_batched(gd, s);
+    set_batched(st, s);
+    partial_lu<double>(pd, c->d_flag.p, s);
+    require_flag_clean(c, "local constrained factorisation");
+
+    // Ktilde (nB x nB), Vt (nP x nB) = [Psi^T | I], Ut (nB x nP) = [Phi; I]
+    gd.clear();
+    st.clear();
+    for (int sub = 0; sub < nsub; ++sub) {
+      const int nB = c->nB[sub], nP = (int)Pi[sub].size(), nD = (int)Dl[sub].size(), na = 2 * nD + nP;
+      gd.push_back({Aug.p + aoff2[sub], Kt.p + c->soff[sub], pool.ptr(vc[sub]), pool.ptr(vc[sub]), nB, nB, na, nB, 1.0});
+      if (nP > 0) {
+        gd.push_back({Aug.p + aoff2[sub], Vt.p + c->uoff[sub], pool.ptr(ur[sub]), pool.ptr(vc[sub]), nP, nB, na, nB, 1.0});
+        gd.push_back({Aug.p + aoff2[sub], Ut.p + c->uoff[sub], pool.ptr(vc[sub]), pool.ptr(ur[sub]), nB, nP, na, nP, -1.0});
+        st.push_back({Vt.p + c->uoff[sub], pool.ptr(iota_off[sub]), pool.ptr(pi_off[sub]), nP, nB, 1.0});
+        st.push_back({Ut.p + c->uoff[sub], pool.ptr(pi_off[sub]), pool.ptr(iota_off[sub]), nP, nP, 1.0});
+      }
+    }
+    gather_batched(gd, s);
+    set_batched(st, s);
+
+    // L = W Ktilde W^T, V = Vt W^T, U = W Ut (W block diagonal)
+    std::vector<GemmDesc<double>> g1, g2, g3, g4;
+    for (int sub = 0; sub < nsub; ++sub) {
+      const SubInfo& si = T.sub[sub];
+      const int nB = c->nB[sub], nP = (int)Pi[sub].size();
+      double* Lm = c->dM.p + c->moff[sub];
+      double* Vm = Lm + (int64_t)nB * nB;
+      for (size_t q = 0; q < si.objs.size(); ++q) {
+        const int n = T.objects[si.objs[q]].n, off = si.obj_off[q];
+        const double* wx = WX.p + wpos[sub][q];
+        g1.push_back({wx, Kt.p + c->soff[sub] + (int64_t)off * nB, Y2.p + c->soff[sub] + (int64_t)off * nB, n, nB, n, n, nB, nB});
+        g2.push_back({Y2.p + c->soff[sub] + off, wx, Lm + off, nB, n, n, nB, n, nB});
+        if (nP > 0) {
+          g3.push_back({Vt.p + c->uoff[sub] + off, wx, Vm + off, nP, n, n, nB, n, nB});
+          g4.push_back({wx, Ut.p + c->uoff[sub] + (int64_t)off * nP, c->dU.p + c->uoff[sub] + (int64_t)off * nP, n, nP, n, n, nP, nP});
+        }
+      }
+    }
+    gemm_batched<double>(g1, false, false, 1.0, 0.0, s);
+    gemm_batched<double>(g2, false, true, 1.0, 0.0, s);
+    gemm_batched<double>(g3, false, true, 1.0, 0.0, s);
+    gemm_batched<double>(g4, false, false, 1.0, 0.0, s);
+
+    // ----------------------------------------------------------- coarse
+    record(c, 6);
+    const int np = c->n_primal;
+    DevBuf<double> Aug2((size_t)std::max(1, 4 * np * np));
+    DevBuf<double> SPi((size_t)std::max(1, np * np));
+    SPi.zero(s);
+    // colour the subdomains by index parity: equal colours share no primal unknown
+    for (int color = 0; color < 8; ++color) {
+      std::vector<CoarseAddDesc> cd;
+      for (int sub = 0; sub < nsub; ++sub) {
+        const int sx = sub % T.nsub[0], sy = (sub / T.nsub[0]) % T.nsub[1], sz = sub / (T.nsub[0] * T.nsub[1]);
+        if (((sx & 1) | ((sy & 1) << 1) | ((sz & 1) << 2)) != color) continue;
+        const int nP = (int)Pi[sub].size(), nD = (int)Dl[sub].size(), na = 2 * nD + nP;
+        if (nP == 0) continue;
+        cd.push_back({Aug.p + aoff2[sub] + (int64_t)nD * na + nD, pool.ptr(pidx[sub]), nP, na});
+      }
+      coarse_add_batched(cd, SPi.p, np, s);
+    }
+    c->dSPinv.alloc((size_t)std::max(1, np * np));
+    if (np > 0) {
+      IntPool cp;
+      std::vector<int32_t> mp(2 * np), r1(np), c1(np), r2(np), c2(np);
+      for (int q = 0; q < 2 * np; ++q) mp[q] = q < np ? q : -1;
+      for (int q = 0; q < np; ++q) {
+        r1[q] = q;
+        c1[q] = np + q;
+        r2[q] = np + q;
+        c2[q] = q;
+      }
+      const size_t o1 = cp.add(mp), o2 = cp.add(r1), o3 = cp.add(c1), o4 = cp.add(r2), o5 = cp.add(c2);
+      cp.upload(s);
+      gather_batched({{SPi.p, Aug2.p, cp.ptr(o1), cp.ptr(o1), 2 * np, 2 * np, np, 2 * np, 1.0}}, s);
+      set_batched({{Aug2.p, cp.ptr(o2), cp.ptr(o3), np, 2 * np, 1.0}, {Aug2.p, cp.ptr(o4), cp.ptr(o5), np, 2 * np, -1.0}},
+                  s);
+      partial_lu<double>({{Aug2.p, 2 * np, 2 * np, 2 * np, np}}, c->d_flag.p, s);
+      gather_batched({{Aug2.p + (int64_t)np * 2 * np + np, c->dSPinv.p, nullptr, nullptr, np, np, 2 * np, np, 1.0}}, s);
+      require_flag_clean(c, "coarse factorisation");
+    }
+
+    // ------------------------------------------- apply metadata (device)
+    record(c, 7);
+    std::vector<int32_t> pid_all, ptr_p(np + 1, 0), idx_p, ptr_a(T.n_gamma + 1, 0), idx_a;
+    std::vector<std::vector<int32_t>> own_p(np), own_a(T.n_gamma);
+    for (int sub = 0; sub < nsub; ++sub) {
+      const int nB = c->nB[sub];
+      pid_all.insert(pid_all.end(), Pid[sub].begin(), Pid[sub].end());
+      for (size_t l = 0; l < Pid[sub].size(); ++l) own_p[Pid[sub][l]].push_back((int32_t)(c->ooff[sub] + nB + l));
+      for (int l = 0; l < nB; ++l) own_a[T.sub[sub].gamma[l]].push_back((int32_t)(c->ooff[sub] + l));
+    }
+    for (int p = 0; p < np; ++p) {
+      ptr_p[p + 1] = ptr_p[p] + (int)own_p[p].size();
+      idx_p.insert(idx_p.end(), own_p[p].begin(), own_p[p].end());
+    }
+    for (int64_t g = 0; g < T.n_gamma; ++g) {
+      ptr_a[g + 1] = ptr_a[g] + (int)own_a[g].size();
+      idx_a.insert(idx_a.end(), own_a[g].begin(), own_a[g].end());
+    }
+    c->d_pid = to_device(pid_all, s);
+    c->d_pown_ptr = to_device(ptr_p, s);
+    c->d_pown_idx = to_device(idx_p, s);
+    c->d_aown_ptr = to_device(ptr_a, s);
+    c->d_aown_idx = to_device(idx_a, s);
+    std::vector<GemvMat> mM, mU, mC;
+    std::vector<GemvBlock> bM, bU, bC;
+    int maxcM = 1, maxcU = 1;
+    for (int sub = 0; sub < nsub; ++sub) {
+      const int nB = c->nB[sub], nP = c->nPi[sub];
+      mM.push_back({c->moff[sub], c->goff[sub], c->ooff[sub], nB + nP, nB, nB, 0});
+      for (int r = 0; r < nB + nP; r += GEMV_ROWS_PER_BLOCK) bM.push_back({sub, r});
+      maxcM = std::max(maxcM, nB);
+      mU.push_back({c->uoff[sub], c->poff[sub], c->ooff[sub], nB, nP, std::max(nP, 1), 0});
+      if (nP > 0)
+        for (int r = 0; r < nB; r += GEMV_ROWS_PER_BLOCK) bU.push_back({sub, r});
+      maxcU = std::max(maxcU, nP);
+    }
+    mC.push_back({0, 0, 0, np, np, std::max(np, 1), 0});
+    for (int r = 0; r < np; r += GEMV_ROWS_PER_BLOCK) bC.push_back({0, r});
+    c->gemv_M = to_device(mM, s);
+    c->gemv_U = to_device(mU, s);
+    c->gemv_C = to_device(mC, s);
+    c->blk_M = to_device(bM, s);
+    c->blk_U = to_device(bU, s);
+    c->blk_C = to_device(bC, s);
+    c->nblk_M = (int)bM.size();
+    c->nblk_U = (int)bU.size();
+    c->nblk_C = (int)bC.size();
+    c->maxc_M = maxcM;
+    c->maxc_U = maxcU;
+    c->d_out.alloc(std::max<int64_t>(ot, 1));
+    c->d_bpi.alloc(std::max(np, 1));
+    c->d_xpi.alloc(std::max(np, 1));
+    ABDDC_HIP(hipStreamSynchronize(s));
+  }
+  record(c, 8);
+}
+
+}  // namespace abddc

@@ -1,0 +1,133 @@
+"""GPU parity: the HIP library through the C ABI against the CPU oracle on
+the same seeded inputs (FP64).
+
+Tolerances: local Schur complements and right-hand sides 1e-11 relative
+(dense elimination, rounding differs only by order and pivoting); GEP
+eigenvalues 1e-9 relative to the largest; M^{-1} r and Shat x 1e-10;
+solution 1e-10 relative at rtol 1e-8 (same iteration count, +-1 allowed at
+a threshold crossing); primal counts identical unless the oracle reports a
+near tie."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_2501_01676_amd import workloads as W  # noqa: E402
+
+CASES = {
+    "config1a": lambda: W.config1a(),
+    "config1b": lambda: W.config1b(),
+    "float3_h3": lambda: W.random_field(3, 3, 5, beta=(2.0, -1.0, 0.5)),
+    "ragged_small": lambda: W.ragged((2, 3, 2), [2, 3, 4], 11),
+}
+
+
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+@pytest.fixture(scope="module")
+def pairs():
+    _need_gpu()
+    from oracle import bddc
+    from paper_2501_01676_amd import api
+    out = {}
+    for name, fn in CASES.items():
+        p = fn()
+        print(f"[parity] {name}: oracle", flush=True)
+        o = bddc.OracleBDDC(p)
+        o.assemble()
+        o.setup_coarse_space()
+        print(f"[parity] {name}: gpu assemble+setup", flush=True)
+        g = api.Solver(p)
+        g.setup_coarse_space()
+        torch.cuda.synchronize()
+        out[name] = (p, o, g)
+    return out
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_local_schur(pairs, name):
+    p, o, g = pairs[name]
+    for s in range(o.topo.n_sub):
+        S = g.stage(0, s).reshape(o.S[s].shape)
+        assert np.abs(S - o.S[s]).max() <= 1e-11 * np.abs(o.S[s]).max(), s
+        gs = g.stage(1, s)
+        assert np.abs(gs - o.g[s]).max() <= 1e-11 * max(np.abs(o.g[s]).max(), 1e-300), s
+    gh = g.rhs().cpu().numpy()
+    assert np.abs(gh - o.ghat).max() <= 1e-11 * np.abs(o.ghat).max()
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_counts_and_spectra(pairs, name):
+    p, o, g = pairs[name]
+    if o.counts["n_near_ties"] == 0:
+        assert g.counts == o.counts
+    topo = o.topo
+    for f, k in enumerate(topo.faces):
+        mu = g.stage(2, f)
+        ref = np.sort(o.face_mu[k])
+        assert np.abs(mu - ref).max() <= 1e-9 * max(1.0, np.abs(ref).max()), f
+    for e, k in enumerate(topo.edges):
+        mu = g.stage(3, e)
+        ref = np.sort(o.edge_mu[k])
+        assert np.abs(mu - ref).max() <= 1e-9 * max(1.0, np.abs(ref).max()), e
+    cnt = g.stage(6)
+    nf = len(topo.faces)
+    assert list(cnt[:nf].astype(int)) == [o.face_p[k] for k in topo.faces]
+    assert list(cnt[nf:].astype(int)) == [o.edge_r[k] for k in topo.edges]
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_primal_subspaces(pairs, name):
+    """Constraint subspaces span(Q_X) agree (the bases themselves may differ
+    by rotations inside each subspace)."""
+    p, o, g = pairs[name]
+    topo = o.topo
+    for f, k in enumerate(topo.faces):
+        n, pF = topo.objects[k]["nodes"].size, o.face_p[k]
+        T = g.stage(4, f).reshape(n, n)
+        assert np.abs(T.T @ T - np.eye(n)).max() <= 1e-12
+        P1 = T[:, :pF] @ T[:, :pF].T
+        P2 = o.face_T[k][:, :pF] @ o.face_T[k][:, :pF].T
+        assert np.abs(P1 - P2).max() <= 1e-8, f
+    for e, k in enumerate(topo.edges):
+        n, r = topo.objects[k]["nodes"].size, o.edge_r[k]
+        T = g.stage(5, e).reshape(n, n)
+        assert np.abs(T.T @ T - np.eye(n)).max() <= 1e-12
+        P1 = T[:, :r] @ T[:, :r].T
+        P2 = o.edge_T[k][:, :r] @ o.edge_T[k][:, :r].T
+        assert np.abs(P1 - P2).max() <= 1e-8, e
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_operators(pairs, name):
+    p, o, g = pairs[name]
+    rng = np.random.default_rng(3)
+    for _ in range(3):
+        r = rng.standard_normal(o.topo.n_gamma)
+        rt = torch.from_numpy(r).cuda()
+        z = g.apply_bddc(rt).cpu().numpy()
+        zr = o.apply_bddc(r)
+        assert np.linalg.norm(z - zr) <= 1e-10 * np.linalg.norm(zr)
+        y = g.apply_schur(rt).cpu().numpy()
+        yr = o.apply_schur(r)
+        assert np.linalg.norm(y - yr) <= 1e-12 * np.linalg.norm(yr)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_solution(pairs, name):
+    p, o, g = pairs[name]
+    u_ref, info_ref = o.gmres_solve(restart=30, rtol=1e-8, maxit=300)
+    u, info = g.gmres_solve(restart=30, rtol=1e-8, maxit=300)
+    u = u.cpu().numpy()
+    assert info["converged"]
+    assert abs(info["iters"] - info_ref["iters"]) <= 1
+    assert info["relres_true"] <= 1e-8
+    assert np.linalg.norm(u - u_ref) <= 1e-10 * np.linalg.norm(u_ref)
+    h = info["history"]
+    href = np.array(info_ref["history"])
+    m = min(len(h), len(href))
+    assert np.allclose(h[:m], href[:m], rtol=1e-6, atol=1e-14)
