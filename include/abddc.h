@@ -28,8 +28,10 @@
  *    abddc_apply_bddc / abddc_apply_schur / abddc_gmres_solve.  Out of order
  *    calls return ABDDC_ESTATE.  One context must not be used by two host
  *    threads at once; different contexts are independent.
- *  - Problem arrays (abddc_problem) are HOST pointers, copied by
- *    abddc_assemble; the caller keeps ownership.
+ *  - Problem arrays (abddc_problem nu, f_nodal) are HOST pointers, or
+ *    DEVICE pointers of the context's device when arrays_on_device is set;
+ *    either way abddc_assemble copies them and the caller keeps ownership.
+ *    The width arrays are always host pointers.
  *  - Vectors passed to apply/solve (r, z, x, y, u) are DEVICE pointers of
  *    the context's device, read and written in stream order on the stream
  *    given at assemble time; the caller owns them.
@@ -87,6 +89,7 @@ typedef struct {
   const double* f_nodal;    /* NULL, or per grid node (x-fastest)               */
   double f_const;
   double tau;               /* GLS constant tau of C(x) (0.7 in the paper)      */
+  int32_t arrays_on_device; /* nonzero: nu / f_nodal are device pointers       */
 } abddc_problem;
 
 enum { ABDDC_PREC_FP64 = 0, ABDDC_PREC_MIXED = 1 };
@@ -154,7 +157,8 @@ int abddc_get_rhs(abddc_ctx* ctx, double* g);
  * u = 0 (Section 4 stopping rule: ||ghat - Shat u|| <= rtol ||ghat|| or maxit
  * Arnoldi steps), then interior recovery u_I = A_II^{-1}(f_I - A_IB u_B).
  * u: device vector of length n_dof (full solution).  info may be NULL.
- * Returns ABDDC_NOT_CONVERGED when maxit is reached first. */
+ * restart must be in [1, 63].  Returns ABDDC_NOT_CONVERGED when maxit is
+ * reached first. */
 int abddc_gmres_solve(abddc_ctx* ctx, int32_t restart, double rtol, int32_t maxit,
                       double* u, abddc_solve_info* info);
 
@@ -190,6 +194,16 @@ int64_t abddc_get_stage(abddc_ctx* ctx, int32_t stage, int32_t index, double* bu
  * [3] face stage, [4] edge stage, [5] change of basis + local factors,
  * [6] coarse, [7] GMRES iterations, [8] recovery.  n <= 16. */
 int abddc_phase_times(const abddc_ctx* ctx, double* t, int32_t n);
+
+/* Live per-kernel statistics accumulated over the context's lifetime from
+ * HIP events recorded around each launch on the context stream:
+ *   ABDDC_KSTAT_PLU_UPDATE  trailing MFMA update of the blocked partial LU
+ *                           (work = algorithmic flops, 2 m n b per matrix)
+ *   ABDDC_KSTAT_GEMV        batched GEMV of M^{-1} and Shat (work =
+ *                           algorithmic bytes: matrix + gathered input + output)
+ * Any output pointer may be NULL. */
+enum { ABDDC_KSTAT_PLU_UPDATE = 0, ABDDC_KSTAT_GEMV = 1 };
+int abddc_kernel_stats(abddc_ctx* ctx, int32_t kernel, double* seconds, int64_t* launches, double* work);
 
 void abddc_destroy(abddc_ctx* ctx);
 

@@ -33,6 +33,7 @@ class Problem(C.Structure):
         ("f_nodal", C.POINTER(C.c_double)),
         ("f_const", C.c_double),
         ("tau", C.c_double),
+        ("arrays_on_device", C.c_int32),
     ]
 
 
@@ -80,6 +81,7 @@ SIGNATURES = {
     "abddc_query": (C.c_int, [_P, _I64P, _I64P, _I32P, _I32P, _I32P]),
     "abddc_get_stage": (C.c_int64, [_P, C.c_int32, C.c_int32, C.POINTER(C.c_double), C.c_int64]),
     "abddc_phase_times": (C.c_int, [_P, C.POINTER(C.c_double), C.c_int32]),
+    "abddc_kernel_stats": (C.c_int, [_P, C.c_int32, C.POINTER(C.c_double), _I64P, C.POINTER(C.c_double)]),
     "abddc_destroy": (None, [_P]),
     "abddc_last_error": (C.c_char_p, []),
     "abddc_test_partial_lu": (C.c_int, [C.c_int32, _P, _I64P, _I32P, _I32P, _I32P, _I32P, C.c_int32, _P]),

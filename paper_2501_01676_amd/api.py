@@ -55,13 +55,26 @@ class Solver:
             p.beta0[a] = float(problem["beta0"][a])
         for i in range(9):
             p.beta1[i] = float(np.asarray(problem["beta1"]).reshape(9)[i])
-        nu = np.ascontiguousarray(problem["nu"], dtype=np.float64)
-        self._keep.append(nu)
-        p.nu = nu.ctypes.data_as(C.POINTER(C.c_double))
-        if problem.get("f_nodal") is not None:
-            f = np.ascontiguousarray(problem["f_nodal"], dtype=np.float64)
-            self._keep.append(f)
-            p.f_nodal = f.ctypes.data_as(C.POINTER(C.c_double))
+        nu = problem["nu"]
+        if isinstance(nu, torch.Tensor):
+            # device-resident coefficient arrays (copied on the device)
+            assert nu.is_cuda and nu.dtype == torch.float64 and nu.is_contiguous()
+            self._keep.append(nu)
+            p.nu = C.cast(C.c_void_p(nu.data_ptr()), C.POINTER(C.c_double))
+            f = problem.get("f_nodal")
+            if f is not None:
+                assert isinstance(f, torch.Tensor) and f.is_cuda
+                self._keep.append(f)
+                p.f_nodal = C.cast(C.c_void_p(f.data_ptr()), C.POINTER(C.c_double))
+            p.arrays_on_device = 1
+        else:
+            nu = np.ascontiguousarray(nu, dtype=np.float64)
+            self._keep.append(nu)
+            p.nu = nu.ctypes.data_as(C.POINTER(C.c_double))
+            if problem.get("f_nodal") is not None:
+                f = np.ascontiguousarray(problem["f_nodal"], dtype=np.float64)
+                self._keep.append(f)
+                p.f_nodal = f.ctypes.data_as(C.POINTER(C.c_double))
         p.f_const = float(problem["f_const"])
         p.c = float(problem["c"])
         p.tau = float(problem["tau"])
@@ -134,6 +147,13 @@ class Solver:
         t = np.zeros(9)
         L.check(self.lib.abddc_phase_times(self.ctx, t.ctypes.data_as(C.POINTER(C.c_double)), 9))
         return t
+
+    def kernel_stats(self, kernel):
+        """(seconds, launches, work) accumulated for a tracked kernel class
+        (0: partial-LU trailing update, flops; 1: batched GEMV, bytes)."""
+        sec, n, w = C.c_double(), C.c_int64(), C.c_double()
+        L.check(self.lib.abddc_kernel_stats(self.ctx, kernel, C.byref(sec), C.byref(n), C.byref(w)))
+        return sec.value, n.value, w.value
 
     def close(self):
         if getattr(self, "ctx", None):

@@ -6,9 +6,11 @@
 
 #include "guard.h"
 #include "internal.h"
+#include "kstats.h"
 
 namespace abddc {
 thread_local std::string g_last_error;
+thread_local KStats* g_kstats = nullptr;
 
 int fail(int code, const std::string& msg) {
   g_last_error = msg;

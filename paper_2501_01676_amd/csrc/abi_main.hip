@@ -37,12 +37,14 @@ void record(abddc_ctx* c, int i) {
 void apply_bddc_dev(abddc_ctx* c, const double* r, double* z) {
   hipStream_t s = c->stream;
   const int np = c->n_primal;
-  launch_gemv<double>(c->blk_M.p, c->nblk_M, c->gemv_M.p, c->maxc_M, c->dM.p, r, c->d_gam.p, c->d_out.p, false, s);
+  launch_gemv<double>(c->blk_M.p, c->nblk_M, c->gemv_M.p, c->maxc_M, c->dM.p, r, c->d_gam.p, c->d_out.p, false, s,
+                      c->bytes_M);
   if (np > 0) {
     launch_gather_sum(c->d_pown_ptr.p, c->d_pown_idx.p, c->d_out.p, c->d_bpi.p, np, s);
-    launch_gemv<double>(c->blk_C.p, c->nblk_C, c->gemv_C.p, np, c->dSPinv.p, c->d_bpi.p, nullptr, c->d_xpi.p, false, s);
+    launch_gemv<double>(c->blk_C.p, c->nblk_C, c->gemv_C.p, np, c->dSPinv.p, c->d_bpi.p, nullptr, c->d_xpi.p, false, s,
+                        c->bytes_C);
     launch_gemv<double>(c->blk_U.p, c->nblk_U, c->gemv_U.p, c->maxc_U, c->dU.p, c->d_xpi.p, c->d_pid.p, c->d_out.p,
-                        true, s);
+                        true, s, c->bytes_U);
   }
   launch_gather_sum(c->d_aown_ptr.p, c->d_aown_idx.p, c->d_out.p, z, c->topo.n_gamma, s);
 }
@@ -50,7 +52,8 @@ void apply_bddc_dev(abddc_ctx* c, const double* r, double* z) {
 // y = Shat x
 void apply_schur_dev(abddc_ctx* c, const double* x, double* y) {
   hipStream_t s = c->stream;
-  launch_gemv<double>(c->blk_S.p, c->nblk_S, c->gemv_S.p, c->maxc_S, c->dS.p, x, c->d_gam.p, c->d_wS.p, false, s);
+  launch_gemv<double>(c->blk_S.p, c->nblk_S, c->gemv_S.p, c->maxc_S, c->dS.p, x, c->d_gam.p, c->d_wS.p, false, s,
+                      c->bytes_S);
   launch_gather_sum(c->d_own_ptr.p, c->d_own_idx.p, c->d_wS.p, y, c->topo.n_gamma, s);
 }
 
@@ -67,6 +70,7 @@ extern "C" int abddc_assemble(const abddc_problem* prob, const abddc_device* dev
     ABDDC_REQUIRE(prob->tau > 0 && std::isfinite(prob->tau), ABDDC_EINVAL, "tau must be > 0");
     ABDDC_REQUIRE(prob->nu, ABDDC_EINVAL, "nu is null");
     std::unique_ptr<abddc_ctx> c(new abddc_ctx());
+    KStatsScope ks(&c->kstats);
     c->device = dev->device;
     ABDDC_HIP(hipSetDevice(dev->device));
     c->stream = (hipStream_t)dev->stream;
@@ -75,8 +79,10 @@ extern "C" int abddc_assemble(const abddc_problem* prob, const abddc_device* dev
     int nsub_in[3] = {prob->nsub[0], prob->nsub[1], prob->nsub[2]};
     const int* w_in[3] = {prob->width[0], prob->width[1], prob->width[2]};
     T.build(nsub_in, w_in);
-    for (int64_t e = 0; e < T.n_elem; ++e)
-      ABDDC_REQUIRE(prob->nu[e] > 0 && std::isfinite(prob->nu[e]), ABDDC_EINVAL, "nu must be positive and finite");
+    const bool on_dev = prob->arrays_on_device != 0;
+    if (!on_dev)
+      for (int64_t e = 0; e < T.n_elem; ++e)
+        ABDDC_REQUIRE(prob->nu[e] > 0 && std::isfinite(prob->nu[e]), ABDDC_EINVAL, "nu must be positive and finite");
     for (int a = 0; a < 3; ++a) {
       c->length[a] = prob->length[a];
       c->beta0[a] = prob->beta0[a];
@@ -166,12 +172,23 @@ extern "C" int abddc_assemble(const abddc_problem* prob, const abddc_device* dev
     for (const Object& o : T.objects)
       for (int q = 0; q < o.n; ++q) iface_dof[o.gstart + q] = (int32_t)T.dof_of_node[o.nodes[q]];
     c->d_iface_dof = to_device(iface_dof, s);
-    std::vector<double> nu(prob->nu, prob->nu + T.n_elem);
-    c->d_nu = to_device(nu, s);
-    if (prob->f_nodal) {
-      std::vector<double> fn(prob->f_nodal, prob->f_nodal + T.n_nodes);
-      c->d_fnodal = to_device(fn, s);
-      c->have_fnodal = true;
+    if (on_dev) {
+      c->d_nu.alloc(T.n_elem);
+      ABDDC_HIP(hipMemcpyAsync(c->d_nu.p, prob->nu, T.n_elem * sizeof(double), hipMemcpyDeviceToDevice, s));
+      launch_check_positive(c->d_nu.p, T.n_elem, c->d_flag.p, s);
+      if (prob->f_nodal) {
+        c->d_fnodal.alloc(T.n_nodes);
+        ABDDC_HIP(hipMemcpyAsync(c->d_fnodal.p, prob->f_nodal, T.n_nodes * sizeof(double), hipMemcpyDeviceToDevice, s));
+        c->have_fnodal = true;
+      }
+    } else {
+      std::vector<double> nu(prob->nu, prob->nu + T.n_elem);
+      c->d_nu = to_device(nu, s);
+      if (prob->f_nodal) {
+        std::vector<double> fn(prob->f_nodal, prob->f_nodal + T.n_nodes);
+        c->d_fnodal = to_device(fn, s);
+        c->have_fnodal = true;
+      }
     }
 
     // -------------------------------------------- element matrices + scatter
@@ -230,6 +247,7 @@ extern "C" int abddc_assemble(const abddc_problem* prob, const abddc_device* dev
       mS.push_back({c->soff[sub], c->goff[sub], c->goff[sub], nB, nB, std::max(nB, 1), 0});
       for (int r = 0; r < nB; r += GEMV_ROWS_PER_BLOCK) bS.push_back({sub, r});
     }
+    for (const GemvMat& m : mS) c->bytes_S += (double)m.nrows * m.ncols * 8.0 + m.ncols * 12.0 + m.nrows * 8.0;
     c->gemv_S = to_device(mS, s);
     c->blk_S = to_device(bS, s);
     c->nblk_S = (int)bS.size();
@@ -240,6 +258,8 @@ extern "C" int abddc_assemble(const abddc_problem* prob, const abddc_device* dev
     int h = 0;
     ABDDC_HIP(hipMemcpyAsync(&h, c->d_flag.p, sizeof(int), hipMemcpyDeviceToHost, s));
     ABDDC_HIP(hipStreamSynchronize(s));
+    c->kstats.resolve();
+    ABDDC_REQUIRE(!(h & 4), ABDDC_EINVAL, "nu must be positive and finite");
     ABDDC_REQUIRE(!(h & 1), ABDDC_ESINGULAR, "interior elimination: zero or non-finite pivot");
     c->phase[0] = ev_ms(c.get(), 10, 11);
     c->phase[1] = ev_ms(c.get(), 11, 12);
@@ -269,10 +289,12 @@ extern "C" int abddc_setup_coarse_space(abddc_ctx* c, const abddc_options* opts,
     ABDDC_REQUIRE(o.precision == ABDDC_PREC_FP64, ABDDC_EINVAL, "precision mode not provided");
     ABDDC_REQUIRE(o.constraint_source == ABDDC_CONSTRAINTS_EXACT, ABDDC_EINVAL, "constraint source not provided");
     ABDDC_REQUIRE(o.pinv_rtol >= 0 && o.svd_rtol >= 0 && o.tie_rtol >= 0, ABDDC_EINVAL, "negative tolerance");
+    KStatsScope ks(&c->kstats);
     c->opt = o;
     c->n_ties = 0;
     c->state = 1;
     run_setup(c);
+    c->kstats.resolve();
     c->phase[2] = ev_ms(c, 2, 3);
     c->phase[3] = ev_ms(c, 3, 4);
     c->phase[4] = ev_ms(c, 4, 5);
@@ -288,6 +310,7 @@ extern "C" int abddc_apply_bddc(abddc_ctx* c, const double* r, double* z) {
   return guarded([&]() -> int {
     ABDDC_REQUIRE(c && r && z, ABDDC_EINVAL, "null argument");
     ABDDC_REQUIRE(c->state >= 2, ABDDC_ESTATE, "apply before setup");
+    KStatsScope ks(&c->kstats);
     apply_bddc_dev(c, r, z);
     return ABDDC_OK;
   });
@@ -297,6 +320,7 @@ extern "C" int abddc_apply_schur(abddc_ctx* c, const double* x, double* y) {
   return guarded([&]() -> int {
     ABDDC_REQUIRE(c && x && y, ABDDC_EINVAL, "null argument");
     ABDDC_REQUIRE(c->state >= 1, ABDDC_ESTATE, "apply before assemble");
+    KStatsScope ks(&c->kstats);
     apply_schur_dev(c, x, y);
     return ABDDC_OK;
   });
@@ -321,6 +345,7 @@ extern "C" int abddc_gmres_solve(abddc_ctx* c, int32_t restart, double rtol, int
     ABDDC_REQUIRE(rtol > 0 && rtol < 1, ABDDC_EINVAL, "rtol must be in (0, 1)");
     ABDDC_REQUIRE(maxit >= 1, ABDDC_EINVAL, "maxit must be >= 1");
     ABDDC_HIP(hipSetDevice(c->device));
+    KStatsScope ks(&c->kstats);
     hipStream_t s = c->stream;
     const int64_t n = c->topo.n_gamma;
     const size_t nn = (size_t)std::max<int64_t>(n, 1);
@@ -408,6 +433,7 @@ extern "C" int abddc_gmres_solve(abddc_ctx* c, int32_t restart, double rtol, int
     record(c, 15);
     ABDDC_HIP(hipStreamSynchronize(s));
     const double wall = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    c->kstats.resolve();
     c->phase[7] = ev_ms(c, 13, 14);
     c->phase[8] = ev_ms(c, 14, 15);
     if (info) {
@@ -503,6 +529,20 @@ extern "C" int64_t abddc_get_stage(abddc_ctx* c, int32_t stage, int32_t index, d
     return ABDDC_OK;
   });
   return rc < 0 ? rc : result;
+}
+
+extern "C" int abddc_kernel_stats(abddc_ctx* c, int32_t kernel, double* seconds, int64_t* launches,
+                                  double* work) {
+  return guarded([&]() -> int {
+    ABDDC_REQUIRE(c, ABDDC_EINVAL, "null context");
+    ABDDC_REQUIRE(kernel >= 0 && kernel < KC_COUNT, ABDDC_EINVAL, "unknown kernel class");
+    ABDDC_HIP(hipStreamSynchronize(c->stream));
+    c->kstats.resolve();
+    if (seconds) *seconds = c->kstats.seconds[kernel];
+    if (launches) *launches = c->kstats.launches[kernel];
+    if (work) *work = c->kstats.work[kernel];
+    return ABDDC_OK;
+  });
 }
 
 extern "C" int abddc_phase_times(const abddc_ctx* c, double* t, int32_t n) {

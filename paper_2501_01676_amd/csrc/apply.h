@@ -36,7 +36,8 @@ struct GmresState {
 
 template <class TM>
 void launch_gemv(const GemvBlock* blocks, int nblk, const GemvMat* mats, int max_ncols, const TM* M,
-                 const double* x, const int32_t* xidx, double* y, bool accumulate, hipStream_t s);
+                 const double* x, const int32_t* xidx, double* y, bool accumulate, hipStream_t s,
+                 double bytes = 0.0);
 void launch_gather_sum(const int32_t* ptr, const int32_t* idx, const double* src, double* dst, int64_t n,
                        hipStream_t s);
 void launch_dots(const double* V, int64_t ldv, int nv, const double* w, int64_t n, double* partial, double* out,

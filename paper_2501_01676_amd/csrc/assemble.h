@@ -27,6 +27,7 @@ struct SubAsm {
   int32_t ebox[6]; // element ranges x0 x1 y0 y1 z0 z1 (node box is inclusive)
 };
 
+void launch_check_positive(const double* v, int64_t n, int* flag, hipStream_t s);
 void launch_elem(const ElemParams& P, const double* nu, const double* fnodal, double* Ae, double* Fe,
                  hipStream_t s);
 void launch_scatter(const SubAsm* subs, const int32_t* rowsub, const int32_t* lnode, const int32_t* lmap,

@@ -9,6 +9,7 @@
 #include "apply.h"
 #include "assemble.h"
 #include "internal.h"
+#include "kstats.h"
 #include "topology.h"
 
 struct abddc_ctx {
@@ -62,6 +63,8 @@ struct abddc_ctx {
   abddc::DevBuf<abddc::GemvBlock> blk_M, blk_U, blk_C, blk_S;
   int nblk_M = 0, nblk_U = 0, nblk_C = 0, nblk_S = 0;
   int maxc_M = 1, maxc_U = 1, maxc_S = 1;
+  double bytes_M = 0, bytes_U = 0, bytes_C = 0, bytes_S = 0;   // algorithmic bytes per GEMV launch
+  abddc::KStats kstats;
   abddc::DevBuf<double> d_out, d_wS, d_bpi, d_xpi;  // apply / Schur work vectors
   abddc::DevBuf<abddc::SubAsm> d_subs;
   abddc::DevBuf<double> d_rec;                      // recovery work (interior space)

@@ -15,6 +15,7 @@
 
 #include "apply.h"
 #include "internal.h"
+#include "kstats.h"
 
 namespace abddc {
 
@@ -186,15 +187,18 @@ inline unsigned nblocks(int64_t n) { return (unsigned)std::max<int64_t>(1, (n + 
 
 template <class TM>
 void launch_gemv(const GemvBlock* blocks, int nblk, const GemvMat* mats, int max_ncols, const TM* M,
-                 const double* x, const int32_t* xidx, double* y, bool accumulate, hipStream_t s) {
+                 const double* x, const int32_t* xidx, double* y, bool accumulate, hipStream_t s, double bytes) {
   if (nblk == 0) return;
+  hipEvent_t end = nullptr;
+  if (g_kstats && bytes > 0) g_kstats->begin(KC_GEMV, bytes, s, &end);
   gemv_kernel<TM><<<nblk, 256, max_ncols * sizeof(double), s>>>(blocks, mats, M, x, xidx, y, accumulate ? 1 : 0);
+  if (end) ABDDC_HIP(hipEventRecord(end, s));
   ABDDC_HIP(hipGetLastError());
 }
 template void launch_gemv<double>(const GemvBlock*, int, const GemvMat*, int, const double*, const double*,
-                                  const int32_t*, double*, bool, hipStream_t);
+                                  const int32_t*, double*, bool, hipStream_t, double);
 template void launch_gemv<float>(const GemvBlock*, int, const GemvMat*, int, const float*, const double*,
-                                 const int32_t*, double*, bool, hipStream_t);
+                                 const int32_t*, double*, bool, hipStream_t, double);
 
 void launch_gather_sum(const int32_t* ptr, const int32_t* idx, const double* src, double* dst, int64_t n,
                        hipStream_t s) {

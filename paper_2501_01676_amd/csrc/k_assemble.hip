@@ -193,6 +193,11 @@ __global__ void __launch_bounds__(256) recover_kernel(const SubAsm* __restrict__
   for (int r = threadIdx.x; r < nI; r += blockDim.x) u[int_dof[d.ioff + r]] = t[r];
 }
 
+__global__ void check_positive_kernel(const double* __restrict__ v, int64_t n, int* flag) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n && !(v[i] > 0.0 && isfinite(v[i]))) atomicOr(flag, 4);
+}
+
 __global__ void iface_scatter_kernel(const double* __restrict__ uhat, const int32_t* __restrict__ iface_dof,
                                      int64_t n, double* __restrict__ u) {
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -200,6 +205,12 @@ __global__ void iface_scatter_kernel(const double* __restrict__ uhat, const int3
 }
 
 }  // namespace
+
+void launch_check_positive(const double* v, int64_t n, int* flag, hipStream_t s) {
+  if (n == 0) return;
+  check_positive_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(v, n, flag);
+  ABDDC_HIP(hipGetLastError());
+}
 
 void launch_elem(const ElemParams& P, const double* nu, const double* fnodal, double* Ae, double* Fe,
                  hipStream_t s) {

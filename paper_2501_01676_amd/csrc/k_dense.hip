@@ -17,6 +17,7 @@
 
 #include "arena.h"
 #include "internal.h"
+#include "kstats.h"
 
 namespace abddc {
 
@@ -289,7 +290,20 @@ void partial_lu(const std::vector<PluDesc<T>>& descs, int* dflag, hipStream_t s)
     const int tiles = 2 * ((rem + TILE - 1) / TILE);
     plu_trsm_kernel<T><<<dim3(std::max(tiles, 1), nb), 256, 0, s>>>(dd, t0, scr);
     const int rt = (maxr - t0 + TILE - 1) / TILE, ct = (maxc - t0 + TILE - 1) / TILE;
-    if (rt > 0 && ct > 0) plu_update_kernel<T><<<dim3(rt, ct, nb), 256, 0, s>>>(dd, t0);
+    if (rt > 0 && ct > 0) {
+      hipEvent_t end = nullptr;
+      if (g_kstats) {
+        double flops = 0.0;  // 2 (nrow - s)(ncol - s) b per matrix still eliminating
+        for (auto& d : descs)
+          if (t0 < d.k) {
+            const int b = std::min(NB, d.k - t0), sr = t0 + b;
+            flops += 2.0 * (double)(d.nrow - sr) * (double)(d.ncol - sr) * b;
+          }
+        g_kstats->begin(KC_PLU_UPDATE, flops, s, &end);
+      }
+      plu_update_kernel<T><<<dim3(rt, ct, nb), 256, 0, s>>>(dd, t0);
+      if (end) ABDDC_HIP(hipEventRecord(end, s));
+    }
   }
   ABDDC_HIP(hipGetLastError());
 }

@@ -1,0 +1,77 @@
+// Live per-kernel timing with HIP events on the launch stream.  An entry
+// point sets the thread's sink to its context; instrumented launchers wrap
+// each launch of a tracked kernel in an event pair and record the launch's
+// algorithmic work (flops or bytes).  resolve() turns finished pairs into
+// accumulated seconds.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <vector>
+
+namespace abddc {
+
+enum KernelClass { KC_PLU_UPDATE = 0, KC_GEMV = 1, KC_COUNT = 2 };
+
+struct KStats {
+  double seconds[KC_COUNT] = {0, 0};
+  double work[KC_COUNT] = {0, 0};
+  int64_t launches[KC_COUNT] = {0, 0};
+  struct Pending {
+    int cls;
+    hipEvent_t a, b;
+    double work;
+  };
+  std::vector<Pending> pending;
+  std::vector<hipEvent_t> pool;
+
+  hipEvent_t take() {
+    if (!pool.empty()) {
+      hipEvent_t e = pool.back();
+      pool.pop_back();
+      return e;
+    }
+    hipEvent_t e;
+    (void)hipEventCreate(&e);
+    return e;
+  }
+  void begin(int cls, double work_amount, hipStream_t s, hipEvent_t* out_end) {
+    Pending p{cls, take(), take(), work_amount};
+    (void)hipEventRecord(p.a, s);
+    pending.push_back(p);
+    *out_end = p.b;
+  }
+  // call after the stream has been synchronised
+  void resolve() {
+    for (auto& p : pending) {
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+        seconds[p.cls] += ms * 1e-3;
+        work[p.cls] += p.work;
+        launches[p.cls] += 1;
+      }
+      pool.push_back(p.a);
+      pool.push_back(p.b);
+    }
+    pending.clear();
+  }
+  ~KStats() {
+    for (auto& p : pending) {
+      (void)hipEventDestroy(p.a);
+      (void)hipEventDestroy(p.b);
+    }
+    for (auto e : pool) (void)hipEventDestroy(e);
+  }
+};
+
+extern thread_local KStats* g_kstats;
+
+// RAII: route the launches of one entry point into ctx stats.
+struct KStatsScope {
+  KStats* prev;
+  explicit KStatsScope(KStats* k) : prev(g_kstats) { g_kstats = k; }
+  ~KStatsScope() { g_kstats = prev; }
+};
+
+}  // namespace abddc

@@ -777,6 +777,14 @@ void run_setup(abddc_ctx* c) {
     }
     mC.push_back({0, 0, 0, np, np, std::max(np, 1), 0});
     for (int r = 0; r < np; r += GEMV_ROWS_PER_BLOCK) bC.push_back({0, r});
+    auto gbytes = [](const std::vector<GemvMat>& v, bool gathered) {
+      double b = 0.0;  // matrix + gathered input (value and index) + output
+      for (const GemvMat& m : v) b += (double)m.nrows * m.ncols * 8.0 + m.ncols * (gathered ? 12.0 : 8.0) + m.nrows * 8.0;
+      return b;
+    };
+    c->bytes_M = gbytes(mM, true);
+    c->bytes_U = gbytes(mU, true);
+    c->bytes_C = gbytes(mC, false);
     c->gemv_M = to_device(mM, s);
     c->gemv_U = to_device(mU, s);
     c->gemv_C = to_device(mC, s);

@@ -15,11 +15,26 @@ pytestmark = pytest.mark.gpu
 
 from paper_2501_01676_amd import workloads as W  # noqa: E402
 
+def _layered(hh=5):
+    p = W.uniform(2, hh, beta=(0.7, -0.4, 1.1))
+    sx, _, sz = W.element_subdomain(p["widths"])
+    p["nu"] = np.where(sx == 0, 1.0, 1e-3) * np.where(sz == 0, 1.0, 0.1)
+    return p
+
+
+LOOSE = {"theta_face": 2.0, "theta_edge": 2.0}
+# name -> (problem, oracle options, library options)
 CASES = {
-    "config1a": lambda: W.config1a(),
-    "config1b": lambda: W.config1b(),
-    "float3_h3": lambda: W.random_field(3, 3, 5, beta=(2.0, -1.0, 0.5)),
-    "ragged_small": lambda: W.ragged((2, 3, 2), [2, 3, 4], 11),
+    "config1a": (W.config1a, {}, {}),
+    "config1b": (W.config1b, {}, {}),
+    "float3_h3": (lambda: W.random_field(3, 3, 5, beta=(2.0, -1.0, 0.5)), {}, {}),
+    "ragged_small": (lambda: W.ragged((2, 3, 2), [2, 3, 4], 11), {}, {}),
+    "layered_loose": (_layered, LOOSE, LOOSE),
+    "float3_loose": (lambda: W.random_field(3, 4, 2, beta=(3.0, 1.0, -2.0)), LOOSE, LOOSE),
+    "ragged_loose": (lambda: W.ragged((3, 2, 2), [3, 4, 5], 4), LOOSE, LOOSE),
+    "separate_h": (_layered, dict(LOOSE, edge_h_mode="separate"), dict(LOOSE, edge_h_mode=1)),
+    "deluxe_b": (_layered, dict(LOOSE, deluxe_source="B"), dict(LOOSE, deluxe_source=1)),
+    "config2": (W.config2, {}, {}),
 }
 
 
@@ -34,18 +49,23 @@ def pairs():
     from oracle import bddc
     from paper_2501_01676_amd import api
     out = {}
-    for name, fn in CASES.items():
+    for name, (fn, oopt, gopt) in CASES.items():
         p = fn()
         print(f"[parity] {name}: oracle", flush=True)
         o = bddc.OracleBDDC(p)
         o.assemble()
-        o.setup_coarse_space()
-        print(f"[parity] {name}: gpu assemble+setup", flush=True)
+        o.setup_coarse_space(oopt)
+        print(f"[parity] {name}: gpu assemble+setup counts {o.counts}", flush=True)
         g = api.Solver(p)
-        g.setup_coarse_space()
+        g.setup_coarse_space(**gopt)
         torch.cuda.synchronize()
         out[name] = (p, o, g)
     return out
+
+
+def test_cases_exercise_face_and_edge_primals(pairs):
+    assert any(o.counts["pnum_face"] > 0 for _, o, _ in pairs.values())
+    assert any(o.counts["pnum_edge"] > 0 for _, o, _ in pairs.values())
 
 
 @pytest.mark.parametrize("name", list(CASES))
