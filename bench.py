@@ -95,14 +95,19 @@ def main():
     opts = {"theta_face": args.theta, "theta_edge": args.theta, "precision": args.precision}
 
     def step():
+        ta = time.perf_counter()
         s = api.Solver(dev_problem)
+        tb = time.perf_counter()
         counts = s.setup_coarse_space(**opts)
+        tc = time.perf_counter()
         _, info = s.gmres_solve(args.restart, args.rtol, args.maxit, history=False)
+        td = time.perf_counter()
         ks = [s.kernel_stats(k) for k in (0, 1)]
         ph = s.phase_times()
         sizes = (s.n_sub, s.n_dof, s.n_gamma)
         s.close()
-        return counts, info, ks, ph, sizes
+        te = time.perf_counter()
+        return counts, info, ks, ph, sizes, (tb - ta, tc - tb, td - tc, te - td)
 
     for _ in range(args.warmup):
         step()
@@ -113,7 +118,7 @@ def main():
     t1 = time.perf_counter()
     per_step = (t1 - t0) / args.steps
 
-    counts, info, _, _, sizes = recs[-1]
+    counts, info, _, _, sizes, _ = recs[-1]
     ok = all(r[1]["converged"] and r[1]["relres_true"] <= args.rtol for r in recs)
     tot = {k: [sum(r[2][k][i] for r in recs) for i in range(3)] for k in (0, 1)}
     plu_s, plu_n, plu_flops = tot[0]
@@ -130,6 +135,7 @@ def main():
                 "seconds_per_step": gemv_s / args.steps}
     dominant, secondary = (roof_mfma, roof_hbm) if plu_s >= gemv_s else (roof_hbm, roof_mfma)
     phases = np.mean([r[3] for r in recs], axis=0)
+    walls = np.mean([r[5] for r in recs], axis=0)
     names = ["assemble", "local_schur", "deluxe", "faces", "edges", "local_factors", "coarse", "gmres", "recover"]
 
     out = {
@@ -154,6 +160,7 @@ def main():
         "converged": ok,
         "counts": counts,
         "phase_device_s": {n: float(v) for n, v in zip(names, phases)},
+        "call_wall_s": {n: float(v) for n, v in zip(["assemble", "setup_coarse_space", "gmres_solve", "destroy"], walls)},
         "roofline": dominant,
         "roofline_secondary": secondary,
     }

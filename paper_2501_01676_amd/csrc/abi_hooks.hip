@@ -2,6 +2,8 @@
 #include <hip/hip_runtime.h>
 
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <string>
 
 #include "guard.h"
@@ -15,6 +17,102 @@ thread_local KStats* g_kstats = nullptr;
 int fail(int code, const std::string& msg) {
   g_last_error = msg;
   return code;
+}
+}  // namespace abddc
+
+namespace abddc {
+thread_local hipStream_t g_stream = nullptr;
+
+namespace {
+// A cached block remembers the stream whose work may still use it and an
+// event recorded there at release; it is reused without waiting on that same
+// stream (stream order protects it) and after the event elsewhere.
+struct Block {
+  void* p;
+  hipStream_t stream;
+  hipEvent_t ev;
+};
+struct Cache {
+  std::mutex mu;
+  std::multimap<std::pair<int, size_t>, Block> free_blocks;  // (device, rounded size)
+};
+Cache& cache() {
+  static Cache* c = new Cache();  // intentionally never destroyed
+  return *c;
+}
+size_t round_size(size_t b) {
+  if (b <= (size_t(1) << 20)) {
+    size_t r = 256;
+    while (r < b) r <<= 1;
+    return r;
+  }
+  const size_t g = size_t(1) << 20;  // 1 MiB granules above 1 MiB
+  return (b + g - 1) / g * g;
+}
+}  // namespace
+
+void* cache_alloc(size_t bytes) {
+  int dev = 0;
+  ABDDC_HIP(hipGetDevice(&dev));
+  const size_t r = round_size(bytes);
+  Cache& c = cache();
+  Block blk{nullptr, nullptr, nullptr};
+  {
+    std::lock_guard<std::mutex> g(c.mu);
+    auto it = c.free_blocks.find({dev, r});
+    if (it != c.free_blocks.end()) {
+      blk = it->second;
+      c.free_blocks.erase(it);
+    }
+  }
+  if (blk.p) {
+    if (blk.ev) {
+      if (blk.stream != g_stream) ABDDC_HIP(hipEventSynchronize(blk.ev));
+      (void)hipEventDestroy(blk.ev);
+    }
+    return blk.p;
+  }
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, r);
+  if (e == hipErrorOutOfMemory) {
+    // return cached blocks of this device to the driver and retry once
+    ABDDC_HIP(hipDeviceSynchronize());
+    std::lock_guard<std::mutex> g(c.mu);
+    for (auto it = c.free_blocks.begin(); it != c.free_blocks.end();) {
+      if (it->first.first == dev) {
+        (void)hipFree(it->second.p);
+        if (it->second.ev) (void)hipEventDestroy(it->second.ev);
+        it = c.free_blocks.erase(it);
+      } else {
+        ++it;
+      }
+    }
+    (void)hipGetLastError();
+    e = hipMalloc(&p, r);
+  }
+  if (e != hipSuccess)
+    throw Error(e == hipErrorOutOfMemory ? ABDDC_ENOMEM : ABDDC_EDEVICE, std::string("hipMalloc: ") + hipGetErrorString(e));
+  return p;
+}
+
+void cache_free(void* p, size_t bytes) {
+  if (!p) return;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return;
+  Block blk{p, g_stream, nullptr};
+  if (hipEventCreateWithFlags(&blk.ev, hipEventDisableTiming) == hipSuccess) {
+    if (hipEventRecord(blk.ev, g_stream) != hipSuccess) {
+      (void)hipEventDestroy(blk.ev);
+      blk.ev = nullptr;
+      (void)hipStreamSynchronize(g_stream);
+    }
+  } else {
+    blk.ev = nullptr;
+    (void)hipStreamSynchronize(g_stream);
+  }
+  Cache& c = cache();
+  std::lock_guard<std::mutex> g(c.mu);
+  c.free_blocks.insert({{dev, round_size(bytes)}, blk});
 }
 }  // namespace abddc
 
@@ -40,6 +138,7 @@ extern "C" int abddc_test_partial_lu(int32_t batch, void* buf, const int64_t* of
   return guarded([&]() -> int {
     ABDDC_REQUIRE(batch >= 0 && buf && off && nrow && ncol && ld && k, ABDDC_EINVAL, "null argument");
     hipStream_t s = (hipStream_t)stream;
+    StreamScope ss(s);
     DevBuf<int> flag(1);
     flag.zero(s);
     if (precision == 0) {
@@ -62,6 +161,7 @@ extern "C" int abddc_test_gemm(int32_t batch, double* buf, const int64_t* offA, 
   return guarded([&]() -> int {
     ABDDC_REQUIRE(batch >= 0 && buf, ABDDC_EINVAL, "null argument");
     hipStream_t s = (hipStream_t)stream;
+    StreamScope ss(s);
     std::vector<GemmDesc<double>> d(batch);
     for (int b = 0; b < batch; ++b)
       d[b] = {buf + offA[b], buf + offB[b], buf + offC[b], m[b], n[b], k[b], lda[b], ldb[b], ldc[b]};
@@ -76,6 +176,7 @@ extern "C" int abddc_test_sygv(int32_t batch, double* buf, const int64_t* offA, 
   return guarded([&]() -> int {
     ABDDC_REQUIRE(batch >= 0 && buf, ABDDC_EINVAL, "null argument");
     hipStream_t s = (hipStream_t)stream;
+    StreamScope ss(s);
     DevBuf<int> flag(1);
     flag.zero(s);
     std::vector<SygvDesc> d(batch);

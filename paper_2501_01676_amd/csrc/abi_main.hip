@@ -75,6 +75,7 @@ extern "C" int abddc_assemble(const abddc_problem* prob, const abddc_device* dev
     ABDDC_HIP(hipSetDevice(dev->device));
     c->stream = (hipStream_t)dev->stream;
     hipStream_t s = c->stream;
+    StreamScope ss(s);
     Topology& T = c->topo;
     int nsub_in[3] = {prob->nsub[0], prob->nsub[1], prob->nsub[2]};
     const int* w_in[3] = {prob->width[0], prob->width[1], prob->width[2]};
@@ -290,6 +291,7 @@ extern "C" int abddc_setup_coarse_space(abddc_ctx* c, const abddc_options* opts,
     ABDDC_REQUIRE(o.constraint_source == ABDDC_CONSTRAINTS_EXACT, ABDDC_EINVAL, "constraint source not provided");
     ABDDC_REQUIRE(o.pinv_rtol >= 0 && o.svd_rtol >= 0 && o.tie_rtol >= 0, ABDDC_EINVAL, "negative tolerance");
     KStatsScope ks(&c->kstats);
+    StreamScope ss(c->stream);
     c->opt = o;
     c->n_ties = 0;
     c->state = 1;
@@ -346,6 +348,7 @@ extern "C" int abddc_gmres_solve(abddc_ctx* c, int32_t restart, double rtol, int
     ABDDC_REQUIRE(maxit >= 1, ABDDC_EINVAL, "maxit must be >= 1");
     ABDDC_HIP(hipSetDevice(c->device));
     KStatsScope ks(&c->kstats);
+    StreamScope ss(c->stream);
     hipStream_t s = c->stream;
     const int64_t n = c->topo.n_gamma;
     const size_t nn = (size_t)std::max<int64_t>(n, 1);
@@ -554,6 +557,7 @@ extern "C" int abddc_phase_times(const abddc_ctx* c, double* t, int32_t n) {
 extern "C" void abddc_destroy(abddc_ctx* c) {
   if (!c) return;
   (void)hipSetDevice(c->device);
+  StreamScope ss(c->stream);
   (void)hipStreamSynchronize(c->stream);
   if (c->h_gst) (void)hipHostFree(c->h_gst);
   for (int i = 0; i < 20; ++i)

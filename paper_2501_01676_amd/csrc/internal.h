@@ -30,6 +30,22 @@ struct Error : std::runtime_error {
     if (!(cond)) throw ::abddc::Error((code), (msg));  \
   } while (0)
 
+// Caching device allocator: blocks are rounded up and kept in per-device
+// free lists for reuse (setup temporaries and repeated solves would
+// otherwise pay hipMalloc / hipFree and their implicit synchronisation).
+// Memory returns to the driver only at process exit.
+void* cache_alloc(size_t bytes);
+void cache_free(void* p, size_t bytes);
+
+// Stream on which the current entry point works (released blocks are tagged
+// with it).
+extern thread_local hipStream_t g_stream;
+struct StreamScope {
+  hipStream_t prev;
+  explicit StreamScope(hipStream_t s) : prev(g_stream) { g_stream = s; }
+  ~StreamScope() { g_stream = prev; }
+};
+
 // Owning device allocation.
 template <class T>
 struct DevBuf {
@@ -49,10 +65,10 @@ struct DevBuf {
   void alloc(size_t count) {
     release();
     n = count;
-    if (count) ABDDC_HIP(hipMalloc(&p, count * sizeof(T)));
+    if (count) p = static_cast<T*>(cache_alloc(count * sizeof(T)));
   }
   void release() {
-    if (p) (void)hipFree(p);
+    if (p) cache_free(p, n * sizeof(T));
     p = nullptr;
     n = 0;
   }

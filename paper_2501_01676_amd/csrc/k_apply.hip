@@ -97,12 +97,17 @@ __global__ void __launch_bounds__(256) dots_partial_kernel(const double* __restr
   }
 }
 
-__global__ void dots_final_kernel(const double* __restrict__ partial, int nblk, int nv, double* __restrict__ out) {
-  const int j = threadIdx.x;
-  if (j >= nv) return;
+// one workgroup per vector j: fixed-order tree over the block partials
+__global__ void __launch_bounds__(256) dots_final_kernel(const double* __restrict__ partial, int nblk,
+                                                         double* __restrict__ out) {
+  __shared__ double red[4];
+  const int j = blockIdx.x;
   double s = 0.0;
-  for (int b = 0; b < nblk; ++b) s += partial[b * DOT_STRIDE + j];
-  out[j] = s;
+  for (int b = threadIdx.x; b < nblk; b += blockDim.x) s += partial[b * DOT_STRIDE + j];
+  s = wave_sum(s);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) out[j] = (red[0] + red[1]) + (red[2] + red[3]);
 }
 
 // w[i] += sign * sum_j coef[j] V[j][i]
@@ -210,7 +215,7 @@ void launch_gather_sum(const int32_t* ptr, const int32_t* idx, const double* src
 void launch_dots(const double* V, int64_t ldv, int nv, const double* w, int64_t n, double* partial, double* out,
                  hipStream_t s) {
   dots_partial_kernel<<<DOT_BLOCKS, 256, 0, s>>>(V, ldv, nv, w, n, partial);
-  dots_final_kernel<<<1, 64, 0, s>>>(partial, DOT_BLOCKS, nv, out);
+  dots_final_kernel<<<nv, 256, 0, s>>>(partial, DOT_BLOCKS, out);
   ABDDC_HIP(hipGetLastError());
 }
 

@@ -140,55 +140,60 @@ template <class T>
 __global__ void __launch_bounds__(256) plu_diag_kernel(const PluDesc<T>* __restrict__ descs, int t0,
                                                         T* __restrict__ scratch, int* dflag) {
   __shared__ T D[NB][NB + 1];
+  __shared__ T Li[NB][NB + 1];
+  __shared__ T Ui[NB][NB + 1];
   const PluDesc<T> d = descs[blockIdx.x];
   if (t0 >= d.k) return;
   const int b = min(NB, d.k - t0);
   const int tid = threadIdx.x;
   T* base = d.a + (size_t)t0 * d.ld + t0;
-  for (int idx = tid; idx < b * b; idx += 256) D[idx / b][idx % b] = base[(size_t)(idx / b) * d.ld + idx % b];
+  // thread (tr, tc) = (tid >> 6, tid & 63): column tc, rows tr, tr + 4, ...
+  const int tr = tid >> 6, tc = tid & 63;
+  if (tc < b)
+    for (int r = tr; r < b; r += 4) D[r][tc] = base[(size_t)r * d.ld + tc];
   __syncthreads();
   for (int j = 0; j < b; ++j) {
     const T piv = D[j][j];
     if (tid == 0 && (!(fabs((double)piv) > 0.0) || !isfinite((double)piv))) atomicOr(dflag, 1);
     const T inv = T(1) / piv;
-    for (int i = j + 1 + tid; i < b; i += 256) D[i][j] *= inv;
+    if (tr == 0 && tc > j && tc < b) D[tc][j] *= inv;
     __syncthreads();
-    const int rem = b - j - 1;
-    for (int idx = tid; idx < rem * rem; idx += 256) {
-      int i = j + 1 + idx / rem, c = j + 1 + idx % rem;
-      D[i][c] -= D[i][j] * D[j][c];
+    if (tc > j && tc < b) {
+      const T u = D[j][tc];
+      for (int i = j + 1 + tr; i < b; i += 4) D[i][tc] -= D[i][j] * u;
     }
     __syncthreads();
   }
-  for (int idx = tid; idx < b * b; idx += 256) base[(size_t)(idx / b) * d.ld + idx % b] = D[idx / b][idx % b];
-  // inverses, one column per thread
-  T* Li = scratch + (size_t)blockIdx.x * 2 * NB * NB;
-  T* Ui = Li + NB * NB;
+  if (tc < b)
+    for (int r = tr; r < b; r += 4) base[(size_t)r * d.ld + tc] = D[r][tc];
+  // L^{-1} (unit lower) by columns with threads 0..63, U^{-1} (upper) by
+  // columns with threads 64..127; both staged in LDS.
   if (tid < b) {
     const int c = tid;
-    // L^{-1}: unit lower, column c
-    for (int r = 0; r < b; ++r) {
-      T v;
-      if (r < c) v = 0;
-      else if (r == c) v = 1;
-      else {
-        v = 0;
-        for (int q = c; q < r; ++q) v -= D[r][q] * Li[q * NB + c];
-      }
-      Li[r * NB + c] = v;
+    for (int r = 0; r < c; ++r) Li[r][c] = 0;
+    Li[c][c] = 1;
+    for (int r = c + 1; r < b; ++r) {
+      T v = 0;
+      for (int q = c; q < r; ++q) v -= D[r][q] * Li[q][c];
+      Li[r][c] = v;
     }
-    // U^{-1}: upper, column c, back substitution
-    for (int r = b - 1; r >= 0; --r) {
-      T v;
-      if (r > c) v = 0;
-      else {
-        v = (r == c) ? T(1) : T(0);
-        for (int q = r + 1; q <= c; ++q) v -= D[r][q] * Ui[q * NB + c];
-        v /= D[r][r];
-      }
-      Ui[r * NB + c] = v;
+  } else if (tid >= 64 && tid < 64 + b) {
+    const int c = tid - 64;
+    for (int r = c + 1; r < b; ++r) Ui[r][c] = 0;
+    for (int r = c; r >= 0; --r) {
+      T v = (r == c) ? T(1) : T(0);
+      for (int q = r + 1; q <= c; ++q) v -= D[r][q] * Ui[q][c];
+      Ui[r][c] = v / D[r][r];
     }
   }
+  __syncthreads();
+  T* gLi = scratch + (size_t)blockIdx.x * 2 * NB * NB;
+  T* gUi = gLi + NB * NB;
+  if (tc < b)
+    for (int r = tr; r < b; r += 4) {
+      gLi[r * NB + tc] = Li[r][tc];
+      gUi[r * NB + tc] = Ui[r][tc];
+    }
 }
 
 // Step 2: A21 <- A21 U11^{-1} (row tiles), A12 <- L11^{-1} A12 (column tiles).

@@ -37,57 +37,46 @@ __device__ inline int rr_slot(int pos, int r, int m) {
 // starts as identity).  Index n (when n is odd) is a dummy that never
 // rotates.  Returns after convergence or 40 sweeps.
 __device__ void jacobi_lds(double (*A)[LDN], double (*V)[LDN], int n, double* cs, double* sn,
-                           int* pp, int* qq, double* red) {
+                           int* pp, int* qq, int* nrot) {
   const int tid = threadIdx.x;
   const int m = (n + 1) & ~1;
   const int half = m / 2;
-  for (int idx = tid; idx < n * n; idx += blockDim.x) V[idx / n][idx % n] = (idx / n == idx % n) ? 1.0 : 0.0;
+  const int tj = tid & 63, ti = tid >> 6, nstep = blockDim.x >> 6;
+  if (tj < n)
+    for (int r = ti; r < n; r += nstep) V[r][tj] = (r == tj) ? 1.0 : 0.0;
+  if (tid == 0) *nrot = 0;
   __syncthreads();
-  for (int sweep = 0; sweep < 40; ++sweep) {
-    // convergence test: off-diagonal vs total Frobenius mass
-    double off = 0.0, tot = 0.0;
-    for (int idx = tid; idx < n * n; idx += blockDim.x) {
-      double v = A[idx / n][idx % n];
-      tot += v * v;
-      if (idx / n != idx % n) off += v * v;
-    }
-    red[tid] = off;
-    red[blockDim.x + tid] = tot;
-    __syncthreads();
-    for (int st = blockDim.x / 2; st > 0; st >>= 1) {
-      if (tid < st) {
-        red[tid] += red[tid + st];
-        red[blockDim.x + tid] += red[blockDim.x + tid + st];
-      }
-      __syncthreads();
-    }
-    const double offs = red[0], tots = red[blockDim.x];
-    __syncthreads();
-    if (!(offs > 1e-32 * tots)) break;
+  // Cyclic sweeps; a rotation is skipped when |a_pq| is negligible against
+  // sqrt(|a_pp a_qq|) (relative threshold 1e-18 below double precision), and
+  // the iteration stops after a sweep without rotations.
+  for (int sweep = 0; sweep < 60; ++sweep) {
     for (int r = 0; r < m - 1; ++r) {
       if (tid < half) {
         int a = rr_slot(tid, r, m), b = rr_slot(m - 1 - tid, r, m);
         int p = min(a, b), q = max(a, b);
         double c = 1.0, s = 0.0;
+        int active = 0;
         if (q < n) {
           const double apq = A[p][q];
-          if (apq != 0.0) {
-            const double tau = (A[q][q] - A[p][p]) / (2.0 * apq);
+          const double app = A[p][p], aqq = A[q][q];
+          if (apq != 0.0 && fabs(apq) > 1e-18 * sqrt(fabs(app) * fabs(aqq))) {
+            const double tau = (aqq - app) / (2.0 * apq);
             const double t = (tau >= 0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
             c = 1.0 / sqrt(1.0 + t * t);
             s = t * c;
+            active = 1;
+            atomicAdd(nrot, 1);
           }
         }
         cs[tid] = c;
         sn[tid] = s;
         pp[tid] = p;
-        qq[tid] = q;
+        qq[tid] = active ? q : n;   // inactive pairs are skipped below
       }
       __syncthreads();
-      // rows: A <- J^T A
-      for (int idx = tid; idx < half * n; idx += blockDim.x) {
-        const int i = idx / n, j = idx % n;
-        const int p = pp[i], q = qq[i];
+      // rows: A <- J^T A   (pair i = ti, ti + nstep, ...; element j = tj)
+      for (int i = ti; i < half && tj < n; i += nstep) {
+        const int p = pp[i], q = qq[i], j = tj;
         if (q >= n) continue;
         const double c = cs[i], s = sn[i];
         const double ap = A[p][j], aq = A[q][j];
@@ -96,9 +85,8 @@ __device__ void jacobi_lds(double (*A)[LDN], double (*V)[LDN], int n, double* cs
       }
       __syncthreads();
       // columns: A <- A J, V <- V J
-      for (int idx = tid; idx < half * n; idx += blockDim.x) {
-        const int i = idx / n, j = idx % n;
-        const int p = pp[i], q = qq[i];
+      for (int i = ti; i < half && tj < n; i += nstep) {
+        const int p = pp[i], q = qq[i], j = tj;
         if (q >= n) continue;
         const double c = cs[i], s = sn[i];
         const double ap = A[j][p], aq = A[j][q];
@@ -109,7 +97,18 @@ __device__ void jacobi_lds(double (*A)[LDN], double (*V)[LDN], int n, double* cs
         V[j][q] = s * vp + c * vq;
       }
       __syncthreads();
+      // the rotation annihilates a_pq
+      if (tid < half && qq[tid] < n) {
+        A[pp[tid]][qq[tid]] = 0.0;
+        A[qq[tid]][pp[tid]] = 0.0;
+      }
+      __syncthreads();
     }
+    const int done = (*nrot == 0);
+    __syncthreads();
+    if (done) break;
+    if (tid == 0) *nrot = 0;
+    __syncthreads();
   }
 }
 
@@ -132,15 +131,16 @@ __global__ void __launch_bounds__(256) sygv_kernel(const SygvDesc* __restrict__ 
   __shared__ double Vm[NMAX][LDN];
   __shared__ double cs[NMAX / 2], sn[NMAX / 2];
   __shared__ int pp[NMAX / 2], qq[NMAX / 2];
-  __shared__ double red[512];
+  __shared__ int nrot;
   const SygvDesc d = descs[blockIdx.x];
   const int n = d.n, tid = threadIdx.x;
   if (n <= 0) return;
-  for (int idx = tid; idx < n * n; idx += blockDim.x) {
-    const int r = idx / n, c = idx % n;
-    Lm[r][c] = 0.5 * (d.B[r * n + c] + d.B[c * n + r]);
-    Cm[r][c] = 0.5 * (d.A[r * n + c] + d.A[c * n + r]);
-  }
+  const int tj = tid & 63, ti = tid >> 6, nstep = blockDim.x >> 6;
+  if (tj < n)
+    for (int r = ti; r < n; r += nstep) {
+      Lm[r][tj] = 0.5 * (d.B[r * n + tj] + d.B[tj * n + r]);
+      Cm[r][tj] = 0.5 * (d.A[r * n + tj] + d.A[tj * n + r]);
+    }
   __syncthreads();
   // right-looking Cholesky, lower triangle
   for (int j = 0; j < n; ++j) {
@@ -153,10 +153,10 @@ __global__ void __launch_bounds__(256) sygv_kernel(const SygvDesc* __restrict__ 
     const double ljj = Lm[j][j];
     for (int i = j + 1 + tid; i < n; i += blockDim.x) Lm[i][j] /= ljj;
     __syncthreads();
-    const int rem = n - j - 1;
-    for (int idx = tid; idx < rem * rem; idx += blockDim.x) {
-      const int i = j + 1 + idx / rem, c = j + 1 + idx % rem;
-      if (c <= i) Lm[i][c] -= Lm[i][j] * Lm[c][j];
+    if (tj > j && tj < n) {
+      const double lc = Lm[tj][j];
+      for (int i = j + 1 + ti; i < n; i += nstep)
+        if (tj <= i) Lm[i][tj] -= Lm[i][j] * lc;
     }
     __syncthreads();
   }
@@ -179,23 +179,23 @@ __global__ void __launch_bounds__(256) sygv_kernel(const SygvDesc* __restrict__ 
     }
   }
   __syncthreads();
-  for (int idx = tid; idx < n * n; idx += blockDim.x) {
-    const int r = idx / n, c = idx % n;
-    if (r < c) {
-      const double v = 0.5 * (Cm[r][c] + Cm[c][r]);
-      Cm[r][c] = v;
-      Cm[c][r] = v;
+  if (tj < n)
+    for (int r = ti; r < tj; r += nstep) {
+      const double v = 0.5 * (Cm[r][tj] + Cm[tj][r]);
+      Cm[r][tj] = v;
+      Cm[tj][r] = v;
     }
-  }
   __syncthreads();
-  jacobi_lds(Cm, Vm, n, cs, sn, pp, qq, red);
+  jacobi_lds(Cm, Vm, n, cs, sn, pp, qq, &nrot);
   // outputs: mu ascending, X[:, rank] = L Y[:, i]
   for (int i = tid; i < n; i += blockDim.x) d.w[rank_of(Cm, n, i)] = Cm[i][i];
-  for (int idx = tid; idx < n * n; idx += blockDim.x) {
-    const int r = idx / n, i = idx % n;
-    double v = 0.0;
-    for (int q = 0; q <= r; ++q) v += Lm[r][q] * Vm[q][i];
-    d.X[r * n + rank_of(Cm, n, i)] = v;
+  if (tj < n) {
+    const int col = rank_of(Cm, n, tj);
+    for (int r = ti; r < n; r += nstep) {
+      double v = 0.0;
+      for (int q = 0; q <= r; ++q) v += Lm[r][q] * Vm[q][tj];
+      d.X[r * n + col] = v;
+    }
   }
 }
 
@@ -205,17 +205,16 @@ __global__ void __launch_bounds__(256) pinv_kernel(const PinvDesc* __restrict__ 
   __shared__ double Vm[NMAX][LDN];
   __shared__ double cs[NMAX / 2], sn[NMAX / 2];
   __shared__ int pp[NMAX / 2], qq[NMAX / 2];
-  __shared__ double red[512];
+  __shared__ int nrot;
   __shared__ double lmax;
   const PinvDesc d = descs[blockIdx.x];
   const int n = d.n, tid = threadIdx.x;
   if (n <= 0) return;
-  for (int idx = tid; idx < n * n; idx += blockDim.x) {
-    const int r = idx / n, c = idx % n;
-    Am[r][c] = 0.5 * (d.M[r * d.ld + c] + d.M[c * d.ld + r]);
-  }
+  const int tj = tid & 63, ti = tid >> 6, nstep = blockDim.x >> 6;
+  if (tj < n)
+    for (int r = ti; r < n; r += nstep) Am[r][tj] = 0.5 * (d.M[r * d.ld + tj] + d.M[tj * d.ld + r]);
   __syncthreads();
-  jacobi_lds(Am, Vm, n, cs, sn, pp, qq, red);
+  jacobi_lds(Am, Vm, n, cs, sn, pp, qq, &nrot);
   if (tid == 0) {
     double m = 0.0;
     for (int i = 0; i < n; ++i) m = fmax(m, Am[i][i]);
@@ -223,16 +222,16 @@ __global__ void __launch_bounds__(256) pinv_kernel(const PinvDesc* __restrict__ 
   }
   __syncthreads();
   const double cut = rtol * lmax;
-  for (int idx = tid; idx < n * n; idx += blockDim.x) {
-    const int r = idx / n, c = idx % n;
-    double v = 0.0;
-    if (lmax > 0.0)
-      for (int k = 0; k < n; ++k) {
-        const double lam = Am[k][k];
-        if (lam > cut) v += Vm[r][k] * Vm[c][k] / lam;
-      }
-    d.out[r * d.ld + c] = v;
-  }
+  if (tj < n)
+    for (int r = ti; r < n; r += nstep) {
+      double v = 0.0;
+      if (lmax > 0.0)
+        for (int k = 0; k < n; ++k) {
+          const double lam = Am[k][k];
+          if (lam > cut) v += Vm[r][k] * Vm[tj][k] / lam;
+        }
+      d.out[r * d.ld + tj] = v;
+    }
 }
 
 // Householder QR of X (n x p), accumulated into Q = H_0 H_1 ... H_{p-1}.

@@ -22,16 +22,28 @@ namespace abddc {
 namespace {
 
 struct IntPool {
-  // Concatenated host int arrays uploaded once; device pointers handed out by offset.
+  // Concatenated host int arrays uploaded once through pinned memory (async);
+  // device pointers handed out by offset.  The pinned staging buffer lives
+  // until the pool is destroyed, after the setup's final synchronisation.
   std::vector<int32_t> h;
   DevBuf<int32_t> d;
+  int32_t* pinned = nullptr;
   size_t add(const std::vector<int32_t>& v) {
     size_t off = h.size();
     h.insert(h.end(), v.begin(), v.end());
     return off;
   }
-  void upload(hipStream_t s) { d = to_device(h, s); }
+  void upload(hipStream_t s) {
+    d.alloc(std::max<size_t>(h.size(), 1));
+    if (h.empty()) return;
+    ABDDC_HIP(hipHostMalloc(&pinned, h.size() * sizeof(int32_t), hipHostMallocDefault));
+    std::copy(h.begin(), h.end(), pinned);
+    ABDDC_HIP(hipMemcpyAsync(d.p, pinned, h.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+  }
   const int32_t* ptr(size_t off) const { return d.p + off; }
+  ~IntPool() {
+    if (pinned) (void)hipHostFree(pinned);   // hipHostFree waits for pending copies
+  }
 };
 
 void record(abddc_ctx* c, int i) {
@@ -114,7 +126,6 @@ void run_setup(abddc_ctx* c) {
     deluxe_build_batched(dd, s);
     partial_lu<double>(pd, c->d_flag.p, s);
     gather_batched(gd, s);
-    require_flag_clean(c, "deluxe");
   }
 
   // ------------------------------------------------------------- faces
@@ -217,7 +228,6 @@ void run_setup(abddc_ctx* c) {
     gemm_batched<double>(h1, false, false, 1.0, 0.0, s);
     gemm_batched<double>(h2, false, false, 1.0, 0.0, s);
     sym_batched(sy, s);  // Sum now holds sym(Btilde_F)
-    require_flag_clean(c, "face elimination");
 
     // Btilde_F y = mu B_F y
     std::vector<SygvDesc> gv;
@@ -225,8 +235,8 @@ void run_setup(abddc_ctx* c) {
       gv.push_back({Sum.p + c->tfoff[f], BF.p + c->tfoff[f], c->dWF.p + c->wfoff[f], XF.p + c->tfoff[f],
                     T.objects[T.faces[f]].n});
     sygv_batched(gv, c->d_flag.p, s);
-    require_flag_clean(c, "face eigenproblem");
     std::vector<double> mu = to_host(c->dWF.p, c->dWF.n, s);
+    require_flag_clean(c, "deluxe / face elimination / face eigenproblem");
     std::vector<QrDesc> qd;
     for (int f = 0; f < nf; ++f) {
       const int n = T.objects[T.faces[f]].n;
@@ -448,7 +458,6 @@ void run_setup(abddc_ctx* c) {
     edge_assemble_batched(ea, s);
     partial_lu<double>(pd, c->d_flag.p, s);
     sym_batched(sy, s);
-    require_flag_clean(c, "edge elimination");
     std::vector<SygvDesc> gv;
     for (int e = 0; e < ned; ++e) {
       const Object& o = T.objects[T.edges[e]];
@@ -456,8 +465,8 @@ void run_setup(abddc_ctx* c) {
       gv.push_back({Btt.p + meoff[e], ME.p + meoff[e], c->dWE.p + c->weoff[e], XE.p + meoff[e], nw});
     }
     sygv_batched(gv, c->d_flag.p, s);
-    require_flag_clean(c, "edge eigenproblem");
     std::vector<double> mu = to_host(c->dWE.p, c->dWE.n, s);
+    require_flag_clean(c, "edge elimination / edge eigenproblem");
     // G = [g_{l,k}] (n_E x (m-1) |N_E|) and its left singular basis
     int64_t gtot = 0;
     std::vector<int64_t> goffE(ned);
@@ -659,7 +668,6 @@ void run_setup(abddc_ctx* c) {
     gather_batched(gd, s);
     set_batched(st, s);
     partial_lu<double>(pd, c->d_flag.p, s);
-    require_flag_clean(c, "local constrained factorisation");
 
     // Ktilde (nB x nB), Vt (nP x nB) = [Psi^T | I], Ut (nB x nP) = [Phi; I]
     gd.clear();
@@ -736,7 +744,6 @@ void run_setup(abddc_ctx* c) {
                   s);
       partial_lu<double>({{Aug2.p, 2 * np, 2 * np, 2 * np, np}}, c->d_flag.p, s);
       gather_batched({{Aug2.p + (int64_t)np * 2 * np + np, c->dSPinv.p, nullptr, nullptr, np, np, 2 * np, np, 1.0}}, s);
-      require_flag_clean(c, "coarse factorisation");
     }
 
     // ------------------------------------------- apply metadata (device)
@@ -799,7 +806,7 @@ void run_setup(abddc_ctx* c) {
     c->d_out.alloc(std::max<int64_t>(ot, 1));
     c->d_bpi.alloc(std::max(np, 1));
     c->d_xpi.alloc(std::max(np, 1));
-    ABDDC_HIP(hipStreamSynchronize(s));
+    require_flag_clean(c, "local constrained / coarse factorisation");
   }
   record(c, 8);
 }
