@@ -125,7 +125,7 @@ def main():
     gemv_s, gemv_n, gemv_bytes = tot[1]
     tflops = plu_flops / plu_s / 1e12 if plu_s > 0 else 0.0
     gbs = gemv_bytes / gemv_s / 1e9 if gemv_s > 0 else 0.0
-    roof_mfma = {"bound": "mfma", "kernel": "plu_update_kernel<double>", "achieved": tflops,
+    roof_mfma = {"bound": "mfma", "kernel": "plu_lead_kernel<double> + plu_update_kernel<double> (partial-LU MFMA updates)", "achieved": tflops,
                  "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": tflops / PEAK_FP64_TFLOPS,
                  "traffic": None, "avg_launch_us": plu_s / max(plu_n, 1) * 1e6, "launches_per_step": plu_n / args.steps,
                  "seconds_per_step": plu_s / args.steps}

@@ -197,8 +197,10 @@ int abddc_phase_times(const abddc_ctx* ctx, double* t, int32_t n);
 
 /* Live per-kernel statistics accumulated over the context's lifetime from
  * HIP events recorded around each launch on the context stream:
- *   ABDDC_KSTAT_PLU_UPDATE  trailing MFMA update of the blocked partial LU
- *                           (work = algorithmic flops, 2 m n b per matrix)
+ *   ABDDC_KSTAT_PLU_UPDATE  MFMA updates of the blocked partial LU: the
+ *                           per-panel update of the still-to-be-factored
+ *                           region and the final trailing Schur product
+ *                           (work = algorithmic flops, 2 m n depth)
  *   ABDDC_KSTAT_GEMV        batched GEMV of M^{-1} and Shat (work =
  *                           algorithmic bytes: matrix + gathered input + output)
  * Any output pointer may be NULL. */

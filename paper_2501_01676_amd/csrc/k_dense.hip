@@ -63,34 +63,53 @@ __device__ void tile_gemm(const T* __restrict__ A, int lda, const T* __restrict_
                           int ldc, int m, int n, int k, T alpha, T beta, int row0, int col0,
                           T (*As)[LDS_PAD], T (*Bs)[LDS_PAD]) {
   typedef typename Mfma<T>::acc_t acc_t;
+  constexpr int PER = TILE * KC / 256;   // elements of each operand per thread and chunk (8)
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int w = tid >> 6;
   const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
+  // Load layouts (contiguous direction across lanes):
+  //   A row-major (!TA): i = (tid >> 5) + 8q, kk = tid & 31
+  //   A k-major  (TA):   kk = (tid >> 6) + 4q, i = tid & 63
+  //   B k-major (!TB):   kk = (tid >> 6) + 4q, j = tid & 63
+  //   B row-major (TB):  j = (tid >> 5) + 8q, kk = tid & 31
+  const int a_i0 = TA ? (tid & 63) : (tid >> 5), a_k0 = TA ? (tid >> 6) : (tid & 31);
+  const int b_j0 = TB ? (tid >> 5) : (tid & 63), b_k0 = TB ? (tid & 31) : (tid >> 6);
+  const int a_di = TA ? 0 : 8, a_dk = TA ? 4 : 0;
+  const int b_dj = TB ? 8 : 0, b_dk = TB ? 0 : 4;
   acc_t acc[2][2];
   for (int i = 0; i < 2; ++i)
     for (int j = 0; j < 2; ++j) acc[i][j] = acc_t{0, 0, 0, 0};
-
+  T ra[PER], rb[PER];
+  // per-thread base pointers; element q of a chunk is base + q * step
+  const int ar = row0 + a_i0, bc = col0 + b_j0;
+  const T* pa = TA ? A + (size_t)a_k0 * lda + ar : A + (size_t)ar * lda + a_k0;
+  const T* pb = TB ? B + (size_t)bc * ldb + b_k0 : B + (size_t)b_k0 * ldb + bc;
+  const size_t sa = TA ? (size_t)4 * lda : (size_t)8 * lda;   // step between q
+  const size_t sb = TB ? (size_t)8 * ldb : (size_t)4 * ldb;
+  auto fetch = [&](int k0) {
+    const T* qa = pa + (TA ? (size_t)k0 * lda : (size_t)k0);
+    const T* qb = pb + (TB ? (size_t)k0 : (size_t)k0 * ldb);
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const bool oka = (ar + q * a_di < m) && (k0 + a_k0 + q * a_dk < k);
+      ra[q] = oka ? qa[q * sa] : T(0);
+      const bool okb = (bc + q * b_dj < n) && (k0 + b_k0 + q * b_dk < k);
+      rb[q] = okb ? qb[q * sb] : T(0);
+    }
+  };
+  if (k > 0) fetch(0);
+  const int kl = lane >> 4, il = lane & 15;
+#pragma unroll 1
   for (int k0 = 0; k0 < k; k0 += KC) {
     __syncthreads();
-    for (int idx = tid; idx < TILE * KC; idx += 256) {
-      int i, kk;
-      if (!TA) { i = idx / KC; kk = idx % KC; } else { kk = idx / TILE; i = idx % TILE; }
-      int gr = row0 + i, gk = k0 + kk;
-      T v = 0;
-      if (gr < m && gk < k) v = TA ? A[(size_t)gk * lda + gr] : A[(size_t)gr * lda + gk];
-      As[kk][i] = v;
-    }
-    for (int idx = tid; idx < TILE * KC; idx += 256) {
-      int j, kk;
-      if (!TB) { kk = idx / TILE; j = idx % TILE; } else { j = idx / KC; kk = idx % KC; }
-      int gc = col0 + j, gk = k0 + kk;
-      T v = 0;
-      if (gc < n && gk < k) v = TB ? B[(size_t)gc * ldb + gk] : B[(size_t)gk * ldb + gc];
-      Bs[kk][j] = v;
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      As[a_k0 + q * a_dk][a_i0 + q * a_di] = ra[q];
+      Bs[b_k0 + q * b_dk][b_j0 + q * b_dj] = rb[q];
     }
     __syncthreads();
-    const int kl = lane >> 4, il = lane & 15;
+    if (k0 + KC < k) fetch(k0 + KC);   // next chunk in flight during the MFMAs
 #pragma unroll
     for (int kk = 0; kk < KC; kk += 4) {
       T a0 = As[kk + kl][wr + il];
@@ -104,7 +123,6 @@ __device__ void tile_gemm(const T* __restrict__ A, int lda, const T* __restrict_
     }
   }
   __syncthreads();
-  const int kl = lane >> 4, il = lane & 15;
   for (int bi = 0; bi < 2; ++bi)
     for (int bj = 0; bj < 2; ++bj)
       for (int q = 0; q < 4; ++q) {
@@ -222,22 +240,60 @@ __global__ void __launch_bounds__(256) plu_trsm_kernel(const PluDesc<T>* __restr
   }
 }
 
-// Step 3: A22 -= A21 A12.
+// Right-looking update after panel t0 (s = t0 + b), restricted to what is
+// still to be factored: rows [s, nrow) x cols [s, k) and rows [s, k) x
+// cols [k, ncol).  The block beyond k in both directions is formed once at
+// the end by plu_update_kernel.
 template <class T>
-__global__ void __launch_bounds__(256) plu_update_kernel(const PluDesc<T>* __restrict__ descs, int t0) {
+__global__ void __launch_bounds__(256) plu_lead_kernel(const PluDesc<T>* __restrict__ descs, int t0) {
   __shared__ T As[KC][LDS_PAD];
   __shared__ T Bs[KC][LDS_PAD];
   const PluDesc<T> d = descs[blockIdx.z];
   if (t0 >= d.k) return;
-  const int b = min(NB, d.k - t0);
-  const int s = t0 + b;
-  const int mr = d.nrow - s, nc = d.ncol - s;
+  const int b = min(NB, d.k - t0), s0 = t0 + b;
+  if (s0 >= d.k) return;
+  const int row0 = blockIdx.x * TILE, col0 = blockIdx.y * TILE;  // relative to s0
+  const int mr = d.nrow - s0, nc = d.ncol - s0, kr = d.k - s0;
+  if (row0 >= mr || col0 >= nc) return;
+  if (row0 >= kr && col0 >= kr) return;   // tile entirely in the trailing block
+  const T* A21 = d.a + (size_t)s0 * d.ld + t0;
+  const T* A12 = d.a + (size_t)t0 * d.ld + s0;
+  T* A22 = d.a + (size_t)s0 * d.ld + s0;
+  // Only entries with row < kr or col < kr are updated.  A tile crossing both
+  // row kr and column kr is done in two segments: rows [row0, kr) with all
+  // its columns, then rows [kr, row0 + TILE) with columns < kr.
+  int sm[2], sn[2], sr[2], nseg = 1;
+  if (row0 >= kr) {
+    sm[0] = mr; sn[0] = min(nc, kr); sr[0] = row0;
+  } else if (col0 >= kr) {
+    sm[0] = min(mr, kr); sn[0] = nc; sr[0] = row0;
+  } else if (row0 + TILE <= kr || col0 + TILE <= kr) {
+    sm[0] = mr; sn[0] = nc; sr[0] = row0;
+  } else {
+    sm[0] = kr; sn[0] = nc; sr[0] = row0;
+    sm[1] = min(mr, row0 + TILE); sn[1] = kr; sr[1] = kr;
+    nseg = 2;
+  }
+#pragma unroll 1
+  for (int g = 0; g < nseg; ++g)
+    tile_gemm<T, false, false>(A21, d.ld, A12, d.ld, A22, d.ld, sm[g], sn[g], b, T(-1), T(1), sr[g], col0, As, Bs);
+}
+
+// Trailing Schur complement A22 -= A21 A12 with K = k (one pass).
+template <class T>
+__global__ void __launch_bounds__(256) plu_update_kernel(const PluDesc<T>* __restrict__ descs) {
+  __shared__ T As[KC][LDS_PAD];
+  __shared__ T Bs[KC][LDS_PAD];
+  const PluDesc<T> d = descs[blockIdx.z];
+  const int k = d.k;
+  if (k == 0) return;
+  const int mr = d.nrow - k, nc = d.ncol - k;
   const int row0 = blockIdx.x * TILE, col0 = blockIdx.y * TILE;
   if (row0 >= mr || col0 >= nc) return;
-  const T* A21 = d.a + (size_t)s * d.ld + t0;
-  const T* A12 = d.a + (size_t)t0 * d.ld + s;
-  T* A22 = d.a + (size_t)s * d.ld + s;
-  tile_gemm<T, false, false>(A21, d.ld, A12, d.ld, A22, d.ld, mr, nc, b, T(-1), T(1), row0, col0, As, Bs);
+  const T* A21 = d.a + (size_t)k * d.ld;
+  const T* A12 = d.a + k;
+  T* A22 = d.a + (size_t)k * d.ld + k;
+  tile_gemm<T, false, false>(A21, d.ld, A12, d.ld, A22, d.ld, mr, nc, k, T(-1), T(1), row0, col0, As, Bs);
 }
 
 __global__ void gather_kernel(const GatherDesc* __restrict__ descs) {
@@ -290,25 +346,39 @@ void partial_lu(const std::vector<PluDesc<T>>& descs, int* dflag, hipStream_t s)
   T* scr = reinterpret_cast<T*>(scratch.p);
   const int nb = (int)descs.size();
   for (int t0 = 0; t0 < maxk; t0 += NB) {
-    plu_diag_kernel<T><<<nb, 256, 0, s>>>(dd, t0, scr, dflag);
     const int rem = std::max(maxr, maxc) - t0;
     const int tiles = 2 * ((rem + TILE - 1) / TILE);
+    plu_diag_kernel<T><<<nb, 256, 0, s>>>(dd, t0, scr, dflag);
     plu_trsm_kernel<T><<<dim3(std::max(tiles, 1), nb), 256, 0, s>>>(dd, t0, scr);
     const int rt = (maxr - t0 + TILE - 1) / TILE, ct = (maxc - t0 + TILE - 1) / TILE;
-    if (rt > 0 && ct > 0) {
+    if (t0 + NB < maxk && rt > 0 && ct > 0) {
       hipEvent_t end = nullptr;
       if (g_kstats) {
-        double flops = 0.0;  // 2 (nrow - s)(ncol - s) b per matrix still eliminating
+        double flops = 0.0;  // rows [s, nrow) x cols [s, k) and rows [s, k) x cols [k, ncol), depth b
         for (auto& d : descs)
-          if (t0 < d.k) {
-            const int b = std::min(NB, d.k - t0), sr = t0 + b;
-            flops += 2.0 * (double)(d.nrow - sr) * (double)(d.ncol - sr) * b;
+          if (t0 + NB < d.k) {
+            const int sr = t0 + NB;
+            flops += 2.0 * NB * ((double)(d.nrow - sr) * (d.k - sr) + (double)(d.k - sr) * (d.ncol - d.k));
           }
         g_kstats->begin(KC_PLU_UPDATE, flops, s, &end);
       }
-      plu_update_kernel<T><<<dim3(rt, ct, nb), 256, 0, s>>>(dd, t0);
+      plu_lead_kernel<T><<<dim3(rt, ct, nb), 256, 0, s>>>(dd, t0);
       if (end) ABDDC_HIP(hipEventRecord(end, s));
     }
+  }
+  // trailing Schur complement with K = k
+  int rt = 0, ct = 0;
+  double flops = 0.0;
+  for (auto& d : descs) {
+    rt = std::max(rt, (d.nrow - d.k + TILE - 1) / TILE);
+    ct = std::max(ct, (d.ncol - d.k + TILE - 1) / TILE);
+    flops += 2.0 * (double)(d.nrow - d.k) * (double)(d.ncol - d.k) * d.k;
+  }
+  if (rt > 0 && ct > 0) {
+    hipEvent_t end = nullptr;
+    if (g_kstats) g_kstats->begin(KC_PLU_UPDATE, flops, s, &end);
+    plu_update_kernel<T><<<dim3(rt, ct, nb), 256, 0, s>>>(dd);
+    if (end) ABDDC_HIP(hipEventRecord(end, s));
   }
   ABDDC_HIP(hipGetLastError());
 }
