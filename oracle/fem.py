@@ -130,8 +130,9 @@ def assemble_global(problem, topo, npts=3):
     return M, b
 
 
-def assemble_subdomains(problem, topo, npts=3, elem=None):
-    """Dense local matrices A^(i) and loads f^(i) in local order [I; Gamma_i].
+def assemble_subdomains(problem, topo, npts=3, elem=None, subs=None):
+    """Dense local matrices A^(i) and loads f^(i) in local order [I; Gamma_i]
+    (for the subdomains in ``subs``, default all).
 
     Section 3: A^(i), f^(i) come from a_i(., .) and g(.) restricted to the
     elements of subdomain i; Dirichlet nodes are dropped."""
@@ -139,7 +140,7 @@ def assemble_subdomains(problem, topo, npts=3, elem=None):
         elem = element_matrices(problem, topo, npts)
     A, F, nodes = elem
     out = []
-    for s in range(topo.n_sub):
+    for s in (range(topo.n_sub) if subs is None else subs):
         (x0, x1), (y0, y1), (z0, z1) = topo.element_box(s)
         EZ, EY, EX = np.meshgrid(np.arange(z0, z1), np.arange(y0, y1), np.arange(x0, x1), indexing="ij")
         eids = topo.elem_id(EX.ravel(), EY.ravel(), EZ.ravel())

@@ -37,14 +37,23 @@ void record(abddc_ctx* c, int i) {
 void apply_bddc_dev(abddc_ctx* c, const double* r, double* z) {
   hipStream_t s = c->stream;
   const int np = c->n_primal;
-  launch_gemv<double>(c->blk_M.p, c->nblk_M, c->gemv_M.p, c->maxc_M, c->dM.p, r, c->d_gam.p, c->d_out.p, false, s,
-                      c->bytes_M);
+  const bool mixed = c->dM32.p != nullptr;
+  if (mixed)
+    launch_gemv<float>(c->blk_M.p, c->nblk_M, c->gemv_M.p, c->maxc_M, c->dM32.p, r, c->d_gam.p, c->d_out.p, false, s,
+                       c->bytes_M);
+  else
+    launch_gemv<double>(c->blk_M.p, c->nblk_M, c->gemv_M.p, c->maxc_M, c->dM.p, r, c->d_gam.p, c->d_out.p, false, s,
+                        c->bytes_M);
   if (np > 0) {
     launch_gather_sum(c->d_pown_ptr.p, c->d_pown_idx.p, c->d_out.p, c->d_bpi.p, np, s);
     launch_gemv<double>(c->blk_C.p, c->nblk_C, c->gemv_C.p, np, c->dSPinv.p, c->d_bpi.p, nullptr, c->d_xpi.p, false, s,
                         c->bytes_C);
-    launch_gemv<double>(c->blk_U.p, c->nblk_U, c->gemv_U.p, c->maxc_U, c->dU.p, c->d_xpi.p, c->d_pid.p, c->d_out.p,
-                        true, s, c->bytes_U);
+    if (mixed)
+      launch_gemv<float>(c->blk_U.p, c->nblk_U, c->gemv_U.p, c->maxc_U, c->dU32.p, c->d_xpi.p, c->d_pid.p, c->d_out.p,
+                         true, s, c->bytes_U);
+    else
+      launch_gemv<double>(c->blk_U.p, c->nblk_U, c->gemv_U.p, c->maxc_U, c->dU.p, c->d_xpi.p, c->d_pid.p, c->d_out.p,
+                          true, s, c->bytes_U);
   }
   launch_gather_sum(c->d_aown_ptr.p, c->d_aown_idx.p, c->d_out.p, z, c->topo.n_gamma, s);
 }
@@ -287,7 +296,8 @@ extern "C" int abddc_setup_coarse_space(abddc_ctx* c, const abddc_options* opts,
     ABDDC_REQUIRE(o.edge_h_mode == ABDDC_H_SHARED || o.edge_h_mode == ABDDC_H_SEPARATE, ABDDC_EINVAL, "bad edge_h_mode");
     ABDDC_REQUIRE(o.deluxe_source == ABDDC_DELUXE_S || o.deluxe_source == ABDDC_DELUXE_B, ABDDC_EINVAL,
                   "bad deluxe_source");
-    ABDDC_REQUIRE(o.precision == ABDDC_PREC_FP64, ABDDC_EINVAL, "precision mode not provided");
+    ABDDC_REQUIRE(o.precision == ABDDC_PREC_FP64 || o.precision == ABDDC_PREC_MIXED, ABDDC_EINVAL,
+                  "bad precision mode");
     ABDDC_REQUIRE(o.constraint_source == ABDDC_CONSTRAINTS_EXACT, ABDDC_EINVAL, "constraint source not provided");
     ABDDC_REQUIRE(o.pinv_rtol >= 0 && o.svd_rtol >= 0 && o.tie_rtol >= 0, ABDDC_EINVAL, "negative tolerance");
     KStatsScope ks(&c->kstats);

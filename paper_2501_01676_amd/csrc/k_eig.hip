@@ -10,6 +10,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <string>
 
 #include "arena.h"
 #include "internal.h"
@@ -33,26 +34,28 @@ __device__ inline int rr_slot(int pos, int r, int m) {
   return 1 + (pos - 1 + r) % (m - 1);
 }
 
-// Jacobi on the symmetric n x n matrix in A (LDS), accumulating V (LDS,
-// starts as identity).  Index n (when n is odd) is a dummy that never
-// rotates.  Returns after convergence or 40 sweeps.
-__device__ void jacobi_lds(double (*A)[LDN], double (*V)[LDN], int n, double* cs, double* sn,
-                           int* pp, int* qq, int* nrot) {
+// Jacobi on the symmetric n x n matrix A (LDS, leading dimension NM + 1),
+// accumulating the eigenvectors transposed: row p of Vt is eigenvector p
+// (Vt starts as identity; LDS or global scratch with leading dimension ldv).
+// Cyclic sweeps in round-robin order; a rotation is skipped when |a_pq| is
+// negligible against sqrt(|a_pp a_qq|) (relative threshold 1e-18, below
+// double precision), and the iteration stops after a sweep without
+// rotations.
+template <int NM>
+__device__ void jacobi(double (*A)[NM + 1], double* Vt, int ldv, int n, double* cs, double* sn, int* pp,
+                       int* qq, int* nrot) {
   const int tid = threadIdx.x;
   const int m = (n + 1) & ~1;
   const int half = m / 2;
   const int tj = tid & 63, ti = tid >> 6, nstep = blockDim.x >> 6;
-  if (tj < n)
-    for (int r = ti; r < n; r += nstep) V[r][tj] = (r == tj) ? 1.0 : 0.0;
+  for (int r = ti; r < n; r += nstep)
+    for (int j = tj; j < n; j += 64) Vt[r * ldv + j] = (r == j) ? 1.0 : 0.0;
   if (tid == 0) *nrot = 0;
   __syncthreads();
-  // Cyclic sweeps; a rotation is skipped when |a_pq| is negligible against
-  // sqrt(|a_pp a_qq|) (relative threshold 1e-18 below double precision), and
-  // the iteration stops after a sweep without rotations.
   for (int sweep = 0; sweep < 60; ++sweep) {
     for (int r = 0; r < m - 1; ++r) {
-      if (tid < half) {
-        int a = rr_slot(tid, r, m), b = rr_slot(m - 1 - tid, r, m);
+      for (int t = tid; t < half; t += blockDim.x) {
+        int a = rr_slot(t, r, m), b = rr_slot(m - 1 - t, r, m);
         int p = min(a, b), q = max(a, b);
         double c = 1.0, s = 0.0;
         int active = 0;
@@ -61,47 +64,52 @@ __device__ void jacobi_lds(double (*A)[LDN], double (*V)[LDN], int n, double* cs
           const double app = A[p][p], aqq = A[q][q];
           if (apq != 0.0 && fabs(apq) > 1e-18 * sqrt(fabs(app) * fabs(aqq))) {
             const double tau = (aqq - app) / (2.0 * apq);
-            const double t = (tau >= 0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-            c = 1.0 / sqrt(1.0 + t * t);
-            s = t * c;
+            const double tt = (tau >= 0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+            c = 1.0 / sqrt(1.0 + tt * tt);
+            s = tt * c;
             active = 1;
             atomicAdd(nrot, 1);
           }
         }
-        cs[tid] = c;
-        sn[tid] = s;
-        pp[tid] = p;
-        qq[tid] = active ? q : n;   // inactive pairs are skipped below
+        cs[t] = c;
+        sn[t] = s;
+        pp[t] = p;
+        qq[t] = active ? q : n;   // inactive pairs are skipped below
       }
       __syncthreads();
-      // rows: A <- J^T A   (pair i = ti, ti + nstep, ...; element j = tj)
-      for (int i = ti; i < half && tj < n; i += nstep) {
-        const int p = pp[i], q = qq[i], j = tj;
+      // rows: A <- J^T A
+      for (int i = ti; i < half; i += nstep) {
+        const int p = pp[i], q = qq[i];
         if (q >= n) continue;
         const double c = cs[i], s = sn[i];
-        const double ap = A[p][j], aq = A[q][j];
-        A[p][j] = c * ap - s * aq;
-        A[q][j] = s * ap + c * aq;
+        for (int j = tj; j < n; j += 64) {
+          const double ap = A[p][j], aq = A[q][j];
+          A[p][j] = c * ap - s * aq;
+          A[q][j] = s * ap + c * aq;
+        }
       }
       __syncthreads();
-      // columns: A <- A J, V <- V J
-      for (int i = ti; i < half && tj < n; i += nstep) {
-        const int p = pp[i], q = qq[i], j = tj;
+      // columns: A <- A J; eigenvectors V <- V J (rows p, q of Vt)
+      for (int i = ti; i < half; i += nstep) {
+        const int p = pp[i], q = qq[i];
         if (q >= n) continue;
         const double c = cs[i], s = sn[i];
-        const double ap = A[j][p], aq = A[j][q];
-        A[j][p] = c * ap - s * aq;
-        A[j][q] = s * ap + c * aq;
-        const double vp = V[j][p], vq = V[j][q];
-        V[j][p] = c * vp - s * vq;
-        V[j][q] = s * vp + c * vq;
+        for (int j = tj; j < n; j += 64) {
+          const double ap = A[j][p], aq = A[j][q];
+          A[j][p] = c * ap - s * aq;
+          A[j][q] = s * ap + c * aq;
+          const double vp = Vt[p * ldv + j], vq = Vt[q * ldv + j];
+          Vt[p * ldv + j] = c * vp - s * vq;
+          Vt[q * ldv + j] = s * vp + c * vq;
+        }
       }
       __syncthreads();
       // the rotation annihilates a_pq
-      if (tid < half && qq[tid] < n) {
-        A[pp[tid]][qq[tid]] = 0.0;
-        A[qq[tid]][pp[tid]] = 0.0;
-      }
+      for (int t = tid; t < half; t += blockDim.x)
+        if (qq[t] < n) {
+          A[pp[t]][qq[t]] = 0.0;
+          A[qq[t]][pp[t]] = 0.0;
+        }
       __syncthreads();
     }
     const int done = (*nrot == 0);
@@ -113,7 +121,8 @@ __device__ void jacobi_lds(double (*A)[LDN], double (*V)[LDN], int n, double* cs
 }
 
 // Position of eigenvalue i in ascending order (ties by index).
-__device__ inline int rank_of(const double (*A)[LDN], int n, int i) {
+template <int NM>
+__device__ inline int rank_of(const double (*A)[NM + 1], int n, int i) {
   const double v = A[i][i];
   int r = 0;
   for (int j = 0; j < n; ++j) {
@@ -123,138 +132,162 @@ __device__ inline int rank_of(const double (*A)[LDN], int n, int i) {
   return r;
 }
 
-// A y = mu B y, B SPD: B = L L^T (Cholesky in LDS), C = L^{-1} A L^{-T},
-// Jacobi C = Y diag(mu) Y^T, output mu ascending and X = L Y.
-__global__ void __launch_bounds__(256) sygv_kernel(const SygvDesc* __restrict__ descs, int* dflag) {
-  __shared__ double Lm[NMAX][LDN];
-  __shared__ double Cm[NMAX][LDN];
-  __shared__ double Vm[NMAX][LDN];
-  __shared__ double cs[NMAX / 2], sn[NMAX / 2];
-  __shared__ int pp[NMAX / 2], qq[NMAX / 2];
+// Per-problem global scratch for the large variant: L and Vt (NM x NM each).
+template <int NM>
+struct EigScratch {
+  static __device__ inline double* L(double* base) { return base + (size_t)blockIdx.x * 2 * NM * NM; }
+  static __device__ inline double* V(double* base) { return base + (size_t)blockIdx.x * 2 * NM * NM + NM * NM; }
+};
+
+// A y = mu B y, B SPD: B = L L^T (Cholesky), C = L^{-1} A L^{-T}, Jacobi
+// C = Y diag(mu) Y^T, output mu ascending and X = L Y.  NM = 64: L, Vt in
+// LDS; NM = 128: L, Vt in global scratch, C in LDS.
+template <int NM>
+__global__ void __launch_bounds__(256) sygv_kernel(const SygvDesc* __restrict__ descs, int* dflag,
+                                                   double* __restrict__ scratch) {
+  constexpr bool SMALL = NM <= 64;
+  __shared__ double Cm[NM][NM + 1];
+  __shared__ double Lsm[SMALL ? NM : 1][SMALL ? NM + 1 : 1];
+  __shared__ double Vsm[SMALL ? NM : 1][SMALL ? NM + 1 : 1];
+  __shared__ double cs[NM / 2], sn[NM / 2];
+  __shared__ int pp[NM / 2], qq[NM / 2];
   __shared__ int nrot;
   const SygvDesc d = descs[blockIdx.x];
   const int n = d.n, tid = threadIdx.x;
   if (n <= 0) return;
+  double* L = SMALL ? &Lsm[0][0] : EigScratch<NM>::L(scratch);
+  double* Vt = SMALL ? &Vsm[0][0] : EigScratch<NM>::V(scratch);
+  const int ldl = SMALL ? NM + 1 : NM;
   const int tj = tid & 63, ti = tid >> 6, nstep = blockDim.x >> 6;
-  if (tj < n)
-    for (int r = ti; r < n; r += nstep) {
-      Lm[r][tj] = 0.5 * (d.B[r * n + tj] + d.B[tj * n + r]);
-      Cm[r][tj] = 0.5 * (d.A[r * n + tj] + d.A[tj * n + r]);
+  for (int r = ti; r < n; r += nstep)
+    for (int j = tj; j < n; j += 64) {
+      L[r * ldl + j] = 0.5 * (d.B[r * n + j] + d.B[j * n + r]);
+      Cm[r][j] = 0.5 * (d.A[r * n + j] + d.A[j * n + r]);
     }
   __syncthreads();
   // right-looking Cholesky, lower triangle
   for (int j = 0; j < n; ++j) {
     if (tid == 0) {
-      const double djj = Lm[j][j];
+      const double djj = L[j * ldl + j];
       if (!(djj > 0.0) || !isfinite(djj)) atomicOr(dflag, 2);
-      Lm[j][j] = sqrt(fmax(djj, 1e-300));
+      L[j * ldl + j] = sqrt(fmax(djj, 1e-300));
     }
     __syncthreads();
-    const double ljj = Lm[j][j];
-    for (int i = j + 1 + tid; i < n; i += blockDim.x) Lm[i][j] /= ljj;
+    const double ljj = L[j * ldl + j];
+    for (int i = j + 1 + tid; i < n; i += blockDim.x) L[i * ldl + j] /= ljj;
     __syncthreads();
-    if (tj > j && tj < n) {
-      const double lc = Lm[tj][j];
+    for (int c = j + 1 + tj; c < n; c += 64) {
+      const double lc = L[c * ldl + j];
       for (int i = j + 1 + ti; i < n; i += nstep)
-        if (tj <= i) Lm[i][tj] -= Lm[i][j] * lc;
+        if (i >= c) L[i * ldl + c] -= L[i * ldl + j] * lc;
     }
     __syncthreads();
   }
   // W = L^{-1} A (columns in place), then Z = L^{-1} W^T (rows of W in place)
-  if (tid < n) {
-    const int c = tid;
+  for (int c = tid; c < n; c += blockDim.x)
     for (int r = 0; r < n; ++r) {
       double v = Cm[r][c];
-      for (int q = 0; q < r; ++q) v -= Lm[r][q] * Cm[q][c];
-      Cm[r][c] = v / Lm[r][r];
+      for (int q = 0; q < r; ++q) v -= L[r * ldl + q] * Cm[q][c];
+      Cm[r][c] = v / L[r * ldl + r];
     }
-  }
   __syncthreads();
-  if (tid < n) {
-    const int j = tid;
+  for (int jr = tid; jr < n; jr += blockDim.x)
     for (int r = 0; r < n; ++r) {
-      double v = Cm[j][r];
-      for (int q = 0; q < r; ++q) v -= Lm[r][q] * Cm[j][q];
-      Cm[j][r] = v / Lm[r][r];
-    }
-  }
-  __syncthreads();
-  if (tj < n)
-    for (int r = ti; r < tj; r += nstep) {
-      const double v = 0.5 * (Cm[r][tj] + Cm[tj][r]);
-      Cm[r][tj] = v;
-      Cm[tj][r] = v;
+      double v = Cm[jr][r];
+      for (int q = 0; q < r; ++q) v -= L[r * ldl + q] * Cm[jr][q];
+      Cm[jr][r] = v / L[r * ldl + r];
     }
   __syncthreads();
-  jacobi_lds(Cm, Vm, n, cs, sn, pp, qq, &nrot);
-  // outputs: mu ascending, X[:, rank] = L Y[:, i]
-  for (int i = tid; i < n; i += blockDim.x) d.w[rank_of(Cm, n, i)] = Cm[i][i];
-  if (tj < n) {
-    const int col = rank_of(Cm, n, tj);
-    for (int r = ti; r < n; r += nstep) {
+  for (int r = ti; r < n; r += nstep)
+    for (int j = tj; j < n; j += 64)
+      if (r < j) {
+        const double v = 0.5 * (Cm[r][j] + Cm[j][r]);
+        Cm[r][j] = v;
+        Cm[j][r] = v;
+      }
+  __syncthreads();
+  jacobi<NM>(Cm, Vt, ldl, n, cs, sn, pp, qq, &nrot);
+  // outputs: mu ascending, X[:, rank(i)] = L y_i
+  for (int i = tid; i < n; i += blockDim.x) d.w[rank_of<NM>(Cm, n, i)] = Cm[i][i];
+  for (int i = ti; i < n; i += nstep) {
+    const int col = rank_of<NM>(Cm, n, i);
+    for (int r = tj; r < n; r += 64) {
       double v = 0.0;
-      for (int q = 0; q <= r; ++q) v += Lm[r][q] * Vm[q][tj];
+      for (int q = 0; q <= r; ++q) v += L[r * ldl + q] * Vt[i * ldl + q];
       d.X[r * n + col] = v;
     }
   }
 }
 
 // out = sum over kept eigenpairs of v v^T / lambda (lambda > rtol lambda_max)
-__global__ void __launch_bounds__(256) pinv_kernel(const PinvDesc* __restrict__ descs, double rtol) {
-  __shared__ double Am[NMAX][LDN];
-  __shared__ double Vm[NMAX][LDN];
-  __shared__ double cs[NMAX / 2], sn[NMAX / 2];
-  __shared__ int pp[NMAX / 2], qq[NMAX / 2];
+template <int NM>
+__global__ void __launch_bounds__(256) pinv_kernel(const PinvDesc* __restrict__ descs, double rtol,
+                                                   double* __restrict__ scratch) {
+  constexpr bool SMALL = NM <= 64;
+  __shared__ double Am[NM][NM + 1];
+  __shared__ double Vsm[SMALL ? NM : 1][SMALL ? NM + 1 : 1];
+  __shared__ double cs[NM / 2], sn[NM / 2];
+  __shared__ int pp[NM / 2], qq[NM / 2];
   __shared__ int nrot;
   __shared__ double lmax;
   const PinvDesc d = descs[blockIdx.x];
   const int n = d.n, tid = threadIdx.x;
   if (n <= 0) return;
+  double* Vt = SMALL ? &Vsm[0][0] : EigScratch<NM>::V(scratch);
+  const int ldv = SMALL ? NM + 1 : NM;
   const int tj = tid & 63, ti = tid >> 6, nstep = blockDim.x >> 6;
-  if (tj < n)
-    for (int r = ti; r < n; r += nstep) Am[r][tj] = 0.5 * (d.M[r * d.ld + tj] + d.M[tj * d.ld + r]);
+  for (int r = ti; r < n; r += nstep)
+    for (int j = tj; j < n; j += 64) Am[r][j] = 0.5 * (d.M[r * d.ld + j] + d.M[j * d.ld + r]);
   __syncthreads();
-  jacobi_lds(Am, Vm, n, cs, sn, pp, qq, &nrot);
+  jacobi<NM>(Am, Vt, ldv, n, cs, sn, pp, qq, &nrot);
   if (tid == 0) {
-    double m = 0.0;
-    for (int i = 0; i < n; ++i) m = fmax(m, Am[i][i]);
-    lmax = m;
+    double mx = 0.0;
+    for (int i = 0; i < n; ++i) mx = fmax(mx, Am[i][i]);
+    lmax = mx;
   }
   __syncthreads();
   const double cut = rtol * lmax;
-  if (tj < n)
-    for (int r = ti; r < n; r += nstep) {
+  for (int r = ti; r < n; r += nstep)
+    for (int j = tj; j < n; j += 64) {
       double v = 0.0;
       if (lmax > 0.0)
         for (int k = 0; k < n; ++k) {
           const double lam = Am[k][k];
-          if (lam > cut) v += Vm[r][k] * Vm[tj][k] / lam;
+          if (lam > cut) v += Vt[k * ldv + r] * Vt[k * ldv + j] / lam;
         }
-      d.out[r * d.ld + tj] = v;
+      d.out[r * d.ld + j] = v;
     }
 }
 
-// Householder QR of X (n x p), accumulated into Q = H_0 H_1 ... H_{p-1}.
-__global__ void __launch_bounds__(256) qr_complete_kernel(const QrDesc* __restrict__ descs) {
-  __shared__ double Xm[NMAX][LDN];
-  __shared__ double Qm[NMAX][LDN];
-  __shared__ double v[NMAX];
+// Householder QR of X (n x p), accumulated into Q = H_0 H_1 ... H_{p-1}
+// (X copy and Q in LDS for NM = 64, in global scratch / the output for 128).
+template <int NM>
+__global__ void __launch_bounds__(256) qr_complete_kernel(const QrDesc* __restrict__ descs,
+                                                          double* __restrict__ scratch) {
+  constexpr bool SMALL = NM <= 64;
+  __shared__ double Xsm[SMALL ? NM : 1][SMALL ? NM + 1 : 1];
+  __shared__ double Qsm[SMALL ? NM : 1][SMALL ? NM + 1 : 1];
+  __shared__ double v[NM];
   __shared__ double tau_s;
   const QrDesc d = descs[blockIdx.x];
   const int n = d.n, p = d.p, tid = threadIdx.x;
+  const int ld = SMALL ? NM + 1 : NM;
+  double* X = SMALL ? &Xsm[0][0] : scratch + (size_t)blockIdx.x * NM * NM;
+  double* Q = SMALL ? &Qsm[0][0] : d.T;
+  const int ldq = SMALL ? NM + 1 : n;
   for (int idx = tid; idx < n * n; idx += blockDim.x) {
     const int r = idx / n, c = idx % n;
-    Qm[r][c] = (r == c) ? 1.0 : 0.0;
-    if (c < p) Xm[r][c] = d.X[r * d.ldx + c];
+    Q[r * ldq + c] = (r == c) ? 1.0 : 0.0;
+    if (c < p) X[r * ld + c] = d.X[r * d.ldx + c];
   }
   __syncthreads();
   for (int j = 0; j < p; ++j) {
     if (tid == 0) {
       double nrm2 = 0.0;
-      for (int i = j; i < n; ++i) nrm2 += Xm[i][j] * Xm[i][j];
-      const double x0 = Xm[j][j];
+      for (int i = j; i < n; ++i) nrm2 += X[i * ld + j] * X[i * ld + j];
+      const double x0 = X[j * ld + j];
       const double alpha = (x0 >= 0 ? -1.0 : 1.0) * sqrt(nrm2);
-      for (int i = 0; i < n; ++i) v[i] = (i < j) ? 0.0 : Xm[i][j];
+      for (int i = 0; i < n; ++i) v[i] = (i < j) ? 0.0 : X[i * ld + j];
       v[j] = x0 - alpha;
       const double vn2 = nrm2 - x0 * x0 + v[j] * v[j];
       tau_s = vn2 > 0.0 ? 2.0 / vn2 : 0.0;
@@ -263,17 +296,18 @@ __global__ void __launch_bounds__(256) qr_complete_kernel(const QrDesc* __restri
     const double tau = tau_s;
     for (int c = j + tid; c < p; c += blockDim.x) {
       double dsum = 0.0;
-      for (int i = j; i < n; ++i) dsum += v[i] * Xm[i][c];
-      for (int i = j; i < n; ++i) Xm[i][c] -= tau * dsum * v[i];
+      for (int i = j; i < n; ++i) dsum += v[i] * X[i * ld + c];
+      for (int i = j; i < n; ++i) X[i * ld + c] -= tau * dsum * v[i];
     }
     for (int r = tid; r < n; r += blockDim.x) {
       double dsum = 0.0;
-      for (int i = j; i < n; ++i) dsum += Qm[r][i] * v[i];
-      for (int i = j; i < n; ++i) Qm[r][i] -= tau * dsum * v[i];
+      for (int i = j; i < n; ++i) dsum += Q[r * ldq + i] * v[i];
+      for (int i = j; i < n; ++i) Q[r * ldq + i] -= tau * dsum * v[i];
     }
     __syncthreads();
   }
-  for (int idx = tid; idx < n * n; idx += blockDim.x) d.T[idx] = Qm[idx / n][idx % n];
+  if (SMALL)
+    for (int idx = tid; idx < n * n; idx += blockDim.x) d.T[idx] = Q[(idx / n) * ldq + idx % n];
 }
 
 // One-sided Jacobi on the rows of G: G = U diag(sigma) W^T, U accumulated.
@@ -347,19 +381,47 @@ __global__ void __launch_bounds__(64) svd_left_kernel(const SvdDesc* __restrict_
 
 }  // namespace
 
+namespace {
+// Split a descriptor list by order: n <= 64 (LDS variant) and 64 < n <= 128.
+template <class D, class F>
+void split_launch(const std::vector<D>& descs, F order, hipStream_t s, const char* what,
+                  std::vector<D>& small, std::vector<D>& big) {
+  for (auto& d : descs) {
+    const int n = order(d);
+    ABDDC_REQUIRE(n <= 128, ABDDC_EINVAL, std::string(what) + ": matrix order exceeds 128");
+    (n <= 64 ? small : big).push_back(d);
+  }
+  (void)s;
+}
+}  // namespace
+
 void pinv_batched(const std::vector<PinvDesc>& descs, double rtol, hipStream_t s) {
-  if (descs.empty()) return;
-  for (auto& d : descs) ABDDC_REQUIRE(d.n <= NMAX, ABDDC_EINVAL, "pinv: matrix order exceeds 64");
-  const PinvDesc* dd = Arena::for_stream(s).put(descs);
-  pinv_kernel<<<descs.size(), 256, 0, s>>>(dd, rtol);
+  std::vector<PinvDesc> sm, bg;
+  split_launch(descs, [](const PinvDesc& d) { return d.n; }, s, "pinv", sm, bg);
+  if (!sm.empty()) {
+    const PinvDesc* dd = Arena::for_stream(s).put(sm);
+    pinv_kernel<64><<<sm.size(), 256, 0, s>>>(dd, rtol, nullptr);
+  }
+  if (!bg.empty()) {
+    DevBuf<double> scr(bg.size() * 2 * 128 * 128);
+    const PinvDesc* dd = Arena::for_stream(s).put(bg);
+    pinv_kernel<128><<<bg.size(), 256, 0, s>>>(dd, rtol, scr.p);
+  }
   ABDDC_HIP(hipGetLastError());
 }
 
 void qr_complete_batched(const std::vector<QrDesc>& descs, hipStream_t s) {
-  if (descs.empty()) return;
-  for (auto& d : descs) ABDDC_REQUIRE(d.n <= NMAX && d.p <= d.n, ABDDC_EINVAL, "qr: order exceeds 64");
-  const QrDesc* dd = Arena::for_stream(s).put(descs);
-  qr_complete_kernel<<<descs.size(), 256, 0, s>>>(dd);
+  std::vector<QrDesc> sm, bg;
+  split_launch(descs, [](const QrDesc& d) { return d.n; }, s, "qr", sm, bg);
+  if (!sm.empty()) {
+    const QrDesc* dd = Arena::for_stream(s).put(sm);
+    qr_complete_kernel<64><<<sm.size(), 256, 0, s>>>(dd, nullptr);
+  }
+  if (!bg.empty()) {
+    DevBuf<double> scr(bg.size() * 128 * 128);
+    const QrDesc* dd = Arena::for_stream(s).put(bg);
+    qr_complete_kernel<128><<<bg.size(), 256, 0, s>>>(dd, scr.p);
+  }
   ABDDC_HIP(hipGetLastError());
 }
 
@@ -372,12 +434,17 @@ void svd_left_batched(const std::vector<SvdDesc>& descs, double rtol, hipStream_
 }
 
 void sygv_batched(const std::vector<SygvDesc>& descs, int* dflag, hipStream_t s) {
-  if (descs.empty()) return;
-  for (auto& d : descs)
-    ABDDC_REQUIRE(d.n <= NMAX, ABDDC_EINVAL, "sygv: matrix order exceeds 64");
-  Arena& ar = Arena::for_stream(s);
-  const SygvDesc* dd = ar.put(descs);
-  sygv_kernel<<<descs.size(), 256, 0, s>>>(dd, dflag);
+  std::vector<SygvDesc> sm, bg;
+  split_launch(descs, [](const SygvDesc& d) { return d.n; }, s, "sygv", sm, bg);
+  if (!sm.empty()) {
+    const SygvDesc* dd = Arena::for_stream(s).put(sm);
+    sygv_kernel<64><<<sm.size(), 256, 0, s>>>(dd, dflag, nullptr);
+  }
+  if (!bg.empty()) {
+    DevBuf<double> scr(bg.size() * 2 * 128 * 128);
+    const SygvDesc* dd = Arena::for_stream(s).put(bg);
+    sygv_kernel<128><<<bg.size(), 256, 0, s>>>(dd, dflag, scr.p);
+  }
   ABDDC_HIP(hipGetLastError());
 }
 

@@ -137,7 +137,25 @@ __global__ void axpby_kernel(const AxpbyDesc* __restrict__ descs) {
   }
 }
 
+template <class S, class D>
+__global__ void convert_kernel(const S* __restrict__ src, D* __restrict__ dst, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    dst[i] = (D)src[i];
+}
+
 }  // namespace
+
+void convert_f64_f32(const double* src, float* dst, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  convert_kernel<double, float><<<(unsigned)std::min<int64_t>((n + 255) / 256, 65535), 256, 0, s>>>(src, dst, n);
+  ABDDC_HIP(hipGetLastError());
+}
+
+void convert_f32_f64(const float* src, double* dst, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  convert_kernel<float, double><<<(unsigned)std::min<int64_t>((n + 255) / 256, 65535), 256, 0, s>>>(src, dst, n);
+  ABDDC_HIP(hipGetLastError());
+}
 
 void deluxe_build_batched(const std::vector<DeluxeDesc>& descs, hipStream_t s) {
   if (descs.empty()) return;

@@ -667,7 +667,19 @@ void run_setup(abddc_ctx* c) {
     }
     gather_batched(gd, s);
     set_batched(st, s);
-    partial_lu<double>(pd, c->d_flag.p, s);
+    if (c->opt.precision == ABDDC_PREC_MIXED) {
+      // local constrained factorisation in FP32 on MFMA; the preconditioner it
+      // defines is applied inside FP64 GMRES, which absorbs its rounding
+      DevBuf<float> Aug32(Aug.n);
+      convert_f64_f32(Aug.p, Aug32.p, (int64_t)Aug.n, s);
+      std::vector<PluDesc<float>> pf;
+      for (auto& q : pd) pf.push_back({Aug32.p + (q.a - Aug.p), q.nrow, q.ncol, q.ld, q.k});
+      partial_lu<float>(pf, c->d_flag.p, s);
+      convert_f32_f64(Aug32.p, Aug.p, (int64_t)Aug.n, s);
+      ABDDC_HIP(hipStreamSynchronize(s));
+    } else {
+      partial_lu<double>(pd, c->d_flag.p, s);
+    }
 
     // Ktilde (nB x nB), Vt (nP x nB) = [Psi^T | I], Ut (nB x nP) = [Phi; I]
     gd.clear();
@@ -784,14 +796,26 @@ void run_setup(abddc_ctx* c) {
     }
     mC.push_back({0, 0, 0, np, np, std::max(np, 1), 0});
     for (int r = 0; r < np; r += GEMV_ROWS_PER_BLOCK) bC.push_back({0, r});
-    auto gbytes = [](const std::vector<GemvMat>& v, bool gathered) {
+    const bool mixed = c->opt.precision == ABDDC_PREC_MIXED;
+    auto gbytes = [](const std::vector<GemvMat>& v, bool gathered, double esize) {
       double b = 0.0;  // matrix + gathered input (value and index) + output
-      for (const GemvMat& m : v) b += (double)m.nrows * m.ncols * 8.0 + m.ncols * (gathered ? 12.0 : 8.0) + m.nrows * 8.0;
+      for (const GemvMat& m : v) b += (double)m.nrows * m.ncols * esize + m.ncols * (gathered ? 12.0 : 8.0) + m.nrows * 8.0;
       return b;
     };
-    c->bytes_M = gbytes(mM, true);
-    c->bytes_U = gbytes(mU, true);
-    c->bytes_C = gbytes(mC, false);
+    c->bytes_M = gbytes(mM, true, mixed ? 4.0 : 8.0);
+    c->bytes_U = gbytes(mU, true, mixed ? 4.0 : 8.0);
+    c->bytes_C = gbytes(mC, false, 8.0);
+    if (mixed) {
+      c->dM32.alloc(c->dM.n);
+      c->dU32.alloc(c->dU.n);
+      convert_f64_f32(c->dM.p, c->dM32.p, (int64_t)c->dM.n, s);
+      convert_f64_f32(c->dU.p, c->dU32.p, (int64_t)c->dU.n, s);
+      c->dM.release();
+      c->dU.release();
+    } else {
+      c->dM32.release();
+      c->dU32.release();
+    }
     c->gemv_M = to_device(mM, s);
     c->gemv_U = to_device(mU, s);
     c->gemv_C = to_device(mC, s);

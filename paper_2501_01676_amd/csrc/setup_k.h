@@ -40,6 +40,8 @@ struct AxpbyDesc {
   double alpha, beta;
 };
 
+void convert_f64_f32(const double* src, float* dst, int64_t n, hipStream_t s);
+void convert_f32_f64(const float* src, double* dst, int64_t n, hipStream_t s);
 void deluxe_build_batched(const std::vector<DeluxeDesc>& d, hipStream_t s);
 void edge_assemble_batched(const std::vector<EdgeAsmDesc>& d, hipStream_t s);
 void coarse_add_batched(const std::vector<CoarseAddDesc>& d, double* SPi, int64_t ldc, hipStream_t s);

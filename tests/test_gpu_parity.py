@@ -35,6 +35,7 @@ CASES = {
     "separate_h": (_layered, dict(LOOSE, edge_h_mode="separate"), dict(LOOSE, edge_h_mode=1)),
     "deluxe_b": (_layered, dict(LOOSE, deluxe_source="B"), dict(LOOSE, deluxe_source=1)),
     "config2": (W.config2, {}, {}),
+    "wide_ragged": (lambda: W.ragged((2, 2, 2), [8, 10, 12], 6, beta0=(3.0, -2.0, 1.0)), LOOSE, LOOSE),
 }
 
 
@@ -151,3 +152,93 @@ def test_solution(pairs, name):
     href = np.array(info_ref["history"])
     m = min(len(h), len(href))
     assert np.allclose(h[:m], href[:m], rtol=1e-6, atol=1e-14)
+
+
+@pytest.mark.parametrize("name", ["config1b", "layered_loose", "config2", "wide_ragged"])
+def test_mixed_precision_solution(pairs, name):
+    """FP32 local constrained factorisation and FP32 apply operators inside
+    FP64 GMRES: the same primal counts as the FP64 oracle; the interface
+    solution meets rtol against the oracle's FP64 Shat; the interior
+    unknowns equal the oracle's FP64 recovery from that interface solution;
+    at most a few more iterations than the FP64 oracle."""
+    from paper_2501_01676_amd import api
+    p, o, _ = pairs[name]
+    topo = o.topo
+    g = api.Solver(p)
+    counts = g.setup_coarse_space(precision=1, **CASES[name][2])
+    if o.counts["n_near_ties"] == 0:
+        assert counts == o.counts
+    _, info_ref = o.gmres_solve(restart=30, rtol=1e-8, maxit=300)
+    u, info = g.gmres_solve(restart=30, rtol=1e-8, maxit=300)
+    u = u.cpu().numpy()
+    assert info["converged"] and info["relres_true"] <= 1e-8
+    uhat = u[topo.dof_of_node[topo.iface_nodes]]
+    res = np.linalg.norm(o.ghat - o.apply_schur(uhat)) / np.linalg.norm(o.ghat)
+    assert res <= 1.01e-8, res
+    ur = o.recover(uhat)
+    assert np.linalg.norm(u - ur) <= 1e-11 * np.linalg.norm(ur)
+    assert info["iters"] <= info_ref["iters"] + 3
+    g.close()
+
+
+def test_config3_full_size_properties():
+    """config3 at full size in the benchmark's configuration: the GPU
+    solution satisfies the global stabilised system assembled by the oracle
+    (interior rows exactly, interface rows to the GMRES tolerance); sampled
+    local Schur complements and face spectra equal the oracle's."""
+    _need_gpu()
+    import scipy.sparse  # noqa: F401
+    from oracle import Topology, bddc, fem
+    from paper_2501_01676_amd import api
+    p = W.config3(0)
+    print("[parity] config3: gpu solve", flush=True)
+    g = api.Solver(p)
+    counts = g.setup_coarse_space()
+    u, info = g.gmres_solve(restart=30, rtol=1e-8, maxit=300)
+    u = u.cpu().numpy()
+    assert info["converged"]
+    topo = Topology(p["nsub"], p["widths"])
+    print("[parity] config3: oracle global system", flush=True)
+    A, b = fem.assemble_global(p, topo)
+    res = np.linalg.norm(A @ u - b) / np.linalg.norm(b)
+    assert res <= 1e-7, res
+    assert counts["n_vertex"] == len(topo.vertices)
+    # sampled subdomains: local Schur complements and right-hand sides
+    elem = fem.element_matrices(p, topo)
+    sample = [0, 73, 146, 292, 511]
+    loc = fem.assemble_subdomains(p, topo, elem=elem, subs=sample)
+    Sref = {}
+    for s_, (Al, fl) in zip(sample, loc):
+        nI = topo.sub[s_]["nI"]
+        X = np.linalg.solve(Al[:nI, :nI], np.concatenate([Al[:nI, nI:], fl[:nI, None]], axis=1))
+        S = Al[nI:, nI:] - Al[nI:, :nI] @ X[:, :-1]
+        Sref[s_] = S
+        Sg = g.stage(0, s_).reshape(S.shape)
+        assert np.abs(Sg - S).max() <= 1e-11 * np.abs(S).max(), s_
+        gg = g.stage(1, s_)
+        gr = fl[nI:] - Al[nI:, :nI] @ X[:, -1]
+        assert np.abs(gg - gr).max() <= 1e-11 * np.abs(gr).max(), s_
+    # sampled faces whose two subdomains are both sampled
+    checked = 0
+    for f, k in enumerate(topo.faces):
+        i, j = topo.objects[k]["subs"]
+        extra = [s_ for s_ in (i, j) if s_ not in Sref]
+        if checked >= 4 and extra:
+            continue
+        for s_, (Al, fl) in zip(extra, fem.assemble_subdomains(p, topo, elem=elem, subs=extra)):
+            nI = topo.sub[s_]["nI"]
+            Sref[s_] = Al[nI:, nI:] - Al[nI:, :nI] @ np.linalg.solve(Al[:nI, :nI], Al[:nI, nI:])
+        li, lj = topo.sub[i]["obj_local"][k], topo.sub[j]["obj_local"][k]
+        Si, Sj = Sref[i], Sref[j]
+        Bi, Bj = bddc.sym(Si), bddc.sym(Sj)
+        tot = Si[np.ix_(li, li)] + Sj[np.ix_(lj, lj)]
+        Di, Dj = np.linalg.solve(tot, Si[np.ix_(li, li)]), np.linalg.solve(tot, Sj[np.ix_(lj, lj)])
+        BF = Dj.T @ Bi[np.ix_(li, li)] @ Dj + Di.T @ Bj[np.ix_(lj, lj)] @ Di
+        Bt = bddc.parallel_sum(bddc.sym(bddc.schur_onto(Bi, li)), bddc.sym(bddc.schur_onto(Bj, lj)), 1e-10)
+        mu, _ = bddc.gep_reciprocal(Bt, bddc.sym(BF))
+        mg = g.stage(2, f)
+        assert np.abs(mg - np.sort(mu)).max() <= 1e-9 * max(1.0, np.abs(mu).max()), f
+        checked += 1
+        if checked >= 6:
+            break
+    g.close()

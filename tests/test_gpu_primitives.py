@@ -77,7 +77,7 @@ def test_sygv_matches_eigen_equation():
     api = _api()
     rng = np.random.default_rng(3)
     As, Bs = [], []
-    for n in (1, 2, 7, 21, 49, 64):
+    for n in (1, 2, 7, 21, 49, 64, 65, 100, 121, 128):
         X = rng.standard_normal((n, n))
         Y = rng.standard_normal((n, n))
         As.append(X @ X.T)
