@@ -30,6 +30,9 @@ METRIC = "BDDC-GMRES solve time to rtol 1e-8 (setup+iters), s; local-solve TFLOP
 PEAK_FP64_TFLOPS = 78.6     # MI355X dense FP64 (vector and matrix)
 PEAK_HBM_GBS = 8000.0       # MI355X HBM3E
 
+# live-timed kernel classes of the library: class -> (kernel, roofline bound)
+TRACKED = {0: ("plu_update_kernel<T>", "mfma"), 1: ("gemv_kernel<T>", "hbm"), 2: ("plu_lead_kernel<T>", "mfma")}
+
 DESCRIPTIONS = {
     "config1a": "2x2x2 subdomains, H/h=4 (8^3 Q1 elements), nu=1, a=(1,1,1), f=1",
     "config1b": "2x2x2 subdomains, H/h=8 (16^3 Q1 elements), nu=1, a=(1,1,1), f=1",
@@ -54,6 +57,9 @@ def parse():
     ap.add_argument("--maxit", type=int, default=300)
     ap.add_argument("--precision", type=int, default=0, help="0 = FP64, 1 = mixed")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="after the timed steps, copy a MIB-MiB device buffer 3 times (a plain copy kernel of "
+                         "known size, the reference for scaling HBM traffic counters)")
     return ap.parse_args()
 
 
@@ -79,8 +85,8 @@ def cpu_baseline(problem, opts, args):
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py: this build runs one problem on one GPU; multi-GPU runs are not part of it "
-              "(see DESIGN.md for how the path would shard). Use --gpus 1.", file=sys.stderr)
+        print("bench.py: the solver runs one problem on one GPU; multi-GPU runs are not supported. "
+              "Use --gpus 1.", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch
@@ -102,7 +108,7 @@ def main():
         tc = time.perf_counter()
         _, info = s.gmres_solve(args.restart, args.rtol, args.maxit, history=False)
         td = time.perf_counter()
-        ks = [s.kernel_stats(k) for k in (0, 1)]
+        ks = {k: s.kernel_stats(k) for k in TRACKED}
         ph = s.phase_times()
         sizes = (s.n_sub, s.n_dof, s.n_gamma)
         s.close()
@@ -120,20 +126,25 @@ def main():
 
     counts, info, _, _, sizes, _ = recs[-1]
     ok = all(r[1]["converged"] and r[1]["relres_true"] <= args.rtol for r in recs)
-    tot = {k: [sum(r[2][k][i] for r in recs) for i in range(3)] for k in (0, 1)}
-    plu_s, plu_n, plu_flops = tot[0]
-    gemv_s, gemv_n, gemv_bytes = tot[1]
-    tflops = plu_flops / plu_s / 1e12 if plu_s > 0 else 0.0
-    gbs = gemv_bytes / gemv_s / 1e9 if gemv_s > 0 else 0.0
-    roof_mfma = {"bound": "mfma", "kernel": "plu_lead_kernel<double> + plu_update_kernel<double> (partial-LU MFMA updates)", "achieved": tflops,
-                 "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": tflops / PEAK_FP64_TFLOPS,
-                 "traffic": None, "avg_launch_us": plu_s / max(plu_n, 1) * 1e6, "launches_per_step": plu_n / args.steps,
-                 "seconds_per_step": plu_s / args.steps}
-    roof_hbm = {"bound": "hbm", "kernel": "gemv_kernel<double>", "achieved": gbs, "peak": PEAK_HBM_GBS,
-                "unit": "GB/s", "frac": gbs / PEAK_HBM_GBS, "traffic": None,
-                "avg_launch_us": gemv_s / max(gemv_n, 1) * 1e6, "launches_per_step": gemv_n / args.steps,
-                "seconds_per_step": gemv_s / args.steps}
-    dominant, secondary = (roof_mfma, roof_hbm) if plu_s >= gemv_s else (roof_hbm, roof_mfma)
+    elt = "double" if args.precision == 0 else "double|float"
+    tracked = {}
+    for cls, (kname, bound) in TRACKED.items():
+        sec = sum(r[2][cls][0] for r in recs)
+        nl = sum(r[2][cls][1] for r in recs)
+        work = sum(r[2][cls][2] for r in recs)
+        if bound == "mfma":
+            ach, peak, unit = (work / sec / 1e12 if sec > 0 else 0.0), PEAK_FP64_TFLOPS, "TFLOP/s"
+        else:
+            ach, peak, unit = (work / sec / 1e9 if sec > 0 else 0.0), PEAK_HBM_GBS, "GB/s"
+        tracked[kname.replace("<T>", f"<{elt}>")] = {
+            "bound": bound, "achieved": ach, "peak": peak, "unit": unit, "frac": ach / peak,
+            "traffic": None, "avg_launch_us": sec / max(nl, 1) * 1e6, "launches_per_step": nl / args.steps,
+            "seconds_per_step": sec / args.steps, "work_per_launch": work / max(nl, 1)}
+    dom = max(tracked, key=lambda k: tracked[k]["seconds_per_step"])
+    roofline = dict(kernel=dom, **tracked[dom])
+    tflops = sum(v["work_per_launch"] * v["launches_per_step"] for v in tracked.values() if v["bound"] == "mfma")
+    tsec = sum(v["seconds_per_step"] for v in tracked.values() if v["bound"] == "mfma")
+    tflops = tflops / tsec / 1e12 if tsec > 0 else 0.0
     phases = np.mean([r[3] for r in recs], axis=0)
     walls = np.mean([r[5] for r in recs], axis=0)
     names = ["assemble", "local_schur", "deluxe", "faces", "edges", "local_factors", "coarse", "gmres", "recover"]
@@ -161,11 +172,19 @@ def main():
         "counts": counts,
         "phase_device_s": {n: float(v) for n, v in zip(names, phases)},
         "call_wall_s": {n: float(v) for n, v in zip(["assemble", "setup_coarse_space", "gmres_solve", "destroy"], walls)},
-        "roofline": dominant,
-        "roofline_secondary": secondary,
+        "roofline": roofline,
+        "kernels_tracked": tracked,
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(problem, opts, args)
+    if args.copy_probe > 0:
+        n = args.copy_probe * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        out["copy_probe_bytes"] = n * 8
     print(json.dumps(out), flush=True)
 
 

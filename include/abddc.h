@@ -197,14 +197,16 @@ int abddc_phase_times(const abddc_ctx* ctx, double* t, int32_t n);
 
 /* Live per-kernel statistics accumulated over the context's lifetime from
  * HIP events recorded around each launch on the context stream:
- *   ABDDC_KSTAT_PLU_UPDATE  MFMA updates of the blocked partial LU: the
- *                           per-panel update of the still-to-be-factored
- *                           region and the final trailing Schur product
- *                           (work = algorithmic flops, 2 m n depth)
+ *   ABDDC_KSTAT_PLU_UPDATE  final trailing Schur product of the blocked
+ *                           partial LU on MFMA (work = algorithmic flops,
+ *                           2 m n k)
  *   ABDDC_KSTAT_GEMV        batched GEMV of M^{-1} and Shat (work =
  *                           algorithmic bytes: matrix + gathered input + output)
+ *   ABDDC_KSTAT_PLU_LEAD    per-panel MFMA update of the still-to-be-factored
+ *                           rows and columns of the blocked partial LU
+ *                           (work = algorithmic flops, 2 m n 64)
  * Any output pointer may be NULL. */
-enum { ABDDC_KSTAT_PLU_UPDATE = 0, ABDDC_KSTAT_GEMV = 1 };
+enum { ABDDC_KSTAT_PLU_UPDATE = 0, ABDDC_KSTAT_GEMV = 1, ABDDC_KSTAT_PLU_LEAD = 2 };
 int abddc_kernel_stats(abddc_ctx* ctx, int32_t kernel, double* seconds, int64_t* launches, double* work);
 
 void abddc_destroy(abddc_ctx* ctx);

@@ -150,7 +150,8 @@ class Solver:
 
     def kernel_stats(self, kernel):
         """(seconds, launches, work) accumulated for a tracked kernel class
-        (0: partial-LU trailing update, flops; 1: batched GEMV, bytes)."""
+        (0: partial-LU trailing Schur product, flops; 1: batched GEMV, bytes;
+        2: partial-LU per-panel update, flops)."""
         sec, n, w = C.c_double(), C.c_int64(), C.c_double()
         L.check(self.lib.abddc_kernel_stats(self.ctx, kernel, C.byref(sec), C.byref(n), C.byref(w)))
         return sec.value, n.value, w.value

@@ -6,6 +6,7 @@
 #include <mutex>
 #include <string>
 
+#include "arena.h"
 #include "guard.h"
 #include "internal.h"
 #include "kstats.h"
@@ -50,6 +51,10 @@ size_t round_size(size_t b) {
   return (b + g - 1) / g * g;
 }
 }  // namespace
+
+void staged_upload(void* dst, const void* src, size_t bytes, hipStream_t s) {
+  if (bytes) Arena::for_stream(s).upload(dst, src, bytes);
+}
 
 void* cache_alloc(size_t bytes) {
   int dev = 0;

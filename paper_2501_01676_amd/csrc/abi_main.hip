@@ -226,7 +226,6 @@ extern "C" int abddc_assemble(const abddc_problem* prob, const abddc_device* dev
       for (int sub = 0; sub < nsub; ++sub)
         pd.push_back({c->dA.p + c->aoff[sub], c->nloc[sub], c->nloc[sub] + 1, c->nloc[sub] + 1, c->nI[sub]});
       partial_lu<double>(pd, c->d_flag.p, s);
-      ABDDC_HIP(hipStreamSynchronize(s));
     }
     c->dS.alloc(std::max<int64_t>(st, 1));
     c->dB.alloc(std::max<int64_t>(st, 1));

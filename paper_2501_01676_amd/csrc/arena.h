@@ -34,6 +34,19 @@ class Arena {
     off_ += need;
     return dst;
   }
+  // Stream-ordered upload into caller-owned device memory through the same
+  // pinned ring (no synchronisation unless the ring wraps).
+  void upload(void* dst, const void* src, size_t bytes) {
+    size_t need = (bytes + 255) & ~size_t(255);
+    if (off_ + need > cap_) {
+      ABDDC_HIP(hipStreamSynchronize(s_));
+      off_ = 0;
+      if (need > cap_) grow(need);
+    }
+    std::memcpy(h_ + off_, src, bytes);
+    ABDDC_HIP(hipMemcpyAsync(dst, h_ + off_, bytes, hipMemcpyHostToDevice, s_));
+    off_ += need;
+  }
   template <class T>
   T* put(const std::vector<T>& v) {
     return static_cast<T*>(put(v.data(), v.size() * sizeof(T)));

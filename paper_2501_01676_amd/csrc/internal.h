@@ -36,6 +36,8 @@ struct Error : std::runtime_error {
 // Memory returns to the driver only at process exit.
 void* cache_alloc(size_t bytes);
 void cache_free(void* p, size_t bytes);
+// Stream-ordered host -> device copy through the stream's pinned staging ring.
+void staged_upload(void* dst, const void* src, size_t bytes, hipStream_t s);
 
 // Stream on which the current entry point works (released blocks are tagged
 // with it).
@@ -74,23 +76,20 @@ struct DevBuf {
   }
   void upload(const std::vector<T>& h, hipStream_t s) {
     if (h.size() > n) alloc(h.size());
-    if (!h.empty()) {
-      ABDDC_HIP(hipMemcpyAsync(p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, s));
-      ABDDC_HIP(hipStreamSynchronize(s));
-    }
+    if (!h.empty()) staged_upload(p, h.data(), h.size() * sizeof(T), s);
   }
   void zero(hipStream_t s) {
     if (n) ABDDC_HIP(hipMemsetAsync(p, 0, n * sizeof(T), s));
   }
 };
 
+// Stream-ordered host -> device copy through the stream's pinned staging
+// ring: the host data is copied out before return, so the caller may free
+// it at once; the device copy completes in stream order.
 template <class T>
 inline DevBuf<T> to_device(const std::vector<T>& h, hipStream_t s) {
   DevBuf<T> d(h.size());
-  if (!h.empty()) {
-    ABDDC_HIP(hipMemcpyAsync(d.p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, s));
-    ABDDC_HIP(hipStreamSynchronize(s));  // the host vector may be released after return
-  }
+  if (!h.empty()) staged_upload(d.p, h.data(), h.size() * sizeof(T), s);
   return d;
 }
 

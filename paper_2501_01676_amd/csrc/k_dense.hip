@@ -360,7 +360,7 @@ void partial_lu(const std::vector<PluDesc<T>>& descs, int* dflag, hipStream_t s)
             const int sr = t0 + NB;
             flops += 2.0 * NB * ((double)(d.nrow - sr) * (d.k - sr) + (double)(d.k - sr) * (d.ncol - d.k));
           }
-        g_kstats->begin(KC_PLU_UPDATE, flops, s, &end);
+        g_kstats->begin(KC_PLU_LEAD, flops, s, &end);
       }
       plu_lead_kernel<T><<<dim3(rt, ct, nb), 256, 0, s>>>(dd, t0);
       if (end) ABDDC_HIP(hipEventRecord(end, s));

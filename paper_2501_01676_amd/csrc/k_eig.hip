@@ -20,6 +20,9 @@ namespace abddc {
 namespace {
 
 constexpr int NMAX = 64;
+// Threads per eigenproblem: the Jacobi rounds are latency-bound chains of
+// LDS accesses, so more waves per problem shorten each round.
+constexpr int EIG_THREADS = 1024;
 constexpr int LDN = NMAX + 1;
 
 __device__ inline double wave_sum64(double v) {
@@ -38,31 +41,48 @@ __device__ inline int rr_slot(int pos, int r, int m) {
 // accumulating the eigenvectors transposed: row p of Vt is eigenvector p
 // (Vt starts as identity; LDS or global scratch with leading dimension ldv).
 // Cyclic sweeps in round-robin order; a rotation is skipped when |a_pq| is
-// negligible against sqrt(|a_pp a_qq|) (relative threshold 1e-18, below
-// double precision), and the iteration stops after a sweep without
-// rotations.
+// negligible against sqrt(|a_pp a_qq|) (relative threshold 1e-16, half the
+// double precision unit roundoff) or against the matrix (1e-17 ||A||_F: below the rounding
+// noise the rotations themselves leave, which would otherwise keep a
+// singular matrix rotating forever), and the iteration stops after a sweep
+// without rotations.  The n/2 rotations of a round act on disjoint index pairs, so
+// the two-sided update A <- J^T A J splits into independent 2 x 2 blocks
+// (pair a rows, pair b columns): block (a, b) becomes J_a^T A_ab J_b.  One
+// pass updates every block and the rotated rows of Vt; a round costs two
+// barriers (rotation parameters, then the update).
 template <int NM>
-__device__ void jacobi(double (*A)[NM + 1], double* Vt, int ldv, int n, double* cs, double* sn, int* pp,
-                       int* qq, int* nrot) {
+__device__ int jacobi(double (*A)[NM + 1], double* Vt, int ldv, int n, double* cs, double* sn, int* pp,
+                      int* qq, int* nrot) {
   const int tid = threadIdx.x;
   const int m = (n + 1) & ~1;
   const int half = m / 2;
   const int tj = tid & 63, ti = tid >> 6, nstep = blockDim.x >> 6;
+  const int bj = tid & 15, bi = tid >> 4, bstep = blockDim.x >> 4;
+  __shared__ double fro2;
+  if (tid == 0) fro2 = 0.0;
+  __syncthreads();
+  double part = 0.0;
   for (int r = ti; r < n; r += nstep)
-    for (int j = tj; j < n; j += 64) Vt[r * ldv + j] = (r == j) ? 1.0 : 0.0;
+    for (int j = tj; j < n; j += 64) {
+      Vt[r * ldv + j] = (r == j) ? 1.0 : 0.0;
+      part += A[r][j] * A[r][j];
+    }
+  part = wave_sum64(part);
+  if ((tid & 63) == 0) atomicAdd(&fro2, part);
   if (tid == 0) *nrot = 0;
   __syncthreads();
+  const double abs_tol = 1e-17 * sqrt(fro2);
   for (int sweep = 0; sweep < 60; ++sweep) {
     for (int r = 0; r < m - 1; ++r) {
       for (int t = tid; t < half; t += blockDim.x) {
-        int a = rr_slot(t, r, m), b = rr_slot(m - 1 - t, r, m);
-        int p = min(a, b), q = max(a, b);
+        const int a = rr_slot(t, r, m), b = rr_slot(m - 1 - t, r, m);
+        const int p = min(a, b), q = max(a, b);
         double c = 1.0, s = 0.0;
         int active = 0;
         if (q < n) {
           const double apq = A[p][q];
           const double app = A[p][p], aqq = A[q][q];
-          if (apq != 0.0 && fabs(apq) > 1e-18 * sqrt(fabs(app) * fabs(aqq))) {
+          if (fabs(apq) > abs_tol && fabs(apq) > 1e-16 * sqrt(fabs(app) * fabs(aqq))) {
             const double tau = (aqq - app) / (2.0 * apq);
             const double tt = (tau >= 0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
             c = 1.0 / sqrt(1.0 + tt * tt);
@@ -74,50 +94,55 @@ __device__ void jacobi(double (*A)[NM + 1], double* Vt, int ldv, int n, double* 
         cs[t] = c;
         sn[t] = s;
         pp[t] = p;
-        qq[t] = active ? q : n;   // inactive pairs are skipped below
+        qq[t] = active ? q : -1 - q;   // negative: pair left unrotated
       }
       __syncthreads();
-      // rows: A <- J^T A
-      for (int i = ti; i < half; i += nstep) {
-        const int p = pp[i], q = qq[i];
-        if (q >= n) continue;
-        const double c = cs[i], s = sn[i];
-        for (int j = tj; j < n; j += 64) {
-          const double ap = A[p][j], aq = A[q][j];
-          A[p][j] = c * ap - s * aq;
-          A[q][j] = s * ap + c * aq;
+      for (int a = bi; a < half; a += bstep) {
+        const int qa_raw = qq[a];
+        const int pa = pp[a], qa = qa_raw >= 0 ? qa_raw : -1 - qa_raw;
+        const double ca = cs[a], sa = sn[a];
+        const bool hasq_a = qa < n;
+        for (int b = bj; b < half; b += 16) {
+          const int qb_raw = qq[b];
+          if (qa_raw < 0 && qb_raw < 0) continue;
+          const int pb = pp[b], qb = qb_raw >= 0 ? qb_raw : -1 - qb_raw;
+          const double cb = cs[b], sb = sn[b];
+          const bool hasq_b = qb < n;
+          const double x00 = A[pa][pb];
+          const double x01 = hasq_b ? A[pa][qb] : 0.0;
+          const double x10 = hasq_a ? A[qa][pb] : 0.0;
+          const double x11 = (hasq_a && hasq_b) ? A[qa][qb] : 0.0;
+          const double y00 = ca * x00 - sa * x10, y01 = ca * x01 - sa * x11;
+          const double y10 = sa * x00 + ca * x10, y11 = sa * x01 + ca * x11;
+          double z00 = cb * y00 - sb * y01, z01 = sb * y00 + cb * y01;
+          double z10 = cb * y10 - sb * y11, z11 = sb * y10 + cb * y11;
+          if (a == b) z01 = z10 = 0.0;   // the rotation annihilates a_pq
+          A[pa][pb] = z00;
+          if (hasq_b) A[pa][qb] = z01;
+          if (hasq_a) A[qa][pb] = z10;
+          if (hasq_a && hasq_b) A[qa][qb] = z11;
         }
       }
-      __syncthreads();
-      // columns: A <- A J; eigenvectors V <- V J (rows p, q of Vt)
-      for (int i = ti; i < half; i += nstep) {
-        const int p = pp[i], q = qq[i];
-        if (q >= n) continue;
-        const double c = cs[i], s = sn[i];
+      for (int t = ti; t < half; t += nstep) {
+        const int q = qq[t];
+        if (q < 0) continue;
+        const int p = pp[t];
+        const double c = cs[t], s = sn[t];
         for (int j = tj; j < n; j += 64) {
-          const double ap = A[j][p], aq = A[j][q];
-          A[j][p] = c * ap - s * aq;
-          A[j][q] = s * ap + c * aq;
           const double vp = Vt[p * ldv + j], vq = Vt[q * ldv + j];
           Vt[p * ldv + j] = c * vp - s * vq;
           Vt[q * ldv + j] = s * vp + c * vq;
         }
       }
       __syncthreads();
-      // the rotation annihilates a_pq
-      for (int t = tid; t < half; t += blockDim.x)
-        if (qq[t] < n) {
-          A[pp[t]][qq[t]] = 0.0;
-          A[qq[t]][pp[t]] = 0.0;
-        }
-      __syncthreads();
     }
     const int done = (*nrot == 0);
     __syncthreads();
-    if (done) break;
+    if (done) return sweep + 1;
     if (tid == 0) *nrot = 0;
     __syncthreads();
   }
+  return 60;
 }
 
 // Position of eigenvalue i in ascending order (ties by index).
@@ -140,23 +165,25 @@ struct EigScratch {
 };
 
 // A y = mu B y, B SPD: B = L L^T (Cholesky), C = L^{-1} A L^{-T}, Jacobi
-// C = Y diag(mu) Y^T, output mu ascending and X = L Y.  NM = 64: L, Vt in
-// LDS; NM = 128: L, Vt in global scratch, C in LDS.
+// C = Y diag(mu) Y^T, output mu ascending and X = L Y.  NM = 64: two LDS
+// matrices, C and one that holds L until C is formed and Vt during Jacobi
+// (L is parked in the output X meanwhile and read back into C's place at
+// the end); NM = 128: C in LDS, L and Vt in global scratch.
 template <int NM>
-__global__ void __launch_bounds__(256) sygv_kernel(const SygvDesc* __restrict__ descs, int* dflag,
+__global__ void __launch_bounds__(EIG_THREADS) sygv_kernel(const SygvDesc* __restrict__ descs, int* dflag,
                                                    double* __restrict__ scratch) {
   constexpr bool SMALL = NM <= 64;
   __shared__ double Cm[NM][NM + 1];
-  __shared__ double Lsm[SMALL ? NM : 1][SMALL ? NM + 1 : 1];
-  __shared__ double Vsm[SMALL ? NM : 1][SMALL ? NM + 1 : 1];
+  __shared__ double LVsm[SMALL ? NM : 1][SMALL ? NM + 1 : 1];
   __shared__ double cs[NM / 2], sn[NM / 2];
   __shared__ int pp[NM / 2], qq[NM / 2];
+  __shared__ int rk[NM];
   __shared__ int nrot;
   const SygvDesc d = descs[blockIdx.x];
   const int n = d.n, tid = threadIdx.x;
   if (n <= 0) return;
-  double* L = SMALL ? &Lsm[0][0] : EigScratch<NM>::L(scratch);
-  double* Vt = SMALL ? &Vsm[0][0] : EigScratch<NM>::V(scratch);
+  double* L = SMALL ? &LVsm[0][0] : EigScratch<NM>::L(scratch);
+  double* Vt = SMALL ? &LVsm[0][0] : EigScratch<NM>::V(scratch);
   const int ldl = SMALL ? NM + 1 : NM;
   const int tj = tid & 63, ti = tid >> 6, nstep = blockDim.x >> 6;
   for (int r = ti; r < n; r += nstep)
@@ -183,37 +210,61 @@ __global__ void __launch_bounds__(256) sygv_kernel(const SygvDesc* __restrict__ 
     }
     __syncthreads();
   }
-  // W = L^{-1} A (columns in place), then Z = L^{-1} W^T (rows of W in place)
-  for (int c = tid; c < n; c += blockDim.x)
-    for (int r = 0; r < n; ++r) {
-      double v = Cm[r][c];
-      for (int q = 0; q < r; ++q) v -= L[r * ldl + q] * Cm[q][c];
-      Cm[r][c] = v / L[r * ldl + r];
-    }
-  __syncthreads();
-  for (int jr = tid; jr < n; jr += blockDim.x)
-    for (int r = 0; r < n; ++r) {
-      double v = Cm[jr][r];
-      for (int q = 0; q < r; ++q) v -= L[r * ldl + q] * Cm[jr][q];
-      Cm[jr][r] = v / L[r * ldl + r];
-    }
-  __syncthreads();
+  // W = L^{-1} A (columns in place), then Z = L^{-1} W^T (rows of W in
+  // place).  Sixteen lanes share one column (row): lane l sums the terms
+  // q = l mod 16 of each substitution step and writes the solved entries
+  // r = l mod 16, so every value a lane reads back is one it wrote itself.
+  {
+    const int g = tid >> 4, l = tid & 15, ng = blockDim.x >> 4;
+    for (int c = g; c < n; c += ng)
+      for (int r = 0; r < n; ++r) {
+        double part = 0.0;
+        for (int q = l; q < r; q += 16) part += L[r * ldl + q] * Cm[q][c];
+        for (int m = 8; m > 0; m >>= 1) part += __shfl_xor(part, m, 16);
+        const double v = (Cm[r][c] - part) / L[r * ldl + r];
+        if ((r & 15) == l) Cm[r][c] = v;
+      }
+    __syncthreads();
+    for (int jr = g; jr < n; jr += ng)
+      for (int r = 0; r < n; ++r) {
+        double part = 0.0;
+        for (int q = l; q < r; q += 16) part += L[r * ldl + q] * Cm[jr][q];
+        for (int m = 8; m > 0; m >>= 1) part += __shfl_xor(part, m, 16);
+        const double v = (Cm[jr][r] - part) / L[r * ldl + r];
+        if ((r & 15) == l) Cm[jr][r] = v;
+      }
+    __syncthreads();
+  }
   for (int r = ti; r < n; r += nstep)
-    for (int j = tj; j < n; j += 64)
+    for (int j = tj; j < n; j += 64) {
       if (r < j) {
         const double v = 0.5 * (Cm[r][j] + Cm[j][r]);
         Cm[r][j] = v;
         Cm[j][r] = v;
       }
+      if (SMALL && j <= r) d.X[r * n + j] = L[r * ldl + j];   // park L
+    }
   __syncthreads();
   jacobi<NM>(Cm, Vt, ldl, n, cs, sn, pp, qq, &nrot);
   // outputs: mu ascending, X[:, rank(i)] = L y_i
-  for (int i = tid; i < n; i += blockDim.x) d.w[rank_of<NM>(Cm, n, i)] = Cm[i][i];
+  for (int i = tid; i < n; i += blockDim.x) {
+    const int ri = rank_of<NM>(Cm, n, i);
+    rk[i] = ri;
+    d.w[ri] = Cm[i][i];
+  }
+  __syncthreads();
+  if (SMALL) {
+    for (int r = ti; r < n; r += nstep)
+      for (int j = tj; j <= r; j += 64) Cm[r][j] = d.X[r * n + j];
+    __syncthreads();
+  }
+  const double* Lr = SMALL ? &Cm[0][0] : L;
+  const int ldr = SMALL ? NM + 1 : NM;
   for (int i = ti; i < n; i += nstep) {
-    const int col = rank_of<NM>(Cm, n, i);
+    const int col = rk[i];
     for (int r = tj; r < n; r += 64) {
       double v = 0.0;
-      for (int q = 0; q <= r; ++q) v += L[r * ldl + q] * Vt[i * ldl + q];
+      for (int q = 0; q <= r; ++q) v += Lr[r * ldr + q] * Vt[i * ldl + q];
       d.X[r * n + col] = v;
     }
   }
@@ -221,7 +272,7 @@ __global__ void __launch_bounds__(256) sygv_kernel(const SygvDesc* __restrict__ 
 
 // out = sum over kept eigenpairs of v v^T / lambda (lambda > rtol lambda_max)
 template <int NM>
-__global__ void __launch_bounds__(256) pinv_kernel(const PinvDesc* __restrict__ descs, double rtol,
+__global__ void __launch_bounds__(EIG_THREADS) pinv_kernel(const PinvDesc* __restrict__ descs, double rtol,
                                                    double* __restrict__ scratch) {
   constexpr bool SMALL = NM <= 64;
   __shared__ double Am[NM][NM + 1];
@@ -400,12 +451,12 @@ void pinv_batched(const std::vector<PinvDesc>& descs, double rtol, hipStream_t s
   split_launch(descs, [](const PinvDesc& d) { return d.n; }, s, "pinv", sm, bg);
   if (!sm.empty()) {
     const PinvDesc* dd = Arena::for_stream(s).put(sm);
-    pinv_kernel<64><<<sm.size(), 256, 0, s>>>(dd, rtol, nullptr);
+    pinv_kernel<64><<<sm.size(), EIG_THREADS, 0, s>>>(dd, rtol, nullptr);
   }
   if (!bg.empty()) {
     DevBuf<double> scr(bg.size() * 2 * 128 * 128);
     const PinvDesc* dd = Arena::for_stream(s).put(bg);
-    pinv_kernel<128><<<bg.size(), 256, 0, s>>>(dd, rtol, scr.p);
+    pinv_kernel<128><<<bg.size(), EIG_THREADS, 0, s>>>(dd, rtol, scr.p);
   }
   ABDDC_HIP(hipGetLastError());
 }
@@ -438,12 +489,12 @@ void sygv_batched(const std::vector<SygvDesc>& descs, int* dflag, hipStream_t s)
   split_launch(descs, [](const SygvDesc& d) { return d.n; }, s, "sygv", sm, bg);
   if (!sm.empty()) {
     const SygvDesc* dd = Arena::for_stream(s).put(sm);
-    sygv_kernel<64><<<sm.size(), 256, 0, s>>>(dd, dflag, nullptr);
+    sygv_kernel<64><<<sm.size(), EIG_THREADS, 0, s>>>(dd, dflag, nullptr);
   }
   if (!bg.empty()) {
     DevBuf<double> scr(bg.size() * 2 * 128 * 128);
     const SygvDesc* dd = Arena::for_stream(s).put(bg);
-    sygv_kernel<128><<<bg.size(), 256, 0, s>>>(dd, dflag, scr.p);
+    sygv_kernel<128><<<bg.size(), EIG_THREADS, 0, s>>>(dd, dflag, scr.p);
   }
   ABDDC_HIP(hipGetLastError());
 }

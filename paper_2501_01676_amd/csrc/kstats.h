@@ -12,12 +12,12 @@
 
 namespace abddc {
 
-enum KernelClass { KC_PLU_UPDATE = 0, KC_GEMV = 1, KC_COUNT = 2 };
+enum KernelClass { KC_PLU_UPDATE = 0, KC_GEMV = 1, KC_PLU_LEAD = 2, KC_COUNT = 3 };
 
 struct KStats {
-  double seconds[KC_COUNT] = {0, 0};
-  double work[KC_COUNT] = {0, 0};
-  int64_t launches[KC_COUNT] = {0, 0};
+  double seconds[KC_COUNT] = {0, 0, 0};
+  double work[KC_COUNT] = {0, 0, 0};
+  int64_t launches[KC_COUNT] = {0, 0, 0};
   struct Pending {
     int cls;
     hipEvent_t a, b;

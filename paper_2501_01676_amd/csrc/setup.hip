@@ -14,6 +14,7 @@
 #include "apply.h"
 #include "arena.h"
 #include "ctx.h"
+#include "htrace.h"
 #include "internal.h"
 #include "setup_k.h"
 
@@ -22,12 +23,10 @@ namespace abddc {
 namespace {
 
 struct IntPool {
-  // Concatenated host int arrays uploaded once through pinned memory (async);
-  // device pointers handed out by offset.  The pinned staging buffer lives
-  // until the pool is destroyed, after the setup's final synchronisation.
+  // Concatenated host int arrays uploaded once (stream-ordered, through the
+  // pinned staging ring); device pointers handed out by offset.
   std::vector<int32_t> h;
   DevBuf<int32_t> d;
-  int32_t* pinned = nullptr;
   size_t add(const std::vector<int32_t>& v) {
     size_t off = h.size();
     h.insert(h.end(), v.begin(), v.end());
@@ -35,15 +34,9 @@ struct IntPool {
   }
   void upload(hipStream_t s) {
     d.alloc(std::max<size_t>(h.size(), 1));
-    if (h.empty()) return;
-    ABDDC_HIP(hipHostMalloc(&pinned, h.size() * sizeof(int32_t), hipHostMallocDefault));
-    std::copy(h.begin(), h.end(), pinned);
-    ABDDC_HIP(hipMemcpyAsync(d.p, pinned, h.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    if (!h.empty()) staged_upload(d.p, h.data(), h.size() * sizeof(int32_t), s);
   }
   const int32_t* ptr(size_t off) const { return d.p + off; }
-  ~IntPool() {
-    if (pinned) (void)hipHostFree(pinned);   // hipHostFree waits for pending copies
-  }
 };
 
 void record(abddc_ctx* c, int i) {
@@ -76,8 +69,10 @@ void run_setup(abddc_ctx* c) {
     const int off = T.sub[sub].local_pos(obj);
     return base + c->soff[sub] + (int64_t)off * c->nB[sub] + off;
   };
+  HostTrace ht;
   c->d_flag.zero(s);
 
+  ht.mark("deluxe");
   // ------------------------------------------------------------ deluxe
   record(c, 2);
   const int nobj = (int)T.objects.size();
@@ -128,6 +123,7 @@ void run_setup(abddc_ctx* c) {
     gather_batched(gd, s);
   }
 
+  ht.mark("faces");
   // ------------------------------------------------------------- faces
   record(c, 3);
   c->pF.assign(nf, 0);
@@ -150,6 +146,7 @@ void run_setup(abddc_ctx* c) {
   c->dTF.alloc(std::max<int64_t>(ftot, 1));
   if (nf > 0) {
     DevBuf<double> W1(ftot), W2(ftot), BF(ftot), Sum(ftot), Pinv(ftot), T1(ftot), Bt(ftot), XF(ftot);
+    ht.mark("B_F = D_j^T B_F^(i) D_j + D_i^T B_F^(j");
     // B_F = D_j^T B_F^(i) D_j + D_i^T B_F^(j) D_i
     std::vector<GemmDesc<double>> g1, g2, g3;
     for (int f = 0; f < nf; ++f) {
@@ -167,6 +164,7 @@ void run_setup(abddc_ctx* c) {
     gemm_batched<double>(g2, true, false, 1.0, 0.0, s);
     gemm_batched<double>(g3, true, false, 1.0, 1.0, s);
 
+    ht.mark("Btilde_F^(nu): Schur complement of B^(");
     // Btilde_F^(nu): Schur complement of B^(nu) onto F (eliminate Gamma_nu minus F)
     std::vector<int64_t> eoff(2 * nf);
     int64_t etot = 0;
@@ -205,6 +203,7 @@ void run_setup(abddc_ctx* c) {
     gather_batched(gd, s);
     partial_lu<double>(pd, c->d_flag.p, s);
 
+    ht.mark("parallel sum Btilde_F = A (A + B)^+ B");
     // parallel sum Btilde_F = A (A + B)^+ B
     std::vector<AxpbyDesc> ad;
     std::vector<PinvDesc> pv;
@@ -229,6 +228,7 @@ void run_setup(abddc_ctx* c) {
     gemm_batched<double>(h2, false, false, 1.0, 0.0, s);
     sym_batched(sy, s);  // Sum now holds sym(Btilde_F)
 
+    ht.mark("Btilde_F y = mu B_F y");
     // Btilde_F y = mu B_F y
     std::vector<SygvDesc> gv;
     for (int f = 0; f < nf; ++f)
@@ -251,9 +251,9 @@ void run_setup(abddc_ctx* c) {
       qd.push_back({XF.p + c->tfoff[f], c->dTF.p + c->tfoff[f], n, p, n});
     }
     qr_complete_batched(qd, s);
-    ABDDC_HIP(hipStreamSynchronize(s));
   }
 
+  ht.mark("primal numbering: vertices, face prima");
   // primal numbering: vertices, face primals, edge primals
   c->n_vertex = nvx;
   std::vector<int> face_pbase(nf, 0);
@@ -264,6 +264,7 @@ void run_setup(abddc_ctx* c) {
   }
   c->pnum_face = nxt - nvx;
 
+  ht.mark("edges");
   // ------------------------------------------------------------- edges
   record(c, 4);
   c->rE.assign(ned, 0);
@@ -283,6 +284,7 @@ void run_setup(abddc_ctx* c) {
     c->dWE.alloc(std::max<int64_t>(wt, 1));
   }
   if (ned > 0) {
+    ht.mark("face-rotated Bbar^(s) = T_F^T B^(s) T_");
     // face-rotated Bbar^(s) = T_F^T B^(s) T_F on every face block
     DevBuf<double> Y(c->dB.n), Bbar(c->dB.n);
     ABDDC_HIP(hipMemcpyAsync(Y.p, c->dB.p, c->dB.n * sizeof(double), hipMemcpyDeviceToDevice, s));
@@ -303,6 +305,7 @@ void run_setup(abddc_ctx* c) {
     ABDDC_HIP(hipMemcpyAsync(Bbar.p, Y.p, c->dB.n * sizeof(double), hipMemcpyDeviceToDevice, s));
     gemm_batched<double>(gr, true, false, 1.0, 0.0, s);
 
+    ht.mark("stage 1: per subdomain eliminate all f");
     // stage 1: per subdomain eliminate all face dual coordinates; the Schur
     // complement W^(s) lives on [edge dofs, vertex dofs, face primals]
     IntPool pool;
@@ -344,6 +347,7 @@ void run_setup(abddc_ctx* c) {
       Hpid[sub] = pid_v;
       Hpid[sub].insert(Hpid[sub].end(), pid_f.begin(), pid_f.end());
     }
+    ht.mark("stage 2 maps per (edge, member): [othe");
     // stage 2 maps per (edge, member): [other edge dofs; E dofs; H] inside W
     std::vector<size_t> m2off((size_t)ned * 4);
     std::vector<int64_t> e2off((size_t)ned * 4);
@@ -412,6 +416,7 @@ void run_setup(abddc_ctx* c) {
       gather_batched(gd, s);
       partial_lu<double>(pd, c->d_flag.p, s);
     }
+    ht.mark("M_E and the coupled matrix; Schur comp");
     // M_E and the coupled matrix; Schur complement onto the jumps
     std::vector<int64_t> meoff(ned), qoff(ned), btoff(ned);
     int64_t metot = 0, qtot = 0;
@@ -467,6 +472,7 @@ void run_setup(abddc_ctx* c) {
     sygv_batched(gv, c->d_flag.p, s);
     std::vector<double> mu = to_host(c->dWE.p, c->dWE.n, s);
     require_flag_clean(c, "edge elimination / edge eigenproblem");
+    ht.mark("G = [g_{l,k}] (n_E x (m-1) |N_E|) and ");
     // G = [g_{l,k}] (n_E x (m-1) |N_E|) and its left singular basis
     int64_t gtot = 0;
     std::vector<int64_t> goffE(ned);
@@ -524,6 +530,7 @@ void run_setup(abddc_ctx* c) {
   }
   c->n_primal = nxt;
 
+  ht.mark("change of basis + local");
   // -------------------------------------------- change of basis + local
   record(c, 5);
   // local coordinate order per object: [primal, dual]; Pi / Delta positions
@@ -583,6 +590,7 @@ void run_setup(abddc_ctx* c) {
   c->dM.alloc(std::max<int64_t>(mt, 1));
   c->dU.alloc(std::max<int64_t>(ut, 1));
   {
+    ht.mark("Sbar = T^T S T (face and edge blocks)");
     // Sbar = T^T S T (face and edge blocks)
     ABDDC_HIP(hipMemcpyAsync(Y.p, c->dS.p, c->dS.n * sizeof(double), hipMemcpyDeviceToDevice, s));
     std::vector<GemmDesc<double>> gc, gr, wg;
@@ -617,6 +625,7 @@ void run_setup(abddc_ctx* c) {
     set_batched(vset, s);                                    // vertices: 1/|n(V)|
   }
   {
+    ht.mark("augmented [[Sdd, Sdp, I], [Spd, Spp, 0");
     // augmented [[Sdd, Sdp, I], [Spd, Spp, 0], [-I, 0, 0]], eliminate Delta
     IntPool pool;
     std::vector<size_t> am(nsub), dr(nsub), dc(nsub), kt(nsub), vr(nsub), vc(nsub), ur(nsub), uc(nsub), pi_off(nsub),
@@ -676,11 +685,11 @@ void run_setup(abddc_ctx* c) {
       for (auto& q : pd) pf.push_back({Aug32.p + (q.a - Aug.p), q.nrow, q.ncol, q.ld, q.k});
       partial_lu<float>(pf, c->d_flag.p, s);
       convert_f32_f64(Aug32.p, Aug.p, (int64_t)Aug.n, s);
-      ABDDC_HIP(hipStreamSynchronize(s));
     } else {
       partial_lu<double>(pd, c->d_flag.p, s);
     }
 
+    ht.mark("Ktilde (nB x nB), Vt (nP x nB) = [Psi^");
     // Ktilde (nB x nB), Vt (nP x nB) = [Psi^T | I], Ut (nB x nP) = [Phi; I]
     gd.clear();
     st.clear();
@@ -697,6 +706,7 @@ void run_setup(abddc_ctx* c) {
     gather_batched(gd, s);
     set_batched(st, s);
 
+    ht.mark("L = W Ktilde W^T, V = Vt W^T, U = W Ut");
     // L = W Ktilde W^T, V = Vt W^T, U = W Ut (W block diagonal)
     std::vector<GemmDesc<double>> g1, g2, g3, g4;
     for (int sub = 0; sub < nsub; ++sub) {
@@ -720,6 +730,7 @@ void run_setup(abddc_ctx* c) {
     gemm_batched<double>(g3, false, true, 1.0, 0.0, s);
     gemm_batched<double>(g4, false, false, 1.0, 0.0, s);
 
+    ht.mark("coarse");
     // ----------------------------------------------------------- coarse
     record(c, 6);
     const int np = c->n_primal;
@@ -758,6 +769,7 @@ void run_setup(abddc_ctx* c) {
       gather_batched({{Aug2.p + (int64_t)np * 2 * np + np, c->dSPinv.p, nullptr, nullptr, np, np, 2 * np, np, 1.0}}, s);
     }
 
+    ht.mark("apply metadata (device)");
     // ------------------------------------------- apply metadata (device)
     record(c, 7);
     std::vector<int32_t> pid_all, ptr_p(np + 1, 0), idx_p, ptr_a(T.n_gamma + 1, 0), idx_a;
@@ -830,7 +842,9 @@ void run_setup(abddc_ctx* c) {
     c->d_out.alloc(std::max<int64_t>(ot, 1));
     c->d_bpi.alloc(std::max(np, 1));
     c->d_xpi.alloc(std::max(np, 1));
+    ht.mark("metadata uploaded");
     require_flag_clean(c, "local constrained / coarse factorisation");
+    ht.mark("final flag check (sync)");
   }
   record(c, 8);
 }
