@@ -152,66 +152,126 @@ __global__ void __launch_bounds__(256) gemm_batched_kernel(const GemmDesc<T>* __
 }
 
 // --------------------------------------------------------------- partial LU
-// Step 1 of panel t0: factor the diagonal block (b = min(NB, k - t0)) in
-// LDS, store L\U back, and write L^{-1} (unit lower) and U^{-1} to scratch.
+template <class T>
+__device__ inline T read_lane(T v, int lane);
+template <>
+__device__ inline double read_lane<double>(double v, int lane) {
+  const long long x = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(x & 0xffffffffll), lane);
+  const int hi = __builtin_amdgcn_readlane((int)(x >> 32), lane);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+template <>
+__device__ inline float read_lane<float>(float v, int lane) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
+}
+
+// Step 1 of panel t0: factor the diagonal block (b = min(NB, k - t0)) and
+// write L\U back, L^{-1} (unit lower) and U^{-1} to scratch.  The block is
+// padded in LDS to diag(D, I) of order 64, which factors and inverts to
+// diag(L\U, I), diag(L^{-1}, I), diag(U^{-1}, I), so every loop below runs
+// to 64 with no size tests.  The LU is blocked in 16-column sub-panels:
+//   (a) wave 0 factors the 64 x 16 column panel in registers (lane = row;
+//       pivot rows broadcast by readlane, no LDS traffic and no barriers),
+//   (b) wave 0 solves the 16-row block row with the unit lower 16 x 16
+//       factor (lane = column),
+//   (c) all waves update the trailing block.
+// The inverses are one column per lane: wave 0 forward-substitutes L,
+// wave 1 back-substitutes U, each holding its column in registers.
 template <class T>
 __global__ void __launch_bounds__(256) plu_diag_kernel(const PluDesc<T>* __restrict__ descs, int t0,
                                                         T* __restrict__ scratch, int* dflag) {
   __shared__ T D[NB][NB + 1];
-  __shared__ T Li[NB][NB + 1];
-  __shared__ T Ui[NB][NB + 1];
+  __shared__ T dinv[NB];
   const PluDesc<T> d = descs[blockIdx.x];
   if (t0 >= d.k) return;
   const int b = min(NB, d.k - t0);
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   T* base = d.a + (size_t)t0 * d.ld + t0;
-  // thread (tr, tc) = (tid >> 6, tid & 63): column tc, rows tr, tr + 4, ...
-  const int tr = tid >> 6, tc = tid & 63;
-  if (tc < b)
-    for (int r = tr; r < b; r += 4) D[r][tc] = base[(size_t)r * d.ld + tc];
+  for (int r = wave; r < NB; r += 4) D[r][lane] = (r < b && lane < b) ? base[(size_t)r * d.ld + lane] : T(r == lane);
   __syncthreads();
-  for (int j = 0; j < b; ++j) {
-    const T piv = D[j][j];
-    if (tid == 0 && (!(fabs((double)piv) > 0.0) || !isfinite((double)piv))) atomicOr(dflag, 1);
-    const T inv = T(1) / piv;
-    if (tr == 0 && tc > j && tc < b) D[tc][j] *= inv;
+  for (int kb = 0; kb < b; kb += 16) {
+    if (wave == 0) {
+      T P[16];
+#pragma unroll
+      for (int j = 0; j < 16; ++j) P[j] = D[lane][kb + j];
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        const int pr = kb + j;
+        const T piv = read_lane(P[j], pr);
+        if (lane == 0 && pr < b && (!(fabs((double)piv) > 0.0) || !isfinite((double)piv))) atomicOr(dflag, 1);
+        const T inv = T(1) / piv;
+        T u[16];
+#pragma unroll
+        for (int j2 = j + 1; j2 < 16; ++j2) u[j2] = read_lane(P[j2], pr);
+        if (lane > pr) {
+          const T l = P[j] * inv;
+          P[j] = l;
+#pragma unroll
+          for (int j2 = j + 1; j2 < 16; ++j2) P[j2] -= l * u[j2];
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < 16; ++j) D[lane][kb + j] = P[j];
+    }
     __syncthreads();
-    if (tc > j && tc < b) {
-      const T u = D[j][tc];
-      for (int i = j + 1 + tr; i < b; i += 4) D[i][tc] -= D[i][j] * u;
+    if (wave == 0 && lane >= kb + 16) {
+      T X[16];
+#pragma unroll
+      for (int t = 0; t < 16; ++t) X[t] = D[kb + t][lane];
+#pragma unroll
+      for (int t = 1; t < 16; ++t) {
+        T v = X[t];
+#pragma unroll
+        for (int q = 0; q < t; ++q) v -= D[kb + t][kb + q] * X[q];
+        X[t] = v;
+      }
+#pragma unroll
+      for (int t = 0; t < 16; ++t) D[kb + t][lane] = X[t];
+    }
+    __syncthreads();
+    if (lane >= kb + 16) {
+      T U[16];
+#pragma unroll
+      for (int t = 0; t < 16; ++t) U[t] = D[kb + t][lane];
+      for (int i = kb + 16 + wave; i < NB; i += 4) {
+        T v = D[i][lane];
+#pragma unroll
+        for (int t = 0; t < 16; ++t) v -= D[i][kb + t] * U[t];
+        D[i][lane] = v;
+      }
     }
     __syncthreads();
   }
-  if (tc < b)
-    for (int r = tr; r < b; r += 4) base[(size_t)r * d.ld + tc] = D[r][tc];
-  // L^{-1} (unit lower) by columns with threads 0..63, U^{-1} (upper) by
-  // columns with threads 64..127; both staged in LDS.
-  if (tid < b) {
-    const int c = tid;
-    for (int r = 0; r < c; ++r) Li[r][c] = 0;
-    Li[c][c] = 1;
-    for (int r = c + 1; r < b; ++r) {
-      T v = 0;
-      for (int q = c; q < r; ++q) v -= D[r][q] * Li[q][c];
-      Li[r][c] = v;
-    }
-  } else if (tid >= 64 && tid < 64 + b) {
-    const int c = tid - 64;
-    for (int r = c + 1; r < b; ++r) Ui[r][c] = 0;
-    for (int r = c; r >= 0; --r) {
-      T v = (r == c) ? T(1) : T(0);
-      for (int q = r + 1; q <= c; ++q) v -= D[r][q] * Ui[q][c];
-      Ui[r][c] = v / D[r][r];
-    }
-  }
+  for (int r = wave; r < b; r += 4)
+    if (lane < b) base[(size_t)r * d.ld + lane] = D[r][lane];
+  if (wave == 1) dinv[lane] = T(1) / D[lane][lane];
   __syncthreads();
   T* gLi = scratch + (size_t)blockIdx.x * 2 * NB * NB;
   T* gUi = gLi + NB * NB;
-  if (tc < b)
-    for (int r = tr; r < b; r += 4) {
-      gLi[r * NB + tc] = Li[r][tc];
-      gUi[r * NB + tc] = Ui[r][tc];
+  if (wave == 0) {
+    T X[NB];
+#pragma unroll
+    for (int r = 0; r < NB; ++r) {
+      T v = T(r == lane);
+#pragma unroll
+      for (int q = 0; q < r; ++q) v -= D[r][q] * X[q];
+      X[r] = v;
     }
+#pragma unroll
+    for (int r = 0; r < NB; ++r) gLi[r * NB + lane] = X[r];
+  } else if (wave == 1) {
+    T X[NB];
+#pragma unroll
+    for (int r = NB - 1; r >= 0; --r) {
+      T v = T(r == lane);
+#pragma unroll
+      for (int q = r + 1; q < NB; ++q) v -= D[r][q] * X[q];
+      X[r] = v * dinv[r];
+    }
+#pragma unroll
+    for (int r = 0; r < NB; ++r) gUi[r * NB + lane] = X[r];
+  }
 }
 
 // Step 2: A21 <- A21 U11^{-1} (row tiles), A12 <- L11^{-1} A12 (column tiles).
