@@ -140,6 +140,9 @@ def main():
             "bound": bound, "achieved": ach, "peak": peak, "unit": unit, "frac": ach / peak,
             "traffic": None, "avg_launch_us": sec / max(nl, 1) * 1e6, "launches_per_step": nl / args.steps,
             "seconds_per_step": sec / args.steps, "work_per_launch": work / max(nl, 1)}
+    from paper_2501_01676_amd import profiling
+    for kname, v in tracked.items():
+        v["traffic"] = profiling.read_traffic(kname, args.config)
     dom = max(tracked, key=lambda k: tracked[k]["seconds_per_step"])
     roofline = dict(kernel=dom, **tracked[dom])
     tflops = sum(v["work_per_launch"] * v["launches_per_step"] for v in tracked.values() if v["bound"] == "mfma")

@@ -194,10 +194,10 @@ template <class TM>
 void launch_gemv(const GemvBlock* blocks, int nblk, const GemvMat* mats, int max_ncols, const TM* M,
                  const double* x, const int32_t* xidx, double* y, bool accumulate, hipStream_t s, double bytes) {
   if (nblk == 0) return;
-  hipEvent_t end = nullptr;
-  if (g_kstats && bytes > 0) g_kstats->begin(KC_GEMV, bytes, s, &end);
-  gemv_kernel<TM><<<nblk, 256, max_ncols * sizeof(double), s>>>(blocks, mats, M, x, xidx, y, accumulate ? 1 : 0);
-  if (end) ABDDC_HIP(hipEventRecord(end, s));
+  hipEvent_t ea, eb;
+  tracked_events(KC_GEMV, bytes, &ea, &eb);
+  hipExtLaunchKernelGGL(gemv_kernel<TM>, dim3(nblk), dim3(256), (uint32_t)(max_ncols * sizeof(double)), s, ea, eb, 0,
+                        blocks, mats, M, x, xidx, y, accumulate ? 1 : 0);
   ABDDC_HIP(hipGetLastError());
 }
 template void launch_gemv<double>(const GemvBlock*, int, const GemvMat*, int, const double*, const double*,

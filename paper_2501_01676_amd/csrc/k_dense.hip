@@ -412,7 +412,7 @@ void partial_lu(const std::vector<PluDesc<T>>& descs, int* dflag, hipStream_t s)
     plu_trsm_kernel<T><<<dim3(std::max(tiles, 1), nb), 256, 0, s>>>(dd, t0, scr);
     const int rt = (maxr - t0 + TILE - 1) / TILE, ct = (maxc - t0 + TILE - 1) / TILE;
     if (t0 + NB < maxk && rt > 0 && ct > 0) {
-      hipEvent_t end = nullptr;
+      hipEvent_t ea = nullptr, eb = nullptr;
       if (g_kstats) {
         double flops = 0.0;  // rows [s, nrow) x cols [s, k) and rows [s, k) x cols [k, ncol), depth b
         for (auto& d : descs)
@@ -420,10 +420,9 @@ void partial_lu(const std::vector<PluDesc<T>>& descs, int* dflag, hipStream_t s)
             const int sr = t0 + NB;
             flops += 2.0 * NB * ((double)(d.nrow - sr) * (d.k - sr) + (double)(d.k - sr) * (d.ncol - d.k));
           }
-        g_kstats->begin(KC_PLU_LEAD, flops, s, &end);
+        tracked_events(KC_PLU_LEAD, flops, &ea, &eb);
       }
-      plu_lead_kernel<T><<<dim3(rt, ct, nb), 256, 0, s>>>(dd, t0);
-      if (end) ABDDC_HIP(hipEventRecord(end, s));
+      hipExtLaunchKernelGGL(plu_lead_kernel<T>, dim3(rt, ct, nb), dim3(256), 0, s, ea, eb, 0, dd, t0);
     }
   }
   // trailing Schur complement with K = k
@@ -435,10 +434,9 @@ void partial_lu(const std::vector<PluDesc<T>>& descs, int* dflag, hipStream_t s)
     flops += 2.0 * (double)(d.nrow - d.k) * (double)(d.ncol - d.k) * d.k;
   }
   if (rt > 0 && ct > 0) {
-    hipEvent_t end = nullptr;
-    if (g_kstats) g_kstats->begin(KC_PLU_UPDATE, flops, s, &end);
-    plu_update_kernel<T><<<dim3(rt, ct, nb), 256, 0, s>>>(dd);
-    if (end) ABDDC_HIP(hipEventRecord(end, s));
+    hipEvent_t ea, eb;
+    tracked_events(KC_PLU_UPDATE, flops, &ea, &eb);
+    hipExtLaunchKernelGGL(plu_update_kernel<T>, dim3(rt, ct, nb), dim3(256), 0, s, ea, eb, 0, dd);
   }
   ABDDC_HIP(hipGetLastError());
 }

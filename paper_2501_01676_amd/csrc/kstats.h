@@ -1,10 +1,11 @@
 // Live per-kernel timing with HIP events on the launch stream.  An entry
-// point sets the thread's sink to its context; instrumented launchers wrap
-// each launch of a tracked kernel in an event pair and record the launch's
-// algorithmic work (flops or bytes).  resolve() turns finished pairs into
-// accumulated seconds.
+// point sets the thread's sink to its context; instrumented launchers take
+// an event pair that hipExtLaunchKernel stamps at the start and the end of
+// the kernel itself, and record the launch's algorithmic work (flops or
+// bytes).  resolve() turns finished pairs into accumulated seconds.
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -36,11 +37,11 @@ struct KStats {
     (void)hipEventCreate(&e);
     return e;
   }
-  void begin(int cls, double work_amount, hipStream_t s, hipEvent_t* out_end) {
+  void events(int cls, double work_amount, hipEvent_t* start, hipEvent_t* stop) {
     Pending p{cls, take(), take(), work_amount};
-    (void)hipEventRecord(p.a, s);
     pending.push_back(p);
-    *out_end = p.b;
+    *start = p.a;
+    *stop = p.b;
   }
   // call after the stream has been synchronised
   void resolve() {
@@ -66,6 +67,13 @@ struct KStats {
 };
 
 extern thread_local KStats* g_kstats;
+
+// Event pair for one launch of a tracked kernel (both null when no sink is
+// set; hipExtLaunchKernel then launches without timing).
+inline void tracked_events(int cls, double work_amount, hipEvent_t* start, hipEvent_t* stop) {
+  *start = *stop = nullptr;
+  if (g_kstats && work_amount > 0) g_kstats->events(cls, work_amount, start, stop);
+}
 
 // RAII: route the launches of one entry point into ctx stats.
 struct KStatsScope {
