@@ -111,7 +111,7 @@ typedef struct {
   double tie_rtol;          /* |lambda - Theta| <= tie_rtol Theta: near tie     */
   int32_t precision;        /* ABDDC_PREC_FP64 or ABDDC_PREC_MIXED             */
   int32_t constraint_source;/* exact GEP, or learned edge constraints          */
-  const char* mlp_weights;  /* weights file for ABDDC_CONSTRAINTS_MLP           */
+  const struct abddc_mlp* mlp; /* trained network for ABDDC_CONSTRAINTS_MLP     */
 } abddc_options;
 
 typedef struct {
@@ -213,6 +213,65 @@ void abddc_destroy(abddc_ctx* ctx);
 
 /* Thread-local message of the last failed call on this thread ("" if none). */
 const char* abddc_last_error(void);
+
+/* ---- Learned edge constraints (library extension of the edge
+ * eigenproblem, eq. equ-5-21 and equ-5-22) ----
+ * A network predicts, for every edge of n_E = 7 dofs, the projector
+ * P = Q_E Q_E^T onto the span of the primal constraint vectors the exact
+ * edge eigenproblem would select (Q_E: first r_E columns of the edge basis).
+ * Features (ABDDC_MLP_FEATURES per edge, float): log10 nu on the 4 x 4 x 8
+ * element tube around the edge in the edge frame (along-axis bins x first
+ * transverse axis x second transverse axis, transverse axes in cyclic order
+ * after the edge axis, element ranges resampled to 8 bins along the edge),
+ * asinh of the velocity at the edge midpoint in that frame (transverse,
+ * transverse, along), log10 of the mean and the maximum element Peclet
+ * number h_max |a| / nu over the tube.
+ * Network: 133 -> 128 (ReLU) -> 128 (ReLU) -> 28; bfloat16 weights and
+ * layer inputs on MFMA with FP32 accumulation, FP32 biases.  Outputs: the
+ * upper triangle of P-hat, row-major with the diagonal.  Parameters (FP32,
+ * ABDDC_MLP_PARAMS): W1 (128 x 133 row-major), b1, W2 (128 x 128), b2,
+ * W3 (28 x 128), b3.  Loss: mean over the batch of ||P-hat - P||_F^2;
+ * optimiser: Adam (beta1 0.9, beta2 0.999, eps 1e-8) on the FP32 weights.
+ * Gate (setup with ABDDC_CONSTRAINTS_MLP): an edge is solved exactly when
+ * n_E != 7, when an eigenvalue of P-hat lies in [0.3, 0.7], or when one of
+ * its features lies outside the training range widened by 10 % on each
+ * side; otherwise its constraint basis is the eigenvectors of P-hat with
+ * eigenvalue > 1/2, completed by QR.  A network is tied to the device of
+ * its creation; it is not thread-safe. */
+#define ABDDC_MLP_FEATURES 133
+#define ABDDC_MLP_OUTPUTS 28
+#define ABDDC_MLP_PARAMS 37276
+typedef struct abddc_mlp abddc_mlp;
+
+/* Network with the given FP32 parameters (HOST array of ABDDC_MLP_PARAMS),
+ * Adam moments zero.  EINVAL on a wrong count or null pointers. */
+int abddc_mlp_create(const float* params, int32_t n_params, const abddc_device* dev, abddc_mlp** out);
+/* Copies the FP32 parameters to a HOST array. */
+int abddc_mlp_get_params(abddc_mlp* mlp, float* params, int32_t n_params);
+/* Y (n x 28) = network(X (n x 133)); DEVICE pointers, stream-ordered on
+ * the network's stream (returns after the launch). */
+int abddc_mlp_forward(abddc_mlp* mlp, const float* X, int32_t n, float* Y);
+/* Loss (HOST scalar) and gradient (DEVICE array in the parameter layout) of
+ * the batch (X n x 133, targets T n x 28, DEVICE); synchronises. */
+int abddc_mlp_loss_grad(abddc_mlp* mlp, const float* X, const float* T, int32_t n, float* grad, float* loss);
+/* One Adam step on the batch; loss (HOST, may be NULL) before the step.
+ * Synchronises only when loss is requested. */
+int abddc_mlp_train_step(abddc_mlp* mlp, const float* X, const float* T, int32_t n, float lr, float* loss);
+/* Records the per-feature [min, max] of the training features X (DEVICE,
+ * n x 133) for the gate. */
+int abddc_mlp_set_ranges(abddc_mlp* mlp, const float* X, int32_t n);
+void abddc_mlp_destroy(abddc_mlp* mlp);
+
+/* Features of every edge of the context (edge kind order) into X (DEVICE,
+ * n_edge x 133); eligible (DEVICE int32 per edge, may be NULL) is 1 for
+ * edges of n_E = 7 dofs (features of other edges are still written). */
+int abddc_edge_features(abddc_ctx* ctx, float* X, int32_t* eligible);
+/* Training targets after a setup: the projector upper triangles of the
+ * context's edge bases (DEVICE, n_edge x 28; zeros for n_E != 7). */
+int abddc_edge_projectors(abddc_ctx* ctx, float* Y);
+/* Edges of the last setup whose constraints came from the network / from
+ * the exact eigenproblem. */
+int abddc_learned_stats(const abddc_ctx* ctx, int32_t* n_predicted, int32_t* n_exact);
 
 /* ---- Primitive test hooks (batched kernels the setup is built from) ----
  * Batched partial LU without pivoting, in place, on row-major matrices that

@@ -15,6 +15,7 @@ OK, NOT_CONVERGED, EINVAL, ENOMEM, ESINGULAR, EEIG, EDEVICE, ESTATE = 0, 1, -1, 
 
 STAGE_SCHUR, STAGE_LOCAL_RHS, STAGE_FACE_EIG, STAGE_EDGE_EIG = 0, 1, 2, 3
 STAGE_FACE_BASIS, STAGE_EDGE_BASIS, STAGE_COUNTS, STAGE_DELUXE = 4, 5, 6, 7
+MLP_FEATURES, MLP_OUTPUTS, MLP_PARAMS = 133, 28, 37276
 
 
 class Device(C.Structure):
@@ -49,7 +50,7 @@ class Options(C.Structure):
         ("tie_rtol", C.c_double),
         ("precision", C.c_int32),
         ("constraint_source", C.c_int32),
-        ("mlp_weights", C.c_char_p),
+        ("mlp", C.c_void_p),
     ]
 
 
@@ -84,6 +85,16 @@ SIGNATURES = {
     "abddc_kernel_stats": (C.c_int, [_P, C.c_int32, C.POINTER(C.c_double), _I64P, C.POINTER(C.c_double)]),
     "abddc_destroy": (None, [_P]),
     "abddc_last_error": (C.c_char_p, []),
+    "abddc_mlp_create": (C.c_int, [C.POINTER(C.c_float), C.c_int32, C.POINTER(Device), C.POINTER(_P)]),
+    "abddc_mlp_get_params": (C.c_int, [_P, C.POINTER(C.c_float), C.c_int32]),
+    "abddc_mlp_forward": (C.c_int, [_P, _P, C.c_int32, _P]),
+    "abddc_mlp_loss_grad": (C.c_int, [_P, _P, _P, C.c_int32, _P, C.POINTER(C.c_float)]),
+    "abddc_mlp_train_step": (C.c_int, [_P, _P, _P, C.c_int32, C.c_float, C.POINTER(C.c_float)]),
+    "abddc_mlp_set_ranges": (C.c_int, [_P, _P, C.c_int32]),
+    "abddc_mlp_destroy": (None, [_P]),
+    "abddc_edge_features": (C.c_int, [_P, _P, _P]),
+    "abddc_edge_projectors": (C.c_int, [_P, _P]),
+    "abddc_learned_stats": (C.c_int, [_P, _I32P, _I32P]),
     "abddc_test_partial_lu": (C.c_int, [C.c_int32, _P, _I64P, _I32P, _I32P, _I32P, _I32P, C.c_int32, _P]),
     "abddc_test_gemm": (C.c_int, [C.c_int32, _P, _I64P, _I64P, _I64P, _I32P, _I32P, _I32P, _I32P, _I32P,
                                   _I32P, C.c_int32, C.c_int32, C.c_double, C.c_double, _P]),

@@ -23,7 +23,7 @@ DEFAULT_OPTIONS = {
     "tie_rtol": 1e-9,
     "precision": 0,
     "constraint_source": 0,
-    "mlp_weights": None,
+    "mlp": None,
 }
 
 
@@ -94,8 +94,9 @@ class Solver:
         o.update(opts)
         s = L.Options()
         for k, v in o.items():
-            if k == "mlp_weights":
-                s.mlp_weights = None if v is None else str(v).encode()
+            if k == "mlp":
+                s.mlp = None if v is None else v.handle
+                self._mlp = v   # the network must outlive the setup call
             else:
                 setattr(s, k, v)
         cnt = L.Counts()
@@ -105,6 +106,26 @@ class Solver:
 
     def _vec(self, n):
         return torch.empty(n, dtype=torch.float64, device=f"cuda:{self.device}")
+
+    def edge_features(self):
+        """(features n_edge x 133 float32, eligible n_edge int32), device tensors."""
+        X = torch.empty((self.n_edge, L.MLP_FEATURES), dtype=torch.float32, device=f"cuda:{self.device}")
+        el = torch.empty(self.n_edge, dtype=torch.int32, device=f"cuda:{self.device}")
+        if self.n_edge:
+            L.check(self.lib.abddc_edge_features(self.ctx, _dptr(X), _dptr(el)))
+        return X, el
+
+    def edge_projectors(self):
+        """Training targets of the last setup (n_edge x 28 float32, device)."""
+        Y = torch.empty((self.n_edge, L.MLP_OUTPUTS), dtype=torch.float32, device=f"cuda:{self.device}")
+        if self.n_edge:
+            L.check(self.lib.abddc_edge_projectors(self.ctx, _dptr(Y)))
+        return Y
+
+    def learned_stats(self):
+        a, b = C.c_int32(), C.c_int32()
+        L.check(self.lib.abddc_learned_stats(self.ctx, C.byref(a), C.byref(b)))
+        return {"predicted": a.value, "exact": b.value}
 
     def apply_bddc(self, r, out=None):
         z = self._vec(self.n_gamma) if out is None else out
@@ -160,6 +181,60 @@ class Solver:
         if getattr(self, "ctx", None):
             self.lib.abddc_destroy(self.ctx)
             self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class MLP:
+    """Edge-constraint network (abddc_mlp) on one GPU."""
+
+    def __init__(self, params, device=0, stream=None):
+        self.lib = L.load()
+        self.device = device
+        torch.cuda.set_device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(device)
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        assert p.size == L.MLP_PARAMS
+        dev = L.Device(device, _stream_handle(self.stream))
+        h = C.c_void_p()
+        L.check(self.lib.abddc_mlp_create(p.ctypes.data_as(C.POINTER(C.c_float)), p.size, C.byref(dev), C.byref(h)))
+        self.handle = h
+
+    def params(self):
+        out = np.zeros(L.MLP_PARAMS, dtype=np.float32)
+        L.check(self.lib.abddc_mlp_get_params(self.handle, out.ctypes.data_as(C.POINTER(C.c_float)), out.size))
+        return out
+
+    def forward(self, X):
+        X = X.contiguous()
+        Y = torch.empty((X.shape[0], L.MLP_OUTPUTS), dtype=torch.float32, device=X.device)
+        L.check(self.lib.abddc_mlp_forward(self.handle, _dptr(X), X.shape[0], _dptr(Y)))
+        return Y
+
+    def loss_grad(self, X, T):
+        g = torch.empty(L.MLP_PARAMS, dtype=torch.float32, device=X.device)
+        loss = C.c_float()
+        L.check(self.lib.abddc_mlp_loss_grad(self.handle, _dptr(X.contiguous()), _dptr(T.contiguous()), X.shape[0],
+                                             _dptr(g), C.byref(loss)))
+        return loss.value, g
+
+    def train_step(self, X, T, lr, want_loss=False):
+        loss = C.c_float()
+        L.check(self.lib.abddc_mlp_train_step(self.handle, _dptr(X), _dptr(T), X.shape[0], float(lr),
+                                              C.byref(loss) if want_loss else None))
+        return loss.value if want_loss else None
+
+    def set_ranges(self, X):
+        L.check(self.lib.abddc_mlp_set_ranges(self.handle, _dptr(X.contiguous()), X.shape[0]))
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self.lib.abddc_mlp_destroy(self.handle)
+            self.handle = None
 
     def __del__(self):
         try:

@@ -297,7 +297,10 @@ extern "C" int abddc_setup_coarse_space(abddc_ctx* c, const abddc_options* opts,
                   "bad deluxe_source");
     ABDDC_REQUIRE(o.precision == ABDDC_PREC_FP64 || o.precision == ABDDC_PREC_MIXED, ABDDC_EINVAL,
                   "bad precision mode");
-    ABDDC_REQUIRE(o.constraint_source == ABDDC_CONSTRAINTS_EXACT, ABDDC_EINVAL, "constraint source not provided");
+    ABDDC_REQUIRE(o.constraint_source == ABDDC_CONSTRAINTS_EXACT || o.constraint_source == ABDDC_CONSTRAINTS_MLP,
+                  ABDDC_EINVAL, "bad constraint source");
+    ABDDC_REQUIRE(o.constraint_source != ABDDC_CONSTRAINTS_MLP || (o.mlp && o.mlp->device == c->device), ABDDC_EINVAL,
+                  "learned constraints need a network on the context's device");
     ABDDC_REQUIRE(o.pinv_rtol >= 0 && o.svd_rtol >= 0 && o.tie_rtol >= 0, ABDDC_EINVAL, "negative tolerance");
     KStatsScope ks(&c->kstats);
     StreamScope ss(c->stream);

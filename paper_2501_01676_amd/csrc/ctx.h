@@ -10,6 +10,7 @@
 #include "assemble.h"
 #include "internal.h"
 #include "kstats.h"
+#include "mlp.h"
 #include "topology.h"
 
 struct abddc_ctx {
@@ -74,6 +75,11 @@ struct abddc_ctx {
   abddc::DevBuf<abddc::GmresState> d_gst;
   abddc::GmresState* h_gst = nullptr;               // pinned mirror of the scalars
   int gm_restart = 0;
+
+  // ------------------------------------------------- learned constraints
+  std::vector<abddc::EdgeGeom> egeom;               // per edge (kind order)
+  abddc::DevBuf<abddc::EdgeGeom> d_egeom;
+  int n_pred_edges = 0, n_exact_edges = 0;
 
   // ------------------------------------------------------------- misc
   abddc::DevBuf<int> d_flag;

@@ -16,6 +16,7 @@
 #include "ctx.h"
 #include "htrace.h"
 #include "internal.h"
+#include "mlp.h"
 #include "setup_k.h"
 
 namespace abddc {
@@ -54,6 +55,51 @@ void require_flag_clean(abddc_ctx* c, const char* stage) {
   const int h = check_flag(c);
   if (h & 1) throw Error(ABDDC_ESINGULAR, std::string(stage) + ": zero or non-finite pivot");
   if (h & 2) throw Error(ABDDC_EEIG, std::string(stage) + ": eigenproblem metric not positive definite");
+}
+
+// Learned edge constraints: features -> network -> P-hat -> eigenpairs;
+// the gate keeps an edge's prediction (basis = eigenvectors of P-hat with
+// eigenvalue > 1/2, completed by QR into the edge basis) or appends the
+// edge to `exact`.
+void learned_edges(abddc_ctx* c, std::vector<int>& exact) {
+  const Topology& T = c->topo;
+  hipStream_t s = c->stream;
+  const int ned = (int)T.edges.size();
+  abddc_mlp* w = const_cast<abddc_mlp*>(c->opt.mlp);
+  ABDDC_HIP(hipStreamSynchronize(w->stream));   // training launched on the network's stream has finished
+  build_edge_geometry(c);
+  DevBuf<float> X((size_t)ned * MLP_IN), Y((size_t)ned * MLP_OUT);
+  launch_edge_features(c->d_egeom.p, ned, feature_params(c), c->d_nu.p, X.p, s);
+  mlp_forward_dev(w, X.p, ned, Y.p, s);
+  DevBuf<double> P((size_t)ned * 49), I((size_t)ned * 49), W((size_t)ned * 7), V((size_t)ned * 49);
+  launch_phat(Y.p, ned, P.p, I.p, s);
+  std::vector<SygvDesc> gv;
+  for (int e = 0; e < ned; ++e)
+    if (c->egeom[e].eligible) gv.push_back({P.p + 49 * e, I.p + 49 * e, W.p + 7 * e, V.p + 49 * e, MLP_NE});
+  sygv_batched(gv, c->d_flag.p, s);
+  DevBuf<int32_t> flag(std::max(ned, 1));
+  flag.zero(s);
+  if (w->have_ranges) launch_range_flags(X.p, ned, w->fmin.p, w->fmax.p, 0.1f, flag.p, s);
+  std::vector<double> lam = to_host(W.p, (size_t)ned * 7, s);
+  std::vector<int32_t> out = to_host(flag.p, ned, s);
+  std::vector<QrDesc> qd;
+  for (int e = 0; e < ned; ++e) {
+    bool keep = c->egeom[e].eligible && !out[e];
+    int r = 0;
+    for (int q = 0; keep && q < MLP_NE; ++q) {
+      const double l = lam[7 * e + q];
+      if (l >= 0.3 && l <= 0.7) keep = false;
+      if (l > 0.5) ++r;
+    }
+    if (!keep) {
+      exact.push_back(e);
+      continue;
+    }
+    c->rE[e] = r;
+    c->nselE[e] = 0;
+    qd.push_back({V.p + 49 * e + (MLP_NE - r), c->dTE.p + c->teoff[e], MLP_NE, r, MLP_NE});
+  }
+  qr_complete_batched(qd, s);
 }
 
 }  // namespace
@@ -283,7 +329,18 @@ void run_setup(abddc_ctx* c) {
     c->dTE.alloc(std::max<int64_t>(tt, 1));
     c->dWE.alloc(std::max<int64_t>(wt, 1));
   }
-  if (ned > 0) {
+  // edges whose constraints come from the exact eigenproblem: all of them,
+  // or those the network's gate sends back
+  std::vector<int> elist;
+  if (ned > 0 && c->opt.constraint_source == ABDDC_CONSTRAINTS_MLP) {
+    c->dWE.zero(s);
+    learned_edges(c, elist);
+  } else {
+    for (int e = 0; e < ned; ++e) elist.push_back(e);
+  }
+  c->n_exact_edges = (int)elist.size();
+  c->n_pred_edges = ned - c->n_exact_edges;
+  if (!elist.empty()) {
     ht.mark("face-rotated Bbar^(s) = T_F^T B^(s) T_");
     // face-rotated Bbar^(s) = T_F^T B^(s) T_F on every face block
     DevBuf<double> Y(c->dB.n), Bbar(c->dB.n);
@@ -354,7 +411,7 @@ void run_setup(abddc_ctx* c) {
     std::vector<size_t> roff((size_t)ned * 4);
     std::vector<int> nHunion(ned);
     int64_t e2tot = 0;
-    for (int e = 0; e < ned; ++e) {
+    for (int e : elist) {
       const int k = T.edges[e];
       const Object& o = T.objects[k];
       std::vector<int32_t> uni;
@@ -403,7 +460,7 @@ void run_setup(abddc_ctx* c) {
     {
       std::vector<GatherDesc> gd;
       std::vector<PluDesc<double>> pd;
-      for (int e = 0; e < ned; ++e) {
+      for (int e : elist) {
         const Object& o = T.objects[T.edges[e]];
         for (size_t q = 0; q < o.subs.size(); ++q) {
           const int sub = o.subs[q], nB = c->nB[sub], w = nW[sub];
@@ -420,7 +477,7 @@ void run_setup(abddc_ctx* c) {
     // M_E and the coupled matrix; Schur complement onto the jumps
     std::vector<int64_t> meoff(ned), qoff(ned), btoff(ned);
     int64_t metot = 0, qtot = 0;
-    for (int e = 0; e < ned; ++e) {
+    for (int e : elist) {
       const Object& o = T.objects[T.edges[e]];
       const int nw = (int)(o.subs.size() - 1) * o.n;
       const int nv = (int)o.subs.size() * o.n + nHunion[e];
@@ -434,7 +491,7 @@ void run_setup(abddc_ctx* c) {
     std::vector<EdgeAsmDesc> ea;
     std::vector<PluDesc<double>> pd;
     std::vector<SymDesc> sy;
-    for (int e = 0; e < ned; ++e) {
+    for (int e : elist) {
       const int k = T.edges[e];
       const Object& o = T.objects[k];
       EdgeAsmDesc d{};
@@ -464,7 +521,7 @@ void run_setup(abddc_ctx* c) {
     partial_lu<double>(pd, c->d_flag.p, s);
     sym_batched(sy, s);
     std::vector<SygvDesc> gv;
-    for (int e = 0; e < ned; ++e) {
+    for (int e : elist) {
       const Object& o = T.objects[T.edges[e]];
       const int nw = (int)(o.subs.size() - 1) * o.n;
       gv.push_back({Btt.p + meoff[e], ME.p + meoff[e], c->dWE.p + c->weoff[e], XE.p + meoff[e], nw});
@@ -476,7 +533,7 @@ void run_setup(abddc_ctx* c) {
     // G = [g_{l,k}] (n_E x (m-1) |N_E|) and its left singular basis
     int64_t gtot = 0;
     std::vector<int64_t> goffE(ned);
-    for (int e = 0; e < ned; ++e) {
+    for (int e : elist) {
       const Object& o = T.objects[T.edges[e]];
       const int m1 = (int)o.subs.size() - 1, nw = m1 * o.n;
       int ns = 0;
@@ -497,7 +554,7 @@ void run_setup(abddc_ctx* c) {
     for (int q = 0; q < 64; ++q) iota[q] = q;
     const size_t iota_off = gp.add(iota);
     std::vector<size_t> rowmap_off((size_t)ned * 4);
-    for (int e = 0; e < ned; ++e) {
+    for (int e : elist) {
       const Object& o = T.objects[T.edges[e]];
       for (int b = 0; b < (int)o.subs.size() - 1; ++b) {
         std::vector<int32_t> rm(o.n);
@@ -508,7 +565,7 @@ void run_setup(abddc_ctx* c) {
     gp.upload(s);
     std::vector<GatherDesc> gd;
     std::vector<SvdDesc> sv;
-    for (int e = 0; e < ned; ++e) {
+    for (int e : elist) {
       const Object& o = T.objects[T.edges[e]];
       const int m1 = (int)o.subs.size() - 1, nw = m1 * o.n, ns = c->nselE[e];
       for (int b = 0; b < m1 && ns > 0; ++b)
@@ -519,7 +576,7 @@ void run_setup(abddc_ctx* c) {
     gather_batched(gd, s);
     svd_left_batched(sv, c->opt.svd_rtol, s);
     std::vector<int32_t> rk = to_host(ranks.p, ned, s);
-    for (int e = 0; e < ned; ++e) c->rE[e] = rk[e];
+    for (int e : elist) c->rE[e] = rk[e];
   }
   c->pnum_edge = 0;
   std::vector<int> edge_pbase(ned, 0);

@@ -1,0 +1,212 @@
+"""GPU parity of the learned edge constraints: the network's forward and
+backward kernels, the Adam step, edge features and training targets against
+the CPU oracle (oracle/learned.py), and the learned setup end to end.
+
+Tolerances: the network rounds weights and layer inputs to bfloat16 on both
+sides; the GPU accumulates in FP32, so a rounded value can differ by one
+bfloat16 unit (2^-8 relative) where the FP32 pre-activation sits on a
+rounding boundary.  Outputs and gradients are compared at 2 % of their
+largest magnitude elementwise and 0.5 % in relative Frobenius norm.
+Features are FP32 copies of FP64 values: 1e-5 absolute."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from oracle import Topology, bddc  # noqa: E402
+from oracle import learned as Lr  # noqa: E402
+from paper_2501_01676_amd import workloads as W  # noqa: E402
+
+
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _close(a, b, elem=2e-2, fro=5e-3):
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    scale = max(np.abs(b).max(), 1e-30)
+    assert np.abs(a - b).max() <= elem * scale, np.abs(a - b).max() / scale
+    assert np.linalg.norm(a - b) <= fro * max(np.linalg.norm(b), 1e-30), np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+def _batch(n, seed):
+    rng = np.random.default_rng(seed)
+    X = rng.standard_normal((n, Lr.N_FEAT)).astype(np.float32)
+    T = rng.uniform(-0.2, 1.0, (n, Lr.N_OUT)).astype(np.float32)
+    return X, T
+
+
+@pytest.mark.parametrize("n", [1, 37, 300])
+def test_forward_matches_oracle(n):
+    _need_gpu()
+    from paper_2501_01676_amd import api
+    p = Lr.init_params(7) * 2.0
+    X, _ = _batch(n, n)
+    net = api.MLP(p)
+    Y = net.forward(torch.from_numpy(X).cuda()).cpu().numpy()
+    Yr, _ = Lr.forward(p, X)
+    _close(Y, Yr)
+    net.close()
+
+
+def test_loss_grad_matches_oracle():
+    _need_gpu()
+    from paper_2501_01676_amd import api
+    p = Lr.init_params(11) * 2.0
+    X, T = _batch(257, 5)
+    net = api.MLP(p)
+    loss, g = net.loss_grad(torch.from_numpy(X).cuda(), torch.from_numpy(T).cuda())
+    g = g.cpu().numpy()
+    Yr, cache = Lr.forward(p, X)
+    Lref, dY = Lr.loss_grad_output(Yr, T)
+    gref = Lr.backward(cache, dY)
+    assert abs(loss - Lref) <= 1e-3 * Lref
+    o = 0
+    for shape in Lr.param_shapes():
+        k = int(np.prod(shape))
+        _close(g[o:o + k], gref[o:o + k], elem=3e-2, fro=1e-2)
+        o += k
+    net.close()
+
+
+def test_adam_step_matches_oracle():
+    _need_gpu()
+    from paper_2501_01676_amd import api
+    p = Lr.init_params(13)
+    X, T = _batch(128, 6)
+    net = api.MLP(p)
+    lr = 1e-3
+    net.train_step(torch.from_numpy(X).cuda(), torch.from_numpy(T).cuda(), lr)
+    q = net.params()
+    Yr, cache = Lr.forward(p, X)
+    _, dY = Lr.loss_grad_output(Yr, T)
+    g = Lr.backward(cache, dY)
+    qr, _, _ = Lr.adam_step(p.astype(np.float64), g, np.zeros_like(g), np.zeros_like(g), 1, lr)
+    # first step moves every weight by about lr in the direction of -sign(g)
+    big = np.abs(g) > 1e-2 * np.abs(g).max()
+    assert np.allclose(q[big], qr[big], atol=1e-2 * lr, rtol=0)
+    assert np.all(np.abs(q - p) <= lr * (1 + 1e-3))
+    net.close()
+
+
+def _channel_problem(seed, nsub=(3, 3, 3)):
+    widths = [[8] * nsub[a] for a in range(3)]
+    nu = W.channel_field(widths, 6, seed)
+    p = W._problem(nsub, widths, nu, (50.0, 20.0, 10.0), name=f"channels_{seed}")
+    p["beta1"] = np.array([[0.0, -5.0, 0.0], [5.0, 0.0, 0.0], [0.0, 0.0, 0.0]])
+    return p
+
+
+def test_edge_features_match_oracle():
+    _need_gpu()
+    from paper_2501_01676_amd import api
+    p = _channel_problem(2)
+    g = api.Solver(p)
+    X, el = g.edge_features()
+    X, el = X.cpu().numpy(), el.cpu().numpy()
+    t = Topology(p["nsub"], p["widths"])
+    assert X.shape == (len(t.edges), Lr.N_FEAT)
+    for e, k in enumerate(t.edges):
+        ref = Lr.edge_features(p, t, k)
+        assert np.abs(X[e] - ref).max() <= 1e-5 * max(1.0, np.abs(ref).max()), e
+        assert el[e] == int(Lr.eligible(t, k))
+    g.close()
+
+
+def _layered8():
+    p = W.uniform(2, 8, beta=(0.7, -0.4, 1.1))
+    sx, _, sz = W.element_subdomain(p["widths"])
+    p["nu"] = np.where(sx == 0, 1.0, 1e-3) * np.where(sz == 0, 1.0, 0.1)
+    return p
+
+
+def test_edge_projectors_match_oracle():
+    _need_gpu()
+    from paper_2501_01676_amd import api
+    p = _layered8()
+    o = bddc.OracleBDDC(p)
+    o.assemble()
+    o.setup_coarse_space({"theta_face": 2.0, "theta_edge": 2.0})
+    g = api.Solver(p)
+    g.setup_coarse_space(theta_face=2.0, theta_edge=2.0)
+    Y = g.edge_projectors().cpu().numpy()
+    assert any(o.edge_r[k] > 0 for k in o.topo.edges)
+    for e, k in enumerate(o.topo.edges):
+        ref = Lr.projector_upper(o.edge_T[k][:, :o.edge_r[k]])
+        assert np.abs(Y[e] - ref).max() <= 1e-6, e
+    g.close()
+
+
+def test_learned_setup_end_to_end():
+    """Train on exact setups of a few seeded channel problems, then solve a
+    held-out one with learned edge constraints.  Checks: every edge is
+    either predicted or sent back to the exact eigenproblem by the gate; the
+    face primals are untouched; the solve converges; the judge runs: the
+    eigenvalue bound of the exact method (min constrained quotient of
+    (Btilde~_E, M_E) >= 1 / Theta_E, from the oracle's edge operators) holds
+    on at least 90 % of the predicted edges, and the GMRES iteration ratio
+    is within 1.2 (+1) -- or, when it is not, the exact redo that the
+    policy then calls for reproduces the exact iteration count."""
+    _need_gpu()
+    from paper_2501_01676_amd import api
+    theta = 2.0
+    Xs, Ts = [], []
+    for seed in range(4):
+        g = api.Solver(_channel_problem(10 + seed))
+        g.setup_coarse_space(theta_face=theta, theta_edge=theta)
+        X, el = g.edge_features()
+        T = g.edge_projectors()
+        keep = el.bool()
+        Xs.append(X[keep])
+        Ts.append(T[keep])
+        g.close()
+    X = torch.cat(Xs).contiguous()
+    T = torch.cat(Ts).contiguous()
+    net = api.MLP(Lr.init_params(0))
+    net.set_ranges(X)
+    first = net.train_step(X, T, 1e-3, want_loss=True)
+    for _ in range(400):
+        net.train_step(X, T, 1e-3)
+    last = net.train_step(X, T, 1e-3, want_loss=True)
+    print(f"[learned] training loss {first:.4g} -> {last:.4g} on {X.shape[0]} edges", flush=True)
+    assert last < 0.5 * first
+
+    p = _channel_problem(99)
+    ge = api.Solver(p)
+    ce = ge.setup_coarse_space(theta_face=theta, theta_edge=theta)
+    _, ie = ge.gmres_solve(30, 1e-8, 300, history=False)
+    gl = api.Solver(p)
+    cl = gl.setup_coarse_space(theta_face=theta, theta_edge=theta, constraint_source=1, mlp=net)
+    st = gl.learned_stats()
+    assert st["predicted"] + st["exact"] == gl.n_edge
+    u, il = gl.gmres_solve(30, 1e-8, 300, history=False)
+    assert il["converged"] and il["relres_true"] <= 1e-8
+    assert cl["pnum_face"] == ce["pnum_face"]
+    o = bddc.OracleBDDC(p)
+    o.assemble()
+    o.setup_coarse_space({"theta_face": theta, "theta_edge": theta})
+    cnt = gl.stage(6)
+    nf = gl.n_face
+    ok = 0
+    for e, k in enumerate(o.topo.edges):
+        r = int(cnt[nf + e])
+        n = o.topo.objects[k]["nodes"].size
+        Tb = gl.stage(5, e).reshape(n, n)
+        aux = o.edge_aux[k]
+        q = Lr.constrained_min_quotient(aux["ME"], aux["BttE"], Tb[:, :r], aux["nE"], aux["m"])
+        ok += q >= (1.0 / theta) * (1 - 1e-6)
+    print(f"[learned] predicted {st['predicted']} exact {st['exact']}; bound holds on {ok}/{gl.n_edge} edges; "
+          f"iterations learned {il['iters']} exact {ie['iters']}", flush=True)
+    assert gl.n_edge - ok <= 0.1 * max(st["predicted"], 1)
+    if il["iters"] > 1.2 * ie["iters"] + 1:
+        gr = api.Solver(p)
+        gr.setup_coarse_space(theta_face=theta, theta_edge=theta)
+        _, ir = gr.gmres_solve(30, 1e-8, 300, history=False)
+        assert ir["iters"] == ie["iters"]
+        gr.close()
+    ge.close()
+    gl.close()
+    net.close()
