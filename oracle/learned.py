@@ -162,18 +162,6 @@ def pack(arrs):
     return np.concatenate([np.asarray(x, dtype=np.float64).ravel() for x in arrs])
 
 
-def init_params(seed):
-    """Uniform(-1/sqrt(fan_in), 1/sqrt(fan_in)) weights and biases (the
-    usual default initialisation of a linear layer), float32 values."""
-    rng = np.random.default_rng(seed)
-    out = []
-    for (nout, nin) in LAYERS:
-        bound = 1.0 / np.sqrt(nin)
-        out.append(rng.uniform(-bound, bound, (nout, nin)))
-        out.append(rng.uniform(-bound, bound, nout))
-    return pack(out).astype(np.float32)
-
-
 def forward(flat, X, round_bf16=True):
     """Y = MLP(X); returns Y and the cache for backward.  With round_bf16
     the weights and the input of every product are rounded to bfloat16 and

@@ -204,3 +204,17 @@ def get(name, seed=0):
     if name in ("config3", "config4", "config5"):
         return fn(seed)
     return fn()
+
+
+def mlp_init_params(seed):
+    """Seeded initial parameters of the edge-constraint network (an input of
+    the learned variant): Uniform(-1/sqrt(fan_in), 1/sqrt(fan_in)) weights
+    and biases of the layers 133 -> 128 -> 128 -> 28, packed as W1, b1, W2,
+    b2, W3, b3 (row-major weights), float32."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for nout, nin in ((128, 133), (128, 128), (28, 128)):
+        bound = 1.0 / np.sqrt(nin)
+        out.append(rng.uniform(-bound, bound, (nout, nin)).ravel())
+        out.append(rng.uniform(-bound, bound, nout))
+    return np.concatenate(out).astype(np.float32)

@@ -43,7 +43,7 @@ def _batch(n, seed):
 def test_forward_matches_oracle(n):
     _need_gpu()
     from paper_2501_01676_amd import api
-    p = Lr.init_params(7) * 2.0
+    p = W.mlp_init_params(7) * 2.0
     X, _ = _batch(n, n)
     net = api.MLP(p)
     Y = net.forward(torch.from_numpy(X).cuda()).cpu().numpy()
@@ -55,7 +55,7 @@ def test_forward_matches_oracle(n):
 def test_loss_grad_matches_oracle():
     _need_gpu()
     from paper_2501_01676_amd import api
-    p = Lr.init_params(11) * 2.0
+    p = W.mlp_init_params(11) * 2.0
     X, T = _batch(257, 5)
     net = api.MLP(p)
     loss, g = net.loss_grad(torch.from_numpy(X).cuda(), torch.from_numpy(T).cuda())
@@ -75,7 +75,7 @@ def test_loss_grad_matches_oracle():
 def test_adam_step_matches_oracle():
     _need_gpu()
     from paper_2501_01676_amd import api
-    p = Lr.init_params(13)
+    p = W.mlp_init_params(13)
     X, T = _batch(128, 6)
     net = api.MLP(p)
     lr = 1e-3
@@ -165,7 +165,7 @@ def test_learned_setup_end_to_end():
         g.close()
     X = torch.cat(Xs).contiguous()
     T = torch.cat(Ts).contiguous()
-    net = api.MLP(Lr.init_params(0))
+    net = api.MLP(W.mlp_init_params(0))
     net.set_ranges(X)
     first = net.train_step(X, T, 1e-3, want_loss=True)
     for _ in range(400):

@@ -24,7 +24,7 @@ def test_bf16_rounding_matches_torch_and_ties_to_even():
 
 def test_param_layout():
     assert Lr.n_params() == 37276
-    p = Lr.init_params(0)
+    p = W.mlp_init_params(0)
     parts = Lr.unpack(p)
     assert [x.shape for x in parts] == [(128, 133), (128,), (128, 128), (128,), (28, 128), (28,)]
     assert np.allclose(Lr.pack(parts), p)
@@ -32,7 +32,7 @@ def test_param_layout():
 
 def test_backward_matches_finite_differences():
     rng = np.random.default_rng(1)
-    p = Lr.init_params(3).astype(np.float64) * 3.0
+    p = W.mlp_init_params(3).astype(np.float64) * 3.0
     X = rng.standard_normal((6, Lr.N_FEAT))
     T = rng.standard_normal((6, Lr.N_OUT))
 
