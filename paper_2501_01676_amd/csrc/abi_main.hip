@@ -2,6 +2,8 @@
 // gmres_solve and the query / parity hooks (include/abddc.h).
 #include <hip/hip_runtime.h>
 
+#include <cstdlib>
+
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -34,8 +36,7 @@ void record(abddc_ctx* c, int i) {
 }
 
 // z = M^{-1} r (device vectors of length n_gamma)
-void apply_bddc_dev(abddc_ctx* c, const double* r, double* z) {
-  hipStream_t s = c->stream;
+void apply_bddc_dev(abddc_ctx* c, const double* r, double* z, hipStream_t s) {
   const int np = c->n_primal;
   const bool mixed = c->dM32.p != nullptr;
   if (mixed)
@@ -59,11 +60,75 @@ void apply_bddc_dev(abddc_ctx* c, const double* r, double* z) {
 }
 
 // y = Shat x
-void apply_schur_dev(abddc_ctx* c, const double* x, double* y) {
-  hipStream_t s = c->stream;
+void apply_schur_dev(abddc_ctx* c, const double* x, double* y, hipStream_t s) {
   launch_gemv<double>(c->blk_S.p, c->nblk_S, c->gemv_S.p, c->maxc_S, c->dS.p, x, c->d_gam.p, c->d_wS.p, false, s,
                       c->bytes_S);
   launch_gather_sum(c->d_own_ptr.p, c->d_own_idx.p, c->d_wS.p, y, c->topo.n_gamma, s);
+}
+
+// One Arnoldi step of right-preconditioned FGMRES on stream s, every kernel
+// taking the step index from the device state: z_j = M^{-1} v_j, Z[:, j] =
+// z_j, w = Shat z_j, two classical Gram-Schmidt passes over V[:, 0..j], the
+// norm, the Hessenberg column with Givens rotations, and v_{j+1} = w / h.
+void arnoldi_step(abddc_ctx* c, int restart, hipStream_t s) {
+  const int64_t n = c->topo.n_gamma;
+  const size_t nn = (size_t)std::max<int64_t>(n, 1);
+  GmresState* st = c->d_gst.p;
+  apply_bddc_dev(c, c->d_vcur.p, c->d_zcur.p, s);
+  launch_store_col(c->d_zcur.p, c->d_Z.p, nn, st, n, s);
+  apply_schur_dev(c, c->d_zcur.p, c->d_w.p, s);
+  launch_dots_dev(c->d_V.p, nn, st, restart, c->d_w.p, n, c->d_partial.p, c->d_h1.p, s);
+  launch_axpy_multi_dev(c->d_V.p, nn, st, c->d_h1.p, -1.0, c->d_w.p, n, s);
+  launch_dots_dev(c->d_V.p, nn, st, restart, c->d_w.p, n, c->d_partial.p, c->d_h2.p, s);
+  launch_axpy_multi_dev(c->d_V.p, nn, st, c->d_h2.p, -1.0, c->d_w.p, n, s);
+  launch_dots(c->d_w.p, n, 1, c->d_w.p, n, c->d_partial.p, c->d_nrm.p, s);
+  launch_arnoldi_finish_dev(st, c->d_h1.p, c->d_h2.p, c->d_nrm.p, s);
+  launch_scale_to_col(c->d_w.p, st, c->d_V.p, nn, c->d_vcur.p, n, s);
+}
+
+// The Arnoldi step captured once per context (and restart length) into a
+// HIP graph on a private capture stream; replays go to the context stream.
+// Returns false (and the caller launches eagerly) when capture fails.
+bool ensure_step_graph(abddc_ctx* c, int restart) {
+  if (c->step_exec && c->step_restart == restart) return true;
+  if (c->graph_failed) return false;
+  if (c->step_exec) {
+    (void)hipGraphExecDestroy(c->step_exec);
+    (void)hipGraphDestroy(c->step_graph);
+    c->step_exec = nullptr;
+    c->step_graph = nullptr;
+  }
+  if (!c->cap_stream) ABDDC_HIP(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+  KStatsScope none(nullptr);   // no timing events inside the graph
+  if (hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+    (void)hipGetLastError();
+    c->graph_failed = true;
+    return false;
+  }
+  bool ok = true;
+  try {
+    arnoldi_step(c, restart, c->cap_stream);
+  } catch (const Error&) {
+    ok = false;
+  }
+  hipGraph_t g = nullptr;
+  if (hipStreamEndCapture(c->cap_stream, &g) != hipSuccess || !ok || !g) {
+    (void)hipGetLastError();
+    if (g) (void)hipGraphDestroy(g);
+    c->graph_failed = true;
+    return false;
+  }
+  hipGraphExec_t e = nullptr;
+  if (hipGraphInstantiate(&e, g, nullptr, nullptr, 0) != hipSuccess) {
+    (void)hipGetLastError();
+    (void)hipGraphDestroy(g);
+    c->graph_failed = true;
+    return false;
+  }
+  c->step_graph = g;
+  c->step_exec = e;
+  c->step_restart = restart;
+  return true;
 }
 
 }  // namespace
@@ -307,6 +372,14 @@ extern "C" int abddc_setup_coarse_space(abddc_ctx* c, const abddc_options* opts,
     c->opt = o;
     c->n_ties = 0;
     c->state = 1;
+    if (c->step_exec) {   // the captured Arnoldi step points at the previous setup's buffers
+      ABDDC_HIP(hipStreamSynchronize(c->stream));
+      (void)hipGraphExecDestroy(c->step_exec);
+      (void)hipGraphDestroy(c->step_graph);
+      c->step_exec = nullptr;
+      c->step_graph = nullptr;
+      c->step_restart = 0;
+    }
     run_setup(c);
     c->kstats.resolve();
     c->phase[2] = ev_ms(c, 2, 3);
@@ -325,7 +398,7 @@ extern "C" int abddc_apply_bddc(abddc_ctx* c, const double* r, double* z) {
     ABDDC_REQUIRE(c && r && z, ABDDC_EINVAL, "null argument");
     ABDDC_REQUIRE(c->state >= 2, ABDDC_ESTATE, "apply before setup");
     KStatsScope ks(&c->kstats);
-    apply_bddc_dev(c, r, z);
+    apply_bddc_dev(c, r, z, c->stream);
     return ABDDC_OK;
   });
 }
@@ -335,7 +408,7 @@ extern "C" int abddc_apply_schur(abddc_ctx* c, const double* x, double* y) {
     ABDDC_REQUIRE(c && x && y, ABDDC_EINVAL, "null argument");
     ABDDC_REQUIRE(c->state >= 1, ABDDC_ESTATE, "apply before assemble");
     KStatsScope ks(&c->kstats);
-    apply_schur_dev(c, x, y);
+    apply_schur_dev(c, x, y, c->stream);
     return ABDDC_OK;
   });
 }
@@ -371,6 +444,8 @@ extern "C" int abddc_gmres_solve(abddc_ctx* c, int32_t restart, double rtol, int
     }
     if (!c->d_w.p) {
       c->d_w.alloc(nn);
+      c->d_vcur.alloc(nn);
+      c->d_zcur.alloc(nn);
       c->d_r.alloc(nn);
       c->d_x.alloc(nn);
       c->d_h1.alloc(GMRES_MAXR + 1);
@@ -401,33 +476,30 @@ extern "C" int abddc_gmres_solve(abddc_ctx* c, int32_t restart, double rtol, int
       read_scalars();
       const double bnorm = c->h_gst->beta;
       if (bnorm == 0.0) converged = true;
+      const char* genv = std::getenv("ABDDC_GRAPH");
+      const bool use_graph = !(genv && genv[0] == '0');
+      bool eager_done = false;   // one eager step per call keeps the live kernel statistics
       while (!converged) {
-        // cycle start: V[0] = r / ||r|| (r and its norm already in place)
-        launch_scale_copy(c->d_r.p, &c->d_gst.p->inv_hn, V, n, s);
+        // cycle start: V[0] = v_cur = r / ||r|| (r, its norm and j = 0 in place)
+        launch_scale_to_col(c->d_r.p, c->d_gst.p, V, nn, c->d_vcur.p, n, s);
         int jend = 0;
         for (int j = 0; j < restart; ++j) {
-          double* vj = V + (size_t)j * nn;
-          double* zj = Z + (size_t)j * nn;
-          apply_bddc_dev(c, vj, zj);
-          apply_schur_dev(c, zj, c->d_w.p);
+          if (use_graph && eager_done && ensure_step_graph(c, restart))
+            ABDDC_HIP(hipGraphLaunch(c->step_exec, s));
+          else
+            arnoldi_step(c, restart, s);
+          eager_done = true;
           ++iters;
-          launch_dots(V, nn, j + 1, c->d_w.p, n, c->d_partial.p, c->d_h1.p, s);
-          launch_axpy_multi(V, nn, j + 1, c->d_h1.p, -1.0, c->d_w.p, n, s);
-          launch_dots(V, nn, j + 1, c->d_w.p, n, c->d_partial.p, c->d_h2.p, s);
-          launch_axpy_multi(V, nn, j + 1, c->d_h2.p, -1.0, c->d_w.p, n, s);
-          launch_dots(c->d_w.p, n, 1, c->d_w.p, n, c->d_partial.p, c->d_nrm.p, s);
-          launch_arnoldi_finish(c->d_gst.p, j, c->d_h1.p, c->d_h2.p, c->d_nrm.p, s);
           read_scalars();
           const double res = c->h_gst->res;
           if (info && info->resid_history && iters <= info->resid_cap) info->resid_history[iters - 1] = res / bnorm;
           jend = j + 1;
           if (c->h_gst->hn == 0.0 || res <= rtol * bnorm || iters >= maxit) break;
-          launch_scale_copy(c->d_w.p, &c->d_gst.p->inv_hn, V + (size_t)(j + 1) * nn, n, s);
         }
         launch_gmres_trisolve(c->d_gst.p, jend, s);
         launch_axpy_multi(Z, nn, jend, c->d_gst.p->y, 1.0, c->d_x.p, n, s);
         // true residual
-        apply_schur_dev(c, c->d_x.p, c->d_w.p);
+        apply_schur_dev(c, c->d_x.p, c->d_w.p, s);
         launch_sub(c->d_ghat.p, c->d_w.p, c->d_r.p, n, s);
         launch_dots(c->d_r.p, n, 1, c->d_r.p, n, c->d_partial.p, c->d_nrm.p, s);
         launch_gmres_start(c->d_gst.p, c->d_nrm.p, s);
@@ -572,6 +644,9 @@ extern "C" void abddc_destroy(abddc_ctx* c) {
   StreamScope ss(c->stream);
   (void)hipStreamSynchronize(c->stream);
   if (c->h_gst) (void)hipHostFree(c->h_gst);
+  if (c->step_exec) (void)hipGraphExecDestroy(c->step_exec);
+  if (c->step_graph) (void)hipGraphDestroy(c->step_graph);
+  if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   for (int i = 0; i < 20; ++i)
     if (c->ev[i]) (void)hipEventDestroy(c->ev[i]);
   delete c;

@@ -32,6 +32,8 @@ struct GmresState {
   double g[GMRES_MAXR + 1];
   double y[GMRES_MAXR];
   double beta, hn, inv_hn, res;
+  int32_t j;   // Arnoldi step inside the cycle (kernels of one step read it)
+  int32_t pad;
 };
 
 template <class TM>
@@ -44,6 +46,21 @@ void launch_dots(const double* V, int64_t ldv, int nv, const double* w, int64_t 
                  hipStream_t s);
 void launch_axpy_multi(const double* V, int64_t ldv, int nv, const double* coef, double sign, double* w, int64_t n,
                        hipStream_t s);
+// The same with the vector count j + 1 read from st->j on the device (the
+// kernels of one Arnoldi step are then independent of j, so the step can be
+// captured once in a HIP graph and replayed).  max_nv bounds j + 1.
+void launch_dots_dev(const double* V, int64_t ldv, const GmresState* st, int max_nv, const double* w, int64_t n,
+                     double* partial, double* out, hipStream_t s);
+void launch_axpy_multi_dev(const double* V, int64_t ldv, const GmresState* st, const double* coef, double sign,
+                           double* w, int64_t n, hipStream_t s);
+// Z[:, st->j] = src
+void launch_store_col(const double* src, double* Z, int64_t ldz, const GmresState* st, int64_t n, hipStream_t s);
+// V[:, st->j] = cur = src * st->inv_hn
+void launch_scale_to_col(const double* src, const GmresState* st, double* V, int64_t ldv, double* cur, int64_t n,
+                         hipStream_t s);
+// Hessenberg column st->j (as launch_arnoldi_finish), then st->j += 1
+void launch_arnoldi_finish_dev(GmresState* st, const double* h1, const double* h2, const double* nrm2,
+                               hipStream_t s);
 void launch_arnoldi_finish(GmresState* st, int j, const double* h1, const double* h2, const double* nrm2,
                            hipStream_t s);
 void launch_gmres_trisolve(GmresState* st, int m, hipStream_t s);

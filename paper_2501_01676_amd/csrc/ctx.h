@@ -75,6 +75,12 @@ struct abddc_ctx {
   abddc::DevBuf<abddc::GmresState> d_gst;
   abddc::GmresState* h_gst = nullptr;               // pinned mirror of the scalars
   int gm_restart = 0;
+  abddc::DevBuf<double> d_vcur, d_zcur;             // current Arnoldi vector and its preconditioned image
+  hipStream_t cap_stream = nullptr;                 // private stream for graph capture
+  hipGraph_t step_graph = nullptr;                  // one captured Arnoldi step
+  hipGraphExec_t step_exec = nullptr;
+  int step_restart = 0;
+  bool graph_failed = false;
 
   // ------------------------------------------------- learned constraints
   std::vector<abddc::EdgeGeom> egeom;               // per edge (kind order)

@@ -79,9 +79,11 @@ __global__ void gather_sum_kernel(const int32_t* __restrict__ ptr, const int32_t
 
 // partial[b * DOT_STRIDE + j] = sum over block b's chunk of V[j][i] w[i]
 __global__ void __launch_bounds__(256) dots_partial_kernel(const double* __restrict__ V, int64_t ldv, int nv,
+                                                           const GmresState* __restrict__ st,
                                                            const double* __restrict__ w, int64_t n,
                                                            double* __restrict__ partial) {
   __shared__ double red[4];
+  if (st) nv = st->j + 1;
   const int64_t chunk = (n + gridDim.x - 1) / gridDim.x;
   const int64_t lo = blockIdx.x * chunk, hi = min(n, lo + chunk);
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -99,9 +101,11 @@ __global__ void __launch_bounds__(256) dots_partial_kernel(const double* __restr
 
 // one workgroup per vector j: fixed-order tree over the block partials
 __global__ void __launch_bounds__(256) dots_final_kernel(const double* __restrict__ partial, int nblk,
+                                                         const GmresState* __restrict__ st,
                                                          double* __restrict__ out) {
   __shared__ double red[4];
   const int j = blockIdx.x;
+  if (st && j > st->j) return;
   double s = 0.0;
   for (int b = threadIdx.x; b < nblk; b += blockDim.x) s += partial[b * DOT_STRIDE + j];
   s = wave_sum(s);
@@ -111,10 +115,12 @@ __global__ void __launch_bounds__(256) dots_final_kernel(const double* __restric
 }
 
 // w[i] += sign * sum_j coef[j] V[j][i]
-__global__ void axpy_multi_kernel(const double* __restrict__ V, int64_t ldv, int nv, const double* __restrict__ coef,
+__global__ void axpy_multi_kernel(const double* __restrict__ V, int64_t ldv, int nv,
+                                  const GmresState* __restrict__ st, const double* __restrict__ coef,
                                   double sign, double* __restrict__ w, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
+  if (st) nv = st->j + 1;
   double s = 0.0;
   for (int j = 0; j < nv; ++j) s += coef[j] * V[(int64_t)j * ldv + i];
   w[i] += sign * s;
@@ -126,6 +132,8 @@ __global__ void axpy_multi_kernel(const double* __restrict__ V, int64_t ldv, int
 __global__ void arnoldi_finish_kernel(GmresState* st, int j, const double* __restrict__ h1,
                                       const double* __restrict__ h2, const double* __restrict__ nrm2) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const bool dev_j = j < 0;
+  if (dev_j) j = st->j;
   double col[GMRES_MAXR + 1];
   for (int i = 0; i <= j; ++i) col[i] = h1[i] + h2[i];
   const double hn = sqrt(fmax(nrm2[0], 0.0));
@@ -152,6 +160,7 @@ __global__ void arnoldi_finish_kernel(GmresState* st, int j, const double* __res
   st->hn = hn;
   st->inv_hn = hn > 0.0 ? 1.0 / hn : 0.0;
   st->res = fabs(st->g[j + 1]);
+  if (dev_j) st->j = j + 1;
 }
 
 // y = H(0:m, 0:m)^{-1} g(0:m) (upper triangular)
@@ -172,6 +181,22 @@ __global__ void gmres_start_kernel(GmresState* st, const double* __restrict__ nr
   st->beta = b;
   st->inv_hn = b > 0.0 ? 1.0 / b : 0.0;
   st->res = b;
+  st->j = 0;
+}
+
+__global__ void store_col_kernel(const double* __restrict__ src, double* __restrict__ Z, int64_t ldz,
+                                 const GmresState* __restrict__ st, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) Z[(int64_t)st->j * ldz + i] = src[i];
+}
+
+__global__ void scale_to_col_kernel(const double* __restrict__ src, const GmresState* __restrict__ st,
+                                    double* __restrict__ V, int64_t ldv, double* __restrict__ cur, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double v = src[i] * st->inv_hn;
+  V[(int64_t)st->j * ldv + i] = v;
+  cur[i] = v;
 }
 
 __global__ void scale_copy_kernel(const double* __restrict__ src, const double* __restrict__ factor,
@@ -196,8 +221,11 @@ void launch_gemv(const GemvBlock* blocks, int nblk, const GemvMat* mats, int max
   if (nblk == 0) return;
   hipEvent_t ea, eb;
   tracked_events(KC_GEMV, bytes, &ea, &eb);
-  hipExtLaunchKernelGGL(gemv_kernel<TM>, dim3(nblk), dim3(256), (uint32_t)(max_ncols * sizeof(double)), s, ea, eb, 0,
-                        blocks, mats, M, x, xidx, y, accumulate ? 1 : 0);
+  if (ea)
+    hipExtLaunchKernelGGL(gemv_kernel<TM>, dim3(nblk), dim3(256), (uint32_t)(max_ncols * sizeof(double)), s, ea, eb,
+                          0, blocks, mats, M, x, xidx, y, accumulate ? 1 : 0);
+  else
+    gemv_kernel<TM><<<nblk, 256, max_ncols * sizeof(double), s>>>(blocks, mats, M, x, xidx, y, accumulate ? 1 : 0);
   ABDDC_HIP(hipGetLastError());
 }
 template void launch_gemv<double>(const GemvBlock*, int, const GemvMat*, int, const double*, const double*,
@@ -214,14 +242,44 @@ void launch_gather_sum(const int32_t* ptr, const int32_t* idx, const double* src
 
 void launch_dots(const double* V, int64_t ldv, int nv, const double* w, int64_t n, double* partial, double* out,
                  hipStream_t s) {
-  dots_partial_kernel<<<DOT_BLOCKS, 256, 0, s>>>(V, ldv, nv, w, n, partial);
-  dots_final_kernel<<<nv, 256, 0, s>>>(partial, DOT_BLOCKS, out);
+  dots_partial_kernel<<<DOT_BLOCKS, 256, 0, s>>>(V, ldv, nv, nullptr, w, n, partial);
+  dots_final_kernel<<<nv, 256, 0, s>>>(partial, DOT_BLOCKS, nullptr, out);
+  ABDDC_HIP(hipGetLastError());
+}
+
+void launch_dots_dev(const double* V, int64_t ldv, const GmresState* st, int max_nv, const double* w, int64_t n,
+                     double* partial, double* out, hipStream_t s) {
+  dots_partial_kernel<<<DOT_BLOCKS, 256, 0, s>>>(V, ldv, 0, st, w, n, partial);
+  dots_final_kernel<<<max_nv, 256, 0, s>>>(partial, DOT_BLOCKS, st, out);
+  ABDDC_HIP(hipGetLastError());
+}
+
+void launch_axpy_multi_dev(const double* V, int64_t ldv, const GmresState* st, const double* coef, double sign,
+                           double* w, int64_t n, hipStream_t s) {
+  axpy_multi_kernel<<<nblocks(n), 256, 0, s>>>(V, ldv, 0, st, coef, sign, w, n);
+  ABDDC_HIP(hipGetLastError());
+}
+
+void launch_store_col(const double* src, double* Z, int64_t ldz, const GmresState* st, int64_t n, hipStream_t s) {
+  store_col_kernel<<<nblocks(n), 256, 0, s>>>(src, Z, ldz, st, n);
+  ABDDC_HIP(hipGetLastError());
+}
+
+void launch_scale_to_col(const double* src, const GmresState* st, double* V, int64_t ldv, double* cur, int64_t n,
+                         hipStream_t s) {
+  scale_to_col_kernel<<<nblocks(n), 256, 0, s>>>(src, st, V, ldv, cur, n);
+  ABDDC_HIP(hipGetLastError());
+}
+
+void launch_arnoldi_finish_dev(GmresState* st, const double* h1, const double* h2, const double* nrm2,
+                               hipStream_t s) {
+  arnoldi_finish_kernel<<<1, 64, 0, s>>>(st, -1, h1, h2, nrm2);
   ABDDC_HIP(hipGetLastError());
 }
 
 void launch_axpy_multi(const double* V, int64_t ldv, int nv, const double* coef, double sign, double* w, int64_t n,
                        hipStream_t s) {
-  axpy_multi_kernel<<<nblocks(n), 256, 0, s>>>(V, ldv, nv, coef, sign, w, n);
+  axpy_multi_kernel<<<nblocks(n), 256, 0, s>>>(V, ldv, nv, nullptr, coef, sign, w, n);
   ABDDC_HIP(hipGetLastError());
 }
 

@@ -242,3 +242,38 @@ def test_config3_full_size_properties():
         if checked >= 6:
             break
     g.close()
+
+
+def _solve_env(g, graph, **kw):
+    import os
+    old = os.environ.get("ABDDC_GRAPH")
+    os.environ["ABDDC_GRAPH"] = "1" if graph else "0"
+    try:
+        return g.gmres_solve(**kw)
+    finally:
+        if old is None:
+            del os.environ["ABDDC_GRAPH"]
+        else:
+            os.environ["ABDDC_GRAPH"] = old
+
+
+@pytest.mark.parametrize("restart", [30, 5])
+def test_graph_replay_matches_eager(pairs, restart):
+    """The Arnoldi step replayed from its HIP graph (with the solver's own
+    eager work and synchronisations between replays) gives bit-identical
+    residual histories and solutions to the eager launches; restart 5 runs
+    several cycles and re-captures for the new length; a second setup on the
+    same context drops the stale graph."""
+    p, o, g = pairs["config2"]
+    kw = dict(restart=restart, rtol=1e-8, maxit=300)
+    u1, i1 = _solve_env(g, True, **kw)
+    u2, i2 = _solve_env(g, False, **kw)
+    assert i1["iters"] == i2["iters"] and i1["restarts"] == i2["restarts"]
+    assert np.array_equal(i1["history"], i2["history"])
+    assert torch.equal(u1, u2)
+    u3, i3 = _solve_env(g, True, **kw)
+    assert torch.equal(u1, u3)
+    if restart == 5:
+        g.setup_coarse_space(**CASES["config2"][2])
+        u4, i4 = _solve_env(g, True, **kw)
+        assert torch.equal(u1, u4) and np.array_equal(i1["history"], i4["history"])
