@@ -40,29 +40,22 @@ void apply_bddc_dev(abddc_ctx* c, const double* r, double* z, hipStream_t s) {
   const int np = c->n_primal;
   const bool mixed = c->dM32.p != nullptr;
   if (mixed)
-    launch_gemv<float>(c->blk_M.p, c->nblk_M, c->gemv_M.p, c->maxc_M, c->dM32.p, r, c->d_gam.p, c->d_out.p, false, s,
-                       c->bytes_M);
+    gemv_run<float>(c->opM, c->dM32.p, r, c->d_gam.p, c->d_out.p, false, s);
   else
-    launch_gemv<double>(c->blk_M.p, c->nblk_M, c->gemv_M.p, c->maxc_M, c->dM.p, r, c->d_gam.p, c->d_out.p, false, s,
-                        c->bytes_M);
+    gemv_run<double>(c->opM, c->dM.p, r, c->d_gam.p, c->d_out.p, false, s);
   if (np > 0) {
     launch_gather_sum(c->d_pown_ptr.p, c->d_pown_idx.p, c->d_out.p, c->d_bpi.p, np, s);
-    launch_gemv<double>(c->blk_C.p, c->nblk_C, c->gemv_C.p, np, c->dSPinv.p, c->d_bpi.p, nullptr, c->d_xpi.p, false, s,
-                        c->bytes_C);
+    gemv_run<double>(c->opC, c->dSPinv.p, c->d_bpi.p, nullptr, c->d_xpi.p, false, s);
     if (mixed)
-      launch_gemv<float>(c->blk_U.p, c->nblk_U, c->gemv_U.p, c->maxc_U, c->dU32.p, c->d_xpi.p, c->d_pid.p, c->d_out.p,
-                         true, s, c->bytes_U);
+      gemv_run<float>(c->opU, c->dU32.p, c->d_xpi.p, c->d_pid.p, c->d_out.p, true, s);
     else
-      launch_gemv<double>(c->blk_U.p, c->nblk_U, c->gemv_U.p, c->maxc_U, c->dU.p, c->d_xpi.p, c->d_pid.p, c->d_out.p,
-                          true, s, c->bytes_U);
+      gemv_run<double>(c->opU, c->dU.p, c->d_xpi.p, c->d_pid.p, c->d_out.p, true, s);
   }
   launch_gather_sum(c->d_aown_ptr.p, c->d_aown_idx.p, c->d_out.p, z, c->topo.n_gamma, s);
 }
 
-// y = Shat x
 void apply_schur_dev(abddc_ctx* c, const double* x, double* y, hipStream_t s) {
-  launch_gemv<double>(c->blk_S.p, c->nblk_S, c->gemv_S.p, c->maxc_S, c->dS.p, x, c->d_gam.p, c->d_wS.p, false, s,
-                      c->bytes_S);
+  gemv_run<double>(c->opS, c->dS.p, x, c->d_gam.p, c->d_wS.p, false, s);
   launch_gather_sum(c->d_own_ptr.p, c->d_own_idx.p, c->d_wS.p, y, c->topo.n_gamma, s);
 }
 
@@ -315,19 +308,16 @@ extern "C" int abddc_assemble(const abddc_problem* prob, const abddc_device* dev
 
     // Schur operator GEMV metadata
     std::vector<GemvMat> mS;
-    std::vector<GemvBlock> bS;
+    double bytesS = 0.0;   // matrix + gathered input (value and index) + output
     for (int sub = 0; sub < nsub; ++sub) {
       const int nB = c->nB[sub];
       mS.push_back({c->soff[sub], c->goff[sub], c->goff[sub], nB, nB, std::max(nB, 1), 0});
-      for (int r = 0; r < nB; r += GEMV_ROWS_PER_BLOCK) bS.push_back({sub, r});
+      bytesS += (double)nB * nB * 8.0 + nB * 12.0 + nB * 8.0;
     }
-    for (const GemvMat& m : mS) c->bytes_S += (double)m.nrows * m.ncols * 8.0 + m.ncols * 12.0 + m.nrows * 8.0;
-    c->gemv_S = to_device(mS, s);
-    c->blk_S = to_device(bS, s);
-    c->nblk_S = (int)bS.size();
-    c->maxc_S = maxnB;
+    gemv_build(c->opS, mS, nullptr, bytesS, s);
     c->d_wS.alloc(std::max<int64_t>(gt, 1));
     c->d_rec.alloc(std::max<int64_t>(it, 1));
+    gemv_tune<double>(c->opS, "schur", c->device, c->dS.p, c->d_ghat.p, c->d_gam.p, c->d_wS.p, s);
     record(c.get(), 12);
     int h = 0;
     ABDDC_HIP(hipMemcpyAsync(&h, c->d_flag.p, sizeof(int), hipMemcpyDeviceToHost, s));

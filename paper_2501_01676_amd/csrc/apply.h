@@ -4,11 +4,15 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <vector>
+
+#include "internal.h"
 
 namespace abddc {
 
-constexpr int GEMV_ROWS_PER_WAVE = 4;
-constexpr int GEMV_ROWS_PER_BLOCK = 4 * GEMV_ROWS_PER_WAVE;
+// GEMV variants: rows per wave (a workgroup is 4 waves)
+constexpr int GEMV_NVAR = 3;
+constexpr int GEMV_ROWS[GEMV_NVAR] = {2, 4, 8};
 constexpr int DOT_BLOCKS = 256;
 constexpr int DOT_STRIDE = 64;   // partial-sum stride (>= restart + 1 vectors)
 constexpr int GMRES_MAXR = 63;   // maximum restart length
@@ -36,10 +40,33 @@ struct GmresState {
   int32_t pad;
 };
 
+// A batched GEMV operator: its matrices, the workgroup lists of every
+// variant, the variant in use and the algorithmic bytes of one launch.
+struct GemvOp {
+  DevBuf<GemvMat> mats;
+  DevBuf<GemvBlock> blocks[GEMV_NVAR];
+  int nblk[GEMV_NVAR] = {0, 0, 0};
+  int maxc = 1;
+  int var = 1;
+  double bytes = 0.0;
+  int64_t rows = 0;
+};
+
+// Builds the operator; only matrices with active[i] != 0 get workgroups
+// (all when active is null).
+void gemv_build(GemvOp& op, const std::vector<GemvMat>& mats, const std::vector<char>* active, double bytes,
+                hipStream_t s);
+// y (+)= M x (x gathered through xidx when xidx is non-null)
 template <class TM>
-void launch_gemv(const GemvBlock* blocks, int nblk, const GemvMat* mats, int max_ncols, const TM* M,
-                 const double* x, const int32_t* xidx, double* y, bool accumulate, hipStream_t s,
-                 double bytes = 0.0);
+void gemv_run(const GemvOp& op, const TM* M, const double* x, const int32_t* xidx, double* y, bool accumulate,
+              hipStream_t s);
+// Picks the variant: ABDDC_GEMV_VARIANT (0..2) when set, else the cached
+// choice for (architecture, operator name, element type, size buckets),
+// else the fastest of timed launches on the operator's own data (x, y as in
+// gemv_run; y is overwritten), recorded in the autotuner cache.
+template <class TM>
+void gemv_tune(GemvOp& op, const char* name, int device, const TM* M, const double* x, const int32_t* xidx,
+               double* y, hipStream_t s);
 void launch_gather_sum(const int32_t* ptr, const int32_t* idx, const double* src, double* dst, int64_t n,
                        hipStream_t s);
 void launch_dots(const double* V, int64_t ldv, int nv, const double* w, int64_t n, double* partial, double* out,

@@ -60,11 +60,7 @@ struct abddc_ctx {
   abddc::DevBuf<int32_t> d_sown_ptr, d_sown_idx;   // interface dof -> positions in goff space
   abddc::DevBuf<int32_t> d_pown_ptr, d_pown_idx;   // primal id -> positions in ooff space
   abddc::DevBuf<int32_t> d_aown_ptr, d_aown_idx;   // interface dof -> positions in ooff space
-  abddc::DevBuf<abddc::GemvMat> gemv_M, gemv_U, gemv_C, gemv_S;
-  abddc::DevBuf<abddc::GemvBlock> blk_M, blk_U, blk_C, blk_S;
-  int nblk_M = 0, nblk_U = 0, nblk_C = 0, nblk_S = 0;
-  int maxc_M = 1, maxc_U = 1, maxc_S = 1;
-  double bytes_M = 0, bytes_U = 0, bytes_C = 0, bytes_S = 0;   // algorithmic bytes per GEMV launch
+  abddc::GemvOp opM, opU, opC, opS;                // [L; V], U, coarse inverse, Schur
   abddc::KStats kstats;
   abddc::DevBuf<double> d_out, d_wS, d_bpi, d_xpi;  // apply / Schur work vectors
   abddc::DevBuf<abddc::SubAsm> d_subs;

@@ -12,10 +12,13 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
+#include <string>
 
 #include "apply.h"
 #include "internal.h"
 #include "kstats.h"
+#include "tune.h"
 
 namespace abddc {
 
@@ -26,9 +29,10 @@ __device__ inline double wave_sum(double v) {
   return v;
 }
 
-// A workgroup = 4 waves x GEMV_ROWS_PER_WAVE rows of one matrix.  The
-// gathered input vector is staged in LDS once per workgroup.
-template <class TM>
+// A workgroup = 4 waves x R rows of one matrix.  The gathered input vector
+// is staged in LDS once per workgroup; each wave streams its R rows with
+// 64-lane coalesced loads and reduces them with wavefront shuffles.
+template <class TM, int R>
 __global__ void __launch_bounds__(256) gemv_kernel(const GemvBlock* __restrict__ blocks,
                                                    const GemvMat* __restrict__ mats, const TM* __restrict__ M,
                                                    const double* __restrict__ x, const int32_t* __restrict__ xidx,
@@ -40,17 +44,17 @@ __global__ void __launch_bounds__(256) gemv_kernel(const GemvBlock* __restrict__
     xs[c] = xidx ? x[xidx[d.xoff + c]] : x[d.xoff + c];
   __syncthreads();
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int r0 = blk.row0 + w * GEMV_ROWS_PER_WAVE;
-  double acc[GEMV_ROWS_PER_WAVE];
+  const int r0 = blk.row0 + w * R;
+  double acc[R];
 #pragma unroll
-  for (int q = 0; q < GEMV_ROWS_PER_WAVE; ++q) acc[q] = 0.0;
+  for (int q = 0; q < R; ++q) acc[q] = 0.0;
   const TM* base = M + d.moff + (int64_t)r0 * d.ld;
-  const int nr = min(GEMV_ROWS_PER_WAVE, d.nrows - r0);
-  if (nr == GEMV_ROWS_PER_WAVE) {
+  const int nr = min(R, d.nrows - r0);
+  if (nr == R) {
     for (int c = lane; c < d.ncols; c += 64) {
       const double xv = xs[c];
 #pragma unroll
-      for (int q = 0; q < GEMV_ROWS_PER_WAVE; ++q) acc[q] += (double)base[(int64_t)q * d.ld + c] * xv;
+      for (int q = 0; q < R; ++q) acc[q] += (double)base[(int64_t)q * d.ld + c] * xv;
     }
   } else {
     for (int c = lane; c < d.ncols; c += 64) {
@@ -59,7 +63,7 @@ __global__ void __launch_bounds__(256) gemv_kernel(const GemvBlock* __restrict__
     }
   }
 #pragma unroll
-  for (int q = 0; q < GEMV_ROWS_PER_WAVE; ++q) {
+  for (int q = 0; q < R; ++q) {
     const double v = wave_sum(acc[q]);
     if (lane == 0 && q < nr) {
       double* yp = y + d.yoff + r0 + q;
@@ -215,23 +219,108 @@ inline unsigned nblocks(int64_t n) { return (unsigned)std::max<int64_t>(1, (n + 
 
 }  // namespace
 
-template <class TM>
-void launch_gemv(const GemvBlock* blocks, int nblk, const GemvMat* mats, int max_ncols, const TM* M,
-                 const double* x, const int32_t* xidx, double* y, bool accumulate, hipStream_t s, double bytes) {
-  if (nblk == 0) return;
+namespace {
+template <class TM, int R>
+void gemv_launch(const GemvOp& op, int v, const TM* M, const double* x, const int32_t* xidx, double* y,
+                 bool accumulate, hipStream_t s) {
   hipEvent_t ea, eb;
-  tracked_events(KC_GEMV, bytes, &ea, &eb);
+  tracked_events(KC_GEMV, op.bytes, &ea, &eb);
+  const uint32_t lds = (uint32_t)(op.maxc * sizeof(double));
   if (ea)
-    hipExtLaunchKernelGGL(gemv_kernel<TM>, dim3(nblk), dim3(256), (uint32_t)(max_ncols * sizeof(double)), s, ea, eb,
-                          0, blocks, mats, M, x, xidx, y, accumulate ? 1 : 0);
+    hipExtLaunchKernelGGL(gemv_kernel<TM, R>, dim3(op.nblk[v]), dim3(256), lds, s, ea, eb, 0, op.blocks[v].p,
+                          op.mats.p, M, x, xidx, y, accumulate ? 1 : 0);
   else
-    gemv_kernel<TM><<<nblk, 256, max_ncols * sizeof(double), s>>>(blocks, mats, M, x, xidx, y, accumulate ? 1 : 0);
+    gemv_kernel<TM, R><<<op.nblk[v], 256, lds, s>>>(op.blocks[v].p, op.mats.p, M, x, xidx, y, accumulate ? 1 : 0);
+}
+
+template <class TM>
+void gemv_variant(const GemvOp& op, int v, const TM* M, const double* x, const int32_t* xidx, double* y,
+                  bool accumulate, hipStream_t s) {
+  if (op.nblk[v] == 0) return;
+  switch (v) {
+    case 0: gemv_launch<TM, 2>(op, v, M, x, xidx, y, accumulate, s); break;
+    case 1: gemv_launch<TM, 4>(op, v, M, x, xidx, y, accumulate, s); break;
+    default: gemv_launch<TM, 8>(op, v, M, x, xidx, y, accumulate, s); break;
+  }
   ABDDC_HIP(hipGetLastError());
 }
-template void launch_gemv<double>(const GemvBlock*, int, const GemvMat*, int, const double*, const double*,
-                                  const int32_t*, double*, bool, hipStream_t, double);
-template void launch_gemv<float>(const GemvBlock*, int, const GemvMat*, int, const float*, const double*,
-                                 const int32_t*, double*, bool, hipStream_t, double);
+}  // namespace
+
+void gemv_build(GemvOp& op, const std::vector<GemvMat>& mats, const std::vector<char>* active, double bytes,
+                hipStream_t s) {
+  op.maxc = 1;
+  op.rows = 0;
+  for (const GemvMat& m : mats) op.maxc = std::max(op.maxc, (int)m.ncols);
+  for (int v = 0; v < GEMV_NVAR; ++v) {
+    std::vector<GemvBlock> b;
+    const int rpb = 4 * GEMV_ROWS[v];
+    for (size_t i = 0; i < mats.size(); ++i) {
+      if (active && !(*active)[i]) continue;
+      for (int r = 0; r < mats[i].nrows; r += rpb) b.push_back({(int32_t)i, r});
+    }
+    op.blocks[v] = to_device(b, s);
+    op.nblk[v] = (int)b.size();
+  }
+  for (size_t i = 0; i < mats.size(); ++i)
+    if (!active || (*active)[i]) op.rows += mats[i].nrows;
+  op.mats = to_device(mats, s);
+  op.bytes = bytes;
+}
+
+template <class TM>
+void gemv_run(const GemvOp& op, const TM* M, const double* x, const int32_t* xidx, double* y, bool accumulate,
+              hipStream_t s) {
+  gemv_variant<TM>(op, op.var, M, x, xidx, y, accumulate, s);
+}
+
+template <class TM>
+void gemv_tune(GemvOp& op, const char* name, int device, const TM* M, const double* x, const int32_t* xidx,
+               double* y, hipStream_t s) {
+  if (op.nblk[0] == 0) return;
+  const char* force = std::getenv("ABDDC_GEMV_VARIANT");   // fixed variant, no timing (tests, experiments)
+  if (force && *force >= '0' && *force < '0' + GEMV_NVAR && force[1] == 0) {
+    op.var = *force - '0';
+    return;
+  }
+  const std::string key = device_arch(device) + "|gemv|" + name + "|" + (sizeof(TM) == 8 ? "f64" : "f32") + "|c" +
+                          std::to_string(size_bucket(op.maxc)) + "|r" + std::to_string(size_bucket(op.rows));
+  const int cached = tune_lookup(key);
+  if (cached >= 0 && cached < GEMV_NVAR) {
+    op.var = cached;
+    return;
+  }
+  KStatsScope none(nullptr);
+  hipEvent_t e0, e1;
+  ABDDC_HIP(hipEventCreate(&e0));
+  ABDDC_HIP(hipEventCreate(&e1));
+  float best = 0.f;
+  int bestv = 1;
+  for (int v = 0; v < GEMV_NVAR; ++v) {
+    gemv_variant<TM>(op, v, M, x, xidx, y, false, s);   // warm-up
+    ABDDC_HIP(hipEventRecord(e0, s));
+    for (int rep = 0; rep < 3; ++rep) gemv_variant<TM>(op, v, M, x, xidx, y, false, s);
+    ABDDC_HIP(hipEventRecord(e1, s));
+    ABDDC_HIP(hipEventSynchronize(e1));
+    float ms = 0.f;
+    ABDDC_HIP(hipEventElapsedTime(&ms, e0, e1));
+    if (v == 0 || ms < best) {
+      best = ms;
+      bestv = v;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  op.var = bestv;
+  tune_store(key, bestv);
+}
+
+template void gemv_run<double>(const GemvOp&, const double*, const double*, const int32_t*, double*, bool,
+                               hipStream_t);
+template void gemv_run<float>(const GemvOp&, const float*, const double*, const int32_t*, double*, bool, hipStream_t);
+template void gemv_tune<double>(GemvOp&, const char*, int, const double*, const double*, const int32_t*, double*,
+                                hipStream_t);
+template void gemv_tune<float>(GemvOp&, const char*, int, const float*, const double*, const int32_t*, double*,
+                               hipStream_t);
 
 void launch_gather_sum(const int32_t* ptr, const int32_t* idx, const double* src, double* dst, int64_t n,
                        hipStream_t s) {

@@ -851,29 +851,20 @@ void run_setup(abddc_ctx* c) {
     c->d_aown_ptr = to_device(ptr_a, s);
     c->d_aown_idx = to_device(idx_a, s);
     std::vector<GemvMat> mM, mU, mC;
-    std::vector<GemvBlock> bM, bU, bC;
-    int maxcM = 1, maxcU = 1;
+    std::vector<char> activeU;
     for (int sub = 0; sub < nsub; ++sub) {
       const int nB = c->nB[sub], nP = c->nPi[sub];
       mM.push_back({c->moff[sub], c->goff[sub], c->ooff[sub], nB + nP, nB, nB, 0});
-      for (int r = 0; r < nB + nP; r += GEMV_ROWS_PER_BLOCK) bM.push_back({sub, r});
-      maxcM = std::max(maxcM, nB);
       mU.push_back({c->uoff[sub], c->poff[sub], c->ooff[sub], nB, nP, std::max(nP, 1), 0});
-      if (nP > 0)
-        for (int r = 0; r < nB; r += GEMV_ROWS_PER_BLOCK) bU.push_back({sub, r});
-      maxcU = std::max(maxcU, nP);
+      activeU.push_back(nP > 0);
     }
     mC.push_back({0, 0, 0, np, np, std::max(np, 1), 0});
-    for (int r = 0; r < np; r += GEMV_ROWS_PER_BLOCK) bC.push_back({0, r});
     const bool mixed = c->opt.precision == ABDDC_PREC_MIXED;
     auto gbytes = [](const std::vector<GemvMat>& v, bool gathered, double esize) {
       double b = 0.0;  // matrix + gathered input (value and index) + output
       for (const GemvMat& m : v) b += (double)m.nrows * m.ncols * esize + m.ncols * (gathered ? 12.0 : 8.0) + m.nrows * 8.0;
       return b;
     };
-    c->bytes_M = gbytes(mM, true, mixed ? 4.0 : 8.0);
-    c->bytes_U = gbytes(mU, true, mixed ? 4.0 : 8.0);
-    c->bytes_C = gbytes(mC, false, 8.0);
     if (mixed) {
       c->dM32.alloc(c->dM.n);
       c->dU32.alloc(c->dU.n);
@@ -885,20 +876,23 @@ void run_setup(abddc_ctx* c) {
       c->dM32.release();
       c->dU32.release();
     }
-    c->gemv_M = to_device(mM, s);
-    c->gemv_U = to_device(mU, s);
-    c->gemv_C = to_device(mC, s);
-    c->blk_M = to_device(bM, s);
-    c->blk_U = to_device(bU, s);
-    c->blk_C = to_device(bC, s);
-    c->nblk_M = (int)bM.size();
-    c->nblk_U = (int)bU.size();
-    c->nblk_C = (int)bC.size();
-    c->maxc_M = maxcM;
-    c->maxc_U = maxcU;
+    gemv_build(c->opM, mM, nullptr, gbytes(mM, true, mixed ? 4.0 : 8.0), s);
+    gemv_build(c->opU, mU, &activeU, gbytes(mU, true, mixed ? 4.0 : 8.0), s);
+    gemv_build(c->opC, mC, nullptr, gbytes(mC, false, 8.0), s);
     c->d_out.alloc(std::max<int64_t>(ot, 1));
     c->d_bpi.alloc(std::max(np, 1));
     c->d_xpi.alloc(std::max(np, 1));
+    // variants of the three apply GEMVs (cached per architecture and size)
+    ABDDC_HIP(hipMemsetAsync(c->d_bpi.p, 0, std::max(np, 1) * sizeof(double), s));
+    ABDDC_HIP(hipMemsetAsync(c->d_xpi.p, 0, std::max(np, 1) * sizeof(double), s));
+    if (mixed) {
+      gemv_tune<float>(c->opM, "bddc_LV", c->device, c->dM32.p, c->d_ghat.p, c->d_gam.p, c->d_out.p, s);
+      gemv_tune<float>(c->opU, "bddc_U", c->device, c->dU32.p, c->d_xpi.p, c->d_pid.p, c->d_out.p, s);
+    } else {
+      gemv_tune<double>(c->opM, "bddc_LV", c->device, c->dM.p, c->d_ghat.p, c->d_gam.p, c->d_out.p, s);
+      gemv_tune<double>(c->opU, "bddc_U", c->device, c->dU.p, c->d_xpi.p, c->d_pid.p, c->d_out.p, s);
+    }
+    gemv_tune<double>(c->opC, "coarse", c->device, c->dSPinv.p, c->d_bpi.p, nullptr, c->d_xpi.p, s);
     ht.mark("metadata uploaded");
     require_flag_clean(c, "local constrained / coarse factorisation");
     ht.mark("final flag check (sync)");

@@ -277,3 +277,40 @@ def test_graph_replay_matches_eager(pairs, restart):
         g.setup_coarse_space(**CASES["config2"][2])
         u4, i4 = _solve_env(g, True, **kw)
         assert torch.equal(u1, u4) and np.array_equal(i1["history"], i4["history"])
+
+
+def test_autotuner_cache(tmp_path):
+    """The GEMV variants are chosen by timing on first use and recorded per
+    architecture and size bucket in the cache file; every variant gives
+    bit-identical results (each row's reduction order is the same)."""
+    _need_gpu()
+    import json
+    import os
+    from paper_2501_01676_amd import api
+    path = tmp_path / "tune.json"
+    saved = {k: os.environ.get(k) for k in ("ABDDC_TUNE_CACHE", "ABDDC_GEMV_VARIANT")}
+    os.environ["ABDDC_TUNE_CACHE"] = str(path)
+    os.environ.pop("ABDDC_GEMV_VARIANT", None)
+    try:
+        p = W.config1b()
+        g = api.Solver(p)
+        g.setup_coarse_space()
+        u0, i0 = g.gmres_solve(30, 1e-8, 300)
+        g.close()
+        table = json.loads(path.read_text())
+        names = {k.split("|")[2] for k in table}
+        assert {"schur", "bddc_LV", "bddc_U", "coarse"} <= names, table
+        assert all(0 <= v <= 2 for v in table.values())
+        for var in "012":
+            os.environ["ABDDC_GEMV_VARIANT"] = var
+            g = api.Solver(p)
+            g.setup_coarse_space()
+            u, i = g.gmres_solve(30, 1e-8, 300)
+            assert torch.equal(u, u0) and np.array_equal(i["history"], i0["history"]), var
+            g.close()
+    finally:
+        for k, v in saved.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
