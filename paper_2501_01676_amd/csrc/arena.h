@@ -1,7 +1,11 @@
-// Bump arena for kernel descriptor arrays: a pinned host mirror and a device
-// buffer; each put() copies into pinned memory and issues a stream-ordered
-// async copy to the device.  When full it synchronises the stream and starts
-// over, so a region is never rewritten before the kernels that read it ran.
+// Ring of kernel descriptor arrays and host->device uploads: a pinned host
+// mirror and a device buffer; each put() copies into pinned memory and
+// issues a stream-ordered async copy.  The ring is split in two halves; an
+// event is recorded on the stream whenever the write position leaves a half,
+// and before a half is reused the event of its previous use is awaited --
+// work issued half a ring earlier, normally long finished -- so a region is
+// never rewritten before the copies and kernels that read it have run, and
+// the host rarely waits.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -20,32 +24,20 @@ class Arena {
   ~Arena() {
     if (d_) (void)hipFree(d_);
     if (h_) (void)hipHostFree(h_);
+    for (int i = 0; i < 2; ++i)
+      if (ev_[i]) (void)hipEventDestroy(ev_[i]);
   }
   void* put(const void* src, size_t bytes) {
-    size_t need = (bytes + 255) & ~size_t(255);
-    if (off_ + need > cap_) {
-      ABDDC_HIP(hipStreamSynchronize(s_));
-      off_ = 0;
-      if (need > cap_) grow(need);
-    }
-    std::memcpy(h_ + off_, src, bytes);
-    void* dst = d_ + off_;
-    ABDDC_HIP(hipMemcpyAsync(dst, h_ + off_, bytes, hipMemcpyHostToDevice, s_));
-    off_ += need;
-    return dst;
+    const size_t off = reserve(bytes);
+    std::memcpy(h_ + off, src, bytes);
+    ABDDC_HIP(hipMemcpyAsync(d_ + off, h_ + off, bytes, hipMemcpyHostToDevice, s_));
+    return d_ + off;
   }
-  // Stream-ordered upload into caller-owned device memory through the same
-  // pinned ring (no synchronisation unless the ring wraps).
+  // Stream-ordered upload into caller-owned device memory through the ring.
   void upload(void* dst, const void* src, size_t bytes) {
-    size_t need = (bytes + 255) & ~size_t(255);
-    if (off_ + need > cap_) {
-      ABDDC_HIP(hipStreamSynchronize(s_));
-      off_ = 0;
-      if (need > cap_) grow(need);
-    }
-    std::memcpy(h_ + off_, src, bytes);
-    ABDDC_HIP(hipMemcpyAsync(dst, h_ + off_, bytes, hipMemcpyHostToDevice, s_));
-    off_ += need;
+    const size_t off = reserve(bytes);
+    std::memcpy(h_ + off, src, bytes);
+    ABDDC_HIP(hipMemcpyAsync(dst, h_ + off, bytes, hipMemcpyHostToDevice, s_));
   }
   template <class T>
   T* put(const std::vector<T>& v) {
@@ -64,8 +56,26 @@ class Arena {
   }
 
  private:
+  size_t reserve(size_t bytes) {
+    const size_t need = (bytes + 255) & ~size_t(255);
+    if (2 * need > cap_) grow(2 * need);
+    const size_t half = cap_ / 2;
+    const int cur = off_ < half ? 0 : 1;
+    if (off_ + need > (size_t)(cur + 1) * half) {
+      // leave the current half; wait for the previous use of the next one
+      ABDDC_HIP(hipEventRecord(ev_[cur], s_));
+      used_[cur] = true;
+      const int nxt = 1 - cur;
+      if (used_[nxt]) ABDDC_HIP(hipEventSynchronize(ev_[nxt]));
+      off_ = (size_t)nxt * half;
+    }
+    const size_t off = off_;
+    off_ += need;
+    return off;
+  }
   void grow(size_t need) {
-    size_t cap = cap_ ? cap_ : (size_t(8) << 20);
+    ABDDC_HIP(hipStreamSynchronize(s_));
+    size_t cap = cap_ ? 2 * cap_ : (size_t(32) << 20);
     while (cap < need) cap *= 2;
     if (d_) ABDDC_HIP(hipFree(d_));
     if (h_) ABDDC_HIP(hipHostFree(h_));
@@ -73,12 +83,19 @@ class Arena {
     h_ = nullptr;
     ABDDC_HIP(hipMalloc(&d_, cap));
     ABDDC_HIP(hipHostMalloc(&h_, cap, hipHostMallocDefault));
+    for (int i = 0; i < 2; ++i) {
+      if (!ev_[i]) ABDDC_HIP(hipEventCreateWithFlags(&ev_[i], hipEventDisableTiming));
+      used_[i] = false;
+    }
     cap_ = cap;
+    off_ = 0;
   }
   hipStream_t s_;
   char* d_ = nullptr;
   char* h_ = nullptr;
   size_t cap_ = 0, off_ = 0;
+  hipEvent_t ev_[2] = {nullptr, nullptr};
+  bool used_[2] = {false, false};
 };
 
 }  // namespace abddc

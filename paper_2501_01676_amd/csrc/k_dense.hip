@@ -138,7 +138,7 @@ __device__ void tile_gemm(const T* __restrict__ A, int lda, const T* __restrict_
 }
 
 template <class T, bool TA, bool TB>
-__global__ void __launch_bounds__(256) gemm_batched_kernel(const GemmDesc<T>* __restrict__ descs,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) gemm_batched_kernel(const GemmDesc<T>* __restrict__ descs,
                                                             T alpha, T beta) {
   __shared__ T As[KC][LDS_PAD];
   __shared__ T Bs[KC][LDS_PAD];
@@ -276,7 +276,7 @@ __global__ void __launch_bounds__(256) plu_diag_kernel(const PluDesc<T>* __restr
 
 // Step 2: A21 <- A21 U11^{-1} (row tiles), A12 <- L11^{-1} A12 (column tiles).
 template <class T>
-__global__ void __launch_bounds__(256) plu_trsm_kernel(const PluDesc<T>* __restrict__ descs, int t0,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) plu_trsm_kernel(const PluDesc<T>* __restrict__ descs, int t0,
                                                         const T* __restrict__ scratch) {
   __shared__ T As[KC][LDS_PAD];
   __shared__ T Bs[KC][LDS_PAD];
@@ -305,7 +305,7 @@ __global__ void __launch_bounds__(256) plu_trsm_kernel(const PluDesc<T>* __restr
 // cols [k, ncol).  The block beyond k in both directions is formed once at
 // the end by plu_update_kernel.
 template <class T>
-__global__ void __launch_bounds__(256) plu_lead_kernel(const PluDesc<T>* __restrict__ descs, int t0) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) plu_lead_kernel(const PluDesc<T>* __restrict__ descs, int t0) {
   __shared__ T As[KC][LDS_PAD];
   __shared__ T Bs[KC][LDS_PAD];
   const PluDesc<T> d = descs[blockIdx.z];
@@ -341,7 +341,7 @@ __global__ void __launch_bounds__(256) plu_lead_kernel(const PluDesc<T>* __restr
 
 // Trailing Schur complement A22 -= A21 A12 with K = k (one pass).
 template <class T>
-__global__ void __launch_bounds__(256) plu_update_kernel(const PluDesc<T>* __restrict__ descs) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) plu_update_kernel(const PluDesc<T>* __restrict__ descs) {
   __shared__ T As[KC][LDS_PAD];
   __shared__ T Bs[KC][LDS_PAD];
   const PluDesc<T> d = descs[blockIdx.z];
