@@ -221,10 +221,10 @@ __global__ void __launch_bounds__(256) plu_diag_kernel(const PluDesc<T>* __restr
       for (int t = 0; t < 16; ++t) X[t] = D[kb + t][lane];
 #pragma unroll
       for (int t = 1; t < 16; ++t) {
-        T v = X[t];
+        T a[2] = {T(0), T(0)};   // two independent chains
 #pragma unroll
-        for (int q = 0; q < t; ++q) v -= D[kb + t][kb + q] * X[q];
-        X[t] = v;
+        for (int q = 0; q < t; ++q) a[q & 1] += D[kb + t][kb + q] * X[q];
+        X[t] -= a[0] + a[1];
       }
 #pragma unroll
       for (int t = 0; t < 16; ++t) D[kb + t][lane] = X[t];
@@ -235,10 +235,10 @@ __global__ void __launch_bounds__(256) plu_diag_kernel(const PluDesc<T>* __restr
 #pragma unroll
       for (int t = 0; t < 16; ++t) U[t] = D[kb + t][lane];
       for (int i = kb + 16 + wave; i < NB; i += 4) {
-        T v = D[i][lane];
+        T a[4] = {T(0), T(0), T(0), T(0)};
 #pragma unroll
-        for (int t = 0; t < 16; ++t) v -= D[i][kb + t] * U[t];
-        D[i][lane] = v;
+        for (int t = 0; t < 16; ++t) a[t & 3] += D[i][kb + t] * U[t];
+        D[i][lane] -= (a[0] + a[1]) + (a[2] + a[3]);
       }
     }
     __syncthreads();
