@@ -316,7 +316,6 @@ extern "C" int abddc_assemble(const abddc_problem* prob, const abddc_device* dev
     }
     gemv_build(c->opS, mS, nullptr, bytesS, s);
     c->d_wS.alloc(std::max<int64_t>(gt, 1));
-    c->d_rec.alloc(std::max<int64_t>(it, 1));
     gemv_tune<double>(c->opS, "schur", c->device, c->dS.p, c->d_ghat.p, c->d_gam.p, c->d_wS.p, s);
     record(c.get(), 12);
     int h = 0;
@@ -505,8 +504,10 @@ extern "C" int abddc_gmres_solve(abddc_ctx* c, int32_t restart, double rtol, int
       }
     }
     record(c, 14);
-    launch_recover(c->d_subs.p, c->topo.n_sub, c->dA.p, c->d_gam.p, c->d_x.p, c->d_int_dof.p, c->d_iface_dof.p, n, u,
-                   c->d_rec.p, s);
+    int max_nloc = 1;
+    for (int sub = 0; sub < c->topo.n_sub; ++sub) max_nloc = std::max(max_nloc, c->nloc[sub]);
+    launch_recover(c->d_subs.p, c->topo.n_sub, max_nloc, c->dA.p, c->d_gam.p, c->d_x.p, c->d_int_dof.p,
+                   c->d_iface_dof.p, n, u, s);
     record(c, 15);
     ABDDC_HIP(hipStreamSynchronize(s));
     const double wall = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();

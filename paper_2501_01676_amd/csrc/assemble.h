@@ -35,8 +35,9 @@ void launch_scatter(const SubAsm* subs, const int32_t* rowsub, const int32_t* ln
                     hipStream_t s);
 void launch_extract(const SubAsm* subs, int nsub, int max_nB, const double* A, double* S, double* B, double* g,
                     hipStream_t s);
-void launch_recover(const SubAsm* subs, int nsub, const double* A, const int32_t* gam, const double* uhat,
-                    const int32_t* int_dof, const int32_t* iface_dof, int64_t n_gamma, double* u, double* work,
+// interior recovery; max_nloc = max over subdomains of n_I + n_B (LDS size)
+void launch_recover(const SubAsm* subs, int nsub, int max_nloc, const double* A, const int32_t* gam,
+                    const double* uhat, const int32_t* int_dof, const int32_t* iface_dof, int64_t n_gamma, double* u,
                     hipStream_t s);
 
 }  // namespace abddc

@@ -64,7 +64,6 @@ struct abddc_ctx {
   abddc::KStats kstats;
   abddc::DevBuf<double> d_out, d_wS, d_bpi, d_xpi;  // apply / Schur work vectors
   abddc::DevBuf<abddc::SubAsm> d_subs;
-  abddc::DevBuf<double> d_rec;                      // recovery work (interior space)
 
   // ------------------------------------------------------------- GMRES
   abddc::DevBuf<double> d_V, d_Z, d_w, d_r, d_x, d_h1, d_h2, d_nrm, d_partial;

@@ -162,35 +162,73 @@ __global__ void extract_kernel(const SubAsm* __restrict__ subs, const double* __
   }
 }
 
+__device__ inline double wave_sum_d(double v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  return v;
+}
+
+__device__ inline double read_lane_d(double v, int lane) {
+  const long long x = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(x & 0xffffffffll), lane);
+  const int hi = __builtin_amdgcn_readlane((int)(x >> 32), lane);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
 // u_I = U11^{-1} (c - U12 u_B) with A_II = L11 U11, c = L11^{-1} f_I and
-// U12 = L11^{-1} A_IB left in place by the interior elimination.
-__global__ void __launch_bounds__(256) recover_kernel(const SubAsm* __restrict__ subs, const double* __restrict__ A,
+// U12 = L11^{-1} A_IB left in place by the interior elimination.  One
+// workgroup per subdomain: t = c - U12 u_B one row per wave (lanes stride
+// the row, coalesced); then back substitution in 64-row panels from the
+// bottom: the panel's right-hand side b = t_p - U_{p,below} x_below (one
+// row per wave), and its 64 x 64 triangular solve in one wave with the
+// panel's diagonal block staged in LDS (lane l holds b_l; step r takes x_r
+// from lane r by readlane and updates the lanes above it).
+__global__ void __launch_bounds__(1024) recover_kernel(const SubAsm* __restrict__ subs, const double* __restrict__ A,
                                                       const int32_t* __restrict__ gam, const double* __restrict__ uhat,
-                                                      const int32_t* __restrict__ int_dof, double* __restrict__ u,
-                                                      double* __restrict__ work) {
+                                                      const int32_t* __restrict__ int_dof, double* __restrict__ u) {
+  extern __shared__ double sm[];
+  __shared__ double Ud[64][65];
+  __shared__ double bv[64];
   const SubAsm d = subs[blockIdx.x];
   const int nI = d.nI, nB = d.nloc - d.nI;
-  double* t = work + d.ioff;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
+  double* xs = sm;        // t, then x (nI)
+  double* ub = sm + nI;   // u_B gathered (nB)
   const double* M = A + d.aoff;
-  for (int r = threadIdx.x; r < nI; r += blockDim.x) {
-    double v = M[(int64_t)r * d.ld + d.nloc];
+  for (int c = tid; c < nB; c += blockDim.x) ub[c] = uhat[gam[d.goff + c]];
+  __syncthreads();
+  for (int r = wave; r < nI; r += nw) {
     const double* row = M + (int64_t)r * d.ld + nI;
-    for (int c = 0; c < nB; ++c) v -= row[c] * uhat[gam[d.goff + c]];
-    t[r] = v;
+    double v = 0.0;
+    for (int c = lane; c < nB; c += 64) v += row[c] * ub[c];
+    v = wave_sum_d(v);
+    if (lane == 0) xs[r] = M[(int64_t)r * d.ld + d.nloc] - v;
   }
   __syncthreads();
-  __shared__ double xr;
-  for (int r = nI - 1; r >= 0; --r) {
-    if (threadIdx.x == 0) {
-      xr = t[r] / M[(int64_t)r * d.ld + r];
-      t[r] = xr;
+  for (int p1 = nI; p1 > 0;) {
+    const int p0 = ((p1 - 1) / 64) * 64, len = p1 - p0;
+    for (int i = wave; i < 64; i += nw)
+      Ud[i][lane] = (i < len && lane < len) ? M[(int64_t)(p0 + i) * d.ld + p0 + lane] : (i == lane ? 1.0 : 0.0);
+    for (int r = p0 + wave; r < p1; r += nw) {
+      const double* row = M + (int64_t)r * d.ld;
+      double v = 0.0;
+      for (int q = p1 + lane; q < nI; q += 64) v += row[q] * xs[q];
+      v = wave_sum_d(v);
+      if (lane == 0) bv[r - p0] = xs[r] - v;
     }
     __syncthreads();
-    const double x = xr;
-    for (int q = threadIdx.x; q < r; q += blockDim.x) t[q] -= M[(int64_t)q * d.ld + r] * x;
+    if (wave == 0) {
+      double b = lane < len ? bv[lane] : 0.0, x = 0.0;
+      for (int r = len - 1; r >= 0; --r) {
+        const double xr = read_lane_d(b, r) / Ud[r][r];
+        if (lane == r) x = xr;
+        if (lane < r) b -= Ud[lane][r] * xr;
+      }
+      if (lane < len) xs[p0 + lane] = x;
+    }
     __syncthreads();
+    p1 = p0;
   }
-  for (int r = threadIdx.x; r < nI; r += blockDim.x) u[int_dof[d.ioff + r]] = t[r];
+  for (int r = tid; r < nI; r += blockDim.x) u[int_dof[d.ioff + r]] = xs[r];
 }
 
 __global__ void check_positive_kernel(const double* __restrict__ v, int64_t n, int* flag) {
@@ -234,10 +272,12 @@ void launch_extract(const SubAsm* subs, int nsub, int max_nB, const double* A, d
   ABDDC_HIP(hipGetLastError());
 }
 
-void launch_recover(const SubAsm* subs, int nsub, const double* A, const int32_t* gam, const double* uhat,
-                    const int32_t* int_dof, const int32_t* iface_dof, int64_t n_gamma, double* u, double* work,
+void launch_recover(const SubAsm* subs, int nsub, int max_nloc, const double* A, const int32_t* gam,
+                    const double* uhat, const int32_t* int_dof, const int32_t* iface_dof, int64_t n_gamma, double* u,
                     hipStream_t s) {
-  recover_kernel<<<nsub, 256, 0, s>>>(subs, A, gam, uhat, int_dof, u, work);
+  ABDDC_REQUIRE((size_t)max_nloc * sizeof(double) <= 64 * 1024, ABDDC_EINVAL, "subdomain too large for recovery");
+  // 16 waves per subdomain: the row sweeps are latency-bound chains of loads
+  recover_kernel<<<nsub, 1024, (size_t)std::max(max_nloc, 1) * sizeof(double), s>>>(subs, A, gam, uhat, int_dof, u);
   if (n_gamma > 0) iface_scatter_kernel<<<(unsigned)((n_gamma + 255) / 256), 256, 0, s>>>(uhat, iface_dof, n_gamma, u);
   ABDDC_HIP(hipGetLastError());
 }
