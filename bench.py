@@ -47,8 +47,8 @@ DESCRIPTIONS = {
 def parse():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", default="config2", choices=sorted(DESCRIPTIONS))
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--theta", type=float, default=10.0)

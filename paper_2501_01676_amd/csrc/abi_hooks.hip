@@ -3,11 +3,13 @@
 
 #include <cstring>
 #include <map>
+#include <unordered_map>
 #include <mutex>
 #include <string>
 
 #include "arena.h"
 #include "guard.h"
+#include "htrace.h"
 #include "internal.h"
 #include "kstats.h"
 
@@ -35,7 +37,8 @@ struct Block {
 };
 struct Cache {
   std::mutex mu;
-  std::multimap<std::pair<int, size_t>, Block> free_blocks;  // (device, rounded size)
+  std::multimap<std::pair<int, size_t>, Block> free_blocks;  // (device, block size)
+  std::unordered_map<void*, size_t> block_size;              // every block ever allocated
 };
 Cache& cache() {
   static Cache* c = new Cache();  // intentionally never destroyed
@@ -63,28 +66,37 @@ void* cache_alloc(size_t bytes) {
   Cache& c = cache();
   Block blk{nullptr, nullptr, nullptr};
   {
+    // best fit: the smallest cached block of at least r bytes, if it wastes
+    // at most r + 1 MiB
     std::lock_guard<std::mutex> g(c.mu);
-    auto it = c.free_blocks.find({dev, r});
-    if (it != c.free_blocks.end()) {
+    auto it = c.free_blocks.lower_bound({dev, r});
+    if (it != c.free_blocks.end() && it->first.first == dev && it->first.second <= 2 * r + (size_t(1) << 20)) {
       blk = it->second;
       c.free_blocks.erase(it);
     }
   }
   if (blk.p) {
     if (blk.ev) {
-      if (blk.stream != g_stream) ABDDC_HIP(hipEventSynchronize(blk.ev));
+      if (blk.stream != g_stream) {
+        HostTrace ht;
+        ABDDC_HIP(hipEventSynchronize(blk.ev));
+        ht.mark("allocator: wait for a block released on another stream");
+      }
       (void)hipEventDestroy(blk.ev);
     }
     return blk.p;
   }
   void* p = nullptr;
+  HostTrace ht;
   hipError_t e = hipMalloc(&p, r);
+  if (ht.on) ht.mark(("allocator: hipMalloc " + std::to_string(r >> 10) + " KiB").c_str());
   if (e == hipErrorOutOfMemory) {
     // return cached blocks of this device to the driver and retry once
     ABDDC_HIP(hipDeviceSynchronize());
     std::lock_guard<std::mutex> g(c.mu);
     for (auto it = c.free_blocks.begin(); it != c.free_blocks.end();) {
       if (it->first.first == dev) {
+        c.block_size.erase(it->second.p);
         (void)hipFree(it->second.p);
         if (it->second.ev) (void)hipEventDestroy(it->second.ev);
         it = c.free_blocks.erase(it);
@@ -97,6 +109,10 @@ void* cache_alloc(size_t bytes) {
   }
   if (e != hipSuccess)
     throw Error(e == hipErrorOutOfMemory ? ABDDC_ENOMEM : ABDDC_EDEVICE, std::string("hipMalloc: ") + hipGetErrorString(e));
+  {
+    std::lock_guard<std::mutex> g(c.mu);
+    c.block_size[p] = r;
+  }
   return p;
 }
 
@@ -117,7 +133,8 @@ void cache_free(void* p, size_t bytes) {
   }
   Cache& c = cache();
   std::lock_guard<std::mutex> g(c.mu);
-  c.free_blocks.insert({{dev, round_size(bytes)}, blk});
+  auto sz = c.block_size.find(p);
+  c.free_blocks.insert({{dev, sz != c.block_size.end() ? sz->second : round_size(bytes)}, blk});
 }
 }  // namespace abddc
 

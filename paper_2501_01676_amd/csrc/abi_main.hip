@@ -15,6 +15,7 @@
 #include "assemble.h"
 #include "ctx.h"
 #include "guard.h"
+#include "htrace.h"
 #include "internal.h"
 
 namespace abddc {
@@ -146,7 +147,9 @@ extern "C" int abddc_assemble(const abddc_problem* prob, const abddc_device* dev
     Topology& T = c->topo;
     int nsub_in[3] = {prob->nsub[0], prob->nsub[1], prob->nsub[2]};
     const int* w_in[3] = {prob->width[0], prob->width[1], prob->width[2]};
+    HostTrace ht;
     T.build(nsub_in, w_in);
+    ht.mark("assemble: topology");
     const bool on_dev = prob->arrays_on_device != 0;
     if (!on_dev)
       for (int64_t e = 0; e < T.n_elem; ++e)
@@ -164,7 +167,45 @@ extern "C" int abddc_assemble(const abddc_problem* prob, const abddc_device* dev
     c->d_flag.alloc(1);
     c->d_flag.zero(s);
     record(c.get(), 10);
+    // coefficients, then the element matrices: they need no layout, so the
+    // GPU computes them while the host builds the local maps below
+    if (on_dev) {
+      c->d_nu.alloc(T.n_elem);
+      ABDDC_HIP(hipMemcpyAsync(c->d_nu.p, prob->nu, T.n_elem * sizeof(double), hipMemcpyDeviceToDevice, s));
+      launch_check_positive(c->d_nu.p, T.n_elem, c->d_flag.p, s);
+      if (prob->f_nodal) {
+        c->d_fnodal.alloc(T.n_nodes);
+        ABDDC_HIP(hipMemcpyAsync(c->d_fnodal.p, prob->f_nodal, T.n_nodes * sizeof(double), hipMemcpyDeviceToDevice, s));
+        c->have_fnodal = true;
+      }
+    } else {
+      std::vector<double> nu(prob->nu, prob->nu + T.n_elem);
+      c->d_nu = to_device(nu, s);
+      if (prob->f_nodal) {
+        std::vector<double> fn(prob->f_nodal, prob->f_nodal + T.n_nodes);
+        c->d_fnodal = to_device(fn, s);
+        c->have_fnodal = true;
+      }
+    }
 
+    DevBuf<double> Ae(T.n_elem * 64), Fe(T.n_elem * 8);
+    {
+      ElemParams P{};
+      P.n_elem = T.n_elem;
+      for (int a = 0; a < 3; ++a) {
+        P.ne[a] = T.ne[a];
+        P.nn[a] = T.nn[a];
+        P.h[a] = c->length[a] / T.ne[a];
+        P.b0[a] = c->beta0[a];
+      }
+      for (int i = 0; i < 9; ++i) P.b1[i] = c->beta1[i];
+      P.c = c->c;
+      P.tau = c->tau;
+      P.f_const = c->f_const;
+      launch_elem(P, c->d_nu.p, c->have_fnodal ? c->d_fnodal.p : nullptr, Ae.p, Fe.p, s);
+    }
+
+    ht.mark("assemble: coefficients, element kernel queued");
     // ---------------------------------------------------- local layout
     const int nsub = T.n_sub;
     c->nI.resize(nsub);
@@ -232,6 +273,7 @@ extern "C" int abddc_assemble(const abddc_problem* prob, const abddc_device* dev
       rows += c->nloc[sub];
     }
     ABDDC_REQUIRE(T.n_nodes < (int64_t)1 << 31 && lmt < (int64_t)1 << 31, ABDDC_EINVAL, "mesh too large");
+    ht.mark("assemble: local layout maps");
     c->d_subs = to_device(sa, s);
     DevBuf<int32_t> d_lnode = to_device(lnode, s), d_rowsub = to_device(rowsub, s), d_lmap = to_device(lmap, s);
     c->d_gam = to_device(gam, s);
@@ -240,43 +282,11 @@ extern "C" int abddc_assemble(const abddc_problem* prob, const abddc_device* dev
     for (const Object& o : T.objects)
       for (int q = 0; q < o.n; ++q) iface_dof[o.gstart + q] = (int32_t)T.dof_of_node[o.nodes[q]];
     c->d_iface_dof = to_device(iface_dof, s);
-    if (on_dev) {
-      c->d_nu.alloc(T.n_elem);
-      ABDDC_HIP(hipMemcpyAsync(c->d_nu.p, prob->nu, T.n_elem * sizeof(double), hipMemcpyDeviceToDevice, s));
-      launch_check_positive(c->d_nu.p, T.n_elem, c->d_flag.p, s);
-      if (prob->f_nodal) {
-        c->d_fnodal.alloc(T.n_nodes);
-        ABDDC_HIP(hipMemcpyAsync(c->d_fnodal.p, prob->f_nodal, T.n_nodes * sizeof(double), hipMemcpyDeviceToDevice, s));
-        c->have_fnodal = true;
-      }
-    } else {
-      std::vector<double> nu(prob->nu, prob->nu + T.n_elem);
-      c->d_nu = to_device(nu, s);
-      if (prob->f_nodal) {
-        std::vector<double> fn(prob->f_nodal, prob->f_nodal + T.n_nodes);
-        c->d_fnodal = to_device(fn, s);
-        c->have_fnodal = true;
-      }
-    }
-
+    ht.mark("assemble: uploads");
     // -------------------------------------------- element matrices + scatter
     c->dA.alloc(std::max<int64_t>(at, 1));
     c->dA.zero(s);
     {
-      DevBuf<double> Ae(T.n_elem * 64), Fe(T.n_elem * 8);
-      ElemParams P{};
-      P.n_elem = T.n_elem;
-      for (int a = 0; a < 3; ++a) {
-        P.ne[a] = T.ne[a];
-        P.nn[a] = T.nn[a];
-        P.h[a] = c->length[a] / T.ne[a];
-        P.b0[a] = c->beta0[a];
-      }
-      for (int i = 0; i < 9; ++i) P.b1[i] = c->beta1[i];
-      P.c = c->c;
-      P.tau = c->tau;
-      P.f_const = c->f_const;
-      launch_elem(P, c->d_nu.p, c->have_fnodal ? c->d_fnodal.p : nullptr, Ae.p, Fe.p, s);
       launch_scatter(c->d_subs.p, d_rowsub.p, d_lnode.p, d_lmap.p, rows, T.nn, T.ne, Ae.p, Fe.p, c->dA.p, s);
       record(c.get(), 11);
       // interior elimination: S^(i), g^(i) in the trailing block / column
@@ -290,17 +300,17 @@ extern "C" int abddc_assemble(const abddc_problem* prob, const abddc_device* dev
     c->dg.alloc(std::max<int64_t>(gt, 1));
     int maxnB = 1;
     for (int sub = 0; sub < nsub; ++sub) maxnB = std::max(maxnB, c->nB[sub]);
+    ht.mark("assemble: element kernels + interior elimination queued");
     launch_extract(c->d_subs.p, nsub, maxnB, c->dA.p, c->dS.p, c->dB.p, c->dg.p, s);
 
     // interface owners (goff space) and ghat = sum R_i^T g^(i)
-    std::vector<std::vector<int32_t>> own(T.n_gamma);
+    std::vector<int32_t> okey, oval, optr, oidx;
     for (int sub = 0; sub < nsub; ++sub)
-      for (int l = 0; l < c->nB[sub]; ++l) own[T.sub[sub].gamma[l]].push_back((int32_t)(c->goff[sub] + l));
-    std::vector<int32_t> optr(T.n_gamma + 1, 0), oidx;
-    for (int64_t g = 0; g < T.n_gamma; ++g) {
-      optr[g + 1] = optr[g] + (int)own[g].size();
-      oidx.insert(oidx.end(), own[g].begin(), own[g].end());
-    }
+      for (int l = 0; l < c->nB[sub]; ++l) {
+        okey.push_back((int32_t)T.sub[sub].gamma[l]);
+        oval.push_back((int32_t)(c->goff[sub] + l));
+      }
+    csr_group(T.n_gamma, okey, oval, optr, oidx);
     c->d_own_ptr = to_device(optr, s);
     c->d_own_idx = to_device(oidx, s);
     c->d_ghat.alloc(std::max<int64_t>(T.n_gamma, 1));
@@ -317,10 +327,12 @@ extern "C" int abddc_assemble(const abddc_problem* prob, const abddc_device* dev
     gemv_build(c->opS, mS, nullptr, bytesS, s);
     c->d_wS.alloc(std::max<int64_t>(gt, 1));
     gemv_tune<double>(c->opS, "schur", c->device, c->dS.p, c->d_ghat.p, c->d_gam.p, c->d_wS.p, s);
+    ht.mark("assemble: owners, Schur GEMV metadata");
     record(c.get(), 12);
     int h = 0;
     ABDDC_HIP(hipMemcpyAsync(&h, c->d_flag.p, sizeof(int), hipMemcpyDeviceToHost, s));
     ABDDC_HIP(hipStreamSynchronize(s));
+    ht.mark("assemble: wait for the device");
     c->kstats.resolve();
     ABDDC_REQUIRE(!(h & 4), ABDDC_EINVAL, "nu must be positive and finite");
     ABDDC_REQUIRE(!(h & 1), ABDDC_ESINGULAR, "interior elimination: zero or non-finite pivot");

@@ -14,6 +14,7 @@
 #include <map>
 #include <mutex>
 
+#include "htrace.h"
 #include "internal.h"
 
 namespace abddc {
@@ -66,7 +67,11 @@ class Arena {
       ABDDC_HIP(hipEventRecord(ev_[cur], s_));
       used_[cur] = true;
       const int nxt = 1 - cur;
-      if (used_[nxt]) ABDDC_HIP(hipEventSynchronize(ev_[nxt]));
+      if (used_[nxt]) {
+        HostTrace ht;
+        ABDDC_HIP(hipEventSynchronize(ev_[nxt]));
+        ht.mark("staging ring: wait for the other half");
+      }
       off_ = (size_t)nxt * half;
     }
     const size_t off = off_;
@@ -74,6 +79,7 @@ class Arena {
     return off;
   }
   void grow(size_t need) {
+    HostTrace ht;
     ABDDC_HIP(hipStreamSynchronize(s_));
     size_t cap = cap_ ? 2 * cap_ : (size_t(32) << 20);
     while (cap < need) cap *= 2;
@@ -89,6 +95,7 @@ class Arena {
     }
     cap_ = cap;
     off_ = 0;
+    ht.mark("staging ring: grow");
   }
   hipStream_t s_;
   char* d_ = nullptr;

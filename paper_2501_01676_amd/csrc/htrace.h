@@ -12,7 +12,11 @@ namespace abddc {
 struct HostTrace {
   bool on;
   std::chrono::steady_clock::time_point last;
-  HostTrace() : on(std::getenv("ABDDC_HOST_TRACE") != nullptr), last(std::chrono::steady_clock::now()) {}
+  HostTrace() : on(enabled()), last(on ? std::chrono::steady_clock::now() : std::chrono::steady_clock::time_point()) {}
+  static bool enabled() {
+    static const bool e = std::getenv("ABDDC_HOST_TRACE") != nullptr;   // read once per process
+    return e;
+  }
   void mark(const char* what) {
     if (!on) return;
     const auto now = std::chrono::steady_clock::now();

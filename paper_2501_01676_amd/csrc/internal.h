@@ -83,6 +83,18 @@ struct DevBuf {
   }
 };
 
+// Groups (key, value) pairs by key into CSR arrays (ptr of nkeys + 1, idx),
+// values of one key in input order (counting sort).
+inline void csr_group(int64_t nkeys, const std::vector<int32_t>& keys, const std::vector<int32_t>& vals,
+                      std::vector<int32_t>& ptr, std::vector<int32_t>& idx) {
+  ptr.assign(nkeys + 1, 0);
+  for (int32_t k : keys) ++ptr[k + 1];
+  for (int64_t k = 0; k < nkeys; ++k) ptr[k + 1] += ptr[k];
+  idx.assign(keys.size(), 0);
+  std::vector<int32_t> fill(ptr.begin(), ptr.end() - 1);
+  for (size_t i = 0; i < keys.size(); ++i) idx[fill[keys[i]]++] = vals[i];
+}
+
 // Stream-ordered host -> device copy through the stream's pinned staging
 // ring: the host data is copied out before return, so the caller may free
 // it at once; the device copy completes in stream order.

@@ -17,6 +17,7 @@
 
 #include "apply.h"
 #include "internal.h"
+#include "htrace.h"
 #include "kstats.h"
 #include "tune.h"
 
@@ -251,6 +252,7 @@ void gemv_build(GemvOp& op, const std::vector<GemvMat>& mats, const std::vector<
   op.maxc = 1;
   op.rows = 0;
   for (const GemvMat& m : mats) op.maxc = std::max(op.maxc, (int)m.ncols);
+  HostTrace ht;
   for (int v = 0; v < GEMV_NVAR; ++v) {
     std::vector<GemvBlock> b;
     const int rpb = 4 * GEMV_ROWS[v];
@@ -263,8 +265,10 @@ void gemv_build(GemvOp& op, const std::vector<GemvMat>& mats, const std::vector<
   }
   for (size_t i = 0; i < mats.size(); ++i)
     if (!active || (*active)[i]) op.rows += mats[i].nrows;
+  ht.mark("gemv_build: block lists");
   op.mats = to_device(mats, s);
   op.bytes = bytes;
+  ht.mark("gemv_build: matrices");
 }
 
 template <class TM>
@@ -290,6 +294,7 @@ void gemv_tune(GemvOp& op, const char* name, int device, const TM* M, const doub
     return;
   }
   KStatsScope none(nullptr);
+  HostTrace ht;
   hipEvent_t e0, e1;
   ABDDC_HIP(hipEventCreate(&e0));
   ABDDC_HIP(hipEventCreate(&e1));
@@ -312,6 +317,7 @@ void gemv_tune(GemvOp& op, const char* name, int device, const TM* M, const doub
   (void)hipEventDestroy(e1);
   op.var = bestv;
   tune_store(key, bestv);
+  ht.mark(("autotuner: timed " + key).c_str());
 }
 
 template void gemv_run<double>(const GemvOp&, const double*, const double*, const int32_t*, double*, bool,

@@ -829,22 +829,22 @@ void run_setup(abddc_ctx* c) {
     ht.mark("apply metadata (device)");
     // ------------------------------------------- apply metadata (device)
     record(c, 7);
-    std::vector<int32_t> pid_all, ptr_p(np + 1, 0), idx_p, ptr_a(T.n_gamma + 1, 0), idx_a;
-    std::vector<std::vector<int32_t>> own_p(np), own_a(T.n_gamma);
+    std::vector<int32_t> pid_all, ptr_p, idx_p, ptr_a, idx_a, kp, vp, ka, va;
     for (int sub = 0; sub < nsub; ++sub) {
       const int nB = c->nB[sub];
       pid_all.insert(pid_all.end(), Pid[sub].begin(), Pid[sub].end());
-      for (size_t l = 0; l < Pid[sub].size(); ++l) own_p[Pid[sub][l]].push_back((int32_t)(c->ooff[sub] + nB + l));
-      for (int l = 0; l < nB; ++l) own_a[T.sub[sub].gamma[l]].push_back((int32_t)(c->ooff[sub] + l));
+      for (size_t l = 0; l < Pid[sub].size(); ++l) {
+        kp.push_back(Pid[sub][l]);
+        vp.push_back((int32_t)(c->ooff[sub] + nB + l));
+      }
+      for (int l = 0; l < nB; ++l) {
+        ka.push_back((int32_t)T.sub[sub].gamma[l]);
+        va.push_back((int32_t)(c->ooff[sub] + l));
+      }
     }
-    for (int p = 0; p < np; ++p) {
-      ptr_p[p + 1] = ptr_p[p] + (int)own_p[p].size();
-      idx_p.insert(idx_p.end(), own_p[p].begin(), own_p[p].end());
-    }
-    for (int64_t g = 0; g < T.n_gamma; ++g) {
-      ptr_a[g + 1] = ptr_a[g] + (int)own_a[g].size();
-      idx_a.insert(idx_a.end(), own_a[g].begin(), own_a[g].end());
-    }
+    csr_group(np, kp, vp, ptr_p, idx_p);
+    csr_group(T.n_gamma, ka, va, ptr_a, idx_a);
+    ht.mark("metadata: owner lists");
     c->d_pid = to_device(pid_all, s);
     c->d_pown_ptr = to_device(ptr_p, s);
     c->d_pown_idx = to_device(idx_p, s);
@@ -876,12 +876,14 @@ void run_setup(abddc_ctx* c) {
       c->dM32.release();
       c->dU32.release();
     }
+    ht.mark("metadata: uploads, fp32 copies");
     gemv_build(c->opM, mM, nullptr, gbytes(mM, true, mixed ? 4.0 : 8.0), s);
     gemv_build(c->opU, mU, &activeU, gbytes(mU, true, mixed ? 4.0 : 8.0), s);
     gemv_build(c->opC, mC, nullptr, gbytes(mC, false, 8.0), s);
     c->d_out.alloc(std::max<int64_t>(ot, 1));
     c->d_bpi.alloc(std::max(np, 1));
     c->d_xpi.alloc(std::max(np, 1));
+    ht.mark("metadata: GEMV operators, buffers");
     // variants of the three apply GEMVs (cached per architecture and size)
     ABDDC_HIP(hipMemsetAsync(c->d_bpi.p, 0, std::max(np, 1) * sizeof(double), s));
     ABDDC_HIP(hipMemsetAsync(c->d_xpi.p, 0, std::max(np, 1) * sizeof(double), s));

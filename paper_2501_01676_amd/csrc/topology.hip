@@ -2,7 +2,6 @@
 #include "topology.h"
 
 #include <algorithm>
-#include <map>
 
 #include "internal.h"
 
@@ -53,7 +52,12 @@ void Topology::build(const int nsub_in[3], const int* const width_in[3]) {
 
   dof_of_node.assign(n_nodes, -1);
   iface_of_node.assign(n_nodes, -1);
-  std::map<std::vector<int>, std::vector<int64_t>> groups;
+  // The sharing set of a node is fixed by (s_lo + s_hi) per axis: 2s inside
+  // subdomain s, 2s + 1 on the cut between s and s + 1; those three numbers
+  // index a dense table of objects.
+  const int kx = 2 * nsub[0] - 1, ky = 2 * nsub[1] - 1, kz = 2 * nsub[2] - 1;
+  std::vector<int> obj_of_key((size_t)kx * ky * kz, -1);
+  objects.clear();
   int64_t ndof = 0;
   for (int iz = 0; iz < nn[2]; ++iz)
     for (int iy = 0; iy < nn[1]; ++iy)
@@ -64,26 +68,26 @@ void Topology::build(const int nsub_in[3], const int* const width_in[3]) {
         dof_of_node[nid] = ndof++;
         const int cnt = oncut[0][ix] + oncut[1][iy] + oncut[2][iz];
         if (cnt == 0) continue;
-        std::vector<int> subs;
-        for (int sz = s_lo[2][iz]; sz <= s_hi[2][iz]; ++sz)
-          for (int sy = s_lo[1][iy]; sy <= s_hi[1][iy]; ++sy)
-            for (int sx = s_lo[0][ix]; sx <= s_hi[0][ix]; ++sx) subs.push_back(sub_id(sx, sy, sz));
-        std::sort(subs.begin(), subs.end());
-        groups[subs].push_back(nid);
+        const size_t key = (size_t)(s_lo[0][ix] + s_hi[0][ix]) +
+                           (size_t)kx * ((s_lo[1][iy] + s_hi[1][iy]) + (size_t)ky * (s_lo[2][iz] + s_hi[2][iz]));
+        int k = obj_of_key[key];
+        if (k < 0) {
+          Object o;
+          for (int sz = s_lo[2][iz]; sz <= s_hi[2][iz]; ++sz)
+            for (int sy = s_lo[1][iy]; sy <= s_hi[1][iy]; ++sy)
+              for (int sx = s_lo[0][ix]; sx <= s_hi[0][ix]; ++sx) o.subs.push_back(sub_id(sx, sy, sz));
+          std::sort(o.subs.begin(), o.subs.end());
+          ABDDC_REQUIRE(o.subs.size() == 2 || o.subs.size() == 4 || o.subs.size() == 8, ABDDC_EINVAL,
+                        "unexpected interface class");
+          o.kind = o.subs.size() == 2 ? KIND_FACE : (o.subs.size() == 4 ? KIND_EDGE : KIND_VERTEX);
+          k = (int)objects.size();
+          obj_of_key[key] = k;
+          objects.push_back(std::move(o));
+        }
+        objects[k].nodes.push_back(nid);   // visited in increasing node id
       }
   n_dof = ndof;
-
-  objects.clear();
-  for (auto& kv : groups) {
-    Object o;
-    o.subs = kv.first;
-    o.nodes = kv.second;  // visited in increasing node id
-    o.kind = o.subs.size() == 2 ? KIND_FACE : (o.subs.size() == 4 ? KIND_EDGE : KIND_VERTEX);
-    ABDDC_REQUIRE(o.subs.size() == 2 || o.subs.size() == 4 || o.subs.size() == 8, ABDDC_EINVAL,
-                  "unexpected interface class");
-    o.n = (int)o.nodes.size();
-    objects.push_back(std::move(o));
-  }
+  for (Object& o : objects) o.n = (int)o.nodes.size();
   std::sort(objects.begin(), objects.end(), [](const Object& a, const Object& b) {
     if (a.kind != b.kind) return a.kind < b.kind;
     return a.nodes[0] < b.nodes[0];
