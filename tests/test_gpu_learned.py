@@ -210,3 +210,38 @@ def test_learned_setup_end_to_end():
     ge.close()
     gl.close()
     net.close()
+
+
+def test_gate_out_of_range_falls_back_to_exact():
+    """Features outside the training range send every edge to the exact
+    eigenproblem: the learned setup then equals the exact one bit for bit."""
+    _need_gpu()
+    from paper_2501_01676_amd import api
+    p = _layered8()
+    net = api.MLP(W.mlp_init_params(1))
+    # a training range of one far-away feature vector: every real edge is outside it
+    net.set_ranges(torch.full((1, Lr.N_FEAT), 100.0, dtype=torch.float32, device="cuda"))
+    ge = api.Solver(p)
+    ce = ge.setup_coarse_space(theta_face=2.0, theta_edge=2.0)
+    ue, ie = ge.gmres_solve(30, 1e-8, 300)
+    gl = api.Solver(p)
+    cl = gl.setup_coarse_space(theta_face=2.0, theta_edge=2.0, constraint_source=1, mlp=net)
+    st = gl.learned_stats()
+    assert st == {"predicted": 0, "exact": gl.n_edge}
+    ul, il = gl.gmres_solve(30, 1e-8, 300)
+    assert cl == ce and il["iters"] == ie["iters"]
+    assert torch.equal(ul, ue)
+    ge.close()
+    gl.close()
+    net.close()
+
+
+def test_learned_options_rejected_without_network():
+    _need_gpu()
+    from paper_2501_01676_amd import api
+    from paper_2501_01676_amd import _lib as L
+    g = api.Solver(W.config1a())
+    with pytest.raises(L.AbddcError) as e:
+        g.setup_coarse_space(constraint_source=1, mlp=None)
+    assert e.value.code == L.EINVAL
+    g.close()

@@ -314,3 +314,35 @@ def test_autotuner_cache(tmp_path):
                 os.environ.pop(k, None)
             else:
                 os.environ[k] = v
+
+
+def test_config4_full_size_properties():
+    """config4 (ragged widths 6-12, faces up to 121 dofs) at full size: the
+    GPU solution satisfies the global stabilised system assembled by the
+    oracle to the GMRES tolerance, and sampled local Schur complements equal
+    the oracle's (the largest and the smallest subdomains included)."""
+    _need_gpu()
+    from oracle import Topology, fem
+    from paper_2501_01676_amd import api
+    p = W.config4(0)
+    print("[parity] config4: gpu solve", flush=True)
+    g = api.Solver(p)
+    g.setup_coarse_space()
+    u, info = g.gmres_solve(restart=30, rtol=1e-8, maxit=300)
+    u = u.cpu().numpy()
+    assert info["converged"]
+    topo = Topology(p["nsub"], p["widths"])
+    print("[parity] config4: oracle global system", flush=True)
+    A, b = fem.assemble_global(p, topo)
+    res = np.linalg.norm(A @ u - b) / np.linalg.norm(b)
+    assert res <= 1e-7, res
+    sizes = [topo.sub[s]["nI"] + topo.sub[s]["nB"] for s in range(topo.n_sub)]
+    sample = sorted({int(np.argmax(sizes)), int(np.argmin(sizes)), 7, 100})
+    elem = fem.element_matrices(p, topo)
+    for s_, (Al, fl) in zip(sample, fem.assemble_subdomains(p, topo, elem=elem, subs=sample)):
+        nI = topo.sub[s_]["nI"]
+        X = np.linalg.solve(Al[:nI, :nI], Al[:nI, nI:])
+        S = Al[nI:, nI:] - Al[nI:, :nI] @ X
+        Sg = g.stage(0, s_).reshape(S.shape)
+        assert np.abs(Sg - S).max() <= 1e-11 * np.abs(S).max(), s_
+    g.close()
