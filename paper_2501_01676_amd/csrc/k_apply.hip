@@ -134,11 +134,8 @@ __global__ void axpy_multi_kernel(const double* __restrict__ V, int64_t ldv, int
 // Hessenberg column j from the two Gram-Schmidt passes and the norm, the
 // previous Givens rotations, a new rotation, the rotated rhs g and the
 // residual estimate |g[j+1]|.
-__global__ void arnoldi_finish_kernel(GmresState* st, int j, const double* __restrict__ h1,
-                                      const double* __restrict__ h2, const double* __restrict__ nrm2) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  const bool dev_j = j < 0;
-  if (dev_j) j = st->j;
+__device__ void arnoldi_column(GmresState* st, int j, const double* __restrict__ h1, const double* __restrict__ h2,
+                               const double* __restrict__ nrm2) {
   double col[GMRES_MAXR + 1];
   for (int i = 0; i <= j; ++i) col[i] = h1[i] + h2[i];
   const double hn = sqrt(fmax(nrm2[0], 0.0));
@@ -165,7 +162,18 @@ __global__ void arnoldi_finish_kernel(GmresState* st, int j, const double* __res
   st->hn = hn;
   st->inv_hn = hn > 0.0 ? 1.0 / hn : 0.0;
   st->res = fabs(st->g[j + 1]);
-  if (dev_j) st->j = j + 1;
+  st->j = j + 1;
+}
+
+
+__global__ void arnoldi_finish_kernel(GmresState* st, int j, const double* __restrict__ h1,
+                                      const double* __restrict__ h2, const double* __restrict__ nrm2) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const bool dev_j = j < 0;
+  const int jj = dev_j ? st->j : j;
+  const int keep = st->j;
+  arnoldi_column(st, jj, h1, h2, nrm2);
+  if (!dev_j) st->j = keep;
 }
 
 // y = H(0:m, 0:m)^{-1} g(0:m) (upper triangular)

@@ -10,10 +10,12 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <string>
 
 #include "arena.h"
 #include "internal.h"
+#include "tune.h"
 
 namespace abddc {
 
@@ -433,6 +435,49 @@ __global__ void __launch_bounds__(64) svd_left_kernel(const SvdDesc* __restrict_
 }  // namespace
 
 namespace {
+// Threads per eigenproblem: small orders have few rotations per round, and
+// a round costs two barriers, so fewer waves can be faster; many problems in
+// a batch also favour fewer waves each.  The autotuner picks among these
+// per (kernel, order bucket, batch bucket); ABDDC_EIG_THREADS forces one.
+constexpr int EIG_VARIANTS[3] = {64, 256, 1024};
+
+template <class Launch>
+int eig_threads(const char* name, int nmax, size_t batch, Launch launch, hipStream_t s) {
+  const char* force = std::getenv("ABDDC_EIG_THREADS");
+  if (force)
+    for (int v : EIG_VARIANTS)
+      if (std::atoi(force) == v) return v;
+  int dev = 0;
+  ABDDC_HIP(hipGetDevice(&dev));
+  const std::string key = device_arch(dev) + "|" + name + "|n" + std::to_string(size_bucket(nmax)) + "|b" +
+                          std::to_string(size_bucket((long long)batch));
+  const int cached = tune_lookup(key);
+  if (cached >= 0 && cached < 3) return EIG_VARIANTS[cached];
+  hipEvent_t e0, e1;
+  ABDDC_HIP(hipEventCreate(&e0));
+  ABDDC_HIP(hipEventCreate(&e1));
+  int best = 2;
+  float best_ms = 0.f;
+  for (int v = 0; v < 3; ++v) {
+    launch(EIG_VARIANTS[v]);   // warm-up; every launch recomputes the same outputs
+    ABDDC_HIP(hipEventRecord(e0, s));
+    launch(EIG_VARIANTS[v]);
+    launch(EIG_VARIANTS[v]);
+    ABDDC_HIP(hipEventRecord(e1, s));
+    ABDDC_HIP(hipEventSynchronize(e1));
+    float ms = 0.f;
+    ABDDC_HIP(hipEventElapsedTime(&ms, e0, e1));
+    if (v == 0 || ms < best_ms) {
+      best_ms = ms;
+      best = v;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  tune_store(key, best);
+  return EIG_VARIANTS[best];
+}
+
 // Split a descriptor list by order: n <= 64 (LDS variant) and 64 < n <= 128.
 template <class D, class F>
 void split_launch(const std::vector<D>& descs, F order, hipStream_t s, const char* what,
@@ -451,7 +496,10 @@ void pinv_batched(const std::vector<PinvDesc>& descs, double rtol, hipStream_t s
   split_launch(descs, [](const PinvDesc& d) { return d.n; }, s, "pinv", sm, bg);
   if (!sm.empty()) {
     const PinvDesc* dd = Arena::for_stream(s).put(sm);
-    pinv_kernel<64><<<sm.size(), EIG_THREADS, 0, s>>>(dd, rtol, nullptr);
+    int nmax = 0;
+    for (auto& d : sm) nmax = std::max(nmax, d.n);
+    auto go = [&](int th) { pinv_kernel<64><<<sm.size(), th, 0, s>>>(dd, rtol, nullptr); };
+    go(eig_threads("pinv", nmax, sm.size(), go, s));
   }
   if (!bg.empty()) {
     DevBuf<double> scr(bg.size() * 2 * 128 * 128);
@@ -489,7 +537,10 @@ void sygv_batched(const std::vector<SygvDesc>& descs, int* dflag, hipStream_t s)
   split_launch(descs, [](const SygvDesc& d) { return d.n; }, s, "sygv", sm, bg);
   if (!sm.empty()) {
     const SygvDesc* dd = Arena::for_stream(s).put(sm);
-    sygv_kernel<64><<<sm.size(), EIG_THREADS, 0, s>>>(dd, dflag, nullptr);
+    int nmax = 0;
+    for (auto& d : sm) nmax = std::max(nmax, d.n);
+    auto go = [&](int th) { sygv_kernel<64><<<sm.size(), th, 0, s>>>(dd, dflag, nullptr); };
+    go(eig_threads("sygv", nmax, sm.size(), go, s));
   }
   if (!bg.empty()) {
     DevBuf<double> scr(bg.size() * 2 * 128 * 128);
