@@ -249,28 +249,84 @@ __global__ void __launch_bounds__(256) plu_diag_kernel(const PluDesc<T>* __restr
   __syncthreads();
   T* gLi = scratch + (size_t)blockIdx.x * 2 * NB * NB;
   T* gUi = gLi + NB * NB;
-  if (wave == 0) {
-    T X[NB];
+  // Inverses by 32 x 32 blocks:
+  //   L^{-1} = [[L11^{-1}, 0], [-L22^{-1} (L21 L11^{-1}), L22^{-1}]]
+  //   U^{-1} = [[U11^{-1}, -U11^{-1} (U12 U22^{-1})], [0, U22^{-1}]]
+  // (1) the four diagonal-block inverses, one column per lane (wave 0:
+  //     L11, L22 in its two lane halves; wave 1: U11, U22), into E:
+  //     E11 = L11^{-1}, E22 = L22^{-1}, E21 = U11^{-1}, E12 = U22^{-1};
+  // (2) T1 = L21 E11 and T2 = U12 E12 over all waves, written over L21, U12;
+  // (3) the off-diagonal blocks -E22 T1 and -E21 T2 straight to global.
+  constexpr int H = NB / 2;
+  __shared__ T E[NB][NB + 1];
+  {
+    const int half = lane >> 5, c = lane & 31, off = half * H;
+    if (wave == 0) {
+      T X[H];
 #pragma unroll
-    for (int r = 0; r < NB; ++r) {
-      T v = T(r == lane);
+      for (int r = 0; r < H; ++r) {
+        T v = T(r == c);
 #pragma unroll
-      for (int q = 0; q < r; ++q) v -= D[r][q] * X[q];
-      X[r] = v;
+        for (int q = 0; q < r; ++q) v -= D[off + r][off + q] * X[q];
+        X[r] = v;
+      }
+#pragma unroll
+      for (int r = 0; r < H; ++r) E[off + r][off + c] = X[r];
+    } else if (wave == 1) {
+      T X[H];
+#pragma unroll
+      for (int r = H - 1; r >= 0; --r) {
+        T v = T(r == c);
+#pragma unroll
+        for (int q = r + 1; q < H; ++q) v -= D[off + r][off + q] * X[q];
+        X[r] = v * dinv[off + r];
+      }
+      // U11^{-1} -> E21 (rows H.., cols 0..), U22^{-1} -> E12 (rows 0.., cols H..)
+#pragma unroll
+      for (int r = 0; r < H; ++r) E[(1 - half) * H + r][half * H + c] = X[r];
     }
+  }
+  __syncthreads();
+  // (2) thread (i, j4): row i of a 32 x 32 product, columns j4, j4 + 8, j4 + 16, j4 + 24
+  const int pi = tid >> 3, pj = tid & 7;
+  T t1[4], t2[4];
 #pragma unroll
-    for (int r = 0; r < NB; ++r) gLi[r * NB + lane] = X[r];
-  } else if (wave == 1) {
-    T X[NB];
-#pragma unroll
-    for (int r = NB - 1; r >= 0; --r) {
-      T v = T(r == lane);
-#pragma unroll
-      for (int q = r + 1; q < NB; ++q) v -= D[r][q] * X[q];
-      X[r] = v * dinv[r];
+  for (int q = 0; q < 4; ++q) {
+    const int j = pj + 8 * q;
+    T a1 = T(0), a2 = T(0);
+#pragma unroll 8
+    for (int k = 0; k < H; ++k) {
+      a1 += D[H + pi][k] * E[k][j];            // L21 * L11^{-1}
+      a2 += D[pi][H + k] * E[k][H + j];        // U12 * U22^{-1}
     }
+    t1[q] = a1;
+    t2[q] = a2;
+  }
+  __syncthreads();
 #pragma unroll
-    for (int r = 0; r < NB; ++r) gUi[r * NB + lane] = X[r];
+  for (int q = 0; q < 4; ++q) {
+    D[H + pi][pj + 8 * q] = t1[q];
+    D[pi][H + pj + 8 * q] = t2[q];
+  }
+  __syncthreads();
+  // (3) and the block-diagonal parts and zeros
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int j = pj + 8 * q;
+    T a1 = T(0), a2 = T(0);
+#pragma unroll 8
+    for (int k = 0; k < H; ++k) {
+      a1 += E[H + pi][H + k] * D[H + k][j];    // L22^{-1} T1
+      a2 += E[H + pi][k] * D[k][H + j];        // U11^{-1} T2
+    }
+    gLi[(H + pi) * NB + j] = -a1;
+    gUi[pi * NB + H + j] = -a2;
+    gLi[pi * NB + j] = E[pi][j];
+    gLi[(H + pi) * NB + H + j] = E[H + pi][H + j];
+    gLi[pi * NB + H + j] = T(0);
+    gUi[pi * NB + j] = E[H + pi][j];
+    gUi[(H + pi) * NB + H + j] = E[pi][H + j];
+    gUi[(H + pi) * NB + j] = T(0);
   }
 }
 
