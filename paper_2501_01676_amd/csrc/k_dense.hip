@@ -440,8 +440,14 @@ __global__ void sym_kernel(const SymDesc* __restrict__ descs) {
 }  // namespace
 
 template <class T>
-void partial_lu(const std::vector<PluDesc<T>>& descs, int* dflag, hipStream_t s) {
-  if (descs.empty()) return;
+void partial_lu(const std::vector<PluDesc<T>>& descs_in, int* dflag, hipStream_t s) {
+  if (descs_in.empty()) return;
+  // largest eliminations first: on ragged batches their workgroups are
+  // dispatched first and the small ones fill in behind them
+  std::vector<PluDesc<T>> descs(descs_in);
+  std::stable_sort(descs.begin(), descs.end(), [](const PluDesc<T>& a, const PluDesc<T>& b) {
+    return (double)a.k * a.nrow * a.ncol > (double)b.k * b.nrow * b.ncol;
+  });
   int maxk = 0, maxr = 0, maxc = 0;
   for (auto& d : descs) {
     ABDDC_REQUIRE(d.k >= 0 && d.k <= d.nrow && d.k <= d.ncol && d.ld >= d.ncol, ABDDC_EINVAL,

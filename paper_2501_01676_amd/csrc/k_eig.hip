@@ -487,6 +487,10 @@ void split_launch(const std::vector<D>& descs, F order, hipStream_t s, const cha
     ABDDC_REQUIRE(n <= 128, ABDDC_EINVAL, std::string(what) + ": matrix order exceeds 128");
     (n <= 64 ? small : big).push_back(d);
   }
+  // largest problems first (ragged batches): they are dispatched first
+  auto by_size = [&](const D& a, const D& b) { return order(a) > order(b); };
+  std::stable_sort(small.begin(), small.end(), by_size);
+  std::stable_sort(big.begin(), big.end(), by_size);
   (void)s;
 }
 }  // namespace
