@@ -28,6 +28,38 @@ constexpr int KC = 32;     // K chunk staged through LDS
 constexpr int NB = 64;     // partial LU panel width
 constexpr int LDS_PAD = TILE + 1;
 
+// Tiled batched launches run on a 1-D grid renumbered for the 8 XCDs.  The
+// hardware hands workgroup w to XCD w % 8, and each XCD has its own L2, so
+// with the plain numbering neighbouring tiles of one matrix -- which read the
+// same row strip of A and column strip of B -- land on different XCDs and
+// every tile fetches its operands from HBM.  xcd_tile() instead gives each
+// XCD whole matrices (matrix z on XCD z % 8, its tiles in row-major order)
+// when the batch has at least 8 of them, and otherwise a contiguous eighth
+// of the (matrix, tile) range, so the operand strips are read from HBM about
+// once per XCD.
+constexpr int N_XCD = 8;
+
+__device__ inline bool xcd_tile(int tiles_per, int nb, int& z, int& r) {
+  const int w = blockIdx.x, x = w % N_XCD, local = w / N_XCD;
+  if (nb >= N_XCD) {
+    z = x + N_XCD * (local / tiles_per);
+    r = local % tiles_per;
+  } else {
+    const int t = x * (int)(gridDim.x / N_XCD) + local;
+    z = t / tiles_per;
+    r = t % tiles_per;
+  }
+  return z < nb;
+}
+
+// grid size for xcd_tile: a multiple of 8 covering every (matrix, tile)
+inline unsigned xcd_grid(int tiles_per, int nb) {
+  const int64_t g = nb >= N_XCD ? (int64_t)N_XCD * ((nb + N_XCD - 1) / N_XCD) * tiles_per
+                                : ((int64_t)nb * tiles_per + N_XCD - 1) / N_XCD * N_XCD;
+  ABDDC_REQUIRE(g < (int64_t(1) << 24), ABDDC_EINVAL, "batched dense launch: too many tiles");
+  return (unsigned)g;
+}
+
 typedef double v4d __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 
@@ -53,15 +85,16 @@ struct Mfma<float> {
 };
 
 // One 64x64 tile of C = alpha op(A) op(B) + beta C, op(A) m x k, op(B) k x n,
-// tile origin (row0, col0).  A wave owns a 32x32 quadrant made of 2x2 MFMA
+// tile origin (row0, col0); entries with row and column both >= kmask are
+// left unwritten.  A wave owns a 32x32 quadrant made of 2x2 MFMA
 // blocks of 16x16; lane l feeds A[l%16][k+l/16], B[k+l/16][l%16]; the
 // output rows each lane holds depend on the instruction (Mfma::out_row).  Safe in place when C aliases op(A)'s
 // rows (n <= TILE) or op(B)'s columns (m <= TILE): all reads of a tile
 // precede its writes.
 template <class T, bool TA, bool TB>
-__device__ void tile_gemm(const T* __restrict__ A, int lda, const T* __restrict__ B, int ldb, T* C,
+__device__ __forceinline__ void tile_gemm(const T* __restrict__ A, int lda, const T* __restrict__ B, int ldb, T* C,
                           int ldc, int m, int n, int k, T alpha, T beta, int row0, int col0,
-                          T (*As)[LDS_PAD], T (*Bs)[LDS_PAD]) {
+                          T (*As)[LDS_PAD], T (*Bs)[LDS_PAD], int kmask = 0x7fffffff) {
   typedef typename Mfma<T>::acc_t acc_t;
   constexpr int PER = TILE * KC / 256;   // elements of each operand per thread and chunk (8)
   const int tid = threadIdx.x;
@@ -77,9 +110,30 @@ __device__ void tile_gemm(const T* __restrict__ A, int lda, const T* __restrict_
   const int b_j0 = TB ? (tid >> 5) : (tid & 63), b_k0 = TB ? (tid & 31) : (tid >> 6);
   const int a_di = TA ? 0 : 8, a_dk = TA ? 4 : 0;
   const int b_dj = TB ? 8 : 0, b_dk = TB ? 0 : 4;
+  const int kl = lane >> 4, il = lane & 15;
+  // C is read up front, straight into the accumulator layout, so its loads
+  // overlap the first operand chunk instead of trailing the last MFMA; the
+  // accumulators start at (beta / alpha) C and the result is alpha * acc
+  // (alpha != 0).
   acc_t acc[2][2];
-  for (int i = 0; i < 2; ++i)
-    for (int j = 0; j < 2; ++j) acc[i][j] = acc_t{0, 0, 0, 0};
+  if (beta != T(0)) {
+    const T cs = beta / alpha;
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+      for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int r = row0 + wr + 16 * bi + Mfma<T>::out_row(kl, q);
+          const int c = col0 + wc + 16 * bj + il;
+          acc[bi][bj][q] = (r < m && c < n) ? cs * C[(size_t)r * ldc + c] : T(0);
+        }
+  } else {
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) acc[i][j] = acc_t{0, 0, 0, 0};
+  }
   T ra[PER], rb[PER];
   // per-thread base pointers; element q of a chunk is base + q * step
   const int ar = row0 + a_i0, bc = col0 + b_j0;
@@ -99,7 +153,6 @@ __device__ void tile_gemm(const T* __restrict__ A, int lda, const T* __restrict_
     }
   };
   if (k > 0) fetch(0);
-  const int kl = lane >> 4, il = lane & 15;
 #pragma unroll 1
   for (int k0 = 0; k0 < k; k0 += KC) {
     __syncthreads();
@@ -123,30 +176,30 @@ __device__ void tile_gemm(const T* __restrict__ A, int lda, const T* __restrict_
     }
   }
   __syncthreads();
+#pragma unroll
   for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
     for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
       for (int q = 0; q < 4; ++q) {
         int r = row0 + wr + 16 * bi + Mfma<T>::out_row(kl, q);
         int c = col0 + wc + 16 * bj + il;
-        if (r < m && c < n) {
-          T v = alpha * acc[bi][bj][q];
-          T* cp = C + (size_t)r * ldc + c;
-          if (beta != T(0)) v += beta * *cp;
-          *cp = v;
-        }
+        if (r < m && c < n && (r < kmask || c < kmask)) C[(size_t)r * ldc + c] = alpha * acc[bi][bj][q];
       }
 }
 
 template <class T, bool TA, bool TB>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) gemm_batched_kernel(const GemmDesc<T>* __restrict__ descs,
-                                                            T alpha, T beta) {
+                                                            int tiles_per, int nb, T alpha, T beta) {
   __shared__ T As[KC][LDS_PAD];
   __shared__ T Bs[KC][LDS_PAD];
-  const GemmDesc<T> d = descs[blockIdx.y];
+  int z, t;
+  if (!xcd_tile(tiles_per, nb, z, t)) return;
+  const GemmDesc<T> d = descs[z];
   const int tn = (d.n + TILE - 1) / TILE;
   const int tm = (d.m + TILE - 1) / TILE;
-  if ((int)blockIdx.x >= tm * tn) return;
-  const int ti = blockIdx.x / tn, tj = blockIdx.x % tn;
+  if (t >= tm * tn) return;
+  const int ti = t / tn, tj = t % tn;
   tile_gemm<T, TA, TB>(d.A, d.lda, d.B, d.ldb, d.C, d.ldc, d.m, d.n, d.k, alpha, beta, ti * TILE,
                        tj * TILE, As, Bs);
 }
@@ -333,17 +386,18 @@ __global__ void __launch_bounds__(256) plu_diag_kernel(const PluDesc<T>* __restr
 // Step 2: A21 <- A21 U11^{-1} (row tiles), A12 <- L11^{-1} A12 (column tiles).
 template <class T>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) plu_trsm_kernel(const PluDesc<T>* __restrict__ descs, int t0,
-                                                        const T* __restrict__ scratch) {
+                                                        const T* __restrict__ scratch, int tiles_per, int nb) {
   __shared__ T As[KC][LDS_PAD];
   __shared__ T Bs[KC][LDS_PAD];
-  const PluDesc<T> d = descs[blockIdx.y];
+  int z, t;
+  if (!xcd_tile(tiles_per, nb, z, t)) return;
+  const PluDesc<T> d = descs[z];
   if (t0 >= d.k) return;
   const int b = min(NB, d.k - t0);
   const int mr = d.nrow - t0 - b, nc = d.ncol - t0 - b;
   const int rt = (mr + TILE - 1) / TILE, ct = (nc + TILE - 1) / TILE;
-  const T* Li = scratch + (size_t)blockIdx.y * 2 * NB * NB;
+  const T* Li = scratch + (size_t)z * 2 * NB * NB;
   const T* Ui = Li + NB * NB;
-  const int t = blockIdx.x;
   if (t < rt) {
     T* C = d.a + (size_t)(t0 + b + t * TILE) * d.ld + t0;
     const int m = min(TILE, mr - t * TILE);
@@ -356,55 +410,81 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) p
   }
 }
 
-// Right-looking update after panel t0 (s = t0 + b), restricted to what is
-// still to be factored: rows [s, nrow) x cols [s, k) and rows [s, k) x
-// cols [k, ncol).  The block beyond k in both directions is formed once at
-// the end by plu_update_kernel.
+// The leading k columns are factored in 64-column panels taken in pairs.
+// After the first panel of a pair, plu_band_kernel updates only what the
+// second one needs (its column strip and its row strip, depth 64); after the
+// second, plu_lead_kernel applies both panels at depth 128 to the rest of the
+// part still to be factored.  Every matrix entry of that part is thus read
+// and written once per 128 pivots rather than once per 64.
+
+// Band update after panel [t0, s), s = t0 + b: rows [s, nrow) x cols
+// [s, s + w) and rows [s, s + w) x cols [s + w, ncol), w = min(NB, k - s).
+// Tile t < ceil((nrow - s) / TILE) is a tile of the column strip, the rest
+// are tiles of the row strip.
 template <class T>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) plu_lead_kernel(const PluDesc<T>* __restrict__ descs, int t0) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) plu_band_kernel(const PluDesc<T>* __restrict__ descs, int t0,
+                                                                                                       int tiles_per, int nb) {
   __shared__ T As[KC][LDS_PAD];
   __shared__ T Bs[KC][LDS_PAD];
-  const PluDesc<T> d = descs[blockIdx.z];
+  int z, t;
+  if (!xcd_tile(tiles_per, nb, z, t)) return;
+  const PluDesc<T> d = descs[z];
   if (t0 >= d.k) return;
   const int b = min(NB, d.k - t0), s0 = t0 + b;
   if (s0 >= d.k) return;
-  const int row0 = blockIdx.x * TILE, col0 = blockIdx.y * TILE;  // relative to s0
+  const int w = min(NB, d.k - s0);
+  const int mr = d.nrow - s0, nc = d.ncol - s0;
+  const int rtl = (mr + TILE - 1) / TILE;
+  const T* A21 = d.a + (size_t)s0 * d.ld + t0;
+  const T* A12 = d.a + (size_t)t0 * d.ld + s0;
+  T* A22 = d.a + (size_t)s0 * d.ld + s0;
+  if (t < rtl) {
+    tile_gemm<T, false, false>(A21, d.ld, A12, d.ld, A22, d.ld, mr, w, b, T(-1), T(1), t * TILE, 0, As, Bs);
+  } else {
+    const int col0 = w + (t - rtl) * TILE;
+    if (col0 >= nc) return;
+    tile_gemm<T, false, false>(A21, d.ld, A12, d.ld, A22, d.ld, w, nc, b, T(-1), T(1), 0, col0, As, Bs);
+  }
+}
+
+// Update after the pivot columns [t0, s), s = t0 + b, b = min(kb, k - t0),
+// restricted to what is still to be factored: rows [s, nrow) x cols [s, k)
+// and rows [s, k) x cols [k, ncol).  The block beyond k in both directions
+// is formed once at the end by plu_update_kernel.
+template <class T>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) plu_lead_kernel(const PluDesc<T>* __restrict__ descs, int t0,
+                                                                                                      int kb, int rt, int ct, int nb) {
+  __shared__ T As[KC][LDS_PAD];
+  __shared__ T Bs[KC][LDS_PAD];
+  int z, t;
+  if (!xcd_tile(rt * ct, nb, z, t)) return;
+  const PluDesc<T> d = descs[z];
+  if (t0 >= d.k) return;
+  const int b = min(kb, d.k - t0), s0 = t0 + b;
+  if (s0 >= d.k) return;
+  const int row0 = (t / ct) * TILE, col0 = (t % ct) * TILE;  // relative to s0
   const int mr = d.nrow - s0, nc = d.ncol - s0, kr = d.k - s0;
   if (row0 >= mr || col0 >= nc) return;
   if (row0 >= kr && col0 >= kr) return;   // tile entirely in the trailing block
   const T* A21 = d.a + (size_t)s0 * d.ld + t0;
   const T* A12 = d.a + (size_t)t0 * d.ld + s0;
   T* A22 = d.a + (size_t)s0 * d.ld + s0;
-  // Only entries with row < kr or col < kr are updated.  A tile crossing both
-  // row kr and column kr is done in two segments: rows [row0, kr) with all
-  // its columns, then rows [kr, row0 + TILE) with columns < kr.
-  int sm[2], sn[2], sr[2], nseg = 1;
-  if (row0 >= kr) {
-    sm[0] = mr; sn[0] = min(nc, kr); sr[0] = row0;
-  } else if (col0 >= kr) {
-    sm[0] = min(mr, kr); sn[0] = nc; sr[0] = row0;
-  } else if (row0 + TILE <= kr || col0 + TILE <= kr) {
-    sm[0] = mr; sn[0] = nc; sr[0] = row0;
-  } else {
-    sm[0] = kr; sn[0] = nc; sr[0] = row0;
-    sm[1] = min(mr, row0 + TILE); sn[1] = kr; sr[1] = kr;
-    nseg = 2;
-  }
-#pragma unroll 1
-  for (int g = 0; g < nseg; ++g)
-    tile_gemm<T, false, false>(A21, d.ld, A12, d.ld, A22, d.ld, sm[g], sn[g], b, T(-1), T(1), sr[g], col0, As, Bs);
+  // only entries with row < kr or col < kr are written
+  tile_gemm<T, false, false>(A21, d.ld, A12, d.ld, A22, d.ld, mr, nc, b, T(-1), T(1), row0, col0, As, Bs, kr);
 }
 
 // Trailing Schur complement A22 -= A21 A12 with K = k (one pass).
 template <class T>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) plu_update_kernel(const PluDesc<T>* __restrict__ descs) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) plu_update_kernel(const PluDesc<T>* __restrict__ descs, int rt, int ct, int nb) {
   __shared__ T As[KC][LDS_PAD];
   __shared__ T Bs[KC][LDS_PAD];
-  const PluDesc<T> d = descs[blockIdx.z];
+  int z, t;
+  if (!xcd_tile(rt * ct, nb, z, t)) return;
+  const PluDesc<T> d = descs[z];
   const int k = d.k;
   if (k == 0) return;
   const int mr = d.nrow - k, nc = d.ncol - k;
-  const int row0 = blockIdx.x * TILE, col0 = blockIdx.y * TILE;
+  const int row0 = (t / ct) * TILE, col0 = (t % ct) * TILE;
   if (row0 >= mr || col0 >= nc) return;
   const T* A21 = d.a + (size_t)k * d.ld;
   const T* A12 = d.a + k;
@@ -471,20 +551,33 @@ void partial_lu(const std::vector<PluDesc<T>>& descs_in, int* dflag, hipStream_t
     const int rem = std::max(maxr, maxc) - t0;
     const int tiles = 2 * ((rem + TILE - 1) / TILE);
     plu_diag_kernel<T><<<nb, 256, 0, s>>>(dd, t0, scr, dflag);
-    plu_trsm_kernel<T><<<dim3(std::max(tiles, 1), nb), 256, 0, s>>>(dd, t0, scr);
-    const int rt = (maxr - t0 + TILE - 1) / TILE, ct = (maxc - t0 + TILE - 1) / TILE;
-    if (t0 + NB < maxk && rt > 0 && ct > 0) {
+    plu_trsm_kernel<T><<<xcd_grid(std::max(tiles, 1), nb), 256, 0, s>>>(dd, t0, scr, std::max(tiles, 1), nb);
+    if ((t0 / NB) % 2 == 0) {
+      // first panel of a pair: the band the second panel needs
+      if (t0 + NB < maxk) {
+        const int sb = t0 + NB;
+        // column strip tiles + row strip tiles (the row strip starts at
+        // column w >= 1 of the trailing part, so it spans < maxc - sb columns)
+        const int bt = (maxr - sb + TILE - 1) / TILE + std::max(0, (maxc - sb - 1 + TILE - 1) / TILE);
+        if (bt > 0) plu_band_kernel<T><<<xcd_grid(bt, nb), 256, 0, s>>>(dd, t0, bt, nb);
+      }
+      continue;
+    }
+    // second panel of a pair: both panels, depth 2 NB
+    const int p0 = t0 - NB, sp = p0 + 2 * NB;
+    const int rt = (maxr - sp + TILE - 1) / TILE, ct = (maxc - sp + TILE - 1) / TILE;
+    if (sp < maxk && rt > 0 && ct > 0) {
       hipEvent_t ea = nullptr, eb = nullptr;
       if (g_kstats) {
         double flops = 0.0;  // rows [s, nrow) x cols [s, k) and rows [s, k) x cols [k, ncol), depth b
         for (auto& d : descs)
-          if (t0 + NB < d.k) {
-            const int sr = t0 + NB;
-            flops += 2.0 * NB * ((double)(d.nrow - sr) * (d.k - sr) + (double)(d.k - sr) * (d.ncol - d.k));
+          if (sp < d.k) {
+            flops += 2.0 * (2 * NB) * ((double)(d.nrow - sp) * (d.k - sp) + (double)(d.k - sp) * (d.ncol - d.k));
           }
         tracked_events(KC_PLU_LEAD, flops, &ea, &eb);
       }
-      hipExtLaunchKernelGGL(plu_lead_kernel<T>, dim3(rt, ct, nb), dim3(256), 0, s, ea, eb, 0, dd, t0);
+      hipExtLaunchKernelGGL(plu_lead_kernel<T>, dim3(xcd_grid(rt * ct, nb)), dim3(256), 0, s, ea, eb, 0, dd, p0,
+                            2 * NB, rt, ct, nb);
     }
   }
   // trailing Schur complement with K = k
@@ -498,7 +591,8 @@ void partial_lu(const std::vector<PluDesc<T>>& descs_in, int* dflag, hipStream_t
   if (rt > 0 && ct > 0) {
     hipEvent_t ea, eb;
     tracked_events(KC_PLU_UPDATE, flops, &ea, &eb);
-    hipExtLaunchKernelGGL(plu_update_kernel<T>, dim3(rt, ct, nb), dim3(256), 0, s, ea, eb, 0, dd);
+    hipExtLaunchKernelGGL(plu_update_kernel<T>, dim3(xcd_grid(rt * ct, nb)), dim3(256), 0, s, ea, eb, 0, dd, rt,
+                          ct, nb);
   }
   ABDDC_HIP(hipGetLastError());
 }
@@ -507,6 +601,7 @@ template <class T>
 void gemm_batched(const std::vector<GemmDesc<T>>& descs, bool transA, bool transB, T alpha, T beta,
                   hipStream_t s) {
   if (descs.empty()) return;
+  ABDDC_REQUIRE(alpha != T(0) || beta == T(0), ABDDC_EINVAL, "gemm: alpha = 0 with beta != 0");
   int maxt = 0;
   for (auto& d : descs) {
     ABDDC_REQUIRE(d.m >= 0 && d.n >= 0 && d.k >= 0, ABDDC_EINVAL, "gemm: negative size");
@@ -515,11 +610,12 @@ void gemm_batched(const std::vector<GemmDesc<T>>& descs, bool transA, bool trans
   if (maxt == 0) return;
   Arena& ar = Arena::for_stream(s);
   const GemmDesc<T>* dd = ar.put(descs);
-  dim3 grid(maxt, descs.size());
-  if (!transA && !transB) gemm_batched_kernel<T, false, false><<<grid, 256, 0, s>>>(dd, alpha, beta);
-  else if (transA && !transB) gemm_batched_kernel<T, true, false><<<grid, 256, 0, s>>>(dd, alpha, beta);
-  else if (!transA && transB) gemm_batched_kernel<T, false, true><<<grid, 256, 0, s>>>(dd, alpha, beta);
-  else gemm_batched_kernel<T, true, true><<<grid, 256, 0, s>>>(dd, alpha, beta);
+  const int nb = (int)descs.size();
+  const dim3 grid(xcd_grid(maxt, nb));
+  if (!transA && !transB) gemm_batched_kernel<T, false, false><<<grid, 256, 0, s>>>(dd, maxt, nb, alpha, beta);
+  else if (transA && !transB) gemm_batched_kernel<T, true, false><<<grid, 256, 0, s>>>(dd, maxt, nb, alpha, beta);
+  else if (!transA && transB) gemm_batched_kernel<T, false, true><<<grid, 256, 0, s>>>(dd, maxt, nb, alpha, beta);
+  else gemm_batched_kernel<T, true, true><<<grid, 256, 0, s>>>(dd, maxt, nb, alpha, beta);
   ABDDC_HIP(hipGetLastError());
 }
 

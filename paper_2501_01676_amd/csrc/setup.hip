@@ -211,43 +211,149 @@ void run_setup(abddc_ctx* c) {
     gemm_batched<double>(g3, true, false, 1.0, 1.0, s);
 
     ht.mark("Btilde_F^(nu): Schur complement of B^(");
-    // Btilde_F^(nu): Schur complement of B^(nu) onto F (eliminate Gamma_nu minus F)
-    std::vector<int64_t> eoff(2 * nf);
-    int64_t etot = 0;
-    for (int f = 0; f < nf; ++f)
-      for (int side = 0; side < 2; ++side) {
-        const int sub = T.objects[T.faces[f]].subs[side];
-        eoff[2 * f + side] = etot;
-        etot += (int64_t)c->nB[sub] * c->nB[sub];
-      }
-    DevBuf<double> E(etot);
-    IntPool pool;
-    std::vector<size_t> mapoff(2 * nf);
+    // Btilde_F^(nu): Schur complement of B^(nu) onto F, eliminating
+    // Gamma_nu minus F.  Schur complements compose (eliminating a set in two
+    // steps gives what eliminating it at once gives), so the work the faces
+    // of one subdomain share is done once:
+    //   (1) per subdomain: eliminate the edge and vertex dofs, leaving C on
+    //       the face dofs of Gamma_nu, ordered by normal axis;
+    //   (2) per (subdomain, axis): eliminate from C the faces normal to the
+    //       other axes, leaving the block of the one or two faces normal to
+    //       this axis;
+    //   (3) per face of a two-face block: eliminate the opposite face.
+    // Every step is a symmetric gather and a partial LU.  Each pivot block is
+    // a Schur complement of a principal submatrix of the one-step pivot block
+    // B_{Gamma minus F}, so it is positive definite whenever that one is.
+    auto face_axis = [&](int k) {
+      const int a = T.objects[k].subs[0], b = T.objects[k].subs[1];
+      if (a % T.nsub[0] != b % T.nsub[0]) return 0;
+      if ((a / T.nsub[0]) % T.nsub[1] != (b / T.nsub[0]) % T.nsub[1]) return 1;
+      return 2;
+    };
+    struct FacePart { int f, side, off, n, axis; };
+    struct Group { int sub, nfaces, cpos, ng; int64_t o2; int k2; size_t m2; };
+    std::vector<std::vector<FacePart>> sfaces(nsub);
     for (int f = 0; f < nf; ++f) {
       const int k = T.faces[f];
       for (int side = 0; side < 2; ++side) {
         const int sub = T.objects[k].subs[side];
-        const int off = T.sub[sub].local_pos(k), n = T.objects[k].n, nB = c->nB[sub];
-        std::vector<int32_t> mp;
-        for (int q = 0; q < nB; ++q)
-          if (q < off || q >= off + n) mp.push_back(q);
-        for (int q = 0; q < n; ++q) mp.push_back(off + q);
-        mapoff[2 * f + side] = pool.add(mp);
+        sfaces[sub].push_back({f, side, T.sub[sub].local_pos(k), T.objects[k].n, face_axis(k)});
+      }
+    }
+    IntPool pool;
+    std::vector<size_t> m1off(nsub);
+    std::vector<int> nR(nsub, 0), nC(nsub, 0);
+    std::vector<Group> groups;
+    std::vector<const double*> res(2 * nf);
+    std::vector<int> resld(2 * nf);
+    std::vector<int64_t> res3(2 * nf, -1);     // Q3 offset of a face solved in step (3)
+    std::vector<int> k3of(2 * nf, 0), ng3(2 * nf, 0), grp_of(2 * nf, -1);
+    std::vector<size_t> m3off(2 * nf);
+    int64_t w2tot = 0, w3tot = 0;
+    for (int sub = 0; sub < nsub; ++sub) {
+      std::vector<FacePart>& fp = sfaces[sub];
+      if (fp.empty()) continue;
+      std::stable_sort(fp.begin(), fp.end(), [](const FacePart& a, const FacePart& b) {
+        return a.axis != b.axis ? a.axis < b.axis : a.off < b.off;
+      });
+      const int nB = c->nB[sub];
+      std::vector<char> isface(nB, 0);
+      for (const FacePart& q : fp)
+        for (int t = 0; t < q.n; ++t) isface[q.off + t] = 1;
+      std::vector<int32_t> mp;
+      for (int t = 0; t < nB; ++t)
+        if (!isface[t]) mp.push_back(t);
+      nR[sub] = (int)mp.size();
+      std::vector<int> cpos(fp.size());
+      for (size_t i = 0; i < fp.size(); ++i) {
+        cpos[i] = (int)mp.size() - nR[sub];
+        for (int t = 0; t < fp[i].n; ++t) mp.push_back(fp[i].off + t);
+      }
+      m1off[sub] = pool.add(mp);
+      nC[sub] = nB - nR[sub];
+      for (size_t i = 0; i < fp.size();) {
+        size_t j = i + 1;
+        while (j < fp.size() && fp[j].axis == fp[i].axis) ++j;
+        Group g{sub, (int)(j - i), cpos[i], 0, w2tot, 0, 0};
+        for (size_t q = i; q < j; ++q) g.ng += fp[q].n;
+        g.k2 = nC[sub] - g.ng;
+        std::vector<int32_t> m2;
+        for (int t = 0; t < nC[sub]; ++t)
+          if (t < g.cpos || t >= g.cpos + g.ng) m2.push_back(t);
+        for (int t = 0; t < g.ng; ++t) m2.push_back(g.cpos + t);
+        g.m2 = pool.add(m2);
+        w2tot += (int64_t)nC[sub] * nC[sub];
+        const int gi = (int)groups.size();
+        groups.push_back(g);
+        int inner = 0;
+        for (size_t q = i; q < j; ++q) {
+          const int id = 2 * fp[q].f + fp[q].side;
+          grp_of[id] = gi;
+          if (g.nfaces > 1) {
+            // [the other face of the pair; this face] inside the pair block
+            std::vector<int32_t> m3;
+            for (int t = 0; t < g.ng; ++t)
+              if (t < inner || t >= inner + fp[q].n) m3.push_back(t);
+            for (int t = 0; t < fp[q].n; ++t) m3.push_back(inner + t);
+            m3off[id] = pool.add(m3);
+            res3[id] = w3tot;
+            k3of[id] = g.ng - fp[q].n;
+            ng3[id] = g.ng;
+            w3tot += (int64_t)g.ng * g.ng;
+          }
+          inner += fp[q].n;
+        }
+        i = j;
       }
     }
     pool.upload(s);
-    std::vector<GatherDesc> gd;
-    std::vector<PluDesc<double>> pd;
-    for (int f = 0; f < nf; ++f)
-      for (int side = 0; side < 2; ++side) {
-        const int sub = T.objects[T.faces[f]].subs[side];
-        const int nB = c->nB[sub], n = T.objects[T.faces[f]].n;
-        gd.push_back({c->dB.p + c->soff[sub], E.p + eoff[2 * f + side], pool.ptr(mapoff[2 * f + side]),
-                      pool.ptr(mapoff[2 * f + side]), nB, nB, nB, nB, 1.0});
-        pd.push_back({E.p + eoff[2 * f + side], nB, nB, nB, nB - n});
+    DevBuf<double> Q1(c->dB.n), Q2(std::max<int64_t>(w2tot, 1)), Q3(std::max<int64_t>(w3tot, 1));
+    {
+      std::vector<GatherDesc> gd;
+      std::vector<PluDesc<double>> pd;
+      for (int sub = 0; sub < nsub; ++sub) {
+        if (sfaces[sub].empty()) continue;
+        const int nB = c->nB[sub];
+        gd.push_back({c->dB.p + c->soff[sub], Q1.p + c->soff[sub], pool.ptr(m1off[sub]), pool.ptr(m1off[sub]), nB, nB,
+                      nB, nB, 1.0});
+        pd.push_back({Q1.p + c->soff[sub], nB, nB, nB, nR[sub]});
       }
-    gather_batched(gd, s);
-    partial_lu<double>(pd, c->d_flag.p, s);
+      gather_batched(gd, s);
+      partial_lu<double>(pd, c->d_flag.p, s);
+    }
+    {
+      std::vector<GatherDesc> gd;
+      std::vector<PluDesc<double>> pd;
+      for (const Group& g : groups) {
+        const int nB = c->nB[g.sub], n2 = nC[g.sub];
+        const double* Cb = Q1.p + c->soff[g.sub] + (int64_t)nR[g.sub] * nB + nR[g.sub];
+        gd.push_back({Cb, Q2.p + g.o2, pool.ptr(g.m2), pool.ptr(g.m2), n2, n2, nB, n2, 1.0});
+        pd.push_back({Q2.p + g.o2, n2, n2, n2, g.k2});
+      }
+      gather_batched(gd, s);
+      partial_lu<double>(pd, c->d_flag.p, s);
+    }
+    {
+      std::vector<GatherDesc> gd;
+      std::vector<PluDesc<double>> pd;
+      for (int id = 0; id < 2 * nf; ++id) {
+        const Group& g = groups[grp_of[id]];
+        const int n2 = nC[g.sub];
+        const double* Pb = Q2.p + g.o2 + (int64_t)g.k2 * n2 + g.k2;   // block of the group's faces
+        if (res3[id] < 0) {
+          res[id] = Pb;
+          resld[id] = n2;
+          continue;
+        }
+        const int ng = ng3[id], k3 = k3of[id];
+        gd.push_back({Pb, Q3.p + res3[id], pool.ptr(m3off[id]), pool.ptr(m3off[id]), ng, ng, n2, ng, 1.0});
+        pd.push_back({Q3.p + res3[id], ng, ng, ng, k3});
+        res[id] = Q3.p + res3[id] + (int64_t)k3 * ng + k3;
+        resld[id] = ng;
+      }
+      gather_batched(gd, s);
+      partial_lu<double>(pd, c->d_flag.p, s);
+    }
 
     ht.mark("parallel sum Btilde_F = A (A + B)^+ B");
     // parallel sum Btilde_F = A (A + B)^+ B
@@ -258,10 +364,9 @@ void run_setup(abddc_ctx* c) {
     for (int f = 0; f < nf; ++f) {
       const int k = T.faces[f];
       const int n = T.objects[k].n;
-      const int si = T.objects[k].subs[0], sj = T.objects[k].subs[1];
-      const int ldi = c->nB[si], ldj = c->nB[sj];
-      const double* A = E.p + eoff[2 * f] + (int64_t)(ldi - n) * ldi + (ldi - n);
-      const double* B = E.p + eoff[2 * f + 1] + (int64_t)(ldj - n) * ldj + (ldj - n);
+      const int ldi = resld[2 * f], ldj = resld[2 * f + 1];
+      const double* A = res[2 * f];
+      const double* B = res[2 * f + 1];
       ad.push_back({A, B, Sum.p + c->tfoff[f], n, n, ldi, ldj, n, 1.0, 1.0});
       pv.push_back({Sum.p + c->tfoff[f], Pinv.p + c->tfoff[f], n, n});
       h1.push_back({Pinv.p + c->tfoff[f], B, T1.p + c->tfoff[f], n, n, n, n, ldj, n});

@@ -41,11 +41,14 @@ def test_gemm_matches_numpy(transA, transB):
 def test_partial_lu_schur_complement(precision):
     api = _api()
     rng = np.random.default_rng(1)
-    cases = [(5, 3, 7), (64, 64, 65), (100, 37, 101), (200, 131, 203), (300, 300, 300)]
+    # (nrow, ncol, k): ragged batch; k around the 64-column panels and their
+    # pairs (64, 65, 128, 129, 192, 256), wide and tall matrices
+    cases = [(5, 7, 3), (64, 65, 64), (100, 101, 37), (200, 203, 131), (300, 300, 300), (260, 140, 128),
+             (129, 300, 129), (321, 257, 192), (190, 190, 65), (257, 257, 256)]
     mats, ks, refs = [], [], []
-    for n, k, nc in cases:
-        A = _posreal(n, rng)
-        M = np.concatenate([A, rng.standard_normal((n, nc - n))], axis=1)
+    for nr, nc, k in cases:
+        M = rng.standard_normal((nr, nc))
+        M[:k, :k] = _posreal(k, rng)
         mats.append(M); ks.append(k)
         A11, A12, A21, A22 = M[:k, :k], M[:k, k:], M[k:, :k], M[k:, k:]
         refs.append(A22 - A21 @ np.linalg.solve(A11, A12))
@@ -55,11 +58,17 @@ def test_partial_lu_schur_complement(precision):
         S = o[k:, k:]
         if r.size:
             assert np.abs(S - r).max() <= tol * max(1.0, np.abs(r).max())
-    # the factors reproduce A11 = L U
-    o, k, M = out[3], ks[3], mats[3]
-    L = np.tril(o[:k, :k], -1) + np.eye(k)
-    U = np.triu(o[:k, :k])
-    assert np.abs(L @ U - M[:k, :k]).max() <= (1e-11 if precision == 0 else 1e-4) * np.abs(M).max()
+    # the factors reproduce A11 = L U, A21 = L21 U, A12 = L U12
+    ftol = 1e-11 if precision == 0 else 1e-4
+    for o, k, M in zip(out, ks, mats):
+        L = np.tril(o[:k, :k], -1) + np.eye(k)
+        U = np.triu(o[:k, :k])
+        scale = np.abs(M).max()
+        assert np.abs(L @ U - M[:k, :k]).max() <= ftol * scale
+        if M.shape[0] > k:
+            assert np.abs(o[k:, :k] @ U - M[k:, :k]).max() <= ftol * scale
+        if M.shape[1] > k:
+            assert np.abs(L @ o[:k, k:] - M[:k, k:]).max() <= ftol * scale
 
 
 def test_partial_lu_inverse_trick():
