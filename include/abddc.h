@@ -301,6 +301,34 @@ int abddc_test_gemm(int32_t batch, double* buf, const int64_t* offA, const int64
 int abddc_test_sygv(int32_t batch, double* buf, const int64_t* offA, const int64_t* offB,
                     const int64_t* offW, const int64_t* offX, const int32_t* n, void* stream);
 
+/* As abddc_test_sygv, but only the columns of X whose eigenvalue is
+ * <= sel are written (the rest of X is left as it was): the solver the face
+ * and edge eigenproblems of eq. equ-4-8 and equ-5-21 use, which need only
+ * those eigenvectors.  Tridiagonalisation, bisection, inverse iteration. */
+int abddc_test_sygv_select(int32_t batch, double* buf, const int64_t* offA, const int64_t* offB,
+                           const int64_t* offW, const int64_t* offX, const int32_t* n, double sel,
+                           void* stream);
+
+/* Batched Schur complement with a pseudo-inverse, in place: for each
+ * nv[b] x nv[b] row-major FP64 DEVICE matrix M at buf + off[b] (ld nv[b]),
+ * the trailing block becomes M22 - M21 (sym M11)^+ M12, M11 the leading
+ * k[b] x k[b] block, the pseudo-inverse dropping eigenvalues <= rtol
+ * lambda_max (the eliminations of the face and edge operators, Section 3,
+ * whose eliminated blocks may be singular).  Leading rows/columns are
+ * scratch afterwards.  Returns ABDDC_ESINGULAR when a block with
+ * k[b] > 128 is not positive definite and well conditioned. */
+int abddc_test_schur_pinv(int32_t batch, double* buf, const int64_t* off, const int32_t* nv, const int32_t* k,
+                          double rtol, void* stream);
+
+/* Batched parallel sum of the face operators (Section 3, face part):
+ * out_b = sym(A_b (A_b + B_b)^+ B_b), the pseudo-inverse dropping
+ * eigenvalues <= rtol lambda_max of sym(A_b + B_b).  n x n row-major FP64
+ * DEVICE matrices in one buffer (A at offA[b], B at offB[b], out at
+ * offOut[b], ld = n[b], 1 <= n[b] <= 128).  A well-conditioned A + B takes
+ * an LU path, the rest an eigenvalue path; both give the definition. */
+int abddc_test_parallel_sum(int32_t batch, double* buf, const int64_t* offA, const int64_t* offB,
+                            const int64_t* offOut, const int32_t* n, double rtol, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -99,6 +99,9 @@ SIGNATURES = {
     "abddc_test_gemm": (C.c_int, [C.c_int32, _P, _I64P, _I64P, _I64P, _I32P, _I32P, _I32P, _I32P, _I32P,
                                   _I32P, C.c_int32, C.c_int32, C.c_double, C.c_double, _P]),
     "abddc_test_sygv": (C.c_int, [C.c_int32, _P, _I64P, _I64P, _I64P, _I64P, _I32P, _P]),
+    "abddc_test_sygv_select": (C.c_int, [C.c_int32, _P, _I64P, _I64P, _I64P, _I64P, _I32P, C.c_double, _P]),
+    "abddc_test_schur_pinv": (C.c_int, [C.c_int32, _P, _I64P, _I32P, _I32P, C.c_double, _P]),
+    "abddc_test_parallel_sum": (C.c_int, [C.c_int32, _P, _I64P, _I64P, _I64P, _I32P, C.c_double, _P]),
 }
 
 _lib = None

@@ -288,6 +288,51 @@ def gemm(As, Bs, Cs, transA=False, transB=False, alpha=1.0, beta=0.0, device="cu
     return [h[o:o + c.size].reshape(c.shape) for o, c in zip(oC, Cs)]
 
 
+def schur_pinv(mats, ks, rtol=1e-10, device="cuda"):
+    """Batched M22 - M21 (sym M11)^+ M12 (library primitive); returns the
+    trailing blocks."""
+    lib = L.load()
+    buf, offs = _pack(mats, np.float64, device)
+    rc = lib.abddc_test_schur_pinv(len(mats), _dptr(buf), L.i64(offs), L.i32([m.shape[0] for m in mats]),
+                                   L.i32(ks), float(rtol), _stream_handle())
+    L.check(rc)
+    h = buf.cpu().numpy()
+    return [h[o:o + m.size].reshape(m.shape)[k:, k:].copy() for o, m, k in zip(offs, mats, ks)]
+
+
+def parallel_sum(As, Bs, rtol=1e-10, device="cuda"):
+    """Batched sym(A (A + B)^+ B) (library primitive) on host matrices."""
+    lib = L.load()
+    n = [a.shape[0] for a in As]
+    outs = [np.zeros((k, k)) for k in n]
+    buf, offs = _pack(list(As) + list(Bs) + outs, np.float64, device)
+    nb = len(As)
+    rc = lib.abddc_test_parallel_sum(nb, _dptr(buf), L.i64(offs[:nb]), L.i64(offs[nb:2 * nb]),
+                                     L.i64(offs[2 * nb:]), L.i32(n), float(rtol), _stream_handle())
+    L.check(rc)
+    h = buf.cpu().numpy()
+    return [h[o:o + k * k].reshape(k, k) for o, k in zip(offs[2 * nb:], n)]
+
+
+def sygv_select(As, Bs, sel, device="cuda"):
+    """Every eigenvalue of A y = mu B y (ascending) and X = B Y for the
+    eigenvalues <= sel (the first columns; the others are returned as 0)."""
+    lib = L.load()
+    n = [a.shape[0] for a in As]
+    Ws = [np.zeros(k) for k in n]
+    Xs = [np.zeros((k, k)) for k in n]
+    buf, offs = _pack(list(As) + list(Bs) + Ws + Xs, np.float64, device)
+    nb = len(As)
+    rc = lib.abddc_test_sygv_select(nb, _dptr(buf), L.i64(offs[:nb]), L.i64(offs[nb:2 * nb]),
+                                    L.i64(offs[2 * nb:3 * nb]), L.i64(offs[3 * nb:]), L.i32(n), float(sel),
+                                    _stream_handle())
+    L.check(rc)
+    h = buf.cpu().numpy()
+    w = [h[o:o + k].copy() for o, k in zip(offs[2 * nb:3 * nb], n)]
+    X = [h[o:o + k * k].reshape(k, k).copy() for o, k in zip(offs[3 * nb:], n)]
+    return w, X
+
+
 def sygv(As, Bs, device="cuda"):
     lib = L.load()
     n = [a.shape[0] for a in As]

@@ -207,3 +207,50 @@ extern "C" int abddc_test_sygv(int32_t batch, double* buf, const int64_t* offA, 
     return check_flag(flag.p, s);
   });
 }
+
+extern "C" int abddc_test_parallel_sum(int32_t batch, double* buf, const int64_t* offA, const int64_t* offB,
+                                       const int64_t* offOut, const int32_t* n, double rtol, void* stream) {
+  return guarded([&]() -> int {
+    ABDDC_REQUIRE(batch >= 0 && buf && offA && offB && offOut && n, ABDDC_EINVAL, "null argument");
+    ABDDC_REQUIRE(rtol >= 0, ABDDC_EINVAL, "negative tolerance");
+    hipStream_t s = (hipStream_t)stream;
+    StreamScope ss(s);
+    std::vector<PsumDesc> d(batch);
+    for (int b = 0; b < batch; ++b) d[b] = {buf + offA[b], buf + offB[b], buf + offOut[b], n[b], n[b], n[b]};
+    parallel_sum_batched(d, rtol, s);
+    ABDDC_HIP(hipStreamSynchronize(s));
+    return ABDDC_OK;
+  });
+}
+
+extern "C" int abddc_test_sygv_select(int32_t batch, double* buf, const int64_t* offA, const int64_t* offB,
+                                      const int64_t* offW, const int64_t* offX, const int32_t* n, double sel,
+                                      void* stream) {
+  return guarded([&]() -> int {
+    ABDDC_REQUIRE(batch >= 0 && buf, ABDDC_EINVAL, "null argument");
+    hipStream_t s = (hipStream_t)stream;
+    StreamScope ss(s);
+    DevBuf<int> flag(1);
+    flag.zero(s);
+    std::vector<SygvDesc> d(batch);
+    for (int b = 0; b < batch; ++b) d[b] = {buf + offA[b], buf + offB[b], buf + offW[b], buf + offX[b], n[b]};
+    sygv_select_batched(d, sel, flag.p, s);
+    return check_flag(flag.p, s);
+  });
+}
+
+extern "C" int abddc_test_schur_pinv(int32_t batch, double* buf, const int64_t* off, const int32_t* nv,
+                                     const int32_t* k, double rtol, void* stream) {
+  return guarded([&]() -> int {
+    ABDDC_REQUIRE(batch >= 0 && buf && off && nv && k, ABDDC_EINVAL, "null argument");
+    ABDDC_REQUIRE(rtol >= 0, ABDDC_EINVAL, "negative tolerance");
+    hipStream_t s = (hipStream_t)stream;
+    StreamScope ss(s);
+    DevBuf<int> flag(1);
+    flag.zero(s);
+    std::vector<SchurPinvDesc> d(batch);
+    for (int b = 0; b < batch; ++b) d[b] = {buf + off[b], nv[b], k[b], nv[b]};
+    schur_pinv_batched(d, rtol, flag.p, s);
+    return check_flag(flag.p, s);
+  });
+}

@@ -160,11 +160,22 @@ struct SymDesc {
   int32_t n, lds, ldd;
 };
 
-// Symmetric pseudo-inverse: out = sum_{lambda > rtol lambda_max} v v^T / lambda.
-struct PinvDesc {
-  const double* M;
+// In place: M22 <- M22 - M21 (sym M11)^+ M12 for the nv x nv matrix M
+// (leading dimension ld) whose leading k x k block M11 is eliminated, the
+// pseudo-inverse dropping eigenvalues <= rtol lambda_max.
+struct SchurPinvDesc {
+  double* M;
+  int32_t nv, k, ld;
+};
+
+// Parallel sum out = sym(A (A + B)^+ B) of two n x n matrices (the face
+// operators of Section 3), pseudo-inverse dropping eigenvalues <=
+// rtol lambda_max.  A, B: ld lda / ldb; out: ld n.
+struct PsumDesc {
+  const double* A;
+  const double* B;
   double* out;
-  int32_t n, ld;
+  int32_t n, lda, ldb;
 };
 
 // Householder completion: T (n x n) orthogonal, first p columns span range(X).
@@ -206,7 +217,12 @@ void sym_batched(const std::vector<SymDesc>& d, hipStream_t s);
 
 // k_eig.hip
 void sygv_batched(const std::vector<SygvDesc>& d, int* dflag, hipStream_t s);
-void pinv_batched(const std::vector<PinvDesc>& d, double rtol, hipStream_t s);
+// Same outputs, but only the columns of X whose mu <= sel are written.
+void sygv_select_batched(const std::vector<SygvDesc>& d, double sel, int* dflag, hipStream_t s);
+void parallel_sum_batched(const std::vector<PsumDesc>& d, double rtol, hipStream_t s);
+// Matrices the test sends to the eigenvalue fallback need k <= 128; larger
+// ones set bit 1 of dflag instead.
+void schur_pinv_batched(const std::vector<SchurPinvDesc>& d, double rtol, int* dflag, hipStream_t s);
 void qr_complete_batched(const std::vector<QrDesc>& d, hipStream_t s);
 void svd_left_batched(const std::vector<SvdDesc>& d, double rtol, hipStream_t s);
 

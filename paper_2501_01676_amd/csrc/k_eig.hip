@@ -166,6 +166,160 @@ struct EigScratch {
   static __device__ inline double* V(double* base) { return base + (size_t)blockIdx.x * 2 * NM * NM + NM * NM; }
 };
 
+__device__ inline double read_lane_d(double v, int lane) {
+  const long long x = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(x & 0xffffffffll), lane);
+  const int hi = __builtin_amdgcn_readlane((int)(x >> 32), lane);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// In-place Cholesky B = L L^T of the lower triangle of L (n <= NM, leading
+// dimension ldl), in 16-column panels: wave 0 factors the panel in
+// registers (lane = row, two rows per lane for NM = 128; pivot and column
+// values broadcast by readlane, no barriers), then all threads update the
+// trailing lower triangle.  Bit 2 of dflag on a non-positive pivot.
+template <int NM>
+__device__ __forceinline__ void cholesky_panels(double* L, int ldl, int n, int* dflag) {
+  constexpr int RPL = (NM + 63) / 64;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int j0 = 0; j0 < n; j0 += 16) {
+    const int jw = min(16, n - j0);
+    if (wave == 0) {
+      double P[RPL][16];
+#pragma unroll
+      for (int sl = 0; sl < RPL; ++sl) {
+        const int r = lane + 64 * sl;
+#pragma unroll
+        for (int jj = 0; jj < 16; ++jj) P[sl][jj] = (r >= j0 && r < n && jj < jw) ? L[r * ldl + j0 + jj] : 0.0;
+      }
+#pragma unroll
+      for (int jj = 0; jj < 16; ++jj) {
+        if (jj < jw) {
+          const int pr = j0 + jj;
+          const double pv = (RPL > 1 && pr >= 64) ? read_lane_d(P[RPL - 1][jj], pr & 63) : read_lane_d(P[0][jj], pr & 63);
+          if (lane == 0 && (!(pv > 0.0) || !isfinite(pv))) atomicOr(dflag, 2);
+          const double lpp = sqrt(fmax(pv, 1e-300));
+          const double inv = 1.0 / lpp;
+#pragma unroll
+          for (int sl = 0; sl < RPL; ++sl) {
+            const int r = lane + 64 * sl;
+            if (r == pr) P[sl][jj] = lpp;
+            else if (r > pr) P[sl][jj] *= inv;
+          }
+#pragma unroll
+          for (int j2 = jj + 1; j2 < 16; ++j2) {
+            if (j2 < jw) {
+              const int cr = j0 + j2;
+              const double lc = (RPL > 1 && cr >= 64) ? read_lane_d(P[RPL - 1][jj], cr & 63)
+                                                      : read_lane_d(P[0][jj], cr & 63);
+#pragma unroll
+              for (int sl = 0; sl < RPL; ++sl) {
+                const int r = lane + 64 * sl;
+                if (r >= cr) P[sl][j2] -= P[sl][jj] * lc;
+              }
+            }
+          }
+        }
+      }
+#pragma unroll
+      for (int sl = 0; sl < RPL; ++sl) {
+        const int r = lane + 64 * sl;
+        if (r >= j0 && r < n)
+#pragma unroll
+          for (int jj = 0; jj < 16; ++jj)
+            if (jj < jw && r >= j0 + jj) L[r * ldl + j0 + jj] = P[sl][jj];
+      }
+    }
+    __syncthreads();
+    const int j1 = j0 + jw, m = n - j1;
+    for (int idx = tid; idx < m * m; idx += blockDim.x) {
+      const int r = j1 + idx / m, c = j1 + idx % m;
+      if (c > r) continue;
+      double a = 0.0;
+      for (int q = 0; q < jw; ++q) a += L[r * ldl + j0 + q] * L[c * ldl + j0 + q];
+      L[r * ldl + c] -= a;
+    }
+    __syncthreads();
+  }
+}
+
+// X <- L^{-1} X for X (n x n, LDS, leading dimension NM + 1) and the lower
+// triangular L: 16-row blocks; in each, one thread per column substitutes
+// through the block (reciprocal diagonal), then all threads update the rows
+// below.
+template <int NM>
+__device__ __forceinline__ void lower_solve_blocks(const double* L, int ldl, double (*X)[NM + 1], int n) {
+  const int tid = threadIdx.x;
+  for (int r0 = 0; r0 < n; r0 += 16) {
+    const int rw = min(16, n - r0);
+    for (int c = tid; c < n; c += blockDim.x) {
+      double x[16];
+#pragma unroll
+      for (int i = 0; i < 16; ++i) x[i] = i < rw ? X[r0 + i][c] : 0.0;
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        if (i < rw) {
+          double v = x[i];
+#pragma unroll
+          for (int q = 0; q < i; ++q) v -= L[(r0 + i) * ldl + r0 + q] * x[q];
+          x[i] = v / L[(r0 + i) * ldl + r0 + i];
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < 16; ++i)
+        if (i < rw) X[r0 + i][c] = x[i];
+    }
+    __syncthreads();
+    const int r1 = r0 + rw, m = n - r1;
+    for (int idx = tid; idx < m * n; idx += blockDim.x) {
+      const int r = r1 + idx / n, c = idx % n;
+      double a = 0.0;
+      for (int q = 0; q < rw; ++q) a += L[r * ldl + r0 + q] * X[r0 + q][c];
+      X[r][c] -= a;
+    }
+    __syncthreads();
+  }
+}
+
+// Reduction of A y = mu B y (B SPD) to standard form: B = L L^T
+// (Cholesky; bit 2 of dflag when B is not positive definite) into L
+// (leading dimension ldl), C = L^{-1} A L^{-T} (symmetrised) into Cm:
+// W = L^{-1} A, then C = L^{-1} W^T.  With park, the lower triangle of L is
+// also copied to the output X, whose LDS space the caller then reuses.
+template <int NM>
+__device__ __forceinline__ void reduce_pencil(const SygvDesc& d, double (*Cm)[NM + 1], double* L, int ldl, bool park, int* dflag) {
+  const int n = d.n, tid = threadIdx.x;
+  const int tj = tid & 63, ti = tid >> 6, nstep = blockDim.x >> 6;
+  for (int r = ti; r < n; r += nstep)
+    for (int j = tj; j < n; j += 64) {
+      L[r * ldl + j] = 0.5 * (d.B[r * n + j] + d.B[j * n + r]);
+      Cm[r][j] = 0.5 * (d.A[r * n + j] + d.A[j * n + r]);
+    }
+  __syncthreads();
+  cholesky_panels<NM>(L, ldl, n, dflag);
+  lower_solve_blocks<NM>(L, ldl, Cm, n);
+  for (int idx = tid; idx < n * n; idx += blockDim.x) {   // W -> W^T
+    const int r = idx / n, c = idx % n;
+    if (r < c) {
+      const double t = Cm[r][c];
+      Cm[r][c] = Cm[c][r];
+      Cm[c][r] = t;
+    }
+  }
+  __syncthreads();
+  lower_solve_blocks<NM>(L, ldl, Cm, n);
+  for (int r = ti; r < n; r += nstep)
+    for (int j = tj; j < n; j += 64) {
+      if (r < j) {
+        const double v = 0.5 * (Cm[r][j] + Cm[j][r]);
+        Cm[r][j] = v;
+        Cm[j][r] = v;
+      }
+      if (park && j <= r) d.X[r * n + j] = L[r * ldl + j];   // park L
+    }
+  __syncthreads();
+}
+
 // A y = mu B y, B SPD: B = L L^T (Cholesky), C = L^{-1} A L^{-T}, Jacobi
 // C = Y diag(mu) Y^T, output mu ascending and X = L Y.  NM = 64: two LDS
 // matrices, C and one that holds L until C is formed and Vt during Jacobi
@@ -188,65 +342,7 @@ __global__ void __launch_bounds__(EIG_THREADS) sygv_kernel(const SygvDesc* __res
   double* Vt = SMALL ? &LVsm[0][0] : EigScratch<NM>::V(scratch);
   const int ldl = SMALL ? NM + 1 : NM;
   const int tj = tid & 63, ti = tid >> 6, nstep = blockDim.x >> 6;
-  for (int r = ti; r < n; r += nstep)
-    for (int j = tj; j < n; j += 64) {
-      L[r * ldl + j] = 0.5 * (d.B[r * n + j] + d.B[j * n + r]);
-      Cm[r][j] = 0.5 * (d.A[r * n + j] + d.A[j * n + r]);
-    }
-  __syncthreads();
-  // right-looking Cholesky, lower triangle
-  for (int j = 0; j < n; ++j) {
-    if (tid == 0) {
-      const double djj = L[j * ldl + j];
-      if (!(djj > 0.0) || !isfinite(djj)) atomicOr(dflag, 2);
-      L[j * ldl + j] = sqrt(fmax(djj, 1e-300));
-    }
-    __syncthreads();
-    const double ljj = L[j * ldl + j];
-    for (int i = j + 1 + tid; i < n; i += blockDim.x) L[i * ldl + j] /= ljj;
-    __syncthreads();
-    for (int c = j + 1 + tj; c < n; c += 64) {
-      const double lc = L[c * ldl + j];
-      for (int i = j + 1 + ti; i < n; i += nstep)
-        if (i >= c) L[i * ldl + c] -= L[i * ldl + j] * lc;
-    }
-    __syncthreads();
-  }
-  // W = L^{-1} A (columns in place), then Z = L^{-1} W^T (rows of W in
-  // place).  Sixteen lanes share one column (row): lane l sums the terms
-  // q = l mod 16 of each substitution step and writes the solved entries
-  // r = l mod 16, so every value a lane reads back is one it wrote itself.
-  {
-    const int g = tid >> 4, l = tid & 15, ng = blockDim.x >> 4;
-    for (int c = g; c < n; c += ng)
-      for (int r = 0; r < n; ++r) {
-        double part = 0.0;
-        for (int q = l; q < r; q += 16) part += L[r * ldl + q] * Cm[q][c];
-        for (int m = 8; m > 0; m >>= 1) part += __shfl_xor(part, m, 16);
-        const double v = (Cm[r][c] - part) / L[r * ldl + r];
-        if ((r & 15) == l) Cm[r][c] = v;
-      }
-    __syncthreads();
-    for (int jr = g; jr < n; jr += ng)
-      for (int r = 0; r < n; ++r) {
-        double part = 0.0;
-        for (int q = l; q < r; q += 16) part += L[r * ldl + q] * Cm[jr][q];
-        for (int m = 8; m > 0; m >>= 1) part += __shfl_xor(part, m, 16);
-        const double v = (Cm[jr][r] - part) / L[r * ldl + r];
-        if ((r & 15) == l) Cm[jr][r] = v;
-      }
-    __syncthreads();
-  }
-  for (int r = ti; r < n; r += nstep)
-    for (int j = tj; j < n; j += 64) {
-      if (r < j) {
-        const double v = 0.5 * (Cm[r][j] + Cm[j][r]);
-        Cm[r][j] = v;
-        Cm[j][r] = v;
-      }
-      if (SMALL && j <= r) d.X[r * n + j] = L[r * ldl + j];   // park L
-    }
-  __syncthreads();
+  reduce_pencil<NM>(d, Cm, L, ldl, SMALL, dflag);
   jacobi<NM>(Cm, Vt, ldl, n, cs, sn, pp, qq, &nrot);
   // outputs: mu ascending, X[:, rank(i)] = L y_i
   for (int i = tid; i < n; i += blockDim.x) {
@@ -272,44 +368,544 @@ __global__ void __launch_bounds__(EIG_THREADS) sygv_kernel(const SygvDesc* __res
   }
 }
 
-// out = sum over kept eigenpairs of v v^T / lambda (lambda > rtol lambda_max)
+// ------------------------------------------- selected generalized eigenpairs
+// A y = mu B y with every eigenvalue but only the eigenvectors of mu <= sel
+// (the adaptive constraints of eq. equ-4-8 and equ-5-21 use just those).
+// After the reduction C = L^{-1} A L^{-T}:
+//   (1) Householder tridiagonalisation C = Q T Q^T (reflectors kept in the
+//       columns of C below the subdiagonal);
+//   (2) each eigenvalue of T by bisection on the Sturm count (one thread
+//       per eigenvalue; the k-th smallest directly, so ascending order);
+//   (3) for each selected eigenvalue, inverse iteration on T - mu I (LU with
+//       partial pivoting of the tridiagonal matrix, three solves), vectors
+//       of a cluster (gap below 1e-3 ||T||) orthogonalised against the
+//       cluster's earlier ones (modified Gram-Schmidt);
+//   (4) back-transformation z = Q y and output X = L z, as the full solver.
+// Work per problem: about (4/3) n^3 for (1), against tens of n^3 for Jacobi.
+constexpr int SEL_THREADS = 256;
+
+// Sturm count: number of eigenvalues of T (diagonal dg, off-diagonal od)
+// below x.  A pivot within pivmin of zero is replaced by -pivmin.
+__device__ inline int sturm_count(const double* dg, const double* od, int n, double x, double pivmin) {
+  int cnt = 0;
+  double q = dg[0] - x;
+  if (fabs(q) < pivmin) q = -pivmin;
+  cnt += q < 0.0;
+  for (int i = 1; i < n; ++i) {
+    q = (dg[i] - x) - od[i - 1] * od[i - 1] / q;
+    if (fabs(q) < pivmin) q = -pivmin;
+    cnt += q < 0.0;
+  }
+  return cnt;
+}
+
+__device__ inline double block_sum_sel(double v, double* red) {
+  v = wave_sum64(v);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double t = 0.0;
+  for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += red[w];
+  return t;
+}
+
+__device__ inline void block_sum5(double* v, double* red) {
+#pragma unroll
+  for (int q = 0; q < 5; ++q) v[q] = wave_sum64(v[q]);
+  __syncthreads();
+  const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  if ((threadIdx.x & 63) == 0)
+#pragma unroll
+    for (int q = 0; q < 5; ++q) red[q * 16 + w] = v[q];
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < 5; ++q) {
+    double t = 0.0;
+    for (int i = 0; i < nw; ++i) t += red[q * 16 + i];
+    v[q] = t;
+  }
+}
+
+// Householder tridiagonalisation C = Q T Q^T of the symmetric C (LDS):
+// T's diagonal in dg, off-diagonal in od; reflector k is I - tau_k v v^T
+// with v = (1, v_2..) on rows k+1.., its tail kept in column k of C below
+// the subdiagonal.  One step reads C once for x (the column below the
+// diagonal), the first column of the active block and its product with x,
+// so that the Householder vector, C v and v^T C v follow from one block
+// reduction; then the rank-2 update C -= v w^T + w v^T.  Three barriers per
+// step.  q1, q2, xs: NM doubles each; red: 80 doubles.
 template <int NM>
-__global__ void __launch_bounds__(EIG_THREADS) pinv_kernel(const PinvDesc* __restrict__ descs, double rtol,
-                                                   double* __restrict__ scratch) {
+__device__ __forceinline__ void tridiagonalize(double (*Cm)[NM + 1], int n, double* dg, double* od, double* tau,
+                                               double* q1, double* q2, double* xs, double* red) {
+  constexpr int TPR = SEL_THREADS / NM;
+  const int tid = threadIdx.x;
+  for (int k = 0; k + 2 < n; ++k) {
+    const int m = n - k - 1;
+    double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};   // |x~|^2, x~ . C x~, x~ . C e0, alpha, c00
+    {
+      const int r = tid / TPR, h = tid % TPR;
+      if (r < m) {
+        const int i = k + 1 + r;
+        double a = 0.0;
+        for (int j = 1 + h; j < m; j += TPR) a += Cm[i][k + 1 + j] * Cm[k + 1 + j][k];
+#pragma unroll
+        for (int o = TPR / 2; o > 0; o >>= 1) a += __shfl_xor(a, o, TPR);
+        if (h == 0) {
+          const double xr = Cm[i][k], c0 = Cm[i][k + 1];
+          q1[r] = c0;
+          q2[r] = a;
+          xs[r] = xr;
+          if (r > 0) {
+            acc[0] = xr * xr;
+            acc[1] = xr * a;
+            acc[2] = xr * c0;
+          } else {
+            acc[3] = xr;
+            acc[4] = c0;
+          }
+        }
+      }
+    }
+    block_sum5(acc, red);
+    const double xn2 = acc[0], alpha = acc[3];
+    if (xn2 == 0.0) {   // nothing below the subdiagonal: H = I
+      if (tid == 0) {
+        dg[k] = Cm[k][k];
+        od[k] = alpha;
+        tau[k] = 0.0;
+      }
+      continue;
+    }
+    const double beta = -copysign(sqrt(alpha * alpha + xn2), alpha);
+    const double t = (beta - alpha) / beta, sc = 1.0 / (alpha - beta);
+    const double vcv = acc[4] + 2.0 * sc * acc[2] + sc * sc * acc[1];
+    const double K = 0.5 * t * t * vcv;
+    if (tid == 0) {
+      dg[k] = Cm[k][k];
+      od[k] = beta;
+      tau[k] = t;
+    }
+    for (int idx = tid; idx < m * m; idx += blockDim.x) {
+      const int r = idx / m, c = idx - r * m;
+      const double vr = r == 0 ? 1.0 : sc * xs[r], vc = c == 0 ? 1.0 : sc * xs[c];
+      const double wr = t * (q1[r] + sc * q2[r]) - K * vr, wc = t * (q1[c] + sc * q2[c]) - K * vc;
+      Cm[k + 1 + r][k + 1 + c] -= vr * wc + wr * vc;
+    }
+    for (int r = 1 + tid; r < m; r += blockDim.x) Cm[k + 1 + r][k] = sc * xs[r];
+    __syncthreads();
+  }
+  if (tid == 0) {
+    if (n >= 2) {
+      dg[n - 2] = Cm[n - 2][n - 2];
+      od[n - 2] = Cm[n - 1][n - 2];
+      tau[n - 2] = 0.0;
+    }
+    dg[n - 1] = Cm[n - 1][n - 1];
+    od[n - 1] = 0.0;
+    tau[n - 1] = 0.0;
+  }
+  __syncthreads();
+}
+
+// Sturm counts at four points at once (four independent recurrences).
+__device__ inline void sturm4(const double* dg, const double* od, int n, const double* x, int* cnt, double pivmin) {
+  double q[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    q[c] = dg[0] - x[c];
+    if (fabs(q[c]) < pivmin) q[c] = -pivmin;
+    cnt[c] = q[c] < 0.0;
+  }
+  for (int i = 1; i < n; ++i) {
+    const double e2 = od[i - 1] * od[i - 1], di = dg[i];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      q[c] = (di - x[c]) - e2 / q[c];
+      if (fabs(q[c]) < pivmin) q[c] = -pivmin;
+      cnt[c] += q[c] < 0.0;
+    }
+  }
+}
+
+// Every eigenvalue of the tridiagonal T by multisection on the Sturm count:
+// G threads per eigenvalue (a power of two, G n <= block size), four points
+// each, so a round cuts the bracket into 4G + 1 pieces; the k-th smallest
+// eigenvalue is bracketed directly.  Stops at 2 eps max(||T||, |lambda|).
+__device__ inline void bisect_all(const double* dg, const double* od, int n, double* lam) {
+  const int tid = threadIdx.x;
+  double glo = 0.0, ghi = 0.0, emax2 = 0.0;
+  for (int i = 0; i < n; ++i) {
+    const double r = (i > 0 ? fabs(od[i - 1]) : 0.0) + (i + 1 < n ? fabs(od[i]) : 0.0);
+    glo = i == 0 ? dg[i] - r : fmin(glo, dg[i] - r);
+    ghi = i == 0 ? dg[i] + r : fmax(ghi, dg[i] + r);
+    if (i + 1 < n) emax2 = fmax(emax2, od[i] * od[i]);
+  }
+  const double eps = 1.1102230246251565e-16;   // 2^-53
+  const double tnorm = fmax(fabs(glo), fabs(ghi));
+  const double pivmin = 2.2250738585072014e-308 * fmax(1.0, emax2) / eps;
+  glo -= 2.0 * eps * tnorm + 2.0 * pivmin;
+  ghi += 2.0 * eps * tnorm + 2.0 * pivmin;
+  const double atol = 2.0 * eps * tnorm + 4.0 * pivmin;
+  int G = 1;
+  while (G < 64 && 2 * G * n <= (int)blockDim.x) G *= 2;
+  const int e = tid / G, g = tid % G;
+  if (e >= n) return;
+  double lo = glo, hi = ghi;
+  for (int round = 0; round < 80; ++round) {
+    if (hi - lo <= fmax(atol, 2.0 * eps * fmax(fabs(lo), fabs(hi)))) break;
+    const double h = (hi - lo) / (double)(4 * G + 1);
+    double x[4];
+    int cnt[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) x[c] = lo + (double)(4 * g + c + 1) * h;
+    sturm4(dg, od, n, x, cnt, pivmin);
+    double nlo = lo, nhi = hi;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      if (x[c] <= lo || x[c] >= hi) continue;
+      if (cnt[c] > e) nhi = fmin(nhi, x[c]);
+      else nlo = fmax(nlo, x[c]);
+    }
+    for (int o = G / 2; o > 0; o >>= 1) {
+      nlo = fmax(nlo, __shfl_xor(nlo, o, G));
+      nhi = fmin(nhi, __shfl_xor(nhi, o, G));
+    }
+    if (nhi - nlo >= hi - lo) break;   // no progress left in floating point
+    lo = nlo;
+    hi = nhi;
+  }
+  if (g == 0) lam[e] = 0.5 * (lo + hi);
+}
+
+template <int NM>
+__global__ void __launch_bounds__(SEL_THREADS) sygv_sel_kernel(const SygvDesc* __restrict__ descs, double sel,
+                                                               int* dflag, double* __restrict__ scratch) {
+  constexpr bool SMALL = NM <= 64;
+  __shared__ double Cm[NM][NM + 1];
+  __shared__ double LZsm[SMALL ? NM : 1][SMALL ? NM + 1 : 1];
+  __shared__ double dg[NM], od[NM], tau[NM], pv[NM], vv[NM], lam[NM];
+  __shared__ double ud[NM], u1[NM], u2[NM], ml[NM], yv[NM];
+  __shared__ int pivs[NM];
+  __shared__ double red[80];
+  const SygvDesc d = descs[blockIdx.x];
+  const int n = d.n, tid = threadIdx.x;
+  if (n <= 0) return;
+  double* L = SMALL ? &LZsm[0][0] : EigScratch<NM>::L(scratch);
+  const int ldl = SMALL ? NM + 1 : NM;
+  reduce_pencil<NM>(d, Cm, L, ldl, SMALL, dflag);
+  // Z: selected vectors (row j = vector j), LDS for the small variant
+  double* Z = SMALL ? &LZsm[0][0] : EigScratch<NM>::V(scratch);
+  const int ldz = SMALL ? NM + 1 : NM;
+
+  // (1) tridiagonalisation, (2) eigenvalues
+  tridiagonalize<NM>(Cm, n, dg, od, tau, pv, vv, ud, red);
+  bisect_all(dg, od, n, lam);
+  __syncthreads();
+  if (tid == 0)   // equal eigenvalues may come out a rounding apart in either order
+    for (int i = 1; i < n; ++i) {
+      const double v = lam[i];
+      int j = i - 1;
+      while (j >= 0 && lam[j] > v) {
+        lam[j + 1] = lam[j];
+        --j;
+      }
+      lam[j + 1] = v;
+    }
+  __syncthreads();
+  for (int t = tid; t < n; t += blockDim.x) d.w[t] = lam[t];
+  int p = 0;
+  while (p < n && lam[p] <= sel) ++p;
+  double tnorm = 0.0;
+  for (int i = 0; i < n; ++i)
+    tnorm = fmax(tnorm, fabs(dg[i]) + (i > 0 ? fabs(od[i - 1]) : 0.0) + (i + 1 < n ? fabs(od[i]) : 0.0));
+  const double eps = 1.1102230246251565e-16;   // 2^-53
+
+  // (3) inverse iteration for the selected eigenvalues
+  const double ortol = 1e-3 * tnorm;
+  for (int j = 0; j < p; ++j) {
+    int c0 = j;   // first vector of j's cluster
+    while (c0 > 0 && lam[c0] - lam[c0 - 1] <= ortol) --c0;
+    if (tid == 0) {
+      // LU with partial pivoting of T - lam_j I: row i of U has diagonal
+      // ud, first and second superdiagonals u1, u2; ml multipliers, pivs
+      // row interchanges
+      const double x = lam[j];
+      double a = dg[0] - x, b = n > 1 ? od[0] : 0.0;
+      for (int i = 0; i + 1 < n; ++i) {
+        const double c = od[i];                        // T[i+1][i]
+        const double a1 = dg[i + 1] - x, b1 = i + 2 < n ? od[i + 1] : 0.0;
+        if (fabs(a) >= fabs(c)) {
+          const double l = (a != 0.0) ? c / a : 0.0;
+          ud[i] = a; u1[i] = b; u2[i] = 0.0; ml[i] = l; pivs[i] = 0;
+          a = a1 - l * b;
+          b = b1;
+        } else {
+          const double l = a / c;
+          ud[i] = c; u1[i] = a1; u2[i] = b1; ml[i] = l; pivs[i] = 1;
+          a = b - l * a1;
+          b = -l * b1;
+        }
+      }
+      ud[n - 1] = a; u1[n - 1] = 0.0; u2[n - 1] = 0.0;
+      const double tiny = eps * (tnorm > 0.0 ? tnorm : 1.0);
+      for (int i = 0; i < n; ++i) {   // ud holds reciprocal pivots from here on
+        const double u = fabs(ud[i]) < tiny ? (ud[i] < 0.0 ? -tiny : tiny) : ud[i];
+        ud[i] = 1.0 / u;
+      }
+      // start vector: a fixed pseudo-random sequence in (-1, 1)
+      unsigned st = 0x9E3779B9u * (unsigned)(j + 1);
+      for (int i = 0; i < n; ++i) {
+        st = st * 1664525u + 1013904223u;
+        yv[i] = ((double)(st >> 8) / 16777216.0) * 2.0 - 1.0;
+      }
+    }
+    __syncthreads();
+    for (int it = 0; it < 3; ++it) {
+      if (tid == 0) {
+        // forward: interchanges and multipliers, row i + 1 carried in a register
+        double cur = yv[0];
+        for (int i = 0; i + 1 < n; ++i) {
+          const double nx = yv[i + 1];
+          if (pivs[i]) {
+            yv[i] = nx;
+            cur -= ml[i] * nx;
+          } else {
+            yv[i] = cur;
+            cur = nx - ml[i] * cur;
+          }
+        }
+        yv[n - 1] = cur;
+        // back substitution with the three bands of U (reciprocal pivots);
+        // near-singular shifts make the solution grow by 1/tiny per small
+        // pivot, so the whole system is rescaled before it could overflow
+        double c1 = 0.0, c2 = 0.0;
+        for (int i = n - 1; i >= 0; --i) {
+          double v = (yv[i] - u1[i] * c1 - u2[i] * c2) * ud[i];
+          for (int g = 0; g < 4 && !(fabs(v) <= 1e150); ++g) {
+            for (int q = 0; q < n; ++q) yv[q] *= 1e-150;
+            c1 *= 1e-150;
+            c2 *= 1e-150;
+            v = (yv[i] - u1[i] * c1 - u2[i] * c2) * ud[i];
+          }
+          yv[i] = v;
+          c2 = c1;
+          c1 = v;
+        }
+      }
+      __syncthreads();
+      // orthogonalise against the cluster's earlier vectors, normalise
+      for (int q = c0; q < j; ++q) {
+        double part = 0.0;
+        for (int i = tid; i < n; i += blockDim.x) part += Z[q * ldz + i] * yv[i];
+        const double dq = block_sum_sel(part, red);
+        for (int i = tid; i < n; i += blockDim.x) yv[i] -= dq * Z[q * ldz + i];
+        __syncthreads();
+      }
+      double part = 0.0;
+      for (int i = tid; i < n; i += blockDim.x) part += yv[i] * yv[i];
+      const double nrm = sqrt(block_sum_sel(part, red));
+      const double inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
+      for (int i = tid; i < n; i += blockDim.x) yv[i] *= inv;
+      __syncthreads();
+    }
+    for (int i = tid; i < n; i += blockDim.x) Z[j * ldz + i] = yv[i];
+    __syncthreads();
+  }
+
+  // (4) z = H_0 H_1 ... H_{n-3} y: each wave takes whole vectors and applies
+  // the reflectors from the last to the first (no block barriers); lane l
+  // owns the entries i = l mod 64 throughout, so no entry changes hands
+  {
+    const int wv = tid >> 6, lane = tid & 63, nw = blockDim.x >> 6;
+    for (int j = wv; j < p; j += nw) {
+      double* z = Z + (size_t)j * ldz;
+      for (int k = n - 3; k >= 0; --k) {
+        const double tk = tau[k];
+        if (tk == 0.0) continue;
+        double part = 0.0;
+        for (int i = lane; i < n; i += 64)
+          if (i > k) part += ((i == k + 1) ? 1.0 : Cm[i][k]) * z[i];
+        part = wave_sum64(part);
+        const double f = tk * __shfl(part, 0, 64);
+        for (int i = lane; i < n; i += 64)
+          if (i > k) z[i] -= f * ((i == k + 1) ? 1.0 : Cm[i][k]);
+      }
+    }
+  }
+  __syncthreads();
+  // X[:, j] = L z_j (L read back into Cm for the small variant)
+  if (SMALL) {
+    const int tj = tid & 63, ti = tid >> 6, nstep = blockDim.x >> 6;
+    for (int r = ti; r < n; r += nstep)
+      for (int j = tj; j <= r; j += 64) Cm[r][j] = d.X[r * n + j];
+    __syncthreads();
+  }
+  const double* Lr = SMALL ? &Cm[0][0] : L;
+  const int ldr = SMALL ? NM + 1 : NM;
+  for (int idx = tid; idx < n * p; idx += blockDim.x) {
+    const int r = idx / p, j = idx - r * p;
+    double v = 0.0;
+    for (int q = 0; q <= r; ++q) v += Lr[r * ldr + q] * Z[j * ldz + q];
+    d.X[r * n + j] = v;
+  }
+}
+
+// ------------------------------------- Schur complement with pseudo-inverse
+// M22 - M21 (sym M11)^+ M12 for M = [[M11, M12], [M21, M22]] (M11 of order
+// k), the pseudo-inverse dropping eigenvalues <= rtol lambda_max.  When
+// M11 is positive definite with ||M11||_F ||M11^{-1}||_F < 1 / rtol (that
+// product bounds lambda_max / lambda_min), the pseudo-inverse keeps every
+// eigenvalue and equals M11^{-1}: one partial LU of
+//   [[M11, M12, I], [M21, M22, 0], [-I, 0, 0]]
+// gives the Schur complement and, in its last block, M11^{-1} for the test
+// (positive pivots = positive definite, M11 being symmetric up to
+// rounding).  A matrix that fails is flagged and takes the eigenvalue
+// pseudo-inverse (Jacobi) instead.  The result overwrites M22.
+
+struct SchurWork {
+  SchurPinvDesc d;
+  double* G;      // (nv + k)^2 augmented matrix, ld nv + k
+  double* work;   // k x max(k, nv - k) (fallback)
+  int32_t* flag;  // 1: take the fallback
+};
+
+__global__ void __launch_bounds__(256) spinv_build_kernel(const SchurWork* __restrict__ ws) {
+  const SchurWork w = ws[blockIdx.x];
+  const int nv = w.d.nv, k = w.d.k, ng = nv + k;
+  for (int idx = threadIdx.x; idx < ng * ng; idx += blockDim.x) {
+    const int r = idx / ng, c = idx - r * ng;
+    double v;
+    if (r < nv) v = c < nv ? w.d.M[(size_t)r * w.d.ld + c] : ((r < k && c - nv == r) ? 1.0 : 0.0);
+    else v = (c < k && r - nv == c) ? -1.0 : 0.0;
+    w.G[idx] = v;
+  }
+}
+
+__device__ inline double block_sum256(double v, double* red) {
+  v = wave_sum64(v);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  return red[0] + red[1] + red[2] + red[3];
+}
+
+__global__ void __launch_bounds__(256) spinv_finish_kernel(const SchurWork* __restrict__ ws, double rtol, int* dflag) {
+  __shared__ double red[4];
+  __shared__ int bad;
+  const SchurWork w = ws[blockIdx.x];
+  const int nv = w.d.nv, k = w.d.k, ng = nv + k, m = nv - k;
+  if (threadIdx.x == 0) bad = 0;
+  __syncthreads();
+  double fs = 0.0, fi = 0.0;
+  for (int idx = threadIdx.x; idx < k * k; idx += blockDim.x) {
+    const int i = idx / k, j = idx - i * k;
+    const double sv = w.d.M[(size_t)i * w.d.ld + j];
+    const double iv = w.G[(size_t)(nv + i) * ng + nv + j];
+    fs += sv * sv;
+    fi += iv * iv;
+  }
+  for (int i = threadIdx.x; i < k; i += blockDim.x)
+    if (!(w.G[(size_t)i * ng + i] > 0.0)) bad = 1;   // a non-positive pivot: not positive definite
+  fs = block_sum256(fs, red);
+  __syncthreads();
+  fi = block_sum256(fi, red);
+  const double prod = sqrt(fs) * sqrt(fi);
+  const bool ok = !bad && isfinite(prod) && prod * rtol < 1.0;
+  if (threadIdx.x == 0) {
+    *w.flag = ok ? 0 : 1;
+    if (!ok && k > 128) atomicOr(dflag, 1);
+  }
+  if (!ok) return;
+  for (int idx = threadIdx.x; idx < m * m; idx += blockDim.x) {
+    const int i = idx / m, j = idx - i * m;
+    w.d.M[(size_t)(k + i) * w.d.ld + k + j] = w.G[(size_t)(k + i) * ng + k + j];
+  }
+}
+
+// Fallback for flagged matrices: sym(M11) = V diag(lambda) V^T (Jacobi),
+// P = sum over lambda > rtol lambda_max of v v^T / lambda, M22 -= M21 P M12.
+template <int NM>
+__global__ void __launch_bounds__(EIG_THREADS) spinv_fallback_kernel(const SchurWork* __restrict__ ws, double rtol,
+                                                             double* __restrict__ scratch) {
   constexpr bool SMALL = NM <= 64;
   __shared__ double Am[NM][NM + 1];
   __shared__ double Vsm[SMALL ? NM : 1][SMALL ? NM + 1 : 1];
   __shared__ double cs[NM / 2], sn[NM / 2];
   __shared__ int pp[NM / 2], qq[NM / 2];
   __shared__ int nrot;
+  __shared__ double lam[NM];
   __shared__ double lmax;
-  const PinvDesc d = descs[blockIdx.x];
-  const int n = d.n, tid = threadIdx.x;
-  if (n <= 0) return;
+  const SchurWork w = ws[blockIdx.x];
+  const int nv = w.d.nv, k = w.d.k, m = nv - k, ld = w.d.ld, tid = threadIdx.x;
+  if (k <= 0 || *w.flag == 0) return;
+  double* M = w.d.M;
   double* Vt = SMALL ? &Vsm[0][0] : EigScratch<NM>::V(scratch);
   const int ldv = SMALL ? NM + 1 : NM;
   const int tj = tid & 63, ti = tid >> 6, nstep = blockDim.x >> 6;
-  for (int r = ti; r < n; r += nstep)
-    for (int j = tj; j < n; j += 64) Am[r][j] = 0.5 * (d.M[r * d.ld + j] + d.M[j * d.ld + r]);
+  for (int r = ti; r < k; r += nstep)
+    for (int j = tj; j < k; j += 64) Am[r][j] = 0.5 * (M[(size_t)r * ld + j] + M[(size_t)j * ld + r]);
   __syncthreads();
-  jacobi<NM>(Am, Vt, ldv, n, cs, sn, pp, qq, &nrot);
+  jacobi<NM>(Am, Vt, ldv, k, cs, sn, pp, qq, &nrot);
+  for (int i = tid; i < k; i += blockDim.x) lam[i] = Am[i][i];
+  __syncthreads();
   if (tid == 0) {
     double mx = 0.0;
-    for (int i = 0; i < n; ++i) mx = fmax(mx, Am[i][i]);
+    for (int i = 0; i < k; ++i) mx = fmax(mx, lam[i]);
     lmax = mx;
   }
   __syncthreads();
   const double cut = rtol * lmax;
-  for (int r = ti; r < n; r += nstep)
-    for (int j = tj; j < n; j += 64) {
+  // P -> Am (k x k)
+  for (int r = ti; r < k; r += nstep)
+    for (int j = tj; j < k; j += 64) {
       double v = 0.0;
       if (lmax > 0.0)
-        for (int k = 0; k < n; ++k) {
-          const double lam = Am[k][k];
-          if (lam > cut) v += Vt[k * ldv + r] * Vt[k * ldv + j] / lam;
-        }
-      d.out[r * d.ld + j] = v;
+        for (int q = 0; q < k; ++q)
+          if (lam[q] > cut) v += Vt[q * ldv + r] * Vt[q * ldv + j] / lam[q];
+      Am[r][j] = v;
     }
+  __syncthreads();
+  // work = P M12 (k x m), then M22 -= M21 work
+  for (int r = ti; r < k; r += nstep)
+    for (int j = tj; j < m; j += 64) {
+      double v = 0.0;
+      for (int q = 0; q < k; ++q) v += Am[r][q] * M[(size_t)q * ld + k + j];
+      w.work[(size_t)r * m + j] = v;
+    }
+  __syncthreads();
+  for (int r = ti; r < m; r += nstep)
+    for (int j = tj; j < m; j += 64) {
+      double v = 0.0;
+      for (int q = 0; q < k; ++q) v += M[(size_t)(k + r) * ld + q] * w.work[(size_t)q * m + j];
+      M[(size_t)(k + r) * ld + k + j] -= v;
+    }
+}
+
+// Parallel sum pieces: [[A + B, B], [-A, 0]] (its pseudo-inverse Schur
+// complement is A (A + B)^+ B), and out = sym of that block.
+__global__ void __launch_bounds__(256) psum_pack_kernel(const PsumDesc* __restrict__ ds, double* __restrict__ buf,
+                                                        const int64_t* __restrict__ off) {
+  const PsumDesc d = ds[blockIdx.x];
+  const int n = d.n, n2 = 2 * n;
+  double* M = buf + off[blockIdx.x];
+  for (int idx = threadIdx.x; idx < n2 * n2; idx += blockDim.x) {
+    const int r = idx / n2, c = idx - r * n2;
+    double v = 0.0;
+    if (r < n) v = c < n ? d.A[r * d.lda + c] + d.B[r * d.ldb + c] : d.B[r * d.ldb + c - n];
+    else if (c < n) v = -d.A[(r - n) * d.lda + c];
+    M[idx] = v;
+  }
+}
+
+__global__ void __launch_bounds__(256) psum_sym_kernel(const PsumDesc* __restrict__ ds, const double* __restrict__ buf,
+                                                       const int64_t* __restrict__ off) {
+  const PsumDesc d = ds[blockIdx.x];
+  const int n = d.n, n2 = 2 * n;
+  const double* T = buf + off[blockIdx.x] + (size_t)n * n2 + n;
+  for (int idx = threadIdx.x; idx < n * n; idx += blockDim.x) {
+    const int i = idx / n, j = idx - i * n;
+    d.out[idx] = 0.5 * (T[(size_t)i * n2 + j] + T[(size_t)j * n2 + i]);
+  }
 }
 
 // Householder QR of X (n x p), accumulated into Q = H_0 H_1 ... H_{p-1}
@@ -495,20 +1091,88 @@ void split_launch(const std::vector<D>& descs, F order, hipStream_t s, const cha
 }
 }  // namespace
 
-void pinv_batched(const std::vector<PinvDesc>& descs, double rtol, hipStream_t s) {
-  std::vector<PinvDesc> sm, bg;
-  split_launch(descs, [](const PinvDesc& d) { return d.n; }, s, "pinv", sm, bg);
+void schur_pinv_batched(const std::vector<SchurPinvDesc>& descs, double rtol, int* dflag, hipStream_t s) {
+  if (descs.empty()) return;
+  int64_t gtot = 0, wtot = 0;
+  for (auto& d : descs) {
+    ABDDC_REQUIRE(d.k >= 0 && d.k <= d.nv && d.ld >= d.nv, ABDDC_EINVAL, "pinv Schur complement: bad shape");
+    gtot += (int64_t)(d.nv + d.k) * (d.nv + d.k);
+    wtot += (int64_t)d.k * std::max(d.k, d.nv - d.k);
+  }
+  const int nb = (int)descs.size();
+  DevBuf<double> G(std::max<int64_t>(gtot, 1)), work(std::max<int64_t>(wtot, 1));
+  DevBuf<int32_t> flags(nb), lu_flag(1);
+  lu_flag.zero(s);
+  std::vector<SchurWork> ws(nb);
+  std::vector<PluDesc<double>> pd(nb);
+  int64_t go = 0, wo = 0;
+  for (int b = 0; b < nb; ++b) {
+    const int ng = descs[b].nv + descs[b].k;
+    ws[b] = {descs[b], G.p + go, work.p + wo, flags.p + b};
+    pd[b] = {G.p + go, ng, ng, ng, descs[b].k};
+    go += (int64_t)ng * ng;
+    wo += (int64_t)descs[b].k * std::max(descs[b].k, descs[b].nv - descs[b].k);
+  }
+  Arena& ar = Arena::for_stream(s);
+  const SchurWork* dw = ar.put(ws);
+  spinv_build_kernel<<<nb, 256, 0, s>>>(dw);
+  // a zero or non-finite pivot only sends the matrix to the fallback: the
+  // finish kernel sees a non-positive pivot or a non-finite ||M11^{-1}||
+  partial_lu<double>(pd, lu_flag.p, s);
+  spinv_finish_kernel<<<nb, 256, 0, s>>>(dw, rtol, dflag);
+  // the eigenvalue fallback exists for k <= 128; a larger block that fails
+  // the test is reported through dflag by the finish kernel
+  std::vector<SchurWork> small_k;
+  for (auto& w : ws)
+    if (w.d.k <= 128) small_k.push_back(w);
+  std::vector<SchurWork> sm, bg;
+  split_launch(small_k, [](const SchurWork& w) { return w.d.k; }, s, "pinv Schur complement", sm, bg);
   if (!sm.empty()) {
-    const PinvDesc* dd = Arena::for_stream(s).put(sm);
-    int nmax = 0;
-    for (auto& d : sm) nmax = std::max(nmax, d.n);
-    auto go = [&](int th) { pinv_kernel<64><<<sm.size(), th, 0, s>>>(dd, rtol, nullptr); };
-    go(eig_threads("pinv", nmax, sm.size(), go, s));
+    const SchurWork* dd = ar.put(sm);
+    spinv_fallback_kernel<64><<<sm.size(), EIG_THREADS, 0, s>>>(dd, rtol, nullptr);
   }
   if (!bg.empty()) {
     DevBuf<double> scr(bg.size() * 2 * 128 * 128);
-    const PinvDesc* dd = Arena::for_stream(s).put(bg);
-    pinv_kernel<128><<<bg.size(), EIG_THREADS, 0, s>>>(dd, rtol, scr.p);
+    const SchurWork* dd = ar.put(bg);
+    spinv_fallback_kernel<128><<<bg.size(), EIG_THREADS, 0, s>>>(dd, rtol, scr.p);
+  }
+  ABDDC_HIP(hipGetLastError());
+}
+
+void parallel_sum_batched(const std::vector<PsumDesc>& descs, double rtol, hipStream_t s) {
+  if (descs.empty()) return;
+  const int nb = (int)descs.size();
+  std::vector<int64_t> off(nb);
+  int64_t tot = 0;
+  for (int b = 0; b < nb; ++b) {
+    ABDDC_REQUIRE(descs[b].n >= 1 && descs[b].n <= 128, ABDDC_EINVAL, "parallel sum: order outside [1, 128]");
+    off[b] = tot;
+    tot += (int64_t)4 * descs[b].n * descs[b].n;
+  }
+  DevBuf<double> M(tot);
+  Arena& ar = Arena::for_stream(s);
+  const PsumDesc* dd = ar.put(descs);
+  const int64_t* doff = ar.put(off);
+  psum_pack_kernel<<<nb, 256, 0, s>>>(dd, M.p, doff);
+  std::vector<SchurPinvDesc> sd(nb);
+  for (int b = 0; b < nb; ++b) sd[b] = {M.p + off[b], 2 * descs[b].n, descs[b].n, 2 * descs[b].n};
+  DevBuf<int> unused(1);
+  schur_pinv_batched(sd, rtol, unused.p, s);
+  psum_sym_kernel<<<nb, 256, 0, s>>>(dd, M.p, doff);
+  ABDDC_HIP(hipGetLastError());
+}
+
+void sygv_select_batched(const std::vector<SygvDesc>& descs, double sel, int* dflag, hipStream_t s) {
+  std::vector<SygvDesc> sm, bg;
+  split_launch(descs, [](const SygvDesc& d) { return d.n; }, s, "sygv", sm, bg);
+  if (!sm.empty()) {
+    const SygvDesc* dd = Arena::for_stream(s).put(sm);
+    sygv_sel_kernel<64><<<sm.size(), SEL_THREADS, 0, s>>>(dd, sel, dflag, nullptr);
+  }
+  if (!bg.empty()) {
+    DevBuf<double> scr(bg.size() * 2 * 128 * 128);
+    const SygvDesc* dd = Arena::for_stream(s).put(bg);
+    sygv_sel_kernel<128><<<bg.size(), SEL_THREADS, 0, s>>>(dd, sel, dflag, scr.p);
   }
   ABDDC_HIP(hipGetLastError());
 }

@@ -9,6 +9,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdlib>
 #include <cmath>
 
 #include "apply.h"
@@ -39,6 +40,18 @@ struct IntPool {
   }
   const int32_t* ptr(size_t off) const { return d.p + off; }
 };
+
+// Generalized eigenproblems of the face / edge constraints: every mu, and
+// the eigenvectors of mu <= sel (the only ones the constraints use).
+// ABDDC_SYGV_JACOBI=1 takes the full Jacobi solver instead (all vectors).
+void eig_selected(const std::vector<SygvDesc>& gv, double sel, int* dflag, hipStream_t s) {
+  static const bool jacobi = [] {
+    const char* e = std::getenv("ABDDC_SYGV_JACOBI");
+    return e && *e == '1';
+  }();
+  if (jacobi) sygv_batched(gv, dflag, s);
+  else sygv_select_batched(gv, sel, dflag, s);
+}
 
 void record(abddc_ctx* c, int i) {
   if (c->events) ABDDC_HIP(hipEventRecord(c->ev[i], c->stream));
@@ -191,7 +204,7 @@ void run_setup(abddc_ctx* c) {
   }
   c->dTF.alloc(std::max<int64_t>(ftot, 1));
   if (nf > 0) {
-    DevBuf<double> W1(ftot), W2(ftot), BF(ftot), Sum(ftot), Pinv(ftot), T1(ftot), Bt(ftot), XF(ftot);
+    DevBuf<double> W1(ftot), W2(ftot), BF(ftot), Sum(ftot), XF(ftot);
     ht.mark("B_F = D_j^T B_F^(i) D_j + D_i^T B_F^(j");
     // B_F = D_j^T B_F^(i) D_j + D_i^T B_F^(j) D_i
     std::vector<GemmDesc<double>> g1, g2, g3;
@@ -356,28 +369,12 @@ void run_setup(abddc_ctx* c) {
     }
 
     ht.mark("parallel sum Btilde_F = A (A + B)^+ B");
-    // parallel sum Btilde_F = A (A + B)^+ B
-    std::vector<AxpbyDesc> ad;
-    std::vector<PinvDesc> pv;
-    std::vector<GemmDesc<double>> h1, h2;
-    std::vector<SymDesc> sy;
-    for (int f = 0; f < nf; ++f) {
-      const int k = T.faces[f];
-      const int n = T.objects[k].n;
-      const int ldi = resld[2 * f], ldj = resld[2 * f + 1];
-      const double* A = res[2 * f];
-      const double* B = res[2 * f + 1];
-      ad.push_back({A, B, Sum.p + c->tfoff[f], n, n, ldi, ldj, n, 1.0, 1.0});
-      pv.push_back({Sum.p + c->tfoff[f], Pinv.p + c->tfoff[f], n, n});
-      h1.push_back({Pinv.p + c->tfoff[f], B, T1.p + c->tfoff[f], n, n, n, n, ldj, n});
-      h2.push_back({A, T1.p + c->tfoff[f], Bt.p + c->tfoff[f], n, n, n, ldi, n, n});
-      sy.push_back({Bt.p + c->tfoff[f], Sum.p + c->tfoff[f], n, n, n});
-    }
-    axpby_batched(ad, s);
-    pinv_batched(pv, c->opt.pinv_rtol, s);
-    gemm_batched<double>(h1, false, false, 1.0, 0.0, s);
-    gemm_batched<double>(h2, false, false, 1.0, 0.0, s);
-    sym_batched(sy, s);  // Sum now holds sym(Btilde_F)
+    // parallel sum Btilde_F = sym(A (A + B)^+ B) into Sum
+    std::vector<PsumDesc> ps;
+    for (int f = 0; f < nf; ++f)
+      ps.push_back({res[2 * f], res[2 * f + 1], Sum.p + c->tfoff[f], T.objects[T.faces[f]].n, resld[2 * f],
+                    resld[2 * f + 1]});
+    parallel_sum_batched(ps, c->opt.pinv_rtol, s);
 
     ht.mark("Btilde_F y = mu B_F y");
     // Btilde_F y = mu B_F y
@@ -385,7 +382,7 @@ void run_setup(abddc_ctx* c) {
     for (int f = 0; f < nf; ++f)
       gv.push_back({Sum.p + c->tfoff[f], BF.p + c->tfoff[f], c->dWF.p + c->wfoff[f], XF.p + c->tfoff[f],
                     T.objects[T.faces[f]].n});
-    sygv_batched(gv, c->d_flag.p, s);
+    eig_selected(gv, 1.0 / c->opt.theta_face, c->d_flag.p, s);
     std::vector<double> mu = to_host(c->dWF.p, c->dWF.n, s);
     require_flag_clean(c, "deluxe / face elimination / face eigenproblem");
     std::vector<QrDesc> qd;
@@ -594,7 +591,7 @@ void run_setup(abddc_ctx* c) {
     DevBuf<double> ME(std::max<int64_t>(metot, 1)), Qb(std::max<int64_t>(qtot, 1)), Btt(std::max<int64_t>(metot, 1)),
         XE(std::max<int64_t>(metot, 1));
     std::vector<EdgeAsmDesc> ea;
-    std::vector<PluDesc<double>> pd;
+    std::vector<SchurPinvDesc> pd;
     std::vector<SymDesc> sy;
     for (int e : elist) {
       const int k = T.edges[e];
@@ -619,11 +616,14 @@ void run_setup(abddc_ctx* c) {
       d.Q = Qb.p + qoff[e];
       ea.push_back(d);
       const int nw = (d.m - 1) * d.nE;
-      pd.push_back({Qb.p + qoff[e], d.nv, d.nv, d.nv, d.nv - nw});
+      pd.push_back({Qb.p + qoff[e], d.nv, d.nv - nw, d.nv});
       sy.push_back({Qb.p + qoff[e] + (int64_t)(d.nv - nw) * d.nv + (d.nv - nw), Btt.p + meoff[e], nw, d.nv, nw});
     }
     edge_assemble_batched(ea, s);
-    partial_lu<double>(pd, c->d_flag.p, s);
+    // the eliminated block [reference edge dofs; H] can be singular (a face
+    // primal coordinate dependent on the others): pseudo-inverse, as in the
+    // parallel sum
+    schur_pinv_batched(pd, c->opt.pinv_rtol, c->d_flag.p, s);
     sym_batched(sy, s);
     std::vector<SygvDesc> gv;
     for (int e : elist) {
@@ -631,7 +631,7 @@ void run_setup(abddc_ctx* c) {
       const int nw = (int)(o.subs.size() - 1) * o.n;
       gv.push_back({Btt.p + meoff[e], ME.p + meoff[e], c->dWE.p + c->weoff[e], XE.p + meoff[e], nw});
     }
-    sygv_batched(gv, c->d_flag.p, s);
+    eig_selected(gv, 1.0 / c->opt.theta_edge, c->d_flag.p, s);
     std::vector<double> mu = to_host(c->dWE.p, c->dWE.n, s);
     require_flag_clean(c, "edge elimination / edge eigenproblem");
     ht.mark("G = [g_{l,k}] (n_E x (m-1) |N_E|) and ");

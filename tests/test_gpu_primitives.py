@@ -82,6 +82,79 @@ def test_partial_lu_inverse_trick():
     assert np.abs(out[n:, n:] - np.linalg.inv(A)).max() <= 1e-10 * np.abs(np.linalg.inv(A)).max()
 
 
+def _pinv_ref(S, rtol):
+    lam, V = np.linalg.eigh(0.5 * (S + S.T))
+    keep = lam > rtol * lam.max()
+    return (V[:, keep] / lam[keep]) @ V[:, keep].T
+
+
+def test_parallel_sum_lu_and_eigen_paths():
+    """sym(A (A + B)^+ B) for a ragged batch mixing the three kinds of face:
+    A + B well conditioned (LU path), singular (a shared null vector) and
+    nonsingular with an eigenvalue below the cut (both eigenvalue path);
+    orders on both sides of 64."""
+    api = _api()
+    rng = np.random.default_rng(5)
+    rtol = 1e-10
+    As, Bs, refs, kinds = [], [], [], []
+    for i, n in enumerate((1, 7, 49, 64, 65, 100, 121, 128, 49, 121, 7, 96)):
+        kind = i % 3 if n > 2 else 0
+        Q = np.linalg.qr(rng.standard_normal((n, n)))[0]
+        if kind == 0:
+            s = rng.uniform(0.1, 1.0, n)
+        elif kind == 1:
+            s = np.concatenate([[0.0], rng.uniform(0.1, 1.0, n - 1)])
+        else:
+            s = np.concatenate([[1e-12], rng.uniform(0.1, 1.0, n - 1)])
+        S = (Q * s) @ Q.T
+        t = rng.uniform(0.3, 0.7)
+        # a symmetric split of S that keeps its small eigenspace: E lives on
+        # the span of the eigenvectors with s > 1e-3
+        F = rng.standard_normal((n, n)) * 0.01
+        P = Q[:, s > 1e-3] @ Q[:, s > 1e-3].T
+        E = P @ (F + F.T) @ P
+        A = t * S + E
+        B = (1 - t) * S - E
+        As.append(A); Bs.append(B); kinds.append(kind)
+        refs.append(0.5 * ((A @ _pinv_ref(A + B, rtol) @ B) + (A @ _pinv_ref(A + B, rtol) @ B).T))
+    out = api.parallel_sum(As, Bs, rtol)
+    for o, r, kind in zip(out, refs, kinds):
+        assert np.abs(o - r).max() <= 1e-11 * max(1.0, np.abs(r).max()), (kind, np.abs(o - r).max())
+
+
+def test_schur_pinv_singular_and_regular_blocks():
+    """M22 - M21 (sym M11)^+ M12 for a ragged batch: M11 positive definite
+    (LU path), singular with a null space of dimension 1 or 3, indefinite
+    (negative eigenvalues dropped), and k = 0 or k = nv."""
+    api = _api()
+    rng = np.random.default_rng(6)
+    rtol = 1e-10
+    mats, ks, refs = [], [], []
+    cases = [(10, 4, "spd"), (74, 47, "null1"), (60, 33, "null3"), (90, 64, "indef"), (150, 100, "spd"),
+             (150, 100, "null1"), (8, 0, "spd"), (12, 12, "spd"), (200, 128, "null1")]
+    for nv, k, kind in cases:
+        M = rng.standard_normal((nv, nv))
+        if k:
+            Q = np.linalg.qr(rng.standard_normal((k, k)))[0]
+            lam = rng.uniform(0.1, 1.0, k)
+            if kind == "null1":
+                lam[0] = 0.0
+            elif kind == "null3":
+                lam[:3] = 0.0
+            elif kind == "indef":
+                lam[:2] = -0.5
+            M[:k, :k] = (Q * lam) @ Q.T
+        mats.append(M); ks.append(k)
+        if k:
+            refs.append(M[k:, k:] - M[k:, :k] @ _pinv_ref(M[:k, :k], rtol) @ M[:k, k:])
+        else:
+            refs.append(M.copy())
+    out = api.schur_pinv(mats, ks, rtol)
+    for o, r, (nv, k, kind) in zip(out, refs, cases):
+        if r.size:
+            assert np.abs(o - r).max() <= 1e-10 * max(1.0, np.abs(r).max()), (nv, k, kind, np.abs(o - r).max())
+
+
 def test_sygv_matches_eigen_equation():
     api = _api()
     rng = np.random.default_rng(3)
@@ -99,3 +172,47 @@ def test_sygv_matches_eigen_equation():
         V = np.linalg.solve(B, X)     # X = B v
         assert np.abs(V.T @ B @ V - np.eye(len(w))).max() <= 1e-10
         assert np.abs(A @ V - B @ V * w).max() <= 1e-9 * np.abs(A).max()
+
+
+def test_sygv_select_eigenvalues_and_selected_vectors():
+    """Tridiagonalisation + bisection + inverse iteration: every eigenvalue,
+    and B-orthonormal eigenvectors (X = B V) for mu <= sel, including
+    multiple eigenvalues across the selection (clusters) and singular A."""
+    api = _api()
+    rng = np.random.default_rng(4)
+    sel = 0.1
+    As, Bs, mus = [], [], []
+    for n in (1, 2, 3, 7, 21, 49, 64, 65, 100, 121, 128):
+        mu = rng.uniform(0.0, 1.0, n)
+        if n >= 7:
+            mu[:3] = 0.0                       # null space of A
+            mu[3:6] = 0.05                     # a triple eigenvalue below sel
+            mu[6] = 0.05 + 1e-9                # and one just beside it
+        if n >= 21:
+            mu[7:9] = 0.5                      # double eigenvalue above sel
+            mu[9] = 0.099                      # near the cut, below
+            mu[10] = 0.101                     # near the cut, above
+        Q = np.linalg.qr(rng.standard_normal((n, n)))[0]
+        V = Q * rng.uniform(0.5, 2.0, n)        # cond(B) <= 16
+        Vi = np.linalg.inv(V)
+        B = Vi.T @ Vi
+        A = Vi.T @ np.diag(mu) @ Vi
+        As.append(0.5 * (A + A.T)); Bs.append(0.5 * (B + B.T)); mus.append(np.sort(mu))
+    ws, Xs = api.sygv_select(As, Bs, sel)
+    for A, B, mu, w, X in zip(As, Bs, mus, ws, Xs):
+        n = len(w)
+        Lc = np.linalg.cholesky(B)
+        Li = np.linalg.inv(Lc)
+        ref = np.linalg.eigvalsh(Li @ A @ Li.T)
+        scale = max(1.0, np.abs(ref).max())
+        assert np.all(np.diff(w) >= 0)
+        assert np.abs(w - ref).max() <= 1e-12 * scale, (n, np.abs(w - ref).max())
+        p = int(np.sum(w <= sel))
+        assert p == int(np.sum(ref <= sel))
+        if p == 0:
+            continue
+        Vs = np.linalg.solve(B, X[:, :p])      # X = B v
+        assert np.abs(Vs.T @ B @ Vs - np.eye(p)).max() <= 1e-10, n
+        res = A @ Vs - B @ Vs * w[:p]
+        assert np.abs(res).max() <= 1e-10 * max(np.abs(A).max(), np.abs(B).max()), (n, np.abs(res).max())
+
