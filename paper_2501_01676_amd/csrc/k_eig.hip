@@ -27,6 +27,31 @@ constexpr int NMAX = 64;
 constexpr int EIG_THREADS = 1024;
 constexpr int LDN = NMAX + 1;
 
+// Wave total by DPP: an inclusive scan inside each 16-lane row (row_shr 1,
+// 2, 4, 8), then row 0 into row 1 and row 2 into row 3 (row_bcast 15), then
+// rows 0-1 into rows 2-3 (row_bcast 31); lane 63 holds the total, which is
+// broadcast.  Every lane of the wave must be active.
+template <int CTRL, int RMASK>
+__device__ inline double dpp_d(double v) {
+  const long long x = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(x & 0xffffffffll), CTRL, RMASK, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(x >> 32), CTRL, RMASK, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+__device__ inline double wave_total(double v) {
+  v += dpp_d<0x111, 0xF>(v);
+  v += dpp_d<0x112, 0xF>(v);
+  v += dpp_d<0x114, 0xF>(v);
+  v += dpp_d<0x118, 0xF>(v);
+  v += dpp_d<0x142, 0xA>(v);
+  v += dpp_d<0x143, 0xC>(v);
+  const long long x = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(x & 0xffffffffll), 63);
+  const int hi = __builtin_amdgcn_readlane((int)(x >> 32), 63);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
 __device__ inline double wave_sum64(double v) {
   for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
   return v;
@@ -374,8 +399,8 @@ __global__ void __launch_bounds__(EIG_THREADS) sygv_kernel(const SygvDesc* __res
 // After the reduction C = L^{-1} A L^{-T}:
 //   (1) Householder tridiagonalisation C = Q T Q^T (reflectors kept in the
 //       columns of C below the subdiagonal);
-//   (2) each eigenvalue of T by bisection on the Sturm count (one thread
-//       per eigenvalue; the k-th smallest directly, so ascending order);
+//   (2) each eigenvalue of T by multisection on the Sturm count (the k-th
+//       smallest bracketed directly, so ascending order);
 //   (3) for each selected eigenvalue, inverse iteration on T - mu I (LU with
 //       partial pivoting of the tridiagonal matrix, three solves), vectors
 //       of a cluster (gap below 1e-3 ||T||) orthogonalised against the
@@ -384,23 +409,8 @@ __global__ void __launch_bounds__(EIG_THREADS) sygv_kernel(const SygvDesc* __res
 // Work per problem: about (4/3) n^3 for (1), against tens of n^3 for Jacobi.
 constexpr int SEL_THREADS = 256;
 
-// Sturm count: number of eigenvalues of T (diagonal dg, off-diagonal od)
-// below x.  A pivot within pivmin of zero is replaced by -pivmin.
-__device__ inline int sturm_count(const double* dg, const double* od, int n, double x, double pivmin) {
-  int cnt = 0;
-  double q = dg[0] - x;
-  if (fabs(q) < pivmin) q = -pivmin;
-  cnt += q < 0.0;
-  for (int i = 1; i < n; ++i) {
-    q = (dg[i] - x) - od[i - 1] * od[i - 1] / q;
-    if (fabs(q) < pivmin) q = -pivmin;
-    cnt += q < 0.0;
-  }
-  return cnt;
-}
-
 __device__ inline double block_sum_sel(double v, double* red) {
-  v = wave_sum64(v);
+  v = wave_total(v);
   __syncthreads();
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
   __syncthreads();
@@ -411,7 +421,7 @@ __device__ inline double block_sum_sel(double v, double* red) {
 
 __device__ inline void block_sum5(double* v, double* red) {
 #pragma unroll
-  for (int q = 0; q < 5; ++q) v[q] = wave_sum64(v[q]);
+  for (int q = 0; q < 5; ++q) v[q] = wave_total(v[q]);
   __syncthreads();
   const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
   if ((threadIdx.x & 63) == 0)
@@ -432,38 +442,43 @@ __device__ inline void block_sum5(double* v, double* red) {
 // the subdiagonal.  One step reads C once for x (the column below the
 // diagonal), the first column of the active block and its product with x,
 // so that the Householder vector, C v and v^T C v follow from one block
-// reduction; then the rank-2 update C -= v w^T + w v^T.  Three barriers per
+// reduction; then the rank-2 update C -= v w^T + w v^T.  Four barriers per
 // step.  q1, q2, xs: NM doubles each; red: 80 doubles.
-template <int NM>
+template <int NM, int NT>
 __device__ __forceinline__ void tridiagonalize(double (*Cm)[NM + 1], int n, double* dg, double* od, double* tau,
                                                double* q1, double* q2, double* xs, double* red) {
-  constexpr int TPR = SEL_THREADS / NM;
-  const int tid = threadIdx.x;
+  constexpr int P = NT / NM;   // column chunks of the matrix-vector product
+  __shared__ double qp[P * NM];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, nw = NT >> 6;
   for (int k = 0; k + 2 < n; ++k) {
     const int m = n - k - 1;
-    double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};   // |x~|^2, x~ . C x~, x~ . C e0, alpha, c00
+    // q2_r = sum_{j >= 1} C[j][r] x_j (C symmetric: lanes on consecutive r,
+    // conflict-free), split into P column chunks summed through LDS
     {
-      const int r = tid / TPR, h = tid % TPR;
-      if (r < m) {
-        const int i = k + 1 + r;
-        double a = 0.0;
-        for (int j = 1 + h; j < m; j += TPR) a += Cm[i][k + 1 + j] * Cm[k + 1 + j][k];
+      const int r = tid % NM, part = tid / NM;
+      double a = 0.0;
+      if (r < m)
+        for (int j = 1 + part; j < m; j += P) a += Cm[k + 1 + j][k + 1 + r] * Cm[k + 1 + j][k];
+      qp[part * NM + r] = a;
+    }
+    __syncthreads();
+    double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};   // |x~|^2, x~ . C x~, x~ . C e0, alpha, c00
+    if (tid < m) {
+      const int r = tid, i = k + 1 + r;
+      double a = 0.0;
 #pragma unroll
-        for (int o = TPR / 2; o > 0; o >>= 1) a += __shfl_xor(a, o, TPR);
-        if (h == 0) {
-          const double xr = Cm[i][k], c0 = Cm[i][k + 1];
-          q1[r] = c0;
-          q2[r] = a;
-          xs[r] = xr;
-          if (r > 0) {
-            acc[0] = xr * xr;
-            acc[1] = xr * a;
-            acc[2] = xr * c0;
-          } else {
-            acc[3] = xr;
-            acc[4] = c0;
-          }
-        }
+      for (int q = 0; q < P; ++q) a += qp[q * NM + r];
+      const double xr = Cm[i][k], c0 = Cm[i][k + 1];
+      q1[r] = c0;
+      q2[r] = a;
+      xs[r] = xr;
+      if (r > 0) {
+        acc[0] = xr * xr;
+        acc[1] = xr * a;
+        acc[2] = xr * c0;
+      } else {
+        acc[3] = xr;
+        acc[4] = c0;
       }
     }
     block_sum5(acc, red);
@@ -485,11 +500,14 @@ __device__ __forceinline__ void tridiagonalize(double (*Cm)[NM + 1], int n, doub
       od[k] = beta;
       tau[k] = t;
     }
-    for (int idx = tid; idx < m * m; idx += blockDim.x) {
-      const int r = idx / m, c = idx - r * m;
-      const double vr = r == 0 ? 1.0 : sc * xs[r], vc = c == 0 ? 1.0 : sc * xs[c];
-      const double wr = t * (q1[r] + sc * q2[r]) - K * vr, wc = t * (q1[c] + sc * q2[c]) - K * vc;
-      Cm[k + 1 + r][k + 1 + c] -= vr * wc + wr * vc;
+    for (int r = wv; r < m; r += nw) {
+      const double vr = r == 0 ? 1.0 : sc * xs[r];
+      const double wr = t * (q1[r] + sc * q2[r]) - K * vr;
+      for (int c = lane; c < m; c += 64) {
+        const double vc = c == 0 ? 1.0 : sc * xs[c];
+        const double wc = t * (q1[c] + sc * q2[c]) - K * vc;
+        Cm[k + 1 + r][k + 1 + c] -= vr * wc + wr * vc;
+      }
     }
     for (int r = 1 + tid; r < m; r += blockDim.x) Cm[k + 1 + r][k] = sc * xs[r];
     __syncthreads();
@@ -507,30 +525,50 @@ __device__ __forceinline__ void tridiagonalize(double (*Cm)[NM + 1], int n, doub
   __syncthreads();
 }
 
-// Sturm counts at four points at once (four independent recurrences).
-__device__ inline void sturm4(const double* dg, const double* od, int n, const double* x, int* cnt, double pivmin) {
-  double q[4];
+// Sturm count at x: the number of negative ratios q_i = p_i / p_{i-1} of
+// consecutive leading principal minors of T - x I, p_i = (d_i - x) p_{i-1}
+// - e_{i-1}^2 p_{i-2}, which is the number of eigenvalues below x.  Carried
+// as minors, not ratios, so a step costs two multiply-adds instead of a
+// division; a ratio of magnitude below pivmin is replaced by -pivmin, and
+// every eight steps the pair (p_{i-1}, p_i) is rescaled by a power of two,
+// which keeps it in range without changing a sign or a ratio.  The eight
+// steps' diagonal and squared off-diagonal entries are loaded up front.
+__device__ inline int sturm_count(const double* dg, const double* od, int n, double x, double pivmin) {
+  double pm = 1.0, pc = dg[0] - x;
+  if (fabs(pc) < pivmin) pc = -pivmin;
+  int cnt = pc < 0.0;
+  for (int i0 = 1; i0 < n; i0 += 8) {
+    double dv[8], ev[8];
 #pragma unroll
-  for (int c = 0; c < 4; ++c) {
-    q[c] = dg[0] - x[c];
-    if (fabs(q[c]) < pivmin) q[c] = -pivmin;
-    cnt[c] = q[c] < 0.0;
-  }
-  for (int i = 1; i < n; ++i) {
-    const double e2 = od[i - 1] * od[i - 1], di = dg[i];
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      q[c] = (di - x[c]) - e2 / q[c];
-      if (fabs(q[c]) < pivmin) q[c] = -pivmin;
-      cnt[c] += q[c] < 0.0;
+    for (int u = 0; u < 8; ++u) {
+      const int i = min(i0 + u, n - 1);
+      dv[u] = dg[i];
+      ev[u] = od[i - 1] * od[i - 1];
     }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      if (i0 + u < n) {
+        double pn = (dv[u] - x) * pc - ev[u] * pm;
+        if (fabs(pn) < pivmin * fabs(pc)) pn = -pivmin * pc;
+        cnt += (pn < 0.0) != (pc < 0.0);
+        pm = pc;
+        pc = pn;
+      }
+    }
+    int ex;
+    frexp(fmax(fabs(pm), fabs(pc)), &ex);
+    pm = ldexp(pm, -ex);
+    pc = ldexp(pc, -ex);
   }
+  return cnt;
 }
 
 // Every eigenvalue of the tridiagonal T by multisection on the Sturm count:
-// G threads per eigenvalue (a power of two, G n <= block size), four points
-// each, so a round cuts the bracket into 4G + 1 pieces; the k-th smallest
-// eigenvalue is bracketed directly.  Stops at 2 eps max(||T||, |lambda|).
+// G threads per eigenvalue (a power of two, G n <= 256: the counts are
+// arithmetic-bound, and one wave per SIMD keeps every SIMD busy without
+// queueing), one point each, so a round cuts the bracket into G + 1
+// pieces; the k-th smallest eigenvalue is bracketed directly.  Stops at
+// 2 eps max(||T||, |lambda|).
 __device__ inline void bisect_all(const double* dg, const double* od, int n, double* lam) {
   const int tid = threadIdx.x;
   double glo = 0.0, ghi = 0.0, emax2 = 0.0;
@@ -547,24 +585,19 @@ __device__ inline void bisect_all(const double* dg, const double* od, int n, dou
   ghi += 2.0 * eps * tnorm + 2.0 * pivmin;
   const double atol = 2.0 * eps * tnorm + 4.0 * pivmin;
   int G = 1;
-  while (G < 64 && 2 * G * n <= (int)blockDim.x) G *= 2;
+  while (G < 64 && 2 * G * n <= min(256, (int)blockDim.x)) G *= 2;
   const int e = tid / G, g = tid % G;
   if (e >= n) return;
   double lo = glo, hi = ghi;
-  for (int round = 0; round < 80; ++round) {
+  for (int round = 0; round < 200; ++round) {
     if (hi - lo <= fmax(atol, 2.0 * eps * fmax(fabs(lo), fabs(hi)))) break;
-    const double h = (hi - lo) / (double)(4 * G + 1);
-    double x[4];
-    int cnt[4];
-#pragma unroll
-    for (int c = 0; c < 4; ++c) x[c] = lo + (double)(4 * g + c + 1) * h;
-    sturm4(dg, od, n, x, cnt, pivmin);
+    const double h = (hi - lo) / (double)(G + 1);
+    const double x = lo + (double)(g + 1) * h;
+    const int cnt = sturm_count(dg, od, n, x, pivmin);
     double nlo = lo, nhi = hi;
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      if (x[c] <= lo || x[c] >= hi) continue;
-      if (cnt[c] > e) nhi = fmin(nhi, x[c]);
-      else nlo = fmax(nlo, x[c]);
+    if (x > lo && x < hi) {
+      if (cnt > e) nhi = x;
+      else nlo = x;
     }
     for (int o = G / 2; o > 0; o >>= 1) {
       nlo = fmax(nlo, __shfl_xor(nlo, o, G));
@@ -577,16 +610,171 @@ __device__ inline void bisect_all(const double* dg, const double* od, int n, dou
   if (g == 0) lam[e] = 0.5 * (lo + hi);
 }
 
+// Shared-memory arrays of the tridiagonal eigen-pipeline (NM doubles each).
+struct TriArrays {
+  double *dg, *od, *tau, *q1, *q2, *lam, *ud, *u1, *u2, *ml, *yv, *red;
+  int* pivs;
+};
+
+// Eigenvalues of the symmetric C (LDS, order n): tridiagonalisation (C
+// keeps the reflectors), multisection, ascending sort into w.lam.  Returns
+// ||T||_inf.
+template <int NM, int NT>
+__device__ __forceinline__ double tri_eigenvalues(double (*C)[NM + 1], int n, const TriArrays& w) {
+  tridiagonalize<NM, NT>(C, n, w.dg, w.od, w.tau, w.q1, w.q2, w.ud, w.red);
+  bisect_all(w.dg, w.od, n, w.lam);
+  __syncthreads();
+  if (threadIdx.x == 0)   // equal eigenvalues may come out a rounding apart in either order
+    for (int i = 1; i < n; ++i) {
+      const double v = w.lam[i];
+      int j = i - 1;
+      while (j >= 0 && w.lam[j] > v) {
+        w.lam[j + 1] = w.lam[j];
+        --j;
+      }
+      w.lam[j + 1] = v;
+    }
+  __syncthreads();
+  double tnorm = 0.0;
+  for (int i = 0; i < n; ++i)
+    tnorm = fmax(tnorm, fabs(w.dg[i]) + (i > 0 ? fabs(w.od[i - 1]) : 0.0) + (i + 1 < n ? fabs(w.od[i]) : 0.0));
+  return tnorm;
+}
+
+// Eigenvectors of T for the p smallest eigenvalues by inverse iteration
+// (rows of Z, leading dimension ldz, tridiagonal coordinates); clusters
+// (gaps <= 1e-3 ||T||) orthogonalised by modified Gram-Schmidt.
+__device__ inline void tri_vectors(int n, int p, double tnorm, const TriArrays& w, double* Z, int ldz) {
+  const int tid = threadIdx.x;
+  const double eps = 1.1102230246251565e-16;   // 2^-53
+  const double ortol = 1e-3 * tnorm;
+  for (int j = 0; j < p; ++j) {
+    int c0 = j;   // first vector of j's cluster
+    while (c0 > 0 && w.lam[c0] - w.lam[c0 - 1] <= ortol) --c0;
+    if (tid == 0) {
+      // LU with partial pivoting of T - lam_j I: row i of U has diagonal
+      // ud, first and second superdiagonals u1, u2; ml multipliers, pivs
+      // row interchanges
+      const double x = w.lam[j];
+      double a = w.dg[0] - x, b = n > 1 ? w.od[0] : 0.0;
+      for (int i = 0; i + 1 < n; ++i) {
+        const double c = w.od[i];                        // T[i+1][i]
+        const double a1 = w.dg[i + 1] - x, b1 = i + 2 < n ? w.od[i + 1] : 0.0;
+        if (fabs(a) >= fabs(c)) {
+          const double l = (a != 0.0) ? c / a : 0.0;
+          w.ud[i] = a; w.u1[i] = b; w.u2[i] = 0.0; w.ml[i] = l; w.pivs[i] = 0;
+          a = a1 - l * b;
+          b = b1;
+        } else {
+          const double l = a / c;
+          w.ud[i] = c; w.u1[i] = a1; w.u2[i] = b1; w.ml[i] = l; w.pivs[i] = 1;
+          a = b - l * a1;
+          b = -l * b1;
+        }
+      }
+      w.ud[n - 1] = a; w.u1[n - 1] = 0.0; w.u2[n - 1] = 0.0;
+      const double tiny = eps * (tnorm > 0.0 ? tnorm : 1.0);
+      for (int i = 0; i < n; ++i) {   // ud holds reciprocal pivots from here on
+        const double u = fabs(w.ud[i]) < tiny ? (w.ud[i] < 0.0 ? -tiny : tiny) : w.ud[i];
+        w.ud[i] = 1.0 / u;
+      }
+      // start vector: a fixed pseudo-random sequence in (-1, 1)
+      unsigned st = 0x9E3779B9u * (unsigned)(j + 1);
+      for (int i = 0; i < n; ++i) {
+        st = st * 1664525u + 1013904223u;
+        w.yv[i] = ((double)(st >> 8) / 16777216.0) * 2.0 - 1.0;
+      }
+    }
+    __syncthreads();
+    for (int it = 0; it < 3; ++it) {
+      if (tid == 0) {
+        // forward: interchanges and multipliers, row i + 1 carried in a register
+        double cur = w.yv[0];
+        for (int i = 0; i + 1 < n; ++i) {
+          const double nx = w.yv[i + 1];
+          if (w.pivs[i]) {
+            w.yv[i] = nx;
+            cur -= w.ml[i] * nx;
+          } else {
+            w.yv[i] = cur;
+            cur = nx - w.ml[i] * cur;
+          }
+        }
+        w.yv[n - 1] = cur;
+        // back substitution with the three bands of U (reciprocal pivots);
+        // near-singular shifts make the solution grow by 1/tiny per small
+        // pivot, so the whole system is rescaled before it could overflow
+        double c1 = 0.0, c2 = 0.0;
+        for (int i = n - 1; i >= 0; --i) {
+          double v = (w.yv[i] - w.u1[i] * c1 - w.u2[i] * c2) * w.ud[i];
+          for (int g = 0; g < 4 && !(fabs(v) <= 1e150); ++g) {
+            for (int q = 0; q < n; ++q) w.yv[q] *= 1e-150;
+            c1 *= 1e-150;
+            c2 *= 1e-150;
+            v = (w.yv[i] - w.u1[i] * c1 - w.u2[i] * c2) * w.ud[i];
+          }
+          w.yv[i] = v;
+          c2 = c1;
+          c1 = v;
+        }
+      }
+      __syncthreads();
+      // orthogonalise against the cluster's earlier vectors, normalise
+      for (int q = c0; q < j; ++q) {
+        double part = 0.0;
+        for (int i = tid; i < n; i += blockDim.x) part += Z[q * ldz + i] * w.yv[i];
+        const double dq = block_sum_sel(part, w.red);
+        for (int i = tid; i < n; i += blockDim.x) w.yv[i] -= dq * Z[q * ldz + i];
+        __syncthreads();
+      }
+      double part = 0.0;
+      for (int i = tid; i < n; i += blockDim.x) part += w.yv[i] * w.yv[i];
+      const double nrm = sqrt(block_sum_sel(part, w.red));
+      const double inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
+      for (int i = tid; i < n; i += blockDim.x) w.yv[i] *= inv;
+      __syncthreads();
+    }
+    for (int i = tid; i < n; i += blockDim.x) Z[j * ldz + i] = w.yv[i];
+    __syncthreads();
+  }
+}
+
+// z = H_0 H_1 ... H_{n-3} y for the p rows of Z: each wave takes whole
+// vectors and applies the reflectors from the last to the first (no block
+// barriers); lane l owns the entries i = l mod 64 throughout.
 template <int NM>
-__global__ void __launch_bounds__(SEL_THREADS) sygv_sel_kernel(const SygvDesc* __restrict__ descs, double sel,
-                                                               int* dflag, double* __restrict__ scratch) {
+__device__ __forceinline__ void tri_back_transform(const double (*C)[NM + 1], const double* tau, int n, int p,
+                                                   double* Z, int ldz) {
+  const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63, nw = blockDim.x >> 6;
+  for (int j = wv; j < p; j += nw) {
+    double* z = Z + (size_t)j * ldz;
+    for (int k = n - 3; k >= 0; --k) {
+      const double tk = tau[k];
+      if (tk == 0.0) continue;
+      double part = 0.0;
+      for (int i = lane; i < n; i += 64)
+        if (i > k) part += ((i == k + 1) ? 1.0 : C[i][k]) * z[i];
+      const double f = tk * wave_total(part);
+      for (int i = lane; i < n; i += 64)
+        if (i > k) z[i] -= f * ((i == k + 1) ? 1.0 : C[i][k]);
+    }
+  }
+  __syncthreads();
+}
+
+#define TRI_SHARED(NM)                                                                          \
+  __shared__ double dg_[NM], od_[NM], tau_[NM], q1_[NM], q2_[NM], lam_[NM], ud_[NM], u1_[NM], \
+      u2_[NM], ml_[NM], yv_[NM], red_[80];                                                      \
+  __shared__ int pivs_[NM];                                                                     \
+  const TriArrays tw{dg_, od_, tau_, q1_, q2_, lam_, ud_, u1_, u2_, ml_, yv_, red_, pivs_};
+
+template <int NM, int NT>
+__global__ void __launch_bounds__(NT) sygv_sel_kernel(const SygvDesc* __restrict__ descs, double sel, int* dflag,
+                                                      double* __restrict__ scratch) {
   constexpr bool SMALL = NM <= 64;
   __shared__ double Cm[NM][NM + 1];
   __shared__ double LZsm[SMALL ? NM : 1][SMALL ? NM + 1 : 1];
-  __shared__ double dg[NM], od[NM], tau[NM], pv[NM], vv[NM], lam[NM];
-  __shared__ double ud[NM], u1[NM], u2[NM], ml[NM], yv[NM];
-  __shared__ int pivs[NM];
-  __shared__ double red[80];
+  TRI_SHARED(NM)
   const SygvDesc d = descs[blockIdx.x];
   const int n = d.n, tid = threadIdx.x;
   if (n <= 0) return;
@@ -596,143 +784,12 @@ __global__ void __launch_bounds__(SEL_THREADS) sygv_sel_kernel(const SygvDesc* _
   // Z: selected vectors (row j = vector j), LDS for the small variant
   double* Z = SMALL ? &LZsm[0][0] : EigScratch<NM>::V(scratch);
   const int ldz = SMALL ? NM + 1 : NM;
-
-  // (1) tridiagonalisation, (2) eigenvalues
-  tridiagonalize<NM>(Cm, n, dg, od, tau, pv, vv, ud, red);
-  bisect_all(dg, od, n, lam);
-  __syncthreads();
-  if (tid == 0)   // equal eigenvalues may come out a rounding apart in either order
-    for (int i = 1; i < n; ++i) {
-      const double v = lam[i];
-      int j = i - 1;
-      while (j >= 0 && lam[j] > v) {
-        lam[j + 1] = lam[j];
-        --j;
-      }
-      lam[j + 1] = v;
-    }
-  __syncthreads();
-  for (int t = tid; t < n; t += blockDim.x) d.w[t] = lam[t];
+  const double tnorm = tri_eigenvalues<NM, NT>(Cm, n, tw);
+  for (int t = tid; t < n; t += blockDim.x) d.w[t] = tw.lam[t];
   int p = 0;
-  while (p < n && lam[p] <= sel) ++p;
-  double tnorm = 0.0;
-  for (int i = 0; i < n; ++i)
-    tnorm = fmax(tnorm, fabs(dg[i]) + (i > 0 ? fabs(od[i - 1]) : 0.0) + (i + 1 < n ? fabs(od[i]) : 0.0));
-  const double eps = 1.1102230246251565e-16;   // 2^-53
-
-  // (3) inverse iteration for the selected eigenvalues
-  const double ortol = 1e-3 * tnorm;
-  for (int j = 0; j < p; ++j) {
-    int c0 = j;   // first vector of j's cluster
-    while (c0 > 0 && lam[c0] - lam[c0 - 1] <= ortol) --c0;
-    if (tid == 0) {
-      // LU with partial pivoting of T - lam_j I: row i of U has diagonal
-      // ud, first and second superdiagonals u1, u2; ml multipliers, pivs
-      // row interchanges
-      const double x = lam[j];
-      double a = dg[0] - x, b = n > 1 ? od[0] : 0.0;
-      for (int i = 0; i + 1 < n; ++i) {
-        const double c = od[i];                        // T[i+1][i]
-        const double a1 = dg[i + 1] - x, b1 = i + 2 < n ? od[i + 1] : 0.0;
-        if (fabs(a) >= fabs(c)) {
-          const double l = (a != 0.0) ? c / a : 0.0;
-          ud[i] = a; u1[i] = b; u2[i] = 0.0; ml[i] = l; pivs[i] = 0;
-          a = a1 - l * b;
-          b = b1;
-        } else {
-          const double l = a / c;
-          ud[i] = c; u1[i] = a1; u2[i] = b1; ml[i] = l; pivs[i] = 1;
-          a = b - l * a1;
-          b = -l * b1;
-        }
-      }
-      ud[n - 1] = a; u1[n - 1] = 0.0; u2[n - 1] = 0.0;
-      const double tiny = eps * (tnorm > 0.0 ? tnorm : 1.0);
-      for (int i = 0; i < n; ++i) {   // ud holds reciprocal pivots from here on
-        const double u = fabs(ud[i]) < tiny ? (ud[i] < 0.0 ? -tiny : tiny) : ud[i];
-        ud[i] = 1.0 / u;
-      }
-      // start vector: a fixed pseudo-random sequence in (-1, 1)
-      unsigned st = 0x9E3779B9u * (unsigned)(j + 1);
-      for (int i = 0; i < n; ++i) {
-        st = st * 1664525u + 1013904223u;
-        yv[i] = ((double)(st >> 8) / 16777216.0) * 2.0 - 1.0;
-      }
-    }
-    __syncthreads();
-    for (int it = 0; it < 3; ++it) {
-      if (tid == 0) {
-        // forward: interchanges and multipliers, row i + 1 carried in a register
-        double cur = yv[0];
-        for (int i = 0; i + 1 < n; ++i) {
-          const double nx = yv[i + 1];
-          if (pivs[i]) {
-            yv[i] = nx;
-            cur -= ml[i] * nx;
-          } else {
-            yv[i] = cur;
-            cur = nx - ml[i] * cur;
-          }
-        }
-        yv[n - 1] = cur;
-        // back substitution with the three bands of U (reciprocal pivots);
-        // near-singular shifts make the solution grow by 1/tiny per small
-        // pivot, so the whole system is rescaled before it could overflow
-        double c1 = 0.0, c2 = 0.0;
-        for (int i = n - 1; i >= 0; --i) {
-          double v = (yv[i] - u1[i] * c1 - u2[i] * c2) * ud[i];
-          for (int g = 0; g < 4 && !(fabs(v) <= 1e150); ++g) {
-            for (int q = 0; q < n; ++q) yv[q] *= 1e-150;
-            c1 *= 1e-150;
-            c2 *= 1e-150;
-            v = (yv[i] - u1[i] * c1 - u2[i] * c2) * ud[i];
-          }
-          yv[i] = v;
-          c2 = c1;
-          c1 = v;
-        }
-      }
-      __syncthreads();
-      // orthogonalise against the cluster's earlier vectors, normalise
-      for (int q = c0; q < j; ++q) {
-        double part = 0.0;
-        for (int i = tid; i < n; i += blockDim.x) part += Z[q * ldz + i] * yv[i];
-        const double dq = block_sum_sel(part, red);
-        for (int i = tid; i < n; i += blockDim.x) yv[i] -= dq * Z[q * ldz + i];
-        __syncthreads();
-      }
-      double part = 0.0;
-      for (int i = tid; i < n; i += blockDim.x) part += yv[i] * yv[i];
-      const double nrm = sqrt(block_sum_sel(part, red));
-      const double inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
-      for (int i = tid; i < n; i += blockDim.x) yv[i] *= inv;
-      __syncthreads();
-    }
-    for (int i = tid; i < n; i += blockDim.x) Z[j * ldz + i] = yv[i];
-    __syncthreads();
-  }
-
-  // (4) z = H_0 H_1 ... H_{n-3} y: each wave takes whole vectors and applies
-  // the reflectors from the last to the first (no block barriers); lane l
-  // owns the entries i = l mod 64 throughout, so no entry changes hands
-  {
-    const int wv = tid >> 6, lane = tid & 63, nw = blockDim.x >> 6;
-    for (int j = wv; j < p; j += nw) {
-      double* z = Z + (size_t)j * ldz;
-      for (int k = n - 3; k >= 0; --k) {
-        const double tk = tau[k];
-        if (tk == 0.0) continue;
-        double part = 0.0;
-        for (int i = lane; i < n; i += 64)
-          if (i > k) part += ((i == k + 1) ? 1.0 : Cm[i][k]) * z[i];
-        part = wave_sum64(part);
-        const double f = tk * __shfl(part, 0, 64);
-        for (int i = lane; i < n; i += 64)
-          if (i > k) z[i] -= f * ((i == k + 1) ? 1.0 : Cm[i][k]);
-      }
-    }
-  }
-  __syncthreads();
+  while (p < n && tw.lam[p] <= sel) ++p;
+  tri_vectors(n, p, tnorm, tw, Z, ldz);
+  tri_back_transform<NM>(Cm, tw.tau, n, p, Z, ldz);
   // X[:, j] = L z_j (L read back into Cm for the small variant)
   if (SMALL) {
     const int tj = tid & 63, ti = tid >> 6, nstep = blockDim.x >> 6;
@@ -765,7 +822,7 @@ __global__ void __launch_bounds__(SEL_THREADS) sygv_sel_kernel(const SygvDesc* _
 struct SchurWork {
   SchurPinvDesc d;
   double* G;      // (nv + k)^2 augmented matrix, ld nv + k
-  double* work;   // k x max(k, nv - k) (fallback)
+  double* work;   // k x nv (fallback: dropped eigenvectors, then M'^{-1} M12)
   int32_t* flag;  // 1: take the fallback
 };
 
@@ -782,7 +839,7 @@ __global__ void __launch_bounds__(256) spinv_build_kernel(const SchurWork* __res
 }
 
 __device__ inline double block_sum256(double v, double* red) {
-  v = wave_sum64(v);
+  v = wave_total(v);
   __syncthreads();
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
   __syncthreads();
@@ -822,63 +879,135 @@ __global__ void __launch_bounds__(256) spinv_finish_kernel(const SchurWork* __re
   }
 }
 
-// Fallback for flagged matrices: sym(M11) = V diag(lambda) V^T (Jacobi),
-// P = sum over lambda > rtol lambda_max of v v^T / lambda, M22 -= M21 P M12.
+// X <- (L L^T)^{-1} X for the Cholesky factor L (LDS, lower triangle) and
+// X (k x m, global, leading dimension ldx): blocked forward and backward
+// substitution, one thread per column inside a 16-row block, all threads
+// on the update of the remaining rows.
 template <int NM>
-__global__ void __launch_bounds__(EIG_THREADS) spinv_fallback_kernel(const SchurWork* __restrict__ ws, double rtol,
-                                                             double* __restrict__ scratch) {
-  constexpr bool SMALL = NM <= 64;
+__device__ __forceinline__ void chol_solve_global(const double (*Lm)[NM + 1], int k, double* X, int ldx, int m) {
+  const int tid = threadIdx.x;
+  for (int r0 = 0; r0 < k; r0 += 16) {
+    const int rw = min(16, k - r0);
+    for (int c = tid; c < m; c += blockDim.x) {
+      double x[16];
+#pragma unroll
+      for (int i = 0; i < 16; ++i) x[i] = i < rw ? X[(size_t)(r0 + i) * ldx + c] : 0.0;
+#pragma unroll
+      for (int i = 0; i < 16; ++i)
+        if (i < rw) {
+          double v = x[i];
+#pragma unroll
+          for (int q = 0; q < i; ++q) v -= Lm[r0 + i][r0 + q] * x[q];
+          x[i] = v / Lm[r0 + i][r0 + i];
+        }
+#pragma unroll
+      for (int i = 0; i < 16; ++i)
+        if (i < rw) X[(size_t)(r0 + i) * ldx + c] = x[i];
+    }
+    __syncthreads();
+    const int r1 = r0 + rw, mr = k - r1;
+    for (int idx = tid; idx < mr * m; idx += blockDim.x) {
+      const int r = r1 + idx / m, c = idx % m;
+      double acc = 0.0;
+      for (int q = 0; q < rw; ++q) acc += Lm[r][r0 + q] * X[(size_t)(r0 + q) * ldx + c];
+      X[(size_t)r * ldx + c] -= acc;
+    }
+    __syncthreads();
+  }
+  for (int r0 = ((k - 1) / 16) * 16; r0 >= 0; r0 -= 16) {
+    const int rw = min(16, k - r0);
+    for (int c = tid; c < m; c += blockDim.x) {
+      double x[16];
+#pragma unroll
+      for (int i = 0; i < 16; ++i) x[i] = i < rw ? X[(size_t)(r0 + i) * ldx + c] : 0.0;
+#pragma unroll
+      for (int i = 15; i >= 0; --i)
+        if (i < rw) {
+          double v = x[i];
+#pragma unroll
+          for (int q = i + 1; q < 16; ++q)
+            if (q < rw) v -= Lm[r0 + q][r0 + i] * x[q];
+          x[i] = v / Lm[r0 + i][r0 + i];
+        }
+#pragma unroll
+      for (int i = 0; i < 16; ++i)
+        if (i < rw) X[(size_t)(r0 + i) * ldx + c] = x[i];
+    }
+    __syncthreads();
+    for (int idx = tid; idx < r0 * m; idx += blockDim.x) {
+      const int r = idx / m, c = idx % m;
+      double acc = 0.0;
+      for (int q = 0; q < rw; ++q) acc += Lm[r0 + q][r] * X[(size_t)(r0 + q) * ldx + c];
+      X[(size_t)r * ldx + c] -= acc;
+    }
+    __syncthreads();
+  }
+}
+
+// Fallback for flagged matrices, by deflation: sym(M11) has the
+// eigenvalues lambda and the dropped ones (<= rtol lambda_max) span V_d.
+// With sigma = lambda_max, M' = sym(M11) + V_d (sigma - Lambda_d) V_d^T is
+// positive definite and (sym M11)^+ = M'^{-1} - V_d V_d^T / sigma, so
+//   M22 -= M21 (M'^{-1} M12 - V_d (V_d^T M12) / sigma).
+// Eigenvalues and V_d come from the tridiagonal pipeline, M'^{-1} M12 from
+// a Cholesky solve in LDS.
+template <int NM, int NT>
+__global__ void __launch_bounds__(NT) spinv_fallback_kernel(const SchurWork* __restrict__ ws, double rtol,
+                                                            int* dflag) {
   __shared__ double Am[NM][NM + 1];
-  __shared__ double Vsm[SMALL ? NM : 1][SMALL ? NM + 1 : 1];
-  __shared__ double cs[NM / 2], sn[NM / 2];
-  __shared__ int pp[NM / 2], qq[NM / 2];
-  __shared__ int nrot;
-  __shared__ double lam[NM];
-  __shared__ double lmax;
+  TRI_SHARED(NM)
+  __shared__ int pd_s;
   const SchurWork w = ws[blockIdx.x];
   const int nv = w.d.nv, k = w.d.k, m = nv - k, ld = w.d.ld, tid = threadIdx.x;
   if (k <= 0 || *w.flag == 0) return;
   double* M = w.d.M;
-  double* Vt = SMALL ? &Vsm[0][0] : EigScratch<NM>::V(scratch);
-  const int ldv = SMALL ? NM + 1 : NM;
+  double* Vd = w.work;                          // dropped eigenvectors, rows, ld k
+  double* X = w.work + (size_t)k * k;           // k x m
   const int tj = tid & 63, ti = tid >> 6, nstep = blockDim.x >> 6;
   for (int r = ti; r < k; r += nstep)
     for (int j = tj; j < k; j += 64) Am[r][j] = 0.5 * (M[(size_t)r * ld + j] + M[(size_t)j * ld + r]);
   __syncthreads();
-  jacobi<NM>(Am, Vt, ldv, k, cs, sn, pp, qq, &nrot);
-  for (int i = tid; i < k; i += blockDim.x) lam[i] = Am[i][i];
-  __syncthreads();
-  if (tid == 0) {
-    double mx = 0.0;
-    for (int i = 0; i < k; ++i) mx = fmax(mx, lam[i]);
-    lmax = mx;
-  }
-  __syncthreads();
+  const double tnorm = tri_eigenvalues<NM, NT>(Am, k, tw);
+  const double lmax = tw.lam[k - 1];
+  if (!(lmax > 0.0)) return;   // nothing kept: the pseudo-inverse is 0
   const double cut = rtol * lmax;
-  // P -> Am (k x k)
+  int pd = 0;
+  while (pd < k && tw.lam[pd] <= cut) ++pd;
+  tri_vectors(k, pd, tnorm, tw, Vd, k);
+  tri_back_transform<NM>(Am, tw.tau, k, pd, Vd, k);
+  // M' in Am, then its Cholesky factor
   for (int r = ti; r < k; r += nstep)
     for (int j = tj; j < k; j += 64) {
-      double v = 0.0;
-      if (lmax > 0.0)
-        for (int q = 0; q < k; ++q)
-          if (lam[q] > cut) v += Vt[q * ldv + r] * Vt[q * ldv + j] / lam[q];
+      double v = 0.5 * (M[(size_t)r * ld + j] + M[(size_t)j * ld + r]);
+      for (int q = 0; q < pd; ++q) v += (lmax - tw.lam[q]) * Vd[(size_t)q * k + r] * Vd[(size_t)q * k + j];
       Am[r][j] = v;
     }
   __syncthreads();
-  // work = P M12 (k x m), then M22 -= M21 work
-  for (int r = ti; r < k; r += nstep)
-    for (int j = tj; j < m; j += 64) {
-      double v = 0.0;
-      for (int q = 0; q < k; ++q) v += Am[r][q] * M[(size_t)q * ld + k + j];
-      w.work[(size_t)r * m + j] = v;
-    }
+  cholesky_panels<NM>(&Am[0][0], NM + 1, k, dflag);
+  // X = M'^{-1} M12 - V_d (V_d^T M12) / sigma
+  for (int idx = tid; idx < k * m; idx += blockDim.x) {
+    const int r = idx / m, c = idx % m;
+    X[(size_t)r * m + c] = M[(size_t)r * ld + k + c];
+  }
   __syncthreads();
-  for (int r = ti; r < m; r += nstep)
-    for (int j = tj; j < m; j += 64) {
-      double v = 0.0;
-      for (int q = 0; q < k; ++q) v += M[(size_t)(k + r) * ld + q] * w.work[(size_t)q * m + j];
-      M[(size_t)(k + r) * ld + k + j] -= v;
-    }
+  chol_solve_global<NM>(Am, k, X, m, m);
+  if (pd > 0) {
+    for (int c = tid; c < m; c += blockDim.x)
+      for (int q = 0; q < pd; ++q) {
+        double t = 0.0;
+        for (int i = 0; i < k; ++i) t += Vd[(size_t)q * k + i] * M[(size_t)i * ld + k + c];
+        t /= lmax;
+        for (int i = 0; i < k; ++i) X[(size_t)i * m + c] -= Vd[(size_t)q * k + i] * t;
+      }
+    __syncthreads();
+  }
+  // M22 -= M21 X
+  for (int idx = tid; idx < m * m; idx += blockDim.x) {
+    const int r = idx / m, c = idx % m;
+    double acc = 0.0;
+    for (int q = 0; q < k; ++q) acc += M[(size_t)(k + r) * ld + q] * X[(size_t)q * m + c];
+    M[(size_t)(k + r) * ld + k + c] -= acc;
+  }
 }
 
 // Parallel sum pieces: [[A + B, B], [-A, 0]] (its pseudo-inverse Schur
@@ -1097,7 +1226,7 @@ void schur_pinv_batched(const std::vector<SchurPinvDesc>& descs, double rtol, in
   for (auto& d : descs) {
     ABDDC_REQUIRE(d.k >= 0 && d.k <= d.nv && d.ld >= d.nv, ABDDC_EINVAL, "pinv Schur complement: bad shape");
     gtot += (int64_t)(d.nv + d.k) * (d.nv + d.k);
-    wtot += (int64_t)d.k * std::max(d.k, d.nv - d.k);
+    wtot += (int64_t)d.k * d.nv;   // V_d (k x k) and X (k x (nv - k))
   }
   const int nb = (int)descs.size();
   DevBuf<double> G(std::max<int64_t>(gtot, 1)), work(std::max<int64_t>(wtot, 1));
@@ -1111,7 +1240,7 @@ void schur_pinv_batched(const std::vector<SchurPinvDesc>& descs, double rtol, in
     ws[b] = {descs[b], G.p + go, work.p + wo, flags.p + b};
     pd[b] = {G.p + go, ng, ng, ng, descs[b].k};
     go += (int64_t)ng * ng;
-    wo += (int64_t)descs[b].k * std::max(descs[b].k, descs[b].nv - descs[b].k);
+    wo += (int64_t)descs[b].k * descs[b].nv;
   }
   Arena& ar = Arena::for_stream(s);
   const SchurWork* dw = ar.put(ws);
@@ -1129,12 +1258,11 @@ void schur_pinv_batched(const std::vector<SchurPinvDesc>& descs, double rtol, in
   split_launch(small_k, [](const SchurWork& w) { return w.d.k; }, s, "pinv Schur complement", sm, bg);
   if (!sm.empty()) {
     const SchurWork* dd = ar.put(sm);
-    spinv_fallback_kernel<64><<<sm.size(), EIG_THREADS, 0, s>>>(dd, rtol, nullptr);
+    spinv_fallback_kernel<64, 512><<<sm.size(), 512, 0, s>>>(dd, rtol, dflag);
   }
   if (!bg.empty()) {
-    DevBuf<double> scr(bg.size() * 2 * 128 * 128);
     const SchurWork* dd = ar.put(bg);
-    spinv_fallback_kernel<128><<<bg.size(), EIG_THREADS, 0, s>>>(dd, rtol, scr.p);
+    spinv_fallback_kernel<128, 1024><<<bg.size(), 1024, 0, s>>>(dd, rtol, dflag);
   }
   ABDDC_HIP(hipGetLastError());
 }
@@ -1167,12 +1295,12 @@ void sygv_select_batched(const std::vector<SygvDesc>& descs, double sel, int* df
   split_launch(descs, [](const SygvDesc& d) { return d.n; }, s, "sygv", sm, bg);
   if (!sm.empty()) {
     const SygvDesc* dd = Arena::for_stream(s).put(sm);
-    sygv_sel_kernel<64><<<sm.size(), SEL_THREADS, 0, s>>>(dd, sel, dflag, nullptr);
+    sygv_sel_kernel<64, 512><<<sm.size(), 512, 0, s>>>(dd, sel, dflag, nullptr);
   }
   if (!bg.empty()) {
     DevBuf<double> scr(bg.size() * 2 * 128 * 128);
     const SygvDesc* dd = Arena::for_stream(s).put(bg);
-    sygv_sel_kernel<128><<<bg.size(), SEL_THREADS, 0, s>>>(dd, sel, dflag, scr.p);
+    sygv_sel_kernel<128, 1024><<<bg.size(), 1024, 0, s>>>(dd, sel, dflag, scr.p);
   }
   ABDDC_HIP(hipGetLastError());
 }
