@@ -455,6 +455,8 @@ extern "C" int abddc_gmres_solve(abddc_ctx* c, int32_t restart, double rtol, int
       c->d_partial.alloc((size_t)DOT_BLOCKS * DOT_STRIDE);
       c->d_gst.alloc(1);
       ABDDC_HIP(hipHostMalloc(&c->h_gst, sizeof(GmresState), hipHostMallocDefault));
+      ABDDC_HIP(hipHostMalloc(&c->h_step, 8 * sizeof(double), hipHostMallocDefault));
+      for (int i = 0; i < 2; ++i) ABDDC_HIP(hipEventCreateWithFlags(&c->ev_step[i], hipEventDisableTiming));
     }
     const auto t0 = std::chrono::steady_clock::now();
     record(c, 13);
@@ -483,19 +485,34 @@ extern "C" int abddc_gmres_solve(abddc_ctx* c, int32_t restart, double rtol, int
       while (!converged) {
         // cycle start: V[0] = v_cur = r / ||r|| (r, its norm and j = 0 in place)
         launch_scale_to_col(c->d_r.p, c->d_gst.p, V, nn, c->d_vcur.p, n, s);
-        int jend = 0;
-        for (int j = 0; j < restart; ++j) {
+        // Steps run one ahead of the convergence test: step j + 1 is queued
+        // before the host waits for the scalars of step j (copied to a
+        // pinned slot of their own), so the device does not idle during
+        // the round trip.  A step queued past the exit is harmless: it
+        // writes only column j + 1 of H, Z and V, its own rotation and
+        // g[j + 1], g[j + 2], none of which the solution of the first
+        // j + 1 columns reads, and the next cycle resets the state.
+        auto launch_step = [&](int j) {
           if (use_graph && eager_done && ensure_step_graph(c, restart))
             ABDDC_HIP(hipGraphLaunch(c->step_exec, s));
           else
             arnoldi_step(c, restart, s);
           eager_done = true;
+          ABDDC_HIP(hipMemcpyAsync(c->h_step + 4 * (j & 1), reinterpret_cast<char*>(c->d_gst.p) + tail,
+                                   4 * sizeof(double), hipMemcpyDeviceToHost, s));
+          ABDDC_HIP(hipEventRecord(c->ev_step[j & 1], s));
+        };
+        int jend = 0;
+        launch_step(0);
+        for (int j = 0; j < restart; ++j) {
+          if (j + 1 < restart && iters + 1 < maxit) launch_step(j + 1);
+          ABDDC_HIP(hipEventSynchronize(c->ev_step[j & 1]));
           ++iters;
-          read_scalars();
-          const double res = c->h_gst->res;
+          const double* sc = c->h_step + 4 * (j & 1);   // beta, hn, inv_hn, res
+          const double res = sc[3];
           if (info && info->resid_history && iters <= info->resid_cap) info->resid_history[iters - 1] = res / bnorm;
           jend = j + 1;
-          if (c->h_gst->hn == 0.0 || res <= rtol * bnorm || iters >= maxit) break;
+          if (sc[1] == 0.0 || res <= rtol * bnorm || iters >= maxit) break;
         }
         launch_gmres_trisolve(c->d_gst.p, jend, s);
         launch_axpy_multi(Z, nn, jend, c->d_gst.p->y, 1.0, c->d_x.p, n, s);
@@ -647,6 +664,9 @@ extern "C" void abddc_destroy(abddc_ctx* c) {
   StreamScope ss(c->stream);
   (void)hipStreamSynchronize(c->stream);
   if (c->h_gst) (void)hipHostFree(c->h_gst);
+  if (c->h_step) (void)hipHostFree(c->h_step);
+  for (int i = 0; i < 2; ++i)
+    if (c->ev_step[i]) (void)hipEventDestroy(c->ev_step[i]);
   if (c->step_exec) (void)hipGraphExecDestroy(c->step_exec);
   if (c->step_graph) (void)hipGraphDestroy(c->step_graph);
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);

@@ -69,6 +69,8 @@ struct abddc_ctx {
   abddc::DevBuf<double> d_V, d_Z, d_w, d_r, d_x, d_h1, d_h2, d_nrm, d_partial;
   abddc::DevBuf<abddc::GmresState> d_gst;
   abddc::GmresState* h_gst = nullptr;               // pinned mirror of the scalars
+  double* h_step = nullptr;                         // pinned: scalars of two Arnoldi steps in flight
+  hipEvent_t ev_step[2] = {nullptr, nullptr};
   int gm_restart = 0;
   abddc::DevBuf<double> d_vcur, d_zcur;             // current Arnoldi vector and its preconditioned image
   hipStream_t cap_stream = nullptr;                 // private stream for graph capture
