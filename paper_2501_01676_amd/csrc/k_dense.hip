@@ -16,6 +16,7 @@
 #include <cmath>
 
 #include "arena.h"
+#include "htrace.h"
 #include "internal.h"
 #include "kstats.h"
 
@@ -537,6 +538,7 @@ void partial_lu(const std::vector<PluDesc<T>>& descs_in, int* dflag, hipStream_t
     maxc = std::max(maxc, d.ncol);
   }
   if (maxk == 0) return;
+  HostTrace ht;
   Arena& ar = Arena::for_stream(s);
   const PluDesc<T>* dd = ar.put(descs);
   static thread_local DevBuf<char> scratch;
@@ -595,6 +597,7 @@ void partial_lu(const std::vector<PluDesc<T>>& descs_in, int* dflag, hipStream_t
                           ct, nb);
   }
   ABDDC_HIP(hipGetLastError());
+  ht.mark("partial LU queued");
 }
 
 template <class T>

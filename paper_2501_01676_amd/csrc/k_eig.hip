@@ -14,6 +14,7 @@
 #include <string>
 
 #include "arena.h"
+#include "htrace.h"
 #include "internal.h"
 #include "tune.h"
 
@@ -1222,6 +1223,7 @@ void split_launch(const std::vector<D>& descs, F order, hipStream_t s, const cha
 
 void schur_pinv_batched(const std::vector<SchurPinvDesc>& descs, double rtol, int* dflag, hipStream_t s) {
   if (descs.empty()) return;
+  HostTrace ht;
   int64_t gtot = 0, wtot = 0;
   for (auto& d : descs) {
     ABDDC_REQUIRE(d.k >= 0 && d.k <= d.nv && d.ld >= d.nv, ABDDC_EINVAL, "pinv Schur complement: bad shape");
@@ -1232,6 +1234,7 @@ void schur_pinv_batched(const std::vector<SchurPinvDesc>& descs, double rtol, in
   DevBuf<double> G(std::max<int64_t>(gtot, 1)), work(std::max<int64_t>(wtot, 1));
   DevBuf<int32_t> flags(nb), lu_flag(1);
   lu_flag.zero(s);
+  ht.mark("pinv Schur: buffers");
   std::vector<SchurWork> ws(nb);
   std::vector<PluDesc<double>> pd(nb);
   int64_t go = 0, wo = 0;
@@ -1245,9 +1248,11 @@ void schur_pinv_batched(const std::vector<SchurPinvDesc>& descs, double rtol, in
   Arena& ar = Arena::for_stream(s);
   const SchurWork* dw = ar.put(ws);
   spinv_build_kernel<<<nb, 256, 0, s>>>(dw);
+  ht.mark("pinv Schur: descriptors, build");
   // a zero or non-finite pivot only sends the matrix to the fallback: the
   // finish kernel sees a non-positive pivot or a non-finite ||M11^{-1}||
   partial_lu<double>(pd, lu_flag.p, s);
+  ht.mark("pinv Schur: partial LU queued");
   spinv_finish_kernel<<<nb, 256, 0, s>>>(dw, rtol, dflag);
   // the eigenvalue fallback exists for k <= 128; a larger block that fails
   // the test is reported through dflag by the finish kernel
@@ -1265,6 +1270,7 @@ void schur_pinv_batched(const std::vector<SchurPinvDesc>& descs, double rtol, in
     spinv_fallback_kernel<128, 1024><<<bg.size(), 1024, 0, s>>>(dd, rtol, dflag);
   }
   ABDDC_HIP(hipGetLastError());
+  ht.mark("pinv Schur: finish, fallback queued");
 }
 
 void parallel_sum_batched(const std::vector<PsumDesc>& descs, double rtol, hipStream_t s) {
