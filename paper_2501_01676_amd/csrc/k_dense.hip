@@ -309,8 +309,8 @@ __global__ void __launch_bounds__(256) plu_diag_kernel(const PluDesc<T>* __restr
   // (1) the four diagonal-block inverses, one column per lane (wave 0:
   //     L11, L22 in its two lane halves; wave 1: U11, U22), into E:
   //     E11 = L11^{-1}, E22 = L22^{-1}, E21 = U11^{-1}, E12 = U22^{-1};
-  // (2) T1 = L21 E11 and T2 = U12 E12 over all waves, written over L21, U12;
-  // (3) the off-diagonal blocks -E22 T1 and -E21 T2 straight to global.
+  // (2) T1 = L21 E11 and T2 = U12 E12 on MFMA, written over L21, U12;
+  // (3) the off-diagonal blocks -E22 T1 and -E21 T2 on MFMA, straight to global.
   constexpr int H = NB / 2;
   __shared__ T E[NB][NB + 1];
   {
@@ -341,40 +341,43 @@ __global__ void __launch_bounds__(256) plu_diag_kernel(const PluDesc<T>* __restr
     }
   }
   __syncthreads();
-  // (2) thread (i, j4): row i of a 32 x 32 product, columns j4, j4 + 8, j4 + 16, j4 + 24
+  // (2), (3): the four 32 x 32 x 32 products on MFMA; wave w computes the
+  // 16 x 16 block (w / 2, w % 2) of both products of a phase
+  {
+    typedef typename Mfma<T>::acc_t acc_t;
+    const int kl = lane >> 4, il = lane & 15, bi = wave >> 1, bj = wave & 1;
+    acc_t p1 = {0, 0, 0, 0}, p2 = {0, 0, 0, 0};
+#pragma unroll
+    for (int kk = 0; kk < H; kk += 4) {
+      p1 = Mfma<T>::run(D[H + 16 * bi + il][kk + kl], E[kk + kl][16 * bj + il], p1);           // L21 L11^{-1}
+      p2 = Mfma<T>::run(D[16 * bi + il][H + kk + kl], E[kk + kl][H + 16 * bj + il], p2);       // U12 U22^{-1}
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int r = 16 * bi + Mfma<T>::out_row(kl, q), cc = 16 * bj + il;
+      D[H + r][cc] = p1[q];
+      D[r][H + cc] = p2[q];
+    }
+    __syncthreads();
+    acc_t p3 = {0, 0, 0, 0}, p4 = {0, 0, 0, 0};
+#pragma unroll
+    for (int kk = 0; kk < H; kk += 4) {
+      p3 = Mfma<T>::run(E[H + 16 * bi + il][H + kk + kl], D[H + kk + kl][16 * bj + il], p3);   // L22^{-1} T1
+      p4 = Mfma<T>::run(E[H + 16 * bi + il][kk + kl], D[kk + kl][H + 16 * bj + il], p4);       // U11^{-1} T2
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int r = 16 * bi + Mfma<T>::out_row(kl, q), cc = 16 * bj + il;
+      gLi[(H + r) * NB + cc] = -p3[q];
+      gUi[r * NB + H + cc] = -p4[q];
+    }
+  }
+  // the block-diagonal parts and zeros
   const int pi = tid >> 3, pj = tid & 7;
-  T t1[4], t2[4];
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     const int j = pj + 8 * q;
-    T a1 = T(0), a2 = T(0);
-#pragma unroll 8
-    for (int k = 0; k < H; ++k) {
-      a1 += D[H + pi][k] * E[k][j];            // L21 * L11^{-1}
-      a2 += D[pi][H + k] * E[k][H + j];        // U12 * U22^{-1}
-    }
-    t1[q] = a1;
-    t2[q] = a2;
-  }
-  __syncthreads();
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    D[H + pi][pj + 8 * q] = t1[q];
-    D[pi][H + pj + 8 * q] = t2[q];
-  }
-  __syncthreads();
-  // (3) and the block-diagonal parts and zeros
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int j = pj + 8 * q;
-    T a1 = T(0), a2 = T(0);
-#pragma unroll 8
-    for (int k = 0; k < H; ++k) {
-      a1 += E[H + pi][H + k] * D[H + k][j];    // L22^{-1} T1
-      a2 += E[H + pi][k] * D[k][H + j];        // U11^{-1} T2
-    }
-    gLi[(H + pi) * NB + j] = -a1;
-    gUi[pi * NB + H + j] = -a2;
     gLi[pi * NB + j] = E[pi][j];
     gLi[(H + pi) * NB + H + j] = E[H + pi][H + j];
     gLi[pi * NB + H + j] = T(0);
