@@ -405,123 +405,139 @@ __global__ void __launch_bounds__(EIG_THREADS) sygv_kernel(const SygvDesc* __res
 //   (3) for each selected eigenvalue, inverse iteration on T - mu I (LU with
 //       partial pivoting of the tridiagonal matrix, three solves), vectors
 //       of a cluster (gap below 1e-3 ||T||) orthogonalised against the
-//       cluster's earlier ones (modified Gram-Schmidt);
+//       cluster's earlier ones (modified Gram-Schmidt), clusters in
+//       parallel, one wave each;
 //   (4) back-transformation z = Q y and output X = L z, as the full solver.
 // Work per problem: about (4/3) n^3 for (1), against tens of n^3 for Jacobi.
-constexpr int SEL_THREADS = 256;
-
-__device__ inline double block_sum_sel(double v, double* red) {
-  v = wave_total(v);
-  __syncthreads();
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
-  __syncthreads();
-  double t = 0.0;
-  for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += red[w];
-  return t;
+// Orders the LDS accesses of the lanes of one wave: a wave's LDS operations
+// complete in issue order, so a fence at wavefront scope is enough for the
+// other lanes to see what one lane wrote.
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-__device__ inline void block_sum5(double* v, double* red) {
-#pragma unroll
-  for (int q = 0; q < 5; ++q) v[q] = wave_total(v[q]);
-  __syncthreads();
-  const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  if ((threadIdx.x & 63) == 0)
-#pragma unroll
-    for (int q = 0; q < 5; ++q) red[q * 16 + w] = v[q];
-  __syncthreads();
-#pragma unroll
-  for (int q = 0; q < 5; ++q) {
-    double t = 0.0;
-    for (int i = 0; i < nw; ++i) t += red[q * 16 + i];
-    v[q] = t;
-  }
-}
-
-// Householder tridiagonalisation C = Q T Q^T of the symmetric C (LDS):
-// T's diagonal in dg, off-diagonal in od; reflector k is I - tau_k v v^T
-// with v = (1, v_2..) on rows k+1.., its tail kept in column k of C below
-// the subdiagonal.  One step reads C once for x (the column below the
-// diagonal), the first column of the active block and its product with x,
-// so that the Householder vector, C v and v^T C v follow from one block
-// reduction; then the rank-2 update C -= v w^T + w v^T.  Four barriers per
-// step.  q1, q2, xs: NM doubles each; red: 80 doubles.
-template <int NM, int NT>
+// Householder tridiagonalisation C = Q T Q^T of the symmetric C (LDS) by
+// wave 0 alone (the other waves wait at the closing barrier): no block
+// barriers inside.  Lane l owns index k+1+l (and k+65+l for NM = 128) of the
+// active block of step k.  A step reads x = C[k+1.., k] and the block's
+// first column, forms q = C~ x~ (the block and x without their first row
+// and entry) row by row, so that the Householder vector, C v and v^T C v
+// follow from three wave sums, |x~|^2, x~ . q and x~ . C e0, and from
+// alpha = x_0 and c00 (lane 0);
+// then the rank-2 update C -= v w^T + w v^T in groups of eight rows (v and
+// w staged in sv, sw for broadcast reads).  T's diagonal in dg, off-diagonal in od; reflector k is
+// I - tau_k v v^T with v = (1, v_2..) on rows k+1.., its tail kept in
+// column k of C below the subdiagonal.
+template <int NM>
 __device__ __forceinline__ void tridiagonalize(double (*Cm)[NM + 1], int n, double* dg, double* od, double* tau,
-                                               double* q1, double* q2, double* xs, double* red) {
-  constexpr int P = NT / NM;   // column chunks of the matrix-vector product
-  __shared__ double qp[P * NM];
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, nw = NT >> 6;
-  for (int k = 0; k + 2 < n; ++k) {
-    const int m = n - k - 1;
-    // q2_r = sum_{j >= 1} C[j][r] x_j (C symmetric: lanes on consecutive r,
-    // conflict-free), split into P column chunks summed through LDS
-    {
-      const int r = tid % NM, part = tid / NM;
-      double a = 0.0;
-      if (r < m)
-        for (int j = 1 + part; j < m; j += P) a += Cm[k + 1 + j][k + 1 + r] * Cm[k + 1 + j][k];
-      qp[part * NM + r] = a;
-    }
-    __syncthreads();
-    double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};   // |x~|^2, x~ . C x~, x~ . C e0, alpha, c00
-    if (tid < m) {
-      const int r = tid, i = k + 1 + r;
-      double a = 0.0;
+                                               double* sv, double* sw) {
+  constexpr int RPL = NM / 64;
+  const int tid = threadIdx.x, lane = tid & 63;
+  if (tid < 64) {
+    for (int k = 0; k + 2 < n; ++k) {
+      const int m = n - k - 1, b = k + 1;
+      // lanes past the block read a clamped (valid) index and are masked
+      // where it matters, so that loads are unconditional and can be batched
+      double xr[RPL], c0[RPL], q[RPL];
+      int cc[RPL], cs[RPL];
 #pragma unroll
-      for (int q = 0; q < P; ++q) a += qp[q * NM + r];
-      const double xr = Cm[i][k], c0 = Cm[i][k + 1];
-      q1[r] = c0;
-      q2[r] = a;
-      xs[r] = xr;
-      if (r > 0) {
-        acc[0] = xr * xr;
-        acc[1] = xr * a;
-        acc[2] = xr * c0;
-      } else {
-        acc[3] = xr;
-        acc[4] = c0;
+      for (int s = 0; s < RPL; ++s) {
+        const int r = lane + 64 * s;
+        cc[s] = b + min(r, m - 1);
+        cs[s] = r < m ? b + r : NM;
+        const double xv = Cm[cc[s]][k], cv = Cm[cc[s]][b];
+        xr[s] = r < m ? xv : 0.0;
+        c0[s] = r < m ? cv : 0.0;
+        q[s] = 0.0;
       }
-    }
-    block_sum5(acc, red);
-    const double xn2 = acc[0], alpha = acc[3];
-    if (xn2 == 0.0) {   // nothing below the subdiagonal: H = I
-      if (tid == 0) {
-        dg[k] = Cm[k][k];
-        od[k] = alpha;
-        tau[k] = 0.0;
+#pragma unroll 8
+      for (int j = 1; j < m; ++j) {
+        const double xj = Cm[b + j][k];
+#pragma unroll
+        for (int s = 0; s < RPL; ++s) q[s] += Cm[b + j][cc[s]] * xj;
       }
-      continue;
-    }
-    const double beta = -copysign(sqrt(alpha * alpha + xn2), alpha);
-    const double t = (beta - alpha) / beta, sc = 1.0 / (alpha - beta);
-    const double vcv = acc[4] + 2.0 * sc * acc[2] + sc * sc * acc[1];
-    const double K = 0.5 * t * t * vcv;
-    if (tid == 0) {
-      dg[k] = Cm[k][k];
-      od[k] = beta;
-      tau[k] = t;
-    }
-    for (int r = wv; r < m; r += nw) {
-      const double vr = r == 0 ? 1.0 : sc * xs[r];
-      const double wr = t * (q1[r] + sc * q2[r]) - K * vr;
-      for (int c = lane; c < m; c += 64) {
-        const double vc = c == 0 ? 1.0 : sc * xs[c];
-        const double wc = t * (q1[c] + sc * q2[c]) - K * vc;
-        Cm[k + 1 + r][k + 1 + c] -= vr * wc + wr * vc;
+      double acc[3] = {0.0, 0.0, 0.0};   // |x~|^2, x~ . q, x~ . C e0 (lanes 1.. of the block)
+#pragma unroll
+      for (int s = 0; s < RPL; ++s) {
+        const int r = lane + 64 * s;
+        const double xm = r > 0 ? xr[s] : 0.0;   // xr is 0 past the block
+        acc[0] += xm * xm;
+        acc[1] += xm * q[s];
+        acc[2] += xm * c0[s];
       }
+#pragma unroll
+      for (int t = 0; t < 3; ++t) acc[t] = wave_total(acc[t]);
+      const double xn2 = acc[0], alpha = read_lane_d(xr[0], 0), c00 = read_lane_d(c0[0], 0);
+      const double dkk = Cm[k][k];
+      if (xn2 == 0.0) {   // nothing below the subdiagonal: H = I
+        if (lane == 0) {
+          dg[k] = dkk;
+          od[k] = alpha;
+          tau[k] = 0.0;
+        }
+        wave_sync();
+        continue;
+      }
+      const double beta = -copysign(sqrt(alpha * alpha + xn2), alpha);
+      const double t = (beta - alpha) / beta, sc = 1.0 / (alpha - beta);
+      const double vcv = c00 + 2.0 * sc * acc[2] + sc * sc * acc[1];
+      const double K = 0.5 * t * t * vcv;
+      if (lane == 0) {
+        dg[k] = dkk;
+        od[k] = beta;
+        tau[k] = t;
+      }
+      double vv[RPL], ww[RPL];
+#pragma unroll
+      for (int s = 0; s < RPL; ++s) {
+        const int r = lane + 64 * s;
+        vv[s] = r < m ? (r == 0 ? 1.0 : sc * xr[s]) : 0.0;
+        ww[s] = r < m ? t * (c0[s] + sc * q[s]) - K * vv[s] : 0.0;
+        if (r < m) {
+          sv[r] = vv[s];
+          sw[r] = ww[s];
+        }
+      }
+      wave_sync();
+      // rows in groups of eight: every load of a group before its stores
+      for (int r0 = 0; r0 < m; r0 += 8) {
+        double cv[8][RPL], vr[8], wr[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int rr = min(r0 + u, m - 1);
+          vr[u] = sv[rr];
+          wr[u] = sw[rr];
+#pragma unroll
+          for (int s = 0; s < RPL; ++s) cv[u][s] = Cm[b + rr][cc[s]];
+        }
+        // unconditional stores: a row past the block repeats the last row's
+        // store with identical inputs, a lane past the block writes the
+        // padding column NM, which holds nothing
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+#pragma unroll
+          for (int s = 0; s < RPL; ++s)
+            Cm[b + min(r0 + u, m - 1)][cs[s]] = cv[u][s] - (vr[u] * ww[s] + wr[u] * vv[s]);
+      }
+#pragma unroll
+      for (int s = 0; s < RPL; ++s) {
+        const int r = lane + 64 * s;
+        if (r >= 1 && r < m) Cm[b + r][k] = vv[s];
+      }
+      wave_sync();
     }
-    for (int r = 1 + tid; r < m; r += blockDim.x) Cm[k + 1 + r][k] = sc * xs[r];
-    __syncthreads();
-  }
-  if (tid == 0) {
-    if (n >= 2) {
-      dg[n - 2] = Cm[n - 2][n - 2];
-      od[n - 2] = Cm[n - 1][n - 2];
-      tau[n - 2] = 0.0;
+    if (lane == 0) {
+      if (n >= 2) {
+        dg[n - 2] = Cm[n - 2][n - 2];
+        od[n - 2] = Cm[n - 1][n - 2];
+        tau[n - 2] = 0.0;
+      }
+      dg[n - 1] = Cm[n - 1][n - 1];
+      od[n - 1] = 0.0;
+      tau[n - 1] = 0.0;
     }
-    dg[n - 1] = Cm[n - 1][n - 1];
-    od[n - 1] = 0.0;
-    tau[n - 1] = 0.0;
   }
   __syncthreads();
 }
@@ -532,9 +548,11 @@ __device__ __forceinline__ void tridiagonalize(double (*Cm)[NM + 1], int n, doub
 // as minors, not ratios, so a step costs two multiply-adds instead of a
 // division; a ratio of magnitude below pivmin is replaced by -pivmin, and
 // every eight steps the pair (p_{i-1}, p_i) is rescaled by a power of two,
-// which keeps it in range without changing a sign or a ratio.  The eight
-// steps' diagonal and squared off-diagonal entries are loaded up front.
-__device__ inline int sturm_count(const double* dg, const double* od, int n, double x, double pivmin) {
+// which keeps it in range without changing a sign or a ratio.  Needs the
+// squared off-diagonal e2 and the padding of tri_prepare_sturm: the last
+// group of eight steps runs past n on decoupled diagonal entries above
+// every x, which change no sign, so no step needs a branch.
+__device__ inline int sturm_count(const double* dg, const double* e2, int n, double x, double pivmin) {
   double pm = 1.0, pc = dg[0] - x;
   if (fabs(pc) < pivmin) pc = -pivmin;
   int cnt = pc < 0.0;
@@ -542,19 +560,16 @@ __device__ inline int sturm_count(const double* dg, const double* od, int n, dou
     double dv[8], ev[8];
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
-      const int i = min(i0 + u, n - 1);
-      dv[u] = dg[i];
-      ev[u] = od[i - 1] * od[i - 1];
+      dv[u] = dg[i0 + u];
+      ev[u] = e2[i0 + u - 1];
     }
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
-      if (i0 + u < n) {
-        double pn = (dv[u] - x) * pc - ev[u] * pm;
-        if (fabs(pn) < pivmin * fabs(pc)) pn = -pivmin * pc;
-        cnt += (pn < 0.0) != (pc < 0.0);
-        pm = pc;
-        pc = pn;
-      }
+      double pn = (dv[u] - x) * pc - ev[u] * pm;
+      if (fabs(pn) < pivmin * fabs(pc)) pn = -pivmin * pc;
+      cnt += (int)(((unsigned)__double2hiint(pn) ^ (unsigned)__double2hiint(pc)) >> 31);   // sign change
+      pm = pc;
+      pc = pn;
     }
     int ex;
     frexp(fmax(fabs(pm), fabs(pc)), &ex);
@@ -564,14 +579,13 @@ __device__ inline int sturm_count(const double* dg, const double* od, int n, dou
   return cnt;
 }
 
-// Every eigenvalue of the tridiagonal T by multisection on the Sturm count:
-// G threads per eigenvalue (a power of two, G n <= 256: the counts are
-// arithmetic-bound, and one wave per SIMD keeps every SIMD busy without
-// queueing), one point each, so a round cuts the bracket into G + 1
-// pieces; the k-th smallest eigenvalue is bracketed directly.  Stops at
-// 2 eps max(||T||, |lambda|).
-__device__ inline void bisect_all(const double* dg, const double* od, int n, double* lam) {
-  const int tid = threadIdx.x;
+// Gershgorin interval of T, widened by the rounding allowance, and the
+// pivot floor of the Sturm count.
+struct TriBounds {
+  double lo, hi, tnorm, pivmin, atol;
+};
+
+__device__ inline TriBounds tri_bounds(const double* dg, const double* od, int n) {
   double glo = 0.0, ghi = 0.0, emax2 = 0.0;
   for (int i = 0; i < n; ++i) {
     const double r = (i > 0 ? fabs(od[i - 1]) : 0.0) + (i + 1 < n ? fabs(od[i]) : 0.0);
@@ -580,21 +594,50 @@ __device__ inline void bisect_all(const double* dg, const double* od, int n, dou
     if (i + 1 < n) emax2 = fmax(emax2, od[i] * od[i]);
   }
   const double eps = 1.1102230246251565e-16;   // 2^-53
-  const double tnorm = fmax(fabs(glo), fabs(ghi));
-  const double pivmin = 2.2250738585072014e-308 * fmax(1.0, emax2) / eps;
-  glo -= 2.0 * eps * tnorm + 2.0 * pivmin;
-  ghi += 2.0 * eps * tnorm + 2.0 * pivmin;
-  const double atol = 2.0 * eps * tnorm + 4.0 * pivmin;
+  TriBounds b;
+  b.tnorm = fmax(fabs(glo), fabs(ghi));
+  b.pivmin = 2.2250738585072014e-308 * fmax(1.0, emax2) / eps;
+  b.lo = glo - (2.0 * eps * b.tnorm + 2.0 * b.pivmin);
+  b.hi = ghi + (2.0 * eps * b.tnorm + 2.0 * b.pivmin);
+  b.atol = 2.0 * eps * b.tnorm + 4.0 * b.pivmin;
+  return b;
+}
+
+// e2[i] = e_i^2 (zero from n - 1 on) and eight diagonal entries past n
+// set above the Gershgorin interval, for sturm_count.  dg and e2 hold n + 8
+// entries.  All threads; a barrier must follow.
+__device__ inline void tri_prepare_sturm(double* dg, const double* od, double* e2, int n) {
+  const TriBounds tb = tri_bounds(dg, od, n);
+  const double pad = tb.hi + (tb.hi - tb.lo) + 1.0;
+  for (int i = threadIdx.x; i < n + 8; i += blockDim.x) {
+    if (i >= n) dg[i] = pad;
+    e2[i] = i + 1 < n ? od[i] * od[i] : 0.0;
+  }
+}
+
+// The eigenvalues e0 <= e < e1 of the tridiagonal T (the e-th smallest into
+// lam[e]) by multisection on the Sturm count (after tri_prepare_sturm): G threads per eigenvalue (a
+// power of two up to 64 with G (e1 - e0) <= 256: about one wave per SIMD,
+// since a second wave on a SIMD costs nearly as much as the rounds it
+// saves), one point each, so a round cuts the bracket into G + 1 pieces; the e-th
+// smallest eigenvalue is bracketed directly.  Stops at 2 eps max(||T||,
+// |lambda|).
+__device__ inline void bisect_range(const double* dg, const double* od, const double* e2, int n, int e0, int e1,
+                                    double* lam) {
+  const int tid = threadIdx.x, ne = e1 - e0;
+  if (ne <= 0) return;
+  const TriBounds tb = tri_bounds(dg, od, n);
+  const double eps = 1.1102230246251565e-16;   // 2^-53
   int G = 1;
-  while (G < 64 && 2 * G * n <= min(256, (int)blockDim.x)) G *= 2;
-  const int e = tid / G, g = tid % G;
-  if (e >= n) return;
-  double lo = glo, hi = ghi;
+  while (G < 64 && 2 * G * ne <= min(256, (int)blockDim.x)) G *= 2;
+  const int e = e0 + tid / G, g = tid % G;
+  if (e >= e1) return;
+  double lo = tb.lo, hi = tb.hi;
   for (int round = 0; round < 200; ++round) {
-    if (hi - lo <= fmax(atol, 2.0 * eps * fmax(fabs(lo), fabs(hi)))) break;
+    if (hi - lo <= fmax(tb.atol, 2.0 * eps * fmax(fabs(lo), fabs(hi)))) break;
     const double h = (hi - lo) / (double)(G + 1);
     const double x = lo + (double)(g + 1) * h;
-    const int cnt = sturm_count(dg, od, n, x, pivmin);
+    const int cnt = sturm_count(dg, e2, n, x, tb.pivmin);
     double nlo = lo, nhi = hi;
     if (x > lo && x < hi) {
       if (cnt > e) nhi = x;
@@ -611,163 +654,256 @@ __device__ inline void bisect_all(const double* dg, const double* od, int n, dou
   if (g == 0) lam[e] = 0.5 * (lo + hi);
 }
 
-// Shared-memory arrays of the tridiagonal eigen-pipeline (NM doubles each).
-struct TriArrays {
-  double *dg, *od, *tau, *q1, *q2, *lam, *ud, *u1, *u2, *ml, *yv, *red;
-  int* pivs;
-};
-
-// Eigenvalues of the symmetric C (LDS, order n): tridiagonalisation (C
-// keeps the reflectors), multisection, ascending sort into w.lam.  Returns
-// ||T||_inf.
-template <int NM, int NT>
-__device__ __forceinline__ double tri_eigenvalues(double (*C)[NM + 1], int n, const TriArrays& w) {
-  tridiagonalize<NM, NT>(C, n, w.dg, w.od, w.tau, w.q1, w.q2, w.ud, w.red);
-  bisect_all(w.dg, w.od, n, w.lam);
-  __syncthreads();
-  if (threadIdx.x == 0)   // equal eigenvalues may come out a rounding apart in either order
-    for (int i = 1; i < n; ++i) {
-      const double v = w.lam[i];
-      int j = i - 1;
-      while (j >= 0 && w.lam[j] > v) {
-        w.lam[j + 1] = w.lam[j];
-        --j;
-      }
-      w.lam[j + 1] = v;
+// Ascending order of v[e0..e1) into out[e0..e1) (out != v), by ranks:
+// equal eigenvalues may come out of the multisection a rounding apart in
+// either order.
+__device__ inline void rank_sort(const double* v, int e0, int e1, double* out) {
+  for (int t = e0 + (int)threadIdx.x; t < e1; t += blockDim.x) {
+    const double x = v[t];
+    int r = e0;
+    for (int j = e0; j < e1; ++j) {
+      const double u = v[j];
+      r += (u < x) || (u == x && j < t);
     }
-  __syncthreads();
+    out[r] = x;
+  }
+}
+
+__device__ inline double tri_norm_inf(const double* dg, const double* od, int n) {
   double tnorm = 0.0;
   for (int i = 0; i < n; ++i)
-    tnorm = fmax(tnorm, fabs(w.dg[i]) + (i > 0 ? fabs(w.od[i - 1]) : 0.0) + (i + 1 < n ? fabs(w.od[i]) : 0.0));
+    tnorm = fmax(tnorm, fabs(dg[i]) + (i > 0 ? fabs(od[i - 1]) : 0.0) + (i + 1 < n ? fabs(od[i]) : 0.0));
   return tnorm;
 }
 
-// Eigenvectors of T for the p smallest eigenvalues by inverse iteration
-// (rows of Z, leading dimension ldz, tridiagonal coordinates); clusters
-// (gaps <= 1e-3 ||T||) orthogonalised by modified Gram-Schmidt.
-__device__ inline void tri_vectors(int n, int p, double tnorm, const TriArrays& w, double* Z, int ldz) {
-  const int tid = threadIdx.x;
-  const double eps = 1.1102230246251565e-16;   // 2^-53
-  const double ortol = 1e-3 * tnorm;
-  for (int j = 0; j < p; ++j) {
-    int c0 = j;   // first vector of j's cluster
-    while (c0 > 0 && w.lam[c0] - w.lam[c0 - 1] <= ortol) --c0;
-    if (tid == 0) {
-      // LU with partial pivoting of T - lam_j I: row i of U has diagonal
-      // ud, first and second superdiagonals u1, u2; ml multipliers, pivs
-      // row interchanges
-      const double x = w.lam[j];
-      double a = w.dg[0] - x, b = n > 1 ? w.od[0] : 0.0;
-      for (int i = 0; i + 1 < n; ++i) {
-        const double c = w.od[i];                        // T[i+1][i]
-        const double a1 = w.dg[i + 1] - x, b1 = i + 2 < n ? w.od[i + 1] : 0.0;
-        if (fabs(a) >= fabs(c)) {
-          const double l = (a != 0.0) ? c / a : 0.0;
-          w.ud[i] = a; w.u1[i] = b; w.u2[i] = 0.0; w.ml[i] = l; w.pivs[i] = 0;
-          a = a1 - l * b;
-          b = b1;
-        } else {
-          const double l = a / c;
-          w.ud[i] = c; w.u1[i] = a1; w.u2[i] = b1; w.ml[i] = l; w.pivs[i] = 1;
-          a = b - l * a1;
-          b = -l * b1;
-        }
-      }
-      w.ud[n - 1] = a; w.u1[n - 1] = 0.0; w.u2[n - 1] = 0.0;
-      const double tiny = eps * (tnorm > 0.0 ? tnorm : 1.0);
-      for (int i = 0; i < n; ++i) {   // ud holds reciprocal pivots from here on
-        const double u = fabs(w.ud[i]) < tiny ? (w.ud[i] < 0.0 ? -tiny : tiny) : w.ud[i];
-        w.ud[i] = 1.0 / u;
-      }
-      // start vector: a fixed pseudo-random sequence in (-1, 1)
-      unsigned st = 0x9E3779B9u * (unsigned)(j + 1);
-      for (int i = 0; i < n; ++i) {
-        st = st * 1664525u + 1013904223u;
-        w.yv[i] = ((double)(st >> 8) / 16777216.0) * 2.0 - 1.0;
-      }
-    }
-    __syncthreads();
-    for (int it = 0; it < 3; ++it) {
-      if (tid == 0) {
-        // forward: interchanges and multipliers, row i + 1 carried in a register
-        double cur = w.yv[0];
-        for (int i = 0; i + 1 < n; ++i) {
-          const double nx = w.yv[i + 1];
-          if (w.pivs[i]) {
-            w.yv[i] = nx;
-            cur -= w.ml[i] * nx;
-          } else {
-            w.yv[i] = cur;
-            cur = nx - w.ml[i] * cur;
-          }
-        }
-        w.yv[n - 1] = cur;
-        // back substitution with the three bands of U (reciprocal pivots);
-        // near-singular shifts make the solution grow by 1/tiny per small
-        // pivot, so the whole system is rescaled before it could overflow
-        double c1 = 0.0, c2 = 0.0;
-        for (int i = n - 1; i >= 0; --i) {
-          double v = (w.yv[i] - w.u1[i] * c1 - w.u2[i] * c2) * w.ud[i];
-          for (int g = 0; g < 4 && !(fabs(v) <= 1e150); ++g) {
-            for (int q = 0; q < n; ++q) w.yv[q] *= 1e-150;
-            c1 *= 1e-150;
-            c2 *= 1e-150;
-            v = (w.yv[i] - w.u1[i] * c1 - w.u2[i] * c2) * w.ud[i];
-          }
-          w.yv[i] = v;
-          c2 = c1;
-          c1 = v;
-        }
-      }
-      __syncthreads();
-      // orthogonalise against the cluster's earlier vectors, normalise
-      for (int q = c0; q < j; ++q) {
-        double part = 0.0;
-        for (int i = tid; i < n; i += blockDim.x) part += Z[q * ldz + i] * w.yv[i];
-        const double dq = block_sum_sel(part, w.red);
-        for (int i = tid; i < n; i += blockDim.x) w.yv[i] -= dq * Z[q * ldz + i];
-        __syncthreads();
-      }
-      double part = 0.0;
-      for (int i = tid; i < n; i += blockDim.x) part += w.yv[i] * w.yv[i];
-      const double nrm = sqrt(block_sum_sel(part, w.red));
-      const double inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
-      for (int i = tid; i < n; i += blockDim.x) w.yv[i] *= inv;
-      __syncthreads();
-    }
-    for (int i = tid; i < n; i += blockDim.x) Z[j * ldz + i] = w.yv[i];
-    __syncthreads();
-  }
+// Shared-memory arrays of the tridiagonal eigen-pipeline: dg, od, e2, tau,
+// q1, lam (NM doubles each, NM + 8 for dg and e2), and nslot inverse-iteration slots of five
+// NM-double arrays (U's diagonal and two superdiagonals, the multipliers,
+// the iterate) and NM pivot flags.
+struct TriArrays {
+  double *dg, *od, *e2, *tau, *q1, *lam;   // dg and e2: NM + 8 entries
+  double* inv;   // nslot x 5 x nm
+  int* ipiv;     // nslot x nm
+  int nslot, nm;
+};
+
+// Eigenvalues of the symmetric C (LDS, order n): tridiagonalisation (C
+// keeps the reflectors), multisection, ascending order into w.lam.  Returns
+// ||T||_inf.
+template <int NM>
+__device__ __forceinline__ double tri_eigenvalues(double (*C)[NM + 1], int n, const TriArrays& w) {
+  tridiagonalize<NM>(C, n, w.dg, w.od, w.tau, w.q1, w.lam);
+  tri_prepare_sturm(w.dg, w.od, w.e2, n);
+  __syncthreads();
+  bisect_range(w.dg, w.od, w.e2, n, 0, n, w.q1);
+  __syncthreads();
+  rank_sort(w.q1, 0, n, w.lam);
+  __syncthreads();
+  return tri_norm_inf(w.dg, w.od, n);
 }
 
-// z = H_0 H_1 ... H_{n-3} y for the p rows of Z: each wave takes whole
-// vectors and applies the reflectors from the last to the first (no block
-// barriers); lane l owns the entries i = l mod 64 throughout.
-template <int NM>
-__device__ __forceinline__ void tri_back_transform(const double (*C)[NM + 1], const double* tau, int n, int p,
-                                                   double* Z, int ldz) {
-  const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63, nw = blockDim.x >> 6;
-  for (int j = wv; j < p; j += nw) {
-    double* z = Z + (size_t)j * ldz;
-    for (int k = n - 3; k >= 0; --k) {
-      const double tk = tau[k];
-      if (tk == 0.0) continue;
-      double part = 0.0;
-      for (int i = lane; i < n; i += 64)
-        if (i > k) part += ((i == k + 1) ? 1.0 : C[i][k]) * z[i];
-      const double f = tk * wave_total(part);
-      for (int i = lane; i < n; i += 64)
-        if (i > k) z[i] -= f * ((i == k + 1) ? 1.0 : C[i][k]);
+// Eigenvectors of T for the p smallest eigenvalues by inverse iteration
+// (rows of Z, leading dimension ldz, tridiagonal coordinates).  Clusters
+// (runs of eigenvalues with gaps <= 1e-3 ||T||) are independent: wave w <
+// nslot takes the clusters w, w + nslot, ..., and inside a cluster computes
+// the vectors in order, each orthogonalised against the cluster's earlier
+// ones by modified Gram-Schmidt after every solve.  Lane 0 runs the serial
+// recurrences (LU with partial pivoting of T - lam_j I, three rounds of the
+// two triangular solves), reading their inputs eight entries at a time; the
+// wave shares the reciprocal pivots, dot products and scaling.
+__device__ inline void tri_vectors(int n, int p, double tnorm, const TriArrays& w, double* Z, int ldz) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const double eps = 1.1102230246251565e-16;   // 2^-53
+  const double ortol = 1e-3 * tnorm;
+  if (wv < w.nslot && n > 0) {
+    double* ud = w.inv + (size_t)wv * 5 * w.nm;   // reciprocal pivots after the factorisation
+    double* u1 = ud + w.nm;
+    double* u2 = u1 + w.nm;
+    double* ml = u2 + w.nm;
+    double* yv = ml + w.nm;
+    int* pivs = w.ipiv + wv * w.nm;
+    int cl = -1, c0 = 0;
+    for (int j = 0; j < p; ++j) {
+      if (j == 0 || w.lam[j] - w.lam[j - 1] > ortol) {   // j opens a cluster
+        ++cl;
+        c0 = j;
+      }
+      if (cl % w.nslot != wv) continue;
+      const double x = w.lam[j];
+      if (lane == 0) {
+        // row i of U: diagonal ud, superdiagonals u1, u2; multipliers ml,
+        // row interchanges pivs.  Full groups of eight steps without
+        // branches, their inputs loaded first; the tail one step at a time.
+        double a = w.dg[0] - x, b = n > 1 ? w.od[0] : 0.0;
+        auto lu_step = [&](int i, double c, double a1, double b1) {
+          const bool sw = fabs(a) < fabs(c);
+          const double pv = sw ? c : a, qv = sw ? a : c;
+          const double l = pv != 0.0 ? qv / pv : 0.0;
+          ud[i] = pv;
+          u1[i] = sw ? a1 : b;
+          u2[i] = sw ? b1 : 0.0;
+          ml[i] = l;
+          pivs[i] = sw;
+          const double na = sw ? b - l * a1 : a1 - l * b;
+          b = sw ? -l * b1 : b1;
+          a = na;
+        };
+        int i = 0;
+        for (; i + 8 < n; i += 8) {
+          double cv[8], av[8], bv[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            cv[u] = w.od[i + u];
+            av[u] = w.dg[i + u + 1] - x;
+            bv[u] = i + u + 2 < n ? w.od[i + u + 1] : 0.0;
+          }
+#pragma unroll
+          for (int u = 0; u < 8; ++u) lu_step(i + u, cv[u], av[u], bv[u]);
+        }
+        for (; i + 1 < n; ++i) lu_step(i, w.od[i], w.dg[i + 1] - x, i + 2 < n ? w.od[i + 1] : 0.0);
+        ud[n - 1] = a; u1[n - 1] = 0.0; u2[n - 1] = 0.0;
+        // start vector: a fixed pseudo-random sequence in (-1, 1)
+        unsigned st = 0x9E3779B9u * (unsigned)(j + 1);
+        for (int i = 0; i < n; ++i) {
+          st = st * 1664525u + 1013904223u;
+          yv[i] = ((double)(st >> 8) / 16777216.0) * 2.0 - 1.0;
+        }
+      }
+      wave_sync();
+      const double tiny = eps * (tnorm > 0.0 ? tnorm : 1.0);
+      for (int i = lane; i < n; i += 64) {
+        const double u = fabs(ud[i]) < tiny ? (ud[i] < 0.0 ? -tiny : tiny) : ud[i];
+        ud[i] = 1.0 / u;
+      }
+      wave_sync();
+      for (int it = 0; it < 3; ++it) {
+        if (lane == 0) {
+          // forward: interchanges and multipliers, row i + 1 carried in a register
+          double cur = yv[0];
+          auto fw_step = [&](int i, double nx, double mv, int pv) {
+            yv[i] = pv ? nx : cur;
+            cur = pv ? cur - mv * nx : nx - mv * cur;
+          };
+          int i = 0;
+          for (; i + 8 < n; i += 8) {
+            double nx[8], mv[8];
+            int pv[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+              nx[u] = yv[i + u + 1];
+              mv[u] = ml[i + u];
+              pv[u] = pivs[i + u];
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) fw_step(i + u, nx[u], mv[u], pv[u]);
+          }
+          for (; i + 1 < n; ++i) fw_step(i, yv[i + 1], ml[i], pivs[i]);
+          yv[n - 1] = cur;
+          // back substitution with the three bands of U (reciprocal pivots);
+          // near-singular shifts make the solution grow by 1/tiny per small
+          // pivot, so the whole system is rescaled before it could overflow
+          double c1 = 0.0, c2 = 0.0;
+          auto bk_step = [&](int i, double y, double a1, double a2, double rp, double* pend, int npend) {
+            double v = (y - a1 * c1 - a2 * c2) * rp;
+            for (int g = 0; g < 4 && !(fabs(v) <= 1e150); ++g) {
+              for (int q = 0; q < n; ++q) yv[q] *= 1e-150;
+              for (int q = 0; q < npend; ++q) pend[q] *= 1e-150;   // loaded, not yet used
+              y *= 1e-150;
+              c1 *= 1e-150;
+              c2 *= 1e-150;
+              v = (y - a1 * c1 - a2 * c2) * rp;
+            }
+            yv[i] = v;
+            c2 = c1;
+            c1 = v;
+          };
+          int i1 = n - 1;
+          for (; i1 - 7 >= 0; i1 -= 8) {
+            double yb[8], a1[8], a2[8], rp[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+              yb[u] = yv[i1 - u];
+              a1[u] = u1[i1 - u];
+              a2[u] = u2[i1 - u];
+              rp[u] = ud[i1 - u];
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) bk_step(i1 - u, yb[u], a1[u], a2[u], rp[u], yb + u + 1, 7 - u);
+          }
+          for (; i1 >= 0; --i1) bk_step(i1, yv[i1], u1[i1], u2[i1], ud[i1], nullptr, 0);
+        }
+        wave_sync();
+        // orthogonalise against the cluster's earlier vectors, normalise
+        for (int q = c0; q < j; ++q) {
+          double part = 0.0;
+          for (int i = lane; i < n; i += 64) part += Z[q * ldz + i] * yv[i];
+          const double dq = wave_total(part);
+          for (int i = lane; i < n; i += 64) yv[i] -= dq * Z[q * ldz + i];
+        }
+        double part = 0.0;
+        for (int i = lane; i < n; i += 64) part += yv[i] * yv[i];
+        const double nrm = sqrt(wave_total(part));
+        const double inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
+        for (int i = lane; i < n; i += 64) yv[i] *= inv;
+        wave_sync();
+      }
+      for (int i = lane; i < n; i += 64) Z[j * ldz + i] = yv[i];
+      wave_sync();
     }
   }
   __syncthreads();
 }
 
-#define TRI_SHARED(NM)                                                                          \
-  __shared__ double dg_[NM], od_[NM], tau_[NM], q1_[NM], q2_[NM], lam_[NM], ud_[NM], u1_[NM], \
-      u2_[NM], ml_[NM], yv_[NM], red_[80];                                                      \
-  __shared__ int pivs_[NM];                                                                     \
-  const TriArrays tw{dg_, od_, tau_, q1_, q2_, lam_, ud_, u1_, u2_, ml_, yv_, red_, pivs_};
+// z = H_0 H_1 ... H_{n-3} y for the p rows of Z: each wave takes whole
+// vectors, holds one in registers (lane l owns the entries l and l + 64)
+// and applies the reflectors from the last to the first (no block
+// barriers).
+template <int NM>
+__device__ __forceinline__ void tri_back_transform(const double (*C)[NM + 1], const double* tau, int n, int p,
+                                                   double* Z, int ldz) {
+  constexpr int RPL = NM / 64;
+  const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63, nw = blockDim.x >> 6;
+  for (int j = wv; j < p; j += nw) {
+    double* z = Z + (size_t)j * ldz;
+    double zr[RPL];
+#pragma unroll
+    for (int s = 0; s < RPL; ++s) {
+      const int i = lane + 64 * s;
+      zr[s] = i < n ? z[i] : 0.0;
+    }
+    for (int k = n - 3; k >= 0; --k) {
+      const double tk = tau[k];
+      if (tk == 0.0) continue;
+      double hv[RPL];
+      double part = 0.0;
+#pragma unroll
+      for (int s = 0; s < RPL; ++s) {
+        const int i = lane + 64 * s;
+        hv[s] = (i > k + 1 && i < n) ? C[i][k] : (i == k + 1 ? 1.0 : 0.0);
+        part += hv[s] * zr[s];
+      }
+      const double f = tk * wave_total(part);
+#pragma unroll
+      for (int s = 0; s < RPL; ++s) zr[s] -= f * hv[s];
+    }
+#pragma unroll
+    for (int s = 0; s < RPL; ++s) {
+      const int i = lane + 64 * s;
+      if (i < n) z[i] = zr[s];
+    }
+  }
+  __syncthreads();
+}
+
+// LDS of the pipeline for order NM and NT threads: one inverse-iteration
+// slot per wave for NM = 64, a single slot for NM = 128 (whose matrix takes
+// most of the LDS).
+#define TRI_SHARED(NM, NT)                                                                     \
+  constexpr int TRI_NSLOT = (NM) <= 64 ? (NT) / 64 : 1;                                        \
+  __shared__ double dg_[(NM) + 8], od_[NM], e2_[(NM) + 8], tau_[NM], q1_[NM], lam_[NM],            \
+      inv_[TRI_NSLOT * 5 * (NM)];                                                              \
+  __shared__ int ipiv_[TRI_NSLOT * (NM)];                                                      \
+  const TriArrays tw{dg_, od_, e2_, tau_, q1_, lam_, inv_, ipiv_, TRI_NSLOT, NM};
 
 template <int NM, int NT>
 __global__ void __launch_bounds__(NT) sygv_sel_kernel(const SygvDesc* __restrict__ descs, double sel, int* dflag,
@@ -775,7 +911,7 @@ __global__ void __launch_bounds__(NT) sygv_sel_kernel(const SygvDesc* __restrict
   constexpr bool SMALL = NM <= 64;
   __shared__ double Cm[NM][NM + 1];
   __shared__ double LZsm[SMALL ? NM : 1][SMALL ? NM + 1 : 1];
-  TRI_SHARED(NM)
+  TRI_SHARED(NM, NT)
   const SygvDesc d = descs[blockIdx.x];
   const int n = d.n, tid = threadIdx.x;
   if (n <= 0) return;
@@ -785,7 +921,7 @@ __global__ void __launch_bounds__(NT) sygv_sel_kernel(const SygvDesc* __restrict
   // Z: selected vectors (row j = vector j), LDS for the small variant
   double* Z = SMALL ? &LZsm[0][0] : EigScratch<NM>::V(scratch);
   const int ldz = SMALL ? NM + 1 : NM;
-  const double tnorm = tri_eigenvalues<NM, NT>(Cm, n, tw);
+  const double tnorm = tri_eigenvalues<NM>(Cm, n, tw);
   for (int t = tid; t < n; t += blockDim.x) d.w[t] = tw.lam[t];
   int p = 0;
   while (p < n && tw.lam[p] <= sel) ++p;
@@ -881,11 +1017,11 @@ __global__ void __launch_bounds__(256) spinv_finish_kernel(const SchurWork* __re
 }
 
 // X <- (L L^T)^{-1} X for the Cholesky factor L (LDS, lower triangle) and
-// X (k x m, global, leading dimension ldx): blocked forward and backward
+// X (k x m, LDS or global, leading dimension ldx): blocked forward and backward
 // substitution, one thread per column inside a 16-row block, all threads
 // on the update of the remaining rows.
 template <int NM>
-__device__ __forceinline__ void chol_solve_global(const double (*Lm)[NM + 1], int k, double* X, int ldx, int m) {
+__device__ __forceinline__ void chol_solve(const double (*Lm)[NM + 1], int k, double* X, int ldx, int m) {
   const int tid = threadIdx.x;
   for (int r0 = 0; r0 < k; r0 += 16) {
     const int rw = min(16, k - r0);
@@ -945,36 +1081,88 @@ __device__ __forceinline__ void chol_solve_global(const double (*Lm)[NM + 1], in
   }
 }
 
+// Second half of the fallback: X = M12 (k x m, leading dimension ldx),
+// projected off V_d (rows of Vd), solved with M' = L L^T (L in Am), then
+// M22 -= M21 X, with M21 staged in Am when it fits.
+template <int NM>
+__device__ __forceinline__ void spinv_fallback_apply(double (*Am)[NM + 1], double* M, int ld, int k, int m,
+                                                     const double* Vd, int pd, double* X, int ldx) {
+  const int tid = threadIdx.x, tj = tid & 63, ti = tid >> 6, nstep = blockDim.x >> 6;
+  for (int idx = tid; idx < k * m; idx += blockDim.x) {
+    const int r = idx / m, c = idx - r * m;
+    X[(size_t)r * ldx + c] = M[(size_t)r * ld + k + c];
+  }
+  __syncthreads();
+  for (int c = tid; c < m; c += blockDim.x)
+    for (int q = 0; q < pd; ++q) {
+      const double* vq = Vd + (size_t)q * k;
+      double t = 0.0;
+      for (int i = 0; i < k; ++i) t += vq[i] * X[(size_t)i * ldx + c];
+      for (int i = 0; i < k; ++i) X[(size_t)i * ldx + c] -= vq[i] * t;
+    }
+  __syncthreads();
+  chol_solve<NM>(Am, k, X, ldx, m);
+  const bool stage = m <= NM;
+  if (stage) {
+    for (int r = ti; r < m; r += nstep)
+      for (int j = tj; j < k; j += 64) Am[r][j] = M[(size_t)(k + r) * ld + j];
+    __syncthreads();
+  }
+  for (int idx = tid; idx < m * m; idx += blockDim.x) {
+    const int r = idx / m, c = idx - r * m;
+    double acc = 0.0;
+    if (stage)
+      for (int q = 0; q < k; ++q) acc += Am[r][q] * X[(size_t)q * ldx + c];
+    else
+      for (int q = 0; q < k; ++q) acc += M[(size_t)(k + r) * ld + q] * X[(size_t)q * ldx + c];
+    M[(size_t)(k + r) * ld + k + c] -= acc;
+  }
+}
+
 // Fallback for flagged matrices, by deflation: sym(M11) has the
 // eigenvalues lambda and the dropped ones (<= rtol lambda_max) span V_d.
 // With sigma = lambda_max, M' = sym(M11) + V_d (sigma - Lambda_d) V_d^T is
-// positive definite and (sym M11)^+ = M'^{-1} - V_d V_d^T / sigma, so
-//   M22 -= M21 (M'^{-1} M12 - V_d (V_d^T M12) / sigma).
-// Eigenvalues and V_d come from the tridiagonal pipeline, M'^{-1} M12 from
-// a Cholesky solve in LDS.
+// positive definite with M'^{-1} V_d = V_d / sigma, so
+//   (sym M11)^+ M12 = M'^{-1} M12 - V_d V_d^T M12 / sigma
+//                   = M'^{-1} (I - V_d V_d^T) M12:
+// M12 is projected off V_d and solved with the Cholesky factor of M'.  Of
+// the spectrum only lambda_max, the number of dropped eigenvalues (a Sturm
+// count at the cut) and the dropped eigenvalues are computed, V_d by
+// inverse iteration on the tridiagonal form.  For NM = 64 the right-hand
+// side lives in LDS.
 template <int NM, int NT>
 __global__ void __launch_bounds__(NT) spinv_fallback_kernel(const SchurWork* __restrict__ ws, double rtol,
                                                             int* dflag) {
+  constexpr bool XL = NM <= 64;
   __shared__ double Am[NM][NM + 1];
-  TRI_SHARED(NM)
+  __shared__ double Xs[XL ? NM : 1][XL ? NM + 1 : 1];
+  TRI_SHARED(NM, NT)
   __shared__ int pd_s;
   const SchurWork w = ws[blockIdx.x];
   const int nv = w.d.nv, k = w.d.k, m = nv - k, ld = w.d.ld, tid = threadIdx.x;
   if (k <= 0 || *w.flag == 0) return;
   double* M = w.d.M;
-  double* Vd = w.work;                          // dropped eigenvectors, rows, ld k
-  double* X = w.work + (size_t)k * k;           // k x m
+  double* Vd = w.work;   // dropped eigenvectors, rows, ld k
   const int tj = tid & 63, ti = tid >> 6, nstep = blockDim.x >> 6;
   for (int r = ti; r < k; r += nstep)
     for (int j = tj; j < k; j += 64) Am[r][j] = 0.5 * (M[(size_t)r * ld + j] + M[(size_t)j * ld + r]);
   __syncthreads();
-  const double tnorm = tri_eigenvalues<NM, NT>(Am, k, tw);
+  tridiagonalize<NM>(Am, k, tw.dg, tw.od, tw.tau, tw.q1, tw.lam);
+  tri_prepare_sturm(tw.dg, tw.od, tw.e2, k);
+  __syncthreads();
+  bisect_range(tw.dg, tw.od, tw.e2, k, k - 1, k, tw.lam);
+  __syncthreads();
   const double lmax = tw.lam[k - 1];
   if (!(lmax > 0.0)) return;   // nothing kept: the pseudo-inverse is 0
   const double cut = rtol * lmax;
-  int pd = 0;
-  while (pd < k && tw.lam[pd] <= cut) ++pd;
-  tri_vectors(k, pd, tnorm, tw, Vd, k);
+  if (tid == 0) pd_s = min(k - 1, sturm_count(tw.dg, tw.e2, k, cut, tri_bounds(tw.dg, tw.od, k).pivmin));
+  __syncthreads();
+  const int pd = pd_s;
+  bisect_range(tw.dg, tw.od, tw.e2, k, 0, pd, tw.q1);
+  __syncthreads();
+  rank_sort(tw.q1, 0, pd, tw.lam);
+  __syncthreads();
+  tri_vectors(k, pd, tri_norm_inf(tw.dg, tw.od, k), tw, Vd, k);
   tri_back_transform<NM>(Am, tw.tau, k, pd, Vd, k);
   // M' in Am, then its Cholesky factor
   for (int r = ti; r < k; r += nstep)
@@ -985,30 +1173,10 @@ __global__ void __launch_bounds__(NT) spinv_fallback_kernel(const SchurWork* __r
     }
   __syncthreads();
   cholesky_panels<NM>(&Am[0][0], NM + 1, k, dflag);
-  // X = M'^{-1} M12 - V_d (V_d^T M12) / sigma
-  for (int idx = tid; idx < k * m; idx += blockDim.x) {
-    const int r = idx / m, c = idx % m;
-    X[(size_t)r * m + c] = M[(size_t)r * ld + k + c];
-  }
-  __syncthreads();
-  chol_solve_global<NM>(Am, k, X, m, m);
-  if (pd > 0) {
-    for (int c = tid; c < m; c += blockDim.x)
-      for (int q = 0; q < pd; ++q) {
-        double t = 0.0;
-        for (int i = 0; i < k; ++i) t += Vd[(size_t)q * k + i] * M[(size_t)i * ld + k + c];
-        t /= lmax;
-        for (int i = 0; i < k; ++i) X[(size_t)i * m + c] -= Vd[(size_t)q * k + i] * t;
-      }
-    __syncthreads();
-  }
-  // M22 -= M21 X
-  for (int idx = tid; idx < m * m; idx += blockDim.x) {
-    const int r = idx / m, c = idx % m;
-    double acc = 0.0;
-    for (int q = 0; q < k; ++q) acc += M[(size_t)(k + r) * ld + q] * X[(size_t)q * m + c];
-    M[(size_t)(k + r) * ld + k + c] -= acc;
-  }
+  if (XL && m <= NM)
+    spinv_fallback_apply<NM>(Am, M, ld, k, m, Vd, pd, &Xs[0][0], NM + 1);
+  else
+    spinv_fallback_apply<NM>(Am, M, ld, k, m, Vd, pd, w.work + (size_t)k * k, m);
 }
 
 // Parallel sum pieces: [[A + B, B], [-A, 0]] (its pseudo-inverse Schur
