@@ -1,6 +1,9 @@
-// Ring of kernel descriptor arrays and host->device uploads: a pinned host
-// mirror and a device buffer; each put() copies into pinned memory and
-// issues a stream-ordered async copy.  The ring is split in two halves; an
+// Ring of kernel descriptor arrays and host->device uploads in pinned,
+// device-coherent host memory.  put() writes a descriptor array into the
+// ring and returns the device view of it: kernels read their descriptor
+// once, at the start, straight from host memory, so no copy is queued.
+// upload() stages bytes in the ring and queues a stream-ordered async copy
+// into caller-owned device memory.  The ring is split in two halves; an
 // event is recorded on the stream whenever the write position leaves a half,
 // and before a half is reused the event of its previous use is awaited --
 // work issued half a ring earlier, normally long finished -- so a region is
@@ -23,7 +26,6 @@ class Arena {
  public:
   explicit Arena(hipStream_t s) : s_(s) {}
   ~Arena() {
-    if (d_) (void)hipFree(d_);
     if (h_) (void)hipHostFree(h_);
     for (int i = 0; i < 2; ++i)
       if (ev_[i]) (void)hipEventDestroy(ev_[i]);
@@ -31,8 +33,7 @@ class Arena {
   void* put(const void* src, size_t bytes) {
     const size_t off = reserve(bytes);
     std::memcpy(h_ + off, src, bytes);
-    ABDDC_HIP(hipMemcpyAsync(d_ + off, h_ + off, bytes, hipMemcpyHostToDevice, s_));
-    return d_ + off;
+    return dh_ + off;
   }
   // Stream-ordered upload into caller-owned device memory through the ring.
   void upload(void* dst, const void* src, size_t bytes) {
@@ -83,12 +84,11 @@ class Arena {
     ABDDC_HIP(hipStreamSynchronize(s_));
     size_t cap = cap_ ? 2 * cap_ : (size_t(32) << 20);
     while (cap < need) cap *= 2;
-    if (d_) ABDDC_HIP(hipFree(d_));
     if (h_) ABDDC_HIP(hipHostFree(h_));
-    d_ = nullptr;
     h_ = nullptr;
-    ABDDC_HIP(hipMalloc(&d_, cap));
-    ABDDC_HIP(hipHostMalloc(&h_, cap, hipHostMallocDefault));
+    dh_ = nullptr;
+    ABDDC_HIP(hipHostMalloc(&h_, cap, hipHostMallocMapped | hipHostMallocCoherent));
+    ABDDC_HIP(hipHostGetDevicePointer(reinterpret_cast<void**>(&dh_), h_, 0));
     for (int i = 0; i < 2; ++i) {
       if (!ev_[i]) ABDDC_HIP(hipEventCreateWithFlags(&ev_[i], hipEventDisableTiming));
       used_[i] = false;
@@ -98,8 +98,8 @@ class Arena {
     ht.mark("staging ring: grow");
   }
   hipStream_t s_;
-  char* d_ = nullptr;
-  char* h_ = nullptr;
+  char* h_ = nullptr;    // pinned ring, host view
+  char* dh_ = nullptr;   // the same memory as the device sees it
   size_t cap_ = 0, off_ = 0;
   hipEvent_t ev_[2] = {nullptr, nullptr};
   bool used_[2] = {false, false};

@@ -16,7 +16,11 @@ namespace {
 // [[sum_k S_k, S_1, ..., S_m], [-I, 0, ..., 0]]: its Schur complement onto
 // the trailing block is [(sum S)^{-1} S_1, ..., (sum S)^{-1} S_m].
 __global__ void deluxe_build_kernel(const DeluxeDesc* __restrict__ descs) {
-  const DeluxeDesc d = descs[blockIdx.y];
+  // the descriptor (indexed by member) staged in LDS once per workgroup
+  __shared__ DeluxeDesc sd;
+  if (threadIdx.x == 0) sd = descs[blockIdx.y];
+  __syncthreads();
+  const DeluxeDesc& d = sd;
   const int n = d.n, cols = (d.m + 1) * n;
   for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < 2 * n * cols; idx += gridDim.x * blockDim.x) {
     const int r = idx / cols, c = idx % cols;
@@ -45,7 +49,10 @@ __global__ void __launch_bounds__(256) edge_assemble_kernel(const EdgeAsmDesc* _
   constexpr int NE = 16, NW = 48;
   __shared__ double Th[4][NE][NW];
   __shared__ double Z[NE][NW + NE];
-  const EdgeAsmDesc d = descs[blockIdx.x];
+  __shared__ EdgeAsmDesc sd;   // the descriptor (indexed by member) staged in LDS once
+  if (threadIdx.x == 0) sd = descs[blockIdx.x];
+  __syncthreads();
+  const EdgeAsmDesc& d = sd;
   const int nE = d.nE, m = d.m, nw = (m - 1) * nE, nv = d.nv, nH = d.nH, tid = threadIdx.x;
   const int nt = nw + nE;  // [wcheck, what] width of T_E^(k) = [That_k | I]
   // variable position in Q of paper-order index a (wcheck, what)
