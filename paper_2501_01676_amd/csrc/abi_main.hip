@@ -76,7 +76,7 @@ void arnoldi_step(abddc_ctx* c, int restart, hipStream_t s) {
   launch_dots_dev(c->d_V.p, nn, st, restart, c->d_w.p, n, c->d_partial.p, c->d_h2.p, s);
   launch_axpy_multi_dev(c->d_V.p, nn, st, c->d_h2.p, -1.0, c->d_w.p, n, s);
   launch_dots(c->d_w.p, n, 1, c->d_w.p, n, c->d_partial.p, c->d_nrm.p, s);
-  launch_arnoldi_finish_dev(st, c->d_h1.p, c->d_h2.p, c->d_nrm.p, s);
+  launch_arnoldi_finish_dev(st, c->d_h1.p, c->d_h2.p, c->d_nrm.p, c->dh_step, s);
   launch_scale_to_col(c->d_w.p, st, c->d_V.p, nn, c->d_vcur.p, n, s);
 }
 
@@ -454,20 +454,18 @@ extern "C" int abddc_gmres_solve(abddc_ctx* c, int32_t restart, double rtol, int
       c->d_nrm.alloc(1);
       c->d_partial.alloc((size_t)DOT_BLOCKS * DOT_STRIDE);
       c->d_gst.alloc(1);
-      ABDDC_HIP(hipHostMalloc(&c->h_gst, sizeof(GmresState), hipHostMallocDefault));
-      ABDDC_HIP(hipHostMalloc(&c->h_step, 8 * sizeof(double), hipHostMallocDefault));
+      // scalars the kernels publish straight to the host: two step slots and
+      // the restart slot (pinned, device-coherent)
+      ABDDC_HIP(hipHostMalloc(&c->h_step, 12 * sizeof(double), hipHostMallocMapped | hipHostMallocCoherent));
+      ABDDC_HIP(hipHostGetDevicePointer(reinterpret_cast<void**>(&c->dh_step), c->h_step, 0));
       for (int i = 0; i < 2; ++i) ABDDC_HIP(hipEventCreateWithFlags(&c->ev_step[i], hipEventDisableTiming));
     }
     const auto t0 = std::chrono::steady_clock::now();
     record(c, 13);
     double* V = c->d_V.p;
     double* Z = c->d_Z.p;
-    const size_t tail = offsetof(GmresState, beta);
-    auto read_scalars = [&]() {
-      ABDDC_HIP(hipMemcpyAsync(reinterpret_cast<char*>(c->h_gst) + tail, reinterpret_cast<char*>(c->d_gst.p) + tail,
-                               4 * sizeof(double), hipMemcpyDeviceToHost, s));
-      ABDDC_HIP(hipStreamSynchronize(s));
-    };
+    const double* h_start = c->h_step + 8;   // beta, hn, inv_hn, res of the last restart
+    auto read_scalars = [&]() { ABDDC_HIP(hipStreamSynchronize(s)); };
     int iters = 0, restarts = 0;
     double relres = 0.0;
     bool converged = false;
@@ -475,9 +473,9 @@ extern "C" int abddc_gmres_solve(abddc_ctx* c, int32_t restart, double rtol, int
     if (n > 0) {
       ABDDC_HIP(hipMemcpyAsync(c->d_r.p, c->d_ghat.p, n * sizeof(double), hipMemcpyDeviceToDevice, s));
       launch_dots(c->d_r.p, n, 1, c->d_r.p, n, c->d_partial.p, c->d_nrm.p, s);
-      launch_gmres_start(c->d_gst.p, c->d_nrm.p, s);
+      launch_gmres_start(c->d_gst.p, c->d_nrm.p, c->dh_step + 8, s);
       read_scalars();
-      const double bnorm = c->h_gst->beta;
+      const double bnorm = h_start[0];
       if (bnorm == 0.0) converged = true;
       const char* genv = std::getenv("ABDDC_GRAPH");
       const bool use_graph = !(genv && genv[0] == '0');
@@ -497,9 +495,7 @@ extern "C" int abddc_gmres_solve(abddc_ctx* c, int32_t restart, double rtol, int
             ABDDC_HIP(hipGraphLaunch(c->step_exec, s));
           else
             arnoldi_step(c, restart, s);
-          eager_done = true;
-          ABDDC_HIP(hipMemcpyAsync(c->h_step + 4 * (j & 1), reinterpret_cast<char*>(c->d_gst.p) + tail,
-                                   4 * sizeof(double), hipMemcpyDeviceToHost, s));
+          eager_done = true;   // the step's last kernel publishes its scalars to h_step[4 (j % 2) ..]
           ABDDC_HIP(hipEventRecord(c->ev_step[j & 1], s));
         };
         int jend = 0;
@@ -520,9 +516,9 @@ extern "C" int abddc_gmres_solve(abddc_ctx* c, int32_t restart, double rtol, int
         apply_schur_dev(c, c->d_x.p, c->d_w.p, s);
         launch_sub(c->d_ghat.p, c->d_w.p, c->d_r.p, n, s);
         launch_dots(c->d_r.p, n, 1, c->d_r.p, n, c->d_partial.p, c->d_nrm.p, s);
-        launch_gmres_start(c->d_gst.p, c->d_nrm.p, s);
+        launch_gmres_start(c->d_gst.p, c->d_nrm.p, c->dh_step + 8, s);
         read_scalars();
-        const double beta = c->h_gst->beta;
+        const double beta = h_start[0];
         relres = beta / bnorm;
         if (beta <= rtol * bnorm) {
           converged = true;
@@ -663,7 +659,6 @@ extern "C" void abddc_destroy(abddc_ctx* c) {
   (void)hipSetDevice(c->device);
   StreamScope ss(c->stream);
   (void)hipStreamSynchronize(c->stream);
-  if (c->h_gst) (void)hipHostFree(c->h_gst);
   if (c->h_step) (void)hipHostFree(c->h_step);
   for (int i = 0; i < 2; ++i)
     if (c->ev_step[i]) (void)hipEventDestroy(c->ev_step[i]);

@@ -85,13 +85,16 @@ void launch_store_col(const double* src, double* Z, int64_t ldz, const GmresStat
 // V[:, st->j] = cur = src * st->inv_hn
 void launch_scale_to_col(const double* src, const GmresState* st, double* V, int64_t ldv, double* cur, int64_t n,
                          hipStream_t s);
-// Hessenberg column st->j (as launch_arnoldi_finish), then st->j += 1
+// Hessenberg column st->j (as launch_arnoldi_finish), then st->j += 1;
+// with host_out (device view of pinned coherent host memory, 8 doubles),
+// beta, hn, inv_hn, res of step j also go to host_out[4 (j % 2) ..]
 void launch_arnoldi_finish_dev(GmresState* st, const double* h1, const double* h2, const double* nrm2,
-                               hipStream_t s);
+                               double* host_out, hipStream_t s);
 void launch_arnoldi_finish(GmresState* st, int j, const double* h1, const double* h2, const double* nrm2,
                            hipStream_t s);
 void launch_gmres_trisolve(GmresState* st, int m, hipStream_t s);
-void launch_gmres_start(GmresState* st, const double* nrm2, hipStream_t s);
+// restart: g = (||r||, 0, ..), j = 0; beta, hn, inv_hn, res to host_out[0..4) when given
+void launch_gmres_start(GmresState* st, const double* nrm2, double* host_out, hipStream_t s);
 void launch_scale_copy(const double* src, const double* factor, double* dst, int64_t n, hipStream_t s);
 void launch_sub(const double* a, const double* b, double* out, int64_t n, hipStream_t s);
 

@@ -68,8 +68,8 @@ struct abddc_ctx {
   // ------------------------------------------------------------- GMRES
   abddc::DevBuf<double> d_V, d_Z, d_w, d_r, d_x, d_h1, d_h2, d_nrm, d_partial;
   abddc::DevBuf<abddc::GmresState> d_gst;
-  abddc::GmresState* h_gst = nullptr;               // pinned mirror of the scalars
-  double* h_step = nullptr;                         // pinned: scalars of two Arnoldi steps in flight
+  double* h_step = nullptr;    // pinned, device-coherent: scalars of two Arnoldi steps in flight and of the restart
+  double* dh_step = nullptr;   // the same memory as the device sees it
   hipEvent_t ev_step[2] = {nullptr, nullptr};
   int gm_restart = 0;
   abddc::DevBuf<double> d_vcur, d_zcur;             // current Arnoldi vector and its preconditioned image

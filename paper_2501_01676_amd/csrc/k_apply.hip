@@ -166,14 +166,27 @@ __device__ void arnoldi_column(GmresState* st, int j, const double* __restrict__
 }
 
 
+// beta, hn, inv_hn, res into pinned host memory (device-coherent), visible
+// to the host once the kernel has completed.
+__device__ inline void publish_scalars(const GmresState* st, double* host) {
+  host[0] = st->beta;
+  host[1] = st->hn;
+  host[2] = st->inv_hn;
+  host[3] = st->res;
+  __threadfence_system();
+}
+
+// host_out (optional): two slots of four scalars; step jj writes slot jj % 2.
 __global__ void arnoldi_finish_kernel(GmresState* st, int j, const double* __restrict__ h1,
-                                      const double* __restrict__ h2, const double* __restrict__ nrm2) {
+                                      const double* __restrict__ h2, const double* __restrict__ nrm2,
+                                      double* host_out) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   const bool dev_j = j < 0;
   const int jj = dev_j ? st->j : j;
   const int keep = st->j;
   arnoldi_column(st, jj, h1, h2, nrm2);
   if (!dev_j) st->j = keep;
+  if (host_out) publish_scalars(st, host_out + 4 * (jj & 1));
 }
 
 // y = H(0:m, 0:m)^{-1} g(0:m) (upper triangular)
@@ -186,7 +199,7 @@ __global__ void gmres_trisolve_kernel(GmresState* st, int m) {
   }
 }
 
-__global__ void gmres_start_kernel(GmresState* st, const double* __restrict__ nrm2) {
+__global__ void gmres_start_kernel(GmresState* st, const double* __restrict__ nrm2, double* host_out) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   const double b = sqrt(fmax(nrm2[0], 0.0));
   for (int i = 0; i <= GMRES_MAXR; ++i) st->g[i] = 0.0;
@@ -195,6 +208,7 @@ __global__ void gmres_start_kernel(GmresState* st, const double* __restrict__ nr
   st->inv_hn = b > 0.0 ? 1.0 / b : 0.0;
   st->res = b;
   st->j = 0;
+  if (host_out) publish_scalars(st, host_out);
 }
 
 __global__ void store_col_kernel(const double* __restrict__ src, double* __restrict__ Z, int64_t ldz,
@@ -375,8 +389,8 @@ void launch_scale_to_col(const double* src, const GmresState* st, double* V, int
 }
 
 void launch_arnoldi_finish_dev(GmresState* st, const double* h1, const double* h2, const double* nrm2,
-                               hipStream_t s) {
-  arnoldi_finish_kernel<<<1, 64, 0, s>>>(st, -1, h1, h2, nrm2);
+                               double* host_out, hipStream_t s) {
+  arnoldi_finish_kernel<<<1, 64, 0, s>>>(st, -1, h1, h2, nrm2, host_out);
   ABDDC_HIP(hipGetLastError());
 }
 
@@ -388,7 +402,7 @@ void launch_axpy_multi(const double* V, int64_t ldv, int nv, const double* coef,
 
 void launch_arnoldi_finish(GmresState* st, int j, const double* h1, const double* h2, const double* nrm2,
                            hipStream_t s) {
-  arnoldi_finish_kernel<<<1, 64, 0, s>>>(st, j, h1, h2, nrm2);
+  arnoldi_finish_kernel<<<1, 64, 0, s>>>(st, j, h1, h2, nrm2, nullptr);
   ABDDC_HIP(hipGetLastError());
 }
 
@@ -397,8 +411,8 @@ void launch_gmres_trisolve(GmresState* st, int m, hipStream_t s) {
   ABDDC_HIP(hipGetLastError());
 }
 
-void launch_gmres_start(GmresState* st, const double* nrm2, hipStream_t s) {
-  gmres_start_kernel<<<1, 64, 0, s>>>(st, nrm2);
+void launch_gmres_start(GmresState* st, const double* nrm2, double* host_out, hipStream_t s) {
+  gmres_start_kernel<<<1, 64, 0, s>>>(st, nrm2, host_out);
   ABDDC_HIP(hipGetLastError());
 }
 
