@@ -20,6 +20,7 @@
 
 namespace abddc {
 void run_setup(abddc_ctx* c);
+void plan_face_elimination(abddc_ctx* c, hipStream_t s);
 }
 
 using namespace abddc;
@@ -148,8 +149,7 @@ extern "C" int abddc_assemble(const abddc_problem* prob, const abddc_device* dev
     int nsub_in[3] = {prob->nsub[0], prob->nsub[1], prob->nsub[2]};
     const int* w_in[3] = {prob->width[0], prob->width[1], prob->width[2]};
     HostTrace ht;
-    T.build(nsub_in, w_in);
-    ht.mark("assemble: topology");
+    T.build_grid(nsub_in, w_in);   // the interface objects follow once the element kernel is queued
     const bool on_dev = prob->arrays_on_device != 0;
     if (!on_dev)
       for (int64_t e = 0; e < T.n_elem; ++e)
@@ -206,6 +206,8 @@ extern "C" int abddc_assemble(const abddc_problem* prob, const abddc_device* dev
     }
 
     ht.mark("assemble: coefficients, element kernel queued");
+    T.build_objects();
+    ht.mark("assemble: topology");
     // ---------------------------------------------------- local layout
     const int nsub = T.n_sub;
     c->nI.resize(nsub);
@@ -329,6 +331,10 @@ extern "C" int abddc_assemble(const abddc_problem* prob, const abddc_device* dev
     gemv_tune<double>(c->opS, "schur", c->device, c->dS.p, c->d_ghat.p, c->d_gam.p, c->d_wS.p, s);
     ht.mark("assemble: owners, Schur GEMV metadata");
     record(c.get(), 12);
+    // host work of the coarse-space setup that needs only the topology,
+    // done while the device finishes the assembly
+    plan_face_elimination(c.get(), s);
+    ht.mark("assemble: face elimination plan");
     int h = 0;
     ABDDC_HIP(hipMemcpyAsync(&h, c->d_flag.p, sizeof(int), hipMemcpyDeviceToHost, s));
     ABDDC_HIP(hipStreamSynchronize(s));

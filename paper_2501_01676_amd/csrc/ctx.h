@@ -13,6 +13,31 @@
 #include "mlp.h"
 #include "topology.h"
 
+namespace abddc {
+
+// Index plan of the staged face eliminations (topology only): built by
+// assemble while the device works, used by the coarse-space setup.
+struct FaceElimPlan {
+  struct Group {
+    int sub, nfaces, cpos, ng;   // subdomain, faces of one normal axis, their position and size in C
+    int64_t o2;                  // offset of the group's matrix
+    int k2;                      // order eliminated in step (2)
+    size_t m2;                   // pool offset of the step (2) map
+  };
+  bool ready = false;
+  std::vector<int32_t> pool;            // concatenated index maps
+  DevBuf<int32_t> d_pool;
+  std::vector<size_t> m1off;            // per subdomain: step (1) map
+  std::vector<int> nR, nC;              // per subdomain: eliminated / kept in step (1)
+  std::vector<Group> groups;
+  std::vector<int64_t> res3;            // per (face, side): step (3) matrix offset, -1 when none
+  std::vector<int> k3of, ng3, grp_of;   // per (face, side)
+  std::vector<size_t> m3off;
+  int64_t w2tot = 0, w3tot = 0;
+};
+
+}  // namespace abddc
+
 struct abddc_ctx {
   // ---------------------------------------------------------- problem
   int device = 0;
@@ -46,6 +71,7 @@ struct abddc_ctx {
   abddc::DevBuf<double> dTF, dTE;
   std::vector<int64_t> wfoff, weoff;       // eigenvalues (mu) of face / edge GEPs
   abddc::DevBuf<double> dWF, dWE;
+  abddc::FaceElimPlan fplan;
   int n_primal = 0, n_vertex = 0, pnum_face = 0, pnum_edge = 0, n_ties = 0;
 
   // ----------------------------------------------------- apply operators

@@ -117,6 +117,111 @@ void learned_edges(abddc_ctx* c, std::vector<int>& exact) {
 
 }  // namespace
 
+// Index plan of the staged face eliminations: topology and interface sizes
+// only, so assemble builds it while the device works.  The Schur complement
+// of B^(nu) onto F, eliminating Gamma_nu minus F, is taken in three steps
+// (Schur complements compose, so the work the faces of one subdomain share
+// is done once):
+//   (1) per subdomain: eliminate the edge and vertex dofs, leaving C on the
+//       face dofs of Gamma_nu, ordered by normal axis;
+//   (2) per (subdomain, axis): eliminate from C the faces normal to the
+//       other axes, leaving the block of the one or two faces normal to this
+//       axis;
+//   (3) per face of a two-face block: eliminate the opposite face.
+void plan_face_elimination(abddc_ctx* c, hipStream_t s) {
+  const Topology& T = c->topo;
+  const int nsub = T.n_sub, nf = (int)T.faces.size();
+  FaceElimPlan& P = c->fplan;
+  P = FaceElimPlan();
+  auto face_axis = [&](int k) {
+    const int a = T.objects[k].subs[0], b = T.objects[k].subs[1];
+    if (a % T.nsub[0] != b % T.nsub[0]) return 0;
+    if ((a / T.nsub[0]) % T.nsub[1] != (b / T.nsub[0]) % T.nsub[1]) return 1;
+    return 2;
+  };
+  struct FacePart { int f, side, off, n, axis; };
+  std::vector<std::vector<FacePart>> sfaces(nsub);
+  for (int f = 0; f < nf; ++f) {
+    const int k = T.faces[f];
+    for (int side = 0; side < 2; ++side) {
+      const int sub = T.objects[k].subs[side];
+      sfaces[sub].push_back({f, side, T.sub[sub].local_pos(k), T.objects[k].n, face_axis(k)});
+    }
+  }
+  auto add = [&](const std::vector<int32_t>& v) {
+    const size_t off = P.pool.size();
+    P.pool.insert(P.pool.end(), v.begin(), v.end());
+    return off;
+  };
+  P.m1off.assign(nsub, 0);
+  P.nR.assign(nsub, 0);
+  P.nC.assign(nsub, 0);
+  P.res3.assign(2 * nf, -1);
+  P.k3of.assign(2 * nf, 0);
+  P.ng3.assign(2 * nf, 0);
+  P.grp_of.assign(2 * nf, -1);
+  P.m3off.assign(2 * nf, 0);
+  for (int sub = 0; sub < nsub; ++sub) {
+    std::vector<FacePart>& fp = sfaces[sub];
+    if (fp.empty()) continue;
+    std::stable_sort(fp.begin(), fp.end(), [](const FacePart& a, const FacePart& b) {
+      return a.axis != b.axis ? a.axis < b.axis : a.off < b.off;
+    });
+    const int nB = c->nB[sub];
+    std::vector<char> isface(nB, 0);
+    for (const FacePart& q : fp)
+      for (int t = 0; t < q.n; ++t) isface[q.off + t] = 1;
+    std::vector<int32_t> mp;
+    for (int t = 0; t < nB; ++t)
+      if (!isface[t]) mp.push_back(t);
+    P.nR[sub] = (int)mp.size();
+    std::vector<int> cpos(fp.size());
+    for (size_t i = 0; i < fp.size(); ++i) {
+      cpos[i] = (int)mp.size() - P.nR[sub];
+      for (int t = 0; t < fp[i].n; ++t) mp.push_back(fp[i].off + t);
+    }
+    P.m1off[sub] = add(mp);
+    P.nC[sub] = nB - P.nR[sub];
+    for (size_t i = 0; i < fp.size();) {
+      size_t j = i + 1;
+      while (j < fp.size() && fp[j].axis == fp[i].axis) ++j;
+      FaceElimPlan::Group g{sub, (int)(j - i), cpos[i], 0, P.w2tot, 0, 0};
+      for (size_t q = i; q < j; ++q) g.ng += fp[q].n;
+      g.k2 = P.nC[sub] - g.ng;
+      std::vector<int32_t> m2;
+      for (int t = 0; t < P.nC[sub]; ++t)
+        if (t < g.cpos || t >= g.cpos + g.ng) m2.push_back(t);
+      for (int t = 0; t < g.ng; ++t) m2.push_back(g.cpos + t);
+      g.m2 = add(m2);
+      P.w2tot += (int64_t)P.nC[sub] * P.nC[sub];
+      const int gi = (int)P.groups.size();
+      P.groups.push_back(g);
+      int inner = 0;
+      for (size_t q = i; q < j; ++q) {
+        const int id = 2 * fp[q].f + fp[q].side;
+        P.grp_of[id] = gi;
+        if (g.nfaces > 1) {
+          // [the other face of the pair; this face] inside the pair block
+          std::vector<int32_t> m3;
+          for (int t = 0; t < g.ng; ++t)
+            if (t < inner || t >= inner + fp[q].n) m3.push_back(t);
+          for (int t = 0; t < fp[q].n; ++t) m3.push_back(inner + t);
+          P.m3off[id] = add(m3);
+          P.res3[id] = P.w3tot;
+          P.k3of[id] = g.ng - fp[q].n;
+          P.ng3[id] = g.ng;
+          P.w3tot += (int64_t)g.ng * g.ng;
+        }
+        inner += fp[q].n;
+      }
+      i = j;
+    }
+  }
+  P.d_pool.alloc(std::max<size_t>(P.pool.size(), 1));
+  if (!P.pool.empty()) staged_upload(P.d_pool.p, P.pool.data(), P.pool.size() * sizeof(int32_t), s);
+  P.ready = true;
+}
+
 void run_setup(abddc_ctx* c) {
   const Topology& T = c->topo;
   hipStream_t s = c->stream;
@@ -225,111 +330,25 @@ void run_setup(abddc_ctx* c) {
 
     ht.mark("Btilde_F^(nu): Schur complement of B^(");
     // Btilde_F^(nu): Schur complement of B^(nu) onto F, eliminating
-    // Gamma_nu minus F.  Schur complements compose (eliminating a set in two
-    // steps gives what eliminating it at once gives), so the work the faces
-    // of one subdomain share is done once:
-    //   (1) per subdomain: eliminate the edge and vertex dofs, leaving C on
-    //       the face dofs of Gamma_nu, ordered by normal axis;
-    //   (2) per (subdomain, axis): eliminate from C the faces normal to the
-    //       other axes, leaving the block of the one or two faces normal to
-    //       this axis;
-    //   (3) per face of a two-face block: eliminate the opposite face.
-    // Every step is a symmetric gather and a partial LU.  Each pivot block is
+    // Gamma_nu minus F, in the three steps of plan_face_elimination.  Every
+    // step is a symmetric gather and a partial LU.  Each pivot block is
     // a Schur complement of a principal submatrix of the one-step pivot block
     // B_{Gamma minus F}, so it is positive definite whenever that one is.
-    auto face_axis = [&](int k) {
-      const int a = T.objects[k].subs[0], b = T.objects[k].subs[1];
-      if (a % T.nsub[0] != b % T.nsub[0]) return 0;
-      if ((a / T.nsub[0]) % T.nsub[1] != (b / T.nsub[0]) % T.nsub[1]) return 1;
-      return 2;
-    };
-    struct FacePart { int f, side, off, n, axis; };
-    struct Group { int sub, nfaces, cpos, ng; int64_t o2; int k2; size_t m2; };
-    std::vector<std::vector<FacePart>> sfaces(nsub);
-    for (int f = 0; f < nf; ++f) {
-      const int k = T.faces[f];
-      for (int side = 0; side < 2; ++side) {
-        const int sub = T.objects[k].subs[side];
-        sfaces[sub].push_back({f, side, T.sub[sub].local_pos(k), T.objects[k].n, face_axis(k)});
-      }
-    }
-    IntPool pool;
-    std::vector<size_t> m1off(nsub);
-    std::vector<int> nR(nsub, 0), nC(nsub, 0);
-    std::vector<Group> groups;
+    if (!c->fplan.ready) plan_face_elimination(c, s);
+    const FaceElimPlan& P = c->fplan;
     std::vector<const double*> res(2 * nf);
     std::vector<int> resld(2 * nf);
-    std::vector<int64_t> res3(2 * nf, -1);     // Q3 offset of a face solved in step (3)
-    std::vector<int> k3of(2 * nf, 0), ng3(2 * nf, 0), grp_of(2 * nf, -1);
-    std::vector<size_t> m3off(2 * nf);
-    int64_t w2tot = 0, w3tot = 0;
-    for (int sub = 0; sub < nsub; ++sub) {
-      std::vector<FacePart>& fp = sfaces[sub];
-      if (fp.empty()) continue;
-      std::stable_sort(fp.begin(), fp.end(), [](const FacePart& a, const FacePart& b) {
-        return a.axis != b.axis ? a.axis < b.axis : a.off < b.off;
-      });
-      const int nB = c->nB[sub];
-      std::vector<char> isface(nB, 0);
-      for (const FacePart& q : fp)
-        for (int t = 0; t < q.n; ++t) isface[q.off + t] = 1;
-      std::vector<int32_t> mp;
-      for (int t = 0; t < nB; ++t)
-        if (!isface[t]) mp.push_back(t);
-      nR[sub] = (int)mp.size();
-      std::vector<int> cpos(fp.size());
-      for (size_t i = 0; i < fp.size(); ++i) {
-        cpos[i] = (int)mp.size() - nR[sub];
-        for (int t = 0; t < fp[i].n; ++t) mp.push_back(fp[i].off + t);
-      }
-      m1off[sub] = pool.add(mp);
-      nC[sub] = nB - nR[sub];
-      for (size_t i = 0; i < fp.size();) {
-        size_t j = i + 1;
-        while (j < fp.size() && fp[j].axis == fp[i].axis) ++j;
-        Group g{sub, (int)(j - i), cpos[i], 0, w2tot, 0, 0};
-        for (size_t q = i; q < j; ++q) g.ng += fp[q].n;
-        g.k2 = nC[sub] - g.ng;
-        std::vector<int32_t> m2;
-        for (int t = 0; t < nC[sub]; ++t)
-          if (t < g.cpos || t >= g.cpos + g.ng) m2.push_back(t);
-        for (int t = 0; t < g.ng; ++t) m2.push_back(g.cpos + t);
-        g.m2 = pool.add(m2);
-        w2tot += (int64_t)nC[sub] * nC[sub];
-        const int gi = (int)groups.size();
-        groups.push_back(g);
-        int inner = 0;
-        for (size_t q = i; q < j; ++q) {
-          const int id = 2 * fp[q].f + fp[q].side;
-          grp_of[id] = gi;
-          if (g.nfaces > 1) {
-            // [the other face of the pair; this face] inside the pair block
-            std::vector<int32_t> m3;
-            for (int t = 0; t < g.ng; ++t)
-              if (t < inner || t >= inner + fp[q].n) m3.push_back(t);
-            for (int t = 0; t < fp[q].n; ++t) m3.push_back(inner + t);
-            m3off[id] = pool.add(m3);
-            res3[id] = w3tot;
-            k3of[id] = g.ng - fp[q].n;
-            ng3[id] = g.ng;
-            w3tot += (int64_t)g.ng * g.ng;
-          }
-          inner += fp[q].n;
-        }
-        i = j;
-      }
-    }
-    pool.upload(s);
-    DevBuf<double> Q1(c->dB.n), Q2(std::max<int64_t>(w2tot, 1)), Q3(std::max<int64_t>(w3tot, 1));
+    auto pptr = [&](size_t off) { return P.d_pool.p + off; };
+    DevBuf<double> Q1(c->dB.n), Q2(std::max<int64_t>(P.w2tot, 1)), Q3(std::max<int64_t>(P.w3tot, 1));
     {
       std::vector<GatherDesc> gd;
       std::vector<PluDesc<double>> pd;
       for (int sub = 0; sub < nsub; ++sub) {
-        if (sfaces[sub].empty()) continue;
+        if (P.nC[sub] == 0) continue;   // no face dofs
         const int nB = c->nB[sub];
-        gd.push_back({c->dB.p + c->soff[sub], Q1.p + c->soff[sub], pool.ptr(m1off[sub]), pool.ptr(m1off[sub]), nB, nB,
+        gd.push_back({c->dB.p + c->soff[sub], Q1.p + c->soff[sub], pptr(P.m1off[sub]), pptr(P.m1off[sub]), nB, nB,
                       nB, nB, 1.0});
-        pd.push_back({Q1.p + c->soff[sub], nB, nB, nB, nR[sub]});
+        pd.push_back({Q1.p + c->soff[sub], nB, nB, nB, P.nR[sub]});
       }
       gather_batched(gd, s);
       partial_lu<double>(pd, c->d_flag.p, s);
@@ -337,10 +356,10 @@ void run_setup(abddc_ctx* c) {
     {
       std::vector<GatherDesc> gd;
       std::vector<PluDesc<double>> pd;
-      for (const Group& g : groups) {
-        const int nB = c->nB[g.sub], n2 = nC[g.sub];
-        const double* Cb = Q1.p + c->soff[g.sub] + (int64_t)nR[g.sub] * nB + nR[g.sub];
-        gd.push_back({Cb, Q2.p + g.o2, pool.ptr(g.m2), pool.ptr(g.m2), n2, n2, nB, n2, 1.0});
+      for (const FaceElimPlan::Group& g : P.groups) {
+        const int nB = c->nB[g.sub], n2 = P.nC[g.sub];
+        const double* Cb = Q1.p + c->soff[g.sub] + (int64_t)P.nR[g.sub] * nB + P.nR[g.sub];
+        gd.push_back({Cb, Q2.p + g.o2, pptr(g.m2), pptr(g.m2), n2, n2, nB, n2, 1.0});
         pd.push_back({Q2.p + g.o2, n2, n2, n2, g.k2});
       }
       gather_batched(gd, s);
@@ -350,18 +369,18 @@ void run_setup(abddc_ctx* c) {
       std::vector<GatherDesc> gd;
       std::vector<PluDesc<double>> pd;
       for (int id = 0; id < 2 * nf; ++id) {
-        const Group& g = groups[grp_of[id]];
-        const int n2 = nC[g.sub];
+        const FaceElimPlan::Group& g = P.groups[P.grp_of[id]];
+        const int n2 = P.nC[g.sub];
         const double* Pb = Q2.p + g.o2 + (int64_t)g.k2 * n2 + g.k2;   // block of the group's faces
-        if (res3[id] < 0) {
+        if (P.res3[id] < 0) {
           res[id] = Pb;
           resld[id] = n2;
           continue;
         }
-        const int ng = ng3[id], k3 = k3of[id];
-        gd.push_back({Pb, Q3.p + res3[id], pool.ptr(m3off[id]), pool.ptr(m3off[id]), ng, ng, n2, ng, 1.0});
-        pd.push_back({Q3.p + res3[id], ng, ng, ng, k3});
-        res[id] = Q3.p + res3[id] + (int64_t)k3 * ng + k3;
+        const int ng = P.ng3[id], k3 = P.k3of[id];
+        gd.push_back({Pb, Q3.p + P.res3[id], pptr(P.m3off[id]), pptr(P.m3off[id]), ng, ng, n2, ng, 1.0});
+        pd.push_back({Q3.p + P.res3[id], ng, ng, ng, k3});
+        res[id] = Q3.p + P.res3[id] + (int64_t)k3 * ng + k3;
         resld[id] = ng;
       }
       gather_batched(gd, s);

@@ -47,6 +47,10 @@ struct Topology {
   std::vector<SubInfo> sub;
 
   void build(const int nsub_in[3], const int* const width_in[3]);
+  // the two halves of build: the grid (cuts, sizes), then the interface
+  // objects and subdomain lists
+  void build_grid(const int nsub_in[3], const int* const width_in[3]);
+  void build_objects();
   int64_t node_id(int64_t ix, int64_t iy, int64_t iz) const { return ix + nn[0] * (iy + (int64_t)nn[1] * iz); }
   int sub_id(int sx, int sy, int sz) const { return sx + nsub[0] * (sy + nsub[1] * sz); }
 };

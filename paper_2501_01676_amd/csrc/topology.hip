@@ -13,7 +13,7 @@ int SubInfo::local_pos(int obj) const {
   return obj_off[it - objs.begin()];
 }
 
-void Topology::build(const int nsub_in[3], const int* const width_in[3]) {
+void Topology::build_grid(const int nsub_in[3], const int* const width_in[3]) {
   for (int a = 0; a < 3; ++a) {
     nsub[a] = nsub_in[a];
     ABDDC_REQUIRE(nsub[a] >= 1, ABDDC_EINVAL, "nsub must be >= 1");
@@ -29,7 +29,14 @@ void Topology::build(const int nsub_in[3], const int* const width_in[3]) {
   n_sub = nsub[0] * nsub[1] * nsub[2];
   n_nodes = (int64_t)nn[0] * nn[1] * nn[2];
   n_elem = (int64_t)ne[0] * ne[1] * ne[2];
+}
 
+void Topology::build(const int nsub_in[3], const int* const width_in[3]) {
+  build_grid(nsub_in, width_in);
+  build_objects();
+}
+
+void Topology::build_objects() {
   // per-axis: is grid index on an internal cut, and which subdomains hold it
   std::vector<char> oncut[3];
   std::vector<int> s_lo[3], s_hi[3];
