@@ -248,30 +248,33 @@ extern "C" int abddc_assemble(const abddc_problem* prob, const abddc_device* dev
       st += (int64_t)si.nB * si.nB;
       gt += si.nB;
       it += si.nI;
-      // local node list [interior; Gamma_i] and the box-local map
-      const int bx = si.ebox[0][1] - si.ebox[0][0] + 1, by = si.ebox[1][1] - si.ebox[1][0] + 1,
-                bz = si.ebox[2][1] - si.ebox[2][0] + 1;
-      std::vector<int32_t> bm((size_t)bx * by * bz, -1);
-      auto boxpos = [&](int64_t nid) {
-        const int ix = (int)(nid % T.nn[0]), iy = (int)((nid / T.nn[0]) % T.nn[1]), iz = (int)(nid / ((int64_t)T.nn[0] * T.nn[1]));
-        return (ix - si.ebox[0][0]) + (int64_t)bx * ((iy - si.ebox[1][0]) + (int64_t)by * (iz - si.ebox[2][0]));
-      };
+      // local node list [interior; Gamma_i] and the box-local map, walking
+      // the grid index boxes (node-id order) of the interior and of every
+      // interface object
+      const int e0[3] = {si.ebox[0][0], si.ebox[1][0], si.ebox[2][0]};
+      const int bx = si.ebox[0][1] - e0[0] + 1, by = si.ebox[1][1] - e0[1] + 1, bz = si.ebox[2][1] - e0[2] + 1;
+      const size_t b0 = lmap.size();
+      lmap.resize(b0 + (size_t)bx * by * bz, -1);
       int loc = 0;
-      for (int64_t nid : si.interior) {
-        lnode.push_back((int32_t)nid);
-        rowsub.push_back(sub);
-        bm[boxpos(nid)] = loc++;
-        int_dof.push_back((int32_t)T.dof_of_node[nid]);
-      }
-      for (int k : si.objs)
-        for (int64_t nid : T.objects[k].nodes) {
-          lnode.push_back((int32_t)nid);
-          rowsub.push_back(sub);
-          bm[boxpos(nid)] = loc++;
-        }
+      auto walk = [&](const int* lo, const int* hi, bool interior) {
+        for (int iz = lo[2]; iz <= hi[2]; ++iz)
+          for (int iy = lo[1]; iy <= hi[1]; ++iy) {
+            const int64_t row = T.node_id(0, iy, iz);
+            const size_t brow = b0 + (size_t)bx * ((iy - e0[1]) + (size_t)by * (iz - e0[2])) - e0[0];
+            for (int ix = lo[0]; ix <= hi[0]; ++ix) {
+              lnode.push_back((int32_t)(row + ix));
+              lmap[brow + ix] = loc++;
+              if (interior) int_dof.push_back((int32_t)T.dof_of_node[row + ix]);
+            }
+          }
+      };
+      const int ilo[3] = {e0[0] + 1, e0[1] + 1, e0[2] + 1};
+      const int ihi[3] = {si.ebox[0][1] - 1, si.ebox[1][1] - 1, si.ebox[2][1] - 1};
+      walk(ilo, ihi, true);
+      for (int k : si.objs) walk(T.objects[k].lo, T.objects[k].hi, false);
+      rowsub.insert(rowsub.end(), (size_t)loc, sub);
       for (int64_t g : si.gamma) gam.push_back((int32_t)g);
-      lmap.insert(lmap.end(), bm.begin(), bm.end());
-      lmt += (int64_t)bm.size();
+      lmt += (int64_t)bx * by * bz;
       rows += c->nloc[sub];
     }
     ABDDC_REQUIRE(T.n_nodes < (int64_t)1 << 31 && lmt < (int64_t)1 << 31, ABDDC_EINVAL, "mesh too large");

@@ -20,6 +20,7 @@ struct Object {
   std::vector<int64_t> nodes;   // sorted grid node ids
   int64_t gstart;               // first interface index
   int n;                        // number of dofs
+  int lo[3], hi[3];             // the nodes: the grid index box [lo, hi] (inclusive) per axis
 };
 
 struct SubInfo {

@@ -37,64 +37,61 @@ void Topology::build(const int nsub_in[3], const int* const width_in[3]) {
 }
 
 void Topology::build_objects() {
-  // per-axis: is grid index on an internal cut, and which subdomains hold it
-  std::vector<char> oncut[3];
-  std::vector<int> s_lo[3], s_hi[3];
+  // Per axis, a grid index has the key 2s inside subdomain s and 2c - 1 on
+  // the cut c between subdomains c - 1 and c; the indices of one key form
+  // the range [klo, khi] (Dirichlet boundary indices belong to no key).  An
+  // interface object is a key triple with at least one odd key, its nodes
+  // the tensor product of the three ranges, its subdomains those holding
+  // every one of them; one odd key makes a face, two an edge, three a vertex.
+  std::vector<int> klo[3], khi[3];
   for (int a = 0; a < 3; ++a) {
-    oncut[a].assign(nn[a], 0);
-    s_lo[a].assign(nn[a], 0);
-    s_hi[a].assign(nn[a], 0);
-    for (int c = 1; c < nsub[a]; ++c) oncut[a][cuts[a][c]] = 1;
-    for (int i = 0; i < nn[a]; ++i) {
-      int lo = -1, hi = -1;
-      for (int s = 0; s < nsub[a]; ++s)
-        if (cuts[a][s] <= i && i <= cuts[a][s + 1]) {
-          if (lo < 0) lo = s;
-          hi = s;
-        }
-      s_lo[a][i] = lo;
-      s_hi[a][i] = hi;
+    const int nk = 2 * nsub[a] - 1;
+    klo[a].assign(nk, 0);
+    khi[a].assign(nk, 0);
+    for (int s = 0; s < nsub[a]; ++s) {
+      klo[a][2 * s] = cuts[a][s] + 1;
+      khi[a][2 * s] = cuts[a][s + 1] - 1;
     }
+    for (int c = 1; c < nsub[a]; ++c) klo[a][2 * c - 1] = khi[a][2 * c - 1] = cuts[a][c];
   }
-
+  // free nodes: the grid minus its boundary, numbered by node id
   dof_of_node.assign(n_nodes, -1);
+  for (int iz = 1; iz < nn[2] - 1; ++iz)
+    for (int iy = 1; iy < nn[1] - 1; ++iy) {
+      const int64_t base = node_id(0, iy, iz);
+      const int64_t d0 = (int64_t)(nn[0] - 2) * ((iy - 1) + (int64_t)(nn[1] - 2) * (iz - 1)) - 1;
+      for (int ix = 1; ix < nn[0] - 1; ++ix) dof_of_node[base + ix] = d0 + ix;
+    }
+  n_dof = (int64_t)(nn[0] - 2) * (nn[1] - 2) * (nn[2] - 2);
   iface_of_node.assign(n_nodes, -1);
-  // The sharing set of a node is fixed by (s_lo + s_hi) per axis: 2s inside
-  // subdomain s, 2s + 1 on the cut between s and s + 1; those three numbers
-  // index a dense table of objects.
-  const int kx = 2 * nsub[0] - 1, ky = 2 * nsub[1] - 1, kz = 2 * nsub[2] - 1;
-  std::vector<int> obj_of_key((size_t)kx * ky * kz, -1);
   objects.clear();
-  int64_t ndof = 0;
-  for (int iz = 0; iz < nn[2]; ++iz)
-    for (int iy = 0; iy < nn[1]; ++iy)
-      for (int ix = 0; ix < nn[0]; ++ix) {
-        const int64_t nid = node_id(ix, iy, iz);
-        const bool fr = ix > 0 && ix < nn[0] - 1 && iy > 0 && iy < nn[1] - 1 && iz > 0 && iz < nn[2] - 1;
-        if (!fr) continue;
-        dof_of_node[nid] = ndof++;
-        const int cnt = oncut[0][ix] + oncut[1][iy] + oncut[2][iz];
-        if (cnt == 0) continue;
-        const size_t key = (size_t)(s_lo[0][ix] + s_hi[0][ix]) +
-                           (size_t)kx * ((s_lo[1][iy] + s_hi[1][iy]) + (size_t)ky * (s_lo[2][iz] + s_hi[2][iz]));
-        int k = obj_of_key[key];
-        if (k < 0) {
-          Object o;
-          for (int sz = s_lo[2][iz]; sz <= s_hi[2][iz]; ++sz)
-            for (int sy = s_lo[1][iy]; sy <= s_hi[1][iy]; ++sy)
-              for (int sx = s_lo[0][ix]; sx <= s_hi[0][ix]; ++sx) o.subs.push_back(sub_id(sx, sy, sz));
-          std::sort(o.subs.begin(), o.subs.end());
-          ABDDC_REQUIRE(o.subs.size() == 2 || o.subs.size() == 4 || o.subs.size() == 8, ABDDC_EINVAL,
-                        "unexpected interface class");
-          o.kind = o.subs.size() == 2 ? KIND_FACE : (o.subs.size() == 4 ? KIND_EDGE : KIND_VERTEX);
-          k = (int)objects.size();
-          obj_of_key[key] = k;
-          objects.push_back(std::move(o));
+  const int nk[3] = {2 * nsub[0] - 1, 2 * nsub[1] - 1, 2 * nsub[2] - 1};
+  for (int kz = 0; kz < nk[2]; ++kz)
+    for (int ky = 0; ky < nk[1]; ++ky)
+      for (int kx = 0; kx < nk[0]; ++kx) {
+        const int odd = (kx & 1) + (ky & 1) + (kz & 1);
+        if (odd == 0) continue;
+        Object o;
+        o.kind = odd == 1 ? KIND_FACE : (odd == 2 ? KIND_EDGE : KIND_VERTEX);
+        const int key[3] = {kx, ky, kz};
+        int slo[3], shi[3];
+        for (int a = 0; a < 3; ++a) {
+          o.lo[a] = klo[a][key[a]];
+          o.hi[a] = khi[a][key[a]];
+          slo[a] = key[a] / 2;
+          shi[a] = (key[a] + 1) / 2;
         }
-        objects[k].nodes.push_back(nid);   // visited in increasing node id
+        for (int sz = slo[2]; sz <= shi[2]; ++sz)
+          for (int sy = slo[1]; sy <= shi[1]; ++sy)
+            for (int sx = slo[0]; sx <= shi[0]; ++sx) o.subs.push_back(sub_id(sx, sy, sz));
+        std::sort(o.subs.begin(), o.subs.end());
+        o.nodes.reserve((size_t)(o.hi[0] - o.lo[0] + 1) * (o.hi[1] - o.lo[1] + 1) * (o.hi[2] - o.lo[2] + 1));
+        for (int iz = o.lo[2]; iz <= o.hi[2]; ++iz)
+          for (int iy = o.lo[1]; iy <= o.hi[1]; ++iy)
+            for (int ix = o.lo[0]; ix <= o.hi[0]; ++ix) o.nodes.push_back(node_id(ix, iy, iz));
+        o.n = (int)o.nodes.size();
+        objects.push_back(std::move(o));
       }
-  n_dof = ndof;
-  for (Object& o : objects) o.n = (int)o.nodes.size();
   std::sort(objects.begin(), objects.end(), [](const Object& a, const Object& b) {
     if (a.kind != b.kind) return a.kind < b.kind;
     return a.nodes[0] < b.nodes[0];
