@@ -25,6 +25,7 @@ int fail(int code, const std::string& msg) {
 
 namespace abddc {
 thread_local hipStream_t g_stream = nullptr;
+thread_local bool g_stream_idle = false;
 
 namespace {
 // A cached block remembers the stream whose work may still use it and an
@@ -121,7 +122,9 @@ void cache_free(void* p, size_t bytes) {
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return;
   Block blk{p, g_stream, nullptr};
-  if (hipEventCreateWithFlags(&blk.ev, hipEventDisableTiming) == hipSuccess) {
+  if (g_stream_idle) {
+    // the caller has synchronised the stream: nothing can still use the block
+  } else if (hipEventCreateWithFlags(&blk.ev, hipEventDisableTiming) == hipSuccess) {
     if (hipEventRecord(blk.ev, g_stream) != hipSuccess) {
       (void)hipEventDestroy(blk.ev);
       blk.ev = nullptr;

@@ -8,7 +8,9 @@
 #include <chrono>
 #include <cmath>
 #include <cstddef>
+#include <map>
 #include <memory>
+#include <mutex>
 
 #include "apply.h"
 #include "arena.h"
@@ -61,6 +63,64 @@ void apply_schur_dev(abddc_ctx* c, const double* x, double* y, hipStream_t s) {
   launch_gather_sum(c->d_own_ptr.p, c->d_own_idx.p, c->d_wS.p, y, c->topo.n_gamma, s);
 }
 
+// Runtime objects of a context (timing events, the pinned scalar slots and
+// their events, the capture stream), kept per device after a context is
+// destroyed and handed to the next one: creating them costs more than a
+// small solve.
+struct CtxResources {
+  hipEvent_t ev[20];
+  double* h_step;
+  double* dh_step;
+  hipEvent_t ev_step[2];
+  hipStream_t cap_stream;
+};
+std::mutex g_res_mu;
+std::map<int, std::vector<CtxResources>> g_res_pool;
+
+void acquire_resources(abddc_ctx* c) {
+  CtxResources r{};
+  bool have = false;
+  {
+    std::lock_guard<std::mutex> g(g_res_mu);
+    std::vector<CtxResources>& v = g_res_pool[c->device];
+    if (!v.empty()) {
+      r = v.back();
+      v.pop_back();
+      have = true;
+    }
+  }
+  if (!have) {
+    for (int i = 0; i < 20; ++i) ABDDC_HIP(hipEventCreate(&r.ev[i]));
+    // scalars the kernels publish straight to the host: two step slots and
+    // the restart slot (pinned, device-coherent)
+    ABDDC_HIP(hipHostMalloc(&r.h_step, 12 * sizeof(double), hipHostMallocMapped | hipHostMallocCoherent));
+    ABDDC_HIP(hipHostGetDevicePointer(reinterpret_cast<void**>(&r.dh_step), r.h_step, 0));
+    for (int i = 0; i < 2; ++i) ABDDC_HIP(hipEventCreateWithFlags(&r.ev_step[i], hipEventDisableTiming));
+    ABDDC_HIP(hipStreamCreateWithFlags(&r.cap_stream, hipStreamNonBlocking));
+  }
+  for (int i = 0; i < 20; ++i) c->ev[i] = r.ev[i];
+  c->h_step = r.h_step;
+  c->dh_step = r.dh_step;
+  c->ev_step[0] = r.ev_step[0];
+  c->ev_step[1] = r.ev_step[1];
+  c->cap_stream = r.cap_stream;
+  c->events = true;
+}
+
+void release_resources(abddc_ctx* c) {
+  if (!c->events) return;
+  CtxResources r{};
+  for (int i = 0; i < 20; ++i) r.ev[i] = c->ev[i];
+  r.h_step = c->h_step;
+  r.dh_step = c->dh_step;
+  r.ev_step[0] = c->ev_step[0];
+  r.ev_step[1] = c->ev_step[1];
+  r.cap_stream = c->cap_stream;
+  std::lock_guard<std::mutex> g(g_res_mu);
+  g_res_pool[c->device].push_back(r);
+  c->events = false;
+}
+
 // One Arnoldi step of right-preconditioned FGMRES on stream s, every kernel
 // taking the step index from the device state: z_j = M^{-1} v_j, Z[:, j] =
 // z_j, w = Shat z_j, two classical Gram-Schmidt passes over V[:, 0..j], the
@@ -93,7 +153,6 @@ bool ensure_step_graph(abddc_ctx* c, int restart) {
     c->step_exec = nullptr;
     c->step_graph = nullptr;
   }
-  if (!c->cap_stream) ABDDC_HIP(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
   KStatsScope none(nullptr);   // no timing events inside the graph
   if (hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
     (void)hipGetLastError();
@@ -162,8 +221,13 @@ extern "C" int abddc_assemble(const abddc_problem* prob, const abddc_device* dev
     c->c = prob->c;
     c->f_const = prob->f_const;
     c->tau = prob->tau;
-    for (int i = 0; i < 20; ++i) ABDDC_HIP(hipEventCreate(&c->ev[i]));
-    c->events = true;
+    acquire_resources(c.get());
+    struct ResGuard {   // back to the pool if assembly fails
+      abddc_ctx* c;
+      ~ResGuard() {
+        if (c) release_resources(c);
+      }
+    } res_guard{c.get()};
     c->d_flag.alloc(1);
     c->d_flag.zero(s);
     record(c.get(), 10);
@@ -348,6 +412,7 @@ extern "C" int abddc_assemble(const abddc_problem* prob, const abddc_device* dev
     c->phase[0] = ev_ms(c.get(), 10, 11);
     c->phase[1] = ev_ms(c.get(), 11, 12);
     c->state = 1;
+    res_guard.c = nullptr;
     *out = c.release();
     return ABDDC_OK;
   });
@@ -465,9 +530,6 @@ extern "C" int abddc_gmres_solve(abddc_ctx* c, int32_t restart, double rtol, int
       c->d_gst.alloc(1);
       // scalars the kernels publish straight to the host: two step slots and
       // the restart slot (pinned, device-coherent)
-      ABDDC_HIP(hipHostMalloc(&c->h_step, 12 * sizeof(double), hipHostMallocMapped | hipHostMallocCoherent));
-      ABDDC_HIP(hipHostGetDevicePointer(reinterpret_cast<void**>(&c->dh_step), c->h_step, 0));
-      for (int i = 0; i < 2; ++i) ABDDC_HIP(hipEventCreateWithFlags(&c->ev_step[i], hipEventDisableTiming));
     }
     const auto t0 = std::chrono::steady_clock::now();
     record(c, 13);
@@ -668,13 +730,10 @@ extern "C" void abddc_destroy(abddc_ctx* c) {
   (void)hipSetDevice(c->device);
   StreamScope ss(c->stream);
   (void)hipStreamSynchronize(c->stream);
-  if (c->h_step) (void)hipHostFree(c->h_step);
-  for (int i = 0; i < 2; ++i)
-    if (c->ev_step[i]) (void)hipEventDestroy(c->ev_step[i]);
   if (c->step_exec) (void)hipGraphExecDestroy(c->step_exec);
   if (c->step_graph) (void)hipGraphDestroy(c->step_graph);
-  if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
-  for (int i = 0; i < 20; ++i)
-    if (c->ev[i]) (void)hipEventDestroy(c->ev[i]);
+  release_resources(c);
+  g_stream_idle = true;   // the stream has drained: the buffers go back to the cache without events
   delete c;
+  g_stream_idle = false;
 }
