@@ -40,7 +40,9 @@ void record(abddc_ctx* c, int i) {
 }
 
 // z = M^{-1} r (device vectors of length n_gamma)
-void apply_bddc_dev(abddc_ctx* c, const double* r, double* z, hipStream_t s) {
+// z = M^{-1} r; with Z and st also Z[:, st->j] = z
+void apply_bddc_dev(abddc_ctx* c, const double* r, double* z, hipStream_t s, double* Z = nullptr, int64_t ldz = 0,
+                    const GmresState* st = nullptr) {
   const int np = c->n_primal;
   const bool mixed = c->dM32.p != nullptr;
   if (mixed)
@@ -55,7 +57,10 @@ void apply_bddc_dev(abddc_ctx* c, const double* r, double* z, hipStream_t s) {
     else
       gemv_run<double>(c->opU, c->dU.p, c->d_xpi.p, c->d_pid.p, c->d_out.p, true, s);
   }
-  launch_gather_sum(c->d_aown_ptr.p, c->d_aown_idx.p, c->d_out.p, z, c->topo.n_gamma, s);
+  if (Z)
+    launch_gather_sum_col(c->d_aown_ptr.p, c->d_aown_idx.p, c->d_out.p, z, Z, ldz, st, c->topo.n_gamma, s);
+  else
+    launch_gather_sum(c->d_aown_ptr.p, c->d_aown_idx.p, c->d_out.p, z, c->topo.n_gamma, s);
 }
 
 void apply_schur_dev(abddc_ctx* c, const double* x, double* y, hipStream_t s) {
@@ -129,8 +134,7 @@ void arnoldi_step(abddc_ctx* c, int restart, hipStream_t s) {
   const int64_t n = c->topo.n_gamma;
   const size_t nn = (size_t)std::max<int64_t>(n, 1);
   GmresState* st = c->d_gst.p;
-  apply_bddc_dev(c, c->d_vcur.p, c->d_zcur.p, s);
-  launch_store_col(c->d_zcur.p, c->d_Z.p, nn, st, n, s);
+  apply_bddc_dev(c, c->d_vcur.p, c->d_zcur.p, s, c->d_Z.p, nn, st);   // also Z[:, j] = z_j
   apply_schur_dev(c, c->d_zcur.p, c->d_w.p, s);
   launch_dots_dev(c->d_V.p, nn, st, restart, c->d_w.p, n, c->d_partial.p, c->d_h1.p, s);
   launch_axpy_multi_dev(c->d_V.p, nn, st, c->d_h1.p, -1.0, c->d_w.p, n, s);

@@ -69,6 +69,9 @@ void gemv_tune(GemvOp& op, const char* name, int device, const TM* M, const doub
                double* y, hipStream_t s);
 void launch_gather_sum(const int32_t* ptr, const int32_t* idx, const double* src, double* dst, int64_t n,
                        hipStream_t s);
+// the same, and a copy into column st->j of Z (leading dimension ldz)
+void launch_gather_sum_col(const int32_t* ptr, const int32_t* idx, const double* src, double* dst, double* Z,
+                           int64_t ldz, const GmresState* st, int64_t n, hipStream_t s);
 void launch_dots(const double* V, int64_t ldv, int nv, const double* w, int64_t n, double* partial, double* out,
                  hipStream_t s);
 void launch_axpy_multi(const double* V, int64_t ldv, int nv, const double* coef, double sign, double* w, int64_t n,
@@ -80,8 +83,6 @@ void launch_dots_dev(const double* V, int64_t ldv, const GmresState* st, int max
                      double* partial, double* out, hipStream_t s);
 void launch_axpy_multi_dev(const double* V, int64_t ldv, const GmresState* st, const double* coef, double sign,
                            double* w, int64_t n, hipStream_t s);
-// Z[:, st->j] = src
-void launch_store_col(const double* src, double* Z, int64_t ldz, const GmresState* st, int64_t n, hipStream_t s);
 // V[:, st->j] = cur = src * st->inv_hn
 void launch_scale_to_col(const double* src, const GmresState* st, double* V, int64_t ldv, double* cur, int64_t n,
                          hipStream_t s);

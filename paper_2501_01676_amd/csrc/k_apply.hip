@@ -82,6 +82,18 @@ __global__ void gather_sum_kernel(const int32_t* __restrict__ ptr, const int32_t
   dst[i] = v;
 }
 
+// dst[i] = sum of src over the positions of i; the same into Z[:, st->j]
+__global__ void gather_sum_col_kernel(const int32_t* __restrict__ ptr, const int32_t* __restrict__ idx,
+                                      const double* __restrict__ src, double* __restrict__ dst, double* __restrict__ Z,
+                                      int64_t ldz, const GmresState* __restrict__ st, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double v = 0.0;
+  for (int j = ptr[i]; j < ptr[i + 1]; ++j) v += src[idx[j]];
+  dst[i] = v;
+  Z[(int64_t)st->j * ldz + i] = v;
+}
+
 // partial[b * DOT_STRIDE + j] = sum over block b's chunk of V[j][i] w[i]
 __global__ void __launch_bounds__(256) dots_partial_kernel(const double* __restrict__ V, int64_t ldv, int nv,
                                                            const GmresState* __restrict__ st,
@@ -209,12 +221,6 @@ __global__ void gmres_start_kernel(GmresState* st, const double* __restrict__ nr
   st->res = b;
   st->j = 0;
   if (host_out) publish_scalars(st, host_out);
-}
-
-__global__ void store_col_kernel(const double* __restrict__ src, double* __restrict__ Z, int64_t ldz,
-                                 const GmresState* __restrict__ st, int64_t n) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) Z[(int64_t)st->j * ldz + i] = src[i];
 }
 
 __global__ void scale_to_col_kernel(const double* __restrict__ src, const GmresState* __restrict__ st,
@@ -357,6 +363,13 @@ void launch_gather_sum(const int32_t* ptr, const int32_t* idx, const double* src
   ABDDC_HIP(hipGetLastError());
 }
 
+void launch_gather_sum_col(const int32_t* ptr, const int32_t* idx, const double* src, double* dst, double* Z,
+                           int64_t ldz, const GmresState* st, int64_t n, hipStream_t s) {
+  if (n == 0) return;
+  gather_sum_col_kernel<<<nblocks(n), 256, 0, s>>>(ptr, idx, src, dst, Z, ldz, st, n);
+  ABDDC_HIP(hipGetLastError());
+}
+
 void launch_dots(const double* V, int64_t ldv, int nv, const double* w, int64_t n, double* partial, double* out,
                  hipStream_t s) {
   dots_partial_kernel<<<DOT_BLOCKS, 256, 0, s>>>(V, ldv, nv, nullptr, w, n, partial);
@@ -374,11 +387,6 @@ void launch_dots_dev(const double* V, int64_t ldv, const GmresState* st, int max
 void launch_axpy_multi_dev(const double* V, int64_t ldv, const GmresState* st, const double* coef, double sign,
                            double* w, int64_t n, hipStream_t s) {
   axpy_multi_kernel<<<nblocks(n), 256, 0, s>>>(V, ldv, 0, st, coef, sign, w, n);
-  ABDDC_HIP(hipGetLastError());
-}
-
-void launch_store_col(const double* src, double* Z, int64_t ldz, const GmresState* st, int64_t n, hipStream_t s) {
-  store_col_kernel<<<nblocks(n), 256, 0, s>>>(src, Z, ldz, st, n);
   ABDDC_HIP(hipGetLastError());
 }
 
