@@ -137,10 +137,9 @@ void arnoldi_step(abddc_ctx* c, int restart, hipStream_t s) {
   apply_bddc_dev(c, c->d_vcur.p, c->d_zcur.p, s, c->d_Z.p, nn, st);   // also Z[:, j] = z_j
   apply_schur_dev(c, c->d_zcur.p, c->d_w.p, s);
   launch_dots_dev(c->d_V.p, nn, st, restart, c->d_w.p, n, c->d_partial.p, c->d_h1.p, s);
-  launch_axpy_multi_dev(c->d_V.p, nn, st, c->d_h1.p, -1.0, c->d_w.p, n, s);
-  launch_dots_dev(c->d_V.p, nn, st, restart, c->d_w.p, n, c->d_partial.p, c->d_h2.p, s);
-  launch_axpy_multi_dev(c->d_V.p, nn, st, c->d_h2.p, -1.0, c->d_w.p, n, s);
-  launch_dots(c->d_w.p, n, 1, c->d_w.p, n, c->d_partial.p, c->d_nrm.p, s);
+  // w -= V h1 with the second pass's products, w -= V h2 with the norm
+  launch_axpy_dots_dev(c->d_V.p, nn, st, restart, c->d_h1.p, c->d_w.p, n, false, c->d_partial.p, c->d_h2.p, s);
+  launch_axpy_dots_dev(c->d_V.p, nn, st, restart, c->d_h2.p, c->d_w.p, n, true, c->d_partial.p, c->d_nrm.p, s);
   launch_arnoldi_finish_dev(st, c->d_h1.p, c->d_h2.p, c->d_nrm.p, c->dh_step, s);
   launch_scale_to_col(c->d_w.p, st, c->d_V.p, nn, c->d_vcur.p, n, s);
 }

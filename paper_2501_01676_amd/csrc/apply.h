@@ -83,6 +83,10 @@ void launch_dots_dev(const double* V, int64_t ldv, const GmresState* st, int max
                      double* partial, double* out, hipStream_t s);
 void launch_axpy_multi_dev(const double* V, int64_t ldv, const GmresState* st, const double* coef, double sign,
                            double* w, int64_t n, hipStream_t s);
+// w -= V[:, 0..st->j] coef, then out = V[:, 0..st->j]^T w (norm: out[0] =
+// w . w), the update fused into the partial products
+void launch_axpy_dots_dev(const double* V, int64_t ldv, const GmresState* st, int max_nv, const double* coef,
+                          double* w, int64_t n, bool norm, double* partial, double* out, hipStream_t s);
 // V[:, st->j] = cur = src * st->inv_hn
 void launch_scale_to_col(const double* src, const GmresState* st, double* V, int64_t ldv, double* cur, int64_t n,
                          hipStream_t s);

@@ -116,6 +116,37 @@ __global__ void __launch_bounds__(256) dots_partial_kernel(const double* __restr
   }
 }
 
+// w -= V[:, 0..nv) coef (nv = st->j + 1), then the partial dot products of
+// the updated w over the same chunks as dots_partial_kernel: with V[j] for
+// j < nv, or with itself (norm) -- each workgroup updates exactly the
+// entries it then reads, so one launch does both.
+__global__ void __launch_bounds__(256) axpy_dots_partial_kernel(const double* __restrict__ V, int64_t ldv,
+                                                                const GmresState* __restrict__ st,
+                                                                const double* __restrict__ coef, double* __restrict__ w,
+                                                                int64_t n, int norm, double* __restrict__ partial) {
+  __shared__ double red[4];
+  const int nv = st->j + 1;
+  const int64_t chunk = (n + gridDim.x - 1) / gridDim.x;
+  const int64_t lo = blockIdx.x * chunk, hi = min(n, lo + chunk);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+    double sacc = 0.0;
+    for (int j = 0; j < nv; ++j) sacc += coef[j] * V[(int64_t)j * ldv + i];
+    w[i] -= sacc;
+  }
+  const int nd = norm ? 1 : nv;
+  for (int j = 0; j < nd; ++j) {
+    double a = 0.0;
+    const double* vj = norm ? w : V + (int64_t)j * ldv;
+    for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) a += vj[i] * w[i];
+    a = wave_sum(a);
+    if (lane == 0) red[wv] = a;
+    __syncthreads();
+    if (threadIdx.x == 0) partial[blockIdx.x * DOT_STRIDE + j] = (red[0] + red[1]) + (red[2] + red[3]);
+    __syncthreads();
+  }
+}
+
 // one workgroup per vector j: fixed-order tree over the block partials
 __global__ void __launch_bounds__(256) dots_final_kernel(const double* __restrict__ partial, int nblk,
                                                          const GmresState* __restrict__ st,
@@ -381,6 +412,16 @@ void launch_dots_dev(const double* V, int64_t ldv, const GmresState* st, int max
                      double* partial, double* out, hipStream_t s) {
   dots_partial_kernel<<<DOT_BLOCKS, 256, 0, s>>>(V, ldv, 0, st, w, n, partial);
   dots_final_kernel<<<max_nv, 256, 0, s>>>(partial, DOT_BLOCKS, st, out);
+  ABDDC_HIP(hipGetLastError());
+}
+
+void launch_axpy_dots_dev(const double* V, int64_t ldv, const GmresState* st, int max_nv, const double* coef,
+                          double* w, int64_t n, bool norm, double* partial, double* out, hipStream_t s) {
+  axpy_dots_partial_kernel<<<DOT_BLOCKS, 256, 0, s>>>(V, ldv, st, coef, w, n, norm ? 1 : 0, partial);
+  if (norm)
+    dots_final_kernel<<<1, 256, 0, s>>>(partial, DOT_BLOCKS, nullptr, out);
+  else
+    dots_final_kernel<<<max_nv, 256, 0, s>>>(partial, DOT_BLOCKS, st, out);
   ABDDC_HIP(hipGetLastError());
 }
 

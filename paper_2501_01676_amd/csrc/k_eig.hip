@@ -1082,25 +1082,28 @@ __device__ __forceinline__ void chol_solve(const double (*Lm)[NM + 1], int k, do
 }
 
 // Second half of the fallback: X = M12 (k x m, leading dimension ldx),
-// projected off V_d (rows of Vd), solved with M' = L L^T (L in Am), then
-// M22 -= M21 X, with M21 staged in Am when it fits.
+// projected off V_d (rows of Vd, each staged in the LDS array vs of NM
+// doubles), solved with M' = L L^T (L in Am), then M22 -= M21 X, with M21
+// staged in Am when it fits.
 template <int NM>
 __device__ __forceinline__ void spinv_fallback_apply(double (*Am)[NM + 1], double* M, int ld, int k, int m,
-                                                     const double* Vd, int pd, double* X, int ldx) {
+                                                     const double* Vd, int pd, double* X, int ldx, double* vs) {
   const int tid = threadIdx.x, tj = tid & 63, ti = tid >> 6, nstep = blockDim.x >> 6;
   for (int idx = tid; idx < k * m; idx += blockDim.x) {
     const int r = idx / m, c = idx - r * m;
     X[(size_t)r * ldx + c] = M[(size_t)r * ld + k + c];
   }
   __syncthreads();
-  for (int c = tid; c < m; c += blockDim.x)
-    for (int q = 0; q < pd; ++q) {
-      const double* vq = Vd + (size_t)q * k;
+  for (int q = 0; q < pd; ++q) {
+    for (int i = tid; i < k; i += blockDim.x) vs[i] = Vd[(size_t)q * k + i];
+    __syncthreads();
+    for (int c = tid; c < m; c += blockDim.x) {
       double t = 0.0;
-      for (int i = 0; i < k; ++i) t += vq[i] * X[(size_t)i * ldx + c];
-      for (int i = 0; i < k; ++i) X[(size_t)i * ldx + c] -= vq[i] * t;
+      for (int i = 0; i < k; ++i) t += vs[i] * X[(size_t)i * ldx + c];
+      for (int i = 0; i < k; ++i) X[(size_t)i * ldx + c] -= vs[i] * t;
     }
-  __syncthreads();
+    __syncthreads();
+  }
   chol_solve<NM>(Am, k, X, ldx, m);
   const bool stage = m <= NM;
   if (stage) {
@@ -1174,9 +1177,9 @@ __global__ void __launch_bounds__(NT) spinv_fallback_kernel(const SchurWork* __r
   __syncthreads();
   cholesky_panels<NM>(&Am[0][0], NM + 1, k, dflag);
   if (XL && m <= NM)
-    spinv_fallback_apply<NM>(Am, M, ld, k, m, Vd, pd, &Xs[0][0], NM + 1);
+    spinv_fallback_apply<NM>(Am, M, ld, k, m, Vd, pd, &Xs[0][0], NM + 1, tw.q1);
   else
-    spinv_fallback_apply<NM>(Am, M, ld, k, m, Vd, pd, w.work + (size_t)k * k, m);
+    spinv_fallback_apply<NM>(Am, M, ld, k, m, Vd, pd, w.work + (size_t)k * k, m, tw.q1);
 }
 
 // Parallel sum pieces: [[A + B, B], [-A, 0]] (its pseudo-inverse Schur
