@@ -85,6 +85,27 @@ struct Mfma<float> {
   }
 };
 
+// 1 / x from the hardware reciprocal and Newton steps e = 1 - x r,
+// r += r e (two for FP64, one for FP32): a few dependent operations instead
+// of the IEEE division sequence, correct to about an ulp -- for the
+// multipliers of the diagonal-block LU, where the pivot chain is the
+// critical path.
+template <class T>
+__device__ inline T recip(T x);
+template <>
+__device__ inline double recip<double>(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+template <>
+__device__ inline float recip<float>(float x) {
+  const float r = __builtin_amdgcn_rcpf(x);
+  return fmaf(r, fmaf(-x, r, 1.0f), r);
+}
+
 // One 64x64 tile of C = alpha op(A) op(B) + beta C, op(A) m x k, op(B) k x n,
 // tile origin (row0, col0); entries with row and column both >= kmask are
 // left unwritten.  A wave owns a 32x32 quadrant made of 2x2 MFMA
@@ -254,7 +275,7 @@ __global__ void __launch_bounds__(256) plu_diag_kernel(const PluDesc<T>* __restr
         const int pr = kb + j;
         const T piv = read_lane(P[j], pr);
         if (lane == 0 && pr < b && (!(fabs((double)piv) > 0.0) || !isfinite((double)piv))) atomicOr(dflag, 1);
-        const T inv = T(1) / piv;
+        const T inv = recip(piv);
         T u[16];
 #pragma unroll
         for (int j2 = j + 1; j2 < 16; ++j2) u[j2] = read_lane(P[j2], pr);
@@ -288,6 +309,7 @@ __global__ void __launch_bounds__(256) plu_diag_kernel(const PluDesc<T>* __restr
       T U[16];
 #pragma unroll
       for (int t = 0; t < 16; ++t) U[t] = D[kb + t][lane];
+#pragma unroll 2
       for (int i = kb + 16 + wave; i < NB; i += 4) {
         T a[4] = {T(0), T(0), T(0), T(0)};
 #pragma unroll
@@ -319,10 +341,10 @@ __global__ void __launch_bounds__(256) plu_diag_kernel(const PluDesc<T>* __restr
       T X[H];
 #pragma unroll
       for (int r = 0; r < H; ++r) {
-        T v = T(r == c);
+        T a[2] = {T(0), T(0)};   // two independent chains
 #pragma unroll
-        for (int q = 0; q < r; ++q) v -= D[off + r][off + q] * X[q];
-        X[r] = v;
+        for (int q = 0; q < r; ++q) a[q & 1] += D[off + r][off + q] * X[q];
+        X[r] = T(r == c) - (a[0] + a[1]);
       }
 #pragma unroll
       for (int r = 0; r < H; ++r) E[off + r][off + c] = X[r];
@@ -330,10 +352,10 @@ __global__ void __launch_bounds__(256) plu_diag_kernel(const PluDesc<T>* __restr
       T X[H];
 #pragma unroll
       for (int r = H - 1; r >= 0; --r) {
-        T v = T(r == c);
+        T a[2] = {T(0), T(0)};
 #pragma unroll
-        for (int q = r + 1; q < H; ++q) v -= D[off + r][off + q] * X[q];
-        X[r] = v * dinv[off + r];
+        for (int q = r + 1; q < H; ++q) a[q & 1] += D[off + r][off + q] * X[q];
+        X[r] = (T(r == c) - (a[0] + a[1])) * dinv[off + r];
       }
       // U11^{-1} -> E21 (rows H.., cols 0..), U22^{-1} -> E12 (rows 0.., cols H..)
 #pragma unroll
