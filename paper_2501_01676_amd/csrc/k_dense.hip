@@ -518,14 +518,25 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) p
   tile_gemm<T, false, false>(A21, d.ld, A12, d.ld, A22, d.ld, mr, nc, k, T(-1), T(1), row0, col0, As, Bs);
 }
 
-__global__ void gather_kernel(const GatherDesc* __restrict__ descs) {
+// One wave per destination row (rows strided over the grid's waves), lanes
+// along the row: the row's source index is read once per wave, the column
+// map and both rows are walked with unit stride across lanes.
+__global__ void __launch_bounds__(256) gather_kernel(const GatherDesc* __restrict__ descs) {
   const GatherDesc d = descs[blockIdx.y];
-  const int total = d.nr * d.nc;
-  for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += gridDim.x * blockDim.x) {
-    const int r = idx / d.nc, c = idx % d.nc;
+  const int lane = threadIdx.x & 63;
+  const int nwv = gridDim.x * (blockDim.x >> 6);
+  for (int r = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); r < d.nr; r += nwv) {
     const int sr = d.rmap ? d.rmap[r] : r;
-    const int sc = d.cmap ? d.cmap[c] : c;
-    d.dst[(size_t)r * d.ldd + c] = (sr >= 0 && sc >= 0) ? d.scale * d.src[(size_t)sr * d.lds + sc] : 0.0;
+    double* drow = d.dst + (size_t)r * d.ldd;
+    if (sr < 0) {
+      for (int c = lane; c < d.nc; c += 64) drow[c] = 0.0;
+      continue;
+    }
+    const double* srow = d.src + (size_t)sr * d.lds;
+    for (int c = lane; c < d.nc; c += 64) {
+      const int sc = d.cmap ? d.cmap[c] : c;
+      drow[c] = sc >= 0 ? d.scale * srow[sc] : 0.0;
+    }
   }
 }
 
@@ -649,12 +660,15 @@ void gemm_batched(const std::vector<GemmDesc<T>>& descs, bool transA, bool trans
 
 void gather_batched(const std::vector<GatherDesc>& descs, hipStream_t s) {
   if (descs.empty()) return;
-  int maxe = 0;
-  for (auto& d : descs) maxe = std::max(maxe, d.nr * d.nc);
+  int maxe = 0, maxr = 0;
+  for (auto& d : descs) {
+    maxe = std::max(maxe, d.nr * d.nc);
+    maxr = std::max(maxr, d.nr);
+  }
   if (maxe == 0) return;
   Arena& ar = Arena::for_stream(s);
   const GatherDesc* dd = ar.put(descs);
-  int gx = std::min((maxe + 255) / 256, 1024);
+  const int gx = std::min((maxr + 3) / 4, 1024);   // four rows (waves) per workgroup
   gather_kernel<<<dim3(gx, descs.size()), 256, 0, s>>>(dd);
   ABDDC_HIP(hipGetLastError());
 }

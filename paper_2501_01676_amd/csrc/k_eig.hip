@@ -895,11 +895,12 @@ __device__ __forceinline__ void tri_back_transform(const double (*C)[NM + 1], co
   __syncthreads();
 }
 
-// LDS of the pipeline for order NM and NT threads: one inverse-iteration
-// slot per wave for NM = 64, a single slot for NM = 128 (whose matrix takes
+// LDS of the pipeline for order NM and NT threads: two inverse-iteration
+// slots for NM = 64 (clusters are few; this keeps a workgroup under 80 KB of
+// LDS, so two share a CU), a single slot for NM = 128 (whose matrix takes
 // most of the LDS).
 #define TRI_SHARED(NM, NT)                                                                     \
-  constexpr int TRI_NSLOT = (NM) <= 64 ? (NT) / 64 : 1;                                        \
+  constexpr int TRI_NSLOT = (NM) <= 64 ? 2 : 1;                                                \
   __shared__ double dg_[(NM) + 8], od_[NM], e2_[(NM) + 8], tau_[NM], q1_[NM], lam_[NM],            \
       inv_[TRI_NSLOT * 5 * (NM)];                                                              \
   __shared__ int ipiv_[TRI_NSLOT * (NM)];                                                      \
