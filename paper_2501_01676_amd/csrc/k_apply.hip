@@ -41,18 +41,31 @@ __global__ void __launch_bounds__(256) gemv_kernel(const GemvBlock* __restrict__
   extern __shared__ double xs[];
   const GemvBlock blk = blocks[blockIdx.x];
   const GemvMat d = mats[blk.mat];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int r0 = blk.row0 + w * R;
+  const TM* base = M + d.moff + (int64_t)r0 * d.ld;
+  const int nr = min(R, d.nrows - r0);
+  // the rows' first 64 columns are requested before the input gather, so
+  // the two latencies overlap
+  TM pre[R];
+  if (nr == R && lane < d.ncols) {
+#pragma unroll
+    for (int q = 0; q < R; ++q) pre[q] = base[(int64_t)q * d.ld + lane];
+  }
   for (int c = threadIdx.x; c < d.ncols; c += blockDim.x)
     xs[c] = xidx ? x[xidx[d.xoff + c]] : x[d.xoff + c];
   __syncthreads();
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int r0 = blk.row0 + w * R;
   double acc[R];
 #pragma unroll
   for (int q = 0; q < R; ++q) acc[q] = 0.0;
-  const TM* base = M + d.moff + (int64_t)r0 * d.ld;
-  const int nr = min(R, d.nrows - r0);
   if (nr == R) {
-    for (int c = lane; c < d.ncols; c += 64) {
+    if (lane < d.ncols) {
+      const double xv = xs[lane];
+#pragma unroll
+      for (int q = 0; q < R; ++q) acc[q] += (double)pre[q] * xv;
+    }
+#pragma unroll 2
+    for (int c = lane + 64; c < d.ncols; c += 64) {
       const double xv = xs[c];
 #pragma unroll
       for (int q = 0; q < R; ++q) acc[q] += (double)base[(int64_t)q * d.ld + c] * xv;
