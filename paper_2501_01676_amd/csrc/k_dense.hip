@@ -14,6 +14,8 @@
 
 #include <algorithm>
 #include <cmath>
+#include <map>
+#include <mutex>
 
 #include "arena.h"
 #include "htrace.h"
@@ -107,8 +109,8 @@ __device__ inline float recip<float>(float x) {
 }
 
 // One 64x64 tile of C = alpha op(A) op(B) + beta C, op(A) m x k, op(B) k x n,
-// tile origin (row0, col0); entries with row and column both >= kmask are
-// left unwritten.  A wave owns a 32x32 quadrant made of 2x2 MFMA
+// tile origin (row0, col0); entries with row and column both >= kmask, or
+// both < skip_lo, are left unwritten.  A wave owns a 32x32 quadrant made of 2x2 MFMA
 // blocks of 16x16; lane l feeds A[l%16][k+l/16], B[k+l/16][l%16]; the
 // output rows each lane holds depend on the instruction (Mfma::out_row).  Safe in place when C aliases op(A)'s
 // rows (n <= TILE) or op(B)'s columns (m <= TILE): all reads of a tile
@@ -116,7 +118,7 @@ __device__ inline float recip<float>(float x) {
 template <class T, bool TA, bool TB>
 __device__ __forceinline__ void tile_gemm(const T* __restrict__ A, int lda, const T* __restrict__ B, int ldb, T* C,
                           int ldc, int m, int n, int k, T alpha, T beta, int row0, int col0,
-                          T (*As)[LDS_PAD], T (*Bs)[LDS_PAD], int kmask = 0x7fffffff) {
+                          T (*As)[LDS_PAD], T (*Bs)[LDS_PAD], int kmask = 0x7fffffff, int skip_lo = 0) {
   typedef typename Mfma<T>::acc_t acc_t;
   constexpr int PER = TILE * KC / 256;   // elements of each operand per thread and chunk (8)
   const int tid = threadIdx.x;
@@ -206,7 +208,8 @@ __device__ __forceinline__ void tile_gemm(const T* __restrict__ A, int lda, cons
       for (int q = 0; q < 4; ++q) {
         int r = row0 + wr + 16 * bi + Mfma<T>::out_row(kl, q);
         int c = col0 + wc + 16 * bj + il;
-        if (r < m && c < n && (r < kmask || c < kmask)) C[(size_t)r * ldc + c] = alpha * acc[bi][bj][q];
+        if (r < m && c < n && (r < kmask || c < kmask) && !(r < skip_lo && c < skip_lo))
+          C[(size_t)r * ldc + c] = alpha * acc[bi][bj][q];
       }
 }
 
@@ -253,11 +256,19 @@ __device__ inline float read_lane<float>(float v, int lane) {
 //   (c) all waves update the trailing block.
 // The inverses are one column per lane: wave 0 forward-substitutes L,
 // wave 1 back-substitutes U, each holding its column in registers.
+//
+// With u0 < t0 the block first receives the update of the pivot columns
+// [u0, t0) (A_dd -= A[t0.., u0..t0) A[u0..t0, t0..), depth 64 or 128), which
+// the band / lead launch of those columns leaves out: that launch and this
+// one then depend on the same triangular solves only and run side by side.
 template <class T>
-__global__ void __launch_bounds__(256) plu_diag_kernel(const PluDesc<T>* __restrict__ descs, int t0,
+__global__ void __launch_bounds__(256) plu_diag_kernel(const PluDesc<T>* __restrict__ descs, int t0, int u0,
                                                         T* __restrict__ scratch, int* dflag) {
+  constexpr int H = NB / 2;
   __shared__ T D[NB][NB + 1];
+  __shared__ T E[NB][NB + 1];   // also the staging of the block update (2 KC rows of LDS_PAD)
   __shared__ T dinv[NB];
+  static_assert(2 * KC * LDS_PAD == NB * (NB + 1), "update staging must fit in E");
   const PluDesc<T> d = descs[blockIdx.x];
   if (t0 >= d.k) return;
   const int b = min(NB, d.k - t0);
@@ -265,6 +276,12 @@ __global__ void __launch_bounds__(256) plu_diag_kernel(const PluDesc<T>* __restr
   T* base = d.a + (size_t)t0 * d.ld + t0;
   for (int r = wave; r < NB; r += 4) D[r][lane] = (r < b && lane < b) ? base[(size_t)r * d.ld + lane] : T(r == lane);
   __syncthreads();
+  if (u0 < t0) {
+    T (*As)[LDS_PAD] = reinterpret_cast<T (*)[LDS_PAD]>(&E[0][0]);
+    tile_gemm<T, false, false>(d.a + (size_t)t0 * d.ld + u0, d.ld, d.a + (size_t)u0 * d.ld + t0, d.ld, &D[0][0],
+                               NB + 1, b, b, t0 - u0, T(-1), T(1), 0, 0, As, As + KC);
+    __syncthreads();
+  }
   for (int kb = 0; kb < b; kb += 16) {
     if (wave == 0) {
       T P[16];
@@ -333,8 +350,6 @@ __global__ void __launch_bounds__(256) plu_diag_kernel(const PluDesc<T>* __restr
   //     E11 = L11^{-1}, E22 = L22^{-1}, E21 = U11^{-1}, E12 = U22^{-1};
   // (2) T1 = L21 E11 and T2 = U12 E12 on MFMA, written over L21, U12;
   // (3) the off-diagonal blocks -E22 T1 and -E21 T2 on MFMA, straight to global.
-  constexpr int H = NB / 2;
-  __shared__ T E[NB][NB + 1];
   {
     const int half = lane >> 5, c = lane & 31, off = half * H;
     if (wave == 0) {
@@ -465,7 +480,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) p
   const T* A12 = d.a + (size_t)t0 * d.ld + s0;
   T* A22 = d.a + (size_t)s0 * d.ld + s0;
   if (t < rtl) {
-    tile_gemm<T, false, false>(A21, d.ld, A12, d.ld, A22, d.ld, mr, w, b, T(-1), T(1), t * TILE, 0, As, Bs);
+    // the next diagonal block [0, w)^2 is updated by the next panel's diag kernel
+    tile_gemm<T, false, false>(A21, d.ld, A12, d.ld, A22, d.ld, mr, w, b, T(-1), T(1), t * TILE, 0, As, Bs,
+                               0x7fffffff, w);
   } else {
     const int col0 = w + (t - rtl) * TILE;
     if (col0 >= nc) return;
@@ -495,8 +512,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) p
   const T* A21 = d.a + (size_t)s0 * d.ld + t0;
   const T* A12 = d.a + (size_t)t0 * d.ld + s0;
   T* A22 = d.a + (size_t)s0 * d.ld + s0;
-  // only entries with row < kr or col < kr are written
-  tile_gemm<T, false, false>(A21, d.ld, A12, d.ld, A22, d.ld, mr, nc, b, T(-1), T(1), row0, col0, As, Bs, kr);
+  // only entries with row < kr or col < kr are written, and not the next
+  // diagonal block [0, min(NB, kr))^2, which the next panel's diag kernel updates
+  tile_gemm<T, false, false>(A21, d.ld, A12, d.ld, A22, d.ld, mr, nc, b, T(-1), T(1), row0, col0, As, Bs, kr,
+                             min(NB, kr));
 }
 
 // Trailing Schur complement A22 -= A21 A12 with K = k (one pass).
@@ -556,6 +575,28 @@ __global__ void sym_kernel(const SymDesc* __restrict__ descs) {
 
 }  // namespace
 
+// A second stream per library stream (default priority) with two events,
+// for the diagonal-block lookahead of partial_lu; created on first use and
+// kept for the process.
+struct SideStream {
+  hipStream_t s = nullptr;
+  hipEvent_t ready = nullptr, done = nullptr;
+  static SideStream& for_stream(hipStream_t main) {
+    static std::mutex mu;
+    static std::map<hipStream_t, SideStream*> table;
+    std::lock_guard<std::mutex> g(mu);
+    SideStream*& e = table[main];
+    if (!e) {
+      SideStream* n = new SideStream();
+      ABDDC_HIP(hipStreamCreateWithFlags(&n->s, hipStreamNonBlocking));
+      ABDDC_HIP(hipEventCreateWithFlags(&n->ready, hipEventDisableTiming));
+      ABDDC_HIP(hipEventCreateWithFlags(&n->done, hipEventDisableTiming));
+      e = n;
+    }
+    return *e;
+  }
+};
+
 template <class T>
 void partial_lu(const std::vector<PluDesc<T>>& descs_in, int* dflag, hipStream_t s) {
   if (descs_in.empty()) return;
@@ -585,11 +626,25 @@ void partial_lu(const std::vector<PluDesc<T>>& descs_in, int* dflag, hipStream_t
   }
   T* scr = reinterpret_cast<T*>(scratch.p);
   const int nb = (int)descs.size();
+  // Lookahead: the diag kernel of panel t0 + NB runs on a side stream, after
+  // the triangular solves of panel t0 and beside the band / lead launch of
+  // that panel (which leaves its block to it); the next solves wait for it.
+  SideStream& side = SideStream::for_stream(s);
+  plu_diag_kernel<T><<<nb, 256, 0, s>>>(dd, 0, 0, scr, dflag);
   for (int t0 = 0; t0 < maxk; t0 += NB) {
     const int rem = std::max(maxr, maxc) - t0;
     const int tiles = 2 * ((rem + TILE - 1) / TILE);
-    plu_diag_kernel<T><<<nb, 256, 0, s>>>(dd, t0, scr, dflag);
+    if (t0 > 0) ABDDC_HIP(hipStreamWaitEvent(s, side.done, 0));
     plu_trsm_kernel<T><<<xcd_grid(std::max(tiles, 1), nb), 256, 0, s>>>(dd, t0, scr, std::max(tiles, 1), nb);
+    if (t0 + NB < maxk) {
+      // the next diagonal block: this panel's columns (and, after the second
+      // panel of a pair, the first one's too) applied in the diag kernel
+      const int u0 = (t0 / NB) % 2 == 0 ? t0 : t0 - NB;
+      ABDDC_HIP(hipEventRecord(side.ready, s));
+      ABDDC_HIP(hipStreamWaitEvent(side.s, side.ready, 0));
+      plu_diag_kernel<T><<<nb, 256, 0, side.s>>>(dd, t0 + NB, u0, scr, dflag);
+      ABDDC_HIP(hipEventRecord(side.done, side.s));
+    }
     if ((t0 / NB) % 2 == 0) {
       // first panel of a pair: the band the second panel needs
       if (t0 + NB < maxk) {
