@@ -176,6 +176,11 @@ __device__ __forceinline__ void tile_gemm(const T* __restrict__ A, int lda, cons
       rb[q] = okb ? qb[q * sb] : T(0);
     }
   };
+  // which of the wave's 16 x 16 blocks have a row / column inside C (a full
+  // 2 x 2 set on every interior tile)
+  const bool rok0 = row0 + wr < m, rok1 = row0 + wr + 16 < m;
+  const bool cok0 = col0 + wc < n, cok1 = col0 + wc + 16 < n;
+  const bool full = rok1 && cok1;
   if (k > 0) fetch(0);
 #pragma unroll 1
   for (int k0 = 0; k0 < k; k0 += KC) {
@@ -187,16 +192,29 @@ __device__ __forceinline__ void tile_gemm(const T* __restrict__ A, int lda, cons
     }
     __syncthreads();
     if (k0 + KC < k) fetch(k0 + KC);   // next chunk in flight during the MFMAs
+    if (full) {
 #pragma unroll
-    for (int kk = 0; kk < KC; kk += 4) {
-      T a0 = As[kk + kl][wr + il];
-      T a1 = As[kk + kl][wr + 16 + il];
-      T b0 = Bs[kk + kl][wc + il];
-      T b1 = Bs[kk + kl][wc + 16 + il];
-      acc[0][0] = Mfma<T>::run(a0, b0, acc[0][0]);
-      acc[0][1] = Mfma<T>::run(a0, b1, acc[0][1]);
-      acc[1][0] = Mfma<T>::run(a1, b0, acc[1][0]);
-      acc[1][1] = Mfma<T>::run(a1, b1, acc[1][1]);
+      for (int kk = 0; kk < KC; kk += 4) {
+        T a0 = As[kk + kl][wr + il];
+        T a1 = As[kk + kl][wr + 16 + il];
+        T b0 = Bs[kk + kl][wc + il];
+        T b1 = Bs[kk + kl][wc + 16 + il];
+        acc[0][0] = Mfma<T>::run(a0, b0, acc[0][0]);
+        acc[0][1] = Mfma<T>::run(a0, b1, acc[0][1]);
+        acc[1][0] = Mfma<T>::run(a1, b0, acc[1][0]);
+        acc[1][1] = Mfma<T>::run(a1, b1, acc[1][1]);
+      }
+    } else if (rok0 && cok0) {
+      // a tile at the edge of C: 16 x 16 blocks with no row or no column
+      // inside C are skipped (wave-uniform tests)
+#pragma unroll
+      for (int kk = 0; kk < KC; kk += 4) {
+        T a0 = As[kk + kl][wr + il];
+        T b0 = Bs[kk + kl][wc + il];
+        acc[0][0] = Mfma<T>::run(a0, b0, acc[0][0]);
+        if (cok1) acc[0][1] = Mfma<T>::run(a0, Bs[kk + kl][wc + 16 + il], acc[0][1]);
+        if (rok1) acc[1][0] = Mfma<T>::run(As[kk + kl][wr + 16 + il], b0, acc[1][0]);
+      }
     }
   }
   __syncthreads();
