@@ -279,6 +279,26 @@ def test_graph_replay_matches_eager(pairs, restart):
         assert torch.equal(u1, u4) and np.array_equal(i1["history"], i4["history"])
 
 
+def test_fresh_contexts_and_streams_repeat(pairs):
+    """Contexts take pooled runtime objects, and every library stream has its
+    own descriptor / upload rings and partial-LU side stream: solving the same
+    problem again in fresh contexts, on the default stream and on a second
+    stream, gives bit-identical solutions and the same iteration count."""
+    from paper_2501_01676_amd import api
+    p, o, g0 = pairs["ragged_loose"]
+    u_ref, i_ref = g0.gmres_solve()
+    torch.cuda.synchronize()
+    second = torch.cuda.Stream()
+    for stream in (None, None, second):
+        g = api.Solver(p, stream=stream)
+        g.setup_coarse_space(**CASES["ragged_loose"][2])
+        u, info = g.gmres_solve()
+        torch.cuda.synchronize()
+        assert info["iters"] == i_ref["iters"]
+        assert torch.equal(u, u_ref)
+        g.close()
+
+
 def test_autotuner_cache(tmp_path):
     """The GEMV variants are chosen by timing on first use and recorded per
     architecture and size bucket in the cache file; every variant gives
