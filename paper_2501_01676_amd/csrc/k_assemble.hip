@@ -196,12 +196,22 @@ __global__ void __launch_bounds__(1024) recover_kernel(const SubAsm* __restrict_
   const double* M = A + d.aoff;
   for (int c = tid; c < nB; c += blockDim.x) ub[c] = uhat[gam[d.goff + c]];
   __syncthreads();
-  for (int r = wave; r < nI; r += nw) {
+  // two rows per wave at a time, so their load chains overlap
+  for (int r = 2 * wave; r < nI; r += 2 * nw) {
+    const bool two = r + 1 < nI;
     const double* row = M + (int64_t)r * d.ld + nI;
-    double v = 0.0;
-    for (int c = lane; c < nB; c += 64) v += row[c] * ub[c];
-    v = wave_sum_d(v);
-    if (lane == 0) xs[r] = M[(int64_t)r * d.ld + d.nloc] - v;
+    double v0 = 0.0, v1 = 0.0;
+    for (int c = lane; c < nB; c += 64) {
+      const double x = ub[c];
+      v0 += row[c] * x;
+      if (two) v1 += row[d.ld + c] * x;
+    }
+    v0 = wave_sum_d(v0);
+    v1 = wave_sum_d(v1);
+    if (lane == 0) {
+      xs[r] = M[(int64_t)r * d.ld + d.nloc] - v0;
+      if (two) xs[r + 1] = M[(int64_t)(r + 1) * d.ld + d.nloc] - v1;
+    }
   }
   __syncthreads();
   for (int p1 = nI; p1 > 0;) {
@@ -217,9 +227,11 @@ __global__ void __launch_bounds__(1024) recover_kernel(const SubAsm* __restrict_
     }
     __syncthreads();
     if (wave == 0) {
+      // reciprocal pivots, one per lane, off the substitution chain
+      const double rp = 1.0 / Ud[lane][lane];
       double b = lane < len ? bv[lane] : 0.0, x = 0.0;
       for (int r = len - 1; r >= 0; --r) {
-        const double xr = read_lane_d(b, r) / Ud[r][r];
+        const double xr = read_lane_d(b, r) * read_lane_d(rp, r);
         if (lane == r) x = xr;
         if (lane < r) b -= Ud[lane][r] * xr;
       }

@@ -1027,16 +1027,19 @@ __device__ __forceinline__ void chol_solve(const double (*Lm)[NM + 1], int k, do
   for (int r0 = 0; r0 < k; r0 += 16) {
     const int rw = min(16, k - r0);
     for (int c = tid; c < m; c += blockDim.x) {
-      double x[16];
+      double x[16], rl[16];   // rl: reciprocal pivots, off the substitution chain
 #pragma unroll
-      for (int i = 0; i < 16; ++i) x[i] = i < rw ? X[(size_t)(r0 + i) * ldx + c] : 0.0;
+      for (int i = 0; i < 16; ++i) {
+        x[i] = i < rw ? X[(size_t)(r0 + i) * ldx + c] : 0.0;
+        rl[i] = i < rw ? 1.0 / Lm[r0 + i][r0 + i] : 0.0;
+      }
 #pragma unroll
       for (int i = 0; i < 16; ++i)
         if (i < rw) {
           double v = x[i];
 #pragma unroll
           for (int q = 0; q < i; ++q) v -= Lm[r0 + i][r0 + q] * x[q];
-          x[i] = v / Lm[r0 + i][r0 + i];
+          x[i] = v * rl[i];
         }
 #pragma unroll
       for (int i = 0; i < 16; ++i)
@@ -1055,9 +1058,12 @@ __device__ __forceinline__ void chol_solve(const double (*Lm)[NM + 1], int k, do
   for (int r0 = ((k - 1) / 16) * 16; r0 >= 0; r0 -= 16) {
     const int rw = min(16, k - r0);
     for (int c = tid; c < m; c += blockDim.x) {
-      double x[16];
+      double x[16], rl[16];
 #pragma unroll
-      for (int i = 0; i < 16; ++i) x[i] = i < rw ? X[(size_t)(r0 + i) * ldx + c] : 0.0;
+      for (int i = 0; i < 16; ++i) {
+        x[i] = i < rw ? X[(size_t)(r0 + i) * ldx + c] : 0.0;
+        rl[i] = i < rw ? 1.0 / Lm[r0 + i][r0 + i] : 0.0;
+      }
 #pragma unroll
       for (int i = 15; i >= 0; --i)
         if (i < rw) {
@@ -1065,7 +1071,7 @@ __device__ __forceinline__ void chol_solve(const double (*Lm)[NM + 1], int k, do
 #pragma unroll
           for (int q = i + 1; q < 16; ++q)
             if (q < rw) v -= Lm[r0 + q][r0 + i] * x[q];
-          x[i] = v / Lm[r0 + i][r0 + i];
+          x[i] = v * rl[i];
         }
 #pragma unroll
       for (int i = 0; i < 16; ++i)
