@@ -71,6 +71,24 @@ def test_partial_lu_schur_complement(precision):
             assert np.abs(L @ o[:k, k:] - M[:k, k:]).max() <= ftol * scale
 
 
+def test_partial_lu_large_batch():
+    """A ragged batch of 140 matrices (more diagonal-block workgroups than
+    half the CUs, running beside the band / lead tiles) against numpy."""
+    api = _api()
+    rng = np.random.default_rng(5)
+    mats, ks, refs = [], [], []
+    for b in range(140):
+        n = int(rng.integers(70, 210))
+        k = int(rng.integers(1, n - 5))
+        M = rng.standard_normal((n, n + 3))
+        M[:k, :k] = _posreal(k, rng)
+        mats.append(M); ks.append(k)
+        refs.append(M[k:, k:] - M[k:, :k] @ np.linalg.solve(M[:k, :k], M[:k, k:]))
+    out = api.partial_lu(mats, ks, 0)
+    for o, k, r in zip(out, ks, refs):
+        assert np.abs(o[k:, k:] - r).max() <= 1e-11 * max(1.0, np.abs(r).max())
+
+
 def test_partial_lu_inverse_trick():
     """Schur complement of [[A, I], [-I, 0]] onto the trailing block is A^{-1}."""
     api = _api()
