@@ -108,6 +108,28 @@ __device__ inline float recip<float>(float x) {
   return fmaf(r, fmaf(-x, r, 1.0f), r);
 }
 
+// Raw buffer loads (CDNA buffer descriptors, record count 2^31 - 1 bytes,
+// no stride): a load whose offset is at or past the record count returns
+// zero, so elements outside an operand are selected to BUF_OUT instead of
+// branched around.  Offsets are 32-bit byte offsets from the descriptor's
+// base; every matrix handed to the tiled launches spans less than 2^31
+// bytes (checked on the host where the descriptors are built).
+constexpr int BUF_OUT = int(0x80000000u);
+constexpr int64_t BUF_LIMIT = int64_t(1) << 31;
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void* p) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, 0x7fffffff, 0x00020000);
+}
+template <class T>
+__device__ __forceinline__ T buf_load(__amdgpu_buffer_rsrc_t r, int voff, int soff);
+template <>
+__device__ __forceinline__ double buf_load<double>(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+}
+template <>
+__device__ __forceinline__ float buf_load<float>(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+}
+
 // One 64x64 tile of C = alpha op(A) op(B) + beta C, op(A) m x k, op(B) k x n,
 // tile origin (row0, col0); entries with row and column both >= kmask, or
 // both < skip_lo, are left unwritten.  A wave owns a 32x32 quadrant made of 2x2 MFMA
@@ -115,7 +137,7 @@ __device__ inline float recip<float>(float x) {
 // output rows each lane holds depend on the instruction (Mfma::out_row).  Safe in place when C aliases op(A)'s
 // rows (n <= TILE) or op(B)'s columns (m <= TILE): all reads of a tile
 // precede its writes.
-template <class T, bool TA, bool TB>
+template <class T, bool TA, bool TB, bool C_LDS = false>
 __device__ __forceinline__ void tile_gemm(const T* __restrict__ A, int lda, const T* __restrict__ B, int ldb, T* C,
                           int ldc, int m, int n, int k, T alpha, T beta, int row0, int col0,
                           T (*As)[LDS_PAD], T (*Bs)[LDS_PAD], int kmask = 0x7fffffff, int skip_lo = 0) {
@@ -140,6 +162,7 @@ __device__ __forceinline__ void tile_gemm(const T* __restrict__ A, int lda, cons
   // accumulators start at (beta / alpha) C and the result is alpha * acc
   // (alpha != 0).
   acc_t acc[2][2];
+  const __amdgpu_buffer_rsrc_t rsa = buf_rsrc(A), rsb = buf_rsrc(B), rsc = buf_rsrc(C_LDS ? nullptr : C);
   if (beta != T(0)) {
     const T cs = beta / alpha;
 #pragma unroll
@@ -150,7 +173,12 @@ __device__ __forceinline__ void tile_gemm(const T* __restrict__ A, int lda, cons
         for (int q = 0; q < 4; ++q) {
           const int r = row0 + wr + 16 * bi + Mfma<T>::out_row(kl, q);
           const int c = col0 + wc + 16 * bj + il;
-          acc[bi][bj][q] = (r < m && c < n) ? cs * C[(size_t)r * ldc + c] : T(0);
+          if constexpr (C_LDS) {
+            acc[bi][bj][q] = (r < m && c < n) ? cs * C[(size_t)r * ldc + c] : T(0);
+          } else {
+            const int oc = (r < m && c < n) ? (r * ldc + c) * (int)sizeof(T) : BUF_OUT;
+            acc[bi][bj][q] = cs * buf_load<T>(rsc, oc, 0);
+          }
         }
   } else {
 #pragma unroll
@@ -159,21 +187,33 @@ __device__ __forceinline__ void tile_gemm(const T* __restrict__ A, int lda, cons
       for (int j = 0; j < 2; ++j) acc[i][j] = acc_t{0, 0, 0, 0};
   }
   T ra[PER], rb[PER];
-  // per-thread base pointers; element q of a chunk is base + q * step
+  // byte offsets of the thread's elements in chunk 0, BUF_OUT where the row
+  // of op(A) or the column of op(B) lies outside; chunk k0 adds the
+  // wave-uniform k0 * (bytes per unit of k) as the scalar offset
   const int ar = row0 + a_i0, bc = col0 + b_j0;
-  const T* pa = TA ? A + (size_t)a_k0 * lda + ar : A + (size_t)ar * lda + a_k0;
-  const T* pb = TB ? B + (size_t)bc * ldb + b_k0 : B + (size_t)b_k0 * ldb + bc;
-  const size_t sa = TA ? (size_t)4 * lda : (size_t)8 * lda;   // step between q
-  const size_t sb = TB ? (size_t)8 * ldb : (size_t)4 * ldb;
-  auto fetch = [&](int k0) {
-    const T* qa = pa + (TA ? (size_t)k0 * lda : (size_t)k0);
-    const T* qb = pb + (TB ? (size_t)k0 : (size_t)k0 * ldb);
+  int oa[PER], ob[PER];
 #pragma unroll
-    for (int q = 0; q < PER; ++q) {
-      const bool oka = (ar + q * a_di < m) && (k0 + a_k0 + q * a_dk < k);
-      ra[q] = oka ? qa[q * sa] : T(0);
-      const bool okb = (bc + q * b_dj < n) && (k0 + b_k0 + q * b_dk < k);
-      rb[q] = okb ? qb[q * sb] : T(0);
+  for (int q = 0; q < PER; ++q) {
+    const int ai = ar + q * a_di, ak = a_k0 + q * a_dk;
+    oa[q] = ai < m ? (TA ? ak * lda + ai : ai * lda + ak) * (int)sizeof(T) : BUF_OUT;
+    const int bj = bc + q * b_dj, bk = b_k0 + q * b_dk;
+    ob[q] = bj < n ? (TB ? bj * ldb + bk : bk * ldb + bj) * (int)sizeof(T) : BUF_OUT;
+  }
+  const int ska = (TA ? lda : 1) * (int)sizeof(T), skb = (TB ? 1 : ldb) * (int)sizeof(T);
+  auto fetch = [&](int k0) {
+    const int sa = k0 * ska, sb = k0 * skb;
+    if (k0 + KC <= k) {
+#pragma unroll
+      for (int q = 0; q < PER; ++q) {
+        ra[q] = buf_load<T>(rsa, oa[q], sa);
+        rb[q] = buf_load<T>(rsb, ob[q], sb);
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < PER; ++q) {
+        ra[q] = buf_load<T>(rsa, k0 + a_k0 + q * a_dk < k ? oa[q] : BUF_OUT, sa);
+        rb[q] = buf_load<T>(rsb, k0 + b_k0 + q * b_dk < k ? ob[q] : BUF_OUT, sb);
+      }
     }
   };
   // which of the wave's 16 x 16 blocks have a row / column inside C (a full
@@ -296,7 +336,7 @@ __global__ void __launch_bounds__(256) plu_diag_kernel(const PluDesc<T>* __restr
   __syncthreads();
   if (u0 < t0) {
     T (*As)[LDS_PAD] = reinterpret_cast<T (*)[LDS_PAD]>(&E[0][0]);
-    tile_gemm<T, false, false>(d.a + (size_t)t0 * d.ld + u0, d.ld, d.a + (size_t)u0 * d.ld + t0, d.ld, &D[0][0],
+    tile_gemm<T, false, false, true>(d.a + (size_t)t0 * d.ld + u0, d.ld, d.a + (size_t)u0 * d.ld + t0, d.ld, &D[0][0],
                                NB + 1, b, b, t0 - u0, T(-1), T(1), 0, 0, As, As + KC);
     __syncthreads();
   }
@@ -628,6 +668,8 @@ void partial_lu(const std::vector<PluDesc<T>>& descs_in, int* dflag, hipStream_t
   for (auto& d : descs) {
     ABDDC_REQUIRE(d.k >= 0 && d.k <= d.nrow && d.k <= d.ncol && d.ld >= d.ncol, ABDDC_EINVAL,
                   "partial_lu: bad matrix shape");
+    ABDDC_REQUIRE((int64_t)d.nrow * d.ld * (int64_t)sizeof(T) < BUF_LIMIT, ABDDC_EINVAL,
+                  "partial_lu: matrix spans 2 GiB or more");
     maxk = std::max(maxk, d.k);
     maxr = std::max(maxr, d.nrow);
     maxc = std::max(maxc, d.ncol);
@@ -717,6 +759,9 @@ void gemm_batched(const std::vector<GemmDesc<T>>& descs, bool transA, bool trans
   int maxt = 0;
   for (auto& d : descs) {
     ABDDC_REQUIRE(d.m >= 0 && d.n >= 0 && d.k >= 0, ABDDC_EINVAL, "gemm: negative size");
+    const int64_t ea = (int64_t)(transA ? d.k : d.m) * d.lda, eb = (int64_t)(transB ? d.n : d.k) * d.ldb;
+    ABDDC_REQUIRE(std::max({ea, eb, (int64_t)d.m * d.ldc}) * (int64_t)sizeof(T) < BUF_LIMIT, ABDDC_EINVAL,
+                  "gemm: operand spans 2 GiB or more");
     maxt = std::max(maxt, ((d.m + TILE - 1) / TILE) * ((d.n + TILE - 1) / TILE));
   }
   if (maxt == 0) return;

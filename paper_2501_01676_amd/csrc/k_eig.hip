@@ -279,16 +279,19 @@ __device__ __forceinline__ void lower_solve_blocks(const double* L, int ldl, dou
   for (int r0 = 0; r0 < n; r0 += 16) {
     const int rw = min(16, n - r0);
     for (int c = tid; c < n; c += blockDim.x) {
-      double x[16];
+      double x[16], rl[16];   // rl: reciprocal pivots, off the substitution chain
 #pragma unroll
-      for (int i = 0; i < 16; ++i) x[i] = i < rw ? X[r0 + i][c] : 0.0;
+      for (int i = 0; i < 16; ++i) {
+        x[i] = i < rw ? X[r0 + i][c] : 0.0;
+        rl[i] = i < rw ? 1.0 / L[(r0 + i) * ldl + r0 + i] : 0.0;
+      }
 #pragma unroll
       for (int i = 0; i < 16; ++i) {
         if (i < rw) {
           double v = x[i];
 #pragma unroll
           for (int q = 0; q < i; ++q) v -= L[(r0 + i) * ldl + r0 + q] * x[q];
-          x[i] = v / L[(r0 + i) * ldl + r0 + i];
+          x[i] = v * rl[i];
         }
       }
 #pragma unroll
