@@ -16,6 +16,7 @@
 #include <string>
 
 #include "apply.h"
+#include "buffer.h"
 #include "internal.h"
 #include "htrace.h"
 #include "kstats.h"
@@ -43,38 +44,41 @@ __global__ void __launch_bounds__(256) gemv_kernel(const GemvBlock* __restrict__
   const GemvMat d = mats[blk.mat];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int r0 = blk.row0 + w * R;
-  const TM* base = M + d.moff + (int64_t)r0 * d.ld;
-  const int nr = min(R, d.nrows - r0);
+  // matrix rows through a buffer descriptor at the matrix's start: a row
+  // past the last one has offset BUF_OUT and reads zero, and so does a
+  // column past the last one in the final partial block
+  const __amdgpu_buffer_rsrc_t rs = buf_rsrc(M + d.moff);
+  const int nr = min(R, d.nrows - r0), cl = lane * (int)sizeof(TM);
+  int ro[R];
+#pragma unroll
+  for (int q = 0; q < R; ++q) ro[q] = q < nr ? (r0 + q) * d.ld * (int)sizeof(TM) + cl : BUF_OUT;
   // the rows' first 64 columns are requested before the input gather, so
   // the two latencies overlap
   TM pre[R];
-  if (nr == R && lane < d.ncols) {
 #pragma unroll
-    for (int q = 0; q < R; ++q) pre[q] = base[(int64_t)q * d.ld + lane];
-  }
+  for (int q = 0; q < R; ++q) pre[q] = buf_load<TM>(rs, lane < d.ncols ? ro[q] : BUF_OUT, 0);
   for (int c = threadIdx.x; c < d.ncols; c += blockDim.x)
     xs[c] = xidx ? x[xidx[d.xoff + c]] : x[d.xoff + c];
   __syncthreads();
   double acc[R];
+  {
+    const double xv = d.ncols > 0 ? xs[min(lane, d.ncols - 1)] : 0.0;
 #pragma unroll
-  for (int q = 0; q < R; ++q) acc[q] = 0.0;
-  if (nr == R) {
-    if (lane < d.ncols) {
-      const double xv = xs[lane];
-#pragma unroll
-      for (int q = 0; q < R; ++q) acc[q] += (double)pre[q] * xv;
-    }
+    for (int q = 0; q < R; ++q) acc[q] = (double)pre[q] * xv;
+  }
+  int c0 = 64;
 #pragma unroll 2
-    for (int c = lane + 64; c < d.ncols; c += 64) {
-      const double xv = xs[c];
+  for (; c0 + 64 <= d.ncols; c0 += 64) {   // whole blocks of 64 columns
+    const double xv = xs[c0 + lane];
 #pragma unroll
-      for (int q = 0; q < R; ++q) acc[q] += (double)base[(int64_t)q * d.ld + c] * xv;
-    }
-  } else {
-    for (int c = lane; c < d.ncols; c += 64) {
-      const double xv = xs[c];
-      for (int q = 0; q < nr; ++q) acc[q] += (double)base[(int64_t)q * d.ld + c] * xv;
-    }
+    for (int q = 0; q < R; ++q) acc[q] += (double)buf_load<TM>(rs, ro[q], c0 * (int)sizeof(TM)) * xv;
+  }
+  if (c0 < d.ncols) {
+    const bool ok = c0 + lane < d.ncols;
+    const double xv = xs[ok ? c0 + lane : d.ncols - 1];
+#pragma unroll
+    for (int q = 0; q < R; ++q)
+      acc[q] += (double)buf_load<TM>(rs, ok ? ro[q] : BUF_OUT, c0 * (int)sizeof(TM)) * xv;
   }
 #pragma unroll
   for (int q = 0; q < R; ++q) {
@@ -323,7 +327,11 @@ void gemv_build(GemvOp& op, const std::vector<GemvMat>& mats, const std::vector<
                 hipStream_t s) {
   op.maxc = 1;
   op.rows = 0;
-  for (const GemvMat& m : mats) op.maxc = std::max(op.maxc, (int)m.ncols);
+  for (const GemvMat& m : mats) {
+    op.maxc = std::max(op.maxc, (int)m.ncols);
+    ABDDC_REQUIRE((int64_t)m.nrows * m.ld * (int64_t)sizeof(double) < BUF_LIMIT, ABDDC_EINVAL,
+                  "gemv: matrix spans 2 GiB or more");
+  }
   HostTrace ht;
   for (int v = 0; v < GEMV_NVAR; ++v) {
     std::vector<GemvBlock> b;

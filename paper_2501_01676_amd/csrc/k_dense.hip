@@ -18,6 +18,7 @@
 #include <mutex>
 
 #include "arena.h"
+#include "buffer.h"
 #include "htrace.h"
 #include "internal.h"
 #include "kstats.h"
@@ -106,28 +107,6 @@ template <>
 __device__ inline float recip<float>(float x) {
   const float r = __builtin_amdgcn_rcpf(x);
   return fmaf(r, fmaf(-x, r, 1.0f), r);
-}
-
-// Raw buffer loads (CDNA buffer descriptors, record count 2^31 - 1 bytes,
-// no stride): a load whose offset is at or past the record count returns
-// zero, so elements outside an operand are selected to BUF_OUT instead of
-// branched around.  Offsets are 32-bit byte offsets from the descriptor's
-// base; every matrix handed to the tiled launches spans less than 2^31
-// bytes (checked on the host where the descriptors are built).
-constexpr int BUF_OUT = int(0x80000000u);
-constexpr int64_t BUF_LIMIT = int64_t(1) << 31;
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void* p) {
-  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, 0x7fffffff, 0x00020000);
-}
-template <class T>
-__device__ __forceinline__ T buf_load(__amdgpu_buffer_rsrc_t r, int voff, int soff);
-template <>
-__device__ __forceinline__ double buf_load<double>(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
-  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
-}
-template <>
-__device__ __forceinline__ float buf_load<float>(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
-  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
 }
 
 // One 64x64 tile of C = alpha op(A) op(B) + beta C, op(A) m x k, op(B) k x n,
@@ -266,8 +245,12 @@ __device__ __forceinline__ void tile_gemm(const T* __restrict__ A, int lda, cons
       for (int q = 0; q < 4; ++q) {
         int r = row0 + wr + 16 * bi + Mfma<T>::out_row(kl, q);
         int c = col0 + wc + 16 * bj + il;
-        if (r < m && c < n && (r < kmask || c < kmask) && !(r < skip_lo && c < skip_lo))
-          C[(size_t)r * ldc + c] = alpha * acc[bi][bj][q];
+        const bool st = r < m && c < n && (r < kmask || c < kmask) && !(r < skip_lo && c < skip_lo);
+        if constexpr (C_LDS) {
+          if (st) C[(size_t)r * ldc + c] = alpha * acc[bi][bj][q];
+        } else {
+          buf_store<T>(alpha * acc[bi][bj][q], rsc, st ? (r * ldc + c) * (int)sizeof(T) : BUF_OUT, 0);
+        }
       }
 }
 
