@@ -63,12 +63,16 @@ def calibration(values, probe_bytes):
     return probe_bytes / statistics.mean(probe)
 
 
-def traffic(fetch_csv, write_csv, kernel, probe_bytes):
+def traffic(fetch_csv, write_csv, kernel, probe_bytes, names=None):
+    """Mean counter bytes per launch of `kernel`, or of every kernel in
+    `names` taken together (template instances the benchmark tracks as one
+    class)."""
+    match = set(names) if names else {kernel}
     f = _per_dispatch(fetch_csv)
     w = _per_dispatch(write_csv)
     cf, cw = calibration(f, probe_bytes), calibration(w, probe_bytes)
-    kf = [v for k, v in f if k == kernel]
-    kw = [v for k, v in w if k == kernel]
+    kf = [v for k, v in f if k in match]
+    kw = [v for k, v in w if k in match]
     if not kf or not kw:
         raise SystemExit(f"kernel {kernel} not in counter output")
     fetch = statistics.mean(kf) * cf
@@ -118,6 +122,8 @@ def main():
     b.add_argument("--workload", required=True)
     b.add_argument("--probe-bytes", type=float, required=True)
     b.add_argument("--algorithmic-bytes", type=float, default=None)
+    b.add_argument("--names", nargs="*", default=None,
+                   help="kernel instances counted together under --kernel (default: --kernel alone)")
     b.add_argument("--out", required=True)
     b.add_argument("--cmd", required=True)
     args = ap.parse_args()
@@ -126,7 +132,7 @@ def main():
                 f"Per solve (the run's solves, warmup included, divide the totals):\n\n"
                 f"{stats_table(args.stats_csv, args.steps)}\n")
     else:
-        t = traffic(args.fetch_csv, args.write_csv, args.kernel, args.probe_bytes)
+        t = traffic(args.fetch_csv, args.write_csv, args.kernel, args.probe_bytes, args.names)
         sha = source_sha256(args.source)
         extra = ""
         if args.algorithmic_bytes:
@@ -136,7 +142,8 @@ def main():
                 f"```\n{args.cmd}\n```\n\n"
                 f"Copy-probe scale (bytes per counter unit): FETCH_SIZE {t['fetch_scale']:.4g}, "
                 f"WRITE_SIZE {t['write_scale']:.4g}.\n\n"
-                f"Per launch, mean over {t['launches']} launches: fetched {t['fetch_bytes'] / 1e6:.2f} MB, "
+                + (f"Instances counted together: {', '.join(args.names)}.\n\n" if args.names else "")
+                + f"Per launch, mean over {t['launches']} launches: fetched {t['fetch_bytes'] / 1e6:.2f} MB, "
                 f"written {t['write_bytes'] / 1e6:.2f} MB, total {t['bytes'] / 1e6:.2f} MB.\n{extra}\n"
                 f"traffic: kernel={args.kernel} workload={args.workload} bytes_per_launch={t['bytes']:.6g} "
                 f"source={args.source} sha256={sha}\n")
