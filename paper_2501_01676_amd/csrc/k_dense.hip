@@ -315,7 +315,22 @@ __global__ void __launch_bounds__(256) plu_diag_kernel(const PluDesc<T>* __restr
   const int b = min(NB, d.k - t0);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   T* base = d.a + (size_t)t0 * d.ld + t0;
-  for (int r = wave; r < NB; r += 4) D[r][lane] = (r < b && lane < b) ? base[(size_t)r * d.ld + lane] : T(r == lane);
+  {
+    // all sixteen rows of the wave requested at once (buffer loads: entries
+    // outside the b x b block read zero and become the identity padding)
+    const __amdgpu_buffer_rsrc_t rs = buf_rsrc(base);
+    T v[NB / 4];
+#pragma unroll
+    for (int i = 0; i < NB / 4; ++i) {
+      const int r = wave + 4 * i;
+      v[i] = buf_load<T>(rs, (r < b && lane < b) ? (r * d.ld + lane) * (int)sizeof(T) : BUF_OUT, 0);
+    }
+#pragma unroll
+    for (int i = 0; i < NB / 4; ++i) {
+      const int r = wave + 4 * i;
+      D[r][lane] = (r < b && lane < b) ? v[i] : T(r == lane);
+    }
+  }
   __syncthreads();
   if (u0 < t0) {
     T (*As)[LDS_PAD] = reinterpret_cast<T (*)[LDS_PAD]>(&E[0][0]);
@@ -593,9 +608,25 @@ __global__ void __launch_bounds__(256) gather_kernel(const GatherDesc* __restric
       continue;
     }
     const double* srow = d.src + (size_t)sr * d.lds;
-    for (int c = lane; c < d.nc; c += 64) {
-      const int sc = d.cmap ? d.cmap[c] : c;
-      drow[c] = sc >= 0 ? d.scale * srow[sc] : 0.0;
+    // four columns per lane at a time, every load of a group issued before
+    // its stores (the stores could alias the maps or the source as far as
+    // the compiler knows, so a plain loop waits out both load latencies per
+    // column)
+    for (int c0 = lane; c0 < d.nc; c0 += 256) {
+      int sc[4];
+      double v[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int c = c0 + 64 * u;
+        sc[u] = c < d.nc ? (d.cmap ? d.cmap[c] : c) : -1;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) v[u] = sc[u] >= 0 ? srow[sc[u]] : 0.0;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int c = c0 + 64 * u;
+        if (c < d.nc) drow[c] = d.scale * v[u];
+      }
     }
   }
 }
