@@ -1,10 +1,11 @@
-// Raw buffer access (CDNA buffer descriptors, record count 2^31 - 1 bytes,
-// no stride).  A load whose offset is at or past the record count returns
-// zero and such a store is dropped, so elements outside a matrix are
-// selected to BUF_OUT instead of branched around.  Offsets are 32-bit byte
-// offsets from the descriptor's base: every matrix read or written this way
-// spans less than BUF_LIMIT bytes (checked on the host where the launch
-// descriptors are built).
+// Raw buffer access (CDNA buffer descriptors: record count 2^31 - 1 bytes,
+// no stride, word 3 = 0x00020000, i.e. data format 32 bits, which untyped
+// buffer loads and stores need on this architecture family).  A load whose
+// offset is at or past the record count returns zero and such a store is
+// dropped, so elements outside a matrix are selected to BUF_OUT instead of
+// branched around.  Offsets are 32-bit byte offsets from the descriptor's
+// base: every matrix read or written this way spans less than BUF_LIMIT
+// bytes (checked on the host where the launch descriptors are built).
 #pragma once
 
 #include <hip/hip_runtime.h>
