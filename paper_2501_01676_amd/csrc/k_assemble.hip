@@ -19,17 +19,24 @@ namespace abddc {
 
 namespace {
 
-__device__ inline void shape(double s, double t, double u, int i, double hx, double hy, double hz,
+// Trilinear basis function i at reference point (s, t, u) of a box with
+// reciprocal edge lengths (ihx, ihy, ihz): value and physical gradient.
+// (+-1) / h equals +-(1 / h) exactly, so passing reciprocals changes no bit
+// against dividing here.
+__device__ inline void shape(double s, double t, double u, int i, double ihx, double ihy, double ihz,
                              double& phi, double& gx, double& gy, double& gz) {
   const int a = i & 1, b = (i >> 1) & 1, c = (i >> 2) & 1;
   const double fs = a ? s : 1.0 - s, ft = b ? t : 1.0 - t, fu = c ? u : 1.0 - u;
   phi = fs * ft * fu;
-  gx = (a ? 1.0 : -1.0) / hx * ft * fu;
-  gy = fs * (b ? 1.0 : -1.0) / hy * fu;
-  gz = fs * ft * (c ? 1.0 : -1.0) / hz;
+  gx = (a ? ihx : -ihx) * ft * fu;
+  gy = fs * (b ? ihy : -ihy) * fu;
+  gz = fs * ft * (c ? ihz : -ihz);
 }
 
 // One thread per (element, test function i): row i of A_K and F_K[i].
+// NODAL: the load is interpolated from nodal values (a separate instance, so
+// the constant-load one keeps its state in registers).
+template <bool NODAL>
 __global__ void elem_kernel(ElemParams P, const double* __restrict__ nu, const double* __restrict__ fnodal,
                             double* __restrict__ Ae, double* __restrict__ Fe) {
   const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -40,6 +47,7 @@ __global__ void elem_kernel(ElemParams P, const double* __restrict__ nu, const d
   const int ey = (int)((e / P.ne[0]) % P.ne[1]);
   const int ez = (int)(e / ((int64_t)P.ne[0] * P.ne[1]));
   const double hx = P.h[0], hy = P.h[1], hz = P.h[2];
+  const double ihx = 1.0 / hx, ihy = 1.0 / hy, ihz = 1.0 / hz;
   const double x0 = ex * hx, y0 = ey * hy, z0 = ez * hz;
   const double nue = nu[e];
   // |a|_K: maximum over the corners (|a| is convex for affine a)
@@ -55,48 +63,51 @@ __global__ void elem_kernel(ElemParams P, const double* __restrict__ nu, const d
   const double peclet = hK * amax / (2.0 * nue);
   const double CK = (peclet >= 1.0) ? P.tau * hK / (2.0 * amax) : P.tau * hK * hK / (4.0 * nue);
   const double ctil = P.c - 0.5 * (P.b1[0] + P.b1[4] + P.b1[8]);
-  int64_t nodes[8];
-  if (fnodal) {
-    for (int k = 0; k < 8; ++k)
-      nodes[k] = (ex + (k & 1)) + (int64_t)P.nn[0] * ((ey + ((k >> 1) & 1)) + (int64_t)P.nn[1] * (ez + ((k >> 2) & 1)));
-  }
-  const double qp[3] = {0.5 - 0.5 * sqrt(0.6), 0.5, 0.5 + 0.5 * sqrt(0.6)};
-  const double qw[3] = {5.0 / 18.0, 8.0 / 18.0, 5.0 / 18.0};
+  // 3-point Gauss rule per axis; the 27 points in one loop (s slowest, u
+  // fastest), not unrolled, and no indexed local arrays, so the thread's
+  // state stays in registers
+  const double q0 = 0.5 - 0.5 * sqrt(0.6), q2 = 0.5 + 0.5 * sqrt(0.6);
+  const double w0 = 5.0 / 18.0, w1 = 8.0 / 18.0;
   const double vol = hx * hy * hz;
   double row[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   double fi = 0.0;
-  for (int a = 0; a < 3; ++a)
-    for (int b = 0; b < 3; ++b)
-      for (int cq = 0; cq < 3; ++cq) {
-        const double s = qp[a], t = qp[b], u = qp[cq];
-        const double w = qw[a] * qw[b] * qw[cq] * vol;
-        const double xq = x0 + s * hx, yq = y0 + t * hy, zq = z0 + u * hz;
-        const double ax = P.b0[0] + P.b1[0] * xq + P.b1[1] * yq + P.b1[2] * zq;
-        const double ay = P.b0[1] + P.b1[3] * xq + P.b1[4] * yq + P.b1[5] * zq;
-        const double az = P.b0[2] + P.b1[6] * xq + P.b1[7] * yq + P.b1[8] * zq;
-        double phii, gix, giy, giz;
-        shape(s, t, u, i, hx, hy, hz, phii, gix, giy, giz);
-        const double agi = ax * gix + ay * giy + az * giz;
-        const double Li = agi + P.c * phii;
-        double fq = P.f_const;
-        if (fnodal) {
-          fq = 0.0;
-          for (int k = 0; k < 8; ++k) {
-            double pk, g1, g2, g3;
-            shape(s, t, u, k, hx, hy, hz, pk, g1, g2, g3);
-            fq += fnodal[nodes[k]] * pk;
-          }
-        }
-        for (int j = 0; j < 8; ++j) {
-          double phij, gjx, gjy, gjz;
-          shape(s, t, u, j, hx, hy, hz, phij, gjx, gjy, gjz);
-          const double agj = ax * gjx + ay * gjy + az * gjz;
-          const double Lj = agj + P.c * phij;
-          row[j] += w * (nue * (gix * gjx + giy * gjy + giz * gjz) + CK * Li * Lj + ctil * phii * phij +
-                         0.5 * (agj * phii - agi * phij));
-        }
-        fi += w * (fq * phii + CK * fq * Li);
+#pragma unroll 1
+  for (int qi = 0; qi < 27; ++qi) {
+    const int a = qi / 9, b = (qi / 3) % 3, cq = qi % 3;
+    const double s = a == 0 ? q0 : (a == 1 ? 0.5 : q2);
+    const double t = b == 0 ? q0 : (b == 1 ? 0.5 : q2);
+    const double u = cq == 0 ? q0 : (cq == 1 ? 0.5 : q2);
+    const double w = (a == 1 ? w1 : w0) * (b == 1 ? w1 : w0) * (cq == 1 ? w1 : w0) * vol;
+    const double xq = x0 + s * hx, yq = y0 + t * hy, zq = z0 + u * hz;
+    const double ax = P.b0[0] + P.b1[0] * xq + P.b1[1] * yq + P.b1[2] * zq;
+    const double ay = P.b0[1] + P.b1[3] * xq + P.b1[4] * yq + P.b1[5] * zq;
+    const double az = P.b0[2] + P.b1[6] * xq + P.b1[7] * yq + P.b1[8] * zq;
+    double phii, gix, giy, giz;
+    shape(s, t, u, i, ihx, ihy, ihz, phii, gix, giy, giz);
+    const double agi = ax * gix + ay * giy + az * giz;
+    const double Li = agi + P.c * phii;
+    double fq = P.f_const;
+    if constexpr (NODAL) {
+      fq = 0.0;
+      for (int k = 0; k < 8; ++k) {
+        double pk, g1, g2, g3;
+        shape(s, t, u, k, ihx, ihy, ihz, pk, g1, g2, g3);
+        const int64_t node =
+            (ex + (k & 1)) + (int64_t)P.nn[0] * ((ey + ((k >> 1) & 1)) + (int64_t)P.nn[1] * (ez + ((k >> 2) & 1)));
+        fq += fnodal[node] * pk;
       }
+    }
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      double phij, gjx, gjy, gjz;
+      shape(s, t, u, j, ihx, ihy, ihz, phij, gjx, gjy, gjz);
+      const double agj = ax * gjx + ay * gjy + az * gjz;
+      const double Lj = agj + P.c * phij;
+      row[j] += w * (nue * (gix * gjx + giy * gjy + giz * gjz) + CK * Li * Lj + ctil * phii * phij +
+                     0.5 * (agj * phii - agi * phij));
+    }
+    fi += w * (fq * phii + CK * fq * Li);
+  }
   for (int j = 0; j < 8; ++j) Ae[e * 64 + i * 8 + j] = row[j];
   Fe[e * 8 + i] = fi;
 }
@@ -148,17 +159,36 @@ __global__ void scatter_kernel(const SubAsm* __restrict__ subs, const int32_t* _
 
 // S^(i) = trailing block after eliminating the interior, g^(i) = trailing
 // rhs column, B^(i) = (S + S^T) / 2.
-__global__ void extract_kernel(const SubAsm* __restrict__ subs, const double* __restrict__ A,
-                               double* __restrict__ S, double* __restrict__ B, double* __restrict__ g) {
+__global__ void __launch_bounds__(256) extract_kernel(const SubAsm* __restrict__ subs, const double* __restrict__ A,
+                                                      double* __restrict__ S, double* __restrict__ B,
+                                                      double* __restrict__ g) {
+  // one 32 x 32 tile (I, J) of the trailing block per workgroup: tile (I, J)
+  // and its mirror (J, I) are read with unit-stride rows into LDS, so the
+  // transposed operand of B = (S + S^T) / 2 costs no strided global reads
+  __shared__ double Ta[32][33], Tb[32][33];
   const SubAsm d = subs[blockIdx.y];
-  const int nB = d.nloc - d.nI;
+  const int nB = d.nloc - d.nI, nt = (nB + 31) / 32;
+  if ((int)blockIdx.x >= nt * nt) return;
+  const int I = blockIdx.x / nt, J = blockIdx.x % nt;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
   const double* T = A + d.aoff + (int64_t)d.nI * d.ld + d.nI;
-  for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < nB * nB; idx += gridDim.x * blockDim.x) {
-    const int i = idx / nB, j = idx % nB;
-    const double sij = T[(int64_t)i * d.ld + j];
-    S[d.soff + idx] = sij;
-    B[d.soff + idx] = 0.5 * (sij + T[(int64_t)j * d.ld + i]);
-    if (j == 0) g[d.goff + i] = T[(int64_t)i * d.ld + nB];
+  for (int r = ty; r < 32; r += 8) {
+    const int i = I * 32 + r, j = J * 32 + tx, i2 = J * 32 + r, j2 = I * 32 + tx;
+    Ta[r][tx] = (i < nB && j < nB) ? T[(int64_t)i * d.ld + j] : 0.0;
+    Tb[r][tx] = (i2 < nB && j2 < nB) ? T[(int64_t)i2 * d.ld + j2] : 0.0;
+  }
+  __syncthreads();
+  for (int r = ty; r < 32; r += 8) {
+    const int i = I * 32 + r, j = J * 32 + tx;
+    if (i < nB && j < nB) {
+      const double sij = Ta[r][tx];
+      S[d.soff + (int64_t)i * nB + j] = sij;
+      B[d.soff + (int64_t)i * nB + j] = 0.5 * (sij + Tb[tx][r]);
+    }
+  }
+  if (J == 0 && ty == 0 && I * 32 + tx < nB) {
+    const int i = I * 32 + tx;
+    g[d.goff + i] = T[(int64_t)i * d.ld + nB];
   }
 }
 
@@ -265,7 +295,10 @@ void launch_check_positive(const double* v, int64_t n, int* flag, hipStream_t s)
 void launch_elem(const ElemParams& P, const double* nu, const double* fnodal, double* Ae, double* Fe,
                  hipStream_t s) {
   const int64_t n = P.n_elem * 8;
-  elem_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(P, nu, fnodal, Ae, Fe);
+  if (fnodal)
+    elem_kernel<true><<<(unsigned)((n + 255) / 256), 256, 0, s>>>(P, nu, fnodal, Ae, Fe);
+  else
+    elem_kernel<false><<<(unsigned)((n + 255) / 256), 256, 0, s>>>(P, nu, fnodal, Ae, Fe);
   ABDDC_HIP(hipGetLastError());
 }
 
@@ -279,8 +312,9 @@ void launch_scatter(const SubAsm* subs, const int32_t* rowsub, const int32_t* ln
 
 void launch_extract(const SubAsm* subs, int nsub, int max_nB, const double* A, double* S, double* B, double* g,
                     hipStream_t s) {
-  const int gx = std::min(1024, (max_nB * max_nB + 255) / 256);
-  extract_kernel<<<dim3(std::max(gx, 1), nsub), 256, 0, s>>>(subs, A, S, B, g);
+  const int nt = (max_nB + 31) / 32;
+  if (nt == 0 || nsub == 0) return;
+  extract_kernel<<<dim3(nt * nt, nsub), 256, 0, s>>>(subs, A, S, B, g);
   ABDDC_HIP(hipGetLastError());
 }
 

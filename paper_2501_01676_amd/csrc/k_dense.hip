@@ -507,33 +507,37 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) p
   }
 }
 
-// The leading k columns are factored in 64-column panels taken in pairs.
-// After the first panel of a pair, plu_band_kernel updates only what the
-// second one needs (its column strip and its row strip, depth 64); after the
-// second, plu_lead_kernel applies both panels at depth 128 to the rest of the
-// part still to be factored.  Every matrix entry of that part is thus read
-// and written once per 128 pivots rather than once per 64.
+// The leading k columns are factored in 64-column panels taken in groups of
+// G (two, or four when the batch's largest elimination has more than 512
+// pivots).  After each panel but the last of a group, plu_band_kernel
+// updates only what the next one needs (its column strip and its row strip)
+// with every pivot of the group so far; after the last, plu_lead_kernel
+// applies the whole group (depth 64 G) to the rest of the part still to be
+// factored.  Every matrix entry of that part is thus read and written once
+// per 64 G pivots rather than once per 64; the deeper groups move work into
+// the narrower band updates, which pays only when there are many panels.
 
-// Band update after panel [t0, s), s = t0 + b: rows [s, nrow) x cols
-// [s, s + w) and rows [s, s + w) x cols [s + w, ncol), w = min(NB, k - s).
+// Band update after panel [t0, s) of the group starting at g0, s = t0 + b,
+// with the pivots [g0, s): rows [s, nrow) x cols [s, s + w) and rows
+// [s, s + w) x cols [s + w, ncol), w = min(NB, k - s).
 // Tile t < ceil((nrow - s) / TILE) is a tile of the column strip, the rest
 // are tiles of the row strip.
 template <class T>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) plu_band_kernel(const PluDesc<T>* __restrict__ descs, int t0,
-                                                                                                       int tiles_per, int nb) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) plu_band_kernel(const PluDesc<T>* __restrict__ descs, int g0,
+                                                                                                       int t0, int tiles_per, int nb) {
   __shared__ T As[KC][LDS_PAD];
   __shared__ T Bs[KC][LDS_PAD];
   int z, t;
   if (!xcd_tile(tiles_per, nb, z, t)) return;
   const PluDesc<T> d = descs[z];
   if (t0 >= d.k) return;
-  const int b = min(NB, d.k - t0), s0 = t0 + b;
+  const int s0 = t0 + min(NB, d.k - t0), b = s0 - g0;   // pivots [g0, s0) of the group so far
   if (s0 >= d.k) return;
   const int w = min(NB, d.k - s0);
   const int mr = d.nrow - s0, nc = d.ncol - s0;
   const int rtl = (mr + TILE - 1) / TILE;
-  const T* A21 = d.a + (size_t)s0 * d.ld + t0;
-  const T* A12 = d.a + (size_t)t0 * d.ld + s0;
+  const T* A21 = d.a + (size_t)s0 * d.ld + g0;
+  const T* A12 = d.a + (size_t)g0 * d.ld + s0;
   T* A22 = d.a + (size_t)s0 * d.ld + s0;
   if (t < rtl) {
     // the next diagonal block [0, w)^2 is updated by the next panel's diag kernel
@@ -704,6 +708,7 @@ void partial_lu(const std::vector<PluDesc<T>>& descs_in, int* dflag, hipStream_t
   // the triangular solves of panel t0 and beside the band / lead launch of
   // that panel (which leaves its block to it); the next solves wait for it.
   SideStream& side = SideStream::for_stream(s);
+  const int grp = maxk > 512 ? 4 : 2;   // panels per group
   plu_diag_kernel<T><<<nb, 256, 0, s>>>(dd, 0, 0, scr, dflag);
   for (int t0 = 0; t0 < maxk; t0 += NB) {
     const int rem = std::max(maxr, maxc) - t0;
@@ -711,27 +716,28 @@ void partial_lu(const std::vector<PluDesc<T>>& descs_in, int* dflag, hipStream_t
     if (t0 > 0) ABDDC_HIP(hipStreamWaitEvent(s, side.done, 0));
     plu_trsm_kernel<T><<<xcd_grid(std::max(tiles, 1), nb), 256, 0, s>>>(dd, t0, scr, std::max(tiles, 1), nb);
     if (t0 + NB < maxk) {
-      // the next diagonal block: this panel's columns (and, after the second
-      // panel of a pair, the first one's too) applied in the diag kernel
-      const int u0 = (t0 / NB) % 2 == 0 ? t0 : t0 - NB;
+      // the next diagonal block: the pivot columns of this panel's group so
+      // far, applied in the diag kernel
+      const int u0 = t0 - ((t0 / NB) % grp) * NB;   // start of this panel's group
       ABDDC_HIP(hipEventRecord(side.ready, s));
       ABDDC_HIP(hipStreamWaitEvent(side.s, side.ready, 0));
       plu_diag_kernel<T><<<nb, 256, 0, side.s>>>(dd, t0 + NB, u0, scr, dflag);
       ABDDC_HIP(hipEventRecord(side.done, side.s));
     }
-    if ((t0 / NB) % 2 == 0) {
-      // first panel of a pair: the band the second panel needs
+    const int g0 = t0 - ((t0 / NB) % grp) * NB;
+    if ((t0 / NB) % grp != grp - 1) {
+      // not the last panel of its group: the band the next panel needs
       if (t0 + NB < maxk) {
         const int sb = t0 + NB;
         // column strip tiles + row strip tiles (the row strip starts at
         // column w >= 1 of the trailing part, so it spans < maxc - sb columns)
         const int bt = (maxr - sb + TILE - 1) / TILE + std::max(0, (maxc - sb - 1 + TILE - 1) / TILE);
-        if (bt > 0) plu_band_kernel<T><<<xcd_grid(bt, nb), 256, 0, s>>>(dd, t0, bt, nb);
+        if (bt > 0) plu_band_kernel<T><<<xcd_grid(bt, nb), 256, 0, s>>>(dd, g0, t0, bt, nb);
       }
       continue;
     }
-    // second panel of a pair: both panels, depth 2 NB
-    const int p0 = t0 - NB, sp = p0 + 2 * NB;
+    // last panel of a group: all its panels, depth grp NB
+    const int p0 = g0, sp = p0 + grp * NB;
     const int rt = (maxr - sp + TILE - 1) / TILE, ct = (maxc - sp + TILE - 1) / TILE;
     if (sp < maxk && rt > 0 && ct > 0) {
       hipEvent_t ea = nullptr, eb = nullptr;
@@ -739,12 +745,12 @@ void partial_lu(const std::vector<PluDesc<T>>& descs_in, int* dflag, hipStream_t
         double flops = 0.0;  // rows [s, nrow) x cols [s, k) and rows [s, k) x cols [k, ncol), depth b
         for (auto& d : descs)
           if (sp < d.k) {
-            flops += 2.0 * (2 * NB) * ((double)(d.nrow - sp) * (d.k - sp) + (double)(d.k - sp) * (d.ncol - d.k));
+            flops += 2.0 * (grp * NB) * ((double)(d.nrow - sp) * (d.k - sp) + (double)(d.k - sp) * (d.ncol - d.k));
           }
         tracked_events(KC_PLU_LEAD, flops, &ea, &eb);
       }
       hipExtLaunchKernelGGL(plu_lead_kernel<T>, dim3(xcd_grid(rt * ct, nb)), dim3(256), 0, s, ea, eb, 0, dd, p0,
-                            2 * NB, rt, ct, nb);
+                            grp * NB, rt, ct, nb);
     }
   }
   // trailing Schur complement with K = k
