@@ -89,6 +89,26 @@ def test_partial_lu_large_batch():
         assert np.abs(o[k:, k:] - r).max() <= 1e-11 * max(1.0, np.abs(r).max())
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_partial_lu_long_eliminations(precision):
+    """Batches whose longest elimination exceeds 512 pivots take the panels in
+    groups of four (band updates at depth 64, 128, 192, lead at 256): a ragged
+    batch with k on both sides of group and panel boundaries, against numpy."""
+    api = _api()
+    rng = np.random.default_rng(9)
+    shapes = [(700, 705, 600), (650, 650, 513), (600, 610, 257), (300, 300, 256), (200, 205, 65), (90, 90, 1)]
+    mats, ks, refs = [], [], []
+    for n, m, k in shapes:
+        M = rng.standard_normal((n, m))
+        M[:k, :k] = _posreal(k, rng)
+        mats.append(M); ks.append(k)
+        refs.append(M[k:, k:] - M[k:, :k] @ np.linalg.solve(M[:k, :k], M[:k, k:]))
+    out = api.partial_lu(mats, ks, precision)
+    tol = 1e-11 if precision == 0 else 2e-3
+    for o, k, r in zip(out, ks, refs):
+        assert np.abs(o[k:, k:] - r).max() <= tol * max(1.0, np.abs(r).max())
+
+
 def test_partial_lu_inverse_trick():
     """Schur complement of [[A, I], [-I, 0]] onto the trailing block is A^{-1}."""
     api = _api()
