@@ -508,8 +508,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) p
 }
 
 // The leading k columns are factored in 64-column panels taken in groups of
-// G (two, or four when the batch's largest elimination has more than 512
-// pivots).  After each panel but the last of a group, plu_band_kernel
+// G (two; three when the batch's longest elimination has 257 to 512 pivots,
+// four above 512).  After each panel but the last of a group, plu_band_kernel
 // updates only what the next one needs (its column strip and its row strip)
 // with every pivot of the group so far; after the last, plu_lead_kernel
 // applies the whole group (depth 64 G) to the rest of the part still to be
@@ -708,7 +708,7 @@ void partial_lu(const std::vector<PluDesc<T>>& descs_in, int* dflag, hipStream_t
   // the triangular solves of panel t0 and beside the band / lead launch of
   // that panel (which leaves its block to it); the next solves wait for it.
   SideStream& side = SideStream::for_stream(s);
-  const int grp = maxk > 512 ? 4 : 2;   // panels per group
+  const int grp = maxk > 512 ? 4 : (maxk > 256 ? 3 : 2);   // panels per group
   plu_diag_kernel<T><<<nb, 256, 0, s>>>(dd, 0, 0, scr, dflag);
   for (int t0 = 0; t0 < maxk; t0 += NB) {
     const int rem = std::max(maxr, maxc) - t0;
