@@ -395,3 +395,80 @@ def test_options_variants_run():
     for opts in ({"edge_h_mode": "separate"}, {"deluxe_source": "B"}):
         o, info = bddc.solve(p, dict(LOOSE, **opts), rtol=1e-10)
         assert info["relres_true"] <= 1e-10
+
+
+# ------------------------------------------------------------- deluxe weights
+def _schur_by_inverse(p, o):
+    """S^(k) formed apart from the oracle's elimination, from the local
+    matrices of the finite-element assembly: by the block-inverse formula
+    the boundary block of (A^(k))^{-1} is (S^(k))^{-1}; a floating subdomain
+    (A^(k) singular) takes A_BB - A_BI A_II^{-1} A_IB with an LU of A_II."""
+    from scipy.linalg import lu_factor, lu_solve
+    local = fem.assemble_subdomains(p, o.topo, 3)
+    out = []
+    for s, (Al, _) in enumerate(local):
+        nI = o.topo.sub[s]["nI"]
+        if np.linalg.cond(Al) < 1e12:
+            out.append(np.linalg.inv(np.linalg.inv(Al)[nI:, nI:]))
+        else:
+            X = lu_solve(lu_factor(Al[:nI, :nI]), Al[:nI, nI:])
+            out.append(Al[nI:, nI:] - Al[nI:, :nI] @ X)
+    return out
+
+
+def _obj_block(M, o, s, k):
+    loc = o.topo.sub[s]["obj_local"][k]
+    return M[np.ix_(loc, loc)]
+
+
+@pytest.mark.parametrize("nsub,hh", [(2, 4), (3, 3)])
+def test_deluxe_average_minimises_weighted_jump(nsub, hh):
+    """Deluxe scaling (Section 3) with a = 0: every S^(k) is symmetric and
+    S_XX^(k) positive definite, and the deluxe average
+    what = sum_k D_X^(k) w_k is the unique minimiser of
+    sum_k (w_k - what)^T S_XX^(k) (w_k - what).  The minimiser is found here
+    as a least-squares problem with the Cholesky factors of the blocks, on
+    random w_k, for every face and edge (two and four subdomains)."""
+    p = W.random_field(nsub, hh, 11, lo=-2, hi=1, beta=(0.0, 0.0, 0.0))
+    o = _setup(p, {"theta_face": 10.0, "theta_edge": 10.0})
+    S = _schur_by_inverse(p, o)
+    rng = np.random.default_rng(5)
+    checked = 0
+    for k, obj in enumerate(o.topo.objects):
+        if obj["kind"] == "vertex":
+            continue
+        subs = list(obj["subs"])
+        n = obj["nodes"].size
+        blocks = [_obj_block(S[s], o, s, k) for s in subs]
+        w = [rng.standard_normal(n) for _ in subs]
+        C = [np.linalg.cholesky(0.5 * (b + b.T)).T for b in blocks]      # S_XX^(k) = C^T C
+        lhs = np.concatenate(C, axis=0)
+        rhs = np.concatenate([c @ wk for c, wk in zip(C, w)])
+        wmin = np.linalg.lstsq(lhs, rhs, rcond=None)[0]
+        what = sum(o.D[(k, s)] @ wk for s, wk in zip(subs, w))
+        assert np.linalg.norm(what - wmin) <= 1e-10 * np.linalg.norm(wmin), (obj["kind"], k)
+        checked += 1
+    assert checked == len(o.topo.faces) + len(o.topo.edges)
+
+
+@pytest.mark.parametrize("source", ["S", "B"])
+def test_deluxe_weight_equation_nonsymmetric(source):
+    """Deluxe scaling (Section 3) with a != 0: D_X^(k) solves
+    (sum_j M_XX^(j)) D_X^(k) = M_XX^(k) with M = S^(j) (nonsymmetric) or
+    M = B^(j) = sym S^(j), the blocks taken from Schur complements formed
+    apart from the oracle (block-inverse formula); faces and edges."""
+    p = W.random_field(2, 4, 13, lo=-2, hi=0, beta=(3.0, -2.0, 1.5))
+    o = _setup(p, {"theta_face": 10.0, "theta_edge": 10.0, "deluxe_source": source})
+    S = _schur_by_inverse(p, o)
+    M = S if source == "S" else [0.5 * (s + s.T) for s in S]
+    for k, obj in enumerate(o.topo.objects):
+        if obj["kind"] == "vertex":
+            continue
+        subs = list(obj["subs"])
+        blocks = [_obj_block(M[s], o, s, k) for s in subs]
+        tot = sum(blocks)
+        asym = max(np.abs(b - b.T).max() / np.abs(b).max() for b in blocks)
+        if source == "S":
+            assert asym > 1e-6     # the blocks are genuinely nonsymmetric here
+        for s, blk in zip(subs, blocks):
+            assert np.abs(tot @ o.D[(k, s)] - blk).max() <= 1e-11 * np.abs(blk).max(), (obj["kind"], k, s)
