@@ -154,6 +154,26 @@ def test_solution(pairs, name):
     assert np.allclose(h[:m], href[:m], rtol=1e-6, atol=1e-14)
 
 
+@pytest.mark.parametrize("name", ["config2", "layered_loose", "ragged_loose"])
+def test_solution_restarted(pairs, name):
+    """GMRES(5): several restart cycles (true residual, new Krylov basis from
+    it) against the oracle's restarted GMRES on the same operators: the same
+    iteration and restart counts (+-1 at a threshold crossing), the same
+    residual history, the solution within 1e-10."""
+    p, o, g = pairs[name]
+    u_ref, info_ref = o.gmres_solve(restart=5, rtol=1e-8, maxit=300)
+    u, info = g.gmres_solve(restart=5, rtol=1e-8, maxit=300)
+    u = u.cpu().numpy()
+    assert info["converged"] and info["relres_true"] <= 1e-8
+    assert info_ref["restarts"] >= 1
+    assert abs(info["iters"] - info_ref["iters"]) <= 1
+    assert abs(info["restarts"] - info_ref["restarts"]) <= 1
+    h, href = info["history"], np.array(info_ref["history"])
+    m = min(len(h), len(href))
+    assert np.allclose(h[:m], href[:m], rtol=1e-6, atol=1e-14)
+    assert np.linalg.norm(u - u_ref) <= 1e-10 * np.linalg.norm(u_ref)
+
+
 @pytest.mark.parametrize("name", ["config1b", "layered_loose", "config2", "wide_ragged"])
 def test_mixed_precision_solution(pairs, name):
     """FP32 local constrained factorisation and FP32 apply operators inside
