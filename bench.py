@@ -7,12 +7,16 @@ and edge eigenproblems, change of basis, local factorisations, coarse
 inverse) + abddc_gmres_solve (BDDC-preconditioned GMRES(30) + interior
 recovery), with the coefficient arrays already resident in HBM.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--config config2]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--config config3]
 
-Prints one JSON line.  `roofline` is the dominant tracked kernel, timed live
-with HIP events around each of its launches on the library stream.
+Prints one JSON line.  `roofline` is the tracked kernel class with the
+largest device time per solve, timed live with HIP events that each launch
+of the class is stamped with on its stream.  `local_solve_tflops` is the
+algorithmic FP64 work of the local Schur complements (S2) and the local
+constrained factorisations (S10) over the device time of those two phases.
 `cpu_baseline` is the FP64 CPU oracle (test infrastructure) timed on the
-host on a bounded sample of the same workload.
+host: the whole solve of the same workload with every BLAS thread, and a
+one-thread figure from a bounded sample.
 """
 from __future__ import annotations
 
@@ -31,7 +35,8 @@ PEAK_FP64_TFLOPS = 78.6     # MI355X dense FP64 (vector and matrix)
 PEAK_HBM_GBS = 8000.0       # MI355X HBM3E
 
 # live-timed kernel classes of the library: class -> (kernel, roofline bound)
-TRACKED = {0: ("plu_update_kernel<T>", "mfma"), 1: ("gemv_kernel<T>", "hbm"), 2: ("plu_lead_kernel<T>", "mfma")}
+TRACKED = {0: ("plu_update_kernel<T>", "mfma"), 1: ("gemv_kernel<T>", "hbm"), 2: ("plu_lead_kernel<T>", "mfma"),
+           3: ("plu_diag_kernel<T>", "mfma"), 4: ("plu_trsm_kernel<T>", "mfma"), 5: ("plu_band_kernel<T>", "mfma")}
 
 DESCRIPTIONS = {
     "config1a": "2x2x2 subdomains, H/h=4 (8^3 Q1 elements), nu=1, a=(1,1,1), f=1",
@@ -49,7 +54,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", default="config2", choices=sorted(DESCRIPTIONS))
+    ap.add_argument("--config", default="config3", choices=sorted(DESCRIPTIONS))
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--theta", type=float, default=10.0)
     ap.add_argument("--restart", type=int, default=30)
@@ -68,23 +73,48 @@ def parse():
     return ap.parse_args()
 
 
-def cpu_baseline(problem, opts, args):
-    """Time the FP64 oracle on the host (same problem, same options)."""
-    from oracle import bddc
+def _cpu_model():
     try:
-        from threadpoolctl import threadpool_info
-        threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
-    except Exception:
-        threads = os.cpu_count() or 1
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _oracle_solve(problem, opts, args):
+    from oracle import bddc
     t0 = time.perf_counter()
     o = bddc.OracleBDDC(problem)
     o.assemble()
     o.setup_coarse_space({"theta_face": opts["theta_face"], "theta_edge": opts["theta_edge"]})
     _, info = o.gmres_solve(args.restart, args.rtol, args.maxit)
-    dt = time.perf_counter() - t0
-    return {"value": dt, "unit": "s", "cores": int(threads), "kind": "oracle",
-            "sample": f"whole {args.config} solve (assemble + setup + GMRES + recovery), numpy/scipy FP64 oracle, "
-                      f"{info['iters']} iterations, counts {o.counts}"}
+    return time.perf_counter() - t0, info, o.counts
+
+
+def cpu_baseline(problem, opts, args):
+    """Time the FP64 oracle on the host: the whole solve of the benchmark
+    problem with every BLAS thread, and again with one BLAS thread (the
+    oracle's own loops are single-threaded either way)."""
+    try:
+        from threadpoolctl import threadpool_info, threadpool_limits
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    except Exception:
+        threadpool_limits = None
+        threads = os.cpu_count() or 1
+    dt, info, counts = _oracle_solve(problem, opts, args)
+    out = {"value": dt, "unit": "s", "cores": int(threads), "kind": "oracle", "cpu_model": _cpu_model(),
+           "host_cpus": os.cpu_count(),
+           "sample": f"whole {args.config} solve (assemble + setup + GMRES + recovery), numpy/scipy FP64 oracle, "
+                     f"{threads} BLAS threads, {info['iters']} iterations, counts {counts}"}
+    if threadpool_limits is not None:
+        with threadpool_limits(limits=1):
+            dt1, info1, _ = _oracle_solve(problem, opts, args)
+        out["single_thread"] = {"value": dt1, "unit": "s", "cores": 1,
+                                "sample": f"whole {args.config} solve at 1 BLAS thread ({info1['iters']} iterations)"}
+    return out
 
 
 def train_network(args, opts):
@@ -132,6 +162,20 @@ def train_network(args, opts):
             "loss_first": first, "loss_last": last, "exact_iters": rinfo["iters"], "exact_counts": rc}
 
 
+def local_solve_flops(solver):
+    """Algorithmic FP64 flops of the local Schur complements (S2: LU of
+    A_II, the solves for [A_IB | f_I], the product A_BI X) and of the local
+    constrained factorisations (S10: LU of Sbar_DD, Phi, Psi, S_Pi^(i)),
+    from the per-subdomain sizes n_I, n_B, n_Pi (n_D = n_B - n_Pi)."""
+    s2 = s10 = 0.0
+    for i in range(solver.n_sub):
+        nI, nB, nP = (float(v) for v in solver.stage(8, i))
+        nD = nB - nP
+        s2 += 2.0 / 3.0 * nI ** 3 + 2.0 * nI ** 2 * (nB + 1) + 2.0 * nB * nI * (nB + 1)
+        s10 += 2.0 / 3.0 * nD ** 3 + 4.0 * nD ** 2 * nP + 2.0 * nP ** 2 * nD
+    return s2, s10
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -154,7 +198,7 @@ def main():
         learned = train_network(args, opts)
         opts = dict(opts, constraint_source=1, mlp=learned["net"])
 
-    def step():
+    def step(want_flops=False):
         ta = time.perf_counter()
         s = api.Solver(dev_problem)
         tb = time.perf_counter()
@@ -164,15 +208,17 @@ def main():
         td = time.perf_counter()
         ks = {k: s.kernel_stats(k) for k in TRACKED}
         ph = s.phase_times()
+        flops = local_solve_flops(s) if want_flops else None
         if learned is not None:
             info["learned"] = s.learned_stats()
         sizes = (s.n_sub, s.n_dof, s.n_gamma)
         s.close()
         te = time.perf_counter()
-        return counts, info, ks, ph, sizes, (tb - ta, tc - tb, td - tc, te - td)
+        return counts, info, ks, ph, sizes, (tb - ta, tc - tb, td - tc, te - td), flops
 
+    flops = None
     for _ in range(args.warmup):
-        step()
+        flops = step(want_flops=flops is None)[6] or flops
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     recs = [step() for _ in range(args.steps)]
@@ -180,7 +226,9 @@ def main():
     t1 = time.perf_counter()
     per_step = (t1 - t0) / args.steps
 
-    counts, info, _, _, sizes, _ = recs[-1]
+    counts, info, _, _, sizes, _, _ = recs[-1]
+    if flops is None:
+        flops = step(want_flops=True)[6]   # untimed
     ok = all(r[1]["converged"] and r[1]["relres_true"] <= args.rtol for r in recs)
     elt = "double" if args.precision == 0 else "double|float"
     tracked = {}
@@ -201,10 +249,13 @@ def main():
         v["traffic"] = profiling.read_traffic(kname, args.config)
     dom = max(tracked, key=lambda k: tracked[k]["seconds_per_step"])
     roofline = dict(kernel=dom, **tracked[dom])
-    tflops = sum(v["work_per_launch"] * v["launches_per_step"] for v in tracked.values() if v["bound"] == "mfma")
-    tsec = sum(v["seconds_per_step"] for v in tracked.values() if v["bound"] == "mfma")
-    tflops = tflops / tsec / 1e12 if tsec > 0 else 0.0
+    upd = [v for k, v in tracked.items() if k.startswith(("plu_update", "plu_lead"))]
+    usec = sum(v["seconds_per_step"] for v in upd)
+    update_tflops = sum(v["work_per_launch"] * v["launches_per_step"] for v in upd) / usec / 1e12 if usec else 0.0
     phases = np.mean([r[3] for r in recs], axis=0)
+    s2, s10 = flops
+    t_local = phases[1] + phases[5]
+    tflops = (s2 + s10) / t_local / 1e12 if t_local > 0 else 0.0
     walls = np.mean([r[5] for r in recs], axis=0)
     names = ["assemble", "local_schur", "deluxe", "faces", "edges", "local_factors", "coarse", "gmres", "recover"]
 
@@ -225,6 +276,8 @@ def main():
                                f"GMRES({args.restart}) rtol {args.rtol:g}",
                    "seed": args.seed, "n_sub": sizes[0], "n_dof": sizes[1], "n_gamma": sizes[2]},
         "local_solve_tflops": tflops,
+        "local_solve_gflop": {"S2": s2 / 1e9, "S10": s10 / 1e9},
+        "mfma_update_tflops": update_tflops,
         "iters": info["iters"],
         "relres_true": info["relres_true"],
         "converged": ok,

@@ -35,8 +35,9 @@
  *  - Vectors passed to apply/solve (r, z, x, y, u) are DEVICE pointers of
  *    the context's device, read and written in stream order on the stream
  *    given at assemble time; the caller owns them.
- *  - The library owns all other device memory (allocated at assemble/setup,
- *    released by abddc_destroy).
+ *  - All other device memory belongs to the library (allocated at assemble,
+ *    setup and solve, released by abddc_destroy), taken from the caller's
+ *    allocation hooks when abddc_device provides them.
  *  - Vector layouts: the interface vector (length n_gamma) lists all faces,
  *    then all edges, then all vertices; objects of one kind by increasing
  *    smallest grid-node id; the nodes of an object by increasing node id.
@@ -67,11 +68,28 @@ enum {
   ABDDC_ESTATE = -6        /* entry point called out of order                   */
 };
 
-/* Device binding: which GPU and which HIP stream (hipStream_t) to use.
- * stream may be NULL for the default stream. */
+/* Device binding: which GPU, which HIP stream (hipStream_t) to use, and
+ * optionally the caller's device memory.  stream may be NULL for the default
+ * stream.  alloc / free / user: when alloc is set, every device allocation
+ * the library makes for the context (or network) created with this binding
+ * -- its persistent buffers and the temporaries of each call -- is
+ * alloc(bytes, user) and is returned by free(p, user); alloc and free must
+ * both be set or both be NULL (NULL: the library's own caching allocator).
+ * alloc must return memory of the binding's device, aligned to 256 bytes,
+ * usable by work queued on the stream after it returns (NULL for failure:
+ * the call then fails with ABDDC_ENOMEM).  free is called once the last
+ * work using p has been queued on the stream; the allocator may hand p out
+ * again for work queued later on that stream (stream-ordered reuse, as a
+ * caching allocator that tags blocks with their stream does).  Both are
+ * called on the thread of the entry point, never concurrently for one
+ * context.  Pinned host memory (descriptor and upload rings) and the
+ * primitive test hooks' work space still come from the library. */
 typedef struct {
   int32_t device;
   void* stream;
+  void* (*alloc)(size_t bytes, void* user);
+  void (*free)(void* p, void* user);
+  void* user;
 } abddc_device;
 
 /* The model problem of Section 2 on a box split into box subdomains.
@@ -176,7 +194,10 @@ int abddc_query(const abddc_ctx* ctx, int64_t* n_dof, int64_t* n_gamma, int32_t*
  *   ABDDC_STAGE_FACE_BASIS [Q_F | Q_F^perp] of face index, n_F x n_F row-major
  *   ABDDC_STAGE_EDGE_BASIS [Q_E | Q_E^perp] of edge index, n_E x n_E row-major
  *   ABDDC_STAGE_COUNTS     per face p_F then per edge r_E (as doubles)
- *   ABDDC_STAGE_DELUXE     D of object index/8, member index%8 of n(X) */
+ *   ABDDC_STAGE_DELUXE     D of object index/8, member index%8 of n(X)
+ *   ABDDC_STAGE_SUB_SIZES  n_I, n_B, n_Pi of subdomain index (interior,
+ *                          interface and primal unknowns; n_Pi is 0 before
+ *                          the coarse-space setup) */
 enum {
   ABDDC_STAGE_SCHUR = 0,
   ABDDC_STAGE_LOCAL_RHS = 1,
@@ -185,7 +206,8 @@ enum {
   ABDDC_STAGE_FACE_BASIS = 4,
   ABDDC_STAGE_EDGE_BASIS = 5,
   ABDDC_STAGE_COUNTS = 6,
-  ABDDC_STAGE_DELUXE = 7
+  ABDDC_STAGE_DELUXE = 7,
+  ABDDC_STAGE_SUB_SIZES = 8
 };
 int64_t abddc_get_stage(abddc_ctx* ctx, int32_t stage, int32_t index, double* buf, int64_t cap);
 
@@ -202,14 +224,34 @@ int abddc_phase_times(const abddc_ctx* ctx, double* t, int32_t n);
  *                           2 m n k)
  *   ABDDC_KSTAT_GEMV        batched GEMV of M^{-1} and Shat (work =
  *                           algorithmic bytes: matrix + gathered input + output)
- *   ABDDC_KSTAT_PLU_LEAD    per-panel MFMA update of the still-to-be-factored
+ *   ABDDC_KSTAT_PLU_LEAD    per-group MFMA update of the still-to-be-factored
  *                           rows and columns of the blocked partial LU
- *                           (work = algorithmic flops, 2 m n 64)
+ *                           (work = algorithmic flops, 2 m n depth)
+ *   ABDDC_KSTAT_PLU_DIAG    LU of the 64 x 64 diagonal blocks with their
+ *                           lookahead update (work = 2/3 b^3 + 2 b^2 depth)
+ *   ABDDC_KSTAT_PLU_TRSM    triangular solves of each panel's row and column
+ *                           strips (work = b^2 per strip row / column)
+ *   ABDDC_KSTAT_PLU_BAND    update of the next panel's strips inside a panel
+ *                           group (work = algorithmic flops, 2 m n depth)
  * Any output pointer may be NULL. */
-enum { ABDDC_KSTAT_PLU_UPDATE = 0, ABDDC_KSTAT_GEMV = 1, ABDDC_KSTAT_PLU_LEAD = 2 };
+enum {
+  ABDDC_KSTAT_PLU_UPDATE = 0,
+  ABDDC_KSTAT_GEMV = 1,
+  ABDDC_KSTAT_PLU_LEAD = 2,
+  ABDDC_KSTAT_PLU_DIAG = 3,
+  ABDDC_KSTAT_PLU_TRSM = 4,
+  ABDDC_KSTAT_PLU_BAND = 5
+};
 int abddc_kernel_stats(abddc_ctx* ctx, int32_t kernel, double* seconds, int64_t* launches, double* work);
 
 void abddc_destroy(abddc_ctx* ctx);
+
+/* Allocations the library's own caching device allocator has served on a
+ * device since the process started (count and bytes requested), for
+ * checking that a binding with allocation hooks routes every allocation
+ * through them.  Either pointer may be NULL; EINVAL for device < 0 or
+ * >= 64. */
+int abddc_cache_stats(int32_t device, int64_t* allocations, int64_t* bytes);
 
 /* Thread-local message of the last failed call on this thread ("" if none). */
 const char* abddc_last_error(void);

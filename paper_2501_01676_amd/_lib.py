@@ -18,8 +18,15 @@ STAGE_FACE_BASIS, STAGE_EDGE_BASIS, STAGE_COUNTS, STAGE_DELUXE = 4, 5, 6, 7
 MLP_FEATURES, MLP_OUTPUTS, MLP_PARAMS = 133, 28, 37276
 
 
+# abddc_device allocation hooks: void* alloc(size_t bytes, void* user),
+# void free(void* p, void* user)
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+
+
 class Device(C.Structure):
-    _fields_ = [("device", C.c_int32), ("stream", C.c_void_p)]
+    _fields_ = [("device", C.c_int32), ("stream", C.c_void_p), ("alloc", ALLOC_FN), ("free", FREE_FN),
+                ("user", C.c_void_p)]
 
 
 class Problem(C.Structure):
@@ -76,6 +83,7 @@ SIGNATURES = {
     "abddc_assemble": (C.c_int, [C.POINTER(Problem), C.POINTER(Device), C.POINTER(_P)]),
     "abddc_setup_coarse_space": (C.c_int, [_P, C.POINTER(Options), C.POINTER(Counts)]),
     "abddc_apply_bddc": (C.c_int, [_P, _P, _P]),
+    "abddc_cache_stats": (C.c_int, [C.c_int32, _I64P, _I64P]),
     "abddc_apply_schur": (C.c_int, [_P, _P, _P]),
     "abddc_get_rhs": (C.c_int, [_P, _P]),
     "abddc_gmres_solve": (C.c_int, [_P, C.c_int32, C.c_double, C.c_int32, _P, C.POINTER(SolveInfo)]),

@@ -36,14 +36,55 @@ def _dptr(t):
     return C.c_void_p(t.data_ptr())
 
 
-class Solver:
-    """One assembled problem on one GPU (abddc_ctx)."""
+class TorchAllocator:
+    """Device allocation hooks of abddc_device backed by torch's caching
+    allocator on one stream (blocks are reused in that stream's order).
+    Counts the library's calls and the bytes it holds."""
 
-    def __init__(self, problem, device=0, stream=None):
+    def __init__(self, device, stream):
+        self.device, self.stream = device, stream
+        self.n_alloc = self.n_free = 0
+        self.bytes_total = 0
+        self.live = {}
+
+        def _alloc(nbytes, user):
+            try:
+                p = torch.cuda.caching_allocator_alloc(int(nbytes), self.device, self.stream)
+            except Exception:   # out of memory: the library reports ENOMEM
+                return None
+            self.n_alloc += 1
+            self.bytes_total += int(nbytes)
+            self.live[int(p)] = int(nbytes)
+            return p
+
+        def _free(p, user):
+            self.n_free += 1
+            self.live.pop(int(p), None)
+            torch.cuda.caching_allocator_delete(int(p))
+
+        # the C function pointers must live as long as any buffer they made
+        self.alloc_fn = L.ALLOC_FN(_alloc)
+        self.free_fn = L.FREE_FN(_free)
+
+    def bind(self, dev):
+        dev.alloc = self.alloc_fn
+        dev.free = self.free_fn
+        return dev
+
+
+class Solver:
+    """One assembled problem on one GPU (abddc_ctx).  allocator: None (the
+    library's caching allocator), "torch" (torch's caching allocator on the
+    solver's stream) or a TorchAllocator."""
+
+    def __init__(self, problem, device=0, stream=None, allocator=None):
         self.lib = L.load()
         self.device = device
         torch.cuda.set_device(device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(device)
+        if allocator == "torch":
+            allocator = TorchAllocator(device, self.stream)
+        self.allocator = allocator
         p = L.Problem()
         self._keep = []
         for a in range(3):
@@ -79,6 +120,8 @@ class Solver:
         p.c = float(problem["c"])
         p.tau = float(problem["tau"])
         dev = L.Device(device, _stream_handle(self.stream))
+        if allocator is not None:
+            allocator.bind(dev)
         ctx = C.c_void_p()
         L.check(self.lib.abddc_assemble(C.byref(p), C.byref(dev), C.byref(ctx)))
         self.ctx = ctx
@@ -172,7 +215,8 @@ class Solver:
     def kernel_stats(self, kernel):
         """(seconds, launches, work) accumulated for a tracked kernel class
         (0: partial-LU trailing Schur product, flops; 1: batched GEMV, bytes;
-        2: partial-LU per-panel update, flops)."""
+        2: partial-LU per-group update, flops; 3: diagonal-block LU, flops;
+        4: panel triangular solves, flops; 5: in-group band update, flops)."""
         sec, n, w = C.c_double(), C.c_int64(), C.c_double()
         L.check(self.lib.abddc_kernel_stats(self.ctx, kernel, C.byref(sec), C.byref(n), C.byref(w)))
         return sec.value, n.value, w.value

@@ -1,6 +1,7 @@
 // C ABI: error reporting and the batched-primitive test hooks.
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cstring>
 #include <map>
 #include <unordered_map>
@@ -24,6 +25,15 @@ int fail(int code, const std::string& msg) {
 }  // namespace abddc
 
 namespace abddc {
+thread_local const DevAlloc* g_dev_alloc = nullptr;
+
+void* hooked_alloc(const DevAlloc& h, size_t bytes) {
+  void* p = h.alloc(bytes, h.user);
+  if (!p) throw Error(ABDDC_ENOMEM, "the caller's device allocation hook returned NULL for " +
+                                        std::to_string(bytes) + " bytes");
+  return p;
+}
+
 thread_local hipStream_t g_stream = nullptr;
 thread_local bool g_stream_idle = false;
 
@@ -44,6 +54,16 @@ struct Cache {
 Cache& cache() {
   static Cache* c = new Cache();  // intentionally never destroyed
   return *c;
+}
+// allocations served by the cache per device since the process started
+constexpr int STAT_DEVICES = 64;
+std::atomic<int64_t> g_cache_allocs[STAT_DEVICES];
+std::atomic<int64_t> g_cache_bytes[STAT_DEVICES];
+void count_alloc(int dev, size_t bytes) {
+  if (dev >= 0 && dev < STAT_DEVICES) {
+    g_cache_allocs[dev].fetch_add(1, std::memory_order_relaxed);
+    g_cache_bytes[dev].fetch_add((int64_t)bytes, std::memory_order_relaxed);
+  }
 }
 size_t round_size(size_t b) {
   if (b <= (size_t(1) << 20)) {
@@ -76,6 +96,7 @@ void* cache_alloc(size_t bytes) {
       c.free_blocks.erase(it);
     }
   }
+  count_alloc(dev, bytes);
   if (blk.p) {
     if (blk.ev) {
       if (blk.stream != g_stream) {
@@ -144,6 +165,13 @@ void cache_free(void* p, size_t bytes) {
 using namespace abddc;
 
 extern "C" const char* abddc_last_error(void) { return g_last_error.c_str(); }
+
+extern "C" int abddc_cache_stats(int32_t device, int64_t* allocations, int64_t* bytes) {
+  if (device < 0 || device >= STAT_DEVICES) return fail(ABDDC_EINVAL, "device index out of range");
+  if (allocations) *allocations = g_cache_allocs[device].load();
+  if (bytes) *bytes = g_cache_bytes[device].load();
+  return ABDDC_OK;
+}
 
 namespace {
 

@@ -39,28 +39,40 @@ void record(abddc_ctx* c, int i) {
   if (c->events) ABDDC_HIP(hipEventRecord(c->ev[i], c->stream));
 }
 
-// z = M^{-1} r (device vectors of length n_gamma)
-// z = M^{-1} r; with Z and st also Z[:, st->j] = z
-void apply_bddc_dev(abddc_ctx* c, const double* r, double* z, hipStream_t s, double* Z = nullptr, int64_t ldz = 0,
-                    const GmresState* st = nullptr) {
+// Work vectors of one M^{-1} application: the local outputs [L; V] r_i and
+// U x_Pi (length sum_i (n_B,i + n_Pi,i)), the coarse right-hand side and
+// the coarse solution (length n_Pi each).  Every entry is written before it
+// is read, so they need no clearing.
+struct ApplyWork {
+  double* out;
+  double* bpi;
+  double* xpi;
+};
+
+ApplyWork ctx_work(abddc_ctx* c) { return {c->d_out.p, c->d_bpi.p, c->d_xpi.p}; }
+
+// z = M^{-1} r (device vectors of length n_gamma); with Z and st also
+// Z[:, st->j] = z
+void apply_bddc_dev(abddc_ctx* c, const double* r, double* z, hipStream_t s, const ApplyWork& w,
+                    double* Z = nullptr, int64_t ldz = 0, const GmresState* st = nullptr) {
   const int np = c->n_primal;
   const bool mixed = c->dM32.p != nullptr;
   if (mixed)
-    gemv_run<float>(c->opM, c->dM32.p, r, c->d_gam.p, c->d_out.p, false, s);
+    gemv_run<float>(c->opM, c->dM32.p, r, c->d_gam.p, w.out, false, s);
   else
-    gemv_run<double>(c->opM, c->dM.p, r, c->d_gam.p, c->d_out.p, false, s);
+    gemv_run<double>(c->opM, c->dM.p, r, c->d_gam.p, w.out, false, s);
   if (np > 0) {
-    launch_gather_sum(c->d_pown_ptr.p, c->d_pown_idx.p, c->d_out.p, c->d_bpi.p, np, s);
-    gemv_run<double>(c->opC, c->dSPinv.p, c->d_bpi.p, nullptr, c->d_xpi.p, false, s);
+    launch_gather_sum(c->d_pown_ptr.p, c->d_pown_idx.p, w.out, w.bpi, np, s);
+    gemv_run<double>(c->opC, c->dSPinv.p, w.bpi, nullptr, w.xpi, false, s);
     if (mixed)
-      gemv_run<float>(c->opU, c->dU32.p, c->d_xpi.p, c->d_pid.p, c->d_out.p, true, s);
+      gemv_run<float>(c->opU, c->dU32.p, w.xpi, c->d_pid.p, w.out, true, s);
     else
-      gemv_run<double>(c->opU, c->dU.p, c->d_xpi.p, c->d_pid.p, c->d_out.p, true, s);
+      gemv_run<double>(c->opU, c->dU.p, w.xpi, c->d_pid.p, w.out, true, s);
   }
   if (Z)
-    launch_gather_sum_col(c->d_aown_ptr.p, c->d_aown_idx.p, c->d_out.p, z, Z, ldz, st, c->topo.n_gamma, s);
+    launch_gather_sum_col(c->d_aown_ptr.p, c->d_aown_idx.p, w.out, z, Z, ldz, st, c->topo.n_gamma, s);
   else
-    launch_gather_sum(c->d_aown_ptr.p, c->d_aown_idx.p, c->d_out.p, z, c->topo.n_gamma, s);
+    launch_gather_sum(c->d_aown_ptr.p, c->d_aown_idx.p, w.out, z, c->topo.n_gamma, s);
 }
 
 void apply_schur_dev(abddc_ctx* c, const double* x, double* y, hipStream_t s) {
@@ -134,7 +146,7 @@ void arnoldi_step(abddc_ctx* c, int restart, hipStream_t s) {
   const int64_t n = c->topo.n_gamma;
   const size_t nn = (size_t)std::max<int64_t>(n, 1);
   GmresState* st = c->d_gst.p;
-  apply_bddc_dev(c, c->d_vcur.p, c->d_zcur.p, s, c->d_Z.p, nn, st);   // also Z[:, j] = z_j
+  apply_bddc_dev(c, c->d_vcur.p, c->d_zcur.p, s, ctx_work(c), c->d_Z.p, nn, st);   // also Z[:, j] = z_j
   apply_schur_dev(c, c->d_zcur.p, c->d_w.p, s);
   launch_dots_dev(c->d_V.p, nn, st, restart, c->d_w.p, n, c->d_partial.p, c->d_h1.p, s);
   // w -= V h1 with the second pass's products, w -= V h2 with the norm
@@ -200,7 +212,11 @@ extern "C" int abddc_assemble(const abddc_problem* prob, const abddc_device* dev
     }
     ABDDC_REQUIRE(prob->tau > 0 && std::isfinite(prob->tau), ABDDC_EINVAL, "tau must be > 0");
     ABDDC_REQUIRE(prob->nu, ABDDC_EINVAL, "nu is null");
+    ABDDC_REQUIRE((dev->alloc == nullptr) == (dev->free == nullptr), ABDDC_EINVAL,
+                  "device allocation hooks: alloc and free must both be set or both be null");
     std::unique_ptr<abddc_ctx> c(new abddc_ctx());
+    c->dalloc = DevAlloc{dev->alloc, dev->free, dev->user};
+    AllocScope as(&c->dalloc);
     KStatsScope ks(&c->kstats);
     c->device = dev->device;
     ABDDC_HIP(hipSetDevice(dev->device));
@@ -445,6 +461,7 @@ extern "C" int abddc_setup_coarse_space(abddc_ctx* c, const abddc_options* opts,
     ABDDC_REQUIRE(o.constraint_source != ABDDC_CONSTRAINTS_MLP || (o.mlp && o.mlp->device == c->device), ABDDC_EINVAL,
                   "learned constraints need a network on the context's device");
     ABDDC_REQUIRE(o.pinv_rtol >= 0 && o.svd_rtol >= 0 && o.tie_rtol >= 0, ABDDC_EINVAL, "negative tolerance");
+    AllocScope as(&c->dalloc);
     KStatsScope ks(&c->kstats);
     StreamScope ss(c->stream);
     c->opt = o;
@@ -475,8 +492,9 @@ extern "C" int abddc_apply_bddc(abddc_ctx* c, const double* r, double* z) {
   return guarded([&]() -> int {
     ABDDC_REQUIRE(c && r && z, ABDDC_EINVAL, "null argument");
     ABDDC_REQUIRE(c->state >= 2, ABDDC_ESTATE, "apply before setup");
+    AllocScope as(&c->dalloc);
     KStatsScope ks(&c->kstats);
-    apply_bddc_dev(c, r, z, c->stream);
+    apply_bddc_dev(c, r, z, c->stream, ctx_work(c));
     return ABDDC_OK;
   });
 }
@@ -485,6 +503,7 @@ extern "C" int abddc_apply_schur(abddc_ctx* c, const double* x, double* y) {
   return guarded([&]() -> int {
     ABDDC_REQUIRE(c && x && y, ABDDC_EINVAL, "null argument");
     ABDDC_REQUIRE(c->state >= 1, ABDDC_ESTATE, "apply before assemble");
+    AllocScope as(&c->dalloc);
     KStatsScope ks(&c->kstats);
     apply_schur_dev(c, x, y, c->stream);
     return ABDDC_OK;
@@ -510,6 +529,7 @@ extern "C" int abddc_gmres_solve(abddc_ctx* c, int32_t restart, double rtol, int
     ABDDC_REQUIRE(rtol > 0 && rtol < 1, ABDDC_EINVAL, "rtol must be in (0, 1)");
     ABDDC_REQUIRE(maxit >= 1, ABDDC_EINVAL, "maxit must be >= 1");
     ABDDC_HIP(hipSetDevice(c->device));
+    AllocScope as(&c->dalloc);
     KStatsScope ks(&c->kstats);
     StreamScope ss(c->stream);
     hipStream_t s = c->stream;
@@ -681,6 +701,12 @@ extern "C" int64_t abddc_get_stage(abddc_ctx* c, int32_t stage, int32_t index, d
         for (int v : c->pF) host.push_back(v);
         for (int v : c->rE) host.push_back(v);
         n = (int64_t)host.size();
+        break;
+      case ABDDC_STAGE_SUB_SIZES:
+        ABDDC_REQUIRE(index >= 0 && index < T.n_sub, ABDDC_EINVAL, "bad subdomain index");
+        host = {(double)c->nI[index], (double)c->nB[index],
+                c->state >= 2 && (size_t)index < c->nPi.size() ? (double)c->nPi[index] : 0.0};
+        n = 3;
         break;
       case ABDDC_STAGE_DELUXE: {
         need_setup();

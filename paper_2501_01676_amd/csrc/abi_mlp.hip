@@ -86,9 +86,13 @@ extern "C" int abddc_mlp_create(const float* params, int32_t n_params, const abd
     ABDDC_REQUIRE(n_params == MLP_NPARAM, ABDDC_EINVAL, "parameter count must be ABDDC_MLP_PARAMS");
     *out = nullptr;
     ABDDC_HIP(hipSetDevice(dev->device));
+    ABDDC_REQUIRE((dev->alloc == nullptr) == (dev->free == nullptr), ABDDC_EINVAL,
+                  "device allocation hooks: alloc and free must both be set or both be null");
     std::unique_ptr<abddc_mlp> w(new abddc_mlp());
     w->device = dev->device;
     w->stream = (hipStream_t)dev->stream;
+    w->dalloc = DevAlloc{dev->alloc, dev->free, dev->user};
+    AllocScope as(&w->dalloc);
     StreamScope ss(w->stream);
     std::vector<float> h(params, params + MLP_NPARAM), z(MLP_NPARAM, 0.f);
     w->params = to_device(h, w->stream);
@@ -109,6 +113,7 @@ extern "C" int abddc_mlp_create(const float* params, int32_t n_params, const abd
 extern "C" int abddc_mlp_get_params(abddc_mlp* mlp, float* params, int32_t n_params) {
   return guarded([&]() -> int {
     abddc_mlp* w = checked(mlp);
+    AllocScope as(&w->dalloc);
     ABDDC_REQUIRE(params && n_params == MLP_NPARAM, ABDDC_EINVAL, "bad parameter buffer");
     StreamScope ss(w->stream);
     std::vector<float> h = to_host(w->params.p, MLP_NPARAM, w->stream);
@@ -120,6 +125,7 @@ extern "C" int abddc_mlp_get_params(abddc_mlp* mlp, float* params, int32_t n_par
 extern "C" int abddc_mlp_forward(abddc_mlp* mlp, const float* X, int32_t n, float* Y) {
   return guarded([&]() -> int {
     abddc_mlp* w = checked(mlp);
+    AllocScope as(&w->dalloc);
     ABDDC_REQUIRE(n >= 0 && (n == 0 || (X && Y)), ABDDC_EINVAL, "bad batch");
     StreamScope ss(w->stream);
     mlp_forward_dev(w, X, n, Y, w->stream);
@@ -131,6 +137,7 @@ extern "C" int abddc_mlp_loss_grad(abddc_mlp* mlp, const float* X, const float* 
                                    float* loss) {
   return guarded([&]() -> int {
     abddc_mlp* w = checked(mlp);
+    AllocScope as(&w->dalloc);
     ABDDC_REQUIRE(n > 0 && X && T && grad && loss, ABDDC_EINVAL, "bad batch");
     StreamScope ss(w->stream);
     mlp_loss_grad_dev(w, X, T, n, w->stream);
@@ -145,6 +152,7 @@ extern "C" int abddc_mlp_train_step(abddc_mlp* mlp, const float* X, const float*
                                     float* loss) {
   return guarded([&]() -> int {
     abddc_mlp* w = checked(mlp);
+    AllocScope as(&w->dalloc);
     ABDDC_REQUIRE(n > 0 && X && T, ABDDC_EINVAL, "bad batch");
     ABDDC_REQUIRE(lr > 0 && std::isfinite(lr), ABDDC_EINVAL, "learning rate must be > 0");
     StreamScope ss(w->stream);
@@ -161,6 +169,7 @@ extern "C" int abddc_mlp_train_step(abddc_mlp* mlp, const float* X, const float*
 extern "C" int abddc_mlp_set_ranges(abddc_mlp* mlp, const float* X, int32_t n) {
   return guarded([&]() -> int {
     abddc_mlp* w = checked(mlp);
+    AllocScope as(&w->dalloc);
     ABDDC_REQUIRE(n > 0 && X, ABDDC_EINVAL, "bad feature set");
     StreamScope ss(w->stream);
     mlp_ranges_dev(w, X, n, w->stream);
@@ -181,6 +190,7 @@ extern "C" int abddc_edge_features(abddc_ctx* c, float* X, int32_t* eligible) {
   return guarded([&]() -> int {
     ABDDC_REQUIRE(c, ABDDC_EINVAL, "null context");
     ABDDC_HIP(hipSetDevice(c->device));
+    AllocScope as(&c->dalloc);
     StreamScope ss(c->stream);
     const int ne = (int)c->topo.edges.size();
     if (ne == 0) return ABDDC_OK;
@@ -201,6 +211,7 @@ extern "C" int abddc_edge_projectors(abddc_ctx* c, float* Y) {
     ABDDC_REQUIRE(c, ABDDC_EINVAL, "null context");
     ABDDC_REQUIRE(c->state >= 2, ABDDC_ESTATE, "setup_coarse_space has not run");
     ABDDC_HIP(hipSetDevice(c->device));
+    AllocScope as(&c->dalloc);
     StreamScope ss(c->stream);
     const int ne = (int)c->topo.edges.size();
     if (ne == 0) return ABDDC_OK;

@@ -42,6 +42,7 @@ struct abddc_ctx {
   // ---------------------------------------------------------- problem
   int device = 0;
   hipStream_t stream = nullptr;
+  abddc::DevAlloc dalloc;   // caller's device allocation hooks (null: the library's cache)
   abddc::Topology topo;
   double length[3], beta0[3], beta1[9], c = 0, f_const = 0, tau = 0;
   bool have_fnodal = false;

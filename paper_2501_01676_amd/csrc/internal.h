@@ -51,29 +51,61 @@ struct StreamScope {
   ~StreamScope() { g_stream = prev; }
 };
 
+// Caller-supplied device allocation hooks (abddc_device alloc / free /
+// user); a null alloc means the library's caching allocator.
+struct DevAlloc {
+  void* (*alloc)(size_t bytes, void* user) = nullptr;
+  void (*free)(void* p, void* user) = nullptr;
+  void* user = nullptr;
+};
+// Hooks of the entry point running on this thread (null: the library's
+// cache).  Buffers remember the hooks they were allocated with and release
+// through them, wherever they are destroyed.
+extern thread_local const DevAlloc* g_dev_alloc;
+struct AllocScope {
+  const DevAlloc* prev;
+  explicit AllocScope(const DevAlloc* a) : prev(g_dev_alloc) { g_dev_alloc = a; }
+  ~AllocScope() { g_dev_alloc = prev; }
+};
+void* hooked_alloc(const DevAlloc& h, size_t bytes);   // throws ENOMEM on a null result
+
 // Owning device allocation.
 template <class T>
 struct DevBuf {
   T* p = nullptr;
   size_t n = 0;
+  DevAlloc hooks{};
   DevBuf() = default;
   explicit DevBuf(size_t count) { alloc(count); }
   DevBuf(const DevBuf&) = delete;
   DevBuf& operator=(const DevBuf&) = delete;
-  DevBuf(DevBuf&& o) noexcept : p(o.p), n(o.n) { o.p = nullptr; o.n = 0; }
+  DevBuf(DevBuf&& o) noexcept : p(o.p), n(o.n), hooks(o.hooks) { o.p = nullptr; o.n = 0; }
   DevBuf& operator=(DevBuf&& o) noexcept {
     release();
-    p = o.p; n = o.n; o.p = nullptr; o.n = 0;
+    p = o.p; n = o.n; hooks = o.hooks; o.p = nullptr; o.n = 0;
     return *this;
   }
   ~DevBuf() { release(); }
   void alloc(size_t count) {
     release();
     n = count;
-    if (count) p = static_cast<T*>(cache_alloc(count * sizeof(T)));
+    if (!count) return;
+    if (g_dev_alloc && g_dev_alloc->alloc) {
+      hooks = *g_dev_alloc;
+      p = static_cast<T*>(hooked_alloc(hooks, count * sizeof(T)));
+    } else {
+      hooks = DevAlloc{};
+      p = static_cast<T*>(cache_alloc(count * sizeof(T)));
+    }
   }
   void release() {
-    if (p) cache_free(p, n * sizeof(T));
+    if (p) {
+      if (hooks.alloc) {
+        if (hooks.free) hooks.free(p, hooks.user);
+      } else {
+        cache_free(p, n * sizeof(T));
+      }
+    }
     p = nullptr;
     n = 0;
   }

@@ -700,6 +700,7 @@ void partial_lu(const std::vector<PluDesc<T>>& descs_in, int* dflag, hipStream_t
   size_t need = descs.size() * 2 * NB * NB * sizeof(T);
   if (scratch.n < need) {
     ABDDC_HIP(hipStreamSynchronize(s));
+    AllocScope own(nullptr);   // outlives every context: the library's cache
     scratch.alloc(need);
   }
   T* scr = reinterpret_cast<T*>(scratch.p);
@@ -709,19 +710,53 @@ void partial_lu(const std::vector<PluDesc<T>>& descs_in, int* dflag, hipStream_t
   // that panel (which leaves its block to it); the next solves wait for it.
   SideStream& side = SideStream::for_stream(s);
   const int grp = maxk > 512 ? 4 : (maxk > 256 ? 3 : 2);   // panels per group
-  plu_diag_kernel<T><<<nb, 256, 0, s>>>(dd, 0, 0, scr, dflag);
+  // Algorithmic flops of each launch for the live kernel statistics (only
+  // counted when a statistics sink is set):
+  //   diag  LU of the b x b diagonal block, 2/3 b^3, plus its lookahead
+  //         update at depth t0 - u0, 2 b^2 (t0 - u0)
+  //   trsm  the two triangular solves, b^2 per row of L21 and per column of U12
+  //   band  the strips of the next panel at the group's depth, leaving out
+  //         the next diagonal block
+  auto diag_flops = [&](int t0, int u0) {
+    double f = 0.0;
+    if (g_kstats)
+      for (auto& d : descs)
+        if (t0 < d.k) {
+          const double b = std::min(NB, d.k - t0);
+          f += 2.0 / 3.0 * b * b * b + 2.0 * b * b * (t0 - u0);
+        }
+    return f;
+  };
+  auto diag_launch = [&](int t0, int u0, hipStream_t st) {
+    hipEvent_t ea = nullptr, eb = nullptr;
+    tracked_events(KC_PLU_DIAG, diag_flops(t0, u0), &ea, &eb);
+    hipExtLaunchKernelGGL(plu_diag_kernel<T>, dim3(nb), dim3(256), 0, st, ea, eb, 0, dd, t0, u0, scr, dflag);
+  };
+  diag_launch(0, 0, s);
   for (int t0 = 0; t0 < maxk; t0 += NB) {
     const int rem = std::max(maxr, maxc) - t0;
     const int tiles = 2 * ((rem + TILE - 1) / TILE);
     if (t0 > 0) ABDDC_HIP(hipStreamWaitEvent(s, side.done, 0));
-    plu_trsm_kernel<T><<<xcd_grid(std::max(tiles, 1), nb), 256, 0, s>>>(dd, t0, scr, std::max(tiles, 1), nb);
+    {
+      double f = 0.0;
+      if (g_kstats)
+        for (auto& d : descs)
+          if (t0 < d.k) {
+            const double b = std::min(NB, d.k - t0);
+            f += b * b * ((double)(d.nrow - t0 - b) + (double)(d.ncol - t0 - b));
+          }
+      hipEvent_t ea = nullptr, eb = nullptr;
+      tracked_events(KC_PLU_TRSM, f, &ea, &eb);
+      hipExtLaunchKernelGGL(plu_trsm_kernel<T>, dim3(xcd_grid(std::max(tiles, 1), nb)), dim3(256), 0, s, ea, eb, 0,
+                            dd, t0, (const T*)scr, std::max(tiles, 1), nb);
+    }
     if (t0 + NB < maxk) {
       // the next diagonal block: the pivot columns of this panel's group so
       // far, applied in the diag kernel
       const int u0 = t0 - ((t0 / NB) % grp) * NB;   // start of this panel's group
       ABDDC_HIP(hipEventRecord(side.ready, s));
       ABDDC_HIP(hipStreamWaitEvent(side.s, side.ready, 0));
-      plu_diag_kernel<T><<<nb, 256, 0, side.s>>>(dd, t0 + NB, u0, scr, dflag);
+      diag_launch(t0 + NB, u0, side.s);
       ABDDC_HIP(hipEventRecord(side.done, side.s));
     }
     const int g0 = t0 - ((t0 / NB) % grp) * NB;
@@ -732,7 +767,21 @@ void partial_lu(const std::vector<PluDesc<T>>& descs_in, int* dflag, hipStream_t
         // column strip tiles + row strip tiles (the row strip starts at
         // column w >= 1 of the trailing part, so it spans < maxc - sb columns)
         const int bt = (maxr - sb + TILE - 1) / TILE + std::max(0, (maxc - sb - 1 + TILE - 1) / TILE);
-        if (bt > 0) plu_band_kernel<T><<<xcd_grid(bt, nb), 256, 0, s>>>(dd, g0, t0, bt, nb);
+        if (bt > 0) {
+          double f = 0.0;
+          if (g_kstats)
+            for (auto& d : descs)
+              if (t0 < d.k) {
+                const int s0 = t0 + std::min(NB, d.k - t0);
+                if (s0 >= d.k) continue;
+                const double w = std::min(NB, d.k - s0), mr = d.nrow - s0, nc = d.ncol - s0;
+                f += 2.0 * (s0 - g0) * ((mr - w) * w + w * (nc - w));
+              }
+          hipEvent_t ea = nullptr, eb = nullptr;
+          tracked_events(KC_PLU_BAND, f, &ea, &eb);
+          hipExtLaunchKernelGGL(plu_band_kernel<T>, dim3(xcd_grid(bt, nb)), dim3(256), 0, s, ea, eb, 0, dd, g0, t0,
+                                bt, nb);
+        }
       }
       continue;
     }
@@ -742,10 +791,14 @@ void partial_lu(const std::vector<PluDesc<T>>& descs_in, int* dflag, hipStream_t
     if (sp < maxk && rt > 0 && ct > 0) {
       hipEvent_t ea = nullptr, eb = nullptr;
       if (g_kstats) {
-        double flops = 0.0;  // rows [s, nrow) x cols [s, k) and rows [s, k) x cols [k, ncol), depth b
+        // rows [s, nrow) x cols [s, k) and rows [s, k) x cols [k, ncol) at
+        // depth b, without the next diagonal block
+        double flops = 0.0;
         for (auto& d : descs)
           if (sp < d.k) {
-            flops += 2.0 * (grp * NB) * ((double)(d.nrow - sp) * (d.k - sp) + (double)(d.k - sp) * (d.ncol - d.k));
+            const double w = std::min(NB, d.k - sp);
+            flops += 2.0 * (grp * NB) *
+                     ((double)(d.nrow - sp) * (d.k - sp) + (double)(d.k - sp) * (d.ncol - d.k) - w * w);
           }
         tracked_events(KC_PLU_LEAD, flops, &ea, &eb);
       }

@@ -13,12 +13,20 @@
 
 namespace abddc {
 
-enum KernelClass { KC_PLU_UPDATE = 0, KC_GEMV = 1, KC_PLU_LEAD = 2, KC_COUNT = 3 };
+enum KernelClass {
+  KC_PLU_UPDATE = 0,
+  KC_GEMV = 1,
+  KC_PLU_LEAD = 2,
+  KC_PLU_DIAG = 3,
+  KC_PLU_TRSM = 4,
+  KC_PLU_BAND = 5,
+  KC_COUNT = 6
+};
 
 struct KStats {
-  double seconds[KC_COUNT] = {0, 0, 0};
-  double work[KC_COUNT] = {0, 0, 0};
-  int64_t launches[KC_COUNT] = {0, 0, 0};
+  double seconds[KC_COUNT] = {};
+  double work[KC_COUNT] = {};
+  int64_t launches[KC_COUNT] = {};
   struct Pending {
     int cls;
     hipEvent_t a, b;

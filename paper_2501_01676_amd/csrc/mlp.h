@@ -39,6 +39,7 @@ struct abddc_ctx;
 struct abddc_mlp {
   int device = 0;
   hipStream_t stream = nullptr;
+  abddc::DevAlloc dalloc;          // caller's device allocation hooks
   abddc::DevBuf<float> params, m, v, grad, fmin, fmax, loss;
   abddc::DevBuf<uint16_t> wbf;     // bfloat16 W1 | W2 | W3
   int64_t step = 0;
