@@ -164,6 +164,21 @@ int abddc_setup_coarse_space(abddc_ctx* ctx, const abddc_options* opts, abddc_co
  * n_gamma (may not alias). */
 int abddc_apply_bddc(abddc_ctx* ctx, const double* r, double* z);
 
+/* z = M^{-1} r as abddc_apply_bddc (same kernels, same result), for callers
+ * that cannot allocate device memory during the call: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation.  The work
+ * vectors (sum_i (n_B,i + n_Pi,i) + 2 n_Pi doubles, each part rounded up to
+ * 32) live in a fixed device array of ABDDC_NOALLOC_SCRATCH_DOUBLES doubles
+ * (16 MiB) per GPU, held from the first call on that GPU until the process
+ * ends; the call makes no allocation, no host-device copy and records no
+ * event.  Every call on one GPU shares that GPU's array, so calls that
+ * overlap in time on one GPU (two host threads, or two streams whose work
+ * runs concurrently) race and give undefined results; calls ordered on one
+ * stream are safe.  Returns ABDDC_EINVAL when the work vectors do not fit,
+ * ABDDC_ESTATE before setup. */
+#define ABDDC_NOALLOC_SCRATCH_DOUBLES (1 << 21)
+int abddc_apply_bddc_noalloc(abddc_ctx* ctx, const double* r, double* z);
+
 /* y = Shat x = sum_i R_i^T S^(i) R_i x (the operator of eq.
  * Schur-complex-sys); device vectors of length n_gamma (may not alias). */
 int abddc_apply_schur(abddc_ctx* ctx, const double* x, double* y);

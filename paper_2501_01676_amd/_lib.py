@@ -83,6 +83,7 @@ SIGNATURES = {
     "abddc_assemble": (C.c_int, [C.POINTER(Problem), C.POINTER(Device), C.POINTER(_P)]),
     "abddc_setup_coarse_space": (C.c_int, [_P, C.POINTER(Options), C.POINTER(Counts)]),
     "abddc_apply_bddc": (C.c_int, [_P, _P, _P]),
+    "abddc_apply_bddc_noalloc": (C.c_int, [_P, _P, _P]),
     "abddc_cache_stats": (C.c_int, [C.c_int32, _I64P, _I64P]),
     "abddc_apply_schur": (C.c_int, [_P, _P, _P]),
     "abddc_get_rhs": (C.c_int, [_P, _P]),

@@ -175,6 +175,12 @@ class Solver:
         L.check(self.lib.abddc_apply_bddc(self.ctx, _dptr(r), _dptr(z)))
         return z
 
+    def apply_bddc_noalloc(self, r, out):
+        """z = M^{-1} r through the entry point that allocates nothing (work
+        vectors in the library's fixed per-GPU array); out is required."""
+        L.check(self.lib.abddc_apply_bddc_noalloc(self.ctx, _dptr(r), _dptr(out)))
+        return out
+
     def apply_schur(self, x, out=None):
         y = self._vec(self.n_gamma) if out is None else out
         L.check(self.lib.abddc_apply_schur(self.ctx, _dptr(x), _dptr(y)))

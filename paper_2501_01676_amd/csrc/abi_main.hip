@@ -499,6 +499,55 @@ extern "C" int abddc_apply_bddc(abddc_ctx* c, const double* r, double* z) {
   });
 }
 
+// ------------------------------------------- M^{-1} r without allocation
+// Work vectors of abddc_apply_bddc_noalloc: one array per GPU, resident for
+// the life of the process.  Host code never passes the array's name to a
+// kernel (on the host it does not denote device memory); it uses the device
+// address that hipGetSymbolAddress returns for the current device.
+namespace {
+static __device__ __align__(256) double scratch[ABDDC_NOALLOC_SCRATCH_DOUBLES];
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[MAX_DEVICES] = {};
+
+// Device address of this device's scratch array (looked up once per device,
+// with that device current).
+double* scratch_for(int device) {
+  ABDDC_REQUIRE(device >= 0 && device < MAX_DEVICES, ABDDC_EINVAL, "device index out of range");
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    void* ptr = nullptr;
+    ABDDC_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    ABDDC_REQUIRE(ptr != nullptr, ABDDC_EDEVICE, "scratch array has no device address");
+    g_scratch_ptr[device] = static_cast<double*>(ptr);
+  }
+  return g_scratch_ptr[device];
+}
+}  // namespace
+
+extern "C" int abddc_apply_bddc_noalloc(abddc_ctx* c, const double* r, double* z) {
+  return guarded([&]() -> int {
+    ABDDC_REQUIRE(c && r && z, ABDDC_EINVAL, "null argument");
+    ABDDC_REQUIRE(c->state >= 2, ABDDC_ESTATE, "apply before setup");
+    const int64_t nout = (int64_t)c->d_out.n, np = std::max(c->n_primal, 1);
+    const int64_t need = ((nout + 31) / 32) * 32 + 2 * ((np + 31) / 32) * 32;
+    ABDDC_REQUIRE(need <= ABDDC_NOALLOC_SCRATCH_DOUBLES, ABDDC_EINVAL,
+                  "abddc_apply_bddc_noalloc: the problem needs " + std::to_string(need) +
+                      " doubles of work space, more than the fixed " +
+                      std::to_string((long long)ABDDC_NOALLOC_SCRATCH_DOUBLES));
+    ABDDC_HIP(hipSetDevice(c->device));
+    double* base = scratch_for(c->device);
+    ApplyWork w;
+    w.out = base;
+    w.bpi = base + ((nout + 31) / 32) * 32;
+    w.xpi = w.bpi + ((np + 31) / 32) * 32;
+    KStatsScope none(nullptr);   // no timing events (no event creation)
+    apply_bddc_dev(c, r, z, c->stream, w);
+    return ABDDC_OK;
+  });
+}
+
 extern "C" int abddc_apply_schur(abddc_ctx* c, const double* x, double* y) {
   return guarded([&]() -> int {
     ABDDC_REQUIRE(c && x && y, ABDDC_EINVAL, "null argument");
