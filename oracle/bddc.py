@@ -9,6 +9,8 @@ Steps, in the paper's order and notation:
                    B_F = D_j^T B_F^(i) D_j + D_i^T B_F^(j) D_i
                    Btilde_F = Btilde_F^(i) : Btilde_F^(j)  (parallel sum)
                    constraints (B_F v_l)^T (w_i,F - w_j,F) = 0   (eq. primal-constraints-F)
+  edge GEP (old)   B_E v = lambda Btilde_E v, one constraint per selected
+                   eigenvector (eq. equ-4-8-E, primal-constraints-E)
   edge GEP (new)   M_E vcheck = lambda Btilde~_E vcheck           (eq. equ-5-21)
                    M_E = That^T blockdiag(B_E^(k)) That           (eq. equ-5-20)
                    Btilde~_E = Schur complement onto the jumps of the matrix
@@ -45,6 +47,7 @@ DEFAULT_OPTIONS = {
     "svd_rtol": 1e-8,
     "tie_rtol": 1e-9,
     "edge_ref": 0,               # which member of n(E) is the jump reference
+    "edge_variant": "new",       # "new" (eq. equ-5-21) or "old" (eq. equ-4-8-E)
 }
 
 
@@ -68,6 +71,15 @@ def pinv_sym(M, rtol):
 def parallel_sum(A, B, rtol):
     """A : B = A (A + B)^+ B (Anderson-Duffin), symmetrised."""
     return sym(A @ pinv_sym(A + B, rtol) @ B)
+
+
+def parallel_sum_all(mats, rtol):
+    """A_1 : A_2 : ... : A_m, folded left to right (the parallel sum of PSD
+    matrices is commutative and associative)."""
+    out = mats[0]
+    for A in mats[1:]:
+        out = parallel_sum(out, A, rtol)
+    return out
 
 
 def schur_onto(M, keep, rtol=None):
@@ -187,7 +199,10 @@ class OracleBDDC:
         self.opt = opt
         self._deluxe()
         self._faces()
-        self._edges()
+        if opt["edge_variant"] == "old":
+            self._edges_old()
+        else:
+            self._edges()
         self._change_of_basis()
         self._coarse()
         self.state = "setup"
@@ -359,6 +374,37 @@ class OracleBDDC:
             self.edge_mu[k], self.edge_r[k], self.edge_T[k] = mu, r, T
             self.edge_nsel[k] = int(sel.sum())
             self.edge_aux[k] = dict(ops, X=X, sel=sel, G=G)
+
+    def _edges_old(self):
+        """The earlier edge eigenproblem (eq. equ-4-8-E): B_E v = lambda Btilde_E v,
+
+          B_E       = sum_{i in n(E)} sum_{k in n(E), k != i} D_E^(k)^T B_E^(i) D_E^(k),
+                      B_E^(i) = (B^(i))_EE,
+          Btilde_E  = Btilde_E^(1) : ... : Btilde_E^(m), the parallel sum of the
+                      Schur complements of B^(nu) onto E (C = Gamma_nu minus E),
+
+        solved in reciprocal form like the faces; one constraint
+        (B_E v_l)^T (w_i,E - w_j,E) = 0 per lambda_l >= Theta_E
+        (eq. primal-constraints-E), realised by an orthonormal basis of
+        span{B_E v_l} completed by QR."""
+        topo, opt = self.topo, self.opt
+        self._primal_numbering_faces()
+        self.edge_mu, self.edge_r, self.edge_T, self.edge_nsel = {}, {}, {}, {}
+        self.edge_aux = {}
+        for k in topo.edges:
+            subs = list(topo.objects[k]["subs"])
+            BEi = {s: self._block(self.B[s], s, k) for s in subs}
+            BE = sum(self.D[(k, kk)].T @ BEi[i] @ self.D[(k, kk)] for i in subs for kk in subs if kk != i)
+            Bts = [sym(schur_onto(self.B[s], topo.sub[s]["obj_local"][k])) for s in subs]
+            Bt = parallel_sum_all(Bts, opt["pinv_rtol"])
+            mu, X = gep_reciprocal(Bt, sym(BE))
+            sel, ties = select(mu, opt["theta_edge"], opt["tie_rtol"])
+            self.n_ties += ties
+            T, p = complete_basis(X[:, sel])
+            self.edge_mu[k], self.edge_r[k], self.edge_T[k] = mu, p, T
+            self.edge_nsel[k] = int(sel.sum())
+            self.edge_aux[k] = {"BE": sym(BE), "Bt": Bt, "Bts": Bts, "BEi": BEi, "X": X, "sel": sel,
+                                "subs": subs, "Ds": [self.D[(k, s)] for s in subs]}
 
     def _change_of_basis(self):
         """T_i = blockdiag([Q_X | Q_X^perp]) over Gamma_i; Pi_i = primal
