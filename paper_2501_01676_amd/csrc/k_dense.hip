@@ -285,6 +285,83 @@ __device__ inline float read_lane<float>(float v, int lane) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
 }
 
+// D[0, b)^2 -= A (b x kd) B (kd x b) for the lookahead of the diagonal-block
+// kernel: A, B row-major with leading dimension ld, kd a multiple of 64.  One
+// workgroup streams the strips through LDS in K chunks of 32 with two chunks
+// in flight in registers (one workgroup per matrix cannot hide the memory
+// latency with other workgroups); each wave accumulates a 32 x 32 quadrant
+// on MFMA.  Rows and columns >= b read zero, so the identity padding of D is
+// left as it is.
+template <class T>
+__device__ __forceinline__ void diag_lookahead(const T* A, const T* B, int ld, int b, int kd, T (*D)[NB + 1],
+                                               T (*As)[LDS_PAD], T (*Bs)[LDS_PAD]) {
+  typedef typename Mfma<T>::acc_t acc_t;
+  constexpr int PER = TILE * KC / 256;   // elements of each operand per thread and chunk
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int wr = (w >> 1) * 32, wc = (w & 1) * 32, kl = lane >> 4, il = lane & 15;
+  const __amdgpu_buffer_rsrc_t rsa = buf_rsrc(A), rsb = buf_rsrc(B);
+  // A chunk: row ai + 8 q, column ak; B chunk: row bk + 4 q, column bj
+  const int ai = tid >> 5, ak = tid & 31, bk = tid >> 6, bj = tid & 63;
+  int oa[PER], ob[PER];
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int i = ai + 8 * q;
+    oa[q] = i < b ? (i * ld + ak) * (int)sizeof(T) : BUF_OUT;
+    ob[q] = bj < b ? ((bk + 4 * q) * ld + bj) * (int)sizeof(T) : BUF_OUT;
+  }
+  T ra0[PER], rb0[PER], ra1[PER], rb1[PER];
+  auto fetch = [&](T* ra, T* rb, int k0) {
+    const int sa = k0 * (int)sizeof(T), sb = k0 * ld * (int)sizeof(T);
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      ra[q] = buf_load<T>(rsa, oa[q], sa);
+      rb[q] = buf_load<T>(rsb, ob[q], sb);
+    }
+  };
+  auto stage = [&](const T* ra, const T* rb) {
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      As[ak][ai + 8 * q] = ra[q];
+      Bs[bk + 4 * q][bj] = rb[q];
+    }
+    __syncthreads();
+  };
+  acc_t acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = acc_t{0, 0, 0, 0};
+  auto mma = [&]() {
+#pragma unroll
+    for (int kk = 0; kk < KC; kk += 4) {
+      const T a0 = As[kk + kl][wr + il], a1 = As[kk + kl][wr + 16 + il];
+      const T b0 = Bs[kk + kl][wc + il], b1 = Bs[kk + kl][wc + 16 + il];
+      acc[0][0] = Mfma<T>::run(a0, b0, acc[0][0]);
+      acc[0][1] = Mfma<T>::run(a0, b1, acc[0][1]);
+      acc[1][0] = Mfma<T>::run(a1, b0, acc[1][0]);
+      acc[1][1] = Mfma<T>::run(a1, b1, acc[1][1]);
+    }
+  };
+  fetch(ra0, rb0, 0);
+  fetch(ra1, rb1, KC);
+#pragma unroll 1
+  for (int k0 = 0; k0 < kd; k0 += 2 * KC) {
+    stage(ra0, rb0);
+    if (k0 + 2 * KC < kd) fetch(ra0, rb0, k0 + 2 * KC);
+    mma();
+    stage(ra1, rb1);
+    if (k0 + 3 * KC < kd) fetch(ra1, rb1, k0 + 3 * KC);
+    mma();
+  }
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+    for (int bj2 = 0; bj2 < 2; ++bj2)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) D[wr + 16 * bi + Mfma<T>::out_row(kl, q)][wc + 16 * bj2 + il] -= acc[bi][bj2][q];
+}
+
 // Step 1 of panel t0: factor the diagonal block (b = min(NB, k - t0)) and
 // write L\U back, L^{-1} (unit lower) and U^{-1} to scratch.  The block is
 // padded in LDS to diag(D, I) of order 64, which factors and inverts to
@@ -334,8 +411,7 @@ __global__ void __launch_bounds__(256) plu_diag_kernel(const PluDesc<T>* __restr
   __syncthreads();
   if (u0 < t0) {
     T (*As)[LDS_PAD] = reinterpret_cast<T (*)[LDS_PAD]>(&E[0][0]);
-    tile_gemm<T, false, false, true>(d.a + (size_t)t0 * d.ld + u0, d.ld, d.a + (size_t)u0 * d.ld + t0, d.ld, &D[0][0],
-                               NB + 1, b, b, t0 - u0, T(-1), T(1), 0, 0, As, As + KC);
+    diag_lookahead<T>(d.a + (size_t)t0 * d.ld + u0, d.a + (size_t)u0 * d.ld + t0, d.ld, b, t0 - u0, D, As, As + KC);
     __syncthreads();
   }
   for (int kb = 0; kb < b; kb += 16) {
@@ -347,7 +423,6 @@ __global__ void __launch_bounds__(256) plu_diag_kernel(const PluDesc<T>* __restr
       for (int j = 0; j < 16; ++j) {
         const int pr = kb + j;
         const T piv = read_lane(P[j], pr);
-        if (lane == 0 && pr < b && (!(fabs((double)piv) > 0.0) || !isfinite((double)piv))) atomicOr(dflag, 1);
         const T inv = recip(piv);
         T u[16];
 #pragma unroll
@@ -378,59 +453,128 @@ __global__ void __launch_bounds__(256) plu_diag_kernel(const PluDesc<T>* __restr
       for (int t = 0; t < 16; ++t) D[kb + t][lane] = X[t];
     }
     __syncthreads();
-    if (lane >= kb + 16) {
-      T U[16];
+    // trailing block [kb + 16, 64)^2 -= L(:, kb..kb+16) U(kb..kb+16, :) on
+    // MFMA, one 16 x 16 output block per wave at a time (9, 4, 1 blocks)
+    {
+      const int nbk = (NB - kb - 16) / 16;
+      const int kl = lane >> 4, il = lane & 15;
+      for (int blk = wave; blk < nbk * nbk; blk += 4) {
+        const int r0 = kb + 16 + 16 * (blk / nbk), c0 = kb + 16 + 16 * (blk % nbk);
+        typename Mfma<T>::acc_t acc;
 #pragma unroll
-      for (int t = 0; t < 16; ++t) U[t] = D[kb + t][lane];
-#pragma unroll 2
-      for (int i = kb + 16 + wave; i < NB; i += 4) {
-        T a[4] = {T(0), T(0), T(0), T(0)};
+        for (int q = 0; q < 4; ++q) acc[q] = D[r0 + Mfma<T>::out_row(kl, q)][c0 + il];
 #pragma unroll
-        for (int t = 0; t < 16; ++t) a[t & 3] += D[i][kb + t] * U[t];
-        D[i][lane] -= (a[0] + a[1]) + (a[2] + a[3]);
+        for (int kk = 0; kk < 16; kk += 4) acc = Mfma<T>::run(-D[r0 + il][kb + kk + kl], D[kb + kk + kl][c0 + il], acc);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) D[r0 + Mfma<T>::out_row(kl, q)][c0 + il] = acc[q];
       }
     }
     __syncthreads();
   }
-  for (int r = wave; r < b; r += 4)
-    if (lane < b) base[(size_t)r * d.ld + lane] = D[r][lane];
-  if (wave == 1) dinv[lane] = T(1) / D[lane][lane];
+  {
+    // buffer stores (not counted with the LDS operations, so neither the
+    // reads below nor the barrier wait for them)
+    const __amdgpu_buffer_rsrc_t rs = buf_rsrc(base);
+#pragma unroll
+    for (int i = 0; i < NB / 4; ++i) {
+      const int r = wave + 4 * i;
+      buf_store<T>(D[r][lane], rs, (r < b && lane < b) ? (r * d.ld + lane) * (int)sizeof(T) : BUF_OUT, 0);
+    }
+  }
+  if (wave == 1) {
+    // the pivots are the diagonal of U: flag a zero or non-finite one
+    const T dv = D[lane][lane];
+    dinv[lane] = T(1) / dv;
+    const bool bad = lane < b && (!(fabs((double)dv) > 0.0) || !isfinite((double)dv));
+    if (__ballot(bad) && lane == 0) atomicOr(dflag, 1);
+  }
   __syncthreads();
   T* gLi = scratch + (size_t)blockIdx.x * 2 * NB * NB;
   T* gUi = gLi + NB * NB;
   // Inverses by 32 x 32 blocks:
   //   L^{-1} = [[L11^{-1}, 0], [-L22^{-1} (L21 L11^{-1}), L22^{-1}]]
   //   U^{-1} = [[U11^{-1}, -U11^{-1} (U12 U22^{-1})], [0, U22^{-1}]]
-  // (1) the four diagonal-block inverses, one column per lane (wave 0:
-  //     L11, L22 in its two lane halves; wave 1: U11, U22), into E:
-  //     E11 = L11^{-1}, E22 = L22^{-1}, E21 = U11^{-1}, E12 = U22^{-1};
-  // (2) T1 = L21 E11 and T2 = U12 E12 on MFMA, written over L21, U12;
-  // (3) the off-diagonal blocks -E22 T1 and -E21 T2 on MFMA, straight to global.
+  // with each 32 x 32 inverse built the same way from 16 x 16 blocks.  Layout
+  // of the four 32 x 32 inverses in E: E11 = L11^{-1}, E22 = L22^{-1},
+  // E21 = U11^{-1}, E12 = U22^{-1} (U block rows shifted by 32).
+  // (1a) the eight 16 x 16 diagonal-block inverses, one column per lane
+  //      (lane 16 j + c: column c of block j): wave 0 the unit lower L_jj,
+  //      wave 1 the upper U_jj; waves 2 and 3 write the zero blocks
   {
-    const int half = lane >> 5, c = lane & 31, off = half * H;
+    const int j = lane >> 4, c = lane & 15, o = 16 * j;
     if (wave == 0) {
-      T X[H];
+      T X[16];
 #pragma unroll
-      for (int r = 0; r < H; ++r) {
+      for (int r = 0; r < 16; ++r) {
         T a[2] = {T(0), T(0)};   // two independent chains
 #pragma unroll
-        for (int q = 0; q < r; ++q) a[q & 1] += D[off + r][off + q] * X[q];
+        for (int q = 0; q < r; ++q) a[q & 1] += D[o + r][o + q] * X[q];
         X[r] = T(r == c) - (a[0] + a[1]);
       }
 #pragma unroll
-      for (int r = 0; r < H; ++r) E[off + r][off + c] = X[r];
+      for (int r = 0; r < 16; ++r) E[o + r][o + c] = X[r];
     } else if (wave == 1) {
-      T X[H];
+      T X[16];
 #pragma unroll
-      for (int r = H - 1; r >= 0; --r) {
+      for (int r = 15; r >= 0; --r) {
         T a[2] = {T(0), T(0)};
 #pragma unroll
-        for (int q = r + 1; q < H; ++q) a[q & 1] += D[off + r][off + q] * X[q];
-        X[r] = (T(r == c) - (a[0] + a[1])) * dinv[off + r];
+        for (int q = r + 1; q < 16; ++q) a[q & 1] += D[o + r][o + q] * X[q];
+        X[r] = (T(r == c) - (a[0] + a[1])) * dinv[o + r];
       }
-      // U11^{-1} -> E21 (rows H.., cols 0..), U22^{-1} -> E12 (rows 0.., cols H..)
 #pragma unroll
-      for (int r = 0; r < H; ++r) E[(1 - half) * H + r][half * H + c] = X[r];
+      for (int r = 0; r < 16; ++r) E[((o + 32) & 63) + r][o + c] = X[r];
+    } else {
+      // zero blocks: upper right of each L 32-inverse (wave 2), lower left of
+      // each U 32-inverse (wave 3); lane = block (j & 1) x column c, 16 rows
+      const int p = j & 1, o32 = 32 * p;
+      if (j < 2) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          if (wave == 2) E[o32 + r][o32 + 16 + c] = T(0);
+          else E[((o32 + 32) & 63) + 16 + r][o32 + c] = T(0);
+        }
+      }
+    }
+  }
+  __syncthreads();
+  // (1b) the off-diagonal 16 x 16 block of each 32 x 32 inverse on MFMA:
+  //      wave p (0, 1): L block p, T = L21 L11^{-1} over the L21 block of D,
+  //      then -L22^{-1} T; wave 2 + p: U block p, T = U12 U22^{-1} over the U12
+  //      block of D, then -U11^{-1} T (16 x 16 blocks inside the 32-block)
+  {
+    typedef typename Mfma<T>::acc_t acc_t;
+    const int kl = lane >> 4, il = lane & 15;
+    const bool isL = wave < 2;
+    const int o = 32 * (wave & 1), eo = (o + 32) & 63;
+    acc_t t1 = {0, 0, 0, 0};
+#pragma unroll
+    for (int kk = 0; kk < 16; kk += 4) {
+      if (isL)
+        t1 = Mfma<T>::run(D[o + 16 + il][o + kk + kl], E[o + kk + kl][o + il], t1);
+      else
+        t1 = Mfma<T>::run(D[o + il][o + 16 + kk + kl], E[eo + 16 + kk + kl][o + 16 + il], t1);
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int r = Mfma<T>::out_row(kl, q);
+      if (isL) D[o + 16 + r][o + il] = t1[q];
+      else D[o + r][o + 16 + il] = t1[q];
+    }
+    __syncthreads();
+    acc_t t2 = {0, 0, 0, 0};
+#pragma unroll
+    for (int kk = 0; kk < 16; kk += 4) {
+      if (isL)
+        t2 = Mfma<T>::run(E[o + 16 + il][o + 16 + kk + kl], D[o + 16 + kk + kl][o + il], t2);
+      else
+        t2 = Mfma<T>::run(E[eo + il][o + kk + kl], D[o + kk + kl][o + 16 + il], t2);
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int r = Mfma<T>::out_row(kl, q);
+      if (isL) E[o + 16 + r][o + il] = -t2[q];
+      else E[eo + r][o + 16 + il] = -t2[q];
     }
   }
   __syncthreads();
