@@ -61,6 +61,8 @@ def parse():
     ap.add_argument("--rtol", type=float, default=1e-8)
     ap.add_argument("--maxit", type=int, default=300)
     ap.add_argument("--precision", type=int, default=0, help="0 = FP64, 1 = mixed")
+    ap.add_argument("--edge-variant", choices=["new", "old"], default="new",
+                    help="edge eigenproblem: the new one (eq. equ-5-21) or the earlier one (eq. equ-4-8-E)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--constraints", choices=["exact", "mlp"], default="exact",
                     help="edge constraints from the exact eigenproblem, or from the network trained first "
@@ -89,7 +91,8 @@ def _oracle_solve(problem, opts, args):
     t0 = time.perf_counter()
     o = bddc.OracleBDDC(problem)
     o.assemble()
-    o.setup_coarse_space({"theta_face": opts["theta_face"], "theta_edge": opts["theta_edge"]})
+    o.setup_coarse_space({"theta_face": opts["theta_face"], "theta_edge": opts["theta_edge"],
+                          "edge_variant": "old" if opts.get("edge_variant") == 1 else "new"})
     _, info = o.gmres_solve(args.restart, args.rtol, args.maxit)
     return time.perf_counter() - t0, info, o.counts
 
@@ -192,7 +195,8 @@ def main():
     dev_problem["nu"] = torch.from_numpy(problem["nu"]).cuda()
     if problem.get("f_nodal") is not None:
         dev_problem["f_nodal"] = torch.from_numpy(problem["f_nodal"]).cuda()
-    opts = {"theta_face": args.theta, "theta_edge": args.theta, "precision": args.precision}
+    opts = {"theta_face": args.theta, "theta_edge": args.theta, "precision": args.precision,
+            "edge_variant": 1 if args.edge_variant == "old" else 0}
     learned = None
     if args.constraints == "mlp":
         learned = train_network(args, opts)
@@ -273,7 +277,8 @@ def main():
         "dtype": "f64" if args.precision == 0 else "f64+f32",
         "data": "synthetic",
         "config": {"workload": f"{args.config}: {DESCRIPTIONS[args.config]}; Theta_F=Theta_E={args.theta:g}, "
-                               f"GMRES({args.restart}) rtol {args.rtol:g}",
+                               f"GMRES({args.restart}) rtol {args.rtol:g}"
+                               + ("; earlier edge eigenproblem (eq. equ-4-8-E)" if args.edge_variant == "old" else ""),
                    "seed": args.seed, "n_sub": sizes[0], "n_dof": sizes[1], "n_gamma": sizes[2]},
         "local_solve_tflops": tflops,
         "local_solve_gflop": {"S2": s2 / 1e9, "S10": s10 / 1e9},

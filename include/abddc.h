@@ -121,7 +121,13 @@ enum { ABDDC_CONSTRAINTS_EXACT = 0, ABDDC_CONSTRAINTS_MLP = 1 };
 typedef struct {
   double theta_face;        /* Theta_F >= 0: select lambda >= Theta_F           */
   double theta_edge;        /* Theta_E >= 0                                      */
-  int32_t edge_variant;     /* ABDDC_EDGE_NEW (eq. equ-5-21); OLD not provided  */
+  int32_t edge_variant;     /* ABDDC_EDGE_NEW (eq. equ-5-21) or ABDDC_EDGE_OLD,
+                               the earlier edge eigenproblem (eq. equ-4-8-E:
+                               B_E over ordered member pairs, parallel sum of
+                               the members' Schur complements onto the edge,
+                               one constraint per selected eigenvector; edges
+                               of 2..4 members and <= 16 dofs; exact
+                               constraints only)                              */
   int32_t edge_h_mode;      /* prior-selected primal unknowns shared / separate */
   int32_t deluxe_source;    /* deluxe weights from S^(i) (default) or B^(i)     */
   double pinv_rtol;         /* pseudo-inverse eigenvalue cut (1e-10)            */
@@ -154,7 +160,8 @@ typedef struct {
 int abddc_assemble(const abddc_problem* prob, const abddc_device* dev, abddc_ctx** out);
 
 /* Section 3: deluxe weights, face eigenproblems (eq. equ-4-8), new edge
- * eigenproblems (eq. equ-5-21) with the SVD/QR edge basis, change of basis,
+ * eigenproblems (eq. equ-5-21) with the SVD/QR edge basis (or the earlier
+ * ones, eq. equ-4-8-E, with edge_variant = ABDDC_EDGE_OLD), change of basis,
  * local constrained factorisations and the coarse matrix.  Fills counts
  * (may be NULL).  opts may be NULL (defaults: Theta_F = Theta_E = 10,
  * shared H, deluxe from S, FP64). */
@@ -205,7 +212,8 @@ int abddc_query(const abddc_ctx* ctx, int64_t* n_dof, int64_t* n_gamma, int32_t*
  *   ABDDC_STAGE_SCHUR      S^(index), n_B x n_B row-major
  *   ABDDC_STAGE_LOCAL_RHS  g^(index)
  *   ABDDC_STAGE_FACE_EIG   mu = 1/lambda of face index (ascending)
- *   ABDDC_STAGE_EDGE_EIG   mu = 1/lambda of edge index (ascending)
+ *   ABDDC_STAGE_EDGE_EIG   mu = 1/lambda of edge index (ascending; (m-1) n_E
+ *                          values for the new eigenproblem, n_E for the old)
  *   ABDDC_STAGE_FACE_BASIS [Q_F | Q_F^perp] of face index, n_F x n_F row-major
  *   ABDDC_STAGE_EDGE_BASIS [Q_E | Q_E^perp] of edge index, n_E x n_E row-major
  *   ABDDC_STAGE_COUNTS     per face p_F then per edge r_E (as doubles)

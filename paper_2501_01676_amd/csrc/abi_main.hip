@@ -450,7 +450,10 @@ extern "C" int abddc_setup_coarse_space(abddc_ctx* c, const abddc_options* opts,
     o.tie_rtol = 1e-9;
     if (opts) o = *opts;
     ABDDC_REQUIRE(o.theta_face >= 0 && o.theta_edge >= 0, ABDDC_EINVAL, "thresholds must be >= 0");
-    ABDDC_REQUIRE(o.edge_variant == ABDDC_EDGE_NEW, ABDDC_EINVAL, "only the new edge eigenproblem is provided");
+    ABDDC_REQUIRE(o.edge_variant == ABDDC_EDGE_NEW || o.edge_variant == ABDDC_EDGE_OLD, ABDDC_EINVAL,
+                  "bad edge_variant");
+    ABDDC_REQUIRE(o.edge_variant == ABDDC_EDGE_NEW || o.constraint_source == ABDDC_CONSTRAINTS_EXACT, ABDDC_EINVAL,
+                  "learned edge constraints predict the new edge eigenproblem's basis only");
     ABDDC_REQUIRE(o.edge_h_mode == ABDDC_H_SHARED || o.edge_h_mode == ABDDC_H_SEPARATE, ABDDC_EINVAL, "bad edge_h_mode");
     ABDDC_REQUIRE(o.deluxe_source == ABDDC_DELUXE_S || o.deluxe_source == ABDDC_DELUXE_B, ABDDC_EINVAL,
                   "bad deluxe_source");
@@ -742,7 +745,8 @@ extern "C" int64_t abddc_get_stage(abddc_ctx* c, int32_t stage, int32_t index, d
         ABDDC_REQUIRE(index >= 0 && index < (int)T.edges.size(), ABDDC_EINVAL, "bad edge index");
         const Object& o = T.objects[T.edges[index]];
         src = stage == ABDDC_STAGE_EDGE_EIG ? c->dWE.p + c->weoff[index] : c->dTE.p + c->teoff[index];
-        n = stage == ABDDC_STAGE_EDGE_EIG ? (int64_t)(o.subs.size() - 1) * o.n : (int64_t)o.n * o.n;
+        const int64_t neig = (c->opt.edge_variant == ABDDC_EDGE_OLD ? 1 : (int64_t)o.subs.size() - 1) * o.n;
+        n = stage == ABDDC_STAGE_EDGE_EIG ? neig : (int64_t)o.n * o.n;
         break;
       }
       case ABDDC_STAGE_COUNTS:

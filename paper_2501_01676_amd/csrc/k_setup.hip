@@ -39,6 +39,48 @@ __global__ void deluxe_build_kernel(const DeluxeDesc* __restrict__ descs) {
   }
 }
 
+// Metric of the earlier edge eigenproblem, regrouped by the weight index:
+// B_E = sum_k D^(k)^T (sum_{i != k} B_E^(i)) D^(k), written symmetrised.
+__global__ void __launch_bounds__(256) edge_old_metric_kernel(const EdgeOldDesc* __restrict__ descs) {
+  constexpr int NE = 16;
+  __shared__ double G[NE][NE + 1], Z[NE][NE + 1], A[NE][NE + 1];
+  __shared__ EdgeOldDesc sd;   // the descriptor (indexed by member) staged in LDS once
+  if (threadIdx.x == 0) sd = descs[blockIdx.x];
+  __syncthreads();
+  const EdgeOldDesc& d = sd;
+  const int n = d.nE, m = d.m, tid = threadIdx.x;
+  for (int idx = tid; idx < n * n; idx += blockDim.x) A[idx / n][idx % n] = 0.0;
+  for (int k = 0; k < m; ++k) {
+    for (int idx = tid; idx < n * n; idx += blockDim.x) {
+      const int r = idx / n, c = idx % n;
+      double v = 0.0;
+      for (int i = 0; i < m; ++i)
+        if (i != k) v += d.BE[i][(size_t)r * d.ldBE[i] + c];
+      G[r][c] = v;
+    }
+    __syncthreads();
+    const double* Dk = d.D[k];
+    for (int idx = tid; idx < n * n; idx += blockDim.x) {
+      const int r = idx / n, c = idx % n;
+      double v = 0.0;
+      for (int q = 0; q < n; ++q) v += G[r][q] * Dk[q * n + c];
+      Z[r][c] = v;
+    }
+    __syncthreads();
+    for (int idx = tid; idx < n * n; idx += blockDim.x) {
+      const int r = idx / n, c = idx % n;
+      double v = 0.0;
+      for (int p = 0; p < n; ++p) v += Dk[p * n + r] * Z[p][c];
+      A[r][c] += v;
+    }
+    __syncthreads();
+  }
+  for (int idx = tid; idx < n * n; idx += blockDim.x) {
+    const int r = idx / n, c = idx % n;
+    d.out[idx] = 0.5 * (A[r][c] + A[c][r]);
+  }
+}
+
 // Edge operators for one edge shared by m subdomains (reference = member 0):
 //   That_k = [-D_2 ... -D_m] + (I in slot k for k >= 2)      (n_E x (m-1) n_E)
 //   M_E    = sum_k That_k^T B_E^(k) That_k
@@ -170,6 +212,16 @@ void deluxe_build_batched(const std::vector<DeluxeDesc>& descs, hipStream_t s) {
   for (auto& d : descs) maxe = std::max(maxe, 2 * d.n * (d.m + 1) * d.n);
   const DeluxeDesc* dd = Arena::for_stream(s).put(descs);
   deluxe_build_kernel<<<dim3(std::min(256, (maxe + 255) / 256), descs.size()), 256, 0, s>>>(dd);
+  ABDDC_HIP(hipGetLastError());
+}
+
+void edge_old_metric_batched(const std::vector<EdgeOldDesc>& descs, hipStream_t s) {
+  if (descs.empty()) return;
+  for (auto& d : descs)
+    ABDDC_REQUIRE(d.nE >= 1 && d.nE <= 16 && d.m >= 2 && d.m <= 4, ABDDC_EINVAL,
+                  "earlier edge eigenproblem: edges need 2..4 members and at most 16 dofs");
+  const EdgeOldDesc* dd = Arena::for_stream(s).put(descs);
+  edge_old_metric_kernel<<<(unsigned)descs.size(), 256, 0, s>>>(dd);
   ABDDC_HIP(hipGetLastError());
 }
 

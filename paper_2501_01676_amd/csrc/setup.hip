@@ -438,6 +438,7 @@ void run_setup(abddc_ctx* c) {
   c->nselE.assign(ned, 0);
   c->teoff.assign(ned, 0);
   c->weoff.assign(ned, 0);
+  const bool old_edges = c->opt.edge_variant == ABDDC_EDGE_OLD;
   {
     int64_t tt = 0, wt = 0;
     for (int e = 0; e < ned; ++e) {
@@ -445,7 +446,7 @@ void run_setup(abddc_ctx* c) {
       c->teoff[e] = tt;
       tt += (int64_t)o.n * o.n;
       c->weoff[e] = wt;
-      wt += (int64_t)(o.subs.size() - 1) * o.n;
+      wt += (int64_t)(old_edges ? 1 : o.subs.size() - 1) * o.n;   // eigenvalues per edge
     }
     c->dTE.alloc(std::max<int64_t>(tt, 1));
     c->dWE.alloc(std::max<int64_t>(wt, 1));
@@ -461,7 +462,166 @@ void run_setup(abddc_ctx* c) {
   }
   c->n_exact_edges = (int)elist.size();
   c->n_pred_edges = ned - c->n_exact_edges;
-  if (!elist.empty()) {
+  if (old_edges && !elist.empty()) {
+    ht.mark("earlier edge eigenproblem: member Schur");
+    // The earlier edge eigenproblem (eq. equ-4-8-E): Btilde_E^(nu) = Schur
+    // complement of B^(nu) onto E (C = Gamma_nu minus E) in two steps, per
+    // subdomain all face dofs, then per (edge, member) the other edges' dofs
+    // and the vertex dofs (each pivot block a Schur complement of a principal
+    // submatrix of B^(nu)_CC, positive definite as that one is); Btilde_E =
+    // their parallel sum; B_E from the deluxe weights; one constraint B_E v_l
+    // per selected eigenvalue, completed to an orthonormal basis.
+    IntPool pool;
+    std::vector<size_t> m1off(nsub);
+    std::vector<int> nfc(nsub), nW(nsub), nedof(nsub);
+    std::vector<std::vector<int>> epos(nsub);   // per object of the subdomain: start among its edge dofs
+    for (int sub = 0; sub < nsub; ++sub) {
+      const SubInfo& si = T.sub[sub];
+      std::vector<int32_t> fdofs, edofs, vdofs;
+      epos[sub].assign(si.objs.size(), -1);
+      for (size_t q = 0; q < si.objs.size(); ++q) {
+        const Object& o = T.objects[si.objs[q]];
+        const int off = si.obj_off[q];
+        if (o.kind == KIND_FACE) {
+          for (int l = 0; l < o.n; ++l) fdofs.push_back(off + l);
+        } else if (o.kind == KIND_EDGE) {
+          epos[sub][q] = (int)edofs.size();
+          for (int l = 0; l < o.n; ++l) edofs.push_back(off + l);
+        } else {
+          vdofs.push_back(off);
+        }
+      }
+      std::vector<int32_t> mp = fdofs;
+      mp.insert(mp.end(), edofs.begin(), edofs.end());
+      mp.insert(mp.end(), vdofs.begin(), vdofs.end());
+      m1off[sub] = pool.add(mp);
+      nfc[sub] = (int)fdofs.size();
+      nedof[sub] = (int)edofs.size();
+      nW[sub] = c->nB[sub] - nfc[sub];
+    }
+    std::vector<size_t> m2off((size_t)ned * 4);
+    std::vector<int64_t> e2off((size_t)ned * 4);
+    int64_t e2tot = 0;
+    int maxm = 0;
+    for (int e : elist) {
+      const int k = T.edges[e];
+      const Object& o = T.objects[k];
+      ABDDC_REQUIRE(o.subs.size() >= 2 && o.subs.size() <= 4 && o.n <= 16, ABDDC_EINVAL,
+                    "earlier edge eigenproblem: edges need 2..4 members and at most 16 dofs");
+      maxm = std::max(maxm, (int)o.subs.size());
+      for (size_t q = 0; q < o.subs.size(); ++q) {
+        const int sub = o.subs[q];
+        const SubInfo& si = T.sub[sub];
+        const int qi = (int)(std::lower_bound(si.objs.begin(), si.objs.end(), k) - si.objs.begin());
+        const int ep = epos[sub][qi];
+        std::vector<int32_t> mp;   // [other edge dofs; vertex dofs; E] inside W = [edge dofs; vertex dofs]
+        for (int t = 0; t < nedof[sub]; ++t)
+          if (t < ep || t >= ep + o.n) mp.push_back(t);
+        for (int t = nedof[sub]; t < nW[sub]; ++t) mp.push_back(t);
+        for (int t = 0; t < o.n; ++t) mp.push_back(ep + t);
+        m2off[(size_t)e * 4 + q] = pool.add(mp);
+        e2off[(size_t)e * 4 + q] = e2tot;
+        e2tot += (int64_t)nW[sub] * nW[sub];
+      }
+    }
+    pool.upload(s);
+    DevBuf<double> E1(c->dB.n), E2(std::max<int64_t>(e2tot, 1));
+    {
+      std::vector<GatherDesc> gd;
+      std::vector<PluDesc<double>> pd;
+      for (int sub = 0; sub < nsub; ++sub) {
+        const int nB = c->nB[sub];
+        gd.push_back({c->dB.p + c->soff[sub], E1.p + c->soff[sub], pool.ptr(m1off[sub]), pool.ptr(m1off[sub]), nB, nB,
+                      nB, nB, 1.0});
+        pd.push_back({E1.p + c->soff[sub], nB, nB, nB, nfc[sub]});
+      }
+      gather_batched(gd, s);
+      partial_lu<double>(pd, c->d_flag.p, s);
+    }
+    // per edge: the members' Schur complements symmetrised (slot q), two
+    // slots for the parallel-sum fold, the metric and the eigenvectors
+    std::vector<int64_t> eoff(ned);
+    int64_t etot = 0;
+    for (int e : elist) {
+      const Object& o = T.objects[T.edges[e]];
+      eoff[e] = etot;
+      etot += (int64_t)(o.subs.size() + 4) * o.n * o.n;
+    }
+    DevBuf<double> EB(std::max<int64_t>(etot, 1));
+    auto slot = [&](int e, int q) { return EB.p + eoff[e] + (int64_t)q * T.objects[T.edges[e]].n * T.objects[T.edges[e]].n; };
+    {
+      std::vector<GatherDesc> gd;
+      std::vector<PluDesc<double>> pd;
+      std::vector<SymDesc> sy;
+      for (int e : elist) {
+        const Object& o = T.objects[T.edges[e]];
+        for (size_t q = 0; q < o.subs.size(); ++q) {
+          const int sub = o.subs[q], nB = c->nB[sub], w = nW[sub], kk = w - o.n;
+          const double* Wbase = E1.p + c->soff[sub] + (int64_t)nfc[sub] * nB + nfc[sub];
+          double* dst = E2.p + e2off[(size_t)e * 4 + q];
+          gd.push_back({Wbase, dst, pool.ptr(m2off[(size_t)e * 4 + q]), pool.ptr(m2off[(size_t)e * 4 + q]), w, w, nB,
+                        w, 1.0});
+          pd.push_back({dst, w, w, w, kk});
+          sy.push_back({dst + (int64_t)kk * w + kk, slot(e, (int)q), o.n, w, o.n});
+        }
+      }
+      gather_batched(gd, s);
+      partial_lu<double>(pd, c->d_flag.p, s);
+      sym_batched(sy, s);
+    }
+    ht.mark("parallel sums, metric, eigenproblems");
+    // Btilde_E = ((Bt_1 : Bt_2) : Bt_3) : Bt_4, alternating between the two fold slots
+    std::vector<const double*> cur(ned, nullptr);
+    for (int e : elist) cur[e] = slot(e, 0);
+    for (int q = 1; q < maxm; ++q) {
+      std::vector<PsumDesc> ps;
+      for (int e : elist) {
+        const Object& o = T.objects[T.edges[e]];
+        if ((int)o.subs.size() <= q) continue;
+        double* out = slot(e, (int)o.subs.size() + (q & 1));
+        ps.push_back({cur[e], slot(e, q), out, o.n, o.n, o.n});
+        cur[e] = out;
+      }
+      parallel_sum_batched(ps, c->opt.pinv_rtol, s);
+    }
+    std::vector<EdgeOldDesc> md;
+    std::vector<SygvDesc> gv;
+    for (int e : elist) {
+      const int k = T.edges[e];
+      const Object& o = T.objects[k];
+      const int m = (int)o.subs.size();
+      EdgeOldDesc d{};
+      d.nE = o.n;
+      d.m = m;
+      for (int q = 0; q < m; ++q) {
+        d.D[q] = c->dD.p + c->dxoff[(size_t)k * 8 + q];
+        d.BE[q] = Sblk(c->dB.p, o.subs[q], k);
+        d.ldBE[q] = c->nB[o.subs[q]];
+      }
+      d.out = slot(e, m + 2);
+      md.push_back(d);
+      gv.push_back({cur[e], slot(e, m + 2), c->dWE.p + c->weoff[e], slot(e, m + 3), o.n});
+    }
+    edge_old_metric_batched(md, s);
+    eig_selected(gv, 1.0 / c->opt.theta_edge, c->d_flag.p, s);
+    std::vector<double> mu = to_host(c->dWE.p, c->dWE.n, s);
+    require_flag_clean(c, "edge elimination / edge eigenproblem");
+    std::vector<QrDesc> qd;
+    for (int e : elist) {
+      const Object& o = T.objects[T.edges[e]];
+      int ns = 0;
+      for (int q = 0; q < o.n; ++q) {
+        const double m = mu[c->weoff[e] + q];
+        if (m <= 1.0 / c->opt.theta_edge) ++ns;
+        const double lam = m > 0 ? 1.0 / m : INFINITY;
+        if (std::fabs(lam - c->opt.theta_edge) <= c->opt.tie_rtol * c->opt.theta_edge) ++c->n_ties;
+      }
+      c->nselE[e] = ns;
+      c->rE[e] = ns;
+      qd.push_back({slot(e, (int)o.subs.size() + 3), c->dTE.p + c->teoff[e], o.n, ns, o.n});
+    }
+    qr_complete_batched(qd, s);
+  } else if (!elist.empty()) {
     ht.mark("face-rotated Bbar^(s) = T_F^T B^(s) T_");
     // face-rotated Bbar^(s) = T_F^T B^(s) T_F on every face block
     DevBuf<double> Y(c->dB.n), Bbar(c->dB.n);

@@ -127,3 +127,32 @@ def test_full_size_separate_prior_primals(name):
     _, info = g.gmres_solve(restart=30, rtol=1e-8, maxit=300, history=False)
     g.close()
     assert info["converged"] and abs(info["iters"] - int(ref["sep_iters"])) <= 1
+
+
+def test_full_size_earlier_edge_eigenproblem_config3():
+    """The earlier edge eigenproblem (eq. equ-4-8-E) on config3 at full
+    size: identical counts per face and per edge, every edge spectrum within
+    1e-9, the solution within 1e-10, iterations +-1."""
+    _need_gpu()
+    from paper_2501_01676_amd import api
+    with np.load(os.path.join(GOLDEN, "oracle_config3_seed0_old.npz")) as z:
+        ref = {k: z[k] for k in z.files}
+    g = api.Solver(W.config3(0))
+    counts = g.setup_coarse_space(edge_variant=1)
+    rc = _counts(ref)
+    print(f"[fullsize] config3 earlier edges: counts {counts} oracle {rc}", flush=True)
+    if rc["n_near_ties"] == 0:
+        assert counts == rc
+        cnt = g.stage(6)
+        assert list(cnt[:g.n_face].astype(int)) == list(ref["face_p"])
+        assert list(cnt[g.n_face:].astype(int)) == list(ref["edge_r"])
+        ep, emu = ref["edge_mu_ptr"], ref["edge_mu"]
+        for e in range(g.n_edge):
+            mu, r = g.stage(3, e), emu[ep[e]:ep[e + 1]]
+            assert mu.size == r.size and np.abs(mu - r).max() <= 1e-9 * max(1.0, np.abs(r).max()), e
+    u, info = g.gmres_solve(restart=30, rtol=1e-8, maxit=300)
+    u = u.cpu().numpy()
+    g.close()
+    assert info["converged"] and abs(info["iters"] - int(ref["iters"])) <= 1
+    err = np.linalg.norm(u - ref["u"]) / np.linalg.norm(ref["u"])
+    assert err <= 1e-10, err

@@ -36,6 +36,13 @@ CASES = {
     "deluxe_b": (_layered, dict(LOOSE, deluxe_source="B"), dict(LOOSE, deluxe_source=1)),
     "config2": (W.config2, {}, {}),
     "wide_ragged": (lambda: W.ragged((2, 2, 2), [8, 10, 12], 6, beta0=(3.0, -2.0, 1.0)), LOOSE, LOOSE),
+    # the earlier edge eigenproblem (eq. equ-4-8-E): partial selections,
+    # a ragged partition, and every edge dof selected (config2)
+    "old_layered": (_layered, dict(LOOSE, theta_edge=30.0, edge_variant="old"),
+                    dict(LOOSE, theta_edge=30.0, edge_variant=1)),
+    "old_ragged": (lambda: W.ragged((3, 2, 2), [3, 4, 5], 4), dict(LOOSE, theta_edge=6.0, edge_variant="old"),
+                   dict(LOOSE, theta_edge=6.0, edge_variant=1)),
+    "old_config2": (W.config2, {"edge_variant": "old"}, {"edge_variant": 1}),
 }
 
 
