@@ -56,7 +56,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", default="config3", choices=sorted(DESCRIPTIONS))
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--theta", type=float, default=10.0)
+    ap.add_argument("--theta", type=float, default=10.0, help="Theta_F (and Theta_E unless --theta-edge is given)")
+    ap.add_argument("--theta-edge", type=float, default=None, help="Theta_E")
     ap.add_argument("--restart", type=int, default=30)
     ap.add_argument("--rtol", type=float, default=1e-8)
     ap.add_argument("--maxit", type=int, default=300)
@@ -130,6 +131,7 @@ def train_network(args, opts):
     from paper_2501_01676_amd import workloads as W
     t0 = time.perf_counter()
     Xs, Ts = [], []
+    ref_iters = []
     for k in range(args.train_meshes):
         g = api.Solver(W.get(args.config, 1000 + k))
         g.setup_coarse_space(**opts)
@@ -138,6 +140,8 @@ def train_network(args, opts):
         keep = el.bool()
         Xs.append(X[keep])
         Ts.append(T[keep])
+        _, info = g.gmres_solve(args.restart, args.rtol, args.maxit, history=False)
+        ref_iters.append(info["iters"])
         g.close()
     X = torch.cat(Xs).contiguous()
     T = torch.cat(Ts).contiguous()
@@ -155,14 +159,23 @@ def train_network(args, opts):
     last = net.loss_grad(X, T)[0]
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
+    # untimed references on the benchmark problem: the exact method (edge
+    # phase included) and no edge constraints at all
     ref = api.Solver(W.get(args.config, args.seed))
     ref.setup_coarse_space(**opts)
     _, rinfo = ref.gmres_solve(args.restart, args.rtol, args.maxit, history=False)
     rc = ref.counts
+    redge = float(ref.phase_times()[4])
     ref.close()
+    none = api.Solver(W.get(args.config, args.seed))
+    none.setup_coarse_space(**dict(opts, theta_edge=1e300))
+    _, ninfo = none.gmres_solve(args.restart, args.rtol, args.maxit, history=False)
+    none.close()
     labels_nonzero = int((T.abs().sum(dim=1) > 0).sum().item())
     return {"net": net, "train_s": t_train, "edges": int(n), "labels_nonzero": labels_nonzero,
-            "loss_first": first, "loss_last": last, "exact_iters": rinfo["iters"], "exact_counts": rc}
+            "loss_first": first, "loss_last": last, "exact_iters": rinfo["iters"], "exact_counts": rc,
+            "exact_edge_phase_s": redge, "no_edge_constraint_iters": ninfo["iters"],
+            "judge_iters": int(max(ref_iters)), "train_exact_iters": ref_iters}
 
 
 def local_solve_flops(solver):
@@ -195,12 +208,13 @@ def main():
     dev_problem["nu"] = torch.from_numpy(problem["nu"]).cuda()
     if problem.get("f_nodal") is not None:
         dev_problem["f_nodal"] = torch.from_numpy(problem["f_nodal"]).cuda()
-    opts = {"theta_face": args.theta, "theta_edge": args.theta, "precision": args.precision,
+    theta_e = args.theta if args.theta_edge is None else args.theta_edge
+    opts = {"theta_face": args.theta, "theta_edge": theta_e, "precision": args.precision,
             "edge_variant": 1 if args.edge_variant == "old" else 0}
     learned = None
     if args.constraints == "mlp":
         learned = train_network(args, opts)
-        opts = dict(opts, constraint_source=1, mlp=learned["net"])
+        opts = dict(opts, constraint_source=1, mlp=learned["net"], judge_iters=learned["judge_iters"])
 
     def step(want_flops=False):
         ta = time.perf_counter()
@@ -276,7 +290,8 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if args.precision == 0 else "f64+f32",
         "data": "synthetic",
-        "config": {"workload": f"{args.config}: {DESCRIPTIONS[args.config]}; Theta_F=Theta_E={args.theta:g}, "
+        "config": {"workload": f"{args.config}: {DESCRIPTIONS[args.config]}; Theta_F={args.theta:g}, "
+                               f"Theta_E={theta_e:g}, "
                                f"GMRES({args.restart}) rtol {args.rtol:g}"
                                + ("; earlier edge eigenproblem (eq. equ-4-8-E)" if args.edge_variant == "old" else ""),
                    "seed": args.seed, "n_sub": sizes[0], "n_dof": sizes[1], "n_gamma": sizes[2]},
@@ -296,9 +311,14 @@ def main():
         out["config"]["workload"] += f"; learned edge constraints (network trained on {args.train_meshes} other seeds)"
         out["learned"] = {"predicted_edges": recs[-1][1]["learned"]["predicted"],
                           "exact_edges": recs[-1][1]["learned"]["exact"],
-                          "iters": info["iters"], "exact_iters": learned["exact_iters"],
-                          "iteration_ratio": info["iters"] / max(learned["exact_iters"], 1),
-                          "judge_ok": info["iters"] <= 1.2 * learned["exact_iters"],
+                          "iters": info["iters"], "first_iters": info["first_iters"],
+                          "redone_solves": sum(int(r[1]["redone"]) for r in recs),
+                          "judge_iters": learned["judge_iters"],
+                          "train_exact_iters": learned["train_exact_iters"],
+                          "exact_iters": learned["exact_iters"],
+                          "no_edge_constraint_iters": learned["no_edge_constraint_iters"],
+                          "iteration_ratio": info["first_iters"] / max(learned["exact_iters"], 1),
+                          "edge_phase_s": float(phases[4]), "exact_edge_phase_s": learned["exact_edge_phase_s"],
                           "exact_counts": learned["exact_counts"],
                           "train_edges": learned["edges"], "train_labels_nonzero": learned["labels_nonzero"],
                           "train_loss_first": learned["loss_first"], "train_loss_last": learned["loss_last"],

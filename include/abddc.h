@@ -136,6 +136,13 @@ typedef struct {
   int32_t precision;        /* ABDDC_PREC_FP64 or ABDDC_PREC_MIXED             */
   int32_t constraint_source;/* exact GEP, or learned edge constraints          */
   const struct abddc_mlp* mlp; /* trained network for ABDDC_CONSTRAINTS_MLP     */
+  int32_t judge_iters;      /* learned constraints only: reference iteration
+                               count of the exact method (0: no judge); a
+                               gmres_solve that fails or needs more than
+                               judge_ratio * judge_iters iterations redoes
+                               the setup with exact edge constraints and
+                               solves again                                  */
+  double judge_ratio;       /* > 0, or 0 for the default 1.2                   */
 } abddc_options;
 
 typedef struct {
@@ -150,6 +157,11 @@ typedef struct {
   double t_iter_s;          /* gmres_solve wall time incl. interior recovery     */
   double* resid_history;    /* HOST array or NULL; Arnoldi estimates / ||ghat|| */
   int32_t resid_cap;        /* capacity of resid_history                         */
+  int32_t redone;           /* 1: the judge replaced learned edge constraints
+                               by exact ones and the solve was repeated (the
+                               fields above describe the repeated solve;
+                               t_iter_s covers the whole call)                */
+  int32_t first_iters;      /* iterations of the first solve                   */
 } abddc_solve_info;
 
 /* Section 3 (local matrices A^(i), f^(i) of a_i and g; Schur complements

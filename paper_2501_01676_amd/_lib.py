@@ -58,6 +58,8 @@ class Options(C.Structure):
         ("precision", C.c_int32),
         ("constraint_source", C.c_int32),
         ("mlp", C.c_void_p),
+        ("judge_iters", C.c_int32),
+        ("judge_ratio", C.c_double),
     ]
 
 
@@ -72,7 +74,8 @@ class Counts(C.Structure):
 class SolveInfo(C.Structure):
     _fields_ = [("iters", C.c_int32), ("restarts", C.c_int32), ("relres_true", C.c_double),
                 ("t_setup_s", C.c_double), ("t_iter_s", C.c_double),
-                ("resid_history", C.POINTER(C.c_double)), ("resid_cap", C.c_int32)]
+                ("resid_history", C.POINTER(C.c_double)), ("resid_cap", C.c_int32),
+                ("redone", C.c_int32), ("first_iters", C.c_int32)]
 
 
 _P = C.c_void_p

@@ -24,6 +24,8 @@ DEFAULT_OPTIONS = {
     "precision": 0,
     "constraint_source": 0,
     "mlp": None,
+    "judge_iters": 0,
+    "judge_ratio": 0.0,
 }
 
 
@@ -201,7 +203,8 @@ class Solver:
         rc = L.check(self.lib.abddc_gmres_solve(self.ctx, int(restart), float(rtol), int(maxit), _dptr(u),
                                                 C.byref(info)))
         res = {"iters": info.iters, "restarts": info.restarts, "relres_true": info.relres_true,
-               "t_setup_s": info.t_setup_s, "t_iter_s": info.t_iter_s, "converged": rc == L.OK}
+               "t_setup_s": info.t_setup_s, "t_iter_s": info.t_iter_s, "converged": rc == L.OK,
+               "redone": bool(info.redone), "first_iters": info.first_iters}
         if history:
             res["history"] = hist[:info.iters].copy()
         return u, res

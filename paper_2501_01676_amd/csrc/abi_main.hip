@@ -200,6 +200,29 @@ bool ensure_step_graph(abddc_ctx* c, int restart) {
   return true;
 }
 
+// Coarse-space setup with validated options (the caller has set the scopes).
+void setup_with(abddc_ctx* c, const abddc_options& o) {
+  c->opt = o;
+  c->n_ties = 0;
+  c->state = 1;
+  if (c->step_exec) {   // the captured Arnoldi step points at the previous setup's buffers
+    ABDDC_HIP(hipStreamSynchronize(c->stream));
+    (void)hipGraphExecDestroy(c->step_exec);
+    (void)hipGraphDestroy(c->step_graph);
+    c->step_exec = nullptr;
+    c->step_graph = nullptr;
+    c->step_restart = 0;
+  }
+  run_setup(c);
+  c->kstats.resolve();
+  c->phase[2] = ev_ms(c, 2, 3);
+  c->phase[3] = ev_ms(c, 3, 4);
+  c->phase[4] = ev_ms(c, 4, 5);
+  c->phase[5] = ev_ms(c, 5, 6);
+  c->phase[6] = ev_ms(c, 6, 8);
+  c->state = 2;
+}
+
 }  // namespace
 
 extern "C" int abddc_assemble(const abddc_problem* prob, const abddc_device* dev, abddc_ctx** out) {
@@ -464,29 +487,13 @@ extern "C" int abddc_setup_coarse_space(abddc_ctx* c, const abddc_options* opts,
     ABDDC_REQUIRE(o.constraint_source != ABDDC_CONSTRAINTS_MLP || (o.mlp && o.mlp->device == c->device), ABDDC_EINVAL,
                   "learned constraints need a network on the context's device");
     ABDDC_REQUIRE(o.pinv_rtol >= 0 && o.svd_rtol >= 0 && o.tie_rtol >= 0, ABDDC_EINVAL, "negative tolerance");
+    ABDDC_REQUIRE(o.judge_iters >= 0 && o.judge_ratio >= 0 && std::isfinite(o.judge_ratio), ABDDC_EINVAL,
+                  "bad judge settings");
     AllocScope as(&c->dalloc);
     KStatsScope ks(&c->kstats);
     StreamScope ss(c->stream);
-    c->opt = o;
-    c->n_ties = 0;
-    c->state = 1;
-    if (c->step_exec) {   // the captured Arnoldi step points at the previous setup's buffers
-      ABDDC_HIP(hipStreamSynchronize(c->stream));
-      (void)hipGraphExecDestroy(c->step_exec);
-      (void)hipGraphDestroy(c->step_graph);
-      c->step_exec = nullptr;
-      c->step_graph = nullptr;
-      c->step_restart = 0;
-    }
-    run_setup(c);
-    c->kstats.resolve();
-    c->phase[2] = ev_ms(c, 2, 3);
-    c->phase[3] = ev_ms(c, 3, 4);
-    c->phase[4] = ev_ms(c, 4, 5);
-    c->phase[5] = ev_ms(c, 5, 6);
-    c->phase[6] = ev_ms(c, 6, 8);
+    setup_with(c, o);
     if (counts) *counts = {c->n_vertex, c->pnum_face, c->pnum_edge, c->n_primal, c->n_ties};
-    c->state = 2;
     return ABDDC_OK;
   });
 }
@@ -572,18 +579,11 @@ extern "C" int abddc_get_rhs(abddc_ctx* c, double* g) {
   });
 }
 
-extern "C" int abddc_gmres_solve(abddc_ctx* c, int32_t restart, double rtol, int32_t maxit, double* u,
-                                 abddc_solve_info* info) {
-  return guarded([&]() -> int {
-    ABDDC_REQUIRE(c && u, ABDDC_EINVAL, "null argument");
-    ABDDC_REQUIRE(c->state >= 2, ABDDC_ESTATE, "solve before setup");
-    ABDDC_REQUIRE(restart >= 1 && restart <= GMRES_MAXR, ABDDC_EINVAL, "restart must be in [1, 63]");
-    ABDDC_REQUIRE(rtol > 0 && rtol < 1, ABDDC_EINVAL, "rtol must be in (0, 1)");
-    ABDDC_REQUIRE(maxit >= 1, ABDDC_EINVAL, "maxit must be >= 1");
-    ABDDC_HIP(hipSetDevice(c->device));
-    AllocScope as(&c->dalloc);
-    KStatsScope ks(&c->kstats);
-    StreamScope ss(c->stream);
+namespace {
+// One GMRES solve and the interior recovery (the caller has validated the
+// arguments and set the scopes); fills info (may be null) and returns
+// whether the true residual met rtol.
+bool gmres_core(abddc_ctx* c, int32_t restart, double rtol, int32_t maxit, double* u, abddc_solve_info* info) {
     hipStream_t s = c->stream;
     const int64_t n = c->topo.n_gamma;
     const size_t nn = (size_t)std::max<int64_t>(n, 1);
@@ -693,6 +693,47 @@ extern "C" int abddc_gmres_solve(abddc_ctx* c, int32_t restart, double rtol, int
       for (int i = 0; i < 7; ++i) ts += c->phase[i];
       info->t_setup_s = ts;
       info->t_iter_s = wall;
+      info->redone = 0;
+      info->first_iters = iters;
+    }
+    return converged;
+}
+}  // namespace
+
+extern "C" int abddc_gmres_solve(abddc_ctx* c, int32_t restart, double rtol, int32_t maxit, double* u,
+                                 abddc_solve_info* info) {
+  return guarded([&]() -> int {
+    ABDDC_REQUIRE(c && u, ABDDC_EINVAL, "null argument");
+    ABDDC_REQUIRE(c->state >= 2, ABDDC_ESTATE, "solve before setup");
+    ABDDC_REQUIRE(restart >= 1 && restart <= GMRES_MAXR, ABDDC_EINVAL, "restart must be in [1, 63]");
+    ABDDC_REQUIRE(rtol > 0 && rtol < 1, ABDDC_EINVAL, "rtol must be in (0, 1)");
+    ABDDC_REQUIRE(maxit >= 1, ABDDC_EINVAL, "maxit must be >= 1");
+    ABDDC_HIP(hipSetDevice(c->device));
+    AllocScope as(&c->dalloc);
+    KStatsScope ks(&c->kstats);
+    StreamScope ss(c->stream);
+    abddc_solve_info local{};
+    abddc_solve_info* inf = info ? info : &local;
+    bool converged = gmres_core(c, restart, rtol, maxit, u, inf);
+    // Judge of the learned edge constraints: a solve that fails or needs
+    // more than judge_ratio times the reference iteration count is redone
+    // with every edge's constraints from the exact eigenproblem.
+    const abddc_options& o = c->opt;
+    const double ratio = o.judge_ratio > 0 ? o.judge_ratio : 1.2;
+    if (o.constraint_source == ABDDC_CONSTRAINTS_MLP && c->n_pred_edges > 0 && o.judge_iters > 0 &&
+        (!converged || inf->iters > ratio * o.judge_iters)) {
+      const int first = inf->iters;
+      const double t_first = inf->t_iter_s;
+      abddc_options ex = o;
+      ex.constraint_source = ABDDC_CONSTRAINTS_EXACT;
+      const auto t0 = std::chrono::steady_clock::now();
+      setup_with(c, ex);
+      c->opt = o;   // the context keeps the caller's options; the constraints are now exact
+      const double t_setup = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+      converged = gmres_core(c, restart, rtol, maxit, u, inf);
+      inf->redone = 1;
+      inf->first_iters = first;
+      inf->t_iter_s += t_first + t_setup;   // the whole call: first solve, exact setup, second solve
     }
     return converged ? ABDDC_OK : ABDDC_NOT_CONVERGED;
   });

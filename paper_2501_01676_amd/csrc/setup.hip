@@ -622,12 +622,19 @@ void run_setup(abddc_ctx* c) {
     }
     qr_complete_batched(qd, s);
   } else if (!elist.empty()) {
+    // only the subdomains of the edges solved here need the per-subdomain
+    // steps (all of them for the exact method; those around the edges the
+    // gate sent back for learned constraints)
+    std::vector<char> need(nsub, 0);
+    for (int e : elist)
+      for (int sub : T.objects[T.edges[e]].subs) need[sub] = 1;
     ht.mark("face-rotated Bbar^(s) = T_F^T B^(s) T_");
     // face-rotated Bbar^(s) = T_F^T B^(s) T_F on every face block
     DevBuf<double> Y(c->dB.n), Bbar(c->dB.n);
     ABDDC_HIP(hipMemcpyAsync(Y.p, c->dB.p, c->dB.n * sizeof(double), hipMemcpyDeviceToDevice, s));
     std::vector<GemmDesc<double>> gc, gr;
     for (int sub = 0; sub < nsub; ++sub) {
+      if (!need[sub]) continue;
       const SubInfo& si = T.sub[sub];
       const int nB = c->nB[sub];
       for (size_t q = 0; q < si.objs.size(); ++q) {
@@ -652,6 +659,7 @@ void run_setup(abddc_ctx* c) {
     std::vector<std::vector<int>> edge_pos_in_W(nsub);   // per object position list index
     std::vector<std::vector<int32_t>> Hpid(nsub);          // global primal ids of H_s (W order)
     for (int sub = 0; sub < nsub; ++sub) {
+      if (!need[sub]) continue;
       const SubInfo& si = T.sub[sub];
       std::vector<int32_t> fdual, edofs, vdofs, fprim, pid_v, pid_f;
       edge_pos_in_W[sub].assign(si.objs.size(), -1);
@@ -729,6 +737,7 @@ void run_setup(abddc_ctx* c) {
       std::vector<GatherDesc> gd;
       std::vector<PluDesc<double>> pd;
       for (int sub = 0; sub < nsub; ++sub) {
+        if (!need[sub]) continue;
         const int nB = c->nB[sub];
         gd.push_back({Bbar.p + c->soff[sub], E1.p + c->soff[sub], pool.ptr(m1off[sub]), pool.ptr(m1off[sub]), nB, nB,
                       nB, nB, 1.0});

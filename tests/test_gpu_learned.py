@@ -140,75 +140,140 @@ def test_edge_projectors_match_oracle():
     g.close()
 
 
+# thresholds at which part of the channel problem's edges select constraints
+# (about 7 % at Theta_E = 2; at 1.5 about 75 % do, but those projectors
+# depend on the coefficients of the whole neighbouring subdomains, which the
+# features do not see, and the gate returns nearly every edge to the exact
+# eigenproblem)
+THETA_F_L, THETA_E_L = 10.0, 2.0
+
+
+def _channels4(seed):
+    """4x4x4 subdomains, H/h = 8, nu = 1e-4 in 8 seeded straight channels of
+    2x2 elements, 1 elsewhere, a = (50, 20, 10): the channel workload at the
+    size of one eighth of its 8x8x8 form."""
+    widths = [[8] * 4] * 3
+    nu = W.channel_field(widths, 8, seed)
+    return W._problem((4, 4, 4), widths, nu, (50.0, 20.0, 10.0), name=f"channels4_{seed}")
+
+
+def _exact(p, **kw):
+    from paper_2501_01676_amd import api
+    g = api.Solver(p)
+    c = g.setup_coarse_space(theta_face=THETA_F_L, theta_edge=kw.pop("theta_edge", THETA_E_L), **kw)
+    return g, c
+
+
 def test_learned_setup_end_to_end():
-    """Train on exact setups of a few seeded channel problems, then solve a
-    held-out one with learned edge constraints.  Checks: every edge is
-    either predicted or sent back to the exact eigenproblem by the gate; the
-    face primals are untouched; the solve converges; the judge runs: the
-    eigenvalue bound of the exact method (min constrained quotient of
-    (Btilde~_E, M_E) >= 1 / Theta_E, from the oracle's edge operators) holds
-    on at least 90 % of the predicted edges, and the GMRES iteration ratio
-    is within 1.2 (+1) -- or, when it is not, the exact redo that the
-    policy then calls for reproduces the exact iteration count."""
+    """Train on exact setups of six seeded channel problems whose exact edge
+    eigenproblems select constraints on many edges, then solve held-out
+    seeds with learned edge constraints and compare with the exact method
+    and with no edge constraints at all.  Checks: non-trivial labels; the
+    loss falls; every edge is predicted or sent back by the gate; faces are
+    untouched; the solve converges; the eigenvalue bound of the exact method
+    (min constrained quotient of (Btilde~_E, M_E) >= 1 / Theta_E, from the
+    oracle's edge operators) holds on at least 90 % of the edges; the
+    iteration count is within the judge's 1.2 of the exact one, or the
+    library's judge redid the setup exactly; at least 80 % of the edges are
+    predicted.  (The edge-phase times are printed: at this size the exact
+    edge pipeline is bound by launch latency, so a smaller edge batch does
+    not make it faster; the gain is measured at full size by bench.py.)"""
     _need_gpu()
     from paper_2501_01676_amd import api
-    theta = 2.0
-    Xs, Ts = [], []
-    for seed in range(4):
-        g = api.Solver(_channel_problem(10 + seed))
-        g.setup_coarse_space(theta_face=theta, theta_edge=theta)
+    Xs, Ts, ref_iters, nonzero, total = [], [], [], 0, 0
+    for seed in range(20, 26):
+        g, c = _exact(_channels4(seed))
         X, el = g.edge_features()
         T = g.edge_projectors()
         keep = el.bool()
         Xs.append(X[keep])
         Ts.append(T[keep])
+        nonzero += int((T[keep].abs().sum(dim=1) > 0).sum().item())
+        total += int(keep.sum().item())
+        _, info = g.gmres_solve(30, 1e-8, 300, history=False)
+        ref_iters.append(info["iters"])
         g.close()
+    print(f"[learned] training edges {total}, with constraints {nonzero}; exact iterations {ref_iters}", flush=True)
+    assert nonzero >= 0.05 * total and nonzero <= 0.9 * total
     X = torch.cat(Xs).contiguous()
     T = torch.cat(Ts).contiguous()
     net = api.MLP(W.mlp_init_params(0))
     net.set_ranges(X)
     first = net.train_step(X, T, 1e-3, want_loss=True)
-    for _ in range(400):
+    for _ in range(600):
         net.train_step(X, T, 1e-3)
     last = net.train_step(X, T, 1e-3, want_loss=True)
-    print(f"[learned] training loss {first:.4g} -> {last:.4g} on {X.shape[0]} edges", flush=True)
+    print(f"[learned] training loss {first:.4g} -> {last:.4g}", flush=True)
     assert last < 0.5 * first
+    judge = max(ref_iters)
+    for seed in (90, 91):
+        p = _channels4(seed)
+        ge, ce = _exact(p)
+        _, ie = ge.gmres_solve(30, 1e-8, 300, history=False)
+        te = ge.phase_times()[4]
+        gn, cn = _exact(p, theta_edge=1e300)
+        _, i_none = gn.gmres_solve(30, 1e-8, 300, history=False)
+        gl, cl = _exact(p, constraint_source=1, mlp=net, judge_iters=judge)
+        st = gl.learned_stats()
+        tl = gl.phase_times()[4]
+        assert st["predicted"] + st["exact"] == gl.n_edge
+        assert cl["pnum_face"] == ce["pnum_face"]
+        cnt = gl.stage(6)
+        nf = gl.n_face
+        o = bddc.OracleBDDC(p)
+        o.assemble()
+        o.setup_coarse_space({"theta_face": THETA_F_L, "theta_edge": THETA_E_L})
+        ok = 0
+        for e, k in enumerate(o.topo.edges):
+            r = int(cnt[nf + e])
+            n = o.topo.objects[k]["nodes"].size
+            Tb = gl.stage(5, e).reshape(n, n)
+            aux = o.edge_aux[k]
+            q = Lr.constrained_min_quotient(aux["ME"], aux["BttE"], Tb[:, :r], aux["nE"], aux["m"])
+            ok += q >= (1.0 / THETA_E_L) * (1 - 1e-6)
+        u, il = gl.gmres_solve(30, 1e-8, 300, history=False)
+        print(f"[learned] seed {seed}: predicted {st['predicted']} exact {st['exact']}; pnumE learned "
+              f"{cl['pnum_edge']} exact {ce['pnum_edge']}; bound holds on {ok}/{gl.n_edge} edges; iterations "
+              f"learned {il['first_iters']} (redone {il['redone']}) exact {ie['iters']} none {i_none['iters']}; "
+              f"edge phase learned {tl * 1e3:.2f} ms exact {te * 1e3:.2f} ms", flush=True)
+        assert il["converged"] and il["relres_true"] <= 1e-8
+        assert gl.n_edge - ok <= 0.1 * gl.n_edge
+        assert il["redone"] or il["iters"] <= 1.2 * judge
+        assert st["predicted"] >= 0.8 * gl.n_edge
+        for g in (ge, gn, gl):
+            g.close()
+    net.close()
 
-    p = _channel_problem(99)
-    ge = api.Solver(p)
-    ce = ge.setup_coarse_space(theta_face=theta, theta_edge=theta)
-    _, ie = ge.gmres_solve(30, 1e-8, 300, history=False)
-    gl = api.Solver(p)
-    cl = gl.setup_coarse_space(theta_face=theta, theta_edge=theta, constraint_source=1, mlp=net)
-    st = gl.learned_stats()
-    assert st["predicted"] + st["exact"] == gl.n_edge
-    u, il = gl.gmres_solve(30, 1e-8, 300, history=False)
-    assert il["converged"] and il["relres_true"] <= 1e-8
-    assert cl["pnum_face"] == ce["pnum_face"]
-    o = bddc.OracleBDDC(p)
-    o.assemble()
-    o.setup_coarse_space({"theta_face": theta, "theta_edge": theta})
-    cnt = gl.stage(6)
-    nf = gl.n_face
-    ok = 0
-    for e, k in enumerate(o.topo.edges):
-        r = int(cnt[nf + e])
-        n = o.topo.objects[k]["nodes"].size
-        Tb = gl.stage(5, e).reshape(n, n)
-        aux = o.edge_aux[k]
-        q = Lr.constrained_min_quotient(aux["ME"], aux["BttE"], Tb[:, :r], aux["nE"], aux["m"])
-        ok += q >= (1.0 / theta) * (1 - 1e-6)
-    print(f"[learned] predicted {st['predicted']} exact {st['exact']}; bound holds on {ok}/{gl.n_edge} edges; "
-          f"iterations learned {il['iters']} exact {ie['iters']}", flush=True)
-    assert gl.n_edge - ok <= 0.1 * max(st["predicted"], 1)
-    if il["iters"] > 1.2 * ie["iters"] + 1:
-        gr = api.Solver(p)
-        gr.setup_coarse_space(theta_face=theta, theta_edge=theta)
-        _, ir = gr.gmres_solve(30, 1e-8, 300, history=False)
-        assert ir["iters"] == ie["iters"]
-        gr.close()
+
+def test_judge_redoes_with_exact_constraints():
+    """The library's judge: a network that predicts no constraint on any
+    edge (zero weights, every edge inside the training range) with a tight
+    reference iteration count makes gmres_solve redo the setup with the exact
+    edge eigenproblems and solve again -- bit for bit the exact solve; without
+    a reference, or with a loose one, nothing is redone."""
+    _need_gpu()
+    from paper_2501_01676_amd import api
+    p = _channels4(30)
+    ge, ce = _exact(p)
+    ue, ie = ge.gmres_solve(30, 1e-8, 300)
+    X, _ = ge.edge_features()
+    from paper_2501_01676_amd import _lib as L
+    net = api.MLP(np.zeros(L.MLP_PARAMS, dtype=np.float32))
+    net.set_ranges(X)
+    for judge, expect in ((1, True), (0, False), (1000, False)):
+        gl, cl = _exact(p, constraint_source=1, mlp=net, judge_iters=judge)
+        st = gl.learned_stats()
+        assert st["predicted"] > 0 and cl["pnum_edge"] < ce["pnum_edge"]
+        ul, il = gl.gmres_solve(30, 1e-8, 300)
+        assert il["redone"] == expect
+        if expect:
+            assert il["first_iters"] > 1.2 * judge
+            assert il["iters"] == ie["iters"] and torch.equal(ul, ue)
+            assert gl.learned_stats() == {"predicted": 0, "exact": gl.n_edge}
+        else:
+            assert il["first_iters"] == il["iters"]
+        gl.close()
     ge.close()
-    gl.close()
     net.close()
 
 
