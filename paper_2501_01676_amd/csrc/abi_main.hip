@@ -18,6 +18,7 @@
 #include "ctx.h"
 #include "guard.h"
 #include "htrace.h"
+#include "host_pool.h"
 #include "internal.h"
 
 namespace abddc {
@@ -325,7 +326,8 @@ extern "C" int abddc_assemble(const abddc_problem* prob, const abddc_device* dev
     c->ioff.resize(nsub);
     int64_t at = 0, st = 0, gt = 0, it = 0, rows = 0, lmt = 0;
     std::vector<SubAsm> sa(nsub);
-    std::vector<int32_t> lnode, rowsub, lmap, gam, int_dof;
+    // offsets of every subdomain in each array, serially; the maps are then
+    // filled per subdomain in parallel
     for (int sub = 0; sub < nsub; ++sub) {
       const SubInfo& si = T.sub[sub];
       c->nI[sub] = si.nI;
@@ -354,44 +356,57 @@ extern "C" int abddc_assemble(const abddc_problem* prob, const abddc_device* dev
       st += (int64_t)si.nB * si.nB;
       gt += si.nB;
       it += si.nI;
-      // local node list [interior; Gamma_i] and the box-local map, walking
-      // the grid index boxes (node-id order) of the interior and of every
-      // interface object
-      const int e0[3] = {si.ebox[0][0], si.ebox[1][0], si.ebox[2][0]};
-      const int bx = si.ebox[0][1] - e0[0] + 1, by = si.ebox[1][1] - e0[1] + 1, bz = si.ebox[2][1] - e0[2] + 1;
-      const size_t b0 = lmap.size();
-      lmap.resize(b0 + (size_t)bx * by * bz, -1);
-      int loc = 0;
-      auto walk = [&](const int* lo, const int* hi, bool interior) {
-        for (int iz = lo[2]; iz <= hi[2]; ++iz)
-          for (int iy = lo[1]; iy <= hi[1]; ++iy) {
-            const int64_t row = T.node_id(0, iy, iz);
-            const size_t brow = b0 + (size_t)bx * ((iy - e0[1]) + (size_t)by * (iz - e0[2])) - e0[0];
-            for (int ix = lo[0]; ix <= hi[0]; ++ix) {
-              lnode.push_back((int32_t)(row + ix));
-              lmap[brow + ix] = loc++;
-              if (interior) int_dof.push_back((int32_t)T.dof_of_node[row + ix]);
-            }
-          }
-      };
-      const int ilo[3] = {e0[0] + 1, e0[1] + 1, e0[2] + 1};
-      const int ihi[3] = {si.ebox[0][1] - 1, si.ebox[1][1] - 1, si.ebox[2][1] - 1};
-      walk(ilo, ihi, true);
-      for (int k : si.objs) walk(T.objects[k].lo, T.objects[k].hi, false);
-      rowsub.insert(rowsub.end(), (size_t)loc, sub);
-      for (int64_t g : si.gamma) gam.push_back((int32_t)g);
-      lmt += (int64_t)bx * by * bz;
+      lmt += (int64_t)(si.ebox[0][1] - si.ebox[0][0] + 1) * (si.ebox[1][1] - si.ebox[1][0] + 1) *
+             (si.ebox[2][1] - si.ebox[2][0] + 1);
       rows += c->nloc[sub];
     }
     ABDDC_REQUIRE(T.n_nodes < (int64_t)1 << 31 && lmt < (int64_t)1 << 31, ABDDC_EINVAL, "mesh too large");
+    std::vector<int32_t> lnode(rows), rowsub(rows), lmap(lmt, -1), gam(gt), int_dof(it);
+    host_parallel_for(nsub, 4, [&](int64_t sb, int64_t se) {
+      for (int sub = (int)sb; sub < (int)se; ++sub) {
+        const SubInfo& si = T.sub[sub];
+        const SubAsm& a = sa[sub];
+        // local node list [interior; Gamma_i] and the box-local map, walking
+        // the grid index boxes (node-id order) of the interior and of every
+        // interface object
+        const int e0[3] = {si.ebox[0][0], si.ebox[1][0], si.ebox[2][0]};
+        const int bx = si.ebox[0][1] - e0[0] + 1, by = si.ebox[1][1] - e0[1] + 1;
+        const size_t b0 = (size_t)a.lmoff;
+        int32_t* ln = lnode.data() + a.loff;
+        int32_t* idof = int_dof.data() + a.ioff;
+        int loc = 0;
+        auto walk = [&](const int* lo, const int* hi, bool interior) {
+          for (int iz = lo[2]; iz <= hi[2]; ++iz)
+            for (int iy = lo[1]; iy <= hi[1]; ++iy) {
+              const int64_t row = T.node_id(0, iy, iz);
+              const size_t brow = b0 + (size_t)bx * ((iy - e0[1]) + (size_t)by * (iz - e0[2])) - e0[0];
+              for (int ix = lo[0]; ix <= hi[0]; ++ix) {
+                if (interior) idof[loc] = (int32_t)T.dof_of_node[row + ix];
+                ln[loc] = (int32_t)(row + ix);
+                lmap[brow + ix] = loc++;
+              }
+            }
+        };
+        const int ilo[3] = {e0[0] + 1, e0[1] + 1, e0[2] + 1};
+        const int ihi[3] = {si.ebox[0][1] - 1, si.ebox[1][1] - 1, si.ebox[2][1] - 1};
+        walk(ilo, ihi, true);
+        for (int k : si.objs) walk(T.objects[k].lo, T.objects[k].hi, false);
+        std::fill(rowsub.begin() + a.loff, rowsub.begin() + a.loff + loc, sub);
+        for (int l = 0; l < si.nB; ++l) gam[a.goff + l] = (int32_t)si.gamma[l];
+      }
+    });
     ht.mark("assemble: local layout maps");
     c->d_subs = to_device(sa, s);
     DevBuf<int32_t> d_lnode = to_device(lnode, s), d_rowsub = to_device(rowsub, s), d_lmap = to_device(lmap, s);
     c->d_gam = to_device(gam, s);
     c->d_int_dof = to_device(int_dof, s);
     std::vector<int32_t> iface_dof(T.n_gamma);
-    for (const Object& o : T.objects)
-      for (int q = 0; q < o.n; ++q) iface_dof[o.gstart + q] = (int32_t)T.dof_of_node[o.nodes[q]];
+    host_parallel_for((int64_t)T.objects.size(), 64, [&](int64_t b, int64_t e) {
+      for (int64_t k = b; k < e; ++k) {
+        const Object& o = T.objects[k];
+        for (int q = 0; q < o.n; ++q) iface_dof[o.gstart + q] = (int32_t)T.dof_of_node[o.nodes[q]];
+      }
+    });
     c->d_iface_dof = to_device(iface_dof, s);
     ht.mark("assemble: uploads");
     // -------------------------------------------- element matrices + scatter

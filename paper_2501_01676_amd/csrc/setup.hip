@@ -15,6 +15,7 @@
 #include "apply.h"
 #include "arena.h"
 #include "ctx.h"
+#include "host_pool.h"
 #include "htrace.h"
 #include "internal.h"
 #include "mlp.h"
@@ -32,6 +33,13 @@ struct IntPool {
   size_t add(const std::vector<int32_t>& v) {
     size_t off = h.size();
     h.insert(h.end(), v.begin(), v.end());
+    return off;
+  }
+  // n uninitialised entries at the end, filled later through h.data() + off
+  // (after every block is reserved, so the storage no longer moves)
+  size_t reserve(size_t n) {
+    size_t off = h.size();
+    h.resize(off + n);
     return off;
   }
   void upload(hipStream_t s) {
@@ -658,41 +666,47 @@ void run_setup(abddc_ctx* c) {
     std::vector<int> nfd(nsub), nW(nsub), nedof(nsub);
     std::vector<std::vector<int>> edge_pos_in_W(nsub);   // per object position list index
     std::vector<std::vector<int32_t>> Hpid(nsub);          // global primal ids of H_s (W order)
-    for (int sub = 0; sub < nsub; ++sub) {
-      if (!need[sub]) continue;
-      const SubInfo& si = T.sub[sub];
+    std::vector<std::vector<int32_t>> m1(nsub);
+    host_parallel_for(nsub, 8, [&](int64_t sb, int64_t se) {
       std::vector<int32_t> fdual, edofs, vdofs, fprim, pid_v, pid_f;
-      edge_pos_in_W[sub].assign(si.objs.size(), -1);
-      for (size_t q = 0; q < si.objs.size(); ++q) {
-        const int k = si.objs[q];
-        const Object& o = T.objects[k];
-        const int off = si.obj_off[q];
-        if (o.kind == KIND_FACE) {
-          const int f = T.kind_index[k], p = c->pF[f];
-          for (int l = 0; l < p; ++l) {
-            fprim.push_back(off + l);
-            pid_f.push_back(face_pbase[f] + l);
+      for (int sub = (int)sb; sub < (int)se; ++sub) {
+        if (!need[sub]) continue;
+        const SubInfo& si = T.sub[sub];
+        fdual.clear(), edofs.clear(), vdofs.clear(), fprim.clear(), pid_v.clear(), pid_f.clear();
+        edge_pos_in_W[sub].assign(si.objs.size(), -1);
+        for (size_t q = 0; q < si.objs.size(); ++q) {
+          const int k = si.objs[q];
+          const Object& o = T.objects[k];
+          const int off = si.obj_off[q];
+          if (o.kind == KIND_FACE) {
+            const int f = T.kind_index[k], p = c->pF[f];
+            for (int l = 0; l < p; ++l) {
+              fprim.push_back(off + l);
+              pid_f.push_back(face_pbase[f] + l);
+            }
+            for (int l = p; l < o.n; ++l) fdual.push_back(off + l);
+          } else if (o.kind == KIND_EDGE) {
+            edge_pos_in_W[sub][q] = (int)edofs.size();
+            for (int l = 0; l < o.n; ++l) edofs.push_back(off + l);
+          } else {
+            vdofs.push_back(off);
+            pid_v.push_back(T.kind_index[k]);
           }
-          for (int l = p; l < o.n; ++l) fdual.push_back(off + l);
-        } else if (o.kind == KIND_EDGE) {
-          edge_pos_in_W[sub][q] = (int)edofs.size();
-          for (int l = 0; l < o.n; ++l) edofs.push_back(off + l);
-        } else {
-          vdofs.push_back(off);
-          pid_v.push_back(T.kind_index[k]);
         }
+        std::vector<int32_t>& mp = m1[sub];
+        mp = fdual;
+        mp.insert(mp.end(), edofs.begin(), edofs.end());
+        mp.insert(mp.end(), vdofs.begin(), vdofs.end());
+        mp.insert(mp.end(), fprim.begin(), fprim.end());
+        nfd[sub] = (int)fdual.size();
+        nedof[sub] = (int)edofs.size();
+        nW[sub] = c->nB[sub] - nfd[sub];
+        Hpid[sub] = pid_v;
+        Hpid[sub].insert(Hpid[sub].end(), pid_f.begin(), pid_f.end());
       }
-      std::vector<int32_t> mp = fdual;
-      mp.insert(mp.end(), edofs.begin(), edofs.end());
-      mp.insert(mp.end(), vdofs.begin(), vdofs.end());
-      mp.insert(mp.end(), fprim.begin(), fprim.end());
-      m1off[sub] = pool.add(mp);
-      nfd[sub] = (int)fdual.size();
-      nedof[sub] = (int)edofs.size();
-      nW[sub] = c->nB[sub] - nfd[sub];
-      Hpid[sub] = pid_v;
-      Hpid[sub].insert(Hpid[sub].end(), pid_f.begin(), pid_f.end());
-    }
+    });
+    for (int sub = 0; sub < nsub; ++sub)
+      if (need[sub]) m1off[sub] = pool.add(m1[sub]);
     ht.mark("stage 2 maps per (edge, member): [othe");
     // stage 2 maps per (edge, member): [other edge dofs; E dofs; H] inside W
     std::vector<size_t> m2off((size_t)ned * 4);
@@ -700,37 +714,48 @@ void run_setup(abddc_ctx* c) {
     std::vector<size_t> roff((size_t)ned * 4);
     std::vector<int> nHunion(ned);
     int64_t e2tot = 0;
+    const bool separate = c->opt.edge_h_mode == ABDDC_H_SEPARATE;
     for (int e : elist) {
-      const int k = T.edges[e];
-      const Object& o = T.objects[k];
-      std::vector<int32_t> uni;
-      for (int sub : o.subs) uni.insert(uni.end(), Hpid[sub].begin(), Hpid[sub].end());
-      std::sort(uni.begin(), uni.end());
-      uni.erase(std::unique(uni.begin(), uni.end()), uni.end());
-      const bool separate = c->opt.edge_h_mode == ABDDC_H_SEPARATE;
-      int hbase = 0;
+      const Object& o = T.objects[T.edges[e]];
       for (size_t q = 0; q < o.subs.size(); ++q) {
         const int sub = o.subs[q];
-        const SubInfo& si = T.sub[sub];
-        const int qi = (int)(std::lower_bound(si.objs.begin(), si.objs.end(), k) - si.objs.begin());
-        const int epos = edge_pos_in_W[sub][qi];
-        std::vector<int32_t> mp;
-        for (int t = 0; t < nedof[sub]; ++t)
-          if (t < epos || t >= epos + o.n) mp.push_back(t);
-        for (int t = 0; t < o.n; ++t) mp.push_back(epos + t);
-        for (int t = nedof[sub]; t < nW[sub]; ++t) mp.push_back(t);
-        m2off[(size_t)e * 4 + q] = pool.add(mp);
+        m2off[(size_t)e * 4 + q] = pool.reserve(nW[sub]);
         e2off[(size_t)e * 4 + q] = e2tot;
         e2tot += (int64_t)nW[sub] * nW[sub];
-        std::vector<int32_t> R;
-        for (size_t h = 0; h < Hpid[sub].size(); ++h)
-          R.push_back(separate ? hbase + (int)h
-                               : (int)(std::lower_bound(uni.begin(), uni.end(), Hpid[sub][h]) - uni.begin()));
-        hbase += (int)Hpid[sub].size();
-        roff[(size_t)e * 4 + q] = pool.add(R);
+        roff[(size_t)e * 4 + q] = pool.reserve(Hpid[sub].size());
       }
-      nHunion[e] = separate ? hbase : (int)uni.size();
     }
+    host_parallel_for((int64_t)elist.size(), 16, [&](int64_t eb, int64_t ee) {
+      std::vector<int32_t> uni;
+      for (int64_t ei = eb; ei < ee; ++ei) {
+        const int e = elist[ei];
+        const int k = T.edges[e];
+        const Object& o = T.objects[k];
+        uni.clear();
+        for (int sub : o.subs) uni.insert(uni.end(), Hpid[sub].begin(), Hpid[sub].end());
+        std::sort(uni.begin(), uni.end());
+        uni.erase(std::unique(uni.begin(), uni.end()), uni.end());
+        int hbase = 0;
+        for (size_t q = 0; q < o.subs.size(); ++q) {
+          const int sub = o.subs[q];
+          const SubInfo& si = T.sub[sub];
+          const int qi = (int)(std::lower_bound(si.objs.begin(), si.objs.end(), k) - si.objs.begin());
+          const int epos = edge_pos_in_W[sub][qi];
+          int32_t* mp = pool.h.data() + m2off[(size_t)e * 4 + q];
+          int t2 = 0;
+          for (int t = 0; t < nedof[sub]; ++t)
+            if (t < epos || t >= epos + o.n) mp[t2++] = t;
+          for (int t = 0; t < o.n; ++t) mp[t2++] = epos + t;
+          for (int t = nedof[sub]; t < nW[sub]; ++t) mp[t2++] = t;
+          int32_t* R = pool.h.data() + roff[(size_t)e * 4 + q];
+          for (size_t h = 0; h < Hpid[sub].size(); ++h)
+            R[h] = separate ? hbase + (int)h
+                            : (int)(std::lower_bound(uni.begin(), uni.end(), Hpid[sub][h]) - uni.begin());
+          hbase += (int)Hpid[sub].size();
+        }
+        nHunion[e] = separate ? hbase : (int)uni.size();
+      }
+    });
     pool.upload(s);
     DevBuf<double> E1(c->dB.n);
     {
@@ -978,41 +1003,53 @@ void run_setup(abddc_ctx* c) {
     ht.mark("augmented [[Sdd, Sdp, I], [Spd, Spp, 0");
     // augmented [[Sdd, Sdp, I], [Spd, Spp, 0], [-I, 0, 0]], eliminate Delta
     IntPool pool;
-    std::vector<size_t> am(nsub), dr(nsub), dc(nsub), kt(nsub), vr(nsub), vc(nsub), ur(nsub), uc(nsub), pi_off(nsub),
+    std::vector<size_t> am(nsub), dr(nsub), dc(nsub), kt(nsub), vr(nsub), vc(nsub), ur(nsub), pi_off(nsub),
         pidx(nsub), iota_off(nsub);
+    size_t total = 0;
+    for (int sub = 0; sub < nsub; ++sub)
+      total += 6 * Dl[sub].size() + 4 * Pi[sub].size() + c->nB[sub] + Pid[sub].size();
+    pool.h.reserve(total);
     for (int sub = 0; sub < nsub; ++sub) {
-      const int nB = c->nB[sub], nP = (int)Pi[sub].size(), nD = (int)Dl[sub].size();
-      std::vector<int32_t> mp = Dl[sub];
-      mp.insert(mp.end(), Pi[sub].begin(), Pi[sub].end());
-      for (int q = 0; q < nD; ++q) mp.push_back(-1);
-      am[sub] = pool.add(mp);
-      std::vector<int32_t> r1(nD), c1(nD), r2(nD), c2(nD);
-      for (int q = 0; q < nD; ++q) {
-        r1[q] = q;
-        c1[q] = nD + nP + q;
-        r2[q] = nD + nP + q;
-        c2[q] = q;
-      }
-      dr[sub] = pool.add(r1);
-      dc[sub] = pool.add(c1);
-      kt[sub] = pool.add(r2);
-      (void)c2;
-      vr[sub] = pool.add(c2);
-      // Ktilde map (local coordinate q -> aug row/col of K), -1 on Pi
-      std::vector<int32_t> km(nB, -1);
-      for (int q = 0; q < nD; ++q) km[Dl[sub][q]] = nD + nP + q;
-      vc[sub] = pool.add(km);
-      // Pi rows of the aug matrix and the -Phi columns
-      std::vector<int32_t> pr(nP), pc(nP), it(nP);
-      for (int l = 0; l < nP; ++l) {
-        pr[l] = nD + l;
-        it[l] = l;
-      }
-      ur[sub] = pool.add(pr);
-      pi_off[sub] = pool.add(Pi[sub]);
-      iota_off[sub] = pool.add(it);
-      pidx[sub] = pool.add(Pid[sub]);
+      const size_t nB = c->nB[sub], nP = Pi[sub].size(), nD = Dl[sub].size();
+      am[sub] = pool.reserve(2 * nD + nP);
+      dr[sub] = pool.reserve(nD);
+      dc[sub] = pool.reserve(nD);
+      kt[sub] = pool.reserve(nD);
+      vr[sub] = pool.reserve(nD);
+      vc[sub] = pool.reserve(nB);
+      ur[sub] = pool.reserve(nP);
+      pi_off[sub] = pool.reserve(nP);
+      iota_off[sub] = pool.reserve(nP);
+      pidx[sub] = pool.reserve(Pid[sub].size());
     }
+    host_parallel_for(nsub, 8, [&](int64_t sb, int64_t se) {
+      for (int sub = (int)sb; sub < (int)se; ++sub) {
+        const int nB = c->nB[sub], nP = (int)Pi[sub].size(), nD = (int)Dl[sub].size();
+        int32_t* h = pool.h.data();
+        // aug row/col -> local coordinate: [Delta; Pi; -1 for the multipliers]
+        int32_t* mp = h + am[sub];
+        std::copy(Dl[sub].begin(), Dl[sub].end(), mp);
+        std::copy(Pi[sub].begin(), Pi[sub].end(), mp + nD);
+        std::fill(mp + nD + nP, mp + 2 * nD + nP, -1);
+        for (int q = 0; q < nD; ++q) {
+          h[dr[sub] + q] = q;               // identity block rows ...
+          h[dc[sub] + q] = nD + nP + q;     // ... and columns
+          h[kt[sub] + q] = nD + nP + q;     // -identity block rows ...
+          h[vr[sub] + q] = q;               // ... and columns
+        }
+        // Ktilde map (local coordinate q -> aug row/col of K), -1 on Pi
+        int32_t* km = h + vc[sub];
+        std::fill(km, km + nB, -1);
+        for (int q = 0; q < nD; ++q) km[Dl[sub][q]] = nD + nP + q;
+        // Pi rows of the aug matrix and the -Phi columns
+        for (int l = 0; l < nP; ++l) {
+          h[ur[sub] + l] = nD + l;
+          h[iota_off[sub] + l] = l;
+        }
+        std::copy(Pi[sub].begin(), Pi[sub].end(), h + pi_off[sub]);
+        std::copy(Pid[sub].begin(), Pid[sub].end(), h + pidx[sub]);
+      }
+    });
     pool.upload(s);
     std::vector<GatherDesc> gd;
     std::vector<SetDesc> st;

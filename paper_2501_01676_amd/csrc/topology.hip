@@ -2,7 +2,9 @@
 #include "topology.h"
 
 #include <algorithm>
+#include <array>
 
+#include "host_pool.h"
 #include "internal.h"
 
 namespace abddc {
@@ -56,46 +58,53 @@ void Topology::build_objects() {
   }
   // free nodes: the grid minus its boundary, numbered by node id
   dof_of_node.assign(n_nodes, -1);
-  for (int iz = 1; iz < nn[2] - 1; ++iz)
-    for (int iy = 1; iy < nn[1] - 1; ++iy) {
-      const int64_t base = node_id(0, iy, iz);
-      const int64_t d0 = (int64_t)(nn[0] - 2) * ((iy - 1) + (int64_t)(nn[1] - 2) * (iz - 1)) - 1;
-      for (int ix = 1; ix < nn[0] - 1; ++ix) dof_of_node[base + ix] = d0 + ix;
-    }
+  host_parallel_for(std::max(nn[2] - 2, 0), 4, [&](int64_t b, int64_t e) {
+    for (int iz = 1 + (int)b; iz < 1 + (int)e; ++iz)
+      for (int iy = 1; iy < nn[1] - 1; ++iy) {
+        const int64_t base = node_id(0, iy, iz);
+        const int64_t d0 = (int64_t)(nn[0] - 2) * ((iy - 1) + (int64_t)(nn[1] - 2) * (iz - 1)) - 1;
+        for (int ix = 1; ix < nn[0] - 1; ++ix) dof_of_node[base + ix] = d0 + ix;
+      }
+  });
   n_dof = (int64_t)(nn[0] - 2) * (nn[1] - 2) * (nn[2] - 2);
   iface_of_node.assign(n_nodes, -1);
   objects.clear();
   const int nk[3] = {2 * nsub[0] - 1, 2 * nsub[1] - 1, 2 * nsub[2] - 1};
-  for (int kz = 0; kz < nk[2]; ++kz)
-    for (int ky = 0; ky < nk[1]; ++ky)
-      for (int kx = 0; kx < nk[0]; ++kx) {
-        const int odd = (kx & 1) + (ky & 1) + (kz & 1);
-        if (odd == 0) continue;
-        Object o;
-        o.kind = odd == 1 ? KIND_FACE : (odd == 2 ? KIND_EDGE : KIND_VERTEX);
-        const int key[3] = {kx, ky, kz};
-        int slo[3], shi[3];
-        for (int a = 0; a < 3; ++a) {
-          o.lo[a] = klo[a][key[a]];
-          o.hi[a] = khi[a][key[a]];
-          slo[a] = key[a] / 2;
-          shi[a] = (key[a] + 1) / 2;
-        }
-        for (int sz = slo[2]; sz <= shi[2]; ++sz)
-          for (int sy = slo[1]; sy <= shi[1]; ++sy)
-            for (int sx = slo[0]; sx <= shi[0]; ++sx) o.subs.push_back(sub_id(sx, sy, sz));
-        std::sort(o.subs.begin(), o.subs.end());
-        o.nodes.reserve((size_t)(o.hi[0] - o.lo[0] + 1) * (o.hi[1] - o.lo[1] + 1) * (o.hi[2] - o.lo[2] + 1));
-        for (int iz = o.lo[2]; iz <= o.hi[2]; ++iz)
-          for (int iy = o.lo[1]; iy <= o.hi[1]; ++iy)
-            for (int ix = o.lo[0]; ix <= o.hi[0]; ++ix) o.nodes.push_back(node_id(ix, iy, iz));
-        o.n = (int)o.nodes.size();
-        objects.push_back(std::move(o));
+  // key triples in interface order: faces, edges, vertices, each by their
+  // first node id, which grows with (kz, ky, kx) lexicographically because
+  // every range's lower end grows with its key
+  std::vector<std::array<int, 3>> keys;
+  for (int odd = 1; odd <= 3; ++odd)
+    for (int kz = 0; kz < nk[2]; ++kz)
+      for (int ky = 0; ky < nk[1]; ++ky)
+        for (int kx = 0; kx < nk[0]; ++kx)
+          if ((kx & 1) + (ky & 1) + (kz & 1) == odd) keys.push_back({kx, ky, kz});
+  objects.resize(keys.size());
+  host_parallel_for((int64_t)keys.size(), 64, [&](int64_t b, int64_t e) {
+    for (int64_t q = b; q < e; ++q) {
+      const int* key = keys[q].data();
+      const int odd = (key[0] & 1) + (key[1] & 1) + (key[2] & 1);
+      Object& o = objects[q];
+      o.kind = odd == 1 ? KIND_FACE : (odd == 2 ? KIND_EDGE : KIND_VERTEX);
+      int slo[3], shi[3];
+      for (int a = 0; a < 3; ++a) {
+        o.lo[a] = klo[a][key[a]];
+        o.hi[a] = khi[a][key[a]];
+        slo[a] = key[a] / 2;
+        shi[a] = (key[a] + 1) / 2;
       }
-  std::sort(objects.begin(), objects.end(), [](const Object& a, const Object& b) {
-    if (a.kind != b.kind) return a.kind < b.kind;
-    return a.nodes[0] < b.nodes[0];
+      for (int sz = slo[2]; sz <= shi[2]; ++sz)
+        for (int sy = slo[1]; sy <= shi[1]; ++sy)
+          for (int sx = slo[0]; sx <= shi[0]; ++sx) o.subs.push_back(sub_id(sx, sy, sz));
+      std::sort(o.subs.begin(), o.subs.end());
+      o.nodes.reserve((size_t)(o.hi[0] - o.lo[0] + 1) * (o.hi[1] - o.lo[1] + 1) * (o.hi[2] - o.lo[2] + 1));
+      for (int iz = o.lo[2]; iz <= o.hi[2]; ++iz)
+        for (int iy = o.lo[1]; iy <= o.hi[1]; ++iy)
+          for (int ix = o.lo[0]; ix <= o.hi[0]; ++ix) o.nodes.push_back(node_id(ix, iy, iz));
+      o.n = (int)o.nodes.size();
+    }
   });
+
   faces.clear();
   edges.clear();
   vertices.clear();
@@ -104,40 +113,49 @@ void Topology::build_objects() {
   for (size_t k = 0; k < objects.size(); ++k) {
     Object& o = objects[k];
     o.gstart = g;
-    for (int q = 0; q < o.n; ++q) iface_of_node[o.nodes[q]] = g + q;
     g += o.n;
     std::vector<int>& lst = o.kind == KIND_FACE ? faces : (o.kind == KIND_EDGE ? edges : vertices);
     kind_index[k] = (int)lst.size();
     lst.push_back((int)k);
   }
   n_gamma = g;
+  host_parallel_for((int64_t)objects.size(), 64, [&](int64_t b, int64_t e) {
+    for (int64_t k = b; k < e; ++k) {
+      const Object& o = objects[k];
+      for (int q = 0; q < o.n; ++q) iface_of_node[o.nodes[q]] = o.gstart + q;
+    }
+  });
 
   sub.assign(n_sub, SubInfo());
-  for (int s = 0; s < n_sub; ++s) {
-    const int sx = s % nsub[0], sy = (s / nsub[0]) % nsub[1], sz = s / (nsub[0] * nsub[1]);
-    const int sc[3] = {sx, sy, sz};
-    SubInfo& si = sub[s];
-    for (int a = 0; a < 3; ++a) {
-      si.ebox[a][0] = cuts[a][sc[a]];
-      si.ebox[a][1] = cuts[a][sc[a] + 1];
-    }
-    for (int iz = si.ebox[2][0] + 1; iz < si.ebox[2][1]; ++iz)
-      for (int iy = si.ebox[1][0] + 1; iy < si.ebox[1][1]; ++iy)
-        for (int ix = si.ebox[0][0] + 1; ix < si.ebox[0][1]; ++ix) si.interior.push_back(node_id(ix, iy, iz));
-    si.nI = (int)si.interior.size();
-  }
   for (size_t k = 0; k < objects.size(); ++k)
     for (int s : objects[k].subs) sub[s].objs.push_back((int)k);
-  for (int s = 0; s < n_sub; ++s) {
-    SubInfo& si = sub[s];
-    int pos = 0;
-    for (int k : si.objs) {
-      si.obj_off.push_back(pos);
-      for (int q = 0; q < objects[k].n; ++q) si.gamma.push_back(objects[k].gstart + q);
-      pos += objects[k].n;
+  host_parallel_for(n_sub, 8, [&](int64_t b, int64_t e) {
+    for (int s = (int)b; s < (int)e; ++s) {
+      const int sx = s % nsub[0], sy = (s / nsub[0]) % nsub[1], sz = s / (nsub[0] * nsub[1]);
+      const int sc[3] = {sx, sy, sz};
+      SubInfo& si = sub[s];
+      for (int a = 0; a < 3; ++a) {
+        si.ebox[a][0] = cuts[a][sc[a]];
+        si.ebox[a][1] = cuts[a][sc[a] + 1];
+      }
+      si.interior.reserve((size_t)(si.ebox[0][1] - si.ebox[0][0] - 1) * (si.ebox[1][1] - si.ebox[1][0] - 1) *
+                          (si.ebox[2][1] - si.ebox[2][0] - 1));
+      for (int iz = si.ebox[2][0] + 1; iz < si.ebox[2][1]; ++iz)
+        for (int iy = si.ebox[1][0] + 1; iy < si.ebox[1][1]; ++iy)
+          for (int ix = si.ebox[0][0] + 1; ix < si.ebox[0][1]; ++ix) si.interior.push_back(node_id(ix, iy, iz));
+      si.nI = (int)si.interior.size();
+      int pos = 0;
+      for (int k : si.objs) pos += objects[k].n;
+      si.gamma.reserve(pos);
+      pos = 0;
+      for (int k : si.objs) {
+        si.obj_off.push_back(pos);
+        for (int q = 0; q < objects[k].n; ++q) si.gamma.push_back(objects[k].gstart + q);
+        pos += objects[k].n;
+      }
+      si.nB = pos;
     }
-    si.nB = pos;
-  }
+  });
 }
 
 }  // namespace abddc
