@@ -1,8 +1,11 @@
 """Seeded synthetic problem generators (inputs only, no method arithmetic).
 
-Every workload is the model advection-diffusion problem of Section 2 on the
-unit cube with zero Dirichlet data, discretised by trilinear (Q1) boxes and
-split into a tensor-product box partition.  A problem is a plain dict that
+Every workload is the model advection-diffusion problem of Section 2 on a
+box grid split into a tensor-product box partition: the synthetic configs on
+the unit cube with zero Dirichlet data and trilinear (Q1) boxes, Section 4's
+example (``example_helicoid``, ``example_random``) with six linear
+tetrahedra per box, a nodal velocity and lifted Dirichlet data.  A problem is
+a plain dict that
 both the GPU library binding and the test oracle read; nothing here computes
 any part of the method.
 
@@ -18,6 +21,14 @@ f_const / f_nodal : constant source, or source values at every grid node
                     (x-fastest, (nx_e+1)(ny_e+1)(nz_e+1) values) interpolated
                     trilinearly; f_nodal overrides f_const when not None
 tau    : stabilisation constant of the GLS parameter (0.7 in the paper)
+element: "q1" (trilinear boxes) or "p1" (six Kuhn tetrahedra per box; nu
+         then holds six values per box, tetrahedra in the order of the axis
+         permutations xyz, xzy, yxz, yzx, zxy, zyx)
+origin : coordinates of grid node (0, 0, 0)
+a_nodal: None (affine velocity) or the velocity at every grid node (3 per
+         node, node-id order); "p1" only
+u_dirichlet : None (zero data) or a value per grid node, of which the
+         boundary nodes' are the Dirichlet data
 
 The random draws (viscosity fields, widths, channels) use
 ``numpy.random.default_rng(seed)`` so that both sides of any comparison see
@@ -31,16 +42,22 @@ THETA_DEFAULT = 10.0
 
 
 def _problem(nsub, widths, nu, beta0, beta1=None, c=0.0, f_const=1.0,
-             f_nodal=None, tau=0.7, length=(1.0, 1.0, 1.0), name=""):
+             f_nodal=None, tau=0.7, length=(1.0, 1.0, 1.0), name="", element="q1",
+             origin=(0.0, 0.0, 0.0), a_nodal=None, u_dirichlet=None):
     widths = [np.asarray(w, dtype=np.int32) for w in widths]
     ne = [int(w.sum()) for w in widths]
+    per = 6 if element == "p1" else 1
     nu = np.asarray(nu, dtype=np.float64)
     if nu.ndim == 0:
-        nu = np.full(ne[0] * ne[1] * ne[2], float(nu))
-    assert nu.size == ne[0] * ne[1] * ne[2]
+        nu = np.full(ne[0] * ne[1] * ne[2] * per, float(nu))
+    assert nu.size == ne[0] * ne[1] * ne[2] * per
     if beta1 is None:
         beta1 = np.zeros((3, 3))
     return {
+        "element": element,
+        "origin": tuple(float(v) for v in origin),
+        "a_nodal": None if a_nodal is None else np.ascontiguousarray(a_nodal, dtype=np.float64).reshape(-1),
+        "u_dirichlet": None if u_dirichlet is None else np.ascontiguousarray(u_dirichlet, dtype=np.float64),
         "name": name,
         "nsub": tuple(int(v) for v in nsub),
         "widths": widths,
@@ -187,6 +204,62 @@ def manufactured(hh, nsub=2):
                                 + s(pi * X) * co(pi * Y) * s(pi * Z)
                                 + s(pi * X) * s(pi * Y) * co(pi * Z))
     return _problem((nsub,) * 3, widths, 1.0, (1.0, 1.0, 1.0), f_nodal=f.ravel(), name=f"mms{hh}")
+
+
+def grid_nodes(widths, length=(1.0, 1.0, 1.0), origin=(0.0, 0.0, 0.0)):
+    """Coordinates X, Y, Z of every grid node, x-fastest flattening."""
+    ne = [int(np.sum(w)) for w in widths]
+    ax = [origin[a] + np.arange(ne[a] + 1) * (length[a] / ne[a]) for a in range(3)]
+    Z, Y, X = np.meshgrid(ax[2], ax[1], ax[0], indexing="ij")
+    return X.ravel(), Y.ravel(), Z.ravel()
+
+
+# Section 4's example: the 2x2x2 subdomains numbered anticlockwise (seen from
+# +z) around the vertical axis, bottom layer first: (x-, y-), (x+, y-),
+# (x+, y+), (x-, y+); value 0 marks the subdomains that take the first of the
+# two viscosities of each test, 1 the others.
+HELICOID = ((0, 0, 0), (1, 0, 0), (1, 1, 0), (0, 1, 0), (0, 0, 1), (1, 0, 1), (1, 1, 1), (0, 1, 1))
+EXAMPLE_TESTS = {
+    1: (0, 1, 1, 0, 0, 1, 1, 0),   # nu_1 = nu_4 = nu_5 = nu_8
+    2: (0, 1, 1, 1, 0, 0, 1, 0),   # nu_1 = nu_5 = nu_6 = nu_8
+    3: (0, 1, 0, 1, 1, 0, 1, 0),   # nu_1 = nu_3 = nu_6 = nu_8
+}
+
+
+def _example_problem(n, m, nu_tet, name):
+    """Section 4's model problem on (-0.5, 0.5)^2 x (0, 1), n^3 cubic
+    subdomains of m^3 boxes, six linear tetrahedra per box: c = 1,
+    a = (-2 pi y, 2 pi x, sin 2 pi x) given at the grid nodes, f = 0,
+    u = 1 on z = 0 and 0 on the rest of the boundary."""
+    widths = [[m] * n] * 3
+    org = (-0.5, -0.5, 0.0)
+    X, Y, Z = grid_nodes(widths, origin=org)
+    a = np.stack([-2.0 * np.pi * Y, 2.0 * np.pi * X, np.sin(2.0 * np.pi * X)], axis=1)
+    u0 = np.where(Z == 0.0, 1.0, 0.0)
+    return _problem((n, n, n), widths, nu_tet, (0.0, 0.0, 0.0), c=1.0, f_const=0.0, name=name,
+                    element="p1", origin=org, a_nodal=a, u_dirichlet=u0)
+
+
+def example_helicoid(test, nu1, nu2, m):
+    """Tests 1-3 of Section 4's uniform-mesh example: 8 subdomains of m^3
+    boxes, nu piecewise constant per subdomain (two values, grouped by the
+    test's pattern over the helicoidal numbering)."""
+    widths = [[m] * 2] * 3
+    sx, sy, sz = element_subdomain(widths)
+    group = np.empty(8, dtype=np.int64)
+    for k, (hx, hy, hz) in enumerate(HELICOID):
+        group[hx + 2 * hy + 4 * hz] = EXAMPLE_TESTS[test][k]
+    g = group[sx + 2 * sy + 4 * sz]
+    nu_box = np.where(g == 0, float(nu1), float(nu2))
+    return _example_problem(2, m, np.repeat(nu_box, 6), f"example_t{test}_m{m}")
+
+
+def example_random(n, m, seed):
+    """Section 4's random-viscosity example: n^3 subdomains of m^3 boxes,
+    nu = 10^r with r ~ U(-3, 3) drawn per tetrahedron."""
+    rng = np.random.default_rng(seed)
+    ntet = 6 * (n * m) ** 3
+    return _example_problem(n, m, 10.0 ** rng.uniform(-3.0, 3.0, ntet), f"example_random_n{n}_m{m}_s{seed}")
 
 
 CONFIGS = {
