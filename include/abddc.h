@@ -15,9 +15,9 @@
  *                after it on the SVD/QR change of basis)
  *   solver       Section 4: GMRES stopped at a residual of 1e-8 or 300 steps
  *
- * Discretisation here: trilinear (Q1) boxes on a tensor-product box
- * partition of a box domain with zero Dirichlet data (the paper uses linear
- * tetrahedra; the element is a reading of this library).
+ * Discretisation here: a box grid on a tensor-product box partition, with
+ * trilinear (Q1) boxes or the paper's linear tetrahedra (six per box), zero
+ * or lifted Dirichlet data (abddc_problem below).
  *
  * Conventions (every entry point):
  *  - Return value: ABDDC_OK (0) on success, a positive warning code when the
@@ -28,7 +28,7 @@
  *    abddc_apply_bddc / abddc_apply_schur / abddc_gmres_solve.  Out of order
  *    calls return ABDDC_ESTATE.  One context must not be used by two host
  *    threads at once; different contexts are independent.
- *  - Problem arrays (abddc_problem nu, f_nodal) are HOST pointers, or
+ *  - Problem arrays (abddc_problem nu, f_nodal, a_nodal, u_dirichlet) are HOST pointers, or
  *    DEVICE pointers of the context's device when arrays_on_device is set;
  *    either way abddc_assemble copies them and the caller keeps ownership.
  *    The width arrays are always host pointers.
@@ -92,22 +92,44 @@ typedef struct {
   void* user;
 } abddc_device;
 
-/* The model problem of Section 2 on a box split into box subdomains.
- * Coefficients: nu > 0 piecewise constant per element; affine velocity
- * a(x) = beta0 + beta1 x (beta1 row-major 3x3); constant reaction c;
- * source f constant (f_nodal == NULL) or trilinear from nodal values. */
+/* The model problem of Section 2 on a box grid split into box subdomains.
+ * Coefficients: nu > 0 piecewise constant per element; velocity affine,
+ * a(x) = beta0 + beta1 x (beta1 row-major 3x3), or given at the grid nodes;
+ * constant reaction c; source f constant (f_nodal == NULL) or interpolated
+ * from nodal values; Dirichlet data zero or given at the grid nodes.
+ *
+ * element selects the finite elements (Section 2's stabilised form on either):
+ *   ABDDC_ELEM_Q1: trilinear boxes; nu has one value per box.
+ *   ABDDC_ELEM_P1: the linear tetrahedra of Section 2 and of Section 4's
+ *     example: every box split into six (the corner paths from its lowest
+ *     to its highest corner, one per ordering of the axes: xyz, xzy, yxz,
+ *     yzx, zxy, zyx); nu has six values per box in that order; the velocity
+ *     is interpolated linearly on each tetrahedron from its nodal values
+ *     (a_nodal, or the affine field at the nodes), so |a|_K is the largest
+ *     vertex speed and div a is constant on K.
+ * u_dirichlet lifts nonzero Dirichlet data (Section 4's example): the
+ * computed u is then the free-node part of u_h = u_0 + w, u_0 the data on
+ * the boundary nodes; boundary entries keep their data. */
+enum { ABDDC_ELEM_Q1 = 0, ABDDC_ELEM_P1 = 1 };
 typedef struct {
   int32_t nsub[3];          /* subdomains per axis                              */
   const int32_t* width[3];  /* elements per subdomain along each axis (>= 2)   */
   double length[3];         /* box edge lengths (> 0)                           */
-  const double* nu;         /* per element, x-fastest, len prod_a sum(width[a]) */
+  const double* nu;         /* per box (x-fastest), six per box for P1: len
+                               prod_a sum(width[a]), times 6 for P1            */
   double beta0[3];
   double beta1[9];
   double c;
   const double* f_nodal;    /* NULL, or per grid node (x-fastest)               */
   double f_const;
   double tau;               /* GLS constant tau of C(x) (0.7 in the paper)      */
-  int32_t arrays_on_device; /* nonzero: nu / f_nodal are device pointers       */
+  int32_t arrays_on_device; /* nonzero: nu / f_nodal / a_nodal / u_dirichlet are device pointers */
+  int32_t element;          /* ABDDC_ELEM_Q1 or ABDDC_ELEM_P1                    */
+  double origin[3];         /* coordinates of grid node (0, 0, 0)                */
+  const double* a_nodal;    /* NULL (affine beta0 + beta1 x), or 3 per grid node
+                               (x, y, z), node-id order; ABDDC_ELEM_P1 only      */
+  const double* u_dirichlet;/* NULL (zero data), or one per grid node; only the
+                               boundary nodes' values are read                   */
 } abddc_problem;
 
 enum { ABDDC_PREC_FP64 = 0, ABDDC_PREC_MIXED = 1 };
@@ -168,7 +190,9 @@ typedef struct {
  * S^(i) = A_BB - A_BI A_II^{-1} A_IB, g^(i) = f_B - A_BI A_II^{-1} f_I;
  * B^(i) = sym(S^(i))).  Builds the topology, assembles every subdomain on
  * the GPU and forms S^(i), g^(i), B^(i) and ghat = sum R_i^T g^(i).
- * EINVAL on bad sizes / non-positive or non-finite nu / tau <= 0. */
+ * EINVAL on bad sizes / non-positive or non-finite nu / tau <= 0 / an
+ * unknown element / a_nodal with ABDDC_ELEM_Q1 / non-finite a_nodal or
+ * u_dirichlet values (host arrays). */
 int abddc_assemble(const abddc_problem* prob, const abddc_device* dev, abddc_ctx** out);
 
 /* Section 3: deluxe weights, face eigenproblems (eq. equ-4-8), new edge
@@ -341,7 +365,9 @@ void abddc_mlp_destroy(abddc_mlp* mlp);
 
 /* Features of every edge of the context (edge kind order) into X (DEVICE,
  * n_edge x 133); eligible (DEVICE int32 per edge, may be NULL) is 1 for
- * edges of n_E = 7 dofs (features of other edges are still written). */
+ * edges of n_E = 7 dofs (features of other edges are still written).
+ * Trilinear-box problems only (EINVAL for ABDDC_ELEM_P1); so is
+ * constraint_source = ABDDC_CONSTRAINTS_MLP in abddc_setup_coarse_space. */
 int abddc_edge_features(abddc_ctx* ctx, float* X, int32_t* eligible);
 /* Training targets after a setup: the projector upper triangles of the
  * context's edge bases (DEVICE, n_edge x 28; zeros for n_E != 7). */

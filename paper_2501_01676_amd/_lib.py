@@ -42,6 +42,10 @@ class Problem(C.Structure):
         ("f_const", C.c_double),
         ("tau", C.c_double),
         ("arrays_on_device", C.c_int32),
+        ("element", C.c_int32),
+        ("origin", C.c_double * 3),
+        ("a_nodal", C.POINTER(C.c_double)),
+        ("u_dirichlet", C.POINTER(C.c_double)),
     ]
 
 

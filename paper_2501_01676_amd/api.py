@@ -12,6 +12,8 @@ import torch
 
 from . import _lib as L
 
+ELEMENTS = {"q1": 0, "p1": 1}   # ABDDC_ELEM_Q1, ABDDC_ELEM_P1
+
 DEFAULT_OPTIONS = {
     "theta_face": 10.0,
     "theta_edge": 10.0,
@@ -98,26 +100,23 @@ class Solver:
             p.beta0[a] = float(problem["beta0"][a])
         for i in range(9):
             p.beta1[i] = float(np.asarray(problem["beta1"]).reshape(9)[i])
+        p.element = ELEMENTS[problem.get("element", "q1")]
+        for a, v in enumerate(problem.get("origin", (0.0, 0.0, 0.0))):
+            p.origin[a] = float(v)
         nu = problem["nu"]
         if isinstance(nu, torch.Tensor):
             # device-resident coefficient arrays (copied on the device)
             assert nu.is_cuda and nu.dtype == torch.float64 and nu.is_contiguous()
-            self._keep.append(nu)
-            p.nu = C.cast(C.c_void_p(nu.data_ptr()), C.POINTER(C.c_double))
-            f = problem.get("f_nodal")
-            if f is not None:
-                assert isinstance(f, torch.Tensor) and f.is_cuda
-                self._keep.append(f)
-                p.f_nodal = C.cast(C.c_void_p(f.data_ptr()), C.POINTER(C.c_double))
+            p.nu = self._device_array(nu)
+            for key in ("f_nodal", "a_nodal", "u_dirichlet"):
+                if problem.get(key) is not None:
+                    setattr(p, key, self._device_array(problem[key]))
             p.arrays_on_device = 1
         else:
-            nu = np.ascontiguousarray(nu, dtype=np.float64)
-            self._keep.append(nu)
-            p.nu = nu.ctypes.data_as(C.POINTER(C.c_double))
-            if problem.get("f_nodal") is not None:
-                f = np.ascontiguousarray(problem["f_nodal"], dtype=np.float64)
-                self._keep.append(f)
-                p.f_nodal = f.ctypes.data_as(C.POINTER(C.c_double))
+            p.nu = self._host_array(nu)
+            for key in ("f_nodal", "a_nodal", "u_dirichlet"):
+                if problem.get(key) is not None:
+                    setattr(p, key, self._host_array(problem[key]))
         p.f_const = float(problem["f_const"])
         p.c = float(problem["c"])
         p.tau = float(problem["tau"])
@@ -133,6 +132,16 @@ class Solver:
         self.n_dof, self.n_gamma = nd.value, ng.value
         self.n_sub, self.n_face, self.n_edge = ns.value, nf.value, ne.value
         self.counts = None
+
+    def _device_array(self, t):
+        assert isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()
+        self._keep.append(t)
+        return C.cast(C.c_void_p(t.data_ptr()), C.POINTER(C.c_double))
+
+    def _host_array(self, a):
+        a = np.ascontiguousarray(a, dtype=np.float64).reshape(-1)
+        self._keep.append(a)
+        return a.ctypes.data_as(C.POINTER(C.c_double))
 
     def setup_coarse_space(self, **opts):
         o = dict(DEFAULT_OPTIONS)

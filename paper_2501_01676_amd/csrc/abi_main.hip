@@ -236,6 +236,12 @@ extern "C" int abddc_assemble(const abddc_problem* prob, const abddc_device* dev
     }
     ABDDC_REQUIRE(prob->tau > 0 && std::isfinite(prob->tau), ABDDC_EINVAL, "tau must be > 0");
     ABDDC_REQUIRE(prob->nu, ABDDC_EINVAL, "nu is null");
+    ABDDC_REQUIRE(prob->element == ABDDC_ELEM_Q1 || prob->element == ABDDC_ELEM_P1, ABDDC_EINVAL,
+                  "element must be ABDDC_ELEM_Q1 or ABDDC_ELEM_P1");
+    ABDDC_REQUIRE(!prob->a_nodal || prob->element == ABDDC_ELEM_P1, ABDDC_EINVAL,
+                  "a_nodal needs element = ABDDC_ELEM_P1");
+    for (int a = 0; a < 3; ++a)
+      ABDDC_REQUIRE(std::isfinite(prob->origin[a]), ABDDC_EINVAL, "origin must be finite");
     ABDDC_REQUIRE((dev->alloc == nullptr) == (dev->free == nullptr), ABDDC_EINVAL,
                   "device allocation hooks: alloc and free must both be set or both be null");
     std::unique_ptr<abddc_ctx> c(new abddc_ctx());
@@ -253,9 +259,18 @@ extern "C" int abddc_assemble(const abddc_problem* prob, const abddc_device* dev
     HostTrace ht;
     T.build_grid(nsub_in, w_in);   // the interface objects follow once the element kernel is queued
     const bool on_dev = prob->arrays_on_device != 0;
-    if (!on_dev)
-      for (int64_t e = 0; e < T.n_elem; ++e)
+    const int64_t n_nu = T.n_elem * (prob->element == ABDDC_ELEM_P1 ? 6 : 1);
+    if (!on_dev) {
+      for (int64_t e = 0; e < n_nu; ++e)
         ABDDC_REQUIRE(prob->nu[e] > 0 && std::isfinite(prob->nu[e]), ABDDC_EINVAL, "nu must be positive and finite");
+      if (prob->a_nodal)
+        for (int64_t q = 0; q < 3 * T.n_nodes; ++q)
+          ABDDC_REQUIRE(std::isfinite(prob->a_nodal[q]), ABDDC_EINVAL, "a_nodal must be finite");
+      if (prob->u_dirichlet)
+        for (int64_t q = 0; q < T.n_nodes; ++q)
+          ABDDC_REQUIRE(std::isfinite(prob->u_dirichlet[q]), ABDDC_EINVAL, "u_dirichlet must be finite");
+    }
+    c->element = prob->element;
     for (int a = 0; a < 3; ++a) {
       c->length[a] = prob->length[a];
       c->beta0[a] = prob->beta0[a];
@@ -276,23 +291,35 @@ extern "C" int abddc_assemble(const abddc_problem* prob, const abddc_device* dev
     record(c.get(), 10);
     // coefficients, then the element matrices: they need no layout, so the
     // GPU computes them while the host builds the local maps below
+    DevBuf<double> d_anodal, d_udir;
     if (on_dev) {
-      c->d_nu.alloc(T.n_elem);
-      ABDDC_HIP(hipMemcpyAsync(c->d_nu.p, prob->nu, T.n_elem * sizeof(double), hipMemcpyDeviceToDevice, s));
-      launch_check_positive(c->d_nu.p, T.n_elem, c->d_flag.p, s);
+      c->d_nu.alloc(n_nu);
+      ABDDC_HIP(hipMemcpyAsync(c->d_nu.p, prob->nu, n_nu * sizeof(double), hipMemcpyDeviceToDevice, s));
+      launch_check_positive(c->d_nu.p, n_nu, c->d_flag.p, s);
       if (prob->f_nodal) {
         c->d_fnodal.alloc(T.n_nodes);
         ABDDC_HIP(hipMemcpyAsync(c->d_fnodal.p, prob->f_nodal, T.n_nodes * sizeof(double), hipMemcpyDeviceToDevice, s));
         c->have_fnodal = true;
       }
+      if (prob->a_nodal) {
+        d_anodal.alloc(3 * T.n_nodes);
+        ABDDC_HIP(hipMemcpyAsync(d_anodal.p, prob->a_nodal, 3 * T.n_nodes * sizeof(double), hipMemcpyDeviceToDevice, s));
+      }
+      if (prob->u_dirichlet) {
+        d_udir.alloc(T.n_nodes);
+        ABDDC_HIP(hipMemcpyAsync(d_udir.p, prob->u_dirichlet, T.n_nodes * sizeof(double), hipMemcpyDeviceToDevice, s));
+      }
     } else {
-      std::vector<double> nu(prob->nu, prob->nu + T.n_elem);
+      std::vector<double> nu(prob->nu, prob->nu + n_nu);
       c->d_nu = to_device(nu, s);
       if (prob->f_nodal) {
         std::vector<double> fn(prob->f_nodal, prob->f_nodal + T.n_nodes);
         c->d_fnodal = to_device(fn, s);
         c->have_fnodal = true;
       }
+      if (prob->a_nodal) d_anodal = to_device(std::vector<double>(prob->a_nodal, prob->a_nodal + 3 * T.n_nodes), s);
+      if (prob->u_dirichlet)
+        d_udir = to_device(std::vector<double>(prob->u_dirichlet, prob->u_dirichlet + T.n_nodes), s);
     }
 
     DevBuf<double> Ae(T.n_elem * 64), Fe(T.n_elem * 8);
@@ -303,13 +330,16 @@ extern "C" int abddc_assemble(const abddc_problem* prob, const abddc_device* dev
         P.ne[a] = T.ne[a];
         P.nn[a] = T.nn[a];
         P.h[a] = c->length[a] / T.ne[a];
+        P.origin[a] = prob->origin[a];
         P.b0[a] = c->beta0[a];
       }
       for (int i = 0; i < 9; ++i) P.b1[i] = c->beta1[i];
       P.c = c->c;
       P.tau = c->tau;
       P.f_const = c->f_const;
-      launch_elem(P, c->d_nu.p, c->have_fnodal ? c->d_fnodal.p : nullptr, Ae.p, Fe.p, s);
+      P.element = prob->element;
+      const ElemFields F{c->have_fnodal ? c->d_fnodal.p : nullptr, d_anodal.p, d_udir.p};
+      launch_elem(P, c->d_nu.p, F, Ae.p, Fe.p, s);
     }
 
     ht.mark("assemble: coefficients, element kernel queued");
@@ -501,6 +531,8 @@ extern "C" int abddc_setup_coarse_space(abddc_ctx* c, const abddc_options* opts,
                   ABDDC_EINVAL, "bad constraint source");
     ABDDC_REQUIRE(o.constraint_source != ABDDC_CONSTRAINTS_MLP || (o.mlp && o.mlp->device == c->device), ABDDC_EINVAL,
                   "learned constraints need a network on the context's device");
+    ABDDC_REQUIRE(o.constraint_source != ABDDC_CONSTRAINTS_MLP || c->element == ABDDC_ELEM_Q1, ABDDC_EINVAL,
+                  "learned edge constraints read one viscosity per box: trilinear-box problems only");
     ABDDC_REQUIRE(o.pinv_rtol >= 0 && o.svd_rtol >= 0 && o.tie_rtol >= 0, ABDDC_EINVAL, "negative tolerance");
     ABDDC_REQUIRE(o.judge_iters >= 0 && o.judge_ratio >= 0 && std::isfinite(o.judge_ratio), ABDDC_EINVAL,
                   "bad judge settings");

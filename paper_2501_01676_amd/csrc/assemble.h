@@ -11,8 +11,17 @@ struct ElemParams {
   int64_t n_elem;
   int ne[3], nn[3];
   double h[3];
+  double origin[3];
   double b0[3], b1[9];
   double c, tau, f_const;
+  int element;                 // ABDDC_ELEM_Q1 / ABDDC_ELEM_P1
+};
+
+// Optional nodal fields of the element kernels (device pointers or null).
+struct ElemFields {
+  const double* f_nodal;       // source per grid node
+  const double* a_nodal;       // velocity per grid node (3), P1 only
+  const double* u_dirichlet;   // Dirichlet data per grid node (boundary read)
 };
 
 // Per-subdomain assembly metadata (device array, one entry per subdomain).
@@ -28,7 +37,7 @@ struct SubAsm {
 };
 
 void launch_check_positive(const double* v, int64_t n, int* flag, hipStream_t s);
-void launch_elem(const ElemParams& P, const double* nu, const double* fnodal, double* Ae, double* Fe,
+void launch_elem(const ElemParams& P, const double* nu, const ElemFields& F, double* Ae, double* Fe,
                  hipStream_t s);
 void launch_scatter(const SubAsm* subs, const int32_t* rowsub, const int32_t* lnode, const int32_t* lmap,
                     int64_t nrows, const int nn[3], const int ne[3], const double* Ae, const double* Fe, double* A,

@@ -46,6 +46,7 @@ struct abddc_ctx {
   abddc::Topology topo;
   double length[3], beta0[3], beta1[9], c = 0, f_const = 0, tau = 0;
   bool have_fnodal = false;
+  int element = 0;                  // ABDDC_ELEM_Q1 or ABDDC_ELEM_P1
   int state = 0;  // 1 assembled, 2 set up
   abddc_options opt{};
 

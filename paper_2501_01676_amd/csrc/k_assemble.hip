@@ -1,12 +1,15 @@
-// Assembly of the GLS-stabilised trilinear-box system (Section 2) into dense
-// per-subdomain matrices [A^(i) | f^(i)] in local order [interior; Gamma_i]
-// (Section 3), extraction of S^(i), g^(i), B^(i) after the interior
-// elimination, and interior recovery u_I = A_II^{-1}(f_I - A_IB u_B).
+// Assembly of the GLS-stabilised system (Section 2) on trilinear boxes or on
+// six linear tetrahedra per box into dense per-subdomain matrices
+// [A^(i) | f^(i)] in local order [interior; Gamma_i] (Section 3), extraction
+// of S^(i), g^(i), B^(i) after the interior elimination, and interior
+// recovery u_I = A_II^{-1}(f_I - A_IB u_B).
 //
 // a(u, v) = int nu grad u . grad v + C_K Lu Lv + ctilde u v
 //           + 1/2 (a . grad u v - a . grad v u),
-// g(v)    = int f v + C_K f Lv,   L u = a . grad u + c u inside a box,
+// g(v)    = int f v + C_K f Lv,   L u = a . grad u + c u inside an element,
 // C_K from the Peclet switch with tau; entry (i, j) = a(phi_j, phi_i).
+// Nonzero Dirichlet data u_0 are lifted: the load of row i loses
+// sum_j A_K[i][j] u_0[j] over the box's boundary corners j.
 
 #include <hip/hip_runtime.h>
 
@@ -33,12 +36,26 @@ __device__ inline void shape(double s, double t, double u, int i, double ihx, do
   gz = fs * ft * (c ? ihz : -ihz);
 }
 
+// Lifting of Dirichlet data into the load of row i of a box: F_K[i] -=
+// A_K[i][j] u_0[j] for every corner j on the grid boundary.
+__device__ inline double lift_row(const ElemParams& P, const double* __restrict__ u0, const double (&row)[8],
+                                  int ex, int ey, int ez, double fi) {
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const int ix = ex + (j & 1), iy = ey + ((j >> 1) & 1), iz = ez + ((j >> 2) & 1);
+    const bool bnd = ix == 0 || iy == 0 || iz == 0 || ix == P.nn[0] - 1 || iy == P.nn[1] - 1 || iz == P.nn[2] - 1;
+    if (bnd) fi -= row[j] * u0[ix + (int64_t)P.nn[0] * (iy + (int64_t)P.nn[1] * iz)];
+  }
+  return fi;
+}
+
 // One thread per (element, test function i): row i of A_K and F_K[i].
 // NODAL: the load is interpolated from nodal values (a separate instance, so
 // the constant-load one keeps its state in registers).
 template <bool NODAL>
-__global__ void elem_kernel(ElemParams P, const double* __restrict__ nu, const double* __restrict__ fnodal,
-                            double* __restrict__ Ae, double* __restrict__ Fe) {
+__global__ void elem_kernel(ElemParams P, const double* __restrict__ nu, ElemFields Fd, double* __restrict__ Ae,
+                            double* __restrict__ Fe) {
+  const double* __restrict__ fnodal = Fd.f_nodal;
   const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (tid >= P.n_elem * 8) return;
   const int64_t e = tid >> 3;
@@ -48,7 +65,7 @@ __global__ void elem_kernel(ElemParams P, const double* __restrict__ nu, const d
   const int ez = (int)(e / ((int64_t)P.ne[0] * P.ne[1]));
   const double hx = P.h[0], hy = P.h[1], hz = P.h[2];
   const double ihx = 1.0 / hx, ihy = 1.0 / hy, ihz = 1.0 / hz;
-  const double x0 = ex * hx, y0 = ey * hy, z0 = ez * hz;
+  const double x0 = P.origin[0] + ex * hx, y0 = P.origin[1] + ey * hy, z0 = P.origin[2] + ez * hz;
   const double nue = nu[e];
   // |a|_K: maximum over the corners (|a| is convex for affine a)
   double amax = 0.0;
@@ -108,6 +125,112 @@ __global__ void elem_kernel(ElemParams P, const double* __restrict__ nu, const d
     }
     fi += w * (fq * phii + CK * fq * Li);
   }
+  if (Fd.u_dirichlet) fi = lift_row(P, Fd.u_dirichlet, row, ex, ey, ez, fi);
+  for (int j = 0; j < 8; ++j) Ae[e * 64 + i * 8 + j] = row[j];
+  Fe[e * 8 + i] = fi;
+}
+
+// The six tetrahedra of a box: tetrahedron t is the corner path
+// 0 -> e_p0 -> e_p0 + e_p1 -> 7 for the t-th ordering (p0, p1, p2) of the
+// axes in lexicographic order.  With xi_a the box-local coordinates in
+// [0, 1], its barycentric coordinates are 1 - xi_p0, xi_p0 - xi_p1,
+// xi_p1 - xi_p2, xi_p2, whose gradients are read off directly.
+__device__ constexpr int KUHN_PERM[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
+
+// One thread per (box, test function i): row i of the box matrix and load as
+// the sum over the box's tetrahedra that contain corner i.  Velocity and
+// source are interpolated linearly on each tetrahedron from the corner
+// values; the symmetric 4-point rule (barycentric alpha, beta, beta, beta,
+// alpha = (5 + 3 sqrt 5) / 20, beta = (5 - sqrt 5) / 20) is exact for every
+// product of two linear factors.  ctilde = c - div(a_h) / 2 per tetrahedron,
+// |a|_K = the largest vertex speed, h_K = the box diagonal (the longest
+// tetrahedron edge).
+template <bool NODAL_F, bool NODAL_A>
+__global__ void elem_p1_kernel(ElemParams P, const double* __restrict__ nu, ElemFields Fd,
+                               double* __restrict__ Ae, double* __restrict__ Fe) {
+  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (tid >= P.n_elem * 8) return;
+  const int64_t e = tid >> 3;
+  const int i = (int)(tid & 7);
+  const int ex = (int)(e % P.ne[0]);
+  const int ey = (int)((e / P.ne[0]) % P.ne[1]);
+  const int ez = (int)(e / ((int64_t)P.ne[0] * P.ne[1]));
+  const double h[3] = {P.h[0], P.h[1], P.h[2]};
+  const double ih[3] = {1.0 / h[0], 1.0 / h[1], 1.0 / h[2]};
+  double av[8][3], fc[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const int ix = ex + (k & 1), iy = ey + ((k >> 1) & 1), iz = ez + ((k >> 2) & 1);
+    const int64_t node = ix + (int64_t)P.nn[0] * (iy + (int64_t)P.nn[1] * iz);
+    if constexpr (NODAL_A) {
+      av[k][0] = Fd.a_nodal[3 * node];
+      av[k][1] = Fd.a_nodal[3 * node + 1];
+      av[k][2] = Fd.a_nodal[3 * node + 2];
+    } else {
+      const double xc = P.origin[0] + ix * h[0], yc = P.origin[1] + iy * h[1], zc = P.origin[2] + iz * h[2];
+#pragma unroll
+      for (int d = 0; d < 3; ++d) av[k][d] = P.b0[d] + P.b1[3 * d] * xc + P.b1[3 * d + 1] * yc + P.b1[3 * d + 2] * zc;
+    }
+    if constexpr (NODAL_F) fc[k] = Fd.f_nodal[node];
+    else fc[k] = P.f_const;
+  }
+  const double hK = sqrt(h[0] * h[0] + h[1] * h[1] + h[2] * h[2]);
+  const double w = h[0] * h[1] * h[2] / 6.0 * 0.25;
+  const double qa = (5.0 + 3.0 * sqrt(5.0)) / 20.0, qb = (5.0 - sqrt(5.0)) / 20.0;
+  double row[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  double fi = 0.0;
+#pragma unroll
+  for (int t = 0; t < 6; ++t) {
+    const int p0 = KUHN_PERM[t][0], p1 = KUHN_PERM[t][1], p2 = KUHN_PERM[t][2];
+    const int v[4] = {0, 1 << p0, (1 << p0) + (1 << p1), 7};
+    const int li = i == v[0] ? 0 : (i == v[1] ? 1 : (i == v[2] ? 2 : (i == v[3] ? 3 : -1)));
+    if (li < 0) continue;
+    double G[4][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+    G[0][p0] = -ih[p0];
+    G[1][p0] = ih[p0];
+    G[1][p1] = -ih[p1];
+    G[2][p1] = ih[p1];
+    G[2][p2] = -ih[p2];
+    G[3][p2] = ih[p2];
+    const double nut = nu[e * 6 + t];
+    double diva = 0.0, amax = 0.0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const double* a = av[v[k]];
+      diva += a[0] * G[k][0] + a[1] * G[k][1] + a[2] * G[k][2];
+      amax = fmax(amax, sqrt(a[0] * a[0] + a[1] * a[1] + a[2] * a[2]));
+    }
+    const double peclet = hK * amax / (2.0 * nut);
+    const double CK = (peclet >= 1.0) ? P.tau * hK / (2.0 * amax) : P.tau * hK * hK / (4.0 * nut);
+    const double ctil = P.c - 0.5 * diva;
+    const double gi0 = li == 0 ? G[0][0] : (li == 1 ? G[1][0] : (li == 2 ? G[2][0] : G[3][0]));
+    const double gi1 = li == 0 ? G[0][1] : (li == 1 ? G[1][1] : (li == 2 ? G[2][1] : G[3][1]));
+    const double gi2 = li == 0 ? G[0][2] : (li == 1 ? G[1][2] : (li == 2 ? G[2][2] : G[3][2]));
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      double aq[3] = {0, 0, 0}, fq = 0.0;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const double lk = k == q ? qa : qb;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) aq[d] += lk * av[v[k]][d];
+        fq += lk * fc[v[k]];
+      }
+      const double lami = li == q ? qa : qb;
+      const double agi = aq[0] * gi0 + aq[1] * gi1 + aq[2] * gi2;
+      const double Li = agi + P.c * lami;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const double lk = k == q ? qa : qb;
+        const double agk = aq[0] * G[k][0] + aq[1] * G[k][1] + aq[2] * G[k][2];
+        const double Lk = agk + P.c * lk;
+        row[v[k]] += w * (nut * (gi0 * G[k][0] + gi1 * G[k][1] + gi2 * G[k][2]) + CK * Li * Lk +
+                          ctil * lami * lk + 0.5 * (agk * lami - agi * lk));
+      }
+      fi += w * (fq * lami + CK * fq * Li);
+    }
+  }
+  if (Fd.u_dirichlet) fi = lift_row(P, Fd.u_dirichlet, row, ex, ey, ez, fi);
   for (int j = 0; j < 8; ++j) Ae[e * 64 + i * 8 + j] = row[j];
   Fe[e * 8 + i] = fi;
 }
@@ -292,13 +415,20 @@ void launch_check_positive(const double* v, int64_t n, int* flag, hipStream_t s)
   ABDDC_HIP(hipGetLastError());
 }
 
-void launch_elem(const ElemParams& P, const double* nu, const double* fnodal, double* Ae, double* Fe,
+void launch_elem(const ElemParams& P, const double* nu, const ElemFields& F, double* Ae, double* Fe,
                  hipStream_t s) {
   const int64_t n = P.n_elem * 8;
-  if (fnodal)
-    elem_kernel<true><<<(unsigned)((n + 255) / 256), 256, 0, s>>>(P, nu, fnodal, Ae, Fe);
-  else
-    elem_kernel<false><<<(unsigned)((n + 255) / 256), 256, 0, s>>>(P, nu, fnodal, Ae, Fe);
+  const unsigned grid = (unsigned)((n + 255) / 256);
+  if (P.element == ABDDC_ELEM_P1) {
+    if (F.f_nodal && F.a_nodal) elem_p1_kernel<true, true><<<grid, 256, 0, s>>>(P, nu, F, Ae, Fe);
+    else if (F.f_nodal) elem_p1_kernel<true, false><<<grid, 256, 0, s>>>(P, nu, F, Ae, Fe);
+    else if (F.a_nodal) elem_p1_kernel<false, true><<<grid, 256, 0, s>>>(P, nu, F, Ae, Fe);
+    else elem_p1_kernel<false, false><<<grid, 256, 0, s>>>(P, nu, F, Ae, Fe);
+  } else if (F.f_nodal) {
+    elem_kernel<true><<<grid, 256, 0, s>>>(P, nu, F, Ae, Fe);
+  } else {
+    elem_kernel<false><<<grid, 256, 0, s>>>(P, nu, F, Ae, Fe);
+  }
   ABDDC_HIP(hipGetLastError());
 }
 

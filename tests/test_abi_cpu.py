@@ -37,3 +37,41 @@ def test_error_path_without_context():
     rc = lib.abddc_apply_bddc(None, None, None)
     assert rc == _lib.EINVAL
     assert b"null" in lib.abddc_last_error()
+
+
+def _problem_struct(element, a_nodal=False):
+    import numpy as np
+    from paper_2501_01676_amd import _lib
+    p = _lib.Problem()
+    keep = []
+    for a in range(3):
+        p.nsub[a] = 1
+        w = np.array([2], dtype=np.int32)
+        keep.append(w)
+        p.width[a] = w.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+        p.length[a] = 1.0
+    nu = np.ones(48)
+    keep.append(nu)
+    p.nu = nu.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    p.tau = 0.7
+    p.element = element
+    if a_nodal:
+        a = np.zeros(81)
+        keep.append(a)
+        p.a_nodal = a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    return p, keep
+
+
+@pytest.mark.parametrize("element,a_nodal,msg", [(7, False, b"element"), (0, True, b"a_nodal")])
+def test_problem_validation_before_device_work(element, a_nodal, msg):
+    """An unknown element and a nodal velocity on trilinear boxes are refused
+    with EINVAL before the library touches a device."""
+    from paper_2501_01676_amd import _lib
+    lib = _lib.load()
+    p, keep = _problem_struct(element, a_nodal)
+    dev = _lib.Device(0, None)
+    ctx = ctypes.c_void_p()
+    rc = lib.abddc_assemble(ctypes.byref(p), ctypes.byref(dev), ctypes.byref(ctx))
+    assert rc == _lib.EINVAL
+    assert msg in lib.abddc_last_error()
+    assert not ctx.value

@@ -136,3 +136,21 @@ def test_null_arguments_are_einval():
     assert lib.abddc_get_stage(g.ctx, 0, 10 ** 6, None, 0) == L.EINVAL
     assert lib.abddc_kernel_stats(g.ctx, 99, None, None, None) == L.EINVAL
     g.close()
+
+
+def test_learned_constraints_refuse_tetrahedra():
+    """Edge features read one viscosity per box, so the learned path is
+    refused (EINVAL, before any feature kernel) on linear-tetrahedron
+    problems; the exact path on the same context still works."""
+    _need_gpu()
+    from paper_2501_01676_amd import _lib as L
+    from paper_2501_01676_amd import api
+    g = api.Solver(W.example_helicoid(1, 1.0, 1e-7, 2))
+    assert _code(g.edge_features) == L.EINVAL
+    assert b"trilinear" in L.load().abddc_last_error()
+    net = api.MLP(W.mlp_init_params(0))
+    assert _code(g.setup_coarse_space, constraint_source=1, mlp=net) == L.EINVAL
+    assert b"trilinear" in L.load().abddc_last_error()
+    counts = g.setup_coarse_space(theta_face=1.0 + np.log(2.0))
+    assert counts["n_vertex"] == 1
+    g.close()

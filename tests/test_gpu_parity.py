@@ -22,6 +22,26 @@ def _layered(hh=5):
     return p
 
 
+def _p1_affine_lifted():
+    """Linear tetrahedra with an affine velocity evaluated at the nodes (the
+    kernel's non-nodal path), a nodal source, a shifted origin, random
+    per-tetrahedron viscosity and random Dirichlet data lifted into the
+    load."""
+    rng = np.random.default_rng(7)
+    widths = [[3, 4], [4, 3], [3, 3]]
+    org = (0.2, -0.3, 0.1)
+    X, Y, Z = W.grid_nodes(widths, origin=org)
+    nu = 10.0 ** rng.uniform(-2.0, 0.0, 6 * 7 * 7 * 6)
+    return W._problem((2, 2, 2), widths, nu, (1.0, -0.5, 0.8), beta1=[[0, -2, 0], [2, 0, 0], [0, 0, 0.5]],
+                      c=1.0, f_nodal=np.sin(X) + Y * Z, element="p1", origin=org,
+                      u_dirichlet=rng.uniform(-1.0, 1.0, X.size), name="p1_affine")
+
+
+def _theta_f(m):
+    """Section 4's face threshold 1 + log m."""
+    return {"theta_face": 1.0 + float(np.log(m))}
+
+
 LOOSE = {"theta_face": 2.0, "theta_edge": 2.0}
 # name -> (problem, oracle options, library options)
 CASES = {
@@ -43,6 +63,14 @@ CASES = {
     "old_ragged": (lambda: W.ragged((3, 2, 2), [3, 4, 5], 4), dict(LOOSE, theta_edge=6.0, edge_variant="old"),
                    dict(LOOSE, theta_edge=6.0, edge_variant=1)),
     "old_config2": (W.config2, {"edge_variant": "old"}, {"edge_variant": 1}),
+    # Section 4's example on linear tetrahedra (nodal velocity, lifted data)
+    "p1_example_t1": (lambda: W.example_helicoid(1, 1.0, 1e-7, 3), _theta_f(3), _theta_f(3)),
+    "p1_example_t2_loose": (lambda: W.example_helicoid(2, 1e3, 1e-3, 4), dict(_theta_f(4), theta_edge=2.0),
+                            dict(_theta_f(4), theta_edge=2.0)),
+    "p1_example_t3_old": (lambda: W.example_helicoid(3, 1e3, 1e-3, 4), dict(_theta_f(4), edge_variant="old"),
+                          dict(_theta_f(4), edge_variant=1)),
+    "p1_random_n3": (lambda: W.example_random(3, 3, 0), _theta_f(3), _theta_f(3)),
+    "p1_affine_lifted": (_p1_affine_lifted, LOOSE, LOOSE),
 }
 
 
