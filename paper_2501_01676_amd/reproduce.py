@@ -1,0 +1,89 @@
+"""Section 4's uniform-mesh experiments on the GPU library.
+
+    python -m paper_2501_01676_amd.reproduce [--table 4|5|random|all] [--json FILE]
+
+Runs the example of Section 4 (linear tetrahedra, c = 1, rotating velocity,
+u = 1 on z = 0) for the rows of its tables with both edge eigenproblems:
+the earlier one (eq. equ-4-8-E, ABDDC-OLD) and the new one (eq. equ-5-21,
+ABDDC-NEW), Theta_F = 1 + log m, Theta_E = 10, GMRES(30) to a relative
+residual of 1e-8 (at most 300 steps).  Prints per row and method
+"iterations(pnumF, pnumE)" as the tables do, plus the wall time of assemble,
+setup and solve.  The random-viscosity table draws nu per tetrahedron with
+seed 0.  Rows whose faces exceed the eigensolvers' 128 dofs (m > 12) are
+skipped with a note.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import time
+
+import torch
+
+from . import api
+from . import workloads as W
+
+TABLE4_ROWS = [(1e-1, 1e-5), (1e-1, 1e-6), (1e-1, 1e-7), (1e3, 1e-3), (1.0, 1e-7)]
+TABLE5_MS = [4, 8, 16]
+RANDOM_ROWS = [(n, m) for n in (2, 3, 4) for m in (4, 8, 12)]
+MAX_FACE_DOFS = 128
+
+
+def run(problem, m, variant):
+    t0 = time.perf_counter()
+    g = api.Solver(problem)
+    counts = g.setup_coarse_space(theta_face=1.0 + math.log(m), theta_edge=10.0, edge_variant=variant)
+    t1 = time.perf_counter()
+    _, info = g.gmres_solve(restart=30, rtol=1e-8, maxit=300)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    g.close()
+    return {"iters": info["iters"], "pnumF": counts["pnum_face"], "pnumE": counts["pnum_edge"],
+            "converged": bool(info["converged"]), "setup_s": t1 - t0, "solve_s": t2 - t1}
+
+
+def _cell(r):
+    return f"{r['iters']}({r['pnumF']},{r['pnumE']})"
+
+
+def rows(table):
+    if table in ("4", "all"):
+        for nu1, nu2 in TABLE4_ROWS:
+            for test in (1, 2, 3):
+                yield "ex-table-4", f"nu={nu1:g},{nu2:g}", f"Test {test}", 6, \
+                    (lambda t=test, a=nu1, b=nu2: W.example_helicoid(t, a, b, 6))
+    if table in ("5", "all"):
+        for m in TABLE5_MS:
+            for test in (1, 2, 3):
+                yield "ex-table-5", f"m={m}", f"Test {test}", m, \
+                    (lambda t=test, mm=m: W.example_helicoid(t, 1.0, 1e-7, mm))
+    if table in ("random", "all"):
+        for n, m in RANDOM_ROWS:
+            yield "ex-table-random", f"{n}({m})", "", m, (lambda nn=n, mm=m: W.example_random(nn, mm, 0))
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--table", default="all", choices=["4", "5", "random", "all"])
+    ap.add_argument("--json", default=None, help="also write the results to this file")
+    args = ap.parse_args()
+    out = []
+    for table, row, test, m, make in rows(args.table):
+        if (m - 1) ** 2 > MAX_FACE_DOFS:
+            print(f"{table:16s} {row:14s} {test:7s} skipped: faces of {(m - 1) ** 2} dofs", flush=True)
+            continue
+        p = make()
+        res = {v: run(p, m, i) for i, v in enumerate(("new", "old"))}
+        rec = {"table": table, "row": row, "test": test, "m": m, "old": res["old"], "new": res["new"]}
+        out.append(rec)
+        print(f"{table:16s} {row:14s} {test:7s} OLD {_cell(res['old']):12s} NEW {_cell(res['new']):12s} "
+              f"time OLD {res['old']['setup_s'] + res['old']['solve_s']:.3f} s "
+              f"NEW {res['new']['setup_s'] + res['new']['solve_s']:.3f} s", flush=True)
+    if args.json:
+        with open(args.json, "w") as f:
+            json.dump(out, f, indent=1)
+
+
+if __name__ == "__main__":
+    main()
