@@ -36,7 +36,7 @@ PEAK_HBM_GBS = 8000.0       # MI355X HBM3E
 
 # live-timed kernel classes of the library: class -> (kernel, roofline bound)
 TRACKED = {0: ("plu_update_kernel<T>", "mfma"), 1: ("gemv_kernel<T>", "hbm"), 2: ("plu_lead_kernel<T>", "mfma"),
-           3: ("plu_diag_kernel<T>", "mfma"), 4: ("plu_trsm_kernel<T>", "mfma"), 5: ("plu_band_kernel<T>", "mfma")}
+           3: ("plu_diag_kernel<T>", "mfma"), 4: ("plu_trsm_kernel<T>", "hbm"), 5: ("plu_band_kernel<T>", "mfma")}
 
 DESCRIPTIONS = {
     "config1a": "2x2x2 subdomains, H/h=4 (8^3 Q1 elements), nu=1, a=(1,1,1), f=1",

@@ -289,7 +289,9 @@ int abddc_phase_times(const abddc_ctx* ctx, double* t, int32_t n);
  *   ABDDC_KSTAT_PLU_DIAG    LU of the 64 x 64 diagonal blocks with their
  *                           lookahead update (work = 2/3 b^3 + 2 b^2 depth)
  *   ABDDC_KSTAT_PLU_TRSM    triangular solves of each panel's row and column
- *                           strips (work = b^2 per strip row / column)
+ *                           strips (work = algorithmic bytes: every strip
+ *                           entry read and written once, 16 b per strip row /
+ *                           column, plus the two b x b inverses read)
  *   ABDDC_KSTAT_PLU_BAND    update of the next panel's strips inside a panel
  *                           group (work = algorithmic flops, 2 m n depth)
  * Any output pointer may be NULL. */

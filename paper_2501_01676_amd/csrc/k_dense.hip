@@ -14,8 +14,6 @@
 
 #include <algorithm>
 #include <cmath>
-#include <map>
-#include <mutex>
 
 #include "arena.h"
 #include "buffer.h"
@@ -377,8 +375,8 @@ __device__ __forceinline__ void diag_lookahead(const T* A, const T* B, int ld, i
 //
 // With u0 < t0 the block first receives the update of the pivot columns
 // [u0, t0) (A_dd -= A[t0.., u0..t0) A[u0..t0, t0..), depth 64 or 128), which
-// the band / lead launch of those columns leaves out: that launch and this
-// one then depend on the same triangular solves only and run side by side.
+// the band / lead launch of those columns leaves out, so that launch may
+// follow this one in any order after the same triangular solves.
 template <class T>
 __global__ void __launch_bounds__(256) plu_diag_kernel(const PluDesc<T>* __restrict__ descs, int t0, int u0,
                                                         T* __restrict__ scratch, int* dflag) {
@@ -795,27 +793,6 @@ __global__ void sym_kernel(const SymDesc* __restrict__ descs) {
 
 }  // namespace
 
-// A second stream per library stream (default priority) with two events,
-// for the diagonal-block lookahead of partial_lu; created on first use and
-// kept for the process.
-struct SideStream {
-  hipStream_t s = nullptr;
-  hipEvent_t ready = nullptr, done = nullptr;
-  static SideStream& for_stream(hipStream_t main) {
-    static std::mutex mu;
-    static std::map<hipStream_t, SideStream*> table;
-    std::lock_guard<std::mutex> g(mu);
-    SideStream*& e = table[main];
-    if (!e) {
-      SideStream* n = new SideStream();
-      ABDDC_HIP(hipStreamCreateWithFlags(&n->s, hipStreamNonBlocking));
-      ABDDC_HIP(hipEventCreateWithFlags(&n->ready, hipEventDisableTiming));
-      ABDDC_HIP(hipEventCreateWithFlags(&n->done, hipEventDisableTiming));
-      e = n;
-    }
-    return *e;
-  }
-};
 
 template <class T>
 void partial_lu(const std::vector<PluDesc<T>>& descs_in, int* dflag, hipStream_t s) {
@@ -849,16 +826,17 @@ void partial_lu(const std::vector<PluDesc<T>>& descs_in, int* dflag, hipStream_t
   }
   T* scr = reinterpret_cast<T*>(scratch.p);
   const int nb = (int)descs.size();
-  // Lookahead: the diag kernel of panel t0 + NB runs on a side stream, after
-  // the triangular solves of panel t0 and beside the band / lead launch of
-  // that panel (which leaves its block to it); the next solves wait for it.
-  SideStream& side = SideStream::for_stream(s);
+  // Lookahead: the diag kernel of panel t0 + NB follows the triangular
+  // solves of panel t0 and comes before the band / lead launch of that panel,
+  // which leaves that diagonal block to it.
   const int grp = maxk > 512 ? 4 : (maxk > 256 ? 3 : 2);   // panels per group
   // Algorithmic flops of each launch for the live kernel statistics (only
   // counted when a statistics sink is set):
   //   diag  LU of the b x b diagonal block, 2/3 b^3, plus its lookahead
   //         update at depth t0 - u0, 2 b^2 (t0 - u0)
-  //   trsm  the two triangular solves, b^2 per row of L21 and per column of U12
+  //   trsm  bytes, not flops (b^2 flops per 16 b bytes of strip is below
+  //         the FP64 ridge): each strip entry of L21 and U12 read and written
+  //         once, the two b x b inverses read once
   //   band  the strips of the next panel at the group's depth, leaving out
   //         the next diagonal block
   auto diag_flops = [&](int t0, int u0) {
@@ -871,23 +849,22 @@ void partial_lu(const std::vector<PluDesc<T>>& descs_in, int* dflag, hipStream_t
         }
     return f;
   };
-  auto diag_launch = [&](int t0, int u0, hipStream_t st) {
+  auto diag_launch = [&](int t0, int u0) {
     hipEvent_t ea = nullptr, eb = nullptr;
     tracked_events(KC_PLU_DIAG, diag_flops(t0, u0), &ea, &eb);
-    hipExtLaunchKernelGGL(plu_diag_kernel<T>, dim3(nb), dim3(256), 0, st, ea, eb, 0, dd, t0, u0, scr, dflag);
+    hipExtLaunchKernelGGL(plu_diag_kernel<T>, dim3(nb), dim3(256), 0, s, ea, eb, 0, dd, t0, u0, scr, dflag);
   };
-  diag_launch(0, 0, s);
+  diag_launch(0, 0);
   for (int t0 = 0; t0 < maxk; t0 += NB) {
     const int rem = std::max(maxr, maxc) - t0;
     const int tiles = 2 * ((rem + TILE - 1) / TILE);
-    if (t0 > 0) ABDDC_HIP(hipStreamWaitEvent(s, side.done, 0));
     {
       double f = 0.0;
       if (g_kstats)
         for (auto& d : descs)
           if (t0 < d.k) {
             const double b = std::min(NB, d.k - t0);
-            f += b * b * ((double)(d.nrow - t0 - b) + (double)(d.ncol - t0 - b));
+            f += 16.0 * b * ((double)(d.nrow - t0 - b) + (double)(d.ncol - t0 - b)) + 16.0 * b * b;
           }
       hipEvent_t ea = nullptr, eb = nullptr;
       tracked_events(KC_PLU_TRSM, f, &ea, &eb);
@@ -898,10 +875,7 @@ void partial_lu(const std::vector<PluDesc<T>>& descs_in, int* dflag, hipStream_t
       // the next diagonal block: the pivot columns of this panel's group so
       // far, applied in the diag kernel
       const int u0 = t0 - ((t0 / NB) % grp) * NB;   // start of this panel's group
-      ABDDC_HIP(hipEventRecord(side.ready, s));
-      ABDDC_HIP(hipStreamWaitEvent(side.s, side.ready, 0));
-      diag_launch(t0 + NB, u0, side.s);
-      ABDDC_HIP(hipEventRecord(side.done, side.s));
+      diag_launch(t0 + NB, u0);
     }
     const int g0 = t0 - ((t0 / NB) % grp) * NB;
     if ((t0 / NB) % grp != grp - 1) {

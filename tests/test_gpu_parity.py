@@ -336,7 +336,7 @@ def test_graph_replay_matches_eager(pairs, restart):
 
 def test_fresh_contexts_and_streams_repeat(pairs):
     """Contexts take pooled runtime objects, and every library stream has its
-    own descriptor / upload rings and partial-LU side stream: solving the same
+    own descriptor / upload rings: solving the same
     problem again in fresh contexts, on the default stream and on a second
     stream, gives bit-identical solutions and the same iteration count."""
     from paper_2501_01676_amd import api
