@@ -20,5 +20,5 @@ Modules
 Parity status of each function is stated in its docstring; functions with no
 independent pin say "parity unpinned".
 """
-from .topology import Topology  # noqa: F401
+from .topology import PartitionTopology, Topology, make_topology  # noqa: F401
 from . import fem, bddc  # noqa: F401

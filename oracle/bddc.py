@@ -34,7 +34,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from .topology import Topology
+from .topology import Topology, make_topology  # noqa: F401
 from . import fem
 
 
@@ -145,7 +145,7 @@ class OracleBDDC:
 
     def __init__(self, problem):
         self.problem = problem
-        self.topo = Topology(problem["nsub"], problem["widths"])
+        self.topo = make_topology(problem)
         self.state = "created"
 
     # ------------------------------------------------------------ assemble

@@ -276,9 +276,7 @@ def assemble_subdomains(problem, topo, npts=3, elem=None, subs=None):
     A, F, nodes = elem
     out = []
     for s in (range(topo.n_sub) if subs is None else subs):
-        (x0, x1), (y0, y1), (z0, z1) = topo.element_box(s)
-        EZ, EY, EX = np.meshgrid(np.arange(z0, z1), np.arange(y0, y1), np.arange(x0, x1), indexing="ij")
-        eids = topo.elem_id(EX.ravel(), EY.ravel(), EZ.ravel())
+        eids = topo.elements_of(s)
         lnodes = topo.local_nodes(s)
         lmap = -np.ones(topo.n_nodes, dtype=np.int64)
         lmap[lnodes] = np.arange(lnodes.size)

@@ -158,6 +158,12 @@ class Topology:
             })
 
     # --------------------------------------------------------------- misc
+    def elements_of(self, s):
+        """Box ids of subdomain s (x-fastest)."""
+        (x0, x1), (y0, y1), (z0, z1) = self.element_box(s)
+        EZ, EY, EX = np.meshgrid(np.arange(z0, z1), np.arange(y0, y1), np.arange(x0, x1), indexing="ij")
+        return self.elem_id(EX.ravel(), EY.ravel(), EZ.ravel())
+
     def element_box(self, s):
         """Element index ranges (ex0, ex1), (ey0, ey1), (ez0, ez1) of subdomain s."""
         sx, sy, sz = self.sub_coords(s)
@@ -171,3 +177,144 @@ class Topology:
         """Node ids of subdomain s in local order [interior; Gamma_s]."""
         sd = self.sub[s]
         return np.concatenate([sd["interior"], self.iface_nodes[sd["gamma"]]])
+
+
+class PartitionTopology(Topology):
+    """Topology of an arbitrary partition of the box grid into face-connected
+    unions of boxes (Section 4's irregular subdomain partitions).
+
+    The interface classes follow the same rule read from Section 3 for
+    general partitions: n(x) = the subdomains holding a box incident to the
+    free node x; a node with |n(x)| = 1 is interior to that subdomain; the
+    nodes with one sharing set split into connected pieces (two nodes are
+    adjacent when a box holds both), and each piece is one object: a face
+    when |n(x)| = 2, an edge when |n(x)| >= 3 and the piece has two or more
+    nodes, a vertex when |n(x)| >= 3 and it is a single node.  On a
+    tensor-product box partition this gives the box classification.
+    Orderings are those of Topology."""
+
+    def __init__(self, widths, part, n_parts):
+        self.nsub = (1, 1, 1)
+        self.widths = [np.asarray(w, dtype=np.int64) for w in widths]
+        self.ne_axis = [int(w.sum()) for w in self.widths]
+        self.cuts = [np.concatenate([[0], np.cumsum(w)]) for w in self.widths]
+        self.nn_axis = [n + 1 for n in self.ne_axis]
+        self.n_nodes = int(np.prod(self.nn_axis))
+        self.n_elem = int(np.prod(self.ne_axis))
+        self.part = np.asarray(part, dtype=np.int64)
+        assert self.part.size == self.n_elem
+        self.n_sub = int(n_parts)
+        assert self.part.min() >= 0 and self.part.max() < self.n_sub
+        self._classify_general()
+        self._subdomains_general()
+
+    def _sharing_sets(self):
+        nx, ny, nz = self.nn_axis
+        ex, ey, ez = self.ne_axis
+        nid = np.arange(self.n_nodes)
+        ix, iy, iz = nid % nx, (nid // nx) % ny, nid // (nx * ny)
+        cols = []
+        for dz in (0, 1):
+            for dy in (0, 1):
+                for dx in (0, 1):
+                    bx, by, bz = ix - dx, iy - dy, iz - dz
+                    ok = (bx >= 0) & (bx < ex) & (by >= 0) & (by < ey) & (bz >= 0) & (bz < ez)
+                    b = np.where(ok, bx + ex * (by + ey * bz), 0)
+                    cols.append(np.where(ok, self.part[b], -1))
+        P = np.sort(np.stack(cols, axis=1), axis=1)
+        return [tuple(sorted(set(int(v) for v in row if v >= 0))) for row in P], (ix, iy, iz)
+
+    def _classify_general(self):
+        nx, ny, nz = self.nn_axis
+        sets, (ix, iy, iz) = self._sharing_sets()
+        free = (ix > 0) & (ix < nx - 1) & (iy > 0) & (iy < ny - 1) & (iz > 0) & (iz < nz - 1)
+        self.free = free
+        self.free_nodes = np.nonzero(free)[0]
+        self.n_dof = int(self.free_nodes.size)
+        self.dof_of_node = -np.ones(self.n_nodes, dtype=np.int64)
+        self.dof_of_node[self.free_nodes] = np.arange(self.n_dof)
+        self.sharing = sets
+        groups = {}
+        for v in self.free_nodes:
+            if len(sets[v]) >= 2:
+                groups.setdefault(sets[v], []).append(int(v))
+        objects = []
+        for subs, nodes in groups.items():
+            member = set(nodes)
+            seen = set()
+            for v0 in nodes:            # node-id order, so pieces come out sorted by first node
+                if v0 in seen:
+                    continue
+                piece, stack = [], [v0]
+                seen.add(v0)
+                while stack:
+                    v = stack.pop()
+                    piece.append(v)
+                    x, y, z = v % nx, (v // nx) % ny, v // (nx * ny)
+                    for dz in (-1, 0, 1):
+                        for dy in (-1, 0, 1):
+                            for dx in (-1, 0, 1):
+                                if dx == dy == dz == 0:
+                                    continue
+                                w = (x + dx) + nx * ((y + dy) + ny * (z + dz))
+                                inside = 0 <= x + dx < nx and 0 <= y + dy < ny and 0 <= z + dz < nz
+                                if inside and w in member and w not in seen:
+                                    seen.add(w)
+                                    stack.append(w)
+                if len(subs) == 2:
+                    kind = "face"
+                else:
+                    kind = "edge" if len(piece) >= 2 else "vertex"
+                objects.append({"kind": kind, "subs": list(subs), "nodes": np.array(sorted(piece), dtype=np.int64)})
+        order = {"face": 0, "edge": 1, "vertex": 2}
+        objects.sort(key=lambda o: (order[o["kind"]], int(o["nodes"][0])))
+        self.objects = objects
+        self.faces = [k for k, o in enumerate(objects) if o["kind"] == "face"]
+        self.edges = [k for k, o in enumerate(objects) if o["kind"] == "edge"]
+        self.vertices = [k for k, o in enumerate(objects) if o["kind"] == "vertex"]
+        self.iface_of_node = -np.ones(self.n_nodes, dtype=np.int64)
+        start = 0
+        for o in objects:
+            n = o["nodes"].size
+            o["gstart"] = start
+            o["gidx"] = np.arange(start, start + n)
+            self.iface_of_node[o["nodes"]] = o["gidx"]
+            start += n
+        self.n_gamma = start
+        self.iface_nodes = np.concatenate([o["nodes"] for o in objects]) if objects else np.zeros(0, np.int64)
+
+    def _subdomains_general(self):
+        interior = [[] for _ in range(self.n_sub)]
+        for v in self.free_nodes:
+            if len(self.sharing[v]) == 1:
+                interior[self.sharing[v][0]].append(int(v))
+        self.sub = []
+        for s in range(self.n_sub):
+            objs = [k for k, o in enumerate(self.objects) if s in o["subs"]]
+            gamma = np.concatenate([self.objects[k]["gidx"] for k in objs]) if objs else np.zeros(0, np.int64)
+            assert np.all(np.diff(gamma) > 0)
+            loc = {}
+            pos = 0
+            for k in objs:
+                n = self.objects[k]["nodes"].size
+                loc[k] = np.arange(pos, pos + n)
+                pos += n
+            self.sub.append({
+                "interior": np.array(interior[s], dtype=np.int64),
+                "gamma": gamma,
+                "objects": objs,
+                "obj_local": loc,
+                "nI": len(interior[s]),
+                "nB": int(gamma.size),
+            })
+
+    def elements_of(self, s):
+        return np.flatnonzero(self.part == s)
+
+
+def make_topology(problem):
+    """The topology of a problem dict: a general partition when it carries
+    per-box part ids, else the tensor-product box partition."""
+    if problem.get("part") is not None:
+        return PartitionTopology(problem["widths"], problem["part"], problem["n_parts"])
+    return Topology(problem["nsub"], problem["widths"])

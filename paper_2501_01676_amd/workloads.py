@@ -29,6 +29,9 @@ a_nodal: None (affine velocity) or the velocity at every grid node (3 per
          node, node-id order); "p1" only
 u_dirichlet : None (zero data) or a value per grid node, of which the
          boundary nodes' are the Dirichlet data
+part, n_parts : optional irregular partition: subdomain id per box
+         (x-fastest, 0 .. n_parts - 1, each part a face-connected union of
+         boxes); nsub is then (1, 1, 1) and widths give the grid
 
 The random draws (viscosity fields, widths, channels) use
 ``numpy.random.default_rng(seed)`` so that both sides of any comparison see
@@ -260,6 +263,86 @@ def example_random(n, m, seed):
     rng = np.random.default_rng(seed)
     ntet = 6 * (n * m) ** 3
     return _example_problem(n, m, 10.0 ** rng.uniform(-3.0, 3.0, ntet), f"example_random_n{n}_m{m}_s{seed}")
+
+
+def aggregate_partition(ne, nparts, seed, jitter=0.6):
+    """Irregular partition of the boxes of an ne[0] x ne[1] x ne[2] grid into
+    nparts connected parts of nearly equal size, by seeded region growing
+    (a stand-in for the load-balanced aggregation of a mesh that Section 4
+    builds with METIS): seeds by farthest-point sampling from a random first
+    box; then, round robin, every part below its quota ceil(n / nparts)
+    takes the unassigned face neighbour of its region with the smallest
+    squared distance to its seed times (1 + jitter u), u ~ U(0, 1) drawn once
+    per box, so the interfaces are ragged; boxes no part could reach join a
+    neighbouring part.  Returns part ids per box, x-fastest, int32."""
+    import heapq
+    rng = np.random.default_rng(seed)
+    nx, ny, nz = (int(v) for v in ne)
+    n = nx * ny * nz
+    ids = np.arange(n)
+    cx, cy, cz = ids % nx + 0.5, (ids // nx) % ny + 0.5, ids // (nx * ny) + 0.5
+    noise = 1.0 + jitter * rng.uniform(0.0, 1.0, n)
+    seeds = [int(rng.integers(0, n))]
+    d2 = (cx - cx[seeds[0]]) ** 2 + (cy - cy[seeds[0]]) ** 2 + (cz - cz[seeds[0]]) ** 2
+    for _ in range(1, nparts):
+        nxt = int(np.argmax(d2))
+        seeds.append(nxt)
+        d2 = np.minimum(d2, (cx - cx[nxt]) ** 2 + (cy - cy[nxt]) ** 2 + (cz - cz[nxt]) ** 2)
+
+    def neighbours(b):
+        x, y, z = b % nx, (b // nx) % ny, b // (nx * ny)
+        if x > 0: yield b - 1
+        if x < nx - 1: yield b + 1
+        if y > 0: yield b - nx
+        if y < ny - 1: yield b + nx
+        if z > 0: yield b - nx * ny
+        if z < nz - 1: yield b + nx * ny
+
+    part = -np.ones(n, dtype=np.int64)
+    quota = -(-n // nparts)
+    size = [0] * nparts
+    heaps = [[] for _ in range(nparts)]
+
+    def take(p, b):
+        part[b] = p
+        size[p] += 1
+        for q in neighbours(b):
+            if part[q] < 0:
+                s0 = seeds[p]
+                key = ((cx[q] - cx[s0]) ** 2 + (cy[q] - cy[s0]) ** 2 + (cz[q] - cz[s0]) ** 2) * noise[q]
+                heapq.heappush(heaps[p], (key, q))
+
+    for p, b in enumerate(seeds):
+        take(p, b)
+    active = True
+    while active:
+        active = False
+        for p in range(nparts):
+            if size[p] >= quota:
+                continue
+            while heaps[p] and part[heaps[p][0][1]] >= 0:
+                heapq.heappop(heaps[p])
+            if heaps[p]:
+                take(p, heapq.heappop(heaps[p])[1])
+                active = True
+    while (part < 0).any():
+        for b in np.flatnonzero(part < 0):
+            owners = [part[q] for q in neighbours(b) if part[q] >= 0]
+            if owners:
+                part[b] = min(owners)
+    return part.astype(np.int32)
+
+
+def example_irregular(nparts, n, seed):
+    """Section 4's irregular-partition example: the model problem of
+    ``_example_problem`` on an n^3 box grid (h = 1/n, six tetrahedra per
+    box) split by ``aggregate_partition`` into nparts subdomains;
+    nu = 10^r, r ~ U(-3, 3) per tetrahedron."""
+    rng = np.random.default_rng(seed)
+    p = _example_problem(1, n, 10.0 ** rng.uniform(-3.0, 3.0, 6 * n ** 3), f"example_irregular_N{nparts}_n{n}_s{seed}")
+    p["part"] = aggregate_partition((n, n, n), nparts, seed + 1)
+    p["n_parts"] = int(nparts)
+    return p
 
 
 CONFIGS = {
