@@ -109,7 +109,17 @@ typedef struct {
  *     vertex speed and div a is constant on K.
  * u_dirichlet lifts nonzero Dirichlet data (Section 4's example): the
  * computed u is then the free-node part of u_h = u_0 + w, u_0 the data on
- * the boundary nodes; boundary entries keep their data. */
+ * the boundary nodes; boundary entries keep their data.
+ *
+ * part gives a general partition (Section 4's irregular subdomains), every
+ * subdomain a union of grid boxes.  Interface objects then follow from the
+ * sharing sets n(x) of the free nodes: nodes with one set split into pieces
+ * connected through common boxes; a piece is a face when |n(x)| = 2, an edge
+ * when |n(x)| >= 3 and it has two or more nodes, else a vertex.  (On box
+ * partitions this is the box rule except that an edge of a single node is
+ * a vertex.)  Limits of the kernels: faces and the edge eigenproblems of at
+ * most 128 dofs, edges of at most 32 dofs shared by at most 4 subdomains;
+ * larger objects return EINVAL. */
 enum { ABDDC_ELEM_Q1 = 0, ABDDC_ELEM_P1 = 1 };
 typedef struct {
   int32_t nsub[3];          /* subdomains per axis                              */
@@ -130,6 +140,12 @@ typedef struct {
                                (x, y, z), node-id order; ABDDC_ELEM_P1 only      */
   const double* u_dirichlet;/* NULL (zero data), or one per grid node; only the
                                boundary nodes' values are read                   */
+  const int32_t* part;      /* NULL (the tensor-product box partition of nsub and
+                               width), or a general partition: the subdomain id
+                               in [0, n_parts) of every box (x-fastest); nsub must
+                               then be {1, 1, 1} (width gives the grid) and every
+                               part hold a box.  Always a HOST array.           */
+  int32_t n_parts;          /* number of subdomains of part                     */
 } abddc_problem;
 
 enum { ABDDC_PREC_FP64 = 0, ABDDC_PREC_MIXED = 1 };
@@ -368,8 +384,9 @@ void abddc_mlp_destroy(abddc_mlp* mlp);
 /* Features of every edge of the context (edge kind order) into X (DEVICE,
  * n_edge x 133); eligible (DEVICE int32 per edge, may be NULL) is 1 for
  * edges of n_E = 7 dofs (features of other edges are still written).
- * Trilinear-box problems only (EINVAL for ABDDC_ELEM_P1); so is
- * constraint_source = ABDDC_CONSTRAINTS_MLP in abddc_setup_coarse_space. */
+ * Trilinear boxes on box partitions only (EINVAL for ABDDC_ELEM_P1 or a
+ * general partition); so is constraint_source = ABDDC_CONSTRAINTS_MLP in
+ * abddc_setup_coarse_space. */
 int abddc_edge_features(abddc_ctx* ctx, float* X, int32_t* eligible);
 /* Training targets after a setup: the projector upper triangles of the
  * context's edge bases (DEVICE, n_edge x 28; zeros for n_E != 7). */

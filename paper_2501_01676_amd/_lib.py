@@ -46,6 +46,8 @@ class Problem(C.Structure):
         ("origin", C.c_double * 3),
         ("a_nodal", C.POINTER(C.c_double)),
         ("u_dirichlet", C.POINTER(C.c_double)),
+        ("part", C.POINTER(C.c_int32)),
+        ("n_parts", C.c_int32),
     ]
 
 

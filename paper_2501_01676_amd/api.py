@@ -101,6 +101,11 @@ class Solver:
         for i in range(9):
             p.beta1[i] = float(np.asarray(problem["beta1"]).reshape(9)[i])
         p.element = ELEMENTS[problem.get("element", "q1")]
+        if problem.get("part") is not None:
+            part = np.ascontiguousarray(problem["part"], dtype=np.int32)
+            self._keep.append(part)
+            p.part = part.ctypes.data_as(C.POINTER(C.c_int32))
+            p.n_parts = int(problem["n_parts"])
         for a, v in enumerate(problem.get("origin", (0.0, 0.0, 0.0))):
             p.origin[a] = float(v)
         nu = problem["nu"]

@@ -240,6 +240,9 @@ extern "C" int abddc_assemble(const abddc_problem* prob, const abddc_device* dev
                   "element must be ABDDC_ELEM_Q1 or ABDDC_ELEM_P1");
     ABDDC_REQUIRE(!prob->a_nodal || prob->element == ABDDC_ELEM_P1, ABDDC_EINVAL,
                   "a_nodal needs element = ABDDC_ELEM_P1");
+    ABDDC_REQUIRE(!prob->part || (prob->nsub[0] == 1 && prob->nsub[1] == 1 && prob->nsub[2] == 1), ABDDC_EINVAL,
+                  "part needs nsub = {1, 1, 1} (width gives the grid)");
+    ABDDC_REQUIRE(!prob->part || prob->n_parts >= 1, ABDDC_EINVAL, "part needs n_parts >= 1");
     for (int a = 0; a < 3; ++a)
       ABDDC_REQUIRE(std::isfinite(prob->origin[a]), ABDDC_EINVAL, "origin must be finite");
     ABDDC_REQUIRE((dev->alloc == nullptr) == (dev->free == nullptr), ABDDC_EINVAL,
@@ -343,7 +346,14 @@ extern "C" int abddc_assemble(const abddc_problem* prob, const abddc_device* dev
     }
 
     ht.mark("assemble: coefficients, element kernel queued");
-    T.build_objects();
+    if (prob->part) {
+      T.build_partition(prob->part, prob->n_parts);
+      for (int e : T.edges)
+        ABDDC_REQUIRE(T.objects[e].subs.size() <= 4 && T.objects[e].n <= 32, ABDDC_EINVAL,
+                      "partition: an edge has more than 4 subdomains or more than 32 dofs");
+    } else {
+      T.build_objects();
+    }
     ht.mark("assemble: topology");
     // ---------------------------------------------------- local layout
     const int nsub = T.n_sub;
@@ -396,31 +406,25 @@ extern "C" int abddc_assemble(const abddc_problem* prob, const abddc_device* dev
       for (int sub = (int)sb; sub < (int)se; ++sub) {
         const SubInfo& si = T.sub[sub];
         const SubAsm& a = sa[sub];
-        // local node list [interior; Gamma_i] and the box-local map, walking
-        // the grid index boxes (node-id order) of the interior and of every
-        // interface object
+        // local node list [interior; Gamma_i] (interior nodes by node id,
+        // then the nodes of every interface object) and the map from the
+        // subdomain's bounding box of nodes to local positions
         const int e0[3] = {si.ebox[0][0], si.ebox[1][0], si.ebox[2][0]};
         const int bx = si.ebox[0][1] - e0[0] + 1, by = si.ebox[1][1] - e0[1] + 1;
         const size_t b0 = (size_t)a.lmoff;
         int32_t* ln = lnode.data() + a.loff;
         int32_t* idof = int_dof.data() + a.ioff;
         int loc = 0;
-        auto walk = [&](const int* lo, const int* hi, bool interior) {
-          for (int iz = lo[2]; iz <= hi[2]; ++iz)
-            for (int iy = lo[1]; iy <= hi[1]; ++iy) {
-              const int64_t row = T.node_id(0, iy, iz);
-              const size_t brow = b0 + (size_t)bx * ((iy - e0[1]) + (size_t)by * (iz - e0[2])) - e0[0];
-              for (int ix = lo[0]; ix <= hi[0]; ++ix) {
-                if (interior) idof[loc] = (int32_t)T.dof_of_node[row + ix];
-                ln[loc] = (int32_t)(row + ix);
-                lmap[brow + ix] = loc++;
-              }
-            }
+        auto place = [&](int64_t v, bool interior) {
+          const int ix = (int)(v % T.nn[0]), iy = (int)((v / T.nn[0]) % T.nn[1]);
+          const int iz = (int)(v / ((int64_t)T.nn[0] * T.nn[1]));
+          if (interior) idof[loc] = (int32_t)T.dof_of_node[v];
+          ln[loc] = (int32_t)v;
+          lmap[b0 + (ix - e0[0]) + (size_t)bx * ((iy - e0[1]) + (size_t)by * (iz - e0[2]))] = loc++;
         };
-        const int ilo[3] = {e0[0] + 1, e0[1] + 1, e0[2] + 1};
-        const int ihi[3] = {si.ebox[0][1] - 1, si.ebox[1][1] - 1, si.ebox[2][1] - 1};
-        walk(ilo, ihi, true);
-        for (int k : si.objs) walk(T.objects[k].lo, T.objects[k].hi, false);
+        for (int64_t v : si.interior) place(v, true);
+        for (int k : si.objs)
+          for (int64_t v : T.objects[k].nodes) place(v, false);
         std::fill(rowsub.begin() + a.loff, rowsub.begin() + a.loff + loc, sub);
         for (int l = 0; l < si.nB; ++l) gam[a.goff + l] = (int32_t)si.gamma[l];
       }
@@ -443,7 +447,9 @@ extern "C" int abddc_assemble(const abddc_problem* prob, const abddc_device* dev
     c->dA.alloc(std::max<int64_t>(at, 1));
     c->dA.zero(s);
     {
-      launch_scatter(c->d_subs.p, d_rowsub.p, d_lnode.p, d_lmap.p, rows, T.nn, T.ne, Ae.p, Fe.p, c->dA.p, s);
+      DevBuf<int32_t> d_part;
+      if (prob->part) d_part = to_device(std::vector<int32_t>(prob->part, prob->part + T.n_elem), s);
+      launch_scatter(c->d_subs.p, d_rowsub.p, d_lnode.p, d_lmap.p, rows, T.nn, T.ne, Ae.p, Fe.p, d_part.p, c->dA.p, s);
       record(c.get(), 11);
       // interior elimination: S^(i), g^(i) in the trailing block / column
       std::vector<PluDesc<double>> pd;
@@ -531,8 +537,10 @@ extern "C" int abddc_setup_coarse_space(abddc_ctx* c, const abddc_options* opts,
                   ABDDC_EINVAL, "bad constraint source");
     ABDDC_REQUIRE(o.constraint_source != ABDDC_CONSTRAINTS_MLP || (o.mlp && o.mlp->device == c->device), ABDDC_EINVAL,
                   "learned constraints need a network on the context's device");
-    ABDDC_REQUIRE(o.constraint_source != ABDDC_CONSTRAINTS_MLP || c->element == ABDDC_ELEM_Q1, ABDDC_EINVAL,
-                  "learned edge constraints read one viscosity per box: trilinear-box problems only");
+    ABDDC_REQUIRE(o.constraint_source != ABDDC_CONSTRAINTS_MLP || (c->element == ABDDC_ELEM_Q1 && !c->topo.general),
+                  ABDDC_EINVAL,
+                  "learned edge constraints read one viscosity per box around straight edges: trilinear boxes on box "
+                  "partitions only");
     ABDDC_REQUIRE(o.pinv_rtol >= 0 && o.svd_rtol >= 0 && o.tie_rtol >= 0, ABDDC_EINVAL, "negative tolerance");
     ABDDC_REQUIRE(o.judge_iters >= 0 && o.judge_ratio >= 0 && std::isfinite(o.judge_ratio), ABDDC_EINVAL,
                   "bad judge settings");

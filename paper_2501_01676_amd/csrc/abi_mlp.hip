@@ -192,8 +192,9 @@ extern "C" int abddc_edge_features(abddc_ctx* c, float* X, int32_t* eligible) {
     ABDDC_HIP(hipSetDevice(c->device));
     AllocScope as(&c->dalloc);
     StreamScope ss(c->stream);
-    ABDDC_REQUIRE(c->element == ABDDC_ELEM_Q1, ABDDC_EINVAL,
-                  "edge features read one viscosity per box: trilinear-box problems only");
+    ABDDC_REQUIRE(c->element == ABDDC_ELEM_Q1 && !c->topo.general, ABDDC_EINVAL,
+                  "edge features read one viscosity per box around straight edges: trilinear boxes on box "
+                  "partitions only");
     const int ne = (int)c->topo.edges.size();
     if (ne == 0) return ABDDC_OK;
     ABDDC_REQUIRE(X, ABDDC_EINVAL, "null feature buffer");

@@ -40,8 +40,8 @@ void launch_check_positive(const double* v, int64_t n, int* flag, hipStream_t s)
 void launch_elem(const ElemParams& P, const double* nu, const ElemFields& F, double* Ae, double* Fe,
                  hipStream_t s);
 void launch_scatter(const SubAsm* subs, const int32_t* rowsub, const int32_t* lnode, const int32_t* lmap,
-                    int64_t nrows, const int nn[3], const int ne[3], const double* Ae, const double* Fe, double* A,
-                    hipStream_t s);
+                    int64_t nrows, const int nn[3], const int ne[3], const double* Ae, const double* Fe,
+                    const int32_t* part, double* A, hipStream_t s);
 void launch_extract(const SubAsm* subs, int nsub, int max_nB, const double* A, double* S, double* B, double* g,
                     hipStream_t s);
 // interior recovery; max_nloc = max over subdomains of n_I + n_B (LDS size)

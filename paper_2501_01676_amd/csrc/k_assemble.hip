@@ -240,7 +240,8 @@ __global__ void elem_p1_kernel(ElemParams P, const double* __restrict__ nu, Elem
 __global__ void scatter_kernel(const SubAsm* __restrict__ subs, const int32_t* __restrict__ rowsub,
                                const int32_t* __restrict__ lnode, const int32_t* __restrict__ lmap,
                                int64_t nrows, int nn0, int nn1, int ne0, int ne1, const double* __restrict__ Ae,
-                               const double* __restrict__ Fe, double* __restrict__ A) {
+                               const double* __restrict__ Fe, const int32_t* __restrict__ part,
+                               double* __restrict__ A) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= nrows) return;
   const int s = rowsub[t];
@@ -264,6 +265,7 @@ __global__ void scatter_kernel(const SubAsm* __restrict__ subs, const int32_t* _
           for (int ey = max(max(iy, qy) - 1, S.ebox[2]); ey <= min(min(iy, qy), S.ebox[3] - 1); ++ey)
             for (int ex = max(max(ix, qx) - 1, S.ebox[0]); ex <= min(min(ix, qx), S.ebox[1] - 1); ++ex) {
               const int64_t e = ex + (int64_t)ne0 * (ey + (int64_t)ne1 * ez);
+              if (part && part[e] != s) continue;
               const int il = (ix - ex) + 2 * (iy - ey) + 4 * (iz - ez);
               const int jl = (qx - ex) + 2 * (qy - ey) + 4 * (qz - ez);
               sum += Ae[e * 64 + il * 8 + jl];
@@ -275,6 +277,7 @@ __global__ void scatter_kernel(const SubAsm* __restrict__ subs, const int32_t* _
     for (int ey = max(iy - 1, S.ebox[2]); ey <= min(iy, S.ebox[3] - 1); ++ey)
       for (int ex = max(ix - 1, S.ebox[0]); ex <= min(ix, S.ebox[1] - 1); ++ex) {
         const int64_t e = ex + (int64_t)ne0 * (ey + (int64_t)ne1 * ez);
+        if (part && part[e] != s) continue;
         f += Fe[e * 8 + (ix - ex) + 2 * (iy - ey) + 4 * (iz - ez)];
       }
   arow[S.nloc] = f;
@@ -433,10 +436,10 @@ void launch_elem(const ElemParams& P, const double* nu, const ElemFields& F, dou
 }
 
 void launch_scatter(const SubAsm* subs, const int32_t* rowsub, const int32_t* lnode, const int32_t* lmap,
-                    int64_t nrows, const int nn[3], const int ne[3], const double* Ae, const double* Fe, double* A,
-                    hipStream_t s) {
+                    int64_t nrows, const int nn[3], const int ne[3], const double* Ae, const double* Fe,
+                    const int32_t* part, double* A, hipStream_t s) {
   scatter_kernel<<<(unsigned)((nrows + 255) / 256), 256, 0, s>>>(subs, rowsub, lnode, lmap, nrows, nn[0], nn[1],
-                                                                  ne[0], ne[1], Ae, Fe, A);
+                                                                  ne[0], ne[1], Ae, Fe, part, A);
   ABDDC_HIP(hipGetLastError());
 }
 

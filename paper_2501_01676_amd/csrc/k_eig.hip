@@ -1271,8 +1271,10 @@ __global__ void __launch_bounds__(256) qr_complete_kernel(const QrDesc* __restri
 }
 
 // One-sided Jacobi on the rows of G: G = U diag(sigma) W^T, U accumulated.
+// RMAX: the largest n_E of the instance.
+template <int RMAX>
 __global__ void __launch_bounds__(64) svd_left_kernel(const SvdDesc* __restrict__ descs, double rtol) {
-  constexpr int RMAX = 16, CMAX = 256;
+  constexpr int CMAX = 256;
   __shared__ double Gm[RMAX][CMAX];
   __shared__ double Um[RMAX][RMAX];
   __shared__ double sig[RMAX];
@@ -1509,9 +1511,14 @@ void qr_complete_batched(const std::vector<QrDesc>& descs, hipStream_t s) {
 
 void svd_left_batched(const std::vector<SvdDesc>& descs, double rtol, hipStream_t s) {
   if (descs.empty()) return;
-  for (auto& d : descs) ABDDC_REQUIRE(d.n <= 16 && d.ncol <= 256, ABDDC_EINVAL, "svd: edge block too large");
+  int nmax = 0;
+  for (auto& d : descs) {
+    ABDDC_REQUIRE(d.n <= 32 && d.ncol <= 256, ABDDC_EINVAL, "svd: edge block too large");
+    nmax = std::max(nmax, d.n);
+  }
   const SvdDesc* dd = Arena::for_stream(s).put(descs);
-  svd_left_kernel<<<descs.size(), 64, 0, s>>>(dd, rtol);
+  if (nmax <= 16) svd_left_kernel<16><<<descs.size(), 64, 0, s>>>(dd, rtol);
+  else svd_left_kernel<32><<<descs.size(), 64, 0, s>>>(dd, rtol);
   ABDDC_HIP(hipGetLastError());
 }
 

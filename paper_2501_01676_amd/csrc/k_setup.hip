@@ -41,8 +41,8 @@ __global__ void deluxe_build_kernel(const DeluxeDesc* __restrict__ descs) {
 
 // Metric of the earlier edge eigenproblem, regrouped by the weight index:
 // B_E = sum_k D^(k)^T (sum_{i != k} B_E^(i)) D^(k), written symmetrised.
+template <int NE>
 __global__ void __launch_bounds__(256) edge_old_metric_kernel(const EdgeOldDesc* __restrict__ descs) {
-  constexpr int NE = 16;
   __shared__ double G[NE][NE + 1], Z[NE][NE + 1], A[NE][NE + 1];
   __shared__ EdgeOldDesc sd;   // the descriptor (indexed by member) staged in LDS once
   if (threadIdx.x == 0) sd = descs[blockIdx.x];
@@ -87,8 +87,9 @@ __global__ void __launch_bounds__(256) edge_old_metric_kernel(const EdgeOldDesc*
 //   Q      = sum_k P_k^T Btilde^(k) P_k in the variable order
 //            [what (n_E), w_H (n_H), wcheck ((m-1) n_E)], where P_k maps
 //            (wcheck, what, w_H) to (w_k,E = That_k wcheck + what, w_k,H = R_k w_H).
+// NE, NW: the largest n_E and (m - 1) n_E of the instance (LDS arrays).
+template <int NE, int NW>
 __global__ void __launch_bounds__(256) edge_assemble_kernel(const EdgeAsmDesc* __restrict__ descs) {
-  constexpr int NE = 16, NW = 48;
   __shared__ double Th[4][NE][NW];
   __shared__ double Z[NE][NW + NE];
   __shared__ EdgeAsmDesc sd;   // the descriptor (indexed by member) staged in LDS once
@@ -217,20 +218,29 @@ void deluxe_build_batched(const std::vector<DeluxeDesc>& descs, hipStream_t s) {
 
 void edge_old_metric_batched(const std::vector<EdgeOldDesc>& descs, hipStream_t s) {
   if (descs.empty()) return;
-  for (auto& d : descs)
-    ABDDC_REQUIRE(d.nE >= 1 && d.nE <= 16 && d.m >= 2 && d.m <= 4, ABDDC_EINVAL,
-                  "earlier edge eigenproblem: edges need 2..4 members and at most 16 dofs");
+  int nmax = 0;
+  for (auto& d : descs) {
+    ABDDC_REQUIRE(d.nE >= 1 && d.nE <= 32 && d.m >= 2 && d.m <= 4, ABDDC_EINVAL,
+                  "earlier edge eigenproblem: edges need 2..4 members and at most 32 dofs");
+    nmax = std::max(nmax, d.nE);
+  }
   const EdgeOldDesc* dd = Arena::for_stream(s).put(descs);
-  edge_old_metric_kernel<<<(unsigned)descs.size(), 256, 0, s>>>(dd);
+  if (nmax <= 16) edge_old_metric_kernel<16><<<(unsigned)descs.size(), 256, 0, s>>>(dd);
+  else edge_old_metric_kernel<32><<<(unsigned)descs.size(), 256, 0, s>>>(dd);
   ABDDC_HIP(hipGetLastError());
 }
 
 void edge_assemble_batched(const std::vector<EdgeAsmDesc>& descs, hipStream_t s) {
   if (descs.empty()) return;
-  for (auto& d : descs)
-    ABDDC_REQUIRE(d.nE <= 16 && (d.m - 1) * d.nE <= 48 && d.m <= 4, ABDDC_EINVAL, "edge too large");
+  bool small = true;
+  for (auto& d : descs) {
+    ABDDC_REQUIRE(d.nE <= 32 && (d.m - 1) * d.nE <= 64 && d.m <= 4, ABDDC_EINVAL,
+                  "edge too large: at most 32 dofs, 4 members and 64 jump unknowns");
+    small = small && d.nE <= 16 && (d.m - 1) * d.nE <= 48;
+  }
   const EdgeAsmDesc* dd = Arena::for_stream(s).put(descs);
-  edge_assemble_kernel<<<descs.size(), 256, 0, s>>>(dd);
+  if (small) edge_assemble_kernel<16, 48><<<descs.size(), 256, 0, s>>>(dd);
+  else edge_assemble_kernel<32, 64><<<descs.size(), 256, 0, s>>>(dd);
   ABDDC_HIP(hipGetLastError());
 }
 

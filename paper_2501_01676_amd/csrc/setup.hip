@@ -142,6 +142,9 @@ void plan_face_elimination(abddc_ctx* c, hipStream_t s) {
   FaceElimPlan& P = c->fplan;
   P = FaceElimPlan();
   auto face_axis = [&](int k) {
+    // general partitions: every face is a group of its own, so step (3)
+    // never runs and step (2) leaves exactly that face
+    if (T.general) return 3 + T.kind_index[k];
     const int a = T.objects[k].subs[0], b = T.objects[k].subs[1];
     if (a % T.nsub[0] != b % T.nsub[0]) return 0;
     if ((a / T.nsub[0]) % T.nsub[1] != (b / T.nsub[0]) % T.nsub[1]) return 1;
@@ -1124,12 +1127,37 @@ void run_setup(abddc_ctx* c) {
     DevBuf<double> Aug2((size_t)std::max(1, 4 * np * np));
     DevBuf<double> SPi((size_t)std::max(1, np * np));
     SPi.zero(s);
-    // colour the subdomains by index parity: equal colours share no primal unknown
-    for (int color = 0; color < 8; ++color) {
-      std::vector<CoarseAddDesc> cd;
+    // colour the subdomains so that equal colours share no primal unknown:
+    // by index parity on box partitions, greedily (first free colour in
+    // subdomain order) on general ones
+    std::vector<int> colour(nsub, 0);
+    int ncolour = 8;
+    if (T.general) {
+      std::vector<std::vector<int>> owners(np);
+      for (int sub = 0; sub < nsub; ++sub)
+        for (int32_t q : Pid[sub]) owners[q].push_back(sub);
+      ncolour = 0;
+      std::vector<int> mark;
+      for (int sub = 0; sub < nsub; ++sub) {
+        mark.assign(ncolour + 1, 0);
+        for (int32_t q : Pid[sub])
+          for (int o : owners[q])
+            if (o < sub) mark[colour[o]] = 1;
+        int cl = 0;
+        while (mark[cl]) ++cl;
+        colour[sub] = cl;
+        ncolour = std::max(ncolour, cl + 1);
+      }
+    } else {
       for (int sub = 0; sub < nsub; ++sub) {
         const int sx = sub % T.nsub[0], sy = (sub / T.nsub[0]) % T.nsub[1], sz = sub / (T.nsub[0] * T.nsub[1]);
-        if (((sx & 1) | ((sy & 1) << 1) | ((sz & 1) << 2)) != color) continue;
+        colour[sub] = (sx & 1) | ((sy & 1) << 1) | ((sz & 1) << 2);
+      }
+    }
+    for (int color = 0; color < ncolour; ++color) {
+      std::vector<CoarseAddDesc> cd;
+      for (int sub = 0; sub < nsub; ++sub) {
+        if (colour[sub] != color) continue;
         const int nP = (int)Pi[sub].size(), nD = (int)Dl[sub].size(), na = 2 * nD + nP;
         if (nP == 0) continue;
         cd.push_back({Aug.p + aoff2[sub] + (int64_t)nD * na + nD, pool.ptr(pidx[sub]), nP, na});

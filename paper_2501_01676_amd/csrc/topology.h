@@ -1,10 +1,16 @@
-// Host-side box-partition topology: interface classes and orderings.
+// Host-side partition topology: interface classes and orderings.
 //
-// A free grid node on an internal subdomain cut plane in exactly one / two /
-// three axes is a face / edge / vertex node; nodes with the same set n(x)
-// of sharing subdomains form one interface object (Section 3 defers the
-// definitions of faces, edges and vertices; this is the box-partition rule).
-// Orderings are part of the C ABI (include/abddc.h).
+// Box partitions: a free grid node on an internal subdomain cut plane in
+// exactly one / two / three axes is a face / edge / vertex node; nodes with
+// the same set n(x) of sharing subdomains form one interface object.
+// General partitions (every subdomain a union of grid boxes): n(x) = the
+// subdomains holding a box incident to the free node x; |n(x)| = 1 makes x
+// interior; the nodes with one sharing set split into connected pieces (two
+// nodes adjacent when a box holds both), each piece one object: a face when
+// |n(x)| = 2, an edge when |n(x)| >= 3 and the piece has two or more nodes,
+// else a vertex.  (Section 3 defers the definitions of faces, edges and
+// vertices; these are the rules read here.)  Orderings are part of the C ABI
+// (include/abddc.h).
 #pragma once
 
 #include <cstdint>
@@ -20,11 +26,13 @@ struct Object {
   std::vector<int64_t> nodes;   // sorted grid node ids
   int64_t gstart;               // first interface index
   int n;                        // number of dofs
-  int lo[3], hi[3];             // the nodes: the grid index box [lo, hi] (inclusive) per axis
+  int lo[3], hi[3];             // grid index box [lo, hi] (inclusive) per axis holding the nodes
+                                // (exactly the nodes on box partitions)
 };
 
 struct SubInfo {
-  int ebox[3][2];               // element index range [lo, hi) per axis
+  int ebox[3][2];               // element index range [lo, hi) per axis (the subdomain's
+                                // bounding box on general partitions)
   std::vector<int64_t> interior;  // grid node ids, sorted
   std::vector<int64_t> gamma;     // interface indices, sorted
   std::vector<int> objs;          // objects of Gamma_i, interface order
@@ -52,6 +60,10 @@ struct Topology {
   // objects and subdomain lists
   void build_grid(const int nsub_in[3], const int* const width_in[3]);
   void build_objects();
+  // general partition: part[box] in [0, n_parts) per box (x-fastest), each
+  // part non-empty; after build_grid with one subdomain per axis
+  void build_partition(const int32_t* part, int n_parts);
+  bool general = false;         // built by build_partition
   int64_t node_id(int64_t ix, int64_t iy, int64_t iz) const { return ix + nn[0] * (iy + (int64_t)nn[1] * iz); }
   int sub_id(int sx, int sy, int sz) const { return sx + nsub[0] * (sy + nsub[1] * sz); }
 };

@@ -159,3 +159,140 @@ void Topology::build_objects() {
 }
 
 }  // namespace abddc
+
+namespace abddc {
+
+void Topology::build_partition(const int32_t* part, int n_parts) {
+  ABDDC_REQUIRE(nsub[0] == 1 && nsub[1] == 1 && nsub[2] == 1, ABDDC_EINVAL,
+                "a general partition takes the grid as one subdomain per axis");
+  ABDDC_REQUIRE(n_parts >= 1, ABDDC_EINVAL, "n_parts must be >= 1");
+  general = true;
+  n_sub = n_parts;
+  std::vector<int64_t> boxes_of(n_parts, 0);
+  for (int64_t e = 0; e < n_elem; ++e) {
+    ABDDC_REQUIRE(part[e] >= 0 && part[e] < n_parts, ABDDC_EINVAL, "part id outside [0, n_parts)");
+    ++boxes_of[part[e]];
+  }
+  for (int p = 0; p < n_parts; ++p) ABDDC_REQUIRE(boxes_of[p] > 0, ABDDC_EINVAL, "a part holds no box");
+  dof_of_node.assign(n_nodes, -1);
+  for (int iz = 1; iz < nn[2] - 1; ++iz)
+    for (int iy = 1; iy < nn[1] - 1; ++iy)
+      for (int ix = 1; ix < nn[0] - 1; ++ix)
+        dof_of_node[node_id(ix, iy, iz)] = (ix - 1) + (int64_t)(nn[0] - 2) * ((iy - 1) + (int64_t)(nn[1] - 2) * (iz - 1));
+  n_dof = (int64_t)(nn[0] - 2) * (nn[1] - 2) * (nn[2] - 2);
+  // sharing set of every free node: the sorted distinct parts of its boxes
+  std::vector<std::array<int, 8>> sets(n_nodes);
+  std::vector<uint8_t> nset(n_nodes, 0);
+  for (int64_t v = 0; v < n_nodes; ++v) {
+    if (dof_of_node[v] < 0) continue;
+    const int ix = (int)(v % nn[0]), iy = (int)((v / nn[0]) % nn[1]), iz = (int)(v / ((int64_t)nn[0] * nn[1]));
+    std::array<int, 8>& S = sets[v];
+    int k = 0;
+    for (int dz = 0; dz < 2; ++dz)
+      for (int dy = 0; dy < 2; ++dy)
+        for (int dx = 0; dx < 2; ++dx) {
+          const int bx = ix - dx, by = iy - dy, bz = iz - dz;   // free nodes have all 8 boxes
+          S[k++] = part[bx + (int64_t)ne[0] * (by + (int64_t)ne[1] * bz)];
+        }
+    std::sort(S.begin(), S.end());
+    nset[v] = (uint8_t)(std::unique(S.begin(), S.end()) - S.begin());
+  }
+  auto same_set = [&](int64_t a, int64_t b) {
+    if (nset[a] != nset[b]) return false;
+    for (int i = 0; i < nset[a]; ++i)
+      if (sets[a][i] != sets[b][i]) return false;
+    return true;
+  };
+  // connected pieces of equal sharing sets (26-neighbourhood), found from
+  // each piece's smallest node, so the pieces come out by first node
+  objects.clear();
+  std::vector<char> seen(n_nodes, 0);
+  std::vector<int64_t> stack;
+  for (int64_t v0 = 0; v0 < n_nodes; ++v0) {
+    if (dof_of_node[v0] < 0 || nset[v0] < 2 || seen[v0]) continue;
+    Object o;
+    o.subs.assign(sets[v0].begin(), sets[v0].begin() + nset[v0]);
+    stack.assign(1, v0);
+    seen[v0] = 1;
+    while (!stack.empty()) {
+      const int64_t v = stack.back();
+      stack.pop_back();
+      o.nodes.push_back(v);
+      const int ix = (int)(v % nn[0]), iy = (int)((v / nn[0]) % nn[1]), iz = (int)(v / ((int64_t)nn[0] * nn[1]));
+      for (int dz = -1; dz <= 1; ++dz)
+        for (int dy = -1; dy <= 1; ++dy)
+          for (int dx = -1; dx <= 1; ++dx) {
+            const int qx = ix + dx, qy = iy + dy, qz = iz + dz;
+            if (qx < 0 || qy < 0 || qz < 0 || qx >= nn[0] || qy >= nn[1] || qz >= nn[2]) continue;
+            const int64_t w = node_id(qx, qy, qz);
+            if (seen[w] || dof_of_node[w] < 0 || !same_set(v0, w)) continue;
+            seen[w] = 1;
+            stack.push_back(w);
+          }
+    }
+    std::sort(o.nodes.begin(), o.nodes.end());
+    o.n = (int)o.nodes.size();
+    o.kind = o.subs.size() == 2 ? KIND_FACE : (o.n >= 2 ? KIND_EDGE : KIND_VERTEX);
+    for (int a = 0; a < 3; ++a) {
+      o.lo[a] = nn[a];
+      o.hi[a] = -1;
+    }
+    for (int64_t v : o.nodes) {
+      const int c[3] = {(int)(v % nn[0]), (int)((v / nn[0]) % nn[1]), (int)(v / ((int64_t)nn[0] * nn[1]))};
+      for (int a = 0; a < 3; ++a) {
+        o.lo[a] = std::min(o.lo[a], c[a]);
+        o.hi[a] = std::max(o.hi[a], c[a]);
+      }
+    }
+    objects.push_back(std::move(o));
+  }
+  std::stable_sort(objects.begin(), objects.end(),
+                   [](const Object& a, const Object& b) { return a.kind < b.kind; });
+  faces.clear();
+  edges.clear();
+  vertices.clear();
+  kind_index.assign(objects.size(), 0);
+  iface_of_node.assign(n_nodes, -1);
+  int64_t g = 0;
+  for (size_t k = 0; k < objects.size(); ++k) {
+    Object& o = objects[k];
+    o.gstart = g;
+    for (int q = 0; q < o.n; ++q) iface_of_node[o.nodes[q]] = g + q;
+    g += o.n;
+    std::vector<int>& lst = o.kind == KIND_FACE ? faces : (o.kind == KIND_EDGE ? edges : vertices);
+    kind_index[k] = (int)lst.size();
+    lst.push_back((int)k);
+  }
+  n_gamma = g;
+  sub.assign(n_sub, SubInfo());
+  for (int s = 0; s < n_sub; ++s)
+    for (int a = 0; a < 3; ++a) {
+      sub[s].ebox[a][0] = ne[a];
+      sub[s].ebox[a][1] = 0;
+    }
+  for (int64_t e = 0; e < n_elem; ++e) {
+    const int c[3] = {(int)(e % ne[0]), (int)((e / ne[0]) % ne[1]), (int)(e / ((int64_t)ne[0] * ne[1]))};
+    SubInfo& si = sub[part[e]];
+    for (int a = 0; a < 3; ++a) {
+      si.ebox[a][0] = std::min(si.ebox[a][0], c[a]);
+      si.ebox[a][1] = std::max(si.ebox[a][1], c[a] + 1);
+    }
+  }
+  for (int64_t v = 0; v < n_nodes; ++v)
+    if (dof_of_node[v] >= 0 && nset[v] == 1) sub[sets[v][0]].interior.push_back(v);
+  for (size_t k = 0; k < objects.size(); ++k)
+    for (int s : objects[k].subs) sub[s].objs.push_back((int)k);
+  for (int s = 0; s < n_sub; ++s) {
+    SubInfo& si = sub[s];
+    si.nI = (int)si.interior.size();
+    int pos = 0;
+    for (int k : si.objs) {
+      si.obj_off.push_back(pos);
+      for (int q = 0; q < objects[k].n; ++q) si.gamma.push_back(objects[k].gstart + q);
+      pos += objects[k].n;
+    }
+    si.nB = pos;
+  }
+}
+
+}  // namespace abddc

@@ -147,10 +147,10 @@ def test_learned_constraints_refuse_tetrahedra():
     from paper_2501_01676_amd import api
     g = api.Solver(W.example_helicoid(1, 1.0, 1e-7, 2))
     assert _code(g.edge_features) == L.EINVAL
-    assert b"trilinear" in L.load().abddc_last_error()
+    assert b"trilinear boxes" in L.load().abddc_last_error()
     net = api.MLP(W.mlp_init_params(0))
     assert _code(g.setup_coarse_space, constraint_source=1, mlp=net) == L.EINVAL
-    assert b"trilinear" in L.load().abddc_last_error()
+    assert b"trilinear boxes" in L.load().abddc_last_error()
     counts = g.setup_coarse_space(theta_face=1.0 + np.log(2.0))
     assert counts["n_vertex"] == 1
     g.close()

@@ -71,6 +71,11 @@ CASES = {
                           dict(_theta_f(4), edge_variant=1)),
     "p1_random_n3": (lambda: W.example_random(3, 3, 0), _theta_f(3), _theta_f(3)),
     "p1_affine_lifted": (_p1_affine_lifted, LOOSE, LOOSE),
+    # Section 4's irregular partitions (region-grown unions of boxes)
+    "irregular_8": (lambda: W.example_irregular(8, 8, 0), _theta_f(4), _theta_f(4)),
+    "irregular_27_old": (lambda: W.example_irregular(27, 12, 1), dict(_theta_f(4), edge_variant="old"),
+                         dict(_theta_f(4), edge_variant=1)),
+    "irregular_12_loose": (lambda: W.example_irregular(12, 10, 5), LOOSE, LOOSE),
 }
 
 
