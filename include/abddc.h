@@ -118,7 +118,7 @@ typedef struct {
  * when |n(x)| >= 3 and it has two or more nodes, else a vertex.  (On box
  * partitions this is the box rule except that an edge of a single node is
  * a vertex.)  Limits of the kernels: faces and the edge eigenproblems of at
- * most 128 dofs, edges of at most 32 dofs shared by at most 4 subdomains;
+ * most 128 dofs, edges of at most 32 dofs shared by at most 8 subdomains;
  * larger objects return EINVAL. */
 enum { ABDDC_ELEM_Q1 = 0, ABDDC_ELEM_P1 = 1 };
 typedef struct {

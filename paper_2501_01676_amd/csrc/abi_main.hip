@@ -20,6 +20,7 @@
 #include "htrace.h"
 #include "host_pool.h"
 #include "internal.h"
+#include "setup_k.h"
 
 namespace abddc {
 void run_setup(abddc_ctx* c);
@@ -348,9 +349,12 @@ extern "C" int abddc_assemble(const abddc_problem* prob, const abddc_device* dev
     ht.mark("assemble: coefficients, element kernel queued");
     if (prob->part) {
       T.build_partition(prob->part, prob->n_parts);
+      for (int f : T.faces)
+        ABDDC_REQUIRE(T.objects[f].n <= 128, ABDDC_EINVAL,
+                      "partition: a face has more than 128 dofs (the eigensolvers' limit)");
       for (int e : T.edges)
-        ABDDC_REQUIRE(T.objects[e].subs.size() <= 4 && T.objects[e].n <= 32, ABDDC_EINVAL,
-                      "partition: an edge has more than 4 subdomains or more than 32 dofs");
+        ABDDC_REQUIRE((int)T.objects[e].subs.size() <= MAX_EDGE_MEMBERS && T.objects[e].n <= 32, ABDDC_EINVAL,
+                      "partition: an edge has more than 8 subdomains or more than 32 dofs");
     } else {
       T.build_objects();
     }

@@ -90,7 +90,9 @@ __global__ void __launch_bounds__(256) edge_old_metric_kernel(const EdgeOldDesc*
 // NE, NW: the largest n_E and (m - 1) n_E of the instance (LDS arrays).
 template <int NE, int NW>
 __global__ void __launch_bounds__(256) edge_assemble_kernel(const EdgeAsmDesc* __restrict__ descs) {
-  __shared__ double Th[4][NE][NW];
+  // Tb[p][a] = -D_slot[p][q] for a = (slot - 1) n_E + q; That_k = Tb + the
+  // identity in slot k (k >= 1), added where That_k is read
+  __shared__ double Tb[NE][NW];
   __shared__ double Z[NE][NW + NE];
   __shared__ EdgeAsmDesc sd;   // the descriptor (indexed by member) staged in LDS once
   if (threadIdx.x == 0) sd = descs[blockIdx.x];
@@ -100,13 +102,11 @@ __global__ void __launch_bounds__(256) edge_assemble_kernel(const EdgeAsmDesc* _
   const int nt = nw + nE;  // [wcheck, what] width of T_E^(k) = [That_k | I]
   // variable position in Q of paper-order index a (wcheck, what)
   auto qpos = [&](int a) { return a < nw ? nE + nH + a : a - nw; };
-  for (int k = 0; k < m; ++k)
-    for (int idx = tid; idx < nE * nw; idx += blockDim.x) {
-      const int p = idx / nw, a = idx % nw, slot = a / nE + 1, q = a % nE;
-      double v = -d.D[slot][p * nE + q];
-      if (slot == k && p == q) v += 1.0;
-      Th[k][p][a] = v;
-    }
+  for (int idx = tid; idx < nE * nw; idx += blockDim.x) {
+    const int p = idx / nw, a = idx % nw, slot = a / nE + 1, q = a % nE;
+    Tb[p][a] = -d.D[slot][p * nE + q];
+  }
+  auto th = [&](int k, int p, int a) { return Tb[p][a] + ((a / nE + 1 == k && p == a % nE) ? 1.0 : 0.0); };
   for (int idx = tid; idx < nw * nw; idx += blockDim.x) d.ME[idx] = 0.0;
   for (int idx = tid; idx < nv * nv; idx += blockDim.x) d.Q[idx] = 0.0;
   __syncthreads();
@@ -115,14 +115,14 @@ __global__ void __launch_bounds__(256) edge_assemble_kernel(const EdgeAsmDesc* _
     for (int idx = tid; idx < nE * nw; idx += blockDim.x) {
       const int p = idx / nw, a = idx % nw;
       double v = 0.0;
-      for (int q = 0; q < nE; ++q) v += d.BE[k][(size_t)p * d.ldBE[k] + q] * Th[k][q][a];
+      for (int q = 0; q < nE; ++q) v += d.BE[k][(size_t)p * d.ldBE[k] + q] * th(k, q, a);
       Z[p][a] = v;
     }
     __syncthreads();
     for (int idx = tid; idx < nw * nw; idx += blockDim.x) {
       const int a = idx / nw, b = idx % nw;
       double v = 0.0;
-      for (int p = 0; p < nE; ++p) v += Th[k][p][a] * Z[p][b];
+      for (int p = 0; p < nE; ++p) v += th(k, p, a) * Z[p][b];
       d.ME[idx] += v;
     }
     __syncthreads();
@@ -133,7 +133,7 @@ __global__ void __launch_bounds__(256) edge_assemble_kernel(const EdgeAsmDesc* _
       const int p = idx / nt, a = idx % nt;
       double v = 0.0;
       if (a < nw)
-        for (int q = 0; q < nE; ++q) v += Bt[(size_t)p * ldb + q] * Th[k][q][a];
+        for (int q = 0; q < nE; ++q) v += Bt[(size_t)p * ldb + q] * th(k, q, a);
       else
         v = Bt[(size_t)p * ldb + (a - nw)];
       Z[p][a] = v;
@@ -144,7 +144,7 @@ __global__ void __launch_bounds__(256) edge_assemble_kernel(const EdgeAsmDesc* _
       const int a = idx / nt, b = idx % nt;
       double v = 0.0;
       if (a < nw)
-        for (int p = 0; p < nE; ++p) v += Th[k][p][a] * Z[p][b];
+        for (int p = 0; p < nE; ++p) v += th(k, p, a) * Z[p][b];
       else
         v = Z[a - nw][b];
       d.Q[(size_t)qpos(a) * nv + qpos(b)] += v;
@@ -154,7 +154,7 @@ __global__ void __launch_bounds__(256) edge_assemble_kernel(const EdgeAsmDesc* _
       const int a = idx / nHk, h = idx % nHk;
       double v1 = 0.0, v2 = 0.0;
       for (int p = 0; p < nE; ++p) {
-        const double t = a < nw ? Th[k][p][a] : (p == a - nw ? 1.0 : 0.0);
+        const double t = a < nw ? th(k, p, a) : (p == a - nw ? 1.0 : 0.0);
         v1 += t * Bt[(size_t)p * ldb + nE + h];
         v2 += Bt[(size_t)(nE + h) * ldb + p] * t;
       }
@@ -220,8 +220,8 @@ void edge_old_metric_batched(const std::vector<EdgeOldDesc>& descs, hipStream_t 
   if (descs.empty()) return;
   int nmax = 0;
   for (auto& d : descs) {
-    ABDDC_REQUIRE(d.nE >= 1 && d.nE <= 32 && d.m >= 2 && d.m <= 4, ABDDC_EINVAL,
-                  "earlier edge eigenproblem: edges need 2..4 members and at most 32 dofs");
+    ABDDC_REQUIRE(d.nE >= 1 && d.nE <= 32 && d.m >= 2 && d.m <= MAX_EDGE_MEMBERS, ABDDC_EINVAL,
+                  "earlier edge eigenproblem: edges need 2..8 members and at most 32 dofs");
     nmax = std::max(nmax, d.nE);
   }
   const EdgeOldDesc* dd = Arena::for_stream(s).put(descs);
@@ -234,13 +234,13 @@ void edge_assemble_batched(const std::vector<EdgeAsmDesc>& descs, hipStream_t s)
   if (descs.empty()) return;
   bool small = true;
   for (auto& d : descs) {
-    ABDDC_REQUIRE(d.nE <= 32 && (d.m - 1) * d.nE <= 64 && d.m <= 4, ABDDC_EINVAL,
-                  "edge too large: at most 32 dofs, 4 members and 64 jump unknowns");
+    ABDDC_REQUIRE(d.nE <= 32 && (d.m - 1) * d.nE <= 128 && d.m <= MAX_EDGE_MEMBERS, ABDDC_EINVAL,
+                  "edge too large: at most 32 dofs, 8 members and 128 jump unknowns");
     small = small && d.nE <= 16 && (d.m - 1) * d.nE <= 48;
   }
   const EdgeAsmDesc* dd = Arena::for_stream(s).put(descs);
   if (small) edge_assemble_kernel<16, 48><<<descs.size(), 256, 0, s>>>(dd);
-  else edge_assemble_kernel<32, 64><<<descs.size(), 256, 0, s>>>(dd);
+  else edge_assemble_kernel<32, 128><<<descs.size(), 256, 0, s>>>(dd);
   ABDDC_HIP(hipGetLastError());
 }
 

@@ -510,15 +510,15 @@ void run_setup(abddc_ctx* c) {
       nedof[sub] = (int)edofs.size();
       nW[sub] = c->nB[sub] - nfc[sub];
     }
-    std::vector<size_t> m2off((size_t)ned * 4);
-    std::vector<int64_t> e2off((size_t)ned * 4);
+    std::vector<size_t> m2off((size_t)ned * MAX_EDGE_MEMBERS);
+    std::vector<int64_t> e2off((size_t)ned * MAX_EDGE_MEMBERS);
     int64_t e2tot = 0;
     int maxm = 0;
     for (int e : elist) {
       const int k = T.edges[e];
       const Object& o = T.objects[k];
-      ABDDC_REQUIRE(o.subs.size() >= 2 && o.subs.size() <= 4 && o.n <= 16, ABDDC_EINVAL,
-                    "earlier edge eigenproblem: edges need 2..4 members and at most 16 dofs");
+      ABDDC_REQUIRE(o.subs.size() >= 2 && (int)o.subs.size() <= MAX_EDGE_MEMBERS && o.n <= 32, ABDDC_EINVAL,
+                    "earlier edge eigenproblem: edges need 2..8 members and at most 32 dofs");
       maxm = std::max(maxm, (int)o.subs.size());
       for (size_t q = 0; q < o.subs.size(); ++q) {
         const int sub = o.subs[q];
@@ -530,8 +530,8 @@ void run_setup(abddc_ctx* c) {
           if (t < ep || t >= ep + o.n) mp.push_back(t);
         for (int t = nedof[sub]; t < nW[sub]; ++t) mp.push_back(t);
         for (int t = 0; t < o.n; ++t) mp.push_back(ep + t);
-        m2off[(size_t)e * 4 + q] = pool.add(mp);
-        e2off[(size_t)e * 4 + q] = e2tot;
+        m2off[(size_t)e * MAX_EDGE_MEMBERS + q] = pool.add(mp);
+        e2off[(size_t)e * MAX_EDGE_MEMBERS + q] = e2tot;
         e2tot += (int64_t)nW[sub] * nW[sub];
       }
     }
@@ -569,8 +569,8 @@ void run_setup(abddc_ctx* c) {
         for (size_t q = 0; q < o.subs.size(); ++q) {
           const int sub = o.subs[q], nB = c->nB[sub], w = nW[sub], kk = w - o.n;
           const double* Wbase = E1.p + c->soff[sub] + (int64_t)nfc[sub] * nB + nfc[sub];
-          double* dst = E2.p + e2off[(size_t)e * 4 + q];
-          gd.push_back({Wbase, dst, pool.ptr(m2off[(size_t)e * 4 + q]), pool.ptr(m2off[(size_t)e * 4 + q]), w, w, nB,
+          double* dst = E2.p + e2off[(size_t)e * MAX_EDGE_MEMBERS + q];
+          gd.push_back({Wbase, dst, pool.ptr(m2off[(size_t)e * MAX_EDGE_MEMBERS + q]), pool.ptr(m2off[(size_t)e * MAX_EDGE_MEMBERS + q]), w, w, nB,
                         w, 1.0});
           pd.push_back({dst, w, w, w, kk});
           sy.push_back({dst + (int64_t)kk * w + kk, slot(e, (int)q), o.n, w, o.n});
@@ -712,9 +712,9 @@ void run_setup(abddc_ctx* c) {
       if (need[sub]) m1off[sub] = pool.add(m1[sub]);
     ht.mark("stage 2 maps per (edge, member): [othe");
     // stage 2 maps per (edge, member): [other edge dofs; E dofs; H] inside W
-    std::vector<size_t> m2off((size_t)ned * 4);
-    std::vector<int64_t> e2off((size_t)ned * 4);
-    std::vector<size_t> roff((size_t)ned * 4);
+    std::vector<size_t> m2off((size_t)ned * MAX_EDGE_MEMBERS);
+    std::vector<int64_t> e2off((size_t)ned * MAX_EDGE_MEMBERS);
+    std::vector<size_t> roff((size_t)ned * MAX_EDGE_MEMBERS);
     std::vector<int> nHunion(ned);
     int64_t e2tot = 0;
     const bool separate = c->opt.edge_h_mode == ABDDC_H_SEPARATE;
@@ -722,10 +722,10 @@ void run_setup(abddc_ctx* c) {
       const Object& o = T.objects[T.edges[e]];
       for (size_t q = 0; q < o.subs.size(); ++q) {
         const int sub = o.subs[q];
-        m2off[(size_t)e * 4 + q] = pool.reserve(nW[sub]);
-        e2off[(size_t)e * 4 + q] = e2tot;
+        m2off[(size_t)e * MAX_EDGE_MEMBERS + q] = pool.reserve(nW[sub]);
+        e2off[(size_t)e * MAX_EDGE_MEMBERS + q] = e2tot;
         e2tot += (int64_t)nW[sub] * nW[sub];
-        roff[(size_t)e * 4 + q] = pool.reserve(Hpid[sub].size());
+        roff[(size_t)e * MAX_EDGE_MEMBERS + q] = pool.reserve(Hpid[sub].size());
       }
     }
     host_parallel_for((int64_t)elist.size(), 16, [&](int64_t eb, int64_t ee) {
@@ -744,13 +744,13 @@ void run_setup(abddc_ctx* c) {
           const SubInfo& si = T.sub[sub];
           const int qi = (int)(std::lower_bound(si.objs.begin(), si.objs.end(), k) - si.objs.begin());
           const int epos = edge_pos_in_W[sub][qi];
-          int32_t* mp = pool.h.data() + m2off[(size_t)e * 4 + q];
+          int32_t* mp = pool.h.data() + m2off[(size_t)e * MAX_EDGE_MEMBERS + q];
           int t2 = 0;
           for (int t = 0; t < nedof[sub]; ++t)
             if (t < epos || t >= epos + o.n) mp[t2++] = t;
           for (int t = 0; t < o.n; ++t) mp[t2++] = epos + t;
           for (int t = nedof[sub]; t < nW[sub]; ++t) mp[t2++] = t;
-          int32_t* R = pool.h.data() + roff[(size_t)e * 4 + q];
+          int32_t* R = pool.h.data() + roff[(size_t)e * MAX_EDGE_MEMBERS + q];
           for (size_t h = 0; h < Hpid[sub].size(); ++h)
             R[h] = separate ? hbase + (int)h
                             : (int)(std::lower_bound(uni.begin(), uni.end(), Hpid[sub][h]) - uni.begin());
@@ -783,9 +783,9 @@ void run_setup(abddc_ctx* c) {
         for (size_t q = 0; q < o.subs.size(); ++q) {
           const int sub = o.subs[q], nB = c->nB[sub], w = nW[sub];
           const double* Wbase = E1.p + c->soff[sub] + (int64_t)nfd[sub] * nB + nfd[sub];
-          gd.push_back({Wbase, E2.p + e2off[(size_t)e * 4 + q], pool.ptr(m2off[(size_t)e * 4 + q]),
-                        pool.ptr(m2off[(size_t)e * 4 + q]), w, w, nB, w, 1.0});
-          pd.push_back({E2.p + e2off[(size_t)e * 4 + q], w, w, w, nedof[sub] - o.n});
+          gd.push_back({Wbase, E2.p + e2off[(size_t)e * MAX_EDGE_MEMBERS + q], pool.ptr(m2off[(size_t)e * MAX_EDGE_MEMBERS + q]),
+                        pool.ptr(m2off[(size_t)e * MAX_EDGE_MEMBERS + q]), w, w, nB, w, 1.0});
+          pd.push_back({E2.p + e2off[(size_t)e * MAX_EDGE_MEMBERS + q], w, w, w, nedof[sub] - o.n});
         }
       }
       gather_batched(gd, s);
@@ -823,10 +823,10 @@ void run_setup(abddc_ctx* c) {
         d.BE[q] = Sblk(c->dB.p, sub, k);
         d.ldBE[q] = c->nB[sub];
         const int kk = w - (nedof[sub] - o.n);  // trailing order n_E + n_H,s
-        d.Bt[q] = E2.p + e2off[(size_t)e * 4 + q] + (int64_t)(w - kk) * w + (w - kk);
+        d.Bt[q] = E2.p + e2off[(size_t)e * MAX_EDGE_MEMBERS + q] + (int64_t)(w - kk) * w + (w - kk);
         d.ldBt[q] = w;
         d.nHk[q] = (int)Hpid[sub].size();
-        d.R[q] = pool.ptr(roff[(size_t)e * 4 + q]);
+        d.R[q] = pool.ptr(roff[(size_t)e * MAX_EDGE_MEMBERS + q]);
       }
       d.ME = ME.p + meoff[e];
       d.Q = Qb.p + qoff[e];
@@ -874,13 +874,13 @@ void run_setup(abddc_ctx* c) {
     std::vector<int32_t> iota(64);
     for (int q = 0; q < 64; ++q) iota[q] = q;
     const size_t iota_off = gp.add(iota);
-    std::vector<size_t> rowmap_off((size_t)ned * 4);
+    std::vector<size_t> rowmap_off((size_t)ned * MAX_EDGE_MEMBERS);
     for (int e : elist) {
       const Object& o = T.objects[T.edges[e]];
       for (int b = 0; b < (int)o.subs.size() - 1; ++b) {
         std::vector<int32_t> rm(o.n);
         for (int i = 0; i < o.n; ++i) rm[i] = b * o.n + i;
-        rowmap_off[(size_t)e * 4 + b] = gp.add(rm);
+        rowmap_off[(size_t)e * MAX_EDGE_MEMBERS + b] = gp.add(rm);
       }
     }
     gp.upload(s);
@@ -890,7 +890,7 @@ void run_setup(abddc_ctx* c) {
       const Object& o = T.objects[T.edges[e]];
       const int m1 = (int)o.subs.size() - 1, nw = m1 * o.n, ns = c->nselE[e];
       for (int b = 0; b < m1 && ns > 0; ++b)
-        gd.push_back({XE.p + meoff[e], G.p + goffE[e] + (int64_t)b * ns, gp.ptr(rowmap_off[(size_t)e * 4 + b]),
+        gd.push_back({XE.p + meoff[e], G.p + goffE[e] + (int64_t)b * ns, gp.ptr(rowmap_off[(size_t)e * MAX_EDGE_MEMBERS + b]),
                       gp.ptr(iota_off), o.n, ns, nw, m1 * ns, 1.0});
       sv.push_back({G.p + goffE[e], c->dTE.p + c->teoff[e], ranks.p + e, o.n, m1 * ns, std::max(m1 * ns, 1)});
     }

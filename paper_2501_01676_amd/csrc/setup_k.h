@@ -8,6 +8,9 @@
 
 namespace abddc {
 
+// Largest number of subdomains sharing one edge that the edge stages take.
+constexpr int MAX_EDGE_MEMBERS = 8;
+
 struct DeluxeDesc {
   const double* src[8];
   int32_t lds[8];
@@ -16,23 +19,23 @@ struct DeluxeDesc {
 };
 
 struct EdgeAsmDesc {
-  const double* D[4];    // deluxe blocks n_E x n_E (member order)
-  const double* BE[4];   // B_E^(k) (original basis), ld ldBE
-  const double* Bt[4];   // Btilde^(k) over [E; H_k], ld ldBt
-  const int32_t* R[4];   // positions of H_k in the union
-  int32_t ldBE[4], ldBt[4], nHk[4];
+  const double* D[MAX_EDGE_MEMBERS];    // deluxe blocks n_E x n_E (member order)
+  const double* BE[MAX_EDGE_MEMBERS];   // B_E^(k) (original basis), ld ldBE
+  const double* Bt[MAX_EDGE_MEMBERS];   // Btilde^(k) over [E; H_k], ld ldBt
+  const int32_t* R[MAX_EDGE_MEMBERS];   // positions of H_k in the union
+  int32_t ldBE[MAX_EDGE_MEMBERS], ldBt[MAX_EDGE_MEMBERS], nHk[MAX_EDGE_MEMBERS];
   double* ME;            // (m-1) n_E square
   double* Q;             // nv square, nv = m n_E + n_H
   int32_t nE, m, nH, nv;
 };
 
-// The metric of the earlier edge eigenproblem for one edge of m <= 4 members
-// and n_E <= 16 dofs: out = sym(B_E), B_E = sum_i sum_{k != i}
+// The metric of the earlier edge eigenproblem for one edge of
+// m <= MAX_EDGE_MEMBERS members and n_E <= 32 dofs: out = sym(B_E), B_E = sum_i sum_{k != i}
 // D^(k)^T B_E^(i) D^(k) (eq. equ-4-8-E), out n_E x n_E with ld n_E.
 struct EdgeOldDesc {
-  const double* D[4];    // deluxe blocks n_E x n_E (member order)
-  const double* BE[4];   // B_E^(i), ld ldBE
-  int32_t ldBE[4];
+  const double* D[MAX_EDGE_MEMBERS];    // deluxe blocks n_E x n_E (member order)
+  const double* BE[MAX_EDGE_MEMBERS];   // B_E^(i), ld ldBE
+  int32_t ldBE[MAX_EDGE_MEMBERS];
   double* out;
   int32_t nE, m;
 };

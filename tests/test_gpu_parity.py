@@ -76,6 +76,10 @@ CASES = {
     "irregular_27_old": (lambda: W.example_irregular(27, 12, 1), dict(_theta_f(4), edge_variant="old"),
                          dict(_theta_f(4), edge_variant=1)),
     "irregular_12_loose": (lambda: W.example_irregular(12, 10, 5), LOOSE, LOOSE),
+    # a partition with an edge shared by five subdomains
+    "irregular_m5_loose": (lambda: W.example_irregular(12, 8, 3), LOOSE, LOOSE),
+    "irregular_m5_old": (lambda: W.example_irregular(12, 8, 3), dict(LOOSE, edge_variant="old"),
+                         dict(LOOSE, edge_variant=1)),
 }
 
 
