@@ -70,6 +70,10 @@ def parse():
                          "(untimed) on exact setups of --train-meshes other seeds of the same workload")
     ap.add_argument("--train-meshes", type=int, default=8)
     ap.add_argument("--train-epochs", type=int, default=40)
+    ap.add_argument("--local-lu-probe", action="store_true",
+                    help="instead of the benchmark: time the local Schur elimination of the workload's "
+                         "subdomains in FP64 and FP32 and the FP64 products one iterative-refinement step "
+                         "would add (the mixed-precision question for that stage)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="after the timed steps, copy a MIB-MiB device buffer 3 times (a plain copy kernel of "
                          "known size, the reference for scaling HBM traffic counters)")
@@ -192,6 +196,73 @@ def local_solve_flops(solver):
     return s2, s10
 
 
+def local_lu_probe(problem, args):
+    """Device times (CUDA events, best of 3) on the workload's batch of local
+    Schur eliminations, with diagonally dominant random matrices of the same
+    shapes (n_I + n_B rows, one load column, n_I pivots): the FP64 partial LU
+    the library runs, the same elimination in FP32, and the two FP64
+    products of an FP32-factorisation-plus-refinement scheme (the residual
+    [A_IB | f_I] - A_II X and the final A_BB - A_BI X)."""
+    import ctypes as C
+    import torch
+    from paper_2501_01676_amd import _lib as L
+    from paper_2501_01676_amd import api
+    g = api.Solver(problem)
+    sizes = [tuple(int(v) for v in g.stage(8, i)[:2]) for i in range(g.n_sub)]
+    g.close()
+    lib = L.load()
+    st = C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    nb = len(sizes)
+    nrow = [nI + nB for nI, nB in sizes]
+    ncol = [r + 1 for r in nrow]
+    off, tot = [], 0
+    for r, c in zip(nrow, ncol):
+        off.append(tot)
+        tot += r * c
+
+    def timed(fn):
+        best = None
+        for _ in range(3):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            torch.cuda.synchronize()
+            best = e0.elapsed_time(e1) if best is None else min(best, e0.elapsed_time(e1))
+        return best
+
+    out = {"batch": nb, "pivots_max": max(nI for nI, _ in sizes), "rows_max": max(nrow)}
+    for prec, dt in ((0, torch.float64), (1, torch.float32)):
+        base = torch.rand(tot, dtype=dt, device="cuda")
+        for b in range(nb):
+            view = base[off[b]:off[b] + nrow[b] * ncol[b]].view(nrow[b], ncol[b])
+            view.diagonal().add_(2.0 * nrow[b])
+        buf = torch.empty_like(base)
+
+        def lu():
+            buf.copy_(base)
+            L.check(lib.abddc_test_partial_lu(nb, C.c_void_p(buf.data_ptr()), L.i64(off), L.i32(nrow), L.i32(ncol),
+                                              L.i32(ncol), L.i32([nI for nI, _ in sizes]), prec, st))
+        copy_ms = timed(lambda: buf.copy_(base))
+        out["partial_lu_fp64_ms" if prec == 0 else "partial_lu_fp32_ms"] = timed(lu) - copy_ms
+        del base, buf
+    # the two FP64 products of one refinement step, on the library's MFMA GEMM
+    for name, dims in (("residual_product_ms", [(nI, nB + 1, nI) for nI, nB in sizes]),
+                       ("schur_product_ms", [(nB, nB + 1, nI) for nI, nB in sizes])):
+        oa, ob, oc, t = [], [], [], 0
+        for m, n, k in dims:
+            oa.append(t); t += m * k
+            ob.append(t); t += k * n
+            oc.append(t); t += m * n
+        gb = torch.rand(t, dtype=torch.float64, device="cuda")
+        ms, ns, ks = [d[0] for d in dims], [d[1] for d in dims], [d[2] for d in dims]
+        out[name] = timed(lambda: L.check(lib.abddc_test_gemm(
+            nb, C.c_void_p(gb.data_ptr()), L.i64(oa), L.i64(ob), L.i64(oc),
+            L.i32(ms), L.i32(ns), L.i32(ks), L.i32(ks), L.i32(ns), L.i32(ns), 0, 0, -1.0, 1.0, st)))
+        del gb
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -204,6 +275,9 @@ def main():
     from paper_2501_01676_amd import workloads as W
 
     problem = W.get(args.config, args.seed)
+    if args.local_lu_probe:
+        print(json.dumps({"config": args.config, "local_lu_probe": local_lu_probe(problem, args)}), flush=True)
+        return
     dev_problem = dict(problem)
     dev_problem["nu"] = torch.from_numpy(problem["nu"]).cuda()
     if problem.get("f_nodal") is not None:
