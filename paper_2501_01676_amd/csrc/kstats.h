@@ -9,9 +9,50 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <map>
+#include <mutex>
 #include <vector>
 
 namespace abddc {
+
+// Timing events kept for the process, per device: contexts come and go once
+// per solve, and creating and destroying a few hundred events each time
+// would cost milliseconds of host time.
+struct EventPool {
+  static hipEvent_t take() {
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    {
+      std::lock_guard<std::mutex> g(mu());
+      std::vector<hipEvent_t>& v = pools()[dev];
+      if (!v.empty()) {
+        hipEvent_t e = v.back();
+        v.pop_back();
+        return e;
+      }
+    }
+    hipEvent_t e = nullptr;
+    (void)hipEventCreate(&e);
+    return e;
+  }
+  // events recorded on device dev, once the work that stamps them has
+  // finished or will never run
+  static void give(int dev, hipEvent_t e) {
+    if (!e) return;
+    std::lock_guard<std::mutex> g(mu());
+    pools()[dev].push_back(e);
+  }
+
+ private:
+  static std::mutex& mu() {
+    static std::mutex m;
+    return m;
+  }
+  static std::map<int, std::vector<hipEvent_t>>& pools() {
+    static auto* p = new std::map<int, std::vector<hipEvent_t>>();   // kept until the process ends
+    return *p;
+  }
+};
 
 enum KernelClass {
   KC_PLU_UPDATE = 0,
@@ -33,20 +74,11 @@ struct KStats {
     double work;
   };
   std::vector<Pending> pending;
-  std::vector<hipEvent_t> pool;
+  int device = -1;   // device of the pending events
 
-  hipEvent_t take() {
-    if (!pool.empty()) {
-      hipEvent_t e = pool.back();
-      pool.pop_back();
-      return e;
-    }
-    hipEvent_t e;
-    (void)hipEventCreate(&e);
-    return e;
-  }
   void events(int cls, double work_amount, hipEvent_t* start, hipEvent_t* stop) {
-    Pending p{cls, take(), take(), work_amount};
+    if (device < 0) (void)hipGetDevice(&device);
+    Pending p{cls, EventPool::take(), EventPool::take(), work_amount};
     pending.push_back(p);
     *start = p.a;
     *stop = p.b;
@@ -60,17 +92,18 @@ struct KStats {
         work[p.cls] += p.work;
         launches[p.cls] += 1;
       }
-      pool.push_back(p.a);
-      pool.push_back(p.b);
+      EventPool::give(device, p.a);
+      EventPool::give(device, p.b);
     }
     pending.clear();
   }
   ~KStats() {
+    // unresolved pairs (a call that failed before its synchronisation): an
+    // event may still be stamped by queued work, so it is not reused
     for (auto& p : pending) {
       (void)hipEventDestroy(p.a);
       (void)hipEventDestroy(p.b);
     }
-    for (auto e : pool) (void)hipEventDestroy(e);
   }
 };
 

@@ -272,27 +272,33 @@ void run_setup(abddc_ctx* c) {
       wtot += (int64_t)2 * o.n * (o.subs.size() + 1) * o.n;
     }
     DevBuf<double> wk(std::max<int64_t>(wtot, 1));
-    std::vector<DeluxeDesc> dd;
-    std::vector<PluDesc<double>> pd;
-    std::vector<GatherDesc> gd;
-    for (int k = 0; k < nobj; ++k) {
-      const Object& o = T.objects[k];
-      if (o.kind == KIND_VERTEX) continue;
-      DeluxeDesc d{};
-      d.n = o.n;
-      d.m = (int)o.subs.size();
-      for (int q = 0; q < d.m; ++q) {
-        d.src[q] = Sblk(src_dx, o.subs[q], k);
-        d.lds[q] = c->nB[o.subs[q]];
+    // descriptors of the faces and edges (objects before the vertices), one
+    // slot each, filled in parallel
+    const int nfe = nf + ned;
+    std::vector<int64_t> gstart(nfe + 1, 0);
+    for (int k = 0; k < nfe; ++k) gstart[k + 1] = gstart[k] + (int64_t)T.objects[k].subs.size();
+    std::vector<DeluxeDesc> dd(nfe);
+    std::vector<PluDesc<double>> pd(nfe);
+    std::vector<GatherDesc> gd(gstart[nfe]);
+    host_parallel_for(nfe, 64, [&](int64_t kb, int64_t ke) {
+      for (int k = (int)kb; k < (int)ke; ++k) {
+        const Object& o = T.objects[k];
+        DeluxeDesc d{};
+        d.n = o.n;
+        d.m = (int)o.subs.size();
+        for (int q = 0; q < d.m; ++q) {
+          d.src[q] = Sblk(src_dx, o.subs[q], k);
+          d.lds[q] = c->nB[o.subs[q]];
+        }
+        d.dst = wk.p + woff[k];
+        dd[k] = d;
+        const int cols = (d.m + 1) * o.n;
+        pd[k] = {wk.p + woff[k], 2 * o.n, cols, cols, o.n};
+        for (int q = 0; q < d.m; ++q)
+          gd[gstart[k] + q] = {wk.p + woff[k] + (int64_t)o.n * cols + o.n + (int64_t)q * o.n,
+                               c->dD.p + c->dxoff[(size_t)k * 8 + q], nullptr, nullptr, o.n, o.n, cols, o.n, 1.0};
       }
-      d.dst = wk.p + woff[k];
-      dd.push_back(d);
-      const int cols = (d.m + 1) * o.n;
-      pd.push_back({wk.p + woff[k], 2 * o.n, cols, cols, o.n});
-      for (int q = 0; q < d.m; ++q)
-        gd.push_back({wk.p + woff[k] + (int64_t)o.n * cols + o.n + (int64_t)q * o.n, c->dD.p + c->dxoff[(size_t)k * 8 + q],
-                      nullptr, nullptr, o.n, o.n, cols, o.n, 1.0});
-    }
+    });
     deluxe_build_batched(dd, s);
     partial_lu<double>(pd, c->d_flag.p, s);
     gather_batched(gd, s);
@@ -911,32 +917,39 @@ void run_setup(abddc_ctx* c) {
   ht.mark("change of basis + local");
   // -------------------------------------------- change of basis + local
   record(c, 5);
+  // Sbar starts as a copy of S (vertex blocks stay as they are): queued
+  // first, so the device copies while the host builds the maps below
+  DevBuf<double> Y(c->dS.n);
+  ABDDC_HIP(hipMemcpyAsync(Y.p, c->dS.p, c->dS.n * sizeof(double), hipMemcpyDeviceToDevice, s));
   // local coordinate order per object: [primal, dual]; Pi / Delta positions
   std::vector<std::vector<int32_t>> Pi(nsub), Dl(nsub), Pid(nsub);
-  for (int sub = 0; sub < nsub; ++sub) {
-    const SubInfo& si = T.sub[sub];
-    for (size_t q = 0; q < si.objs.size(); ++q) {
-      const int k = si.objs[q];
-      const Object& o = T.objects[k];
-      const int off = si.obj_off[q];
-      int p = 0, base = 0;
-      if (o.kind == KIND_VERTEX) {
-        p = 1;
-        base = T.kind_index[k];
-      } else if (o.kind == KIND_FACE) {
-        p = c->pF[T.kind_index[k]];
-        base = face_pbase[T.kind_index[k]];
-      } else {
-        p = c->rE[T.kind_index[k]];
-        base = edge_pbase[T.kind_index[k]];
+  host_parallel_for(nsub, 8, [&](int64_t sb, int64_t se) {
+    for (int sub = (int)sb; sub < (int)se; ++sub) {
+      const SubInfo& si = T.sub[sub];
+      Dl[sub].reserve(si.nB);
+      for (size_t q = 0; q < si.objs.size(); ++q) {
+        const int k = si.objs[q];
+        const Object& o = T.objects[k];
+        const int off = si.obj_off[q];
+        int p = 0, base = 0;
+        if (o.kind == KIND_VERTEX) {
+          p = 1;
+          base = T.kind_index[k];
+        } else if (o.kind == KIND_FACE) {
+          p = c->pF[T.kind_index[k]];
+          base = face_pbase[T.kind_index[k]];
+        } else {
+          p = c->rE[T.kind_index[k]];
+          base = edge_pbase[T.kind_index[k]];
+        }
+        for (int l = 0; l < p; ++l) {
+          Pi[sub].push_back(off + l);
+          Pid[sub].push_back(base + l);
+        }
+        for (int l = p; l < o.n; ++l) Dl[sub].push_back(off + l);
       }
-      for (int l = 0; l < p; ++l) {
-        Pi[sub].push_back(off + l);
-        Pid[sub].push_back(base + l);
-      }
-      for (int l = p; l < o.n; ++l) Dl[sub].push_back(off + l);
     }
-  }
+  });
   c->nPi.assign(nsub, 0);
   c->moff.assign(nsub, 0);
   c->uoff.assign(nsub, 0);
@@ -963,14 +976,13 @@ void run_setup(abddc_ctx* c) {
       wt += (int64_t)T.objects[k].n * T.objects[k].n;
     }
   }
-  DevBuf<double> Sb(c->dS.n), Y(c->dS.n), Aug(std::max<int64_t>(at, 1)), WX(std::max<int64_t>(wt, 1));
+  DevBuf<double> Sb(c->dS.n), Aug(std::max<int64_t>(at, 1)), WX(std::max<int64_t>(wt, 1));
   DevBuf<double> Kt(c->dS.n), Y2(c->dS.n), Vt(std::max<int64_t>(ut, 1)), Ut(std::max<int64_t>(ut, 1));
   c->dM.alloc(std::max<int64_t>(mt, 1));
   c->dU.alloc(std::max<int64_t>(ut, 1));
   {
     ht.mark("Sbar = T^T S T (face and edge blocks)");
-    // Sbar = T^T S T (face and edge blocks)
-    ABDDC_HIP(hipMemcpyAsync(Y.p, c->dS.p, c->dS.n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    // Sbar = T^T S T (face and edge blocks), on the copy of S queued above
     std::vector<GemmDesc<double>> gc, gr, wg;
     std::vector<SetDesc> vset;
     IntPool vp;
