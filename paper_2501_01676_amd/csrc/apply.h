@@ -10,9 +10,11 @@
 
 namespace abddc {
 
-// GEMV variants: rows per wave (a workgroup is 4 waves)
-constexpr int GEMV_NVAR = 3;
-constexpr int GEMV_ROWS[GEMV_NVAR] = {2, 4, 8};
+// GEMV variants: rows per wave (a workgroup is 4 waves); the last one, for
+// operators of at most 64 columns, gives every lane a row of its own
+constexpr int GEMV_NVAR = 4;
+constexpr int GEMV_ROWS[GEMV_NVAR] = {2, 4, 8, 64};
+constexpr int GEMV_NARROW = 3;
 constexpr int DOT_BLOCKS = 256;
 constexpr int DOT_STRIDE = 64;   // partial-sum stride (>= restart + 1 vectors)
 constexpr int GMRES_MAXR = 63;   // maximum restart length
@@ -45,7 +47,7 @@ struct GmresState {
 struct GemvOp {
   DevBuf<GemvMat> mats;
   DevBuf<GemvBlock> blocks[GEMV_NVAR];
-  int nblk[GEMV_NVAR] = {0, 0, 0};
+  int nblk[GEMV_NVAR] = {0, 0, 0, 0};
   int maxc = 1;
   int var = 1;
   double bytes = 0.0;
@@ -60,7 +62,7 @@ void gemv_build(GemvOp& op, const std::vector<GemvMat>& mats, const std::vector<
 template <class TM>
 void gemv_run(const GemvOp& op, const TM* M, const double* x, const int32_t* xidx, double* y, bool accumulate,
               hipStream_t s);
-// Picks the variant: ABDDC_GEMV_VARIANT (0..2) when set, else the cached
+// Picks the variant: ABDDC_GEMV_VARIANT (0..3) when set, else the cached
 // choice for (architecture, operator name, element type, size buckets),
 // else the fastest of timed launches on the operator's own data (x, y as in
 // gemv_run; y is overwritten), recorded in the autotuner cache.

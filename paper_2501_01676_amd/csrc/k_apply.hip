@@ -90,6 +90,40 @@ __global__ void __launch_bounds__(256) gemv_kernel(const GemvBlock* __restrict__
   }
 }
 
+// Operators of at most 64 columns (the tall and thin U): one lane per row,
+// the workgroup's 256 rows of one matrix.  A lane forms the 64 products the
+// 64 lanes of gemv_kernel would hold and adds them in the same tree as its
+// wavefront reduction, so every variant gives the same bits.
+template <class TM>
+__global__ void __launch_bounds__(256) gemv_narrow_kernel(const GemvBlock* __restrict__ blocks,
+                                                          const GemvMat* __restrict__ mats,
+                                                          const TM* __restrict__ M, const double* __restrict__ x,
+                                                          const int32_t* __restrict__ xidx, double* __restrict__ y,
+                                                          int accumulate) {
+  extern __shared__ double xs[];
+  const GemvBlock blk = blocks[blockIdx.x];
+  const GemvMat d = mats[blk.mat];
+  for (int c = threadIdx.x; c < d.ncols; c += blockDim.x)
+    xs[c] = xidx ? x[xidx[d.xoff + c]] : x[d.xoff + c];
+  __syncthreads();
+  const int r = blk.row0 + (int)threadIdx.x;
+  if (r >= d.nrows) return;
+  // loads through a buffer descriptor: a column past the last one reads zero
+  const __amdgpu_buffer_rsrc_t rs = buf_rsrc(M + d.moff);
+  const int ro = r * d.ld * (int)sizeof(TM);
+  const double xlast = d.ncols > 0 ? xs[d.ncols - 1] : 0.0;
+  double a[64];
+#pragma unroll
+  for (int l = 0; l < 64; ++l)
+    a[l] = (double)buf_load<TM>(rs, l < d.ncols ? ro : BUF_OUT, l * (int)sizeof(TM)) * (l < d.ncols ? xs[l] : xlast);
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+    for (int l = 0; l < off; ++l) a[l] += a[l + off];
+  double* yp = y + d.yoff + r;
+  *yp = accumulate ? *yp + a[0] : a[0];
+}
+
 __global__ void gather_sum_kernel(const int32_t* __restrict__ ptr, const int32_t* __restrict__ idx,
                                   const double* __restrict__ src, double* __restrict__ dst, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -311,13 +345,29 @@ void gemv_launch(const GemvOp& op, int v, const TM* M, const double* x, const in
 }
 
 template <class TM>
+void gemv_narrow_launch(const GemvOp& op, const TM* M, const double* x, const int32_t* xidx, double* y,
+                        bool accumulate, hipStream_t s) {
+  hipEvent_t ea, eb;
+  tracked_events(KC_GEMV, op.bytes, &ea, &eb);
+  const uint32_t lds = (uint32_t)(op.maxc * sizeof(double));
+  const int v = GEMV_NARROW;
+  if (ea)
+    hipExtLaunchKernelGGL(gemv_narrow_kernel<TM>, dim3(op.nblk[v]), dim3(256), lds, s, ea, eb, 0, op.blocks[v].p,
+                          op.mats.p, M, x, xidx, y, accumulate ? 1 : 0);
+  else
+    gemv_narrow_kernel<TM><<<op.nblk[v], 256, lds, s>>>(op.blocks[v].p, op.mats.p, M, x, xidx, y,
+                                                        accumulate ? 1 : 0);
+}
+
+template <class TM>
 void gemv_variant(const GemvOp& op, int v, const TM* M, const double* x, const int32_t* xidx, double* y,
                   bool accumulate, hipStream_t s) {
   if (op.nblk[v] == 0) return;
   switch (v) {
     case 0: gemv_launch<TM, 2>(op, v, M, x, xidx, y, accumulate, s); break;
     case 1: gemv_launch<TM, 4>(op, v, M, x, xidx, y, accumulate, s); break;
-    default: gemv_launch<TM, 8>(op, v, M, x, xidx, y, accumulate, s); break;
+    case 2: gemv_launch<TM, 8>(op, v, M, x, xidx, y, accumulate, s); break;
+    default: gemv_narrow_launch<TM>(op, M, x, xidx, y, accumulate, s); break;
   }
   ABDDC_HIP(hipGetLastError());
 }
@@ -335,8 +385,8 @@ void gemv_build(GemvOp& op, const std::vector<GemvMat>& mats, const std::vector<
   HostTrace ht;
   for (int v = 0; v < GEMV_NVAR; ++v) {
     std::vector<GemvBlock> b;
-    const int rpb = 4 * GEMV_ROWS[v];
-    for (size_t i = 0; i < mats.size(); ++i) {
+    const int rpb = v == GEMV_NARROW ? 256 : 4 * GEMV_ROWS[v];
+    for (size_t i = 0; i < mats.size() && (v != GEMV_NARROW || op.maxc <= 64); ++i) {
       if (active && !(*active)[i]) continue;
       for (int r = 0; r < mats[i].nrows; r += rpb) b.push_back({(int32_t)i, r});
     }
@@ -363,13 +413,13 @@ void gemv_tune(GemvOp& op, const char* name, int device, const TM* M, const doub
   if (op.nblk[0] == 0) return;
   const char* force = std::getenv("ABDDC_GEMV_VARIANT");   // fixed variant, no timing (tests, experiments)
   if (force && *force >= '0' && *force < '0' + GEMV_NVAR && force[1] == 0) {
-    op.var = *force - '0';
+    op.var = op.nblk[*force - '0'] > 0 ? *force - '0' : 1;   // the narrow form only where it applies
     return;
   }
   const std::string key = device_arch(device) + "|gemv|" + name + "|" + (sizeof(TM) == 8 ? "f64" : "f32") + "|c" +
                           std::to_string(size_bucket(op.maxc)) + "|r" + std::to_string(size_bucket(op.rows));
   const int cached = tune_lookup(key);
-  if (cached >= 0 && cached < GEMV_NVAR) {
+  if (cached >= 0 && cached < GEMV_NVAR && op.nblk[cached] > 0) {
     op.var = cached;
     return;
   }
@@ -381,6 +431,7 @@ void gemv_tune(GemvOp& op, const char* name, int device, const TM* M, const doub
   float best = 0.f;
   int bestv = 1;
   for (int v = 0; v < GEMV_NVAR; ++v) {
+    if (op.nblk[v] == 0) continue;
     gemv_variant<TM>(op, v, M, x, xidx, y, false, s);   // warm-up
     ABDDC_HIP(hipEventRecord(e0, s));
     for (int rep = 0; rep < 3; ++rep) gemv_variant<TM>(op, v, M, x, xidx, y, false, s);
