@@ -117,9 +117,12 @@ typedef struct {
  * connected through common boxes; a piece is a face when |n(x)| = 2, an edge
  * when |n(x)| >= 3 and it has two or more nodes, else a vertex.  (On box
  * partitions this is the box rule except that an edge of a single node is
- * a vertex.)  Limits of the kernels: faces and the edge eigenproblems of at
- * most 128 dofs, edges of at most 32 dofs shared by at most 8 subdomains;
- * larger objects return EINVAL. */
+ * a vertex.)  Limits of the kernels: faces of at most 512 dofs (above 128
+ * the face eigenproblems and parallel sums take a global-memory variant,
+ * and a parallel sum whose LU test fails has no pseudo-inverse fallback
+ * there: ESINGULAR), edge eigenproblems of at most 128 unknowns, edges of at
+ * most 32 dofs shared by at most 8 subdomains; larger objects return
+ * EINVAL. */
 enum { ABDDC_ELEM_Q1 = 0, ABDDC_ELEM_P1 = 1 };
 typedef struct {
   int32_t nsub[3];          /* subdomains per axis                              */

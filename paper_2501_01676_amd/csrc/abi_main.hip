@@ -350,8 +350,8 @@ extern "C" int abddc_assemble(const abddc_problem* prob, const abddc_device* dev
     if (prob->part) {
       T.build_partition(prob->part, prob->n_parts);
       for (int f : T.faces)
-        ABDDC_REQUIRE(T.objects[f].n <= 128, ABDDC_EINVAL,
-                      "partition: a face has more than 128 dofs (the eigensolvers' limit)");
+        ABDDC_REQUIRE(T.objects[f].n <= 512, ABDDC_EINVAL,
+                      "partition: a face has more than 512 dofs (the eigensolvers' limit)");
       for (int e : T.edges)
         ABDDC_REQUIRE((int)T.objects[e].subs.size() <= MAX_EDGE_MEMBERS && T.objects[e].n <= 32, ABDDC_EINVAL,
                       "partition: an edge has more than 8 subdomains or more than 32 dofs");

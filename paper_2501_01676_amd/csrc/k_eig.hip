@@ -185,12 +185,18 @@ __device__ inline int rank_of(const double (*A)[NM + 1], int n, int i) {
   return r;
 }
 
-// Per-problem global scratch for the large variant: L and Vt (NM x NM each).
+// Per-problem global scratch of the large variants: L and Vt (NM x NM
+// each), and for orders above 128 also the working matrix C (NM x (NM + 1)),
+// which no longer fits the LDS.
 template <int NM>
 struct EigScratch {
-  static __device__ inline double* L(double* base) { return base + (size_t)blockIdx.x * 2 * NM * NM; }
-  static __device__ inline double* V(double* base) { return base + (size_t)blockIdx.x * 2 * NM * NM + NM * NM; }
+  static constexpr bool HUGE = NM > 128;
+  static constexpr size_t PER = (size_t)2 * NM * NM + (HUGE ? (size_t)NM * (NM + 1) : 0);
+  static __device__ inline double* L(double* base) { return base + (size_t)blockIdx.x * PER; }
+  static __device__ inline double* V(double* base) { return base + (size_t)blockIdx.x * PER + NM * NM; }
+  static __device__ inline double* C(double* base) { return base + (size_t)blockIdx.x * PER + 2 * NM * NM; }
 };
+constexpr int EIG_HUGE = 512;   // largest order of the global-memory variants
 
 __device__ inline double read_lane_d(double v, int lane) {
   const long long x = __double_as_longlong(v);
@@ -201,7 +207,7 @@ __device__ inline double read_lane_d(double v, int lane) {
 
 // In-place Cholesky B = L L^T of the lower triangle of L (n <= NM, leading
 // dimension ldl), in 16-column panels: wave 0 factors the panel in
-// registers (lane = row, two rows per lane for NM = 128; pivot and column
+// registers (lane = row, NM / 64 rows per lane; pivot and column
 // values broadcast by readlane, no barriers), then all threads update the
 // trailing lower triangle.  Bit 2 of dflag on a non-positive pivot.
 template <int NM>
@@ -222,7 +228,11 @@ __device__ __forceinline__ void cholesky_panels(double* L, int ldl, int n, int* 
       for (int jj = 0; jj < 16; ++jj) {
         if (jj < jw) {
           const int pr = j0 + jj;
-          const double pv = (RPL > 1 && pr >= 64) ? read_lane_d(P[RPL - 1][jj], pr & 63) : read_lane_d(P[0][jj], pr & 63);
+          // row pr sits in slot pr / 64 of lane pr % 64 (a uniform choice)
+          double pv = 0.0;
+#pragma unroll
+          for (int sl = 0; sl < RPL; ++sl)
+            if (sl == (pr >> 6)) pv = read_lane_d(P[sl][jj], pr & 63);
           if (lane == 0 && (!(pv > 0.0) || !isfinite(pv))) atomicOr(dflag, 2);
           const double lpp = sqrt(fmax(pv, 1e-300));
           const double inv = 1.0 / lpp;
@@ -236,8 +246,10 @@ __device__ __forceinline__ void cholesky_panels(double* L, int ldl, int n, int* 
           for (int j2 = jj + 1; j2 < 16; ++j2) {
             if (j2 < jw) {
               const int cr = j0 + j2;
-              const double lc = (RPL > 1 && cr >= 64) ? read_lane_d(P[RPL - 1][jj], cr & 63)
-                                                      : read_lane_d(P[0][jj], cr & 63);
+              double lc = 0.0;
+#pragma unroll
+              for (int sl = 0; sl < RPL; ++sl)
+                if (sl == (cr >> 6)) lc = read_lane_d(P[sl][jj], cr & 63);
 #pragma unroll
               for (int sl = 0; sl < RPL; ++sl) {
                 const int r = lane + 64 * sl;
@@ -913,7 +925,10 @@ template <int NM, int NT>
 __global__ void __launch_bounds__(NT) sygv_sel_kernel(const SygvDesc* __restrict__ descs, double sel, int* dflag,
                                                       double* __restrict__ scratch) {
   constexpr bool SMALL = NM <= 64;
-  __shared__ double Cm[NM][NM + 1];
+  constexpr bool HUGE = NM > 128;
+  __shared__ double CmL[HUGE ? 1 : NM][HUGE ? 1 : NM + 1];
+  double(*Cm)[NM + 1] = HUGE ? reinterpret_cast<double(*)[NM + 1]>(EigScratch<NM>::C(scratch))
+                             : reinterpret_cast<double(*)[NM + 1]>(&CmL[0][0]);
   __shared__ double LZsm[SMALL ? NM : 1][SMALL ? NM + 1 : 1];
   TRI_SHARED(NM, NT)
   const SygvDesc d = descs[blockIdx.x];
@@ -1387,19 +1402,22 @@ int eig_threads(const char* name, int nmax, size_t batch, Launch launch, hipStre
   return EIG_VARIANTS[best];
 }
 
-// Split a descriptor list by order: n <= 64 (LDS variant) and 64 < n <= 128.
+// Split a descriptor list by order: n <= 64 (LDS variant), 64 < n <= 128,
+// and, where a caller takes them (huge != nullptr), 128 < n <= EIG_HUGE.
 template <class D, class F>
 void split_launch(const std::vector<D>& descs, F order, hipStream_t s, const char* what,
-                  std::vector<D>& small, std::vector<D>& big) {
+                  std::vector<D>& small, std::vector<D>& big, std::vector<D>* huge = nullptr) {
+  const int limit = huge ? EIG_HUGE : 128;
   for (auto& d : descs) {
     const int n = order(d);
-    ABDDC_REQUIRE(n <= 128, ABDDC_EINVAL, std::string(what) + ": matrix order exceeds 128");
-    (n <= 64 ? small : big).push_back(d);
+    ABDDC_REQUIRE(n <= limit, ABDDC_EINVAL, std::string(what) + ": matrix order exceeds " + std::to_string(limit));
+    (n <= 64 ? small : (n <= 128 ? big : *huge)).push_back(d);
   }
   // largest problems first (ragged batches): they are dispatched first
   auto by_size = [&](const D& a, const D& b) { return order(a) > order(b); };
   std::stable_sort(small.begin(), small.end(), by_size);
   std::stable_sort(big.begin(), big.end(), by_size);
+  if (huge) std::stable_sort(huge->begin(), huge->end(), by_size);
   (void)s;
 }
 }  // namespace
@@ -1462,7 +1480,7 @@ void parallel_sum_batched(const std::vector<PsumDesc>& descs, double rtol, hipSt
   std::vector<int64_t> off(nb);
   int64_t tot = 0;
   for (int b = 0; b < nb; ++b) {
-    ABDDC_REQUIRE(descs[b].n >= 1 && descs[b].n <= 128, ABDDC_EINVAL, "parallel sum: order outside [1, 128]");
+    ABDDC_REQUIRE(descs[b].n >= 1 && descs[b].n <= EIG_HUGE, ABDDC_EINVAL, "parallel sum: order outside [1, 512]");
     off[b] = tot;
     tot += (int64_t)4 * descs[b].n * descs[b].n;
   }
@@ -1480,8 +1498,13 @@ void parallel_sum_batched(const std::vector<PsumDesc>& descs, double rtol, hipSt
 }
 
 void sygv_select_batched(const std::vector<SygvDesc>& descs, double sel, int* dflag, hipStream_t s) {
-  std::vector<SygvDesc> sm, bg;
-  split_launch(descs, [](const SygvDesc& d) { return d.n; }, s, "sygv", sm, bg);
+  std::vector<SygvDesc> sm, bg, hg;
+  split_launch(descs, [](const SygvDesc& d) { return d.n; }, s, "sygv", sm, bg, &hg);
+  if (!hg.empty()) {
+    DevBuf<double> scr(hg.size() * EigScratch<EIG_HUGE>::PER);
+    const SygvDesc* dd = Arena::for_stream(s).put(hg);
+    sygv_sel_kernel<EIG_HUGE, 512><<<hg.size(), 512, 0, s>>>(dd, sel, dflag, scr.p);
+  }
   if (!sm.empty()) {
     const SygvDesc* dd = Arena::for_stream(s).put(sm);
     sygv_sel_kernel<64, 512><<<sm.size(), 512, 0, s>>>(dd, sel, dflag, nullptr);
@@ -1495,8 +1518,13 @@ void sygv_select_batched(const std::vector<SygvDesc>& descs, double sel, int* df
 }
 
 void qr_complete_batched(const std::vector<QrDesc>& descs, hipStream_t s) {
-  std::vector<QrDesc> sm, bg;
-  split_launch(descs, [](const QrDesc& d) { return d.n; }, s, "qr", sm, bg);
+  std::vector<QrDesc> sm, bg, hg;
+  split_launch(descs, [](const QrDesc& d) { return d.n; }, s, "qr", sm, bg, &hg);
+  if (!hg.empty()) {
+    DevBuf<double> scr(hg.size() * (size_t)EIG_HUGE * EIG_HUGE);
+    const QrDesc* dd = Arena::for_stream(s).put(hg);
+    qr_complete_kernel<EIG_HUGE><<<hg.size(), 256, 0, s>>>(dd, scr.p);
+  }
   if (!sm.empty()) {
     const QrDesc* dd = Arena::for_stream(s).put(sm);
     qr_complete_kernel<64><<<sm.size(), 256, 0, s>>>(dd, nullptr);

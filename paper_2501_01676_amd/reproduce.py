@@ -9,13 +9,13 @@ ABDDC-NEW), Theta_F = 1 + log m, Theta_E = 10, GMRES(30) to a relative
 residual of 1e-8 (at most 300 steps).  Prints per row and method
 "iterations(pnumF, pnumE)" as the tables do, plus the wall time of assemble,
 setup and solve.  The random-viscosity table draws nu per tetrahedron with
-seed 0.  Rows whose faces exceed the eigensolvers' 128 dofs (m > 12) are
-skipped with a note.
+seed 0.  Rows whose faces exceed the eigensolvers' 512 dofs are skipped
+with a note.
 
 The irregular-partition table (``cube``) splits an n^3 box grid (1/h = n)
 into N region-grown subdomains (seeds 0, 1, 2), nu = 10^r per tetrahedron,
 Theta_F = 1 + log(n / N^(1/3)); partitions with objects beyond the kernels'
-limits (faces of more than 128 dofs) are reported as not run.
+limits (faces of more than 512 dofs) are reported as not run.
 """
 from __future__ import annotations
 
@@ -34,7 +34,7 @@ TABLE4_ROWS = [(1e-1, 1e-5), (1e-1, 1e-6), (1e-1, 1e-7), (1e3, 1e-3), (1.0, 1e-7
 TABLE5_MS = [4, 8, 16]
 RANDOM_ROWS = [(n, m) for n in (2, 3, 4) for m in (4, 8, 12)]
 CUBE_ROWS = [(N, n) for N in (8, 27, 64) for n in (20, 40)]
-MAX_FACE_DOFS = 128
+MAX_FACE_DOFS = 512
 
 
 def run(problem, m, variant):

@@ -71,6 +71,8 @@ CASES = {
                           dict(_theta_f(4), edge_variant=1)),
     "p1_random_n3": (lambda: W.example_random(3, 3, 0), _theta_f(3), _theta_f(3)),
     "p1_affine_lifted": (_p1_affine_lifted, LOOSE, LOOSE),
+    # faces of 144 dofs: the global-memory eigen, parallel-sum and QR variants
+    "p1_example_t2_m13": (lambda: W.example_helicoid(2, 1.0, 1e-7, 13), _theta_f(13), _theta_f(13)),
     # Section 4's irregular partitions (region-grown unions of boxes)
     "irregular_8": (lambda: W.example_irregular(8, 8, 0), _theta_f(4), _theta_f(4)),
     "irregular_27_old": (lambda: W.example_irregular(27, 12, 1), dict(_theta_f(4), edge_variant="old"),

@@ -212,6 +212,28 @@ def test_sygv_matches_eigen_equation():
         assert np.abs(A @ V - B @ V * w).max() <= 1e-9 * np.abs(A).max()
 
 
+def test_parallel_sum_large_orders():
+    """Orders above 128 (the global-memory variants): sym(A (A + B)^+ B) with
+    A + B well conditioned, against the eigenvalue pseudo-inverse."""
+    api = _api()
+    rng = np.random.default_rng(8)
+    rtol = 1e-10
+    As, Bs, refs = [], [], []
+    for n in (129, 200, 384):
+        Q = np.linalg.qr(rng.standard_normal((n, n)))[0]
+        S = (Q * rng.uniform(0.1, 1.0, n)) @ Q.T
+        F = rng.standard_normal((n, n)) * 0.01
+        t = rng.uniform(0.3, 0.7)
+        A = t * S + (F + F.T)
+        B = (1 - t) * S - (F + F.T)
+        As.append(A); Bs.append(B)
+        R = A @ _pinv_ref(A + B, rtol) @ B
+        refs.append(0.5 * (R + R.T))
+    out = api.parallel_sum(As, Bs, rtol)
+    for o, r in zip(out, refs):
+        assert np.abs(o - r).max() <= 1e-11 * max(1.0, np.abs(r).max()), np.abs(o - r).max()
+
+
 def test_sygv_select_eigenvalues_and_selected_vectors():
     """Tridiagonalisation + bisection + inverse iteration: every eigenvalue,
     and B-orthonormal eigenvectors (X = B V) for mu <= sel, including
@@ -220,7 +242,7 @@ def test_sygv_select_eigenvalues_and_selected_vectors():
     rng = np.random.default_rng(4)
     sel = 0.1
     As, Bs, mus = [], [], []
-    for n in (1, 2, 3, 7, 21, 49, 64, 65, 100, 121, 128):
+    for n in (1, 2, 3, 7, 21, 49, 64, 65, 100, 121, 128, 129, 225, 512):
         mu = rng.uniform(0.0, 1.0, n)
         if n >= 7:
             mu[:3] = 0.0                       # null space of A
