@@ -34,32 +34,81 @@ constexpr int LDS_PAD = TILE + 1;
 // hardware hands workgroup w to XCD w % 8, and each XCD has its own L2, so
 // with the plain numbering neighbouring tiles of one matrix -- which read the
 // same row strip of A and column strip of B -- land on different XCDs and
-// every tile fetches its operands from HBM.  xcd_tile() instead gives each
-// XCD whole matrices (matrix z on XCD z % 8, its tiles in row-major order)
-// when the batch has at least 8 of them, and otherwise a contiguous eighth
-// of the (matrix, tile) range, so the operand strips are read from HBM about
-// once per XCD.
+// every tile fetches its operands from HBM.  Matrix z instead goes to XCD
+// z % 8 with its tiles in order (for batches of at least 8 matrices;
+// otherwise each XCD takes a contiguous eighth of the (matrix, tile) range),
+// so the operand strips are read from HBM about once per XCD.  The grid is
+// ragged: every matrix gets exactly its own tiles (a host-built schedule of
+// per-XCD prefix sums of the tile counts), so a batch of uneven problems
+// launches no workgroup that only exits.
 constexpr int N_XCD = 8;
 
-__device__ inline bool xcd_tile(int tiles_per, int nb, int& z, int& r) {
-  const int w = blockIdx.x, x = w % N_XCD, local = w / N_XCD;
+// sched: for nb >= 8, N_XCD rows of J + 1 prefix sums (J = ceil(nb / 8)),
+// row x over the matrices x, x + 8, ...; for nb < 8, nb + 1 prefix sums.
+// Sets the matrix z and its tile u of this workgroup.
+__device__ inline bool ragged_tile(const int32_t* __restrict__ sched, int nb, int& z, int& u) {
+  const int w = blockIdx.x;
   if (nb >= N_XCD) {
-    z = x + N_XCD * (local / tiles_per);
-    r = local % tiles_per;
-  } else {
-    const int t = x * (int)(gridDim.x / N_XCD) + local;
-    z = t / tiles_per;
-    r = t % tiles_per;
+    const int x = w % N_XCD, local = w / N_XCD, J = (nb + N_XCD - 1) / N_XCD;
+    const int nj = (nb - x + N_XCD - 1) / N_XCD;   // matrices on this XCD
+    const int32_t* P = sched + x * (J + 1);
+    if (nj <= 0 || local >= P[nj]) return false;
+    int lo = 0, hi = nj - 1;   // the last matrix that starts at or before local
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (P[mid] <= local) lo = mid;
+      else hi = mid - 1;
+    }
+    z = x + N_XCD * lo;
+    u = local - P[lo];
+    return true;
   }
-  return z < nb;
+  const int t = (w % N_XCD) * (int)(gridDim.x / N_XCD) + w / N_XCD;
+  if (t >= sched[nb]) return false;
+  int lo = 0, hi = nb - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (sched[mid] <= t) lo = mid;
+    else hi = mid - 1;
+  }
+  z = lo;
+  u = t - sched[lo];
+  return true;
 }
 
-// grid size for xcd_tile: a multiple of 8 covering every (matrix, tile)
-inline unsigned xcd_grid(int tiles_per, int nb) {
-  const int64_t g = nb >= N_XCD ? (int64_t)N_XCD * ((nb + N_XCD - 1) / N_XCD) * tiles_per
-                                : ((int64_t)nb * tiles_per + N_XCD - 1) / N_XCD * N_XCD;
+// The schedule and grid of a ragged launch with count[z] tiles of matrix z
+// (grid 0: nothing to launch).
+struct RaggedGrid {
+  const int32_t* sched = nullptr;
+  unsigned grid = 0;
+};
+inline RaggedGrid ragged_grid(const std::vector<int>& count, Arena& ar) {
+  const int nb = (int)count.size();
+  std::vector<int32_t> sched;
+  int64_t g = 0;
+  if (nb >= N_XCD) {
+    const int J = (nb + N_XCD - 1) / N_XCD;
+    sched.assign((size_t)N_XCD * (J + 1), 0);
+    int64_t mx = 0;
+    for (int x = 0; x < N_XCD; ++x) {
+      int32_t* P = sched.data() + (size_t)x * (J + 1);
+      int j = 0;
+      for (int z = x; z < nb; z += N_XCD, ++j) P[j + 1] = P[j] + count[z];
+      for (int q = j + 1; q <= J; ++q) P[q] = P[j];
+      mx = std::max<int64_t>(mx, P[j]);
+    }
+    g = (int64_t)N_XCD * mx;
+  } else {
+    sched.assign(nb + 1, 0);
+    for (int z = 0; z < nb; ++z) sched[z + 1] = sched[z] + count[z];
+    g = ((int64_t)sched[nb] + N_XCD - 1) / N_XCD * N_XCD;
+  }
   ABDDC_REQUIRE(g < (int64_t(1) << 24), ABDDC_EINVAL, "batched dense launch: too many tiles");
-  return (unsigned)g;
+  RaggedGrid r;
+  if (g == 0) return r;
+  r.sched = ar.put(sched);
+  r.grid = (unsigned)g;
+  return r;
 }
 
 typedef double v4d __attribute__((ext_vector_type(4)));
@@ -254,11 +303,11 @@ __device__ __forceinline__ void tile_gemm(const T* __restrict__ A, int lda, cons
 
 template <class T, bool TA, bool TB>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) gemm_batched_kernel(const GemmDesc<T>* __restrict__ descs,
-                                                            int tiles_per, int nb, T alpha, T beta) {
+                                                            const int32_t* __restrict__ sched, int nb, T alpha, T beta) {
   __shared__ T As[KC][LDS_PAD];
   __shared__ T Bs[KC][LDS_PAD];
   int z, t;
-  if (!xcd_tile(tiles_per, nb, z, t)) return;
+  if (!ragged_tile(sched, nb, z, t)) return;
   const GemmDesc<T> d = descs[z];
   const int tn = (d.n + TILE - 1) / TILE;
   const int tm = (d.m + TILE - 1) / TILE;
@@ -625,11 +674,11 @@ __global__ void __launch_bounds__(256) plu_diag_kernel(const PluDesc<T>* __restr
 // Step 2: A21 <- A21 U11^{-1} (row tiles), A12 <- L11^{-1} A12 (column tiles).
 template <class T>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) plu_trsm_kernel(const PluDesc<T>* __restrict__ descs, int t0,
-                                                        const T* __restrict__ scratch, int tiles_per, int nb) {
+                                                        const T* __restrict__ scratch, const int32_t* __restrict__ sched, int nb) {
   __shared__ T As[KC][LDS_PAD];
   __shared__ T Bs[KC][LDS_PAD];
   int z, t;
-  if (!xcd_tile(tiles_per, nb, z, t)) return;
+  if (!ragged_tile(sched, nb, z, t)) return;
   const PluDesc<T> d = descs[z];
   if (t0 >= d.k) return;
   const int b = min(NB, d.k - t0);
@@ -666,11 +715,11 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) p
 // are tiles of the row strip.
 template <class T>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) plu_band_kernel(const PluDesc<T>* __restrict__ descs, int g0,
-                                                                                                       int t0, int tiles_per, int nb) {
+                                                                                                       int t0, const int32_t* __restrict__ sched, int nb) {
   __shared__ T As[KC][LDS_PAD];
   __shared__ T Bs[KC][LDS_PAD];
   int z, t;
-  if (!xcd_tile(tiles_per, nb, z, t)) return;
+  if (!ragged_tile(sched, nb, z, t)) return;
   const PluDesc<T> d = descs[z];
   if (t0 >= d.k) return;
   const int s0 = t0 + min(NB, d.k - t0), b = s0 - g0;   // pivots [g0, s0) of the group so far
@@ -698,17 +747,18 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) p
 // is formed once at the end by plu_update_kernel.
 template <class T>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) plu_lead_kernel(const PluDesc<T>* __restrict__ descs, int t0,
-                                                                                                      int kb, int rt, int ct, int nb) {
+                                                                                                      int kb, const int32_t* __restrict__ sched, int nb) {
   __shared__ T As[KC][LDS_PAD];
   __shared__ T Bs[KC][LDS_PAD];
   int z, t;
-  if (!xcd_tile(rt * ct, nb, z, t)) return;
+  if (!ragged_tile(sched, nb, z, t)) return;
   const PluDesc<T> d = descs[z];
   if (t0 >= d.k) return;
   const int b = min(kb, d.k - t0), s0 = t0 + b;
   if (s0 >= d.k) return;
-  const int row0 = (t / ct) * TILE, col0 = (t % ct) * TILE;  // relative to s0
   const int mr = d.nrow - s0, nc = d.ncol - s0, kr = d.k - s0;
+  const int ct = (nc + TILE - 1) / TILE;
+  const int row0 = (t / ct) * TILE, col0 = (t % ct) * TILE;  // relative to s0
   if (row0 >= mr || col0 >= nc) return;
   if (row0 >= kr && col0 >= kr) return;   // tile entirely in the trailing block
   const T* A21 = d.a + (size_t)s0 * d.ld + t0;
@@ -722,15 +772,16 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) p
 
 // Trailing Schur complement A22 -= A21 A12 with K = k (one pass).
 template <class T>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) plu_update_kernel(const PluDesc<T>* __restrict__ descs, int rt, int ct, int nb) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) plu_update_kernel(const PluDesc<T>* __restrict__ descs, const int32_t* __restrict__ sched, int nb) {
   __shared__ T As[KC][LDS_PAD];
   __shared__ T Bs[KC][LDS_PAD];
   int z, t;
-  if (!xcd_tile(rt * ct, nb, z, t)) return;
+  if (!ragged_tile(sched, nb, z, t)) return;
   const PluDesc<T> d = descs[z];
   const int k = d.k;
   if (k == 0) return;
   const int mr = d.nrow - k, nc = d.ncol - k;
+  const int ct = (nc + TILE - 1) / TILE;
   const int row0 = (t / ct) * TILE, col0 = (t % ct) * TILE;
   if (row0 >= mr || col0 >= nc) return;
   const T* A21 = d.a + (size_t)k * d.ld;
@@ -803,15 +854,13 @@ void partial_lu(const std::vector<PluDesc<T>>& descs_in, int* dflag, hipStream_t
   std::stable_sort(descs.begin(), descs.end(), [](const PluDesc<T>& a, const PluDesc<T>& b) {
     return (double)a.k * a.nrow * a.ncol > (double)b.k * b.nrow * b.ncol;
   });
-  int maxk = 0, maxr = 0, maxc = 0;
+  int maxk = 0;
   for (auto& d : descs) {
     ABDDC_REQUIRE(d.k >= 0 && d.k <= d.nrow && d.k <= d.ncol && d.ld >= d.ncol, ABDDC_EINVAL,
                   "partial_lu: bad matrix shape");
     ABDDC_REQUIRE((int64_t)d.nrow * d.ld * (int64_t)sizeof(T) < BUF_LIMIT, ABDDC_EINVAL,
                   "partial_lu: matrix spans 2 GiB or more");
     maxk = std::max(maxk, d.k);
-    maxr = std::max(maxr, d.nrow);
-    maxc = std::max(maxc, d.ncol);
   }
   if (maxk == 0) return;
   HostTrace ht;
@@ -855,10 +904,18 @@ void partial_lu(const std::vector<PluDesc<T>>& descs_in, int* dflag, hipStream_t
     hipExtLaunchKernelGGL(plu_diag_kernel<T>, dim3(nb), dim3(256), 0, s, ea, eb, 0, dd, t0, u0, scr, dflag);
   };
   diag_launch(0, 0);
+  auto tiles_of = [](int n) { return n > 0 ? (n + TILE - 1) / TILE : 0; };
+  std::vector<int> cnt(nb);
   for (int t0 = 0; t0 < maxk; t0 += NB) {
-    const int rem = std::max(maxr, maxc) - t0;
-    const int tiles = 2 * ((rem + TILE - 1) / TILE);
-    {
+    // triangular solves: the row strip and the column strip of every matrix
+    // with pivots left
+    for (int z = 0; z < nb; ++z) {
+      const PluDesc<T>& d = descs[z];
+      const int b = std::min(NB, d.k - t0);
+      cnt[z] = t0 < d.k ? tiles_of(d.nrow - t0 - b) + tiles_of(d.ncol - t0 - b) : 0;
+    }
+    const RaggedGrid gt = ragged_grid(cnt, ar);
+    if (gt.grid) {
       double f = 0.0;
       if (g_kstats)
         for (auto& d : descs)
@@ -868,8 +925,8 @@ void partial_lu(const std::vector<PluDesc<T>>& descs_in, int* dflag, hipStream_t
           }
       hipEvent_t ea = nullptr, eb = nullptr;
       tracked_events(KC_PLU_TRSM, f, &ea, &eb);
-      hipExtLaunchKernelGGL(plu_trsm_kernel<T>, dim3(xcd_grid(std::max(tiles, 1), nb)), dim3(256), 0, s, ea, eb, 0,
-                            dd, t0, (const T*)scr, std::max(tiles, 1), nb);
+      hipExtLaunchKernelGGL(plu_trsm_kernel<T>, dim3(gt.grid), dim3(256), 0, s, ea, eb, 0, dd, t0, (const T*)scr,
+                            gt.sched, nb);
     }
     if (t0 + NB < maxk) {
       // the next diagonal block: the pivot columns of this panel's group so
@@ -881,11 +938,19 @@ void partial_lu(const std::vector<PluDesc<T>>& descs_in, int* dflag, hipStream_t
     if ((t0 / NB) % grp != grp - 1) {
       // not the last panel of its group: the band the next panel needs
       if (t0 + NB < maxk) {
-        const int sb = t0 + NB;
         // column strip tiles + row strip tiles (the row strip starts at
-        // column w >= 1 of the trailing part, so it spans < maxc - sb columns)
-        const int bt = (maxr - sb + TILE - 1) / TILE + std::max(0, (maxc - sb - 1 + TILE - 1) / TILE);
-        if (bt > 0) {
+        // column w of the trailing part)
+        for (int z = 0; z < nb; ++z) {
+          const PluDesc<T>& d = descs[z];
+          cnt[z] = 0;
+          if (t0 >= d.k) continue;
+          const int s0 = t0 + std::min(NB, d.k - t0);
+          if (s0 >= d.k) continue;
+          const int w = std::min(NB, d.k - s0);
+          cnt[z] = tiles_of(d.nrow - s0) + tiles_of(d.ncol - s0 - w);
+        }
+        const RaggedGrid gb = ragged_grid(cnt, ar);
+        if (gb.grid) {
           double f = 0.0;
           if (g_kstats)
             for (auto& d : descs)
@@ -897,16 +962,21 @@ void partial_lu(const std::vector<PluDesc<T>>& descs_in, int* dflag, hipStream_t
               }
           hipEvent_t ea = nullptr, eb = nullptr;
           tracked_events(KC_PLU_BAND, f, &ea, &eb);
-          hipExtLaunchKernelGGL(plu_band_kernel<T>, dim3(xcd_grid(bt, nb)), dim3(256), 0, s, ea, eb, 0, dd, g0, t0,
-                                bt, nb);
+          hipExtLaunchKernelGGL(plu_band_kernel<T>, dim3(gb.grid), dim3(256), 0, s, ea, eb, 0, dd, g0, t0, gb.sched,
+                                nb);
         }
       }
       continue;
     }
     // last panel of a group: all its panels, depth grp NB
     const int p0 = g0, sp = p0 + grp * NB;
-    const int rt = (maxr - sp + TILE - 1) / TILE, ct = (maxc - sp + TILE - 1) / TILE;
-    if (sp < maxk && rt > 0 && ct > 0) {
+    for (int z = 0; z < nb; ++z) {
+      const PluDesc<T>& d = descs[z];
+      const int s0 = p0 + std::min(grp * NB, d.k - p0);
+      cnt[z] = (p0 < d.k && s0 < d.k) ? tiles_of(d.nrow - s0) * tiles_of(d.ncol - s0) : 0;
+    }
+    const RaggedGrid gl = ragged_grid(cnt, ar);
+    if (sp < maxk && gl.grid) {
       hipEvent_t ea = nullptr, eb = nullptr;
       if (g_kstats) {
         // rows [s, nrow) x cols [s, k) and rows [s, k) x cols [k, ncol) at
@@ -920,23 +990,22 @@ void partial_lu(const std::vector<PluDesc<T>>& descs_in, int* dflag, hipStream_t
           }
         tracked_events(KC_PLU_LEAD, flops, &ea, &eb);
       }
-      hipExtLaunchKernelGGL(plu_lead_kernel<T>, dim3(xcd_grid(rt * ct, nb)), dim3(256), 0, s, ea, eb, 0, dd, p0,
-                            grp * NB, rt, ct, nb);
+      hipExtLaunchKernelGGL(plu_lead_kernel<T>, dim3(gl.grid), dim3(256), 0, s, ea, eb, 0, dd, p0, grp * NB,
+                            gl.sched, nb);
     }
   }
   // trailing Schur complement with K = k
-  int rt = 0, ct = 0;
   double flops = 0.0;
-  for (auto& d : descs) {
-    rt = std::max(rt, (d.nrow - d.k + TILE - 1) / TILE);
-    ct = std::max(ct, (d.ncol - d.k + TILE - 1) / TILE);
+  for (int z = 0; z < nb; ++z) {
+    const PluDesc<T>& d = descs[z];
+    cnt[z] = d.k > 0 ? tiles_of(d.nrow - d.k) * tiles_of(d.ncol - d.k) : 0;
     flops += 2.0 * (double)(d.nrow - d.k) * (double)(d.ncol - d.k) * d.k;
   }
-  if (rt > 0 && ct > 0) {
+  const RaggedGrid gu = ragged_grid(cnt, ar);
+  if (gu.grid) {
     hipEvent_t ea, eb;
     tracked_events(KC_PLU_UPDATE, flops, &ea, &eb);
-    hipExtLaunchKernelGGL(plu_update_kernel<T>, dim3(xcd_grid(rt * ct, nb)), dim3(256), 0, s, ea, eb, 0, dd, rt,
-                          ct, nb);
+    hipExtLaunchKernelGGL(plu_update_kernel<T>, dim3(gu.grid), dim3(256), 0, s, ea, eb, 0, dd, gu.sched, nb);
   }
   ABDDC_HIP(hipGetLastError());
   ht.mark("partial LU queued");
@@ -947,23 +1016,25 @@ void gemm_batched(const std::vector<GemmDesc<T>>& descs, bool transA, bool trans
                   hipStream_t s) {
   if (descs.empty()) return;
   ABDDC_REQUIRE(alpha != T(0) || beta == T(0), ABDDC_EINVAL, "gemm: alpha = 0 with beta != 0");
-  int maxt = 0;
-  for (auto& d : descs) {
+  std::vector<int> cnt(descs.size());
+  for (size_t z = 0; z < descs.size(); ++z) {
+    const auto& d = descs[z];
     ABDDC_REQUIRE(d.m >= 0 && d.n >= 0 && d.k >= 0, ABDDC_EINVAL, "gemm: negative size");
     const int64_t ea = (int64_t)(transA ? d.k : d.m) * d.lda, eb = (int64_t)(transB ? d.n : d.k) * d.ldb;
     ABDDC_REQUIRE(std::max({ea, eb, (int64_t)d.m * d.ldc}) * (int64_t)sizeof(T) < BUF_LIMIT, ABDDC_EINVAL,
                   "gemm: operand spans 2 GiB or more");
-    maxt = std::max(maxt, ((d.m + TILE - 1) / TILE) * ((d.n + TILE - 1) / TILE));
+    cnt[z] = ((d.m + TILE - 1) / TILE) * ((d.n + TILE - 1) / TILE);
   }
-  if (maxt == 0) return;
   Arena& ar = Arena::for_stream(s);
+  const RaggedGrid rg = ragged_grid(cnt, ar);
+  if (rg.grid == 0) return;
   const GemmDesc<T>* dd = ar.put(descs);
   const int nb = (int)descs.size();
-  const dim3 grid(xcd_grid(maxt, nb));
-  if (!transA && !transB) gemm_batched_kernel<T, false, false><<<grid, 256, 0, s>>>(dd, maxt, nb, alpha, beta);
-  else if (transA && !transB) gemm_batched_kernel<T, true, false><<<grid, 256, 0, s>>>(dd, maxt, nb, alpha, beta);
-  else if (!transA && transB) gemm_batched_kernel<T, false, true><<<grid, 256, 0, s>>>(dd, maxt, nb, alpha, beta);
-  else gemm_batched_kernel<T, true, true><<<grid, 256, 0, s>>>(dd, maxt, nb, alpha, beta);
+  const dim3 grid(rg.grid);
+  if (!transA && !transB) gemm_batched_kernel<T, false, false><<<grid, 256, 0, s>>>(dd, rg.sched, nb, alpha, beta);
+  else if (transA && !transB) gemm_batched_kernel<T, true, false><<<grid, 256, 0, s>>>(dd, rg.sched, nb, alpha, beta);
+  else if (!transA && transB) gemm_batched_kernel<T, false, true><<<grid, 256, 0, s>>>(dd, rg.sched, nb, alpha, beta);
+  else gemm_batched_kernel<T, true, true><<<grid, 256, 0, s>>>(dd, rg.sched, nb, alpha, beta);
   ABDDC_HIP(hipGetLastError());
 }
 
