@@ -10,8 +10,12 @@ recovery), with the coefficient arrays already resident in HBM.
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--config config3]
 
 Prints one JSON line.  `roofline` is the tracked kernel class with the
-largest device time per solve, timed live with HIP events that each launch
-of the class is stamped with on its stream.  `local_solve_tflops` is the
+largest device time per solve, timed live over the timed steps with HIP
+events that each launch of the class is stamped with on its stream.  The
+warmup steps time every class and pick that one; the timed steps time only
+it (a timed launch adds a few microseconds before the next kernel), and
+`kernels_tracked` takes the other classes from two untimed solves that
+follow (`--kernel-stats all` times every class in the timed steps).  `local_solve_tflops` is the
 algorithmic FP64 work of the local Schur complements (S2) and the local
 constrained factorisations (S10) over the device time of those two phases.
 `cpu_baseline` is the FP64 CPU oracle (test infrastructure) timed on the
@@ -65,6 +69,8 @@ def parse():
     ap.add_argument("--edge-variant", choices=["new", "old"], default="new",
                     help="edge eigenproblem: the new one (eq. equ-5-21) or the earlier one (eq. equ-4-8-E)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--kernel-stats", choices=["dominant", "all"], default="dominant",
+                    help="kernel classes timed with events in the timed steps")
     ap.add_argument("--constraints", choices=["exact", "mlp"], default="exact",
                     help="edge constraints from the exact eigenproblem, or from the network trained first "
                          "(untimed) on exact setups of --train-meshes other seeds of the same workload")
@@ -308,15 +314,25 @@ def main():
         te = time.perf_counter()
         return counts, info, ks, ph, sizes, (tb - ta, tc - tb, td - tc, te - td), flops
 
-    flops = None
+    all_classes = (1 << len(TRACKED)) - 1
+    api.set_kernel_stats(all_classes)
+    flops, warm = None, []
     for _ in range(args.warmup):
-        flops = step(want_flops=flops is None)[6] or flops
+        r = step(want_flops=flops is None)
+        flops = r[6] or flops
+        warm.append(r)
+    # the class with the largest device time over the warmup solves
+    dom_cls = max(TRACKED, key=lambda c: sum(r[2][c][0] for r in warm)) if warm else None
+    timed_mask = all_classes if args.kernel_stats == "all" or dom_cls is None else 1 << dom_cls
+    api.set_kernel_stats(timed_mask)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     recs = [step() for _ in range(args.steps)]
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     per_step = (t1 - t0) / args.steps
+    api.set_kernel_stats(all_classes)
+    extra = [] if timed_mask == all_classes else [step() for _ in range(2)]   # untimed
 
     counts, info, _, _, sizes, _, _ = recs[-1]
     if flops is None:
@@ -325,21 +341,25 @@ def main():
     elt = "double" if args.precision == 0 else "double|float"
     tracked = {}
     for cls, (kname, bound) in TRACKED.items():
-        sec = sum(r[2][cls][0] for r in recs)
-        nl = sum(r[2][cls][1] for r in recs)
-        work = sum(r[2][cls][2] for r in recs)
+        live = (timed_mask >> cls) & 1
+        src, nsteps = (recs, args.steps) if live else (extra, len(extra))
+        sec = sum(r[2][cls][0] for r in src)
+        nl = sum(r[2][cls][1] for r in src)
+        work = sum(r[2][cls][2] for r in src)
         if bound == "mfma":
             ach, peak, unit = (work / sec / 1e12 if sec > 0 else 0.0), PEAK_FP64_TFLOPS, "TFLOP/s"
         else:
             ach, peak, unit = (work / sec / 1e9 if sec > 0 else 0.0), PEAK_HBM_GBS, "GB/s"
         tracked[kname.replace("<T>", f"<{elt}>")] = {
             "bound": bound, "achieved": ach, "peak": peak, "unit": unit, "frac": ach / peak,
-            "traffic": None, "avg_launch_us": sec / max(nl, 1) * 1e6, "launches_per_step": nl / args.steps,
-            "seconds_per_step": sec / args.steps, "work_per_launch": work / max(nl, 1)}
+            "traffic": None, "avg_launch_us": sec / max(nl, 1) * 1e6, "launches_per_step": nl / nsteps,
+            "seconds_per_step": sec / nsteps, "work_per_launch": work / max(nl, 1),
+            "timed_over": "timed steps" if live else f"{nsteps} untimed solves after the timed steps"}
     from paper_2501_01676_amd import profiling
     for kname, v in tracked.items():
         v["traffic"] = profiling.read_traffic(kname, args.config)
-    dom = max(tracked, key=lambda k: tracked[k]["seconds_per_step"])
+    dom = TRACKED[dom_cls][0].replace("<T>", f"<{elt}>") if dom_cls is not None else \
+        max(tracked, key=lambda k: tracked[k]["seconds_per_step"])
     roofline = dict(kernel=dom, **tracked[dom])
     upd = [v for k, v in tracked.items() if k.startswith(("plu_update", "plu_lead"))]
     usec = sum(v["seconds_per_step"] for v in upd)

@@ -324,6 +324,15 @@ enum {
 };
 int abddc_kernel_stats(abddc_ctx* ctx, int32_t kernel, double* seconds, int64_t* launches, double* work);
 
+/* Which of the classes above are timed, process-wide: bit k (1 << k) times
+ * class k on every context from the next launch on; returns the previous
+ * mask (bits beyond the last class are ignored).  Default: every class.  A
+ * timed launch carries its start and stop events, which adds a few
+ * microseconds between it and the next kernel on the stream, so a caller
+ * that needs no statistics clears the mask; untimed classes report no
+ * launches. */
+uint32_t abddc_set_kernel_stats(uint32_t mask);
+
 void abddc_destroy(abddc_ctx* ctx);
 
 /* Allocations the library's own caching device allocator has served on a

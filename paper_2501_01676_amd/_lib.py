@@ -101,6 +101,7 @@ SIGNATURES = {
     "abddc_get_stage": (C.c_int64, [_P, C.c_int32, C.c_int32, C.POINTER(C.c_double), C.c_int64]),
     "abddc_phase_times": (C.c_int, [_P, C.POINTER(C.c_double), C.c_int32]),
     "abddc_kernel_stats": (C.c_int, [_P, C.c_int32, C.POINTER(C.c_double), _I64P, C.POINTER(C.c_double)]),
+    "abddc_set_kernel_stats": (C.c_uint32, [C.c_uint32]),
     "abddc_destroy": (None, [_P]),
     "abddc_last_error": (C.c_char_p, []),
     "abddc_mlp_create": (C.c_int, [C.POINTER(C.c_float), C.c_int32, C.POINTER(Device), C.POINTER(_P)]),

@@ -239,7 +239,8 @@ class Solver:
         """(seconds, launches, work) accumulated for a tracked kernel class
         (0: partial-LU trailing Schur product, flops; 1: batched GEMV, bytes;
         2: partial-LU per-group update, flops; 3: diagonal-block LU, flops;
-        4: panel triangular solves, flops; 5: in-group band update, flops)."""
+        4: panel triangular solves, bytes; 5: in-group band update, flops).
+        Only classes in the process-wide mask (set_kernel_stats) are timed."""
         sec, n, w = C.c_double(), C.c_int64(), C.c_double()
         L.check(self.lib.abddc_kernel_stats(self.ctx, kernel, C.byref(sec), C.byref(n), C.byref(w)))
         return sec.value, n.value, w.value
@@ -311,6 +312,12 @@ class MLP:
 
 
 # ------------------------------------------------------------- test hooks
+def set_kernel_stats(mask):
+    """Time the kernel classes whose bits are set in `mask` (bit k: class k
+    of Solver.kernel_stats), process-wide; returns the previous mask."""
+    return int(L.load().abddc_set_kernel_stats(int(mask) & 0xFFFFFFFF))
+
+
 def _pack(mats, dtype, device):
     offs, flat = [], []
     pos = 0

@@ -17,6 +17,7 @@
 namespace abddc {
 thread_local std::string g_last_error;
 thread_local KStats* g_kstats = nullptr;
+std::atomic<uint32_t> g_kstats_mask{(1u << KC_COUNT) - 1};
 
 int fail(int code, const std::string& msg) {
   g_last_error = msg;
@@ -171,6 +172,10 @@ extern "C" int abddc_cache_stats(int32_t device, int64_t* allocations, int64_t* 
   if (allocations) *allocations = g_cache_allocs[device].load();
   if (bytes) *bytes = g_cache_bytes[device].load();
   return ABDDC_OK;
+}
+
+extern "C" uint32_t abddc_set_kernel_stats(uint32_t mask) {
+  return g_kstats_mask.exchange(mask & ((1u << KC_COUNT) - 1));
 }
 
 namespace {

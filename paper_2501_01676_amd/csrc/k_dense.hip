@@ -671,6 +671,88 @@ __global__ void __launch_bounds__(256) plu_diag_kernel(const PluDesc<T>* __restr
   }
 }
 
+// One 64-wide tile of a panel's triangular solves, by the explicit inverses
+// of the diagonal block (K = b <= 64, two K chunks at most):
+//   ROW:  C (m x b) <- C U^{-1}, U^{-1} upper triangular (the B operand)
+//   !ROW: C (b x n) <- L^{-1} C, L^{-1} lower triangular (the A operand)
+// Output block v (a 16-column block for ROW, a 16-row block otherwise)
+// takes only k < 16 (v + 1): the zero 16 x 16 blocks of the triangular
+// factor are skipped, 40 of the 64 MFMA steps of the dense product.  Wave w
+// owns stripe w of the tile (16 rows for ROW, 16 columns otherwise) across
+// all four blocks v, so every wave issues the same 40 steps (blocks beyond
+// the edge of C multiply the zeros that the bounded loads read and are not
+// stored; a per-block test here makes the compiler spill).  Loads follow
+// tile_gemm<T, false, false>; in place (C aliasing A or B) is safe: every
+// read of the tile has landed in LDS before the barrier that precedes the
+// MFMAs of its last chunk, and the stores come after those.
+template <class T, bool ROW>
+__device__ __forceinline__ void tile_trsm(const T* __restrict__ A, int lda, const T* __restrict__ B, int ldb, T* C,
+                                          int ldc, int m, int n, int k, T (*As)[LDS_PAD], T (*Bs)[LDS_PAD]) {
+  typedef typename Mfma<T>::acc_t acc_t;
+  constexpr int PER = TILE * KC / 256;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int kl = lane >> 4, il = lane & 15;
+  // A row-major: i = (tid >> 5) + 8q, kk = tid & 31; B k-major: kk = (tid >> 6) + 4q, j = tid & 63
+  const int a_i0 = tid >> 5, a_k0 = tid & 31, b_j0 = tid & 63, b_k0 = tid >> 6;
+  const __amdgpu_buffer_rsrc_t rsa = buf_rsrc(A), rsb = buf_rsrc(B), rsc = buf_rsrc(C);
+  int oa[PER], ob[PER];
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int ai = a_i0 + 8 * q;
+    oa[q] = ai < m ? (ai * lda + a_k0) * (int)sizeof(T) : BUF_OUT;
+    ob[q] = b_j0 < n ? ((b_k0 + 4 * q) * ldb + b_j0) * (int)sizeof(T) : BUF_OUT;
+  }
+  T ra[PER], rb[PER];
+  auto fetch = [&](int k0) {
+    const int sa = k0 * (int)sizeof(T), sb = k0 * ldb * (int)sizeof(T);
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      ra[q] = buf_load<T>(rsa, k0 + a_k0 < k ? oa[q] : BUF_OUT, sa);
+      rb[q] = buf_load<T>(rsb, k0 + b_k0 + 4 * q < k ? ob[q] : BUF_OUT, sb);
+    }
+  };
+  acc_t acc[4];
+#pragma unroll
+  for (int v = 0; v < 4; ++v) acc[v] = acc_t{0, 0, 0, 0};
+  const bool wok = 16 * w < (ROW ? m : n);  // the wave's stripe holds part of C
+  if (k > 0) fetch(0);
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+    const int k0 = c * KC;
+    if (k0 >= k) break;
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      As[a_k0][a_i0 + 8 * q] = ra[q];
+      Bs[b_k0 + 4 * q][b_j0] = rb[q];
+    }
+    __syncthreads();
+    if (c == 0 && KC < k) fetch(KC);   // the second chunk in flight during the first chunk's MFMAs
+    if (wok) {
+#pragma unroll
+      for (int kk = 0; kk < KC; kk += 4) {
+        const T sv = ROW ? As[kk + kl][16 * w + il] : Bs[kk + kl][16 * w + il];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          if (c * KC + kk >= 16 * (v + 1)) continue;   // zero block of the factor (compile time)
+          if (ROW)
+            acc[v] = Mfma<T>::run(sv, Bs[kk + kl][16 * v + il], acc[v]);
+          else
+            acc[v] = Mfma<T>::run(As[kk + kl][16 * v + il], sv, acc[v]);
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int v = 0; v < 4; ++v)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int r = ROW ? 16 * w + Mfma<T>::out_row(kl, q) : 16 * v + Mfma<T>::out_row(kl, q);
+      const int cc = ROW ? 16 * v + il : 16 * w + il;
+      buf_store<T>(acc[v][q], rsc, (r < m && cc < n) ? (r * ldc + cc) * (int)sizeof(T) : BUF_OUT, 0);
+    }
+}
+
 // Step 2: A21 <- A21 U11^{-1} (row tiles), A12 <- L11^{-1} A12 (column tiles).
 template <class T>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) plu_trsm_kernel(const PluDesc<T>* __restrict__ descs, int t0,
@@ -689,12 +771,12 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) p
   if (t < rt) {
     T* C = d.a + (size_t)(t0 + b + t * TILE) * d.ld + t0;
     const int m = min(TILE, mr - t * TILE);
-    tile_gemm<T, false, false>(C, d.ld, Ui, NB, C, d.ld, m, b, b, T(1), T(0), 0, 0, As, Bs);
+    tile_trsm<T, true>(C, d.ld, Ui, NB, C, d.ld, m, b, b, As, Bs);
   } else if (t < rt + ct) {
     const int c = t - rt;
     T* C = d.a + (size_t)t0 * d.ld + t0 + b + c * TILE;
     const int n = min(TILE, nc - c * TILE);
-    tile_gemm<T, false, false>(Li, NB, C, d.ld, C, d.ld, b, n, b, T(1), T(0), 0, 0, As, Bs);
+    tile_trsm<T, false>(Li, NB, C, d.ld, C, d.ld, b, n, b, As, Bs);
   }
 }
 
@@ -890,7 +972,7 @@ void partial_lu(const std::vector<PluDesc<T>>& descs_in, int* dflag, hipStream_t
   //         the next diagonal block
   auto diag_flops = [&](int t0, int u0) {
     double f = 0.0;
-    if (g_kstats)
+    if (kstats_on(KC_PLU_DIAG))
       for (auto& d : descs)
         if (t0 < d.k) {
           const double b = std::min(NB, d.k - t0);
@@ -917,7 +999,7 @@ void partial_lu(const std::vector<PluDesc<T>>& descs_in, int* dflag, hipStream_t
     const RaggedGrid gt = ragged_grid(cnt, ar);
     if (gt.grid) {
       double f = 0.0;
-      if (g_kstats)
+      if (kstats_on(KC_PLU_TRSM))
         for (auto& d : descs)
           if (t0 < d.k) {
             const double b = std::min(NB, d.k - t0);
@@ -952,7 +1034,7 @@ void partial_lu(const std::vector<PluDesc<T>>& descs_in, int* dflag, hipStream_t
         const RaggedGrid gb = ragged_grid(cnt, ar);
         if (gb.grid) {
           double f = 0.0;
-          if (g_kstats)
+          if (kstats_on(KC_PLU_BAND))
             for (auto& d : descs)
               if (t0 < d.k) {
                 const int s0 = t0 + std::min(NB, d.k - t0);
@@ -978,7 +1060,7 @@ void partial_lu(const std::vector<PluDesc<T>>& descs_in, int* dflag, hipStream_t
     const RaggedGrid gl = ragged_grid(cnt, ar);
     if (sp < maxk && gl.grid) {
       hipEvent_t ea = nullptr, eb = nullptr;
-      if (g_kstats) {
+      if (kstats_on(KC_PLU_LEAD)) {
         // rows [s, nrow) x cols [s, k) and rows [s, k) x cols [k, ncol) at
         // depth b, without the next diagonal block
         double flops = 0.0;

@@ -39,6 +39,52 @@ __global__ void deluxe_build_kernel(const DeluxeDesc* __restrict__ descs) {
   }
 }
 
+// Aug = [[Sbar_r, W_r^T], [-W_r, 0]] (AugDesc), one wave per row (rows
+// strided over the grid's waves), lanes along the row.  Eliminating its
+// n_Delta leading pivots leaves [[S_PiPi - S_PiD X S_DPi, V], [-U, L]] with
+// X = S_DD^{-1}: L = W_D X W_D^T, V = W_Pi^T - S_PiD X W_D^T and
+// U = W_Pi - W_D X S_DPi, the averaged local solve operators.
+__global__ void __launch_bounds__(256) aug_build_kernel(const AugDesc* __restrict__ descs) {
+  __shared__ AugDesc sd;
+  if (threadIdx.x == 0) sd = descs[blockIdx.y];
+  __syncthreads();
+  const AugDesc& d = sd;
+  const int nB = d.nB, na = 2 * nB, lane = threadIdx.x & 63;
+  const int nwv = gridDim.x * (blockDim.x >> 6);
+  for (int i = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); i < na; i += nwv) {
+    double* row = d.aug + (size_t)i * na;
+    if (i < nB) {
+      // row of coordinate ci: Sbar(ci, am(j)), then W(m, ci) = W_X(m - off, ci - off)
+      // for m in the object of ci
+      const int ci = d.am[i], q = d.slot[ci], off = d.obj_off[q], n = d.obj_n[q];
+      const double* srow = d.sbar + (size_t)ci * nB;
+      const double* wcol = d.wx + d.obj_w[q] + (ci - off);
+      for (int j = lane; j < na; j += 64) {
+        double v;
+        if (j < nB) {
+          v = srow[d.am[j]];
+        } else {
+          const int m = j - nB;
+          v = (m >= off && m < off + n) ? wcol[(size_t)(m - off) * n] : 0.0;
+        }
+        row[j] = v;
+      }
+    } else {
+      // row of original coordinate m: -W(m, am(j)) inside its object, then zeros
+      const int m = i - nB, q = d.slot[m], off = d.obj_off[q], n = d.obj_n[q];
+      const double* wrow = d.wx + d.obj_w[q] + (size_t)(m - off) * n;
+      for (int j = lane; j < na; j += 64) {
+        double v = 0.0;
+        if (j < nB) {
+          const int c = d.am[j];
+          if (c >= off && c < off + n) v = -wrow[c - off];
+        }
+        row[j] = v;
+      }
+    }
+  }
+}
+
 // Metric of the earlier edge eigenproblem, regrouped by the weight index:
 // B_E = sum_k D^(k)^T (sum_{i != k} B_E^(i)) D^(k), written symmetrised.
 template <int NE>
@@ -213,6 +259,17 @@ void deluxe_build_batched(const std::vector<DeluxeDesc>& descs, hipStream_t s) {
   for (auto& d : descs) maxe = std::max(maxe, 2 * d.n * (d.m + 1) * d.n);
   const DeluxeDesc* dd = Arena::for_stream(s).put(descs);
   deluxe_build_kernel<<<dim3(std::min(256, (maxe + 255) / 256), descs.size()), 256, 0, s>>>(dd);
+  ABDDC_HIP(hipGetLastError());
+}
+
+void aug_build_batched(const std::vector<AugDesc>& descs, hipStream_t s) {
+  if (descs.empty()) return;
+  int maxr = 0;
+  for (auto& d : descs) maxr = std::max(maxr, 2 * d.nB);
+  if (maxr == 0) return;
+  const AugDesc* dd = Arena::for_stream(s).put(descs);
+  const int gx = std::min((maxr + 3) / 4, 1024);   // four rows (waves) per workgroup
+  aug_build_kernel<<<dim3(gx, descs.size()), 256, 0, s>>>(dd);
   ABDDC_HIP(hipGetLastError());
 }
 

@@ -8,6 +8,7 @@
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cstdint>
 #include <map>
 #include <mutex>
@@ -108,12 +109,20 @@ struct KStats {
 };
 
 extern thread_local KStats* g_kstats;
+// Classes timed with events, process-wide (bit k: class k); a timed launch
+// waits for its events, so classes outside the mask run untimed.
+extern std::atomic<uint32_t> g_kstats_mask;
+
+inline bool kstats_on(int cls) {
+  return g_kstats && ((g_kstats_mask.load(std::memory_order_relaxed) >> cls) & 1u);
+}
 
 // Event pair for one launch of a tracked kernel (both null when no sink is
-// set; hipExtLaunchKernel then launches without timing).
+// set or the class is not timed; hipExtLaunchKernel then launches without
+// timing).
 inline void tracked_events(int cls, double work_amount, hipEvent_t* start, hipEvent_t* stop) {
   *start = *stop = nullptr;
-  if (g_kstats && work_amount > 0) g_kstats->events(cls, work_amount, start, stop);
+  if (kstats_on(cls) && work_amount > 0) g_kstats->events(cls, work_amount, start, stop);
 }
 
 // RAII: route the launches of one entry point into ctx stats.

@@ -970,14 +970,13 @@ void run_setup(abddc_ctx* c) {
     c->poff[sub] = pt;
     pt += nP;
     aoff2[sub] = at;
-    at += (int64_t)(2 * nD + nP) * (2 * nD + nP);
+    at += (int64_t)(2 * nB) * (2 * nB);
     for (int k : T.sub[sub].objs) {
       wpos[sub].push_back(wt);
       wt += (int64_t)T.objects[k].n * T.objects[k].n;
     }
   }
   DevBuf<double> Sb(c->dS.n), Aug(std::max<int64_t>(at, 1)), WX(std::max<int64_t>(wt, 1));
-  DevBuf<double> Kt(c->dS.n), Y2(c->dS.n), Vt(std::max<int64_t>(ut, 1)), Ut(std::max<int64_t>(ut, 1));
   c->dM.alloc(std::max<int64_t>(mt, 1));
   c->dU.alloc(std::max<int64_t>(ut, 1));
   {
@@ -1015,69 +1014,60 @@ void run_setup(abddc_ctx* c) {
     set_batched(vset, s);                                    // vertices: 1/|n(V)|
   }
   {
-    ht.mark("augmented [[Sdd, Sdp, I], [Spd, Spp, 0");
-    // augmented [[Sdd, Sdp, I], [Spd, Spp, 0], [-I, 0, 0]], eliminate Delta
+    ht.mark("augmented [[Sbar, W^T], [-W, 0]]");
+    // Local constrained solve with the averaging folded in (the order of
+    // rows and columns is [Delta; Pi] of rotated coordinates, then the nB
+    // original coordinates):
+    //   Aug = [[S_DD, S_DPi, W_D^T], [S_PiD, S_PiPi, W_Pi^T], [-W_D, -W_Pi, 0]].
+    // Eliminating the Delta pivots leaves [[S_c, V], [-U, L]] with
+    // X = S_DD^{-1}, S_c = S_PiPi - S_PiD X S_DPi (the local coarse matrix),
+    // L = W_D X W_D^T, V = W_Pi^T - S_PiD X W_D^T, U = W_Pi - W_D X S_DPi:
+    // M = [L; V] and U are read off the trailing block.
     IntPool pool;
-    std::vector<size_t> am(nsub), dr(nsub), dc(nsub), kt(nsub), vr(nsub), vc(nsub), ur(nsub), pi_off(nsub),
-        pidx(nsub), iota_off(nsub);
-    size_t total = 0;
-    for (int sub = 0; sub < nsub; ++sub)
-      total += 6 * Dl[sub].size() + 4 * Pi[sub].size() + c->nB[sub] + Pid[sub].size();
-    pool.h.reserve(total);
+    std::vector<size_t> am(nsub), sl(nsub), oo(nsub), on(nsub), ow(nsub), mr(nsub), pidx(nsub);
+    ABDDC_REQUIRE(wt < ((int64_t)1 << 31), ABDDC_EINVAL, "interface blocks too large");
     for (int sub = 0; sub < nsub; ++sub) {
-      const size_t nB = c->nB[sub], nP = Pi[sub].size(), nD = Dl[sub].size();
-      am[sub] = pool.reserve(2 * nD + nP);
-      dr[sub] = pool.reserve(nD);
-      dc[sub] = pool.reserve(nD);
-      kt[sub] = pool.reserve(nD);
-      vr[sub] = pool.reserve(nD);
-      vc[sub] = pool.reserve(nB);
-      ur[sub] = pool.reserve(nP);
-      pi_off[sub] = pool.reserve(nP);
-      iota_off[sub] = pool.reserve(nP);
+      const size_t nB = c->nB[sub], nP = Pi[sub].size(), no = T.sub[sub].objs.size();
+      am[sub] = pool.reserve(nB);
+      sl[sub] = pool.reserve(nB);
+      oo[sub] = pool.reserve(no);
+      on[sub] = pool.reserve(no);
+      ow[sub] = pool.reserve(no);
+      mr[sub] = pool.reserve(nB + nP);
       pidx[sub] = pool.reserve(Pid[sub].size());
     }
     host_parallel_for(nsub, 8, [&](int64_t sb, int64_t se) {
       for (int sub = (int)sb; sub < (int)se; ++sub) {
+        const SubInfo& si = T.sub[sub];
         const int nB = c->nB[sub], nP = (int)Pi[sub].size(), nD = (int)Dl[sub].size();
         int32_t* h = pool.h.data();
-        // aug row/col -> local coordinate: [Delta; Pi; -1 for the multipliers]
         int32_t* mp = h + am[sub];
         std::copy(Dl[sub].begin(), Dl[sub].end(), mp);
         std::copy(Pi[sub].begin(), Pi[sub].end(), mp + nD);
-        std::fill(mp + nD + nP, mp + 2 * nD + nP, -1);
-        for (int q = 0; q < nD; ++q) {
-          h[dr[sub] + q] = q;               // identity block rows ...
-          h[dc[sub] + q] = nD + nP + q;     // ... and columns
-          h[kt[sub] + q] = nD + nP + q;     // -identity block rows ...
-          h[vr[sub] + q] = q;               // ... and columns
+        for (size_t q = 0; q < si.objs.size(); ++q) {
+          const int n = T.objects[si.objs[q]].n, off = si.obj_off[q];
+          std::fill(h + sl[sub] + off, h + sl[sub] + off + n, (int32_t)q);
+          h[oo[sub] + q] = off;
+          h[on[sub] + q] = n;
+          h[ow[sub] + q] = (int32_t)wpos[sub][q];
         }
-        // Ktilde map (local coordinate q -> aug row/col of K), -1 on Pi
-        int32_t* km = h + vc[sub];
-        std::fill(km, km + nB, -1);
-        for (int q = 0; q < nD; ++q) km[Dl[sub][q]] = nD + nP + q;
-        // Pi rows of the aug matrix and the -Phi columns
-        for (int l = 0; l < nP; ++l) {
-          h[ur[sub] + l] = nD + l;
-          h[iota_off[sub] + l] = l;
-        }
-        std::copy(Pi[sub].begin(), Pi[sub].end(), h + pi_off[sub]);
+        // rows of M = [L; V] in the trailing block: the original
+        // coordinates, then the Pi rows
+        for (int l = 0; l < nB; ++l) h[mr[sub] + l] = nB + l;
+        for (int l = 0; l < nP; ++l) h[mr[sub] + nB + l] = nD + l;
         std::copy(Pid[sub].begin(), Pid[sub].end(), h + pidx[sub]);
       }
     });
     pool.upload(s);
-    std::vector<GatherDesc> gd;
-    std::vector<SetDesc> st;
+    std::vector<AugDesc> ad;
     std::vector<PluDesc<double>> pd;
     for (int sub = 0; sub < nsub; ++sub) {
-      const int nB = c->nB[sub], nP = (int)Pi[sub].size(), nD = (int)Dl[sub].size(), na = 2 * nD + nP;
-      gd.push_back({Sb.p + c->soff[sub], Aug.p + aoff2[sub], pool.ptr(am[sub]), pool.ptr(am[sub]), na, na, nB, na, 1.0});
-      st.push_back({Aug.p + aoff2[sub], pool.ptr(dr[sub]), pool.ptr(dc[sub]), nD, na, 1.0});
-      st.push_back({Aug.p + aoff2[sub], pool.ptr(kt[sub]), pool.ptr(vr[sub]), nD, na, -1.0});
-      pd.push_back({Aug.p + aoff2[sub], na, na, na, nD});
+      const int nB = c->nB[sub], nD = (int)Dl[sub].size();
+      ad.push_back({Sb.p + c->soff[sub], Aug.p + aoff2[sub], pool.ptr(am[sub]), pool.ptr(sl[sub]),
+                    pool.ptr(oo[sub]), pool.ptr(on[sub]), pool.ptr(ow[sub]), WX.p, nB});
+      pd.push_back({Aug.p + aoff2[sub], 2 * nB, 2 * nB, 2 * nB, nD});
     }
-    gather_batched(gd, s);
-    set_batched(st, s);
+    aug_build_batched(ad, s);
     if (c->opt.precision == ABDDC_PREC_MIXED) {
       // local constrained factorisation in FP32 on MFMA; the preconditioner it
       // defines is applied inside FP64 GMRES, which absorbs its rounding
@@ -1091,46 +1081,16 @@ void run_setup(abddc_ctx* c) {
       partial_lu<double>(pd, c->d_flag.p, s);
     }
 
-    ht.mark("Ktilde (nB x nB), Vt (nP x nB) = [Psi^");
-    // Ktilde (nB x nB), Vt (nP x nB) = [Psi^T | I], Ut (nB x nP) = [Phi; I]
-    gd.clear();
-    st.clear();
+    ht.mark("M = [L; V], U from the trailing block");
+    std::vector<GatherDesc> gd;
     for (int sub = 0; sub < nsub; ++sub) {
-      const int nB = c->nB[sub], nP = (int)Pi[sub].size(), nD = (int)Dl[sub].size(), na = 2 * nD + nP;
-      gd.push_back({Aug.p + aoff2[sub], Kt.p + c->soff[sub], pool.ptr(vc[sub]), pool.ptr(vc[sub]), nB, nB, na, nB, 1.0});
-      if (nP > 0) {
-        gd.push_back({Aug.p + aoff2[sub], Vt.p + c->uoff[sub], pool.ptr(ur[sub]), pool.ptr(vc[sub]), nP, nB, na, nB, 1.0});
-        gd.push_back({Aug.p + aoff2[sub], Ut.p + c->uoff[sub], pool.ptr(vc[sub]), pool.ptr(ur[sub]), nB, nP, na, nP, -1.0});
-        st.push_back({Vt.p + c->uoff[sub], pool.ptr(iota_off[sub]), pool.ptr(pi_off[sub]), nP, nB, 1.0});
-        st.push_back({Ut.p + c->uoff[sub], pool.ptr(pi_off[sub]), pool.ptr(iota_off[sub]), nP, nP, 1.0});
-      }
+      const int nB = c->nB[sub], nP = (int)Pi[sub].size(), nD = (int)Dl[sub].size(), na = 2 * nB;
+      const double* A = Aug.p + aoff2[sub];
+      gd.push_back({A + nB, c->dM.p + c->moff[sub], pool.ptr(mr[sub]), nullptr, nB + nP, nB, na, nB, 1.0});
+      if (nP > 0)
+        gd.push_back({A + (int64_t)nB * na + nD, c->dU.p + c->uoff[sub], nullptr, nullptr, nB, nP, na, nP, -1.0});
     }
     gather_batched(gd, s);
-    set_batched(st, s);
-
-    ht.mark("L = W Ktilde W^T, V = Vt W^T, U = W Ut");
-    // L = W Ktilde W^T, V = Vt W^T, U = W Ut (W block diagonal)
-    std::vector<GemmDesc<double>> g1, g2, g3, g4;
-    for (int sub = 0; sub < nsub; ++sub) {
-      const SubInfo& si = T.sub[sub];
-      const int nB = c->nB[sub], nP = (int)Pi[sub].size();
-      double* Lm = c->dM.p + c->moff[sub];
-      double* Vm = Lm + (int64_t)nB * nB;
-      for (size_t q = 0; q < si.objs.size(); ++q) {
-        const int n = T.objects[si.objs[q]].n, off = si.obj_off[q];
-        const double* wx = WX.p + wpos[sub][q];
-        g1.push_back({wx, Kt.p + c->soff[sub] + (int64_t)off * nB, Y2.p + c->soff[sub] + (int64_t)off * nB, n, nB, n, n, nB, nB});
-        g2.push_back({Y2.p + c->soff[sub] + off, wx, Lm + off, nB, n, n, nB, n, nB});
-        if (nP > 0) {
-          g3.push_back({Vt.p + c->uoff[sub] + off, wx, Vm + off, nP, n, n, nB, n, nB});
-          g4.push_back({wx, Ut.p + c->uoff[sub] + (int64_t)off * nP, c->dU.p + c->uoff[sub] + (int64_t)off * nP, n, nP, n, n, nP, nP});
-        }
-      }
-    }
-    gemm_batched<double>(g1, false, false, 1.0, 0.0, s);
-    gemm_batched<double>(g2, false, true, 1.0, 0.0, s);
-    gemm_batched<double>(g3, false, true, 1.0, 0.0, s);
-    gemm_batched<double>(g4, false, false, 1.0, 0.0, s);
 
     ht.mark("coarse");
     // ----------------------------------------------------------- coarse
@@ -1170,7 +1130,7 @@ void run_setup(abddc_ctx* c) {
       std::vector<CoarseAddDesc> cd;
       for (int sub = 0; sub < nsub; ++sub) {
         if (colour[sub] != color) continue;
-        const int nP = (int)Pi[sub].size(), nD = (int)Dl[sub].size(), na = 2 * nD + nP;
+        const int nP = (int)Pi[sub].size(), nD = (int)Dl[sub].size(), na = 2 * c->nB[sub];
         if (nP == 0) continue;
         cd.push_back({Aug.p + aoff2[sub] + (int64_t)nD * na + nD, pool.ptr(pidx[sub]), nP, na});
       }
@@ -1199,7 +1159,7 @@ void run_setup(abddc_ctx* c) {
     ht.mark("apply metadata (device)");
     // ------------------------------------------- apply metadata (device)
     record(c, 7);
-    std::vector<int32_t> pid_all, ptr_p, idx_p, ptr_a, idx_a, kp, vp, ka, va;
+    std::vector<int32_t> pid_all, ptr_p, idx_p, kp, vp;
     for (int sub = 0; sub < nsub; ++sub) {
       const int nB = c->nB[sub];
       pid_all.insert(pid_all.end(), Pid[sub].begin(), Pid[sub].end());
@@ -1207,13 +1167,32 @@ void run_setup(abddc_ctx* c) {
         kp.push_back(Pid[sub][l]);
         vp.push_back((int32_t)(c->ooff[sub] + nB + l));
       }
-      for (int l = 0; l < nB; ++l) {
-        ka.push_back((int32_t)T.sub[sub].gamma[l]);
-        va.push_back((int32_t)(c->ooff[sub] + l));
-      }
     }
     csr_group(np, kp, vp, ptr_p, idx_p);
-    csr_group(T.n_gamma, ka, va, ptr_a, idx_a);
+    // interface dof -> its output rows, one per sharing subdomain in
+    // subdomain order: dof gstart + q of object k sits at row
+    // ooff[s] + (offset of k in Gamma_s) + q of every s in n(k); objects
+    // are in interface order, so each object's entries form one range
+    std::vector<int64_t> opos(T.objects.size() + 1, 0);
+    for (size_t k = 0; k < T.objects.size(); ++k)
+      opos[k + 1] = opos[k] + (int64_t)T.objects[k].n * (int64_t)T.objects[k].subs.size();
+    std::vector<int32_t> ptr_a((size_t)T.n_gamma + 1), idx_a((size_t)opos.back());
+    host_parallel_for((int64_t)T.objects.size(), 64, [&](int64_t kb, int64_t ke) {
+      std::vector<int32_t> base;
+      for (int64_t k = kb; k < ke; ++k) {
+        const Object& o = T.objects[k];
+        const int m = (int)o.subs.size();
+        base.resize(m);
+        for (int j = 0; j < m; ++j)
+          base[j] = (int32_t)(c->ooff[o.subs[j]] + T.sub[o.subs[j]].local_pos((int)k));
+        for (int q = 0; q < o.n; ++q) {
+          const int64_t at = opos[k] + (int64_t)q * m;
+          ptr_a[o.gstart + q] = (int32_t)at;
+          for (int j = 0; j < m; ++j) idx_a[at + j] = base[j] + q;
+        }
+      }
+    });
+    ptr_a[T.n_gamma] = (int32_t)opos.back();
     ht.mark("metadata: owner lists");
     c->d_pid = to_device(pid_all, s);
     c->d_pown_ptr = to_device(ptr_p, s);

@@ -40,6 +40,26 @@ struct EdgeOldDesc {
   int32_t nE, m;
 };
 
+// The local constrained system of one subdomain with the averaging folded
+// in: Aug = [[Sbar_r, W_r^T], [-W_r, 0]] of order 2 nB, Sbar_r the rotated
+// Schur complement with rows and columns in the order am = [Delta; Pi] of
+// rotated local coordinates, W_r = W(:, am), W block diagonal by interface
+// object (W_X = D_X T_X, n_X x n_X, rows original and columns rotated
+// coordinates of the object).  Objects occupy contiguous coordinate ranges;
+// slot maps a local coordinate to its object, whose first coordinate, size
+// and W_X offset (in wx) are obj_off, obj_n and obj_w.
+struct AugDesc {
+  const double* sbar;     // nB x nB, ld nB
+  double* aug;            // 2 nB x 2 nB, ld 2 nB
+  const int32_t* am;      // nB
+  const int32_t* slot;    // nB
+  const int32_t* obj_off;
+  const int32_t* obj_n;
+  const int32_t* obj_w;
+  const double* wx;
+  int32_t nB;
+};
+
 struct CoarseAddDesc {
   const double* src;
   const int32_t* gid;
@@ -57,6 +77,7 @@ struct AxpbyDesc {
 void convert_f64_f32(const double* src, float* dst, int64_t n, hipStream_t s);
 void convert_f32_f64(const float* src, double* dst, int64_t n, hipStream_t s);
 void deluxe_build_batched(const std::vector<DeluxeDesc>& d, hipStream_t s);
+void aug_build_batched(const std::vector<AugDesc>& d, hipStream_t s);
 void edge_assemble_batched(const std::vector<EdgeAsmDesc>& d, hipStream_t s);
 void edge_old_metric_batched(const std::vector<EdgeOldDesc>& d, hipStream_t s);
 void coarse_add_batched(const std::vector<CoarseAddDesc>& d, double* SPi, int64_t ldc, hipStream_t s);

@@ -5,6 +5,7 @@
 #include <array>
 
 #include "host_pool.h"
+#include "htrace.h"
 #include "internal.h"
 
 namespace abddc {
@@ -39,6 +40,7 @@ void Topology::build(const int nsub_in[3], const int* const width_in[3]) {
 }
 
 void Topology::build_objects() {
+  HostTrace ht;
   // Per axis, a grid index has the key 2s inside subdomain s and 2c - 1 on
   // the cut c between subdomains c - 1 and c; the indices of one key form
   // the range [klo, khi] (Dirichlet boundary indices belong to no key).  An
@@ -67,6 +69,7 @@ void Topology::build_objects() {
       }
   });
   n_dof = (int64_t)(nn[0] - 2) * (nn[1] - 2) * (nn[2] - 2);
+  ht.mark("topology: free-node numbering");
   iface_of_node.assign(n_nodes, -1);
   objects.clear();
   const int nk[3] = {2 * nsub[0] - 1, 2 * nsub[1] - 1, 2 * nsub[2] - 1};
@@ -105,6 +108,7 @@ void Topology::build_objects() {
     }
   });
 
+  ht.mark("topology: objects");
   faces.clear();
   edges.clear();
   vertices.clear();
@@ -126,6 +130,7 @@ void Topology::build_objects() {
     }
   });
 
+  ht.mark("topology: interface numbering");
   sub.assign(n_sub, SubInfo());
   for (size_t k = 0; k < objects.size(); ++k)
     for (int s : objects[k].subs) sub[s].objs.push_back((int)k);
@@ -156,6 +161,7 @@ void Topology::build_objects() {
       si.nB = pos;
     }
   });
+  ht.mark("topology: subdomain lists");
 }
 
 }  // namespace abddc
