@@ -215,8 +215,11 @@ void setup_with(abddc_ctx* c, const abddc_options& o) {
     c->step_graph = nullptr;
     c->step_restart = 0;
   }
+  HostTrace ht;
   run_setup(c);
+  ht.mark("setup: stage buffers released");
   c->kstats.resolve();
+  ht.mark("setup: kernel statistics resolved");
   c->phase[2] = ev_ms(c, 2, 3);
   c->phase[3] = ev_ms(c, 3, 4);
   c->phase[4] = ev_ms(c, 4, 5);
@@ -422,7 +425,7 @@ extern "C" int abddc_assemble(const abddc_problem* prob, const abddc_device* dev
         auto place = [&](int64_t v, bool interior) {
           const int ix = (int)(v % T.nn[0]), iy = (int)((v / T.nn[0]) % T.nn[1]);
           const int iz = (int)(v / ((int64_t)T.nn[0] * T.nn[1]));
-          if (interior) idof[loc] = (int32_t)T.dof_of_node[v];
+          if (interior) idof[loc] = (int32_t)T.dof_of(v);
           ln[loc] = (int32_t)v;
           lmap[b0 + (ix - e0[0]) + (size_t)bx * ((iy - e0[1]) + (size_t)by * (iz - e0[2]))] = loc++;
         };
@@ -442,7 +445,7 @@ extern "C" int abddc_assemble(const abddc_problem* prob, const abddc_device* dev
     host_parallel_for((int64_t)T.objects.size(), 64, [&](int64_t b, int64_t e) {
       for (int64_t k = b; k < e; ++k) {
         const Object& o = T.objects[k];
-        for (int q = 0; q < o.n; ++q) iface_dof[o.gstart + q] = (int32_t)T.dof_of_node[o.nodes[q]];
+        for (int q = 0; q < o.n; ++q) iface_dof[o.gstart + q] = (int32_t)T.dof_of(o.nodes[q]);
       }
     });
     c->d_iface_dof = to_device(iface_dof, s);
@@ -551,6 +554,7 @@ extern "C" int abddc_setup_coarse_space(abddc_ctx* c, const abddc_options* opts,
     AllocScope as(&c->dalloc);
     KStatsScope ks(&c->kstats);
     StreamScope ss(c->stream);
+    HostTrace().mark("setup: entry (since the last library mark)");
     setup_with(c, o);
     if (counts) *counts = {c->n_vertex, c->pnum_face, c->pnum_edge, c->n_primal, c->n_ties};
     return ABDDC_OK;
@@ -643,6 +647,7 @@ namespace {
 // arguments and set the scopes); fills info (may be null) and returns
 // whether the true residual met rtol.
 bool gmres_core(abddc_ctx* c, int32_t restart, double rtol, int32_t maxit, double* u, abddc_solve_info* info) {
+    HostTrace ht;
     hipStream_t s = c->stream;
     const int64_t n = c->topo.n_gamma;
     const size_t nn = (size_t)std::max<int64_t>(n, 1);
@@ -665,6 +670,7 @@ bool gmres_core(abddc_ctx* c, int32_t restart, double rtol, int32_t maxit, doubl
       // scalars the kernels publish straight to the host: two step slots and
       // the restart slot (pinned, device-coherent)
     }
+    ht.mark("gmres: work vectors");
     const auto t0 = std::chrono::steady_clock::now();
     record(c, 13);
     double* V = c->d_V.p;
@@ -679,7 +685,9 @@ bool gmres_core(abddc_ctx* c, int32_t restart, double rtol, int32_t maxit, doubl
       ABDDC_HIP(hipMemcpyAsync(c->d_r.p, c->d_ghat.p, n * sizeof(double), hipMemcpyDeviceToDevice, s));
       launch_dots(c->d_r.p, n, 1, c->d_r.p, n, c->d_partial.p, c->d_nrm.p, s);
       launch_gmres_start(c->d_gst.p, c->d_nrm.p, c->dh_step + 8, s);
+      ht.mark("gmres: initial residual queued");
       read_scalars();
+      ht.mark("gmres: initial residual norm (sync)");
       const double bnorm = h_start[0];
       if (bnorm == 0.0) converged = true;
       const char* genv = std::getenv("ABDDC_GRAPH");

@@ -1,6 +1,7 @@
 // Optional host-side timeline (environment variable ABDDC_HOST_TRACE=1):
-// each mark prints the host time spent since the previous mark, and the
-// minor page faults taken meanwhile, to stderr.
+// each mark prints the host time spent since the previous mark of any trace
+// on the calling thread (one continuous timeline), and the minor page faults
+// taken meanwhile, to stderr.
 // It shows host work and synchronisations that leave the GPU idle.
 #pragma once
 
@@ -14,10 +15,20 @@ namespace abddc {
 
 struct HostTrace {
   bool on;
-  std::chrono::steady_clock::time_point last;
-  long faults = 0;   // minor page faults of the process at the last mark
-  HostTrace() : on(enabled()), last(on ? std::chrono::steady_clock::now() : std::chrono::steady_clock::time_point()) {
-    if (on) faults = minor_faults();
+  HostTrace() : on(enabled()) {
+    if (on && last().time_since_epoch().count() == 0) {
+      last() = std::chrono::steady_clock::now();
+      faults() = minor_faults();
+    }
+  }
+  // the thread's previous mark and the process's minor page faults then
+  static std::chrono::steady_clock::time_point& last() {
+    static thread_local std::chrono::steady_clock::time_point t;
+    return t;
+  }
+  static long& faults() {
+    static thread_local long f = 0;
+    return f;
   }
   static long minor_faults() {
     rusage u{};
@@ -33,9 +44,9 @@ struct HostTrace {
     const auto now = std::chrono::steady_clock::now();
     const long f = minor_faults();
     std::fprintf(stderr, "[host] %-40s %9.1f us %7ld faults\n", what,
-                 std::chrono::duration<double, std::micro>(now - last).count(), f - faults);
-    last = now;
-    faults = f;
+                 std::chrono::duration<double, std::micro>(now - last()).count(), f - faults());
+    last() = now;
+    faults() = f;
   }
 };
 

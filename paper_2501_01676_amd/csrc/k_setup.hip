@@ -51,35 +51,65 @@ __global__ void __launch_bounds__(256) aug_build_kernel(const AugDesc* __restric
   const AugDesc& d = sd;
   const int nB = d.nB, na = 2 * nB, lane = threadIdx.x & 63;
   const int nwv = gridDim.x * (blockDim.x >> 6);
+  // four columns per lane at a time, every load of a group issued before
+  // its stores (the stores could alias the maps as far as the compiler knows)
   for (int i = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); i < na; i += nwv) {
     double* row = d.aug + (size_t)i * na;
     if (i < nB) {
-      // row of coordinate ci: Sbar(ci, am(j)), then W(m, ci) = W_X(m - off, ci - off)
-      // for m in the object of ci
+      // row of rotated coordinate ci: Sbar(ci, am(j)), then W(m, ci) =
+      // W_X(m - off, ci - off) for the m of the object of ci
       const int ci = d.am[i], q = d.slot[ci], off = d.obj_off[q], n = d.obj_n[q];
       const double* srow = d.sbar + (size_t)ci * nB;
       const double* wcol = d.wx + d.obj_w[q] + (ci - off);
-      for (int j = lane; j < na; j += 64) {
-        double v;
-        if (j < nB) {
-          v = srow[d.am[j]];
-        } else {
-          const int m = j - nB;
-          v = (m >= off && m < off + n) ? wcol[(size_t)(m - off) * n] : 0.0;
-        }
-        row[j] = v;
+      for (int j0 = lane; j0 < nB; j0 += 256) {
+        int sc[4];
+        double v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) sc[u] = j0 + 64 * u < nB ? d.am[j0 + 64 * u] : -1;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) v[u] = sc[u] >= 0 ? srow[sc[u]] : 0.0;
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          if (sc[u] >= 0) row[j0 + 64 * u] = v[u];
       }
+      for (int m = lane; m < nB; m += 64)
+        row[nB + m] = (m >= off && m < off + n) ? wcol[(size_t)(m - off) * n] : 0.0;
     } else {
       // row of original coordinate m: -W(m, am(j)) inside its object, then zeros
       const int m = i - nB, q = d.slot[m], off = d.obj_off[q], n = d.obj_n[q];
       const double* wrow = d.wx + d.obj_w[q] + (size_t)(m - off) * n;
-      for (int j = lane; j < na; j += 64) {
-        double v = 0.0;
-        if (j < nB) {
-          const int c = d.am[j];
-          if (c >= off && c < off + n) v = -wrow[c - off];
-        }
-        row[j] = v;
+      for (int j0 = lane; j0 < nB; j0 += 256) {
+        int cc[4];
+        double v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) cc[u] = j0 + 64 * u < nB ? d.am[j0 + 64 * u] : -1;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) v[u] = (cc[u] >= off && cc[u] < off + n) ? -wrow[cc[u] - off] : 0.0;
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          if (cc[u] >= 0) row[j0 + 64 * u] = v[u];
+      }
+      for (int j = nB + lane; j < na; j += 64) row[j] = 0.0;
+    }
+  }
+}
+
+// LinesDesc: one wave per copied row (rows = 1, lanes along the row) or per
+// matrix row (rows = 0, lanes over the copied columns of that row).
+__global__ void __launch_bounds__(256) copy_lines_kernel(const LinesDesc* __restrict__ descs) {
+  const LinesDesc d = descs[blockIdx.y];
+  const int lane = threadIdx.x & 63;
+  const int nwv = gridDim.x * (blockDim.x >> 6);
+  const int nr = d.rows ? d.nidx : d.n;
+  for (int r = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); r < nr; r += nwv) {
+    if (d.rows) {
+      const size_t o = (size_t)d.idx[r] * d.n;
+      for (int c = lane; c < d.n; c += 64) d.dst[o + c] = d.src[o + c];
+    } else {
+      const size_t o = (size_t)r * d.n;
+      for (int q = lane; q < d.nidx; q += 64) {
+        const int c = d.idx[q];
+        d.dst[o + c] = d.src[o + c];
       }
     }
   }
@@ -270,6 +300,17 @@ void aug_build_batched(const std::vector<AugDesc>& descs, hipStream_t s) {
   const AugDesc* dd = Arena::for_stream(s).put(descs);
   const int gx = std::min((maxr + 3) / 4, 1024);   // four rows (waves) per workgroup
   aug_build_kernel<<<dim3(gx, descs.size()), 256, 0, s>>>(dd);
+  ABDDC_HIP(hipGetLastError());
+}
+
+void copy_lines_batched(const std::vector<LinesDesc>& descs, hipStream_t s) {
+  if (descs.empty()) return;
+  int maxr = 0;
+  for (auto& d : descs) maxr = std::max(maxr, d.rows ? d.nidx : d.n);
+  if (maxr == 0) return;
+  const LinesDesc* dd = Arena::for_stream(s).put(descs);
+  const int gx = std::min((maxr + 3) / 4, 1024);   // four lines (waves) per workgroup
+  copy_lines_kernel<<<dim3(gx, descs.size()), 256, 0, s>>>(dd);
   ABDDC_HIP(hipGetLastError());
 }
 

@@ -272,6 +272,7 @@ void run_setup(abddc_ctx* c) {
       wtot += (int64_t)2 * o.n * (o.subs.size() + 1) * o.n;
     }
     DevBuf<double> wk(std::max<int64_t>(wtot, 1));
+    ht.mark("deluxe: offsets, buffers");
     // descriptors of the faces and edges (objects before the vertices), one
     // slot each, filled in parallel
     const int nfe = nf + ned;
@@ -299,6 +300,7 @@ void run_setup(abddc_ctx* c) {
                                c->dD.p + c->dxoff[(size_t)k * 8 + q], nullptr, nullptr, o.n, o.n, cols, o.n, 1.0};
       }
     });
+    ht.mark("deluxe: descriptors");
     deluxe_build_batched(dd, s);
     partial_lu<double>(pd, c->d_flag.p, s);
     gather_batched(gd, s);
@@ -647,24 +649,43 @@ void run_setup(abddc_ctx* c) {
       for (int sub : T.objects[T.edges[e]].subs) need[sub] = 1;
     ht.mark("face-rotated Bbar^(s) = T_F^T B^(s) T_");
     // face-rotated Bbar^(s) = T_F^T B^(s) T_F on every face block
+    // (Y = B T_F, then Bbar = T_F^T Y; the edge and vertex lines, which the
+    // rotation leaves alone, are copied instead)
     DevBuf<double> Y(c->dB.n), Bbar(c->dB.n);
-    ABDDC_HIP(hipMemcpyAsync(Y.p, c->dB.p, c->dB.n * sizeof(double), hipMemcpyDeviceToDevice, s));
     std::vector<GemmDesc<double>> gc, gr;
+    IntPool lpool;
+    std::vector<size_t> loff(nsub, 0);
+    std::vector<int> lcnt(nsub, 0);
     for (int sub = 0; sub < nsub; ++sub) {
       if (!need[sub]) continue;
       const SubInfo& si = T.sub[sub];
       const int nB = c->nB[sub];
+      std::vector<int32_t> lines;
       for (size_t q = 0; q < si.objs.size(); ++q) {
         const int k = si.objs[q];
-        if (T.objects[k].kind != KIND_FACE) continue;
-        const int f = T.kind_index[k], n = T.objects[k].n, off = si.obj_off[q];
+        const int n = T.objects[k].n, off = si.obj_off[q];
+        if (T.objects[k].kind != KIND_FACE) {
+          for (int l = 0; l < n; ++l) lines.push_back(off + l);
+          continue;
+        }
+        const int f = T.kind_index[k];
         gc.push_back({c->dB.p + c->soff[sub] + off, c->dTF.p + c->tfoff[f], Y.p + c->soff[sub] + off, nB, n, n, nB, n, nB});
         gr.push_back({c->dTF.p + c->tfoff[f], Y.p + c->soff[sub] + (int64_t)off * nB, Bbar.p + c->soff[sub] + (int64_t)off * nB,
                       n, nB, n, n, nB, nB});
       }
+      lcnt[sub] = (int)lines.size();
+      loff[sub] = lpool.add(lines);
+    }
+    lpool.upload(s);
+    std::vector<LinesDesc> lcol, lrow;
+    for (int sub = 0; sub < nsub; ++sub) {
+      if (!need[sub] || lcnt[sub] == 0) continue;
+      lcol.push_back({c->dB.p + c->soff[sub], Y.p + c->soff[sub], lpool.ptr(loff[sub]), lcnt[sub], c->nB[sub], 0});
+      lrow.push_back({Y.p + c->soff[sub], Bbar.p + c->soff[sub], lpool.ptr(loff[sub]), lcnt[sub], c->nB[sub], 1});
     }
     gemm_batched<double>(gc, false, false, 1.0, 0.0, s);
-    ABDDC_HIP(hipMemcpyAsync(Bbar.p, Y.p, c->dB.n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    copy_lines_batched(lcol, s);
+    copy_lines_batched(lrow, s);
     gemm_batched<double>(gr, true, false, 1.0, 0.0, s);
 
     ht.mark("stage 1: per subdomain eliminate all f");
@@ -917,10 +938,7 @@ void run_setup(abddc_ctx* c) {
   ht.mark("change of basis + local");
   // -------------------------------------------- change of basis + local
   record(c, 5);
-  // Sbar starts as a copy of S (vertex blocks stay as they are): queued
-  // first, so the device copies while the host builds the maps below
   DevBuf<double> Y(c->dS.n);
-  ABDDC_HIP(hipMemcpyAsync(Y.p, c->dS.p, c->dS.n * sizeof(double), hipMemcpyDeviceToDevice, s));
   // local coordinate order per object: [primal, dual]; Pi / Delta positions
   std::vector<std::vector<int32_t>> Pi(nsub), Dl(nsub), Pid(nsub);
   host_parallel_for(nsub, 8, [&](int64_t sb, int64_t se) {
@@ -981,13 +999,30 @@ void run_setup(abddc_ctx* c) {
   c->dU.alloc(std::max<int64_t>(ut, 1));
   {
     ht.mark("Sbar = T^T S T (face and edge blocks)");
-    // Sbar = T^T S T (face and edge blocks), on the copy of S queued above
+    // Sbar = T^T S T: Y = S T, then Sbar = T^T Y on the face and edge
+    // blocks; the vertex lines, which the rotation leaves alone, are copied
     std::vector<GemmDesc<double>> gc, gr, wg;
     std::vector<SetDesc> vset;
     IntPool vp;
     std::vector<int32_t> zero1(1, 0);
     const size_t z_off = vp.add(zero1);
+    std::vector<size_t> voff(nsub);
+    std::vector<int> vcnt(nsub);
+    for (int sub = 0; sub < nsub; ++sub) {
+      std::vector<int32_t> lines;
+      const SubInfo& si = T.sub[sub];
+      for (size_t q = 0; q < si.objs.size(); ++q)
+        if (T.objects[si.objs[q]].kind == KIND_VERTEX) lines.push_back(si.obj_off[q]);
+      vcnt[sub] = (int)lines.size();
+      voff[sub] = vp.add(lines);
+    }
     vp.upload(s);
+    std::vector<LinesDesc> lcol, lrow;
+    for (int sub = 0; sub < nsub; ++sub) {
+      if (vcnt[sub] == 0) continue;
+      lcol.push_back({c->dS.p + c->soff[sub], Y.p + c->soff[sub], vp.ptr(voff[sub]), vcnt[sub], c->nB[sub], 0});
+      lrow.push_back({Y.p + c->soff[sub], Sb.p + c->soff[sub], vp.ptr(voff[sub]), vcnt[sub], c->nB[sub], 1});
+    }
     for (int sub = 0; sub < nsub; ++sub) {
       const SubInfo& si = T.sub[sub];
       const int nB = c->nB[sub];
@@ -1008,7 +1043,8 @@ void run_setup(abddc_ctx* c) {
       }
     }
     gemm_batched<double>(gc, false, false, 1.0, 0.0, s);
-    ABDDC_HIP(hipMemcpyAsync(Sb.p, Y.p, c->dS.n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    copy_lines_batched(lcol, s);
+    copy_lines_batched(lrow, s);
     gemm_batched<double>(gr, true, false, 1.0, 0.0, s);
     gemm_batched<double>(wg, false, false, 1.0, 0.0, s);   // W_X = D_X T_X
     set_batched(vset, s);                                    // vertices: 1/|n(V)|

@@ -60,6 +60,15 @@ struct AugDesc {
   int32_t nB;
 };
 
+// Rows (rows = 1) or columns (rows = 0) idx[0..nidx) of an n x n matrix
+// (ld n) copied from src to dst: the lines a block rotation leaves as they are.
+struct LinesDesc {
+  const double* src;
+  double* dst;
+  const int32_t* idx;
+  int32_t nidx, n, rows;
+};
+
 struct CoarseAddDesc {
   const double* src;
   const int32_t* gid;
@@ -78,6 +87,7 @@ void convert_f64_f32(const double* src, float* dst, int64_t n, hipStream_t s);
 void convert_f32_f64(const float* src, double* dst, int64_t n, hipStream_t s);
 void deluxe_build_batched(const std::vector<DeluxeDesc>& d, hipStream_t s);
 void aug_build_batched(const std::vector<AugDesc>& d, hipStream_t s);
+void copy_lines_batched(const std::vector<LinesDesc>& d, hipStream_t s);
 void edge_assemble_batched(const std::vector<EdgeAsmDesc>& d, hipStream_t s);
 void edge_old_metric_batched(const std::vector<EdgeOldDesc>& d, hipStream_t s);
 void coarse_add_batched(const std::vector<CoarseAddDesc>& d, double* SPi, int64_t ldc, hipStream_t s);

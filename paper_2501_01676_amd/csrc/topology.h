@@ -48,8 +48,6 @@ struct Topology {
   int ne[3], nn[3];
   int64_t n_nodes, n_elem, n_dof, n_gamma;
   int n_sub;
-  std::vector<int64_t> dof_of_node;   // -1 for Dirichlet nodes
-  std::vector<int64_t> iface_of_node; // -1 for non-interface nodes
   std::vector<Object> objects;
   std::vector<int> faces, edges, vertices;   // indices into objects
   std::vector<int> kind_index;               // position of object within its kind
@@ -65,6 +63,13 @@ struct Topology {
   void build_partition(const int32_t* part, int n_parts);
   bool general = false;         // built by build_partition
   int64_t node_id(int64_t ix, int64_t iy, int64_t iz) const { return ix + nn[0] * (iy + (int64_t)nn[1] * iz); }
+  // global dof of node v: the free nodes (the grid minus its boundary)
+  // numbered by node id; -1 for a Dirichlet node
+  int64_t dof_of(int64_t v) const {
+    const int64_t ix = v % nn[0], iy = (v / nn[0]) % nn[1], iz = v / ((int64_t)nn[0] * nn[1]);
+    if (ix == 0 || iy == 0 || iz == 0 || ix == nn[0] - 1 || iy == nn[1] - 1 || iz == nn[2] - 1) return -1;
+    return (ix - 1) + (int64_t)(nn[0] - 2) * ((iy - 1) + (int64_t)(nn[1] - 2) * (iz - 1));
+  }
   int sub_id(int sx, int sy, int sz) const { return sx + nsub[0] * (sy + nsub[1] * sz); }
 };
 

@@ -58,19 +58,8 @@ void Topology::build_objects() {
     }
     for (int c = 1; c < nsub[a]; ++c) klo[a][2 * c - 1] = khi[a][2 * c - 1] = cuts[a][c];
   }
-  // free nodes: the grid minus its boundary, numbered by node id
-  dof_of_node.assign(n_nodes, -1);
-  host_parallel_for(std::max(nn[2] - 2, 0), 4, [&](int64_t b, int64_t e) {
-    for (int iz = 1 + (int)b; iz < 1 + (int)e; ++iz)
-      for (int iy = 1; iy < nn[1] - 1; ++iy) {
-        const int64_t base = node_id(0, iy, iz);
-        const int64_t d0 = (int64_t)(nn[0] - 2) * ((iy - 1) + (int64_t)(nn[1] - 2) * (iz - 1)) - 1;
-        for (int ix = 1; ix < nn[0] - 1; ++ix) dof_of_node[base + ix] = d0 + ix;
-      }
-  });
+  // free nodes: the grid minus its boundary, numbered by node id (dof_of)
   n_dof = (int64_t)(nn[0] - 2) * (nn[1] - 2) * (nn[2] - 2);
-  ht.mark("topology: free-node numbering");
-  iface_of_node.assign(n_nodes, -1);
   objects.clear();
   const int nk[3] = {2 * nsub[0] - 1, 2 * nsub[1] - 1, 2 * nsub[2] - 1};
   // key triples in interface order: faces, edges, vertices, each by their
@@ -123,17 +112,11 @@ void Topology::build_objects() {
     lst.push_back((int)k);
   }
   n_gamma = g;
-  host_parallel_for((int64_t)objects.size(), 64, [&](int64_t b, int64_t e) {
-    for (int64_t k = b; k < e; ++k) {
-      const Object& o = objects[k];
-      for (int q = 0; q < o.n; ++q) iface_of_node[o.nodes[q]] = o.gstart + q;
-    }
-  });
 
-  ht.mark("topology: interface numbering");
   sub.assign(n_sub, SubInfo());
   for (size_t k = 0; k < objects.size(); ++k)
     for (int s : objects[k].subs) sub[s].objs.push_back((int)k);
+  ht.mark("topology: interface numbering, object lists");
   host_parallel_for(n_sub, 8, [&](int64_t b, int64_t e) {
     for (int s = (int)b; s < (int)e; ++s) {
       const int sx = s % nsub[0], sy = (s / nsub[0]) % nsub[1], sz = s / (nsub[0] * nsub[1]);
@@ -180,17 +163,12 @@ void Topology::build_partition(const int32_t* part, int n_parts) {
     ++boxes_of[part[e]];
   }
   for (int p = 0; p < n_parts; ++p) ABDDC_REQUIRE(boxes_of[p] > 0, ABDDC_EINVAL, "a part holds no box");
-  dof_of_node.assign(n_nodes, -1);
-  for (int iz = 1; iz < nn[2] - 1; ++iz)
-    for (int iy = 1; iy < nn[1] - 1; ++iy)
-      for (int ix = 1; ix < nn[0] - 1; ++ix)
-        dof_of_node[node_id(ix, iy, iz)] = (ix - 1) + (int64_t)(nn[0] - 2) * ((iy - 1) + (int64_t)(nn[1] - 2) * (iz - 1));
   n_dof = (int64_t)(nn[0] - 2) * (nn[1] - 2) * (nn[2] - 2);
   // sharing set of every free node: the sorted distinct parts of its boxes
   std::vector<std::array<int, 8>> sets(n_nodes);
   std::vector<uint8_t> nset(n_nodes, 0);
   for (int64_t v = 0; v < n_nodes; ++v) {
-    if (dof_of_node[v] < 0) continue;
+    if (dof_of(v) < 0) continue;
     const int ix = (int)(v % nn[0]), iy = (int)((v / nn[0]) % nn[1]), iz = (int)(v / ((int64_t)nn[0] * nn[1]));
     std::array<int, 8>& S = sets[v];
     int k = 0;
@@ -215,7 +193,7 @@ void Topology::build_partition(const int32_t* part, int n_parts) {
   std::vector<char> seen(n_nodes, 0);
   std::vector<int64_t> stack;
   for (int64_t v0 = 0; v0 < n_nodes; ++v0) {
-    if (dof_of_node[v0] < 0 || nset[v0] < 2 || seen[v0]) continue;
+    if (nset[v0] < 2 || seen[v0]) continue;   // Dirichlet nodes have no set
     Object o;
     o.subs.assign(sets[v0].begin(), sets[v0].begin() + nset[v0]);
     stack.assign(1, v0);
@@ -231,7 +209,7 @@ void Topology::build_partition(const int32_t* part, int n_parts) {
             const int qx = ix + dx, qy = iy + dy, qz = iz + dz;
             if (qx < 0 || qy < 0 || qz < 0 || qx >= nn[0] || qy >= nn[1] || qz >= nn[2]) continue;
             const int64_t w = node_id(qx, qy, qz);
-            if (seen[w] || dof_of_node[w] < 0 || !same_set(v0, w)) continue;
+            if (seen[w] || nset[w] == 0 || !same_set(v0, w)) continue;
             seen[w] = 1;
             stack.push_back(w);
           }
@@ -258,12 +236,10 @@ void Topology::build_partition(const int32_t* part, int n_parts) {
   edges.clear();
   vertices.clear();
   kind_index.assign(objects.size(), 0);
-  iface_of_node.assign(n_nodes, -1);
   int64_t g = 0;
   for (size_t k = 0; k < objects.size(); ++k) {
     Object& o = objects[k];
     o.gstart = g;
-    for (int q = 0; q < o.n; ++q) iface_of_node[o.nodes[q]] = g + q;
     g += o.n;
     std::vector<int>& lst = o.kind == KIND_FACE ? faces : (o.kind == KIND_EDGE ? edges : vertices);
     kind_index[k] = (int)lst.size();
@@ -285,7 +261,7 @@ void Topology::build_partition(const int32_t* part, int n_parts) {
     }
   }
   for (int64_t v = 0; v < n_nodes; ++v)
-    if (dof_of_node[v] >= 0 && nset[v] == 1) sub[sets[v][0]].interior.push_back(v);
+    if (nset[v] == 1) sub[sets[v][0]].interior.push_back(v);   // (0 for Dirichlet nodes)
   for (size_t k = 0; k < objects.size(); ++k)
     for (int s : objects[k].subs) sub[s].objs.push_back((int)k);
   for (int s = 0; s < n_sub; ++s) {
