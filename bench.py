@@ -12,7 +12,8 @@ recovery), with the coefficient arrays already resident in HBM.
 Prints one JSON line.  `roofline` is the tracked kernel class with the
 largest device time per solve, timed live over the timed steps with HIP
 events that each launch of the class is stamped with on its stream.  The
-warmup steps time every class and pick that one; the timed steps time only
+warmup steps time every class and pick that one (the first warmup, which
+also tunes and allocates, left out); the timed steps time only
 it (a timed launch adds a few microseconds before the next kernel), and
 `kernels_tracked` takes the other classes from two untimed solves that
 follow (`--kernel-stats all` times every class in the timed steps).  `local_solve_tflops` is the
@@ -321,8 +322,10 @@ def main():
         r = step(want_flops=flops is None)
         flops = r[6] or flops
         warm.append(r)
-    # the class with the largest device time over the warmup solves
-    dom_cls = max(TRACKED, key=lambda c: sum(r[2][c][0] for r in warm)) if warm else None
+    # the class with the largest device time over the warmup solves after
+    # the first (which also tunes and allocates)
+    steady = warm[1:] if len(warm) > 1 else warm
+    dom_cls = max(TRACKED, key=lambda c: sum(r[2][c][0] for r in steady)) if steady else None
     timed_mask = all_classes if args.kernel_stats == "all" or dom_cls is None else 1 << dom_cls
     api.set_kernel_stats(timed_mask)
     torch.cuda.synchronize()

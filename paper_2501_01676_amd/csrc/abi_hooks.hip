@@ -7,6 +7,7 @@
 #include <unordered_map>
 #include <mutex>
 #include <string>
+#include <tuple>
 
 #include "arena.h"
 #include "guard.h"
@@ -36,21 +37,17 @@ void* hooked_alloc(const DevAlloc& h, size_t bytes) {
 }
 
 thread_local hipStream_t g_stream = nullptr;
-thread_local bool g_stream_idle = false;
 
 namespace {
-// A cached block remembers the stream whose work may still use it and an
-// event recorded there at release; it is reused without waiting on that same
-// stream (stream order protects it) and after the event elsewhere.
-struct Block {
-  void* p;
-  hipStream_t stream;
-  hipEvent_t ev;
-};
+// A cached block is kept under the stream whose work may still use it.  On
+// that same stream it is reused at once (stream order protects it); another
+// stream takes it only behind an event recorded on the first one at that
+// moment, which it waits for on the device.
 struct Cache {
   std::mutex mu;
-  std::multimap<std::pair<int, size_t>, Block> free_blocks;  // (device, block size)
-  std::unordered_map<void*, size_t> block_size;              // every block ever allocated
+  // (device, releasing stream, block size) -> block
+  std::multimap<std::tuple<int, hipStream_t, size_t>, void*> free_blocks;
+  std::unordered_map<void*, size_t> block_size;   // every block ever allocated
 };
 Cache& cache() {
   static Cache* c = new Cache();  // intentionally never destroyed
@@ -85,29 +82,49 @@ void* cache_alloc(size_t bytes) {
   int dev = 0;
   ABDDC_HIP(hipGetDevice(&dev));
   const size_t r = round_size(bytes);
+  const size_t rmax = 2 * r + (size_t(1) << 20);   // best fit wasting at most r + 1 MiB
   Cache& c = cache();
-  Block blk{nullptr, nullptr, nullptr};
+  void* blk = nullptr;
+  hipStream_t from = nullptr;
   {
-    // best fit: the smallest cached block of at least r bytes, if it wastes
-    // at most r + 1 MiB
     std::lock_guard<std::mutex> g(c.mu);
-    auto it = c.free_blocks.lower_bound({dev, r});
-    if (it != c.free_blocks.end() && it->first.first == dev && it->first.second <= 2 * r + (size_t(1) << 20)) {
+    auto it = c.free_blocks.lower_bound({dev, g_stream, r});
+    if (it != c.free_blocks.end() && std::get<0>(it->first) == dev && std::get<1>(it->first) == g_stream &&
+        std::get<2>(it->first) <= rmax) {
       blk = it->second;
+      from = g_stream;
       c.free_blocks.erase(it);
+    } else {
+      // the smallest fitting block released on another stream of the device
+      auto best = c.free_blocks.end();
+      for (auto jt = c.free_blocks.lower_bound({dev, nullptr, 0}); jt != c.free_blocks.end() && std::get<0>(jt->first) == dev;
+           ++jt) {
+        const size_t sz = std::get<2>(jt->first);
+        if (std::get<1>(jt->first) != g_stream && sz >= r && sz <= rmax &&
+            (best == c.free_blocks.end() || sz < std::get<2>(best->first)))
+          best = jt;
+      }
+      if (best != c.free_blocks.end()) {
+        blk = best->second;
+        from = std::get<1>(best->first);
+        c.free_blocks.erase(best);
+      }
     }
   }
   count_alloc(dev, bytes);
-  if (blk.p) {
-    if (blk.ev) {
-      if (blk.stream != g_stream) {
-        HostTrace ht;
-        ABDDC_HIP(hipEventSynchronize(blk.ev));
-        ht.mark("allocator: wait for a block released on another stream");
+  if (blk) {
+    if (from != g_stream) {
+      // the work queued on the releasing stream so far comes first
+      hipEvent_t ev = nullptr;
+      bool ok = hipEventCreateWithFlags(&ev, hipEventDisableTiming) == hipSuccess;
+      ok = ok && hipEventRecord(ev, from) == hipSuccess && hipStreamWaitEvent(g_stream, ev, 0) == hipSuccess;
+      if (ev) (void)hipEventDestroy(ev);
+      if (!ok) {
+        (void)hipGetLastError();
+        ABDDC_HIP(hipDeviceSynchronize());
       }
-      (void)hipEventDestroy(blk.ev);
     }
-    return blk.p;
+    return blk;
   }
   void* p = nullptr;
   HostTrace ht;
@@ -118,10 +135,9 @@ void* cache_alloc(size_t bytes) {
     ABDDC_HIP(hipDeviceSynchronize());
     std::lock_guard<std::mutex> g(c.mu);
     for (auto it = c.free_blocks.begin(); it != c.free_blocks.end();) {
-      if (it->first.first == dev) {
-        c.block_size.erase(it->second.p);
-        (void)hipFree(it->second.p);
-        if (it->second.ev) (void)hipEventDestroy(it->second.ev);
+      if (std::get<0>(it->first) == dev) {
+        c.block_size.erase(it->second);
+        (void)hipFree(it->second);
         it = c.free_blocks.erase(it);
       } else {
         ++it;
@@ -143,23 +159,10 @@ void cache_free(void* p, size_t bytes) {
   if (!p) return;
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return;
-  Block blk{p, g_stream, nullptr};
-  if (g_stream_idle) {
-    // the caller has synchronised the stream: nothing can still use the block
-  } else if (hipEventCreateWithFlags(&blk.ev, hipEventDisableTiming) == hipSuccess) {
-    if (hipEventRecord(blk.ev, g_stream) != hipSuccess) {
-      (void)hipEventDestroy(blk.ev);
-      blk.ev = nullptr;
-      (void)hipStreamSynchronize(g_stream);
-    }
-  } else {
-    blk.ev = nullptr;
-    (void)hipStreamSynchronize(g_stream);
-  }
   Cache& c = cache();
   std::lock_guard<std::mutex> g(c.mu);
   auto sz = c.block_size.find(p);
-  c.free_blocks.insert({{dev, sz != c.block_size.end() ? sz->second : round_size(bytes)}, blk});
+  c.free_blocks.insert({{dev, g_stream, sz != c.block_size.end() ? sz->second : round_size(bytes)}, p});
 }
 }  // namespace abddc
 

@@ -24,6 +24,7 @@
 
 namespace abddc {
 void run_setup(abddc_ctx* c);
+void setup_final_check(abddc_ctx* c);
 void plan_face_elimination(abddc_ctx* c, hipStream_t s);
 }
 
@@ -217,7 +218,8 @@ void setup_with(abddc_ctx* c, const abddc_options& o) {
   }
   HostTrace ht;
   run_setup(c);
-  ht.mark("setup: stage buffers released");
+  ht.mark("setup: queued, stage buffers released");
+  setup_final_check(c);
   c->kstats.resolve();
   ht.mark("setup: kernel statistics resolved");
   c->phase[2] = ev_ms(c, 2, 3);
@@ -919,11 +921,13 @@ extern "C" void abddc_destroy(abddc_ctx* c) {
   if (!c) return;
   (void)hipSetDevice(c->device);
   StreamScope ss(c->stream);
+  HostTrace ht;
   (void)hipStreamSynchronize(c->stream);
+  ht.mark("destroy: stream drained");
   if (c->step_exec) (void)hipGraphExecDestroy(c->step_exec);
   if (c->step_graph) (void)hipGraphDestroy(c->step_graph);
+  ht.mark("destroy: Arnoldi-step graph");
   release_resources(c);
-  g_stream_idle = true;   // the stream has drained: the buffers go back to the cache without events
   delete c;
-  g_stream_idle = false;
+  ht.mark("destroy: buffers released");
 }

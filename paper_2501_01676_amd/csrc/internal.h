@@ -42,9 +42,6 @@ void staged_upload(void* dst, const void* src, size_t bytes, hipStream_t s);
 // Stream on which the current entry point works (released blocks are tagged
 // with it).
 extern thread_local hipStream_t g_stream;
-// Set while every block released on this thread is known idle (its stream
-// synchronised): releases then need no event.
-extern thread_local bool g_stream_idle;
 struct StreamScope {
   hipStream_t prev;
   explicit StreamScope(hipStream_t s) : prev(g_stream) { g_stream = s; }

@@ -1281,10 +1281,16 @@ void run_setup(abddc_ctx* c) {
     }
     gemv_tune<double>(c->opC, "coarse", c->device, c->dSPinv.p, c->d_bpi.p, nullptr, c->d_xpi.p, s);
     ht.mark("metadata uploaded");
-    require_flag_clean(c, "local constrained / coarse factorisation");
-    ht.mark("final flag check (sync)");
   }
   record(c, 8);
+  // the stage buffers go back to the cache here, in stream order, before
+  // the caller waits for the flag (setup_final_check)
+}
+
+void setup_final_check(abddc_ctx* c) {
+  HostTrace ht;
+  require_flag_clean(c, "local constrained / coarse factorisation");
+  ht.mark("final flag check (sync)");
 }
 
 }  // namespace abddc
