@@ -21,6 +21,7 @@
 #include <map>
 #include <mutex>
 
+#include "host_pool.h"
 #include "htrace.h"
 #include "internal.h"
 
@@ -126,11 +127,22 @@ class Arena {
     std::memcpy(desc_.host() + off, src, bytes);
     return desc_.dev() + off;
   }
-  // Stream-ordered upload into caller-owned device memory through the ring.
+  // Stream-ordered upload into caller-owned device memory through the ring
+  // (the staging copy of a large upload split over the host pool).
   void upload(void* dst, const void* src, size_t bytes) {
     const size_t off = up_.reserve(bytes);
-    std::memcpy(up_.host() + off, src, bytes);
-    ABDDC_HIP(hipMemcpyAsync(dst, up_.host() + off, bytes, hipMemcpyHostToDevice, s_));
+    char* stage = up_.host() + off;
+    constexpr size_t PIECE = size_t(128) << 10;
+    if (bytes >= 4 * PIECE) {
+      const int64_t np = (int64_t)((bytes + PIECE - 1) / PIECE);
+      host_parallel_for(np, 1, [&](int64_t b, int64_t e) {
+        const size_t lo = (size_t)b * PIECE, hi = std::min(bytes, (size_t)e * PIECE);
+        std::memcpy(stage + lo, static_cast<const char*>(src) + lo, hi - lo);
+      });
+    } else {
+      std::memcpy(stage, src, bytes);
+    }
+    ABDDC_HIP(hipMemcpyAsync(dst, stage, bytes, hipMemcpyHostToDevice, s_));
   }
   template <class T>
   T* put(const std::vector<T>& v) {

@@ -113,15 +113,27 @@ void Topology::build_objects() {
   }
   n_gamma = g;
 
+  // object of each key triple (-1: no object)
+  std::vector<int> obj_of_key((size_t)nk[0] * nk[1] * nk[2], -1);
+  for (size_t q = 0; q < keys.size(); ++q)
+    obj_of_key[keys[q][0] + (size_t)nk[0] * (keys[q][1] + (size_t)nk[1] * keys[q][2])] = (int)q;
   sub.assign(n_sub, SubInfo());
-  for (size_t k = 0; k < objects.size(); ++k)
-    for (int s : objects[k].subs) sub[s].objs.push_back((int)k);
-  ht.mark("topology: interface numbering, object lists");
+  ht.mark("topology: interface numbering");
   host_parallel_for(n_sub, 8, [&](int64_t b, int64_t e) {
     for (int s = (int)b; s < (int)e; ++s) {
       const int sx = s % nsub[0], sy = (s / nsub[0]) % nsub[1], sz = s / (nsub[0] * nsub[1]);
       const int sc[3] = {sx, sy, sz};
       SubInfo& si = sub[s];
+      // the objects of subdomain s: the key triples with every key in
+      // {2 s_a - 1, 2 s_a, 2 s_a + 1}, in interface order
+      for (int kz = 2 * sz - 1; kz <= 2 * sz + 1; ++kz)
+        for (int ky = 2 * sy - 1; ky <= 2 * sy + 1; ++ky)
+          for (int kx = 2 * sx - 1; kx <= 2 * sx + 1; ++kx) {
+            if (kx < 0 || ky < 0 || kz < 0 || kx >= nk[0] || ky >= nk[1] || kz >= nk[2]) continue;
+            const int q = obj_of_key[kx + (size_t)nk[0] * (ky + (size_t)nk[1] * kz)];
+            if (q >= 0) si.objs.push_back(q);
+          }
+      std::sort(si.objs.begin(), si.objs.end());
       for (int a = 0; a < 3; ++a) {
         si.ebox[a][0] = cuts[a][sc[a]];
         si.ebox[a][1] = cuts[a][sc[a] + 1];

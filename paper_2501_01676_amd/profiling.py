@@ -48,18 +48,22 @@ def stats_table(stats_csv, steps, top=15):
 
 
 def _per_dispatch(counter_csv):
-    out = []
-    for r in csv.DictReader(open(counter_csv)):
-        out.append((short_name(r["Kernel_Name"]), float(r["Counter_Value"])))
-    return out
+    """(kernel, counter value) per dispatch, in dispatch order."""
+    rows = list(csv.DictReader(open(counter_csv)))
+    if rows and "Dispatch_Id" in rows[0]:
+        rows.sort(key=lambda r: int(r["Dispatch_Id"]))
+    return [(short_name(r["Kernel_Name"]), float(r["Counter_Value"])) for r in rows]
 
 
 def calibration(values, probe_bytes):
-    """bytes per counter unit from the three probe copies (the largest
-    copyBuffer dispatches)."""
-    probe = sorted(v for k, v in values if "copyBuffer" in k)[-3:]
+    """bytes per counter unit from the three probe copies: the last three
+    copyBuffer dispatches (bench.py --copy-probe runs them after every
+    solve), which must agree with each other."""
+    probe = [v for k, v in values if "copyBuffer" in k][-3:]
     if len(probe) < 3:
         raise SystemExit("copy probe dispatches not found")
+    if max(probe) > 1.05 * min(probe):
+        raise SystemExit(f"the last three copies disagree ({probe}): not the probe")
     return probe_bytes / statistics.mean(probe)
 
 
@@ -129,7 +133,9 @@ def main():
     args = ap.parse_args()
     if args.cmd_name == "stats":
         text = (f"# {args.title}\n\nCommand:\n\n```\n{args.cmd}\n```\n\n"
-                f"Per solve (the run's solves, warmup included, divide the totals):\n\n"
+                f"Per solve: the totals divided by {args.steps:g}, every solve the run made (bench.py: the "
+                f"warmup solves, the timed ones and the two untimed solves that time the other kernel "
+                f"classes):\n\n"
                 f"{stats_table(args.stats_csv, args.steps)}\n")
     else:
         t = traffic(args.fetch_csv, args.write_csv, args.kernel, args.probe_bytes, args.names)
