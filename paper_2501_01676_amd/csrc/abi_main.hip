@@ -351,6 +351,26 @@ extern "C" int abddc_assemble(const abddc_problem* prob, const abddc_device* dev
       launch_elem(P, c->d_nu.p, F, Ae.p, Fe.p, s);
     }
 
+    // box partitions: the dense local matrices (order n_loc = the free nodes
+    // of the subdomain's box, one extra column) are sized from the cuts
+    // alone, so their zero fill runs beside the host's topology and maps
+    int64_t at_early = -1;
+    if (!prob->part) {
+      at_early = 0;
+      for (int sz = 0; sz < T.nsub[2]; ++sz)
+        for (int sy = 0; sy < T.nsub[1]; ++sy)
+          for (int sx = 0; sx < T.nsub[0]; ++sx) {
+            const int sc[3] = {sx, sy, sz};
+            int64_t nl = 1;
+            for (int a = 0; a < 3; ++a) {
+              const int lo = std::max(T.cuts[a][sc[a]], 1), hi = std::min(T.cuts[a][sc[a] + 1], T.nn[a] - 2);
+              nl *= std::max(0, hi - lo + 1);
+            }
+            at_early += nl * (nl + 1);
+          }
+      c->dA.alloc(std::max<int64_t>(at_early, 1));
+      c->dA.zero(s);
+    }
     ht.mark("assemble: coefficients, element kernel queued");
     if (prob->part) {
       T.build_partition(prob->part, prob->n_parts);
@@ -453,8 +473,11 @@ extern "C" int abddc_assemble(const abddc_problem* prob, const abddc_device* dev
     c->d_iface_dof = to_device(iface_dof, s);
     ht.mark("assemble: uploads");
     // -------------------------------------------- element matrices + scatter
-    c->dA.alloc(std::max<int64_t>(at, 1));
-    c->dA.zero(s);
+    if (at_early < 0) {
+      c->dA.alloc(std::max<int64_t>(at, 1));
+      c->dA.zero(s);
+    }
+    ABDDC_REQUIRE(at_early < 0 || at_early == at, ABDDC_EINVAL, "internal: local matrix sizes from the cuts disagree");
     {
       DevBuf<int32_t> d_part;
       if (prob->part) d_part = to_device(std::vector<int32_t>(prob->part, prob->part + T.n_elem), s);

@@ -317,6 +317,75 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) g
                        tj * TILE, As, Bs);
 }
 
+// C = alpha op(A) op(B) + beta C for thin products: k <= THIN and either
+// n <= THIN ("tall") or m <= THIN ("wide"), where a 64 x 64 MFMA tile would
+// leave most of its lanes idle (an interface edge of 7 dofs).
+//   tall: a workgroup takes THIN_ROWS rows of C; op(A)'s rows (k entries
+//         each) and op(B) (k x n) are staged in LDS, so a wave's loads cover
+//         several rows of contiguous entries, and one thread per entry of C
+//         writes the rows back;
+//   wide: one thread per column of C, all its m rows, with op(A) (m x k)
+//         staged in LDS and op(B)'s column read coalesced across threads.
+// Safe in place when C aliases op(A)'s rows (tall) or op(B)'s columns
+// (wide): a workgroup (thread) reads what it overwrites before it writes it.
+constexpr int THIN = 32;
+constexpr int THIN_ROWS = 64;
+
+template <class T, bool TA, bool TB>
+__global__ void __launch_bounds__(256) gemm_thin_kernel(const GemmDesc<T>* __restrict__ descs, int nd, T alpha,
+                                                        T beta) {
+  __shared__ T As[THIN_ROWS][THIN + 1];
+  __shared__ T Bs[THIN][THIN + 1];
+  for (int z = blockIdx.y; z < nd; z += gridDim.y) {
+    const GemmDesc<T> d = descs[z];
+    const bool tall = d.n <= THIN;
+    const int span = tall ? THIN_ROWS : (int)blockDim.x;   // rows (tall) or columns (wide) per workgroup
+    const int len = tall ? d.m : d.n, base = blockIdx.x * span;
+    if (base >= len) continue;   // the same for the whole workgroup
+    __syncthreads();             // the previous descriptor's tiles are no longer read
+    if (tall) {
+      const int rows = min(THIN_ROWS, d.m - base);
+      for (int q = threadIdx.x; q < rows * d.k; q += blockDim.x) {
+        const int r = q / d.k, kk = q % d.k;
+        As[r][kk] = TA ? d.A[(size_t)kk * d.lda + base + r] : d.A[(size_t)(base + r) * d.lda + kk];
+      }
+      for (int q = threadIdx.x; q < d.k * d.n; q += blockDim.x) {
+        const int kk = q / d.n, c = q % d.n;
+        Bs[kk][c] = TB ? d.B[(size_t)c * d.ldb + kk] : d.B[(size_t)kk * d.ldb + c];
+      }
+      __syncthreads();
+      for (int q = threadIdx.x; q < rows * d.n; q += blockDim.x) {
+        const int r = q / d.n, c = q % d.n;
+        T acc = T(0);
+        for (int kk = 0; kk < d.k; ++kk) acc += As[r][kk] * Bs[kk][c];
+        T* cp = d.C + (size_t)(base + r) * d.ldc + c;
+        *cp = beta != T(0) ? alpha * acc + beta * *cp : alpha * acc;
+      }
+    } else {
+      for (int q = threadIdx.x; q < d.m * d.k; q += blockDim.x) {
+        const int r = q / d.k, kk = q % d.k;
+        Bs[r][kk] = TA ? d.A[(size_t)kk * d.lda + r] : d.A[(size_t)r * d.lda + kk];
+      }
+      __syncthreads();
+      const int i = base + threadIdx.x;
+      if (i < len) {
+        T v[THIN];
+#pragma unroll
+        for (int kk = 0; kk < THIN; ++kk)
+          v[kk] = kk < d.k ? (TB ? d.B[(size_t)i * d.ldb + kk] : d.B[(size_t)kk * d.ldb + i]) : T(0);
+        for (int r = 0; r < d.m; ++r) {
+          T acc = T(0);
+#pragma unroll
+          for (int kk = 0; kk < THIN; ++kk)
+            if (kk < d.k) acc += Bs[r][kk] * v[kk];
+          T* cp = d.C + (size_t)r * d.ldc + i;
+          *cp = beta != T(0) ? alpha * acc + beta * *cp : alpha * acc;
+        }
+      }
+    }
+  }
+}
+
 // --------------------------------------------------------------- partial LU
 template <class T>
 __device__ inline T read_lane(T v, int lane);
@@ -1094,20 +1163,44 @@ void partial_lu(const std::vector<PluDesc<T>>& descs_in, int* dflag, hipStream_t
 }
 
 template <class T>
-void gemm_batched(const std::vector<GemmDesc<T>>& descs, bool transA, bool transB, T alpha, T beta,
+void gemm_batched(const std::vector<GemmDesc<T>>& descs_in, bool transA, bool transB, T alpha, T beta,
                   hipStream_t s) {
-  if (descs.empty()) return;
+  if (descs_in.empty()) return;
   ABDDC_REQUIRE(alpha != T(0) || beta == T(0), ABDDC_EINVAL, "gemm: alpha = 0 with beta != 0");
-  std::vector<int> cnt(descs.size());
-  for (size_t z = 0; z < descs.size(); ++z) {
-    const auto& d = descs[z];
+  // thin products (k and one side of C at most THIN) to the streaming kernel
+  std::vector<GemmDesc<T>> descs, thin;
+  int thin_len = 0;
+  for (const auto& d : descs_in) {
     ABDDC_REQUIRE(d.m >= 0 && d.n >= 0 && d.k >= 0, ABDDC_EINVAL, "gemm: negative size");
     const int64_t ea = (int64_t)(transA ? d.k : d.m) * d.lda, eb = (int64_t)(transB ? d.n : d.k) * d.ldb;
     ABDDC_REQUIRE(std::max({ea, eb, (int64_t)d.m * d.ldc}) * (int64_t)sizeof(T) < BUF_LIMIT, ABDDC_EINVAL,
                   "gemm: operand spans 2 GiB or more");
-    cnt[z] = ((d.m + TILE - 1) / TILE) * ((d.n + TILE - 1) / TILE);
+    if (d.m == 0 || d.n == 0) continue;
+    if (d.k <= THIN && (d.n <= THIN || d.m <= THIN)) {
+      thin.push_back(d);
+      // workgroups along the long side: THIN_ROWS rows (tall) or 256 columns (wide)
+      thin_len = std::max(thin_len, d.n <= THIN ? (d.m + THIN_ROWS - 1) / THIN_ROWS : (d.n + 255) / 256);
+    } else {
+      descs.push_back(d);
+    }
   }
   Arena& ar = Arena::for_stream(s);
+  if (!thin.empty()) {
+    const GemmDesc<T>* dt = ar.put(thin);
+    const int nd = (int)thin.size();
+    const dim3 grid(thin_len, std::min(nd, 65535));
+    if (!transA && !transB) gemm_thin_kernel<T, false, false><<<grid, 256, 0, s>>>(dt, nd, alpha, beta);
+    else if (transA && !transB) gemm_thin_kernel<T, true, false><<<grid, 256, 0, s>>>(dt, nd, alpha, beta);
+    else if (!transA && transB) gemm_thin_kernel<T, false, true><<<grid, 256, 0, s>>>(dt, nd, alpha, beta);
+    else gemm_thin_kernel<T, true, true><<<grid, 256, 0, s>>>(dt, nd, alpha, beta);
+    ABDDC_HIP(hipGetLastError());
+  }
+  if (descs.empty()) return;
+  std::vector<int> cnt(descs.size());
+  for (size_t z = 0; z < descs.size(); ++z) {
+    const auto& d = descs[z];
+    cnt[z] = ((d.m + TILE - 1) / TILE) * ((d.n + TILE - 1) / TILE);
+  }
   const RaggedGrid rg = ragged_grid(cnt, ar);
   if (rg.grid == 0) return;
   const GemmDesc<T>* dd = ar.put(descs);

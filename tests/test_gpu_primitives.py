@@ -24,17 +24,21 @@ def _posreal(n, rng, skew=3.0):
 def test_gemm_matches_numpy(transA, transB):
     api = _api()
     rng = np.random.default_rng(0)
-    shapes = [(1, 1, 1), (16, 16, 4), (63, 65, 33), (130, 70, 97), (5, 200, 64)]
-    As, Bs, Cs, ref = [], [], [], []
-    for m, n, k in shapes:
-        A = rng.standard_normal((k, m) if transA else (m, k))
-        B = rng.standard_normal((n, k) if transB else (k, n))
-        Cm = rng.standard_normal((m, n))
-        As.append(A); Bs.append(B); Cs.append(Cm)
-        ref.append(-0.5 * (A.T if transA else A) @ (B.T if transB else B) + 2.0 * Cm)
-    out = api.gemm(As, Bs, Cs, transA, transB, alpha=-0.5, beta=2.0)
-    for o, r in zip(out, ref):
-        assert np.abs(o - r).max() <= 1e-12 * max(1.0, np.abs(r).max())
+    # tiled shapes, and thin ones (k <= 32 with n <= 32 or m <= 32) that take
+    # the streaming kernel: tall, wide, both sides at the limit, single rows
+    shapes = [(1, 1, 1), (16, 16, 4), (63, 65, 33), (130, 70, 97), (5, 200, 64),
+              (300, 7, 7), (7, 300, 7), (257, 32, 32), (32, 513, 31), (1, 100, 1), (700, 3, 20), (40, 33, 32)]
+    for alpha, beta in ((-0.5, 2.0), (1.5, 0.0)):
+        As, Bs, Cs, ref = [], [], [], []
+        for m, n, k in shapes:
+            A = rng.standard_normal((k, m) if transA else (m, k))
+            B = rng.standard_normal((n, k) if transB else (k, n))
+            Cm = rng.standard_normal((m, n))
+            As.append(A); Bs.append(B); Cs.append(Cm)
+            ref.append(alpha * (A.T if transA else A) @ (B.T if transB else B) + beta * Cm)
+        out = api.gemm(As, Bs, Cs, transA, transB, alpha=alpha, beta=beta)
+        for (m, n, k), o, r in zip(shapes, out, ref):
+            assert np.abs(o - r).max() <= 1e-12 * max(1.0, np.abs(r).max()), (m, n, k, alpha, beta)
 
 
 @pytest.mark.parametrize("precision", [0, 1])
