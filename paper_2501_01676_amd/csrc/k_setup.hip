@@ -44,6 +44,7 @@ __global__ void deluxe_build_kernel(const DeluxeDesc* __restrict__ descs) {
 // n_Delta leading pivots leaves [[S_PiPi - S_PiD X S_DPi, V], [-U, L]] with
 // X = S_DD^{-1}: L = W_D X W_D^T, V = W_Pi^T - S_PiD X W_D^T and
 // U = W_Pi - W_D X S_DPi, the averaged local solve operators.
+template <class TO>
 __global__ void __launch_bounds__(256) aug_build_kernel(const AugDesc* __restrict__ descs) {
   __shared__ AugDesc sd;
   if (threadIdx.x == 0) sd = descs[blockIdx.y];
@@ -54,7 +55,7 @@ __global__ void __launch_bounds__(256) aug_build_kernel(const AugDesc* __restric
   // four columns per lane at a time, every load of a group issued before
   // its stores (the stores could alias the maps as far as the compiler knows)
   for (int i = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); i < na; i += nwv) {
-    double* row = d.aug + (size_t)i * na;
+    TO* row = static_cast<TO*>(d.aug) + (size_t)i * na;
     if (i < nB) {
       // row of rotated coordinate ci: Sbar(ci, am(j)), then W(m, ci) =
       // W_X(m - off, ci - off) for the m of the object of ci
@@ -70,10 +71,10 @@ __global__ void __launch_bounds__(256) aug_build_kernel(const AugDesc* __restric
         for (int u = 0; u < 4; ++u) v[u] = sc[u] >= 0 ? srow[sc[u]] : 0.0;
 #pragma unroll
         for (int u = 0; u < 4; ++u)
-          if (sc[u] >= 0) row[j0 + 64 * u] = v[u];
+          if (sc[u] >= 0) row[j0 + 64 * u] = (TO)v[u];
       }
       for (int m = lane; m < nB; m += 64)
-        row[nB + m] = (m >= off && m < off + n) ? wcol[(size_t)(m - off) * n] : 0.0;
+        row[nB + m] = (TO)((m >= off && m < off + n) ? wcol[(size_t)(m - off) * n] : 0.0);
     } else {
       // row of original coordinate m: -W(m, am(j)) inside its object, then zeros
       const int m = i - nB, q = d.slot[m], off = d.obj_off[q], n = d.obj_n[q];
@@ -87,9 +88,31 @@ __global__ void __launch_bounds__(256) aug_build_kernel(const AugDesc* __restric
         for (int u = 0; u < 4; ++u) v[u] = (cc[u] >= off && cc[u] < off + n) ? -wrow[cc[u] - off] : 0.0;
 #pragma unroll
         for (int u = 0; u < 4; ++u)
-          if (cc[u] >= 0) row[j0 + 64 * u] = v[u];
+          if (cc[u] >= 0) row[j0 + 64 * u] = (TO)v[u];
       }
-      for (int j = nB + lane; j < na; j += 64) row[j] = 0.0;
+      for (int j = nB + lane; j < na; j += 64) row[j] = TO(0);
+    }
+  }
+}
+
+// AugOutDesc: one wave per output row (the rows of M, then those of U),
+// lanes along the row.
+template <class T>
+__global__ void __launch_bounds__(256) aug_extract_kernel(const AugOutDesc* __restrict__ descs) {
+  const AugOutDesc d = descs[blockIdx.y];
+  const int nB = d.nB, nD = d.nD, nP = nB - nD, na = 2 * nB, lane = threadIdx.x & 63;
+  const T* A = static_cast<const T*>(d.aug);
+  const int nwv = gridDim.x * (blockDim.x >> 6);
+  for (int r = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); r < 2 * nB + nP; r += nwv) {
+    if (r < nB + nP) {
+      const T* src = A + (size_t)(r < nB ? nB + r : nD + r - nB) * na + nB;
+      T* dst = static_cast<T*>(d.M) + (size_t)r * nB;
+      for (int c = lane; c < nB; c += 64) dst[c] = src[c];
+    } else {
+      const int m = r - nB - nP;
+      const T* src = A + (size_t)(nB + m) * na + nD;
+      T* dst = static_cast<T*>(d.U) + (size_t)m * nP;
+      for (int c = lane; c < nP; c += 64) dst[c] = -src[c];
     }
   }
 }
@@ -251,7 +274,7 @@ __global__ void coarse_add_kernel(const CoarseAddDesc* __restrict__ descs, doubl
   const CoarseAddDesc d = descs[blockIdx.y];
   for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < d.n * d.n; idx += gridDim.x * blockDim.x) {
     const int a = idx / d.n, b = idx % d.n;
-    SPi[(int64_t)d.gid[a] * ldc + d.gid[b]] += d.src[(size_t)a * d.ld + b];
+    SPi[(int64_t)d.gid[a] * ldc + d.gid[b]] += d.src32 ? (double)d.src32[(size_t)a * d.ld + b] : d.src[(size_t)a * d.ld + b];
   }
 }
 
@@ -263,25 +286,7 @@ __global__ void axpby_kernel(const AxpbyDesc* __restrict__ descs) {
   }
 }
 
-template <class S, class D>
-__global__ void convert_kernel(const S* __restrict__ src, D* __restrict__ dst, int64_t n) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-    dst[i] = (D)src[i];
-}
-
 }  // namespace
-
-void convert_f64_f32(const double* src, float* dst, int64_t n, hipStream_t s) {
-  if (n <= 0) return;
-  convert_kernel<double, float><<<(unsigned)std::min<int64_t>((n + 255) / 256, 65535), 256, 0, s>>>(src, dst, n);
-  ABDDC_HIP(hipGetLastError());
-}
-
-void convert_f32_f64(const float* src, double* dst, int64_t n, hipStream_t s) {
-  if (n <= 0) return;
-  convert_kernel<float, double><<<(unsigned)std::min<int64_t>((n + 255) / 256, 65535), 256, 0, s>>>(src, dst, n);
-  ABDDC_HIP(hipGetLastError());
-}
 
 void deluxe_build_batched(const std::vector<DeluxeDesc>& descs, hipStream_t s) {
   if (descs.empty()) return;
@@ -292,14 +297,27 @@ void deluxe_build_batched(const std::vector<DeluxeDesc>& descs, hipStream_t s) {
   ABDDC_HIP(hipGetLastError());
 }
 
-void aug_build_batched(const std::vector<AugDesc>& descs, hipStream_t s) {
+void aug_build_batched(const std::vector<AugDesc>& descs, bool f32, hipStream_t s) {
   if (descs.empty()) return;
   int maxr = 0;
   for (auto& d : descs) maxr = std::max(maxr, 2 * d.nB);
   if (maxr == 0) return;
   const AugDesc* dd = Arena::for_stream(s).put(descs);
   const int gx = std::min((maxr + 3) / 4, 1024);   // four rows (waves) per workgroup
-  aug_build_kernel<<<dim3(gx, descs.size()), 256, 0, s>>>(dd);
+  if (f32) aug_build_kernel<float><<<dim3(gx, descs.size()), 256, 0, s>>>(dd);
+  else aug_build_kernel<double><<<dim3(gx, descs.size()), 256, 0, s>>>(dd);
+  ABDDC_HIP(hipGetLastError());
+}
+
+void aug_extract_batched(const std::vector<AugOutDesc>& descs, bool f32, hipStream_t s) {
+  if (descs.empty()) return;
+  int maxr = 0;
+  for (auto& d : descs) maxr = std::max(maxr, 3 * d.nB - d.nD);
+  if (maxr == 0) return;
+  const AugOutDesc* dd = Arena::for_stream(s).put(descs);
+  const int gx = std::min((maxr + 3) / 4, 1024);
+  if (f32) aug_extract_kernel<float><<<dim3(gx, descs.size()), 256, 0, s>>>(dd);
+  else aug_extract_kernel<double><<<dim3(gx, descs.size()), 256, 0, s>>>(dd);
   ABDDC_HIP(hipGetLastError());
 }
 

@@ -994,9 +994,24 @@ void run_setup(abddc_ctx* c) {
       wt += (int64_t)T.objects[k].n * T.objects[k].n;
     }
   }
-  DevBuf<double> Sb(c->dS.n), Aug(std::max<int64_t>(at, 1)), WX(std::max<int64_t>(wt, 1));
-  c->dM.alloc(std::max<int64_t>(mt, 1));
-  c->dU.alloc(std::max<int64_t>(ut, 1));
+  // the augmented systems and the apply operators in the factorisation's
+  // precision: FP64, or FP32 throughout for the mixed form (no copies)
+  const bool mixed = c->opt.precision == ABDDC_PREC_MIXED;
+  DevBuf<double> Sb(c->dS.n), WX(std::max<int64_t>(wt, 1)), Aug;
+  DevBuf<float> Aug32;
+  if (mixed) {
+    Aug32.alloc(std::max<int64_t>(at, 1));
+    c->dM32.alloc(std::max<int64_t>(mt, 1));
+    c->dU32.alloc(std::max<int64_t>(ut, 1));
+    c->dM.release();
+    c->dU.release();
+  } else {
+    Aug.alloc(std::max<int64_t>(at, 1));
+    c->dM.alloc(std::max<int64_t>(mt, 1));
+    c->dU.alloc(std::max<int64_t>(ut, 1));
+    c->dM32.release();
+    c->dU32.release();
+  }
   {
     ht.mark("Sbar = T^T S T (face and edge blocks)");
     // Sbar = T^T S T: Y = S T, then Sbar = T^T Y on the face and edge
@@ -1060,22 +1075,21 @@ void run_setup(abddc_ctx* c) {
     // L = W_D X W_D^T, V = W_Pi^T - S_PiD X W_D^T, U = W_Pi - W_D X S_DPi:
     // M = [L; V] and U are read off the trailing block.
     IntPool pool;
-    std::vector<size_t> am(nsub), sl(nsub), oo(nsub), on(nsub), ow(nsub), mr(nsub), pidx(nsub);
+    std::vector<size_t> am(nsub), sl(nsub), oo(nsub), on(nsub), ow(nsub), pidx(nsub);
     ABDDC_REQUIRE(wt < ((int64_t)1 << 31), ABDDC_EINVAL, "interface blocks too large");
     for (int sub = 0; sub < nsub; ++sub) {
-      const size_t nB = c->nB[sub], nP = Pi[sub].size(), no = T.sub[sub].objs.size();
+      const size_t nB = c->nB[sub], no = T.sub[sub].objs.size();
       am[sub] = pool.reserve(nB);
       sl[sub] = pool.reserve(nB);
       oo[sub] = pool.reserve(no);
       on[sub] = pool.reserve(no);
       ow[sub] = pool.reserve(no);
-      mr[sub] = pool.reserve(nB + nP);
       pidx[sub] = pool.reserve(Pid[sub].size());
     }
     host_parallel_for(nsub, 8, [&](int64_t sb, int64_t se) {
       for (int sub = (int)sb; sub < (int)se; ++sub) {
         const SubInfo& si = T.sub[sub];
-        const int nB = c->nB[sub], nP = (int)Pi[sub].size(), nD = (int)Dl[sub].size();
+        const int nD = (int)Dl[sub].size();
         int32_t* h = pool.h.data();
         int32_t* mp = h + am[sub];
         std::copy(Dl[sub].begin(), Dl[sub].end(), mp);
@@ -1087,46 +1101,35 @@ void run_setup(abddc_ctx* c) {
           h[on[sub] + q] = n;
           h[ow[sub] + q] = (int32_t)wpos[sub][q];
         }
-        // rows of M = [L; V] in the trailing block: the original
-        // coordinates, then the Pi rows
-        for (int l = 0; l < nB; ++l) h[mr[sub] + l] = nB + l;
-        for (int l = 0; l < nP; ++l) h[mr[sub] + nB + l] = nD + l;
         std::copy(Pid[sub].begin(), Pid[sub].end(), h + pidx[sub]);
       }
     });
     pool.upload(s);
     std::vector<AugDesc> ad;
     std::vector<PluDesc<double>> pd;
+    std::vector<PluDesc<float>> pf;
+    std::vector<AugOutDesc> od;
     for (int sub = 0; sub < nsub; ++sub) {
       const int nB = c->nB[sub], nD = (int)Dl[sub].size();
-      ad.push_back({Sb.p + c->soff[sub], Aug.p + aoff2[sub], pool.ptr(am[sub]), pool.ptr(sl[sub]),
-                    pool.ptr(oo[sub]), pool.ptr(on[sub]), pool.ptr(ow[sub]), WX.p, nB});
-      pd.push_back({Aug.p + aoff2[sub], 2 * nB, 2 * nB, 2 * nB, nD});
+      void* a = mixed ? (void*)(Aug32.p + aoff2[sub]) : (void*)(Aug.p + aoff2[sub]);
+      ad.push_back({Sb.p + c->soff[sub], a, pool.ptr(am[sub]), pool.ptr(sl[sub]), pool.ptr(oo[sub]),
+                    pool.ptr(on[sub]), pool.ptr(ow[sub]), WX.p, nB});
+      if (mixed) {
+        pf.push_back({Aug32.p + aoff2[sub], 2 * nB, 2 * nB, 2 * nB, nD});
+        od.push_back({a, c->dM32.p + c->moff[sub], c->dU32.p + c->uoff[sub], nB, nD});
+      } else {
+        pd.push_back({Aug.p + aoff2[sub], 2 * nB, 2 * nB, 2 * nB, nD});
+        od.push_back({a, c->dM.p + c->moff[sub], c->dU.p + c->uoff[sub], nB, nD});
+      }
     }
-    aug_build_batched(ad, s);
-    if (c->opt.precision == ABDDC_PREC_MIXED) {
-      // local constrained factorisation in FP32 on MFMA; the preconditioner it
-      // defines is applied inside FP64 GMRES, which absorbs its rounding
-      DevBuf<float> Aug32(Aug.n);
-      convert_f64_f32(Aug.p, Aug32.p, (int64_t)Aug.n, s);
-      std::vector<PluDesc<float>> pf;
-      for (auto& q : pd) pf.push_back({Aug32.p + (q.a - Aug.p), q.nrow, q.ncol, q.ld, q.k});
-      partial_lu<float>(pf, c->d_flag.p, s);
-      convert_f32_f64(Aug32.p, Aug.p, (int64_t)Aug.n, s);
-    } else {
-      partial_lu<double>(pd, c->d_flag.p, s);
-    }
+    aug_build_batched(ad, mixed, s);
+    // the mixed form factors in FP32 on MFMA; the preconditioner it defines
+    // is applied inside FP64 GMRES, which absorbs its rounding
+    if (mixed) partial_lu<float>(pf, c->d_flag.p, s);
+    else partial_lu<double>(pd, c->d_flag.p, s);
 
     ht.mark("M = [L; V], U from the trailing block");
-    std::vector<GatherDesc> gd;
-    for (int sub = 0; sub < nsub; ++sub) {
-      const int nB = c->nB[sub], nP = (int)Pi[sub].size(), nD = (int)Dl[sub].size(), na = 2 * nB;
-      const double* A = Aug.p + aoff2[sub];
-      gd.push_back({A + nB, c->dM.p + c->moff[sub], pool.ptr(mr[sub]), nullptr, nB + nP, nB, na, nB, 1.0});
-      if (nP > 0)
-        gd.push_back({A + (int64_t)nB * na + nD, c->dU.p + c->uoff[sub], nullptr, nullptr, nB, nP, na, nP, -1.0});
-    }
-    gather_batched(gd, s);
+    aug_extract_batched(od, mixed, s);
 
     ht.mark("coarse");
     // ----------------------------------------------------------- coarse
@@ -1168,7 +1171,8 @@ void run_setup(abddc_ctx* c) {
         if (colour[sub] != color) continue;
         const int nP = (int)Pi[sub].size(), nD = (int)Dl[sub].size(), na = 2 * c->nB[sub];
         if (nP == 0) continue;
-        cd.push_back({Aug.p + aoff2[sub] + (int64_t)nD * na + nD, pool.ptr(pidx[sub]), nP, na});
+        const int64_t o = aoff2[sub] + (int64_t)nD * na + nD;   // the Pi x Pi block
+        cd.push_back({mixed ? nullptr : Aug.p + o, pool.ptr(pidx[sub]), nP, na, mixed ? Aug32.p + o : nullptr});
       }
       coarse_add_batched(cd, SPi.p, np, s);
     }
@@ -1244,23 +1248,11 @@ void run_setup(abddc_ctx* c) {
       activeU.push_back(nP > 0);
     }
     mC.push_back({0, 0, 0, np, np, std::max(np, 1), 0});
-    const bool mixed = c->opt.precision == ABDDC_PREC_MIXED;
     auto gbytes = [](const std::vector<GemvMat>& v, bool gathered, double esize) {
       double b = 0.0;  // matrix + gathered input (value and index) + output
       for (const GemvMat& m : v) b += (double)m.nrows * m.ncols * esize + m.ncols * (gathered ? 12.0 : 8.0) + m.nrows * 8.0;
       return b;
     };
-    if (mixed) {
-      c->dM32.alloc(c->dM.n);
-      c->dU32.alloc(c->dU.n);
-      convert_f64_f32(c->dM.p, c->dM32.p, (int64_t)c->dM.n, s);
-      convert_f64_f32(c->dU.p, c->dU32.p, (int64_t)c->dU.n, s);
-      c->dM.release();
-      c->dU.release();
-    } else {
-      c->dM32.release();
-      c->dU32.release();
-    }
     ht.mark("metadata: uploads, fp32 copies");
     gemv_build(c->opM, mM, nullptr, gbytes(mM, true, mixed ? 4.0 : 8.0), s);
     gemv_build(c->opU, mU, &activeU, gbytes(mU, true, mixed ? 4.0 : 8.0), s);

@@ -50,7 +50,7 @@ struct EdgeOldDesc {
 // and W_X offset (in wx) are obj_off, obj_n and obj_w.
 struct AugDesc {
   const double* sbar;     // nB x nB, ld nB
-  double* aug;            // 2 nB x 2 nB, ld 2 nB
+  void* aug;              // 2 nB x 2 nB, ld 2 nB (double, or float for the FP32 factorisation)
   const int32_t* am;      // nB
   const int32_t* slot;    // nB
   const int32_t* obj_off;
@@ -69,10 +69,24 @@ struct LinesDesc {
   int32_t nidx, n, rows;
 };
 
+// M = [L; V] ((nB + nP) x nB, ld nB) and U (nB x nP, ld nP) read off the
+// trailing block of an eliminated augmented system (AugDesc layout, nD
+// pivots): M(r, c) = Aug(nB + r, nB + c) for r < nB, Aug(nD + r - nB, nB + c)
+// below; U(m, l) = -Aug(nB + m, nD + l).  All three in one element type.
+struct AugOutDesc {
+  const void* aug;
+  void* M;
+  void* U;
+  int32_t nB, nD;
+};
+
+// SPi[gid[a]][gid[b]] += src[a][b] (n x n, ld ld); src32 instead of src
+// when set.
 struct CoarseAddDesc {
   const double* src;
   const int32_t* gid;
   int32_t n, ld;
+  const float* src32;
 };
 
 struct AxpbyDesc {
@@ -83,10 +97,9 @@ struct AxpbyDesc {
   double alpha, beta;
 };
 
-void convert_f64_f32(const double* src, float* dst, int64_t n, hipStream_t s);
-void convert_f32_f64(const float* src, double* dst, int64_t n, hipStream_t s);
 void deluxe_build_batched(const std::vector<DeluxeDesc>& d, hipStream_t s);
-void aug_build_batched(const std::vector<AugDesc>& d, hipStream_t s);
+void aug_build_batched(const std::vector<AugDesc>& d, bool f32, hipStream_t s);
+void aug_extract_batched(const std::vector<AugOutDesc>& d, bool f32, hipStream_t s);
 void copy_lines_batched(const std::vector<LinesDesc>& d, hipStream_t s);
 void edge_assemble_batched(const std::vector<EdgeAsmDesc>& d, hipStream_t s);
 void edge_old_metric_batched(const std::vector<EdgeOldDesc>& d, hipStream_t s);
