@@ -20,8 +20,10 @@ kernel), the larger of them over the timed steps is reported, and
 follow (`--kernel-stats all` times every class in the timed steps).  `local_solve_tflops` is the
 algorithmic FP64 work of the local Schur complements (S2) and the local
 constrained factorisations (S10) over the device time of those two phases.
-`cpu_baseline` is the FP64 CPU oracle (test infrastructure) timed on the
-host: the whole solve of the same workload with every BLAS thread, and a
+After an FP64 run, `mixed_precision` times the same solve in the mixed form
+(FP32 local constrained factorisation and apply operators inside FP64 GMRES);
+`value` stays the FP64 solve.  `cpu_baseline` is the FP64 CPU oracle (test
+infrastructure) timed on the host: the whole solve of the same workload with every BLAS thread, and a
 one-thread figure from a bounded sample.
 """
 from __future__ import annotations
@@ -71,6 +73,8 @@ def parse():
     ap.add_argument("--edge-variant", choices=["new", "old"], default="new",
                     help="edge eigenproblem: the new one (eq. equ-5-21) or the earlier one (eq. equ-4-8-E)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true",
+                    help="skip the mixed-precision timing that follows an FP64 run")
     ap.add_argument("--kernel-stats", choices=["dominant", "all"], default="dominant",
                     help="kernel classes timed with events in the timed steps")
     ap.add_argument("--constraints", choices=["exact", "mlp"], default="exact",
@@ -298,11 +302,11 @@ def main():
         learned = train_network(args, opts)
         opts = dict(opts, constraint_source=1, mlp=learned["net"], judge_iters=learned["judge_iters"])
 
-    def step(want_flops=False):
+    def step(want_flops=False, o=None):
         ta = time.perf_counter()
         s = api.Solver(dev_problem)
         tb = time.perf_counter()
-        counts = s.setup_coarse_space(**opts)
+        counts = s.setup_coarse_space(**(opts if o is None else o))
         tc = time.perf_counter()
         _, info = s.gmres_solve(args.restart, args.rtol, args.maxit, history=False)
         td = time.perf_counter()
@@ -426,6 +430,26 @@ def main():
                           "train_edges": learned["edges"], "train_labels_nonzero": learned["labels_nonzero"],
                           "train_loss_first": learned["loss_first"], "train_loss_last": learned["loss_last"],
                           "train_s_untimed": learned["train_s"]}
+    if args.precision == 0 and learned is None and not args.no_mixed:
+        # the mixed form of the same solve (FP32 local constrained factorisation
+        # and apply operators inside FP64 GMRES), warmed up and timed the same
+        # way, with no kernel timed by events; `value` stays the FP64 solve
+        api.set_kernel_stats(0)
+        mo = dict(opts, precision=1)
+        for _ in range(args.warmup):
+            step(o=mo)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        mrecs = [step(o=mo) for _ in range(args.steps)]
+        torch.cuda.synchronize()
+        mt = (time.perf_counter() - t0) / args.steps
+        api.set_kernel_stats(all_classes)
+        out["mixed_precision"] = {
+            "value": mt, "unit": "s", "ms_per_step": mt * 1e3, "dtype": "f64+f32",
+            "iters": mrecs[-1][1]["iters"], "relres_true": mrecs[-1][1]["relres_true"],
+            "converged": all(r[1]["converged"] and r[1]["relres_true"] <= args.rtol for r in mrecs),
+            "counts": mrecs[-1][0], "speedup_vs_fp64": per_step / mt,
+            "phase_device_s": {n: float(v) for n, v in zip(names, np.mean([r[3] for r in mrecs], axis=0))}}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(problem, {k: v for k, v in opts.items() if k != "mlp"}, args)
     if args.copy_probe > 0:
