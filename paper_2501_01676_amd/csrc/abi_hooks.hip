@@ -78,6 +78,19 @@ void staged_upload(void* dst, const void* src, size_t bytes, hipStream_t s) {
   if (bytes) Arena::for_stream(s).upload(dst, src, bytes);
 }
 
+int32_t* pinned_ints(size_t n) {
+  static thread_local int32_t* p = nullptr;
+  static thread_local size_t cap = 0;
+  if (n > cap) {
+    if (p) (void)hipHostFree(p);
+    p = nullptr;
+    cap = 0;
+    ABDDC_HIP(hipHostMalloc((void**)&p, n * sizeof(int32_t), hipHostMallocDefault));
+    cap = n;
+  }
+  return p;
+}
+
 void* cache_alloc(size_t bytes) {
   int dev = 0;
   ABDDC_HIP(hipGetDevice(&dev));

@@ -39,6 +39,11 @@ void cache_free(void* p, size_t bytes);
 // Stream-ordered host -> device copy through the stream's pinned staging ring.
 void staged_upload(void* dst, const void* src, size_t bytes, hipStream_t s);
 
+// Pinned host memory for at least n ints, per thread, for device-to-host
+// readbacks the host waits for by event (grown as needed; the caller waits
+// for every readback before it calls again).
+int32_t* pinned_ints(size_t n);
+
 // Stream on which the current entry point works (released blocks are tagged
 // with it).
 extern thread_local hipStream_t g_stream;

@@ -450,6 +450,85 @@ void run_setup(abddc_ctx* c) {
   }
   c->pnum_face = nxt - nvx;
 
+  // Sbar = T^T S T and W_X = D_X T_X need the face and edge transforms and
+  // the deluxe blocks, not the edge ranks: queued by the edge path that
+  // builds the last transforms (before its rank readback, so the device
+  // rotates while the host waits and then builds the local maps), or at the
+  // change of basis
+  DevBuf<double> Y(c->dS.n), Sb(c->dS.n);
+  std::vector<std::vector<int64_t>> wpos(nsub);
+  int64_t wt = 0;
+  for (int sub = 0; sub < nsub; ++sub)
+    for (int k : T.sub[sub].objs) {
+      wpos[sub].push_back(wt);
+      wt += (int64_t)T.objects[k].n * T.objects[k].n;
+    }
+  DevBuf<double> WX(std::max<int64_t>(wt, 1));
+  // descriptors first (pointers and sizes only: built while the device runs
+  // the edge stage), launches later
+  std::vector<GemmDesc<double>> rot_gc, rot_gr, rot_wg;
+  std::vector<SetDesc> rot_vset;
+  std::vector<LinesDesc> rot_lcol, rot_lrow;
+  IntPool rot_vp;
+  bool rot_ready = false, rotated = false;
+  auto prepare_rotation = [&]() {
+    if (rot_ready) return;
+    rot_ready = true;
+    // Sbar = T^T S T: Y = S T, then Sbar = T^T Y on the face and edge
+    // blocks; the vertex lines, which the rotation leaves alone, are copied
+    std::vector<int32_t> zero1(1, 0);
+    const size_t z_off = rot_vp.add(zero1);
+    std::vector<size_t> voff(nsub);
+    std::vector<int> vcnt(nsub);
+    for (int sub = 0; sub < nsub; ++sub) {
+      std::vector<int32_t> lines;
+      const SubInfo& si = T.sub[sub];
+      for (size_t q = 0; q < si.objs.size(); ++q)
+        if (T.objects[si.objs[q]].kind == KIND_VERTEX) lines.push_back(si.obj_off[q]);
+      vcnt[sub] = (int)lines.size();
+      voff[sub] = rot_vp.add(lines);
+    }
+    rot_vp.upload(s);
+    for (int sub = 0; sub < nsub; ++sub) {
+      if (vcnt[sub] == 0) continue;
+      rot_lcol.push_back({c->dS.p + c->soff[sub], Y.p + c->soff[sub], rot_vp.ptr(voff[sub]), vcnt[sub], c->nB[sub], 0});
+      rot_lrow.push_back({Y.p + c->soff[sub], Sb.p + c->soff[sub], rot_vp.ptr(voff[sub]), vcnt[sub], c->nB[sub], 1});
+    }
+    for (int sub = 0; sub < nsub; ++sub) {
+      const SubInfo& si = T.sub[sub];
+      const int nB = c->nB[sub];
+      for (size_t q = 0; q < si.objs.size(); ++q) {
+        const int k = si.objs[q];
+        const Object& o = T.objects[k];
+        const int off = si.obj_off[q], n = o.n;
+        double* wx = WX.p + wpos[sub][q];
+        if (o.kind == KIND_VERTEX) {
+          rot_vset.push_back({wx, rot_vp.ptr(z_off), rot_vp.ptr(z_off), 1, 1, 1.0 / (double)o.subs.size()});
+          continue;
+        }
+        const double* TX = o.kind == KIND_FACE ? c->dTF.p + c->tfoff[T.kind_index[k]] : c->dTE.p + c->teoff[T.kind_index[k]];
+        rot_gc.push_back({c->dS.p + c->soff[sub] + off, TX, Y.p + c->soff[sub] + off, nB, n, n, nB, n, nB});
+        rot_gr.push_back({TX, Y.p + c->soff[sub] + (int64_t)off * nB, Sb.p + c->soff[sub] + (int64_t)off * nB, n, nB, n, n,
+                          nB, nB});
+        const int mem = (int)(std::lower_bound(o.subs.begin(), o.subs.end(), sub) - o.subs.begin());
+        rot_wg.push_back({c->dD.p + c->dxoff[(size_t)k * 8 + mem], TX, wx, n, n, n, n, n, n});
+      }
+    }
+    ht.mark("rotation descriptors");
+  };
+  auto queue_rotation = [&]() {
+    if (rotated) return;
+    rotated = true;
+    prepare_rotation();
+    gemm_batched<double>(rot_gc, false, false, 1.0, 0.0, s);
+    copy_lines_batched(rot_lcol, s);
+    copy_lines_batched(rot_lrow, s);
+    gemm_batched<double>(rot_gr, true, false, 1.0, 0.0, s);
+    gemm_batched<double>(rot_wg, false, false, 1.0, 0.0, s);   // W_X = D_X T_X
+    set_batched(rot_vset, s);                                    // vertices: 1/|n(V)|
+    ht.mark("Sbar = T^T S T, W_X = D_X T_X queued");
+  };
+
   ht.mark("edges");
   // ------------------------------------------------------------- edges
   record(c, 4);
@@ -623,6 +702,7 @@ void run_setup(abddc_ctx* c) {
     }
     edge_old_metric_batched(md, s);
     eig_selected(gv, 1.0 / c->opt.theta_edge, c->d_flag.p, s);
+    prepare_rotation();   // while the device solves the edge eigenproblems
     std::vector<double> mu = to_host(c->dWE.p, c->dWE.n, s);
     require_flag_clean(c, "edge elimination / edge eigenproblem");
     std::vector<QrDesc> qd;
@@ -640,6 +720,7 @@ void run_setup(abddc_ctx* c) {
       qd.push_back({slot(e, (int)o.subs.size() + 3), c->dTE.p + c->teoff[e], o.n, ns, o.n});
     }
     qr_complete_batched(qd, s);
+    queue_rotation();
   } else if (!elist.empty()) {
     // only the subdomains of the edges solved here need the per-subdomain
     // steps (all of them for the exact method; those around the edges the
@@ -875,6 +956,7 @@ void run_setup(abddc_ctx* c) {
       gv.push_back({Btt.p + meoff[e], ME.p + meoff[e], c->dWE.p + c->weoff[e], XE.p + meoff[e], nw});
     }
     eig_selected(gv, 1.0 / c->opt.theta_edge, c->d_flag.p, s);
+    prepare_rotation();   // while the device solves the edge eigenproblems
     std::vector<double> mu = to_host(c->dWE.p, c->dWE.n, s);
     require_flag_clean(c, "edge elimination / edge eigenproblem");
     ht.mark("G = [g_{l,k}] (n_E x (m-1) |N_E|) and ");
@@ -923,7 +1005,16 @@ void run_setup(abddc_ctx* c) {
     }
     gather_batched(gd, s);
     svd_left_batched(sv, c->opt.svd_rtol, s);
-    std::vector<int32_t> rk = to_host(ranks.p, ned, s);
+    // the ranks into pinned memory behind an event, then the rotation, then
+    // the wait (for the ranks only)
+    int32_t* rk = pinned_ints((size_t)std::max(ned, 1));
+    ABDDC_HIP(hipMemcpyAsync(rk, ranks.p, (size_t)ned * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    hipEvent_t rev = EventPool::take();
+    ABDDC_HIP(hipEventRecord(rev, s));
+    queue_rotation();
+    const hipError_t werr = hipEventSynchronize(rev);
+    EventPool::give(c->device, rev);
+    ABDDC_HIP(werr);
     for (int e : elist) c->rE[e] = rk[e];
   }
   c->pnum_edge = 0;
@@ -938,7 +1029,7 @@ void run_setup(abddc_ctx* c) {
   ht.mark("change of basis + local");
   // -------------------------------------------- change of basis + local
   record(c, 5);
-  DevBuf<double> Y(c->dS.n);
+  queue_rotation();   // unless an edge path has queued it already
   // local coordinate order per object: [primal, dual]; Pi / Delta positions
   std::vector<std::vector<int32_t>> Pi(nsub), Dl(nsub), Pid(nsub);
   host_parallel_for(nsub, 8, [&](int64_t sb, int64_t se) {
@@ -973,9 +1064,8 @@ void run_setup(abddc_ctx* c) {
   c->uoff.assign(nsub, 0);
   c->ooff.assign(nsub, 0);
   c->poff.assign(nsub, 0);
-  int64_t mt = 0, ut = 0, ot = 0, pt = 0, at = 0, wt = 0;
-  std::vector<int64_t> aoff2(nsub), woffX;
-  std::vector<std::vector<int64_t>> wpos(nsub);
+  int64_t mt = 0, ut = 0, ot = 0, pt = 0, at = 0;
+  std::vector<int64_t> aoff2(nsub);
   for (int sub = 0; sub < nsub; ++sub) {
     const int nB = c->nB[sub], nP = (int)Pi[sub].size(), nD = (int)Dl[sub].size();
     c->nPi[sub] = nP;
@@ -989,15 +1079,11 @@ void run_setup(abddc_ctx* c) {
     pt += nP;
     aoff2[sub] = at;
     at += (int64_t)(2 * nB) * (2 * nB);
-    for (int k : T.sub[sub].objs) {
-      wpos[sub].push_back(wt);
-      wt += (int64_t)T.objects[k].n * T.objects[k].n;
-    }
   }
   // the augmented systems and the apply operators in the factorisation's
   // precision: FP64, or FP32 throughout for the mixed form (no copies)
   const bool mixed = c->opt.precision == ABDDC_PREC_MIXED;
-  DevBuf<double> Sb(c->dS.n), WX(std::max<int64_t>(wt, 1)), Aug;
+  DevBuf<double> Aug;
   DevBuf<float> Aug32;
   if (mixed) {
     Aug32.alloc(std::max<int64_t>(at, 1));
@@ -1011,58 +1097,6 @@ void run_setup(abddc_ctx* c) {
     c->dU.alloc(std::max<int64_t>(ut, 1));
     c->dM32.release();
     c->dU32.release();
-  }
-  {
-    ht.mark("Sbar = T^T S T (face and edge blocks)");
-    // Sbar = T^T S T: Y = S T, then Sbar = T^T Y on the face and edge
-    // blocks; the vertex lines, which the rotation leaves alone, are copied
-    std::vector<GemmDesc<double>> gc, gr, wg;
-    std::vector<SetDesc> vset;
-    IntPool vp;
-    std::vector<int32_t> zero1(1, 0);
-    const size_t z_off = vp.add(zero1);
-    std::vector<size_t> voff(nsub);
-    std::vector<int> vcnt(nsub);
-    for (int sub = 0; sub < nsub; ++sub) {
-      std::vector<int32_t> lines;
-      const SubInfo& si = T.sub[sub];
-      for (size_t q = 0; q < si.objs.size(); ++q)
-        if (T.objects[si.objs[q]].kind == KIND_VERTEX) lines.push_back(si.obj_off[q]);
-      vcnt[sub] = (int)lines.size();
-      voff[sub] = vp.add(lines);
-    }
-    vp.upload(s);
-    std::vector<LinesDesc> lcol, lrow;
-    for (int sub = 0; sub < nsub; ++sub) {
-      if (vcnt[sub] == 0) continue;
-      lcol.push_back({c->dS.p + c->soff[sub], Y.p + c->soff[sub], vp.ptr(voff[sub]), vcnt[sub], c->nB[sub], 0});
-      lrow.push_back({Y.p + c->soff[sub], Sb.p + c->soff[sub], vp.ptr(voff[sub]), vcnt[sub], c->nB[sub], 1});
-    }
-    for (int sub = 0; sub < nsub; ++sub) {
-      const SubInfo& si = T.sub[sub];
-      const int nB = c->nB[sub];
-      for (size_t q = 0; q < si.objs.size(); ++q) {
-        const int k = si.objs[q];
-        const Object& o = T.objects[k];
-        const int off = si.obj_off[q], n = o.n;
-        double* wx = WX.p + wpos[sub][q];
-        if (o.kind == KIND_VERTEX) {
-          vset.push_back({wx, vp.ptr(z_off), vp.ptr(z_off), 1, 1, 1.0 / (double)o.subs.size()});
-          continue;
-        }
-        const double* TX = o.kind == KIND_FACE ? c->dTF.p + c->tfoff[T.kind_index[k]] : c->dTE.p + c->teoff[T.kind_index[k]];
-        gc.push_back({c->dS.p + c->soff[sub] + off, TX, Y.p + c->soff[sub] + off, nB, n, n, nB, n, nB});
-        gr.push_back({TX, Y.p + c->soff[sub] + (int64_t)off * nB, Sb.p + c->soff[sub] + (int64_t)off * nB, n, nB, n, n, nB, nB});
-        const int mem = (int)(std::lower_bound(o.subs.begin(), o.subs.end(), sub) - o.subs.begin());
-        wg.push_back({c->dD.p + c->dxoff[(size_t)k * 8 + mem], TX, wx, n, n, n, n, n, n});
-      }
-    }
-    gemm_batched<double>(gc, false, false, 1.0, 0.0, s);
-    copy_lines_batched(lcol, s);
-    copy_lines_batched(lrow, s);
-    gemm_batched<double>(gr, true, false, 1.0, 0.0, s);
-    gemm_batched<double>(wg, false, false, 1.0, 0.0, s);   // W_X = D_X T_X
-    set_batched(vset, s);                                    // vertices: 1/|n(V)|
   }
   {
     ht.mark("augmented [[Sbar, W^T], [-W, 0]]");
