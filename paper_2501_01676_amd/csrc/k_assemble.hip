@@ -288,31 +288,42 @@ __global__ void scatter_kernel(const SubAsm* __restrict__ subs, const int32_t* _
 __global__ void __launch_bounds__(256) extract_kernel(const SubAsm* __restrict__ subs, const double* __restrict__ A,
                                                       double* __restrict__ S, double* __restrict__ B,
                                                       double* __restrict__ g) {
-  // one 32 x 32 tile (I, J) of the trailing block per workgroup: tile (I, J)
-  // and its mirror (J, I) are read with unit-stride rows into LDS, so the
-  // transposed operand of B = (S + S^T) / 2 costs no strided global reads
+  // one pair of 32 x 32 tiles (I, J) and (J, I), I <= J, of the trailing
+  // block per workgroup: both are read once with unit-stride rows into LDS,
+  // and S and B = (S + S^T) / 2 are written for both, so the transposed
+  // operand costs neither strided global reads nor a second read
   __shared__ double Ta[32][33], Tb[32][33];
   const SubAsm d = subs[blockIdx.y];
   const int nB = d.nloc - d.nI, nt = (nB + 31) / 32;
   if ((int)blockIdx.x >= nt * nt) return;
   const int I = blockIdx.x / nt, J = blockIdx.x % nt;
+  if (I > J) return;   // its pair is handled by workgroup (J, I)
   const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
   const double* T = A + d.aoff + (int64_t)d.nI * d.ld + d.nI;
   for (int r = ty; r < 32; r += 8) {
     const int i = I * 32 + r, j = J * 32 + tx, i2 = J * 32 + r, j2 = I * 32 + tx;
     Ta[r][tx] = (i < nB && j < nB) ? T[(int64_t)i * d.ld + j] : 0.0;
-    Tb[r][tx] = (i2 < nB && j2 < nB) ? T[(int64_t)i2 * d.ld + j2] : 0.0;
+    if (I != J) Tb[r][tx] = (i2 < nB && j2 < nB) ? T[(int64_t)i2 * d.ld + j2] : 0.0;
   }
   __syncthreads();
+  const double (*Tm)[33] = I != J ? Tb : Ta;   // the mirror tile (J, I)
   for (int r = ty; r < 32; r += 8) {
     const int i = I * 32 + r, j = J * 32 + tx;
     if (i < nB && j < nB) {
       const double sij = Ta[r][tx];
       S[d.soff + (int64_t)i * nB + j] = sij;
-      B[d.soff + (int64_t)i * nB + j] = 0.5 * (sij + Tb[tx][r]);
+      B[d.soff + (int64_t)i * nB + j] = 0.5 * (sij + Tm[tx][r]);
+    }
+    if (I != J) {
+      const int i2 = J * 32 + r, j2 = I * 32 + tx;
+      if (i2 < nB && j2 < nB) {
+        const double sji = Tb[r][tx];
+        S[d.soff + (int64_t)i2 * nB + j2] = sji;
+        B[d.soff + (int64_t)i2 * nB + j2] = 0.5 * (sji + Ta[tx][r]);
+      }
     }
   }
-  if (J == 0 && ty == 0 && I * 32 + tx < nB) {
+  if (I == J && ty == 0 && I * 32 + tx < nB) {
     const int i = I * 32 + tx;
     g[d.goff + i] = T[(int64_t)i * d.ld + nB];
   }

@@ -956,22 +956,24 @@ __global__ void __launch_bounds__(256) gather_kernel(const GatherDesc* __restric
       continue;
     }
     const double* srow = d.src + (size_t)sr * d.lds;
-    // four columns per lane at a time, every load of a group issued before
-    // its stores (the stores could alias the maps or the source as far as
-    // the compiler knows, so a plain loop waits out both load latencies per
-    // column)
-    for (int c0 = lane; c0 < d.nc; c0 += 256) {
-      int sc[4];
-      double v[4];
+    // eight columns per lane at a time (a row of up to 512 in one round of
+    // two load latencies: the column map, then the source), every load of a
+    // group issued before its stores (the stores could alias the maps or the
+    // source as far as the compiler knows, so a plain loop waits out both
+    // load latencies per column)
+    constexpr int U = 8;
+    for (int c0 = lane; c0 < d.nc; c0 += 64 * U) {
+      int sc[U];
+      double v[U];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
+      for (int u = 0; u < U; ++u) {
         const int c = c0 + 64 * u;
         sc[u] = c < d.nc ? (d.cmap ? d.cmap[c] : c) : -1;
       }
 #pragma unroll
-      for (int u = 0; u < 4; ++u) v[u] = sc[u] >= 0 ? srow[sc[u]] : 0.0;
+      for (int u = 0; u < U; ++u) v[u] = sc[u] >= 0 ? srow[sc[u]] : 0.0;
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
+      for (int u = 0; u < U; ++u) {
         const int c = c0 + 64 * u;
         if (c < d.nc) drow[c] = d.scale * v[u];
       }
