@@ -1165,74 +1165,12 @@ void run_setup(abddc_ctx* c) {
     ht.mark("M = [L; V], U from the trailing block");
     aug_extract_batched(od, mixed, s);
 
-    ht.mark("coarse");
-    // ----------------------------------------------------------- coarse
-    record(c, 6);
-    const int np = c->n_primal;
-    DevBuf<double> Aug2((size_t)std::max(1, 4 * np * np));
-    DevBuf<double> SPi((size_t)std::max(1, np * np));
-    SPi.zero(s);
-    // colour the subdomains so that equal colours share no primal unknown:
-    // by index parity on box partitions, greedily (first free colour in
-    // subdomain order) on general ones
-    std::vector<int> colour(nsub, 0);
-    int ncolour = 8;
-    if (T.general) {
-      std::vector<std::vector<int>> owners(np);
-      for (int sub = 0; sub < nsub; ++sub)
-        for (int32_t q : Pid[sub]) owners[q].push_back(sub);
-      ncolour = 0;
-      std::vector<int> mark;
-      for (int sub = 0; sub < nsub; ++sub) {
-        mark.assign(ncolour + 1, 0);
-        for (int32_t q : Pid[sub])
-          for (int o : owners[q])
-            if (o < sub) mark[colour[o]] = 1;
-        int cl = 0;
-        while (mark[cl]) ++cl;
-        colour[sub] = cl;
-        ncolour = std::max(ncolour, cl + 1);
-      }
-    } else {
-      for (int sub = 0; sub < nsub; ++sub) {
-        const int sx = sub % T.nsub[0], sy = (sub / T.nsub[0]) % T.nsub[1], sz = sub / (T.nsub[0] * T.nsub[1]);
-        colour[sub] = (sx & 1) | ((sy & 1) << 1) | ((sz & 1) << 2);
-      }
-    }
-    for (int color = 0; color < ncolour; ++color) {
-      std::vector<CoarseAddDesc> cd;
-      for (int sub = 0; sub < nsub; ++sub) {
-        if (colour[sub] != color) continue;
-        const int nP = (int)Pi[sub].size(), nD = (int)Dl[sub].size(), na = 2 * c->nB[sub];
-        if (nP == 0) continue;
-        const int64_t o = aoff2[sub] + (int64_t)nD * na + nD;   // the Pi x Pi block
-        cd.push_back({mixed ? nullptr : Aug.p + o, pool.ptr(pidx[sub]), nP, na, mixed ? Aug32.p + o : nullptr});
-      }
-      coarse_add_batched(cd, SPi.p, np, s);
-    }
-    c->dSPinv.alloc((size_t)std::max(1, np * np));
-    if (np > 0) {
-      IntPool cp;
-      std::vector<int32_t> mp(2 * np), r1(np), c1(np), r2(np), c2(np);
-      for (int q = 0; q < 2 * np; ++q) mp[q] = q < np ? q : -1;
-      for (int q = 0; q < np; ++q) {
-        r1[q] = q;
-        c1[q] = np + q;
-        r2[q] = np + q;
-        c2[q] = q;
-      }
-      const size_t o1 = cp.add(mp), o2 = cp.add(r1), o3 = cp.add(c1), o4 = cp.add(r2), o5 = cp.add(c2);
-      cp.upload(s);
-      gather_batched({{SPi.p, Aug2.p, cp.ptr(o1), cp.ptr(o1), 2 * np, 2 * np, np, 2 * np, 1.0}}, s);
-      set_batched({{Aug2.p, cp.ptr(o2), cp.ptr(o3), np, 2 * np, 1.0}, {Aug2.p, cp.ptr(o4), cp.ptr(o5), np, 2 * np, -1.0}},
-                  s);
-      partial_lu<double>({{Aug2.p, 2 * np, 2 * np, 2 * np, np}}, c->d_flag.p, s);
-      gather_batched({{Aug2.p + (int64_t)np * 2 * np + np, c->dSPinv.p, nullptr, nullptr, np, np, 2 * np, np, 1.0}}, s);
-    }
-
     ht.mark("apply metadata (device)");
     // ------------------------------------------- apply metadata (device)
+    // (sizes and maps only: built while the device runs the local
+    // factorisations, before the coarse factorisation is queued)
     record(c, 7);
+    const int np = c->n_primal;
     std::vector<int32_t> pid_all, ptr_p, idx_p, kp, vp;
     for (int sub = 0; sub < nsub; ++sub) {
       const int nB = c->nB[sub];
@@ -1295,6 +1233,70 @@ void run_setup(abddc_ctx* c) {
     c->d_bpi.alloc(std::max(np, 1));
     c->d_xpi.alloc(std::max(np, 1));
     ht.mark("metadata: GEMV operators, buffers");
+    ht.mark("coarse");
+    // ----------------------------------------------------------- coarse
+    record(c, 6);
+    DevBuf<double> Aug2((size_t)std::max(1, 4 * np * np));
+    DevBuf<double> SPi((size_t)std::max(1, np * np));
+    SPi.zero(s);
+    // colour the subdomains so that equal colours share no primal unknown:
+    // by index parity on box partitions, greedily (first free colour in
+    // subdomain order) on general ones
+    std::vector<int> colour(nsub, 0);
+    int ncolour = 8;
+    if (T.general) {
+      std::vector<std::vector<int>> owners(np);
+      for (int sub = 0; sub < nsub; ++sub)
+        for (int32_t q : Pid[sub]) owners[q].push_back(sub);
+      ncolour = 0;
+      std::vector<int> mark;
+      for (int sub = 0; sub < nsub; ++sub) {
+        mark.assign(ncolour + 1, 0);
+        for (int32_t q : Pid[sub])
+          for (int o : owners[q])
+            if (o < sub) mark[colour[o]] = 1;
+        int cl = 0;
+        while (mark[cl]) ++cl;
+        colour[sub] = cl;
+        ncolour = std::max(ncolour, cl + 1);
+      }
+    } else {
+      for (int sub = 0; sub < nsub; ++sub) {
+        const int sx = sub % T.nsub[0], sy = (sub / T.nsub[0]) % T.nsub[1], sz = sub / (T.nsub[0] * T.nsub[1]);
+        colour[sub] = (sx & 1) | ((sy & 1) << 1) | ((sz & 1) << 2);
+      }
+    }
+    for (int color = 0; color < ncolour; ++color) {
+      std::vector<CoarseAddDesc> cd;
+      for (int sub = 0; sub < nsub; ++sub) {
+        if (colour[sub] != color) continue;
+        const int nP = (int)Pi[sub].size(), nD = (int)Dl[sub].size(), na = 2 * c->nB[sub];
+        if (nP == 0) continue;
+        const int64_t o = aoff2[sub] + (int64_t)nD * na + nD;   // the Pi x Pi block
+        cd.push_back({mixed ? nullptr : Aug.p + o, pool.ptr(pidx[sub]), nP, na, mixed ? Aug32.p + o : nullptr});
+      }
+      coarse_add_batched(cd, SPi.p, np, s);
+    }
+    c->dSPinv.alloc((size_t)std::max(1, np * np));
+    if (np > 0) {
+      IntPool cp;
+      std::vector<int32_t> mp(2 * np), r1(np), c1(np), r2(np), c2(np);
+      for (int q = 0; q < 2 * np; ++q) mp[q] = q < np ? q : -1;
+      for (int q = 0; q < np; ++q) {
+        r1[q] = q;
+        c1[q] = np + q;
+        r2[q] = np + q;
+        c2[q] = q;
+      }
+      const size_t o1 = cp.add(mp), o2 = cp.add(r1), o3 = cp.add(c1), o4 = cp.add(r2), o5 = cp.add(c2);
+      cp.upload(s);
+      gather_batched({{SPi.p, Aug2.p, cp.ptr(o1), cp.ptr(o1), 2 * np, 2 * np, np, 2 * np, 1.0}}, s);
+      set_batched({{Aug2.p, cp.ptr(o2), cp.ptr(o3), np, 2 * np, 1.0}, {Aug2.p, cp.ptr(o4), cp.ptr(o5), np, 2 * np, -1.0}},
+                  s);
+      partial_lu<double>({{Aug2.p, 2 * np, 2 * np, 2 * np, np}}, c->d_flag.p, s);
+      gather_batched({{Aug2.p + (int64_t)np * 2 * np + np, c->dSPinv.p, nullptr, nullptr, np, np, 2 * np, np, 1.0}}, s);
+    }
+
     // variants of the three apply GEMVs (cached per architecture and size)
     ABDDC_HIP(hipMemsetAsync(c->d_bpi.p, 0, std::max(np, 1) * sizeof(double), s));
     ABDDC_HIP(hipMemsetAsync(c->d_xpi.p, 0, std::max(np, 1) * sizeof(double), s));
