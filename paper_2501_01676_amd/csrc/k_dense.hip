@@ -401,83 +401,6 @@ __device__ inline float read_lane<float>(float v, int lane) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
 }
 
-// D[0, b)^2 -= A (b x kd) B (kd x b) for the lookahead of the diagonal-block
-// kernel: A, B row-major with leading dimension ld, kd a multiple of 64.  One
-// workgroup streams the strips through LDS in K chunks of 32 with two chunks
-// in flight in registers (one workgroup per matrix cannot hide the memory
-// latency with other workgroups); each wave accumulates a 32 x 32 quadrant
-// on MFMA.  Rows and columns >= b read zero, so the identity padding of D is
-// left as it is.
-template <class T>
-__device__ __forceinline__ void diag_lookahead(const T* A, const T* B, int ld, int b, int kd, T (*D)[NB + 1],
-                                               T (*As)[LDS_PAD], T (*Bs)[LDS_PAD]) {
-  typedef typename Mfma<T>::acc_t acc_t;
-  constexpr int PER = TILE * KC / 256;   // elements of each operand per thread and chunk
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int wr = (w >> 1) * 32, wc = (w & 1) * 32, kl = lane >> 4, il = lane & 15;
-  const __amdgpu_buffer_rsrc_t rsa = buf_rsrc(A), rsb = buf_rsrc(B);
-  // A chunk: row ai + 8 q, column ak; B chunk: row bk + 4 q, column bj
-  const int ai = tid >> 5, ak = tid & 31, bk = tid >> 6, bj = tid & 63;
-  int oa[PER], ob[PER];
-#pragma unroll
-  for (int q = 0; q < PER; ++q) {
-    const int i = ai + 8 * q;
-    oa[q] = i < b ? (i * ld + ak) * (int)sizeof(T) : BUF_OUT;
-    ob[q] = bj < b ? ((bk + 4 * q) * ld + bj) * (int)sizeof(T) : BUF_OUT;
-  }
-  T ra0[PER], rb0[PER], ra1[PER], rb1[PER];
-  auto fetch = [&](T* ra, T* rb, int k0) {
-    const int sa = k0 * (int)sizeof(T), sb = k0 * ld * (int)sizeof(T);
-#pragma unroll
-    for (int q = 0; q < PER; ++q) {
-      ra[q] = buf_load<T>(rsa, oa[q], sa);
-      rb[q] = buf_load<T>(rsb, ob[q], sb);
-    }
-  };
-  auto stage = [&](const T* ra, const T* rb) {
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < PER; ++q) {
-      As[ak][ai + 8 * q] = ra[q];
-      Bs[bk + 4 * q][bj] = rb[q];
-    }
-    __syncthreads();
-  };
-  acc_t acc[2][2];
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j) acc[i][j] = acc_t{0, 0, 0, 0};
-  auto mma = [&]() {
-#pragma unroll
-    for (int kk = 0; kk < KC; kk += 4) {
-      const T a0 = As[kk + kl][wr + il], a1 = As[kk + kl][wr + 16 + il];
-      const T b0 = Bs[kk + kl][wc + il], b1 = Bs[kk + kl][wc + 16 + il];
-      acc[0][0] = Mfma<T>::run(a0, b0, acc[0][0]);
-      acc[0][1] = Mfma<T>::run(a0, b1, acc[0][1]);
-      acc[1][0] = Mfma<T>::run(a1, b0, acc[1][0]);
-      acc[1][1] = Mfma<T>::run(a1, b1, acc[1][1]);
-    }
-  };
-  fetch(ra0, rb0, 0);
-  fetch(ra1, rb1, KC);
-#pragma unroll 1
-  for (int k0 = 0; k0 < kd; k0 += 2 * KC) {
-    stage(ra0, rb0);
-    if (k0 + 2 * KC < kd) fetch(ra0, rb0, k0 + 2 * KC);
-    mma();
-    stage(ra1, rb1);
-    if (k0 + 3 * KC < kd) fetch(ra1, rb1, k0 + 3 * KC);
-    mma();
-  }
-#pragma unroll
-  for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-    for (int bj2 = 0; bj2 < 2; ++bj2)
-#pragma unroll
-      for (int q = 0; q < 4; ++q) D[wr + 16 * bi + Mfma<T>::out_row(kl, q)][wc + 16 * bj2 + il] -= acc[bi][bj2][q];
-}
-
 // Step 1 of panel t0: factor the diagonal block (b = min(NB, k - t0)) and
 // write L\U back, L^{-1} (unit lower) and U^{-1} to scratch.  The block is
 // padded in LDS to diag(D, I) of order 64, which factors and inverts to
@@ -490,19 +413,13 @@ __device__ __forceinline__ void diag_lookahead(const T* A, const T* B, int ld, i
 //   (c) all waves update the trailing block.
 // The inverses are one column per lane: wave 0 forward-substitutes L,
 // wave 1 back-substitutes U, each holding its column in registers.
-//
-// With u0 < t0 the block first receives the update of the pivot columns
-// [u0, t0) (A_dd -= A[t0.., u0..t0) A[u0..t0, t0..), depth 64 or 128), which
-// the band / lead launch of those columns leaves out, so that launch may
-// follow this one in any order after the same triangular solves.
 template <class T>
-__global__ void __launch_bounds__(256) plu_diag_kernel(const PluDesc<T>* __restrict__ descs, int t0, int u0,
+__global__ void __launch_bounds__(256) plu_diag_kernel(const PluDesc<T>* __restrict__ descs, int t0,
                                                         T* __restrict__ scratch, int* dflag) {
   constexpr int H = NB / 2;
   __shared__ T D[NB][NB + 1];
-  __shared__ T E[NB][NB + 1];   // also the staging of the block update (2 KC rows of LDS_PAD)
+  __shared__ T E[NB][NB + 1];
   __shared__ T dinv[NB];
-  static_assert(2 * KC * LDS_PAD == NB * (NB + 1), "update staging must fit in E");
   const PluDesc<T> d = descs[blockIdx.x];
   if (t0 >= d.k) return;
   const int b = min(NB, d.k - t0);
@@ -525,11 +442,6 @@ __global__ void __launch_bounds__(256) plu_diag_kernel(const PluDesc<T>* __restr
     }
   }
   __syncthreads();
-  if (u0 < t0) {
-    T (*As)[LDS_PAD] = reinterpret_cast<T (*)[LDS_PAD]>(&E[0][0]);
-    diag_lookahead<T>(d.a + (size_t)t0 * d.ld + u0, d.a + (size_t)u0 * d.ld + t0, d.ld, b, t0 - u0, D, As, As + KC);
-    __syncthreads();
-  }
   for (int kb = 0; kb < b; kb += 16) {
     if (wave == 0) {
       T P[16];
@@ -882,9 +794,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) p
   const T* A12 = d.a + (size_t)g0 * d.ld + s0;
   T* A22 = d.a + (size_t)s0 * d.ld + s0;
   if (t < rtl) {
-    // the next diagonal block [0, w)^2 is updated by the next panel's diag kernel
-    tile_gemm<T, false, false>(A21, d.ld, A12, d.ld, A22, d.ld, mr, w, b, T(-1), T(1), t * TILE, 0, As, Bs,
-                               0x7fffffff, w);
+    tile_gemm<T, false, false>(A21, d.ld, A12, d.ld, A22, d.ld, mr, w, b, T(-1), T(1), t * TILE, 0, As, Bs);
   } else {
     const int col0 = w + (t - rtl) * TILE;
     if (col0 >= nc) return;
@@ -915,10 +825,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) p
   const T* A21 = d.a + (size_t)s0 * d.ld + t0;
   const T* A12 = d.a + (size_t)t0 * d.ld + s0;
   T* A22 = d.a + (size_t)s0 * d.ld + s0;
-  // only entries with row < kr or col < kr are written, and not the next
-  // diagonal block [0, min(NB, kr))^2, which the next panel's diag kernel updates
-  tile_gemm<T, false, false>(A21, d.ld, A12, d.ld, A22, d.ld, mr, nc, b, T(-1), T(1), row0, col0, As, Bs, kr,
-                             min(NB, kr));
+  // only entries with row < kr or col < kr are written
+  tile_gemm<T, false, false>(A21, d.ld, A12, d.ld, A22, d.ld, mr, nc, b, T(-1), T(1), row0, col0, As, Bs, kr);
 }
 
 // Trailing Schur complement A22 -= A21 A12 with K = k (one pass).
@@ -1028,35 +936,30 @@ void partial_lu(const std::vector<PluDesc<T>>& descs_in, int* dflag, hipStream_t
   }
   T* scr = reinterpret_cast<T*>(scratch.p);
   const int nb = (int)descs.size();
-  // Lookahead: the diag kernel of panel t0 + NB follows the triangular
-  // solves of panel t0 and comes before the band / lead launch of that panel,
-  // which leaves that diagonal block to it.
+  // The band / lead launch of panel t0 also updates the next diagonal block
+  // (one more tile at the same depth), so the diag kernel of panel t0 + NB
+  // follows it and factors the block as it finds it.
   const int grp = maxk > 512 ? 4 : (maxk > 256 ? 3 : 2);   // panels per group
   // Algorithmic flops of each launch for the live kernel statistics (only
   // counted when a statistics sink is set):
-  //   diag  LU of the b x b diagonal block, 2/3 b^3, plus its lookahead
-  //         update at depth t0 - u0, 2 b^2 (t0 - u0)
+  //   diag  LU of the b x b diagonal block, 2/3 b^3
   //   trsm  bytes, not flops (b^2 flops per 16 b bytes of strip is below
   //         the FP64 ridge): each strip entry of L21 and U12 read and written
   //         once, the two b x b inverses read once
-  //   band  the strips of the next panel at the group's depth, leaving out
-  //         the next diagonal block
-  auto diag_flops = [&](int t0, int u0) {
+  //   band  the strips of the next panel at the group's depth
+  auto diag_launch = [&](int t0) {
     double f = 0.0;
     if (kstats_on(KC_PLU_DIAG))
       for (auto& d : descs)
         if (t0 < d.k) {
           const double b = std::min(NB, d.k - t0);
-          f += 2.0 / 3.0 * b * b * b + 2.0 * b * b * (t0 - u0);
+          f += 2.0 / 3.0 * b * b * b;
         }
-    return f;
-  };
-  auto diag_launch = [&](int t0, int u0) {
     hipEvent_t ea = nullptr, eb = nullptr;
-    tracked_events(KC_PLU_DIAG, diag_flops(t0, u0), &ea, &eb);
-    hipExtLaunchKernelGGL(plu_diag_kernel<T>, dim3(nb), dim3(256), 0, s, ea, eb, 0, dd, t0, u0, scr, dflag);
+    tracked_events(KC_PLU_DIAG, f, &ea, &eb);
+    hipExtLaunchKernelGGL(plu_diag_kernel<T>, dim3(nb), dim3(256), 0, s, ea, eb, 0, dd, t0, scr, dflag);
   };
-  diag_launch(0, 0);
+  diag_launch(0);
   auto tiles_of = [](int n) { return n > 0 ? (n + TILE - 1) / TILE : 0; };
   std::vector<int> cnt(nb);
   for (int t0 = 0; t0 < maxk; t0 += NB) {
@@ -1080,12 +983,6 @@ void partial_lu(const std::vector<PluDesc<T>>& descs_in, int* dflag, hipStream_t
       tracked_events(KC_PLU_TRSM, f, &ea, &eb);
       hipExtLaunchKernelGGL(plu_trsm_kernel<T>, dim3(gt.grid), dim3(256), 0, s, ea, eb, 0, dd, t0, (const T*)scr,
                             gt.sched, nb);
-    }
-    if (t0 + NB < maxk) {
-      // the next diagonal block: the pivot columns of this panel's group so
-      // far, applied in the diag kernel
-      const int u0 = t0 - ((t0 / NB) % grp) * NB;   // start of this panel's group
-      diag_launch(t0 + NB, u0);
     }
     const int g0 = t0 - ((t0 / NB) % grp) * NB;
     if ((t0 / NB) % grp != grp - 1) {
@@ -1111,13 +1008,14 @@ void partial_lu(const std::vector<PluDesc<T>>& descs_in, int* dflag, hipStream_t
                 const int s0 = t0 + std::min(NB, d.k - t0);
                 if (s0 >= d.k) continue;
                 const double w = std::min(NB, d.k - s0), mr = d.nrow - s0, nc = d.ncol - s0;
-                f += 2.0 * (s0 - g0) * ((mr - w) * w + w * (nc - w));
+                f += 2.0 * (s0 - g0) * (mr * w + w * (nc - w));
               }
           hipEvent_t ea = nullptr, eb = nullptr;
           tracked_events(KC_PLU_BAND, f, &ea, &eb);
           hipExtLaunchKernelGGL(plu_band_kernel<T>, dim3(gb.grid), dim3(256), 0, s, ea, eb, 0, dd, g0, t0, gb.sched,
                                 nb);
         }
+        diag_launch(t0 + NB);
       }
       continue;
     }
@@ -1133,19 +1031,18 @@ void partial_lu(const std::vector<PluDesc<T>>& descs_in, int* dflag, hipStream_t
       hipEvent_t ea = nullptr, eb = nullptr;
       if (kstats_on(KC_PLU_LEAD)) {
         // rows [s, nrow) x cols [s, k) and rows [s, k) x cols [k, ncol) at
-        // depth b, without the next diagonal block
+        // depth b
         double flops = 0.0;
         for (auto& d : descs)
           if (sp < d.k) {
-            const double w = std::min(NB, d.k - sp);
-            flops += 2.0 * (grp * NB) *
-                     ((double)(d.nrow - sp) * (d.k - sp) + (double)(d.k - sp) * (d.ncol - d.k) - w * w);
+            flops += 2.0 * (grp * NB) * ((double)(d.nrow - sp) * (d.k - sp) + (double)(d.k - sp) * (d.ncol - d.k));
           }
         tracked_events(KC_PLU_LEAD, flops, &ea, &eb);
       }
       hipExtLaunchKernelGGL(plu_lead_kernel<T>, dim3(gl.grid), dim3(256), 0, s, ea, eb, 0, dd, p0, grp * NB,
                             gl.sched, nb);
     }
+    if (t0 + NB < maxk) diag_launch(t0 + NB);
   }
   // trailing Schur complement with K = k
   double flops = 0.0;
