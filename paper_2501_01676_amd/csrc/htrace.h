@@ -1,7 +1,7 @@
 // Optional host-side timeline (environment variable ABDDC_HOST_TRACE=1):
 // each mark prints the host time spent since the previous mark of any trace
-// on the calling thread (one continuous timeline), and the minor page faults
-// taken meanwhile, to stderr.
+// on the calling thread (one continuous timeline), the minor page faults
+// taken meanwhile and the mark's steady-clock time, to stderr.
 // It shows host work and synchronisations that leave the GPU idle.
 #pragma once
 
@@ -43,8 +43,9 @@ struct HostTrace {
     if (!on) return;
     const auto now = std::chrono::steady_clock::now();
     const long f = minor_faults();
-    std::fprintf(stderr, "[host] %-40s %9.1f us %7ld faults\n", what,
-                 std::chrono::duration<double, std::micro>(now - last()).count(), f - faults());
+    std::fprintf(stderr, "[host] %-40s %9.1f us %7ld faults @ %.1f us\n", what,
+                 std::chrono::duration<double, std::micro>(now - last()).count(), f - faults(),
+                 std::chrono::duration<double, std::micro>(now.time_since_epoch()).count());
     last() = now;
     faults() = f;
   }
