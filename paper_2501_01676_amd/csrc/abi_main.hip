@@ -430,7 +430,11 @@ extern "C" int abddc_assemble(const abddc_problem* prob, const abddc_device* dev
       rows += c->nloc[sub];
     }
     ABDDC_REQUIRE(T.n_nodes < (int64_t)1 << 31 && lmt < (int64_t)1 << 31, ABDDC_EINVAL, "mesh too large");
-    std::vector<int32_t> lnode(rows), rowsub(rows), lmap(lmt, -1), gam(gt), int_dof(it);
+    // host arrays left uninitialised (a serial zero fill of these ~5 MB
+    // would cost more than the parallel loop that writes every entry; each
+    // subdomain clears its own range of the box map first)
+    auto uninit = [](int64_t n) { return std::unique_ptr<int32_t[]>(new int32_t[std::max<int64_t>(n, 1)]); };
+    auto lnode = uninit(rows), rowsub = uninit(rows), lmap = uninit(lmt), gam = uninit(gt), int_dof = uninit(it);
     host_parallel_for(nsub, 4, [&](int64_t sb, int64_t se) {
       for (int sub = (int)sb; sub < (int)se; ++sub) {
         const SubInfo& si = T.sub[sub];
@@ -440,9 +444,11 @@ extern "C" int abddc_assemble(const abddc_problem* prob, const abddc_device* dev
         // subdomain's bounding box of nodes to local positions
         const int e0[3] = {si.ebox[0][0], si.ebox[1][0], si.ebox[2][0]};
         const int bx = si.ebox[0][1] - e0[0] + 1, by = si.ebox[1][1] - e0[1] + 1;
+        const int bz = si.ebox[2][1] - e0[2] + 1;
         const size_t b0 = (size_t)a.lmoff;
-        int32_t* ln = lnode.data() + a.loff;
-        int32_t* idof = int_dof.data() + a.ioff;
+        std::fill(lmap.get() + b0, lmap.get() + b0 + (size_t)bx * by * bz, -1);
+        int32_t* ln = lnode.get() + a.loff;
+        int32_t* idof = int_dof.get() + a.ioff;
         int loc = 0;
         auto place = [&](int64_t v, bool interior) {
           const int ix = (int)(v % T.nn[0]), iy = (int)((v / T.nn[0]) % T.nn[1]);
@@ -454,15 +460,18 @@ extern "C" int abddc_assemble(const abddc_problem* prob, const abddc_device* dev
         for (int64_t v : si.interior) place(v, true);
         for (int k : si.objs)
           for (int64_t v : T.objects[k].nodes) place(v, false);
-        std::fill(rowsub.begin() + a.loff, rowsub.begin() + a.loff + loc, sub);
+        ABDDC_REQUIRE(loc == a.nloc && (int)si.interior.size() == a.nI, ABDDC_EINVAL,
+                      "local layout: node lists do not match the subdomain sizes");
+        std::fill(rowsub.get() + a.loff, rowsub.get() + a.loff + loc, sub);
         for (int l = 0; l < si.nB; ++l) gam[a.goff + l] = (int32_t)si.gamma[l];
       }
     });
     ht.mark("assemble: local layout maps");
     c->d_subs = to_device(sa, s);
-    DevBuf<int32_t> d_lnode = to_device(lnode, s), d_rowsub = to_device(rowsub, s), d_lmap = to_device(lmap, s);
-    c->d_gam = to_device(gam, s);
-    c->d_int_dof = to_device(int_dof, s);
+    DevBuf<int32_t> d_lnode = to_device(lnode.get(), rows, s), d_rowsub = to_device(rowsub.get(), rows, s),
+                    d_lmap = to_device(lmap.get(), lmt, s);
+    c->d_gam = to_device(gam.get(), gt, s);
+    c->d_int_dof = to_device(int_dof.get(), it, s);
     std::vector<int32_t> iface_dof(T.n_gamma);
     host_parallel_for((int64_t)T.objects.size(), 64, [&](int64_t b, int64_t e) {
       for (int64_t k = b; k < e; ++k) {

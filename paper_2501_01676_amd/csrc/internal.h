@@ -141,6 +141,12 @@ inline DevBuf<T> to_device(const std::vector<T>& h, hipStream_t s) {
   if (!h.empty()) staged_upload(d.p, h.data(), h.size() * sizeof(T), s);
   return d;
 }
+template <class T>
+inline DevBuf<T> to_device(const T* h, size_t n, hipStream_t s) {
+  DevBuf<T> d(n);
+  if (n) staged_upload(d.p, h, n * sizeof(T), s);
+  return d;
+}
 
 template <class T>
 inline std::vector<T> to_host(const T* d, size_t n, hipStream_t s) {
