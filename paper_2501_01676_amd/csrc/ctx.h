@@ -25,8 +25,7 @@ struct FaceElimPlan {
     size_t m2;                   // pool offset of the step (2) map
   };
   bool ready = false;
-  std::vector<int32_t> pool;            // concatenated index maps
-  DevBuf<int32_t> d_pool;
+  DevBuf<int32_t> d_pool;               // concatenated index maps
   std::vector<size_t> m1off;            // per subdomain: step (1) map
   std::vector<int> nR, nC;              // per subdomain: eliminated / kept in step (1)
   std::vector<Group> groups;

@@ -9,6 +9,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <memory>
 #include <cstdlib>
 #include <cmath>
 
@@ -159,11 +160,6 @@ void plan_face_elimination(abddc_ctx* c, hipStream_t s) {
       sfaces[sub].push_back({f, side, T.sub[sub].local_pos(k), T.objects[k].n, face_axis(k)});
     }
   }
-  auto add = [&](const std::vector<int32_t>& v) {
-    const size_t off = P.pool.size();
-    P.pool.insert(P.pool.end(), v.begin(), v.end());
-    return off;
-  };
   P.m1off.assign(nsub, 0);
   P.nR.assign(nsub, 0);
   P.nC.assign(nsub, 0);
@@ -172,64 +168,105 @@ void plan_face_elimination(abddc_ctx* c, hipStream_t s) {
   P.ng3.assign(2 * nf, 0);
   P.grp_of.assign(2 * nf, -1);
   P.m3off.assign(2 * nf, 0);
-  for (int sub = 0; sub < nsub; ++sub) {
-    std::vector<FacePart>& fp = sfaces[sub];
-    if (fp.empty()) continue;
-    std::stable_sort(fp.begin(), fp.end(), [](const FacePart& a, const FacePart& b) {
-      return a.axis != b.axis ? a.axis < b.axis : a.off < b.off;
-    });
-    const int nB = c->nB[sub];
-    std::vector<char> isface(nB, 0);
-    for (const FacePart& q : fp)
-      for (int t = 0; t < q.n; ++t) isface[q.off + t] = 1;
-    std::vector<int32_t> mp;
-    for (int t = 0; t < nB; ++t)
-      if (!isface[t]) mp.push_back(t);
-    P.nR[sub] = (int)mp.size();
-    std::vector<int> cpos(fp.size());
-    for (size_t i = 0; i < fp.size(); ++i) {
-      cpos[i] = (int)mp.size() - P.nR[sub];
-      for (int t = 0; t < fp[i].n; ++t) mp.push_back(fp[i].off + t);
+  // (a) per subdomain, in parallel: its maps in pool order (step (1), then
+  // per group the step (2) map and the step (3) maps of its faces) with
+  // offsets relative to the subdomain's block; (b) serially, the blocks'
+  // pool offsets, the group numbers and the work-array offsets in subdomain
+  // order; (c) in parallel, every block into the pool
+  struct FaceRec { int id, k3, ng3; int64_t m3; };   // m3: relative offset, -1 without step (3)
+  struct GroupRec { FaceElimPlan::Group g; std::vector<FaceRec> faces; };
+  struct SubPlan { std::vector<int32_t> ints; std::vector<GroupRec> groups; };
+  std::vector<SubPlan> sp(nsub);
+  host_parallel_for(nsub, 8, [&](int64_t sb, int64_t se) {
+    for (int sub = (int)sb; sub < (int)se; ++sub) {
+      std::vector<FacePart>& fp = sfaces[sub];
+      if (fp.empty()) continue;
+      std::stable_sort(fp.begin(), fp.end(), [](const FacePart& a, const FacePart& b) {
+        return a.axis != b.axis ? a.axis < b.axis : a.off < b.off;
+      });
+      SubPlan& S = sp[sub];
+      std::vector<int32_t>& v = S.ints;
+      const int nB = c->nB[sub];
+      std::vector<char> isface(nB, 0);
+      for (const FacePart& q : fp)
+        for (int t = 0; t < q.n; ++t) isface[q.off + t] = 1;
+      for (int t = 0; t < nB; ++t)
+        if (!isface[t]) v.push_back(t);
+      const int nR = (int)v.size();
+      std::vector<int> cpos(fp.size());
+      for (size_t i = 0; i < fp.size(); ++i) {
+        cpos[i] = (int)v.size() - nR;
+        for (int t = 0; t < fp[i].n; ++t) v.push_back(fp[i].off + t);
+      }
+      P.nR[sub] = nR;
+      const int nC = nB - nR;
+      P.nC[sub] = nC;
+      for (size_t i = 0; i < fp.size();) {
+        size_t j = i + 1;
+        while (j < fp.size() && fp[j].axis == fp[i].axis) ++j;
+        GroupRec gr;
+        FaceElimPlan::Group& g = gr.g;
+        g.sub = sub;
+        g.nfaces = (int)(j - i);
+        g.cpos = cpos[i];
+        g.ng = 0;
+        for (size_t q = i; q < j; ++q) g.ng += fp[q].n;
+        g.k2 = nC - g.ng;
+        g.o2 = 0;
+        g.m2 = v.size();
+        for (int t = 0; t < nC; ++t)
+          if (t < g.cpos || t >= g.cpos + g.ng) v.push_back(t);
+        for (int t = 0; t < g.ng; ++t) v.push_back(g.cpos + t);
+        int inner = 0;
+        for (size_t q = i; q < j; ++q) {
+          FaceRec fr{2 * fp[q].f + fp[q].side, g.ng - fp[q].n, g.ng, -1};
+          if (g.nfaces > 1) {
+            // [the other face of the pair; this face] inside the pair block
+            fr.m3 = (int64_t)v.size();
+            for (int t = 0; t < g.ng; ++t)
+              if (t < inner || t >= inner + fp[q].n) v.push_back(t);
+            for (int t = 0; t < fp[q].n; ++t) v.push_back(inner + t);
+          }
+          gr.faces.push_back(fr);
+          inner += fp[q].n;
+        }
+        S.groups.push_back(std::move(gr));
+        i = j;
+      }
     }
-    P.m1off[sub] = add(mp);
-    P.nC[sub] = nB - P.nR[sub];
-    for (size_t i = 0; i < fp.size();) {
-      size_t j = i + 1;
-      while (j < fp.size() && fp[j].axis == fp[i].axis) ++j;
-      FaceElimPlan::Group g{sub, (int)(j - i), cpos[i], 0, P.w2tot, 0, 0};
-      for (size_t q = i; q < j; ++q) g.ng += fp[q].n;
-      g.k2 = P.nC[sub] - g.ng;
-      std::vector<int32_t> m2;
-      for (int t = 0; t < P.nC[sub]; ++t)
-        if (t < g.cpos || t >= g.cpos + g.ng) m2.push_back(t);
-      for (int t = 0; t < g.ng; ++t) m2.push_back(g.cpos + t);
-      g.m2 = add(m2);
-      P.w2tot += (int64_t)P.nC[sub] * P.nC[sub];
+  });
+  std::vector<size_t> base(nsub + 1, 0);
+  for (int sub = 0; sub < nsub; ++sub) {
+    base[sub + 1] = base[sub] + sp[sub].ints.size();
+    if (sp[sub].ints.empty()) continue;
+    P.m1off[sub] = base[sub];
+    const int nC = P.nC[sub];
+    for (GroupRec& gr : sp[sub].groups) {
+      FaceElimPlan::Group g = gr.g;
+      g.o2 = P.w2tot;
+      g.m2 += base[sub];
+      P.w2tot += (int64_t)nC * nC;
       const int gi = (int)P.groups.size();
       P.groups.push_back(g);
-      int inner = 0;
-      for (size_t q = i; q < j; ++q) {
-        const int id = 2 * fp[q].f + fp[q].side;
-        P.grp_of[id] = gi;
-        if (g.nfaces > 1) {
-          // [the other face of the pair; this face] inside the pair block
-          std::vector<int32_t> m3;
-          for (int t = 0; t < g.ng; ++t)
-            if (t < inner || t >= inner + fp[q].n) m3.push_back(t);
-          for (int t = 0; t < fp[q].n; ++t) m3.push_back(inner + t);
-          P.m3off[id] = add(m3);
-          P.res3[id] = P.w3tot;
-          P.k3of[id] = g.ng - fp[q].n;
-          P.ng3[id] = g.ng;
-          P.w3tot += (int64_t)g.ng * g.ng;
-        }
-        inner += fp[q].n;
+      for (const FaceRec& fr : gr.faces) {
+        P.grp_of[fr.id] = gi;
+        if (fr.m3 < 0) continue;
+        P.m3off[fr.id] = base[sub] + (size_t)fr.m3;
+        P.res3[fr.id] = P.w3tot;
+        P.k3of[fr.id] = fr.k3;
+        P.ng3[fr.id] = fr.ng3;
+        P.w3tot += (int64_t)fr.ng3 * fr.ng3;
       }
-      i = j;
     }
   }
-  P.d_pool.alloc(std::max<size_t>(P.pool.size(), 1));
-  if (!P.pool.empty()) staged_upload(P.d_pool.p, P.pool.data(), P.pool.size() * sizeof(int32_t), s);
+  const size_t total = base[nsub];
+  std::unique_ptr<int32_t[]> pool(new int32_t[std::max<size_t>(total, 1)]);
+  host_parallel_for(nsub, 16, [&](int64_t sb, int64_t se) {
+    for (int64_t sub = sb; sub < se; ++sub)
+      std::copy(sp[sub].ints.begin(), sp[sub].ints.end(), pool.get() + base[sub]);
+  });
+  P.d_pool.alloc(std::max<size_t>(total, 1));
+  if (total) staged_upload(P.d_pool.p, pool.get(), total * sizeof(int32_t), s);
   P.ready = true;
 }
 
