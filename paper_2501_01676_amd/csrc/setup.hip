@@ -73,10 +73,24 @@ int check_flag(abddc_ctx* c) {
   return h;
 }
 
-void require_flag_clean(abddc_ctx* c, const char* stage) {
-  const int h = check_flag(c);
+void throw_on_flag(int h, const char* stage) {
   if (h & 1) throw Error(ABDDC_ESINGULAR, std::string(stage) + ": zero or non-finite pivot");
   if (h & 2) throw Error(ABDDC_EEIG, std::string(stage) + ": eigenproblem metric not positive definite");
+}
+
+void require_flag_clean(abddc_ctx* c, const char* stage) { throw_on_flag(check_flag(c), stage); }
+
+// The n eigenvalues at d and the error flag, read back through pinned memory
+// behind one wait; the flag is then checked as require_flag_clean does.
+std::vector<double> eigenvalues_checked(abddc_ctx* c, const double* d, size_t n, const char* stage) {
+  int32_t* buf = pinned_ints(2 * n + 2);   // n doubles, then the flag
+  double* hv = reinterpret_cast<double*>(buf);
+  int32_t* hf = buf + 2 * n;
+  ABDDC_HIP(hipMemcpyAsync(hf, c->d_flag.p, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+  if (n) ABDDC_HIP(hipMemcpyAsync(hv, d, n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  ABDDC_HIP(hipStreamSynchronize(c->stream));
+  throw_on_flag(*hf, stage);
+  return std::vector<double>(hv, hv + n);
 }
 
 // Learned edge constraints: features -> network -> P-hat -> eigenpairs;
@@ -458,8 +472,8 @@ void run_setup(abddc_ctx* c) {
       gv.push_back({Sum.p + c->tfoff[f], BF.p + c->tfoff[f], c->dWF.p + c->wfoff[f], XF.p + c->tfoff[f],
                     T.objects[T.faces[f]].n});
     eig_selected(gv, 1.0 / c->opt.theta_face, c->d_flag.p, s);
-    std::vector<double> mu = to_host(c->dWF.p, c->dWF.n, s);
-    require_flag_clean(c, "deluxe / face elimination / face eigenproblem");
+    std::vector<double> mu =
+        eigenvalues_checked(c, c->dWF.p, c->dWF.n, "deluxe / face elimination / face eigenproblem");
     std::vector<QrDesc> qd;
     for (int f = 0; f < nf; ++f) {
       const int n = T.objects[T.faces[f]].n;
@@ -740,8 +754,7 @@ void run_setup(abddc_ctx* c) {
     edge_old_metric_batched(md, s);
     eig_selected(gv, 1.0 / c->opt.theta_edge, c->d_flag.p, s);
     prepare_rotation();   // while the device solves the edge eigenproblems
-    std::vector<double> mu = to_host(c->dWE.p, c->dWE.n, s);
-    require_flag_clean(c, "edge elimination / edge eigenproblem");
+    std::vector<double> mu = eigenvalues_checked(c, c->dWE.p, c->dWE.n, "edge elimination / edge eigenproblem");
     std::vector<QrDesc> qd;
     for (int e : elist) {
       const Object& o = T.objects[T.edges[e]];
@@ -994,8 +1007,7 @@ void run_setup(abddc_ctx* c) {
     }
     eig_selected(gv, 1.0 / c->opt.theta_edge, c->d_flag.p, s);
     prepare_rotation();   // while the device solves the edge eigenproblems
-    std::vector<double> mu = to_host(c->dWE.p, c->dWE.n, s);
-    require_flag_clean(c, "edge elimination / edge eigenproblem");
+    std::vector<double> mu = eigenvalues_checked(c, c->dWE.p, c->dWE.n, "edge elimination / edge eigenproblem");
     ht.mark("G = [g_{l,k}] (n_E x (m-1) |N_E|) and ");
     // G = [g_{l,k}] (n_E x (m-1) |N_E|) and its left singular basis
     int64_t gtot = 0;
