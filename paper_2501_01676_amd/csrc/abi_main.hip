@@ -7,10 +7,12 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <condition_variable>
 #include <cstddef>
 #include <map>
 #include <memory>
 #include <mutex>
+#include <thread>
 
 #include "apply.h"
 #include "arena.h"
@@ -125,6 +127,37 @@ void acquire_resources(abddc_ctx* c) {
   c->ev_step[1] = r.ev_step[1];
   c->cap_stream = r.cap_stream;
   c->events = true;
+}
+
+// A destroyed context's topology (per-object and per-subdomain index lists,
+// thousands of small allocations: ~0.5 ms to free on config3) is freed by one
+// background thread, so that abddc_destroy returns without waiting for it.
+// Host memory only; the thread and its queue live until the process ends.
+void reap_topology(Topology&& t) {
+  struct Reaper {
+    std::mutex mu;
+    std::condition_variable cv;
+    std::vector<Topology> q;
+    Reaper() {
+      std::thread([this] {
+        std::unique_lock<std::mutex> g(mu);
+        for (;;) {
+          cv.wait(g, [&] { return !q.empty(); });
+          std::vector<Topology> batch;
+          batch.swap(q);
+          g.unlock();
+          batch.clear();
+          g.lock();
+        }
+      }).detach();
+    }
+  };
+  static Reaper* r = new Reaper();   // never destroyed: its thread runs until exit
+  {
+    std::lock_guard<std::mutex> g(r->mu);
+    r->q.push_back(std::move(t));
+  }
+  r->cv.notify_one();
 }
 
 void release_resources(abddc_ctx* c) {
@@ -960,6 +993,7 @@ extern "C" void abddc_destroy(abddc_ctx* c) {
   if (c->step_graph) (void)hipGraphDestroy(c->step_graph);
   ht.mark("destroy: Arnoldi-step graph");
   release_resources(c);
+  reap_topology(std::move(c->topo));
   delete c;
   ht.mark("destroy: buffers released");
 }
